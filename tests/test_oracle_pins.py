@@ -1,0 +1,406 @@
+"""Pins of the CPU oracle to facts the paper and the mathematics fix.
+
+None of these re-types an oracle formula and compares it with itself: each
+checks the oracle against an independent route (exact rational arithmetic, a
+brute-force per-cell loop, an eigen-decomposition, a textbook direct solver,
+the Gaussian kernel closed form with wall images, or the numbers the paper
+prints), chosen so that a dropped term, a wrong sign or index, or a
+transposed operand in the oracle fails at least one of them.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import cgd_oracle as O
+from paper_1409_0001_amd import inputs
+
+# ---------------------------------------------------------------- deposition
+
+
+def _exact_bin(x, lo, hi, n):
+    """Host cell index by exact rational arithmetic (no floating point)."""
+    fx, flo, fhi = Fraction(float(x)), Fraction(float(lo)), Fraction(float(hi))
+    u = (fx - flo) * n / (fhi - flo)
+    i = math.floor(u)
+    return min(max(i, 0), n - 1), u
+
+
+@pytest.mark.parametrize("lo,hi,shape,exact", [
+    ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (24, 24, 24), True),
+    ((0.0, 0.0, 0.0), (1.0, 1.0, 2.0), (256, 256, 512), True),
+    ((-0.3, 0.1, 2.0), (0.7, 0.35, 2.9), (7, 5, 11), False),
+])
+def test_binning_matches_exact_rational(lo, hi, shape, exact):
+    rng = np.random.default_rng(1)
+    n = 3000
+    pos = (np.array(lo) + (np.array(hi) - np.array(lo)) * rng.random((n, 3))).astype(np.float32)
+    # points exactly on interior faces and on both walls
+    for a in range(3):
+        pos[a, a] = np.float32(lo[a])
+        pos[3 + a, a] = np.float32(hi[a])
+    cell, mask, _ = O.bin_hex(pos, lo, hi, shape)
+    nx, ny, _ = shape
+    for p in range(n):
+        if not mask[p]:
+            continue
+        ijk = []
+        near = False
+        for a in range(3):
+            i, u = _exact_bin(pos[p, a], lo[a], hi[a], shape[a])
+            ijk.append(i)
+            frac = u - math.floor(u)
+            near |= min(frac, 1 - frac) < Fraction(1, 10 ** 9)
+        want = ijk[0] + nx * (ijk[1] + ny * ijk[2])
+        if exact or not near:
+            assert cell[p] == want, (p, pos[p])
+
+
+def test_binning_drops_outside_and_nonfinite():
+    lo, hi, shape = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (4, 4, 4)
+    pos = np.array([[0.5, 0.5, 0.5], [1.0, 1.0, 1.0], [0.0, 0.0, 0.0],
+                    [1.0000001, 0.5, 0.5], [-1e-7, 0.5, 0.5], [np.nan, 0.5, 0.5],
+                    [0.5, np.inf, 0.5]], dtype=np.float32)
+    cell, mask, nonfinite = O.bin_hex(pos, lo, hi, shape)
+    assert mask.tolist() == [True, True, True, False, False, False, False]
+    assert nonfinite == 2
+    assert cell[1] == 63 and cell[2] == 0 and cell[0] == 2 + 4 * (2 + 4 * 2)
+
+
+def test_deposit_brute_force_per_cell():
+    """eq. pcm-k written out as a loop over cells, in exact rationals."""
+    rng = np.random.default_rng(2)
+    lo, hi, shape = (0.0, -1.0, 0.5), (1.0, 1.0, 1.25), (3, 4, 2)
+    n = 60
+    pos = (np.array(lo) + (np.array(hi) - np.array(lo)) * rng.random((n, 3))).astype(np.float32)
+    vals = rng.random((2, n)).astype(np.float32)
+    vals[1] -= 0.5
+    dep = O.deposit_hex(pos, vals, lo, hi, shape)
+    hx = [Fraction(hi[a]) - Fraction(lo[a]) for a in range(3)]
+    V = hx[0] * hx[1] * hx[2] / (shape[0] * shape[1] * shape[2])
+    for f in range(2):
+        for k in range(shape[0] * shape[1] * shape[2]):
+            ix, iy, iz = k % 3, (k // 3) % 4, k // 12
+            tot = Fraction(0)
+            for p in range(n):
+                cell = [_exact_bin(pos[p, a], lo[a], hi[a], shape[a])[0] for a in range(3)]
+                if cell == [ix, iy, iz]:
+                    tot += Fraction(float(vals[f, p]))
+            want = float(tot / V)
+            # quantisation error: at most n * 2^-(S+1) / V
+            tol = n * 2.0 ** (-dep["S"][f] - 1) / float(V)
+            assert abs(dep["field64"][f, k] - want) <= tol + 1e-15 * abs(want)
+
+
+def test_deposit_conserves_exactly_and_is_order_free():
+    w = inputs.tiny()
+    pos, vals = w.particles.pos, w.particles.values
+    dep = O.deposit_hex(pos, vals, w.box.lo, w.box.hi, w.box.shape)
+    q = O.quantise(vals[0], dep["S"][0])
+    assert int(dep["acc"][0].sum()) == int(q.sum())  # eq. conserve, exactly
+    perm = np.random.default_rng(3).permutation(len(pos))
+    dep2 = O.deposit_hex(pos[perm], vals[:, perm], w.box.lo, w.box.hi, w.box.shape)
+    assert np.array_equal(dep["acc"], dep2["acc"])
+    assert np.array_equal(dep["field32"].view(np.uint32), dep2["field32"].view(np.uint32))
+    V = O.hex_cell_volume(w.box.lo, w.box.hi, w.box.shape)
+    tot = dep["field64"][0].sum() * V
+    assert abs(tot - vals[0].astype(np.float64).sum()) <= 1e-12 * tot
+
+
+def test_frac_bits_never_overflows():
+    """Worst case: every particle at max |v| in one cell, all one sign."""
+    for n, v in [(1, 1.0), (5, 3.0e-9), (1 << 20, 0.999), (3000, -7.5e20)]:
+        vals = np.full(n, v, dtype=np.float32)
+        S = O.frac_bits(vals, n)
+        q = int(O.quantise(vals[:1], S)[0])
+        assert abs(q) * n < 2 ** 62 <= abs(q) * n * 8  # no overflow, and not wasteful
+    assert O.frac_bits(np.zeros(4, np.float32), 4) == 0
+    assert O.frac_bits(np.array([np.nan, 2.0], np.float32), 2) == O.frac_bits(np.array([0.0, 2.0]), 2)
+
+
+# ---------------------------------------------------------------- operator
+
+
+def test_hex_laplacian_entries_and_walls():
+    lo, hi, shape = (0.0, 0.0, 0.0), (0.3, 0.8, 1.5), (3, 4, 5)
+    hx, hy, hz = 0.1, 0.2, 0.3
+    K = O.hex_laplacian(shape, lo, hi).toarray()
+    assert np.allclose(K, K.T)
+    assert np.allclose(K.sum(axis=0), 0.0, atol=1e-12)
+    idx = lambda i, j, k: i + 3 * (j + 4 * k)
+    ax, ay, az = hy * hz / hx, hx * hz / hy, hx * hy / hz
+    # corner cell: one neighbour per axis, wall faces add nothing
+    assert math.isclose(K[0, 0], ax + ay + az)
+    assert math.isclose(K[0, idx(1, 0, 0)], -ax)
+    assert math.isclose(K[0, idx(0, 1, 0)], -ay)
+    assert math.isclose(K[0, idx(0, 0, 1)], -az)
+    # interior cell: two neighbours per axis
+    c = idx(1, 1, 1)
+    assert math.isclose(K[c, c], 2 * (ax + ay + az))
+    # no wrap-around between the end of one row and the start of the next
+    assert K[idx(2, 0, 0), idx(0, 1, 0)] == 0.0
+    assert K[idx(0, 3, 0), idx(0, 0, 1)] == 0.0
+    assert np.count_nonzero(K[idx(2, 3, 4)]) == 4
+
+
+def test_neumann_eigenvectors_explicit_cosine_sum():
+    """The 1-D zero-flux operator has eigenvectors cos(pi k (i+1/2)/n)."""
+    n, L = 13, 2.6
+    h = L / n
+    K = O.hex_laplacian((n, 1, 1), (0, 0, 0), (L, 1, 1)).toarray() / (h * 1 * 1)
+    lam = O.neumann_eigenvalues(n, h)
+    i = np.arange(n)
+    for k in range(n):
+        v = np.cos(np.pi * k * (i + 0.5) / n)
+        assert np.allclose(K @ v, lam[k] * v, atol=1e-10 * max(1, lam[k]))
+
+
+@pytest.mark.parametrize("shape,hi", [((17, 1, 1), (1.0, 1, 1)), ((6, 9, 1), (0.6, 1.8, 0.1)),
+                                      ((5, 6, 7), (1.0, 1.0, 1.0)), ((8, 4, 6), (0.8, 0.2, 1.2))])
+def test_cg_route_equals_dct_closed_form(shape, hi):
+    rng = np.random.default_rng(4)
+    n = shape[0] * shape[1] * shape[2]
+    f = rng.random((2, n))
+    f[1] -= 0.5
+    lo = (0.0, 0.0, 0.0)
+    b = 0.3 * max(hi)
+    a = O.diffuse_hex(f, lo, hi, shape, b, 3, solver="cg")
+    d = O.diffuse_hex(f, lo, hi, shape, b, 3, solver="direct")
+    c = O.diffuse_hex_dct(f, lo, hi, shape, b, 3)
+    assert np.abs(a - c).max() <= 1e-10 * np.abs(c).max()
+    assert np.abs(d - c).max() <= 1e-12 * np.abs(c).max()
+
+
+def test_thomas_textbook():
+    rng = np.random.default_rng(5)
+    n = 40
+    a, c = rng.random(n), rng.random(n)
+    b = 3 + rng.random(n)
+    d = rng.random(n)
+    A = np.diag(b) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+    assert np.allclose(O.thomas(a, b, c, d), np.linalg.solve(A, d), rtol=1e-13)
+    f = rng.random(n)
+    e1 = O.diffuse_1d_thomas(f, 3.0, 0.4, 5)
+    e2 = O.diffuse_hex(f, (0, 0, 0), (3.0, 1, 1), (n, 1, 1), 0.4, 5, solver="direct")
+    assert np.allclose(e1, e2, rtol=1e-12, atol=1e-14)
+
+
+def test_conservation_positivity_max_principle():
+    w = inputs.tiny()
+    dep = O.deposit_hex(w.particles.pos, w.particles.values, w.box.lo, w.box.hi, w.box.shape)
+    e0 = dep["field64"][0]
+    e = O.diffuse_hex(e0, w.box.lo, w.box.hi, w.box.shape, w.bandwidth, w.n_steps, solver="direct")
+    assert abs(e.sum() - e0.sum()) <= 1e-13 * e0.sum()       # eq. conserve under zero-flux walls
+    assert e.min() >= 0.0                                     # M-matrix: positivity
+    assert e.max() <= e0.max() and e.min() >= e0.min()        # maximum principle
+    # smoothing: a diffused field is flatter than the PCM field
+    assert e.std() < 0.5 * e0.std()
+
+
+# ---------------------------------------------------------------- equivalence with the kernel
+
+
+def test_kernel_normalisation_with_images():
+    """eq. normal on the whole space, and images restore it in a box (eq. hi-bound)."""
+    b = 0.13
+    x = np.linspace(-6 * b, 6 * b, 161)
+    dx = x[1] - x[0]
+    r2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
+    assert abs(O.gaussian_kernel(r2, b).sum() * dx ** 3 - 1) < 1e-10  # 3-D quadrature
+    rng = np.random.default_rng(6)
+    pos = rng.random((7, 3)) * np.array([1.0, 0.5, 0.25])
+    pos[0] = [0.001, 0.002, 0.249]  # in a corner: 8 kernels
+    vals = rng.random(7)
+    lo, hi, shape = (0, 0, 0), (1.0, 0.5, 0.25), (20, 10, 5)
+    ca = O.kernel_cell_average_hex(pos, vals, lo, hi, shape, 0.2)
+    V = O.hex_cell_volume(lo, hi, shape)
+    assert abs(ca.sum() * V - vals.sum()) < 1e-12
+    no_img = O.kernel_cell_average_1d(0.001, np.linspace(0, 1, 11), 0.2)
+    assert no_img.sum() * 0.1 < 0.6  # without images half the mass leaves the box
+
+
+def test_single_particle_converges_to_gaussian():
+    """Section 3.2: a delta diffused for T = b^2/4 is the kernel of eq. hi
+    with images; error falls like h^2 + dtau under refinement (dtau ~ h^2)."""
+    b = 0.15
+    errs = []
+    for n, steps in [(9, 1), (27, 9), (81, 81)]:
+        lo, hi, shape = (0, 0, 0), (1, 1, 1), (n, n, n)
+        pos = np.array([[0.5, 0.5, 0.5]])
+        vals = np.array([[1.0]])
+        dep = O.deposit_hex(pos, vals, lo, hi, shape)
+        e = O.diffuse_hex_dct(dep["field64"][0], lo, hi, shape, b, steps)
+        ref = O.kernel_cell_average_hex(pos, vals[0], lo, hi, shape, b)
+        errs.append(np.linalg.norm(e - ref) / np.linalg.norm(ref))
+    # h -> h/3 with dtau ~ h^2: second order predicts a factor 9 per level
+    assert errs[0] > 6 * errs[1] and errs[1] > 6 * errs[2], errs
+    assert errs[2] < 0.02
+    # the coarsest case also through the CG route
+    lo, hi, shape = (0, 0, 0), (1, 1, 1), (9, 9, 9)
+    dep = O.deposit_hex(np.array([[0.5, 0.5, 0.5]]), np.array([[1.0]]), lo, hi, shape)
+    e = O.diffuse_hex(dep["field64"][0], lo, hi, shape, b, 1)
+    ref = O.kernel_cell_average_hex(np.array([[0.5, 0.5, 0.5]]), [1.0], lo, hi, shape, b)
+    assert abs(np.linalg.norm(e - ref) / np.linalg.norm(ref) - errs[0]) < 1e-9
+
+
+def test_brute_force_kernel_sum_agrees_to_discretisation_error():
+    """eqs. superpo + hi + images summed over all particles and cells, against
+    the method on successively refined meshes: the gap shrinks monotonically."""
+    rng = np.random.default_rng(7)
+    n = 300
+    pos = rng.random((n, 3))
+    pos[:20, 0] *= 0.05  # some particles near a wall
+    vals = np.full(n, 1e-3)
+    lo, hi, b = (0, 0, 0), (1, 1, 1), 0.12
+    gaps = []
+    for m, steps in [(8, 1), (16, 4), (32, 16), (64, 64)]:
+        shape = (m, m, m)
+        dep = O.deposit_hex(pos.astype(np.float32), vals[None], lo, hi, shape)
+        e = O.diffuse_hex_dct(dep["field64"][0], lo, hi, shape, b, steps)
+        ref = O.kernel_cell_average_hex(pos.astype(np.float32).astype(np.float64), vals,
+                                        lo, hi, shape, b)
+        gaps.append(np.linalg.norm(e - ref) / np.linalg.norm(ref))
+    assert all(gaps[i] > 1.8 * gaps[i + 1] for i in range(3)), gaps
+    assert gaps[3] < 0.03, gaps
+
+
+def _gamma_setup(dx, b=6.0, steps=256):
+    n = int(round(135.0 / dx))
+    if n % 2 == 0:
+        n += 1  # odd, so the domain centre is a cell centre
+    L = n * dx
+    f = np.zeros(n)
+    f[n // 2] = 1.0 / dx  # one particle of unit length-volume at L/2
+    num = O.diffuse_1d_thomas(f, L, b, steps)
+    ana = O.kernel_cell_average_1d(L / 2, np.linspace(0, L, n + 1), b, 0, L)
+    return O.numerical_diffusion_gamma(num, ana)
+
+
+def test_numerical_diffusion_gamma_matches_paper_trend():
+    """Section 5.2: gamma = 0.6, 2.6, 8.1, 23.1 % at b/dx = 4, 2, 1, 0.5.
+
+    The paper's integrator (Crank-Nicolson, unstated step) differs, so the
+    check is the trend and the magnitude for b/dx = 4, 2, 1: monotone, each
+    within a factor 2 of the printed value (the semi-discrete limit, reached
+    here by many small backward-Euler steps).  The printed 23.1 % at
+    b/dx = 0.5 is not reproduced by any reading tried (cell-averaged kernel,
+    Crank-Nicolson or backward Euler, 1 to 100 steps: 4.6-5.8 %); that row
+    only checks that the value stays of order percent."""
+    rows = [l.split() for l in open(__file__.replace("test_oracle_pins.py", "golden/gamma_1d.txt"))
+            if l.strip() and not l.startswith("#")]
+    got = []
+    for ratio, dx, pct in rows[:3]:
+        g = 100 * _gamma_setup(float(dx))
+        got.append(g)
+        assert float(pct) / 2 <= g <= float(pct) * 2, (ratio, g, pct)
+    assert got == sorted(got)
+    g05 = 100 * _gamma_setup(float(rows[3][1]))
+    assert 1.0 < g05 < float(rows[3][2])
+
+
+def test_time_step_study():
+    """Section 5.1 (dtau = T/8, T/3, T almost identical): with backward Euler
+    the fields stay close and approach each other as dtau shrinks."""
+    w = inputs.tiny()
+    dep = O.deposit_hex(w.particles.pos, w.particles.values, w.box.lo, w.box.hi, w.box.shape)
+    e0 = dep["field64"][0]
+    r = {k: O.diffuse_hex_dct(e0, w.box.lo, w.box.hi, w.box.shape, 0.1, k) for k in (1, 3, 8, 64)}
+    d = lambda a, c: np.linalg.norm(r[a] - r[c]) / np.linalg.norm(r[c])
+    assert d(8, 64) < d(3, 64) < d(1, 64) < 0.15
+
+
+def test_mesh_convergence_no_overshoot():
+    """Section 4.4: refined meshes agree more and more; no cell exceeds the
+    largest PCM value, even on cells smaller than a particle."""
+    rng = np.random.default_rng(8)
+    pos = (rng.random((2000, 3)) * 0.6 + 0.2).astype(np.float32)
+    vals = np.full((1, 2000), 4.2e-4, np.float32)
+    lo, hi, b = (0, 0, 0), (1, 1, 1), 0.1
+    coarse = []
+    for m in (10, 20, 40, 80):
+        shape = (m, m, m)
+        dep = O.deposit_hex(pos, vals, lo, hi, shape)
+        e = O.diffuse_hex_dct(dep["field64"][0], lo, hi, shape, b, 4)
+        assert e.max() <= dep["field64"][0].max()
+        k = m // 10  # average onto the 10^3 mesh for comparison
+        coarse.append(e.reshape(10, k, 10, k, 10, k).mean(axis=(1, 3, 5)).ravel())
+    diffs = [np.linalg.norm(coarse[i + 1] - coarse[i]) for i in range(3)]
+    assert diffs[0] > diffs[1] > diffs[2]
+
+
+# ---------------------------------------------------------------- tetrahedra
+
+
+def test_kuhn_mesh_conforming_positive():
+    xyz, tets = inputs.kuhn_tet_mesh(6, 0.2, seed=9)
+    V, det = O.tet_volumes(xyz, tets)
+    assert (det > 0).all()
+    assert abs(V.sum() - 1.0) < 1e-12
+    P, N, _ = O.tet_faces(tets)
+    assert len(P) == (4 * len(tets) - 12 * 6 * 6) // 2   # interior faces shared by 2
+    xyz0, tets0 = inputs.kuhn_tet_mesh(6, 0.0)
+    V0, _ = O.tet_volumes(xyz0, tets0)
+    assert np.allclose(V0, 1 / (6 * 216))
+
+
+def test_tpfa_properties():
+    xyz, tets = inputs.kuhn_tet_mesh(5, 0.2, seed=10)
+    K, V = O.tet_tpfa(xyz, tets)
+    Kd = K.toarray()
+    assert np.allclose(Kd, Kd.T)
+    assert np.allclose(Kd.sum(axis=1), 0, atol=1e-14)
+    off = Kd - np.diag(np.diag(Kd))
+    assert (off <= 0).all() and (np.count_nonzero(off, axis=1) <= 4).all()
+    # on an unjittered Kuhn mesh, a_f = |A_f| / |c_N - c_P| by hand for one face
+    xyz0, tets0 = inputs.kuhn_tet_mesh(1, 0.0)
+    K0, _ = O.tet_tpfa(xyz0, tets0)
+    P, N, tri = O.tet_faces(tets0)
+    c = xyz0[tets0].mean(axis=1)
+    a, bb, cc = xyz0[tri[0]]
+    area = 0.5 * np.linalg.norm(np.cross(bb - a, cc - a))
+    assert math.isclose(-K0[P[0], N[0]], area / np.linalg.norm(c[P[0]] - c[N[0]]))
+
+
+def test_point_location_against_barycentric_brute_force():
+    xyz, tets = inputs.kuhn_tet_mesh(4, 0.2, seed=11)
+    rng = np.random.default_rng(12)
+    pts = rng.random((400, 3))
+    pts[:8] = xyz[tets[:8, 0]]  # on vertices: shared by many tets, lowest id wins
+    got = O.locate_tets(xyz, tets, pts)
+    T = xyz[tets]
+    for i, p in enumerate(pts):
+        inside = []
+        for t in range(len(tets)):
+            A = (T[t, 1:] - T[t, 0]).T
+            lam = np.linalg.solve(A, p - T[t, 0])
+            bary = np.concatenate([[1 - lam.sum()], lam])
+            if (bary >= -1e-12).all():
+                inside.append(t)
+        assert inside, i
+        if min(abs(np.linalg.solve((T[got[i], 1:] - T[got[i], 0]).T, p - T[got[i], 0]))) > 1e-9 \
+                and i >= 8:
+            assert got[i] == inside[0] and len(inside) == 1
+        else:
+            assert got[i] in inside and got[i] == min(inside)
+
+
+def test_tet_diffusion_approaches_kernel_closed_form():
+    """Unstructured meshes (Section 4.3): on unjittered Kuhn meshes a single
+    particle's diffused field, summed back onto the hexes, approaches the
+    cell-averaged Gaussian under refinement; conservation holds."""
+    b = 0.3
+    errs = []
+    for n, steps in [(3, 1), (9, 9)]:
+        xyz, tets = inputs.kuhn_tet_mesh(n, 0.0)
+        pos = np.array([[0.5, 0.5, 0.5]])
+        dep = O.deposit_tet(xyz, tets, pos, np.array([[1.0]]))
+        K, V = O.tet_tpfa(xyz, tets)
+        e = O.diffuse_tet(dep["field64"][0], xyz, tets, b, steps, solver="direct")
+        assert abs((e * V).sum() - 1.0) < 1e-12
+        hexv = (e * V).reshape(-1, 6).sum(axis=1) * n ** 3  # per-hex average
+        hexv = hexv.reshape(n, n, n).ravel()
+        ref = O.kernel_cell_average_hex(pos, [1.0], (0, 0, 0), (1, 1, 1), (n, n, n), b)
+        errs.append(np.linalg.norm(hexv - ref) / np.linalg.norm(ref))
+    assert errs[1] < 0.5 * errs[0], errs
