@@ -1,0 +1,185 @@
+"""Throughput of diffusion-based coarse graining on one MI355X.
+
+One step = one cgd_coarse_grain call over the dense particle bed: PCM
+deposition of 20M particles into a 256 x 256 x 512 hex mesh (box 1 x 1 x 2,
+h = 1/256), then 4 backward-Euler pseudo-steps of T = b^2/4 with b = 4h,
+each a CG solve to rtol 1e-6.  Inputs are resident in HBM before timing.
+value = fields coarse-grained per second.
+
+Prints one JSON line.  Also reports:
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                mean duration (HIP events on the library's stream), vs 8 TB/s
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same recipe
+  rel_l2        accuracy of the timed result against the float64 oracle
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "coarse-grained fields/sec at 256^3, 20M particles, rel L2<=1e-5 vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fields", type=int, default=1, help="1: volume; 4: volume + 3 drag components")
+    ap.add_argument("--particles", type=int, default=20_000_000)
+    ap.add_argument("--shape", default="256,256,512")
+    ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--check-every", type=int, default=4)
+    ap.add_argument("--no-check", action="store_true", help="skip the float64 accuracy check")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def traffic_from_profiles(kernel_src):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "cg_sweep_traffic_dense_bed.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    if d.get("source_sha256") != sha:
+        return None
+    return d
+
+
+def cpu_baseline(args):
+    """The oracle as it stands (float64, scipy CG), single thread, on the
+    dense-bed recipe at 1/8 of the cells and particles; scaled to fields/s
+    of the full workload by the cell ratio."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cgd_oracle as O
+    from paper_1409_0001_amd import inputs
+    nx, ny, nz = (int(v) for v in args.shape.split(","))
+    sx, sy, sz = nx // 2, ny // 2, nz // 2
+    ratio = (nx * ny * nz) / (sx * sy * sz)
+    w = inputs.dense_bed(n_particles=int(args.particles / ratio), shape=(sx, sy, sz), n_fields=1)
+    with threadpool_limits(1):
+        t = time.perf_counter()
+        O.coarse_grain_hex(w.particles.pos, w.particles.values, w.box.lo, w.box.hi, w.box.shape,
+                           w.bandwidth, w.n_steps, rtol=1e-12)
+        dt = time.perf_counter() - t
+    return {"value": 1.0 / (dt * ratio), "unit": "fields/s", "cores": 1, "kind": "oracle",
+            "sample": f"dense-bed recipe at {sx}x{sy}x{sz} cells, {w.particles.pos.shape[0]} particles "
+                      f"(1/{ratio:g} of the workload), 1 field, deposit + 4 backward-Euler steps by "
+                      f"float64 CG to 1e-12; {dt:.1f} s, scaled by the cell ratio"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1409_0001_amd as cgd
+    from paper_1409_0001_amd import inputs
+
+    if args.profile_copy:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}))
+        return
+
+    shape = tuple(int(v) for v in args.shape.split(","))
+    t0 = time.perf_counter()
+    w = inputs.dense_bed(n_particles=args.particles, shape=shape, n_fields=args.fields)
+    print(f"[bench] inputs {w.name} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    pos = torch.from_numpy(w.particles.pos).cuda()
+    vals = torch.from_numpy(w.particles.values).cuda()
+    mesh = cgd.HexMesh(w.box.shape, w.box.lo, w.box.hi)
+    out = torch.empty((args.fields, mesh.cells), dtype=torch.float32, device="cuda")
+    kw = dict(rtol=args.rtol, check_every=args.check_every, field=out)
+
+    for _ in range(args.warmup):
+        cgd.coarse_grain(mesh, pos, vals, w.bandwidth, w.n_steps, **kw)
+    _, st = cgd.coarse_grain(mesh, pos, vals, w.bandwidth, w.n_steps, stats=True, **kw)
+    iters = [row[0] for row in st.iters]
+    print(f"[bench] warm: CG iterations per step {iters}", file=sys.stderr, flush=True)
+
+    cgd.timing_enable(mesh, True)
+    cgd.timing_read(mesh, reset=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        cgd.coarse_grain(mesh, pos, vals, w.bandwidth, w.n_steps, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    cgd.timing_enable(mesh, False)
+    tim = cgd.timing_read(mesh, reset=True)
+    ms_per_step = 1e3 * dt / args.steps
+    value = args.fields * args.steps / dt
+    print(f"[bench] {ms_per_step:.2f} ms/step, {value:.2f} fields/s", file=sys.stderr, flush=True)
+
+    # dominant kernel: the CG sweep with the most total time
+    dom = max(("cg_sweep1", "cg_sweep2"), key=lambda k: tim[k][1])
+    launches, total_ms, bpl = tim[dom]
+    avg_ms = total_ms / max(launches, 1)
+    achieved = bpl / (avg_ms * 1e-3) / 1e9
+    kernel_src = os.path.join(ROOT, "paper_1409_0001_amd", "csrc", "cg_hex.hip")
+    tr = traffic_from_profiles(kernel_src)
+    traffic = None
+    if tr and dom in tr.get("kernels", {}):
+        traffic = tr["kernels"][dom]["hbm_bytes_per_launch"]
+    other = "cg_sweep1" if dom == "cg_sweep2" else "cg_sweep2"
+    o_l, o_ms, o_b = tim[other]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dom, "launches": launches, "avg_us": round(avg_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": bpl,
+                "other_sweep": {"kernel": other, "avg_us": round(o_ms / max(o_l, 1) * 1e3, 2),
+                                "achieved_GBs": round(o_b / (o_ms / max(o_l, 1) * 1e-3) / 1e9, 1)
+                                if o_l else None},
+                "deposit": {"launches": tim["deposit"][0],
+                            "avg_us": round(tim["deposit"][1] / max(tim["deposit"][0], 1) * 1e3, 2)}}
+
+    rel = None
+    if not args.no_check:
+        from oracle import cgd_oracle as O
+        dep = O.deposit_hex(w.particles.pos, w.particles.values, w.box.lo, w.box.hi, w.box.shape)
+        ref = O.diffuse_hex_dct(dep["field64"], w.box.lo, w.box.hi, w.box.shape, w.bandwidth, w.n_steps)
+        got = out.cpu().numpy().astype(np.float64)
+        rel = max(float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])) for f in range(args.fields))
+        print(f"[bench] rel L2 vs float64 oracle {rel:.3e}", file=sys.stderr, flush=True)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args)
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "fields/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"dense bed {shape[0]}x{shape[1]}x{shape[2]} hex, box 1x1x2, "
+                               f"{args.particles} particles, F={args.fields}, b=4h, 4 backward-Euler "
+                               f"steps, CG rtol {args.rtol:g}",
+                   "particles": args.particles, "cells": int(mesh.cells), "fields": args.fields,
+                   "cg_iters_per_step": iters},
+        "rel_l2": rel,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

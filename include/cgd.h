@@ -1,0 +1,193 @@
+/*
+ * cgd.h - C-ABI of libcgd: diffusion-based coarse graining on MI355X (gfx950).
+ *
+ * The method (Sun & Xiao, "Diffusion-based coarse graining in hybrid
+ * continuum-discrete solvers", Section 2.6): particle quantities are first
+ * deposited into the mesh cells that contain the particle centroids (the
+ * particle centroid method, Section 2.2, eq. pcm-k); the resulting cell field
+ * is then diffused for a pseudo-time T = b^2 / 4 (Section 3.2.1: with this T
+ * the heat kernel equals the Gaussian kernel of bandwidth b, eq. hi) with
+ * zero-flux walls (Section 3.2.2).  Diffusion is integrated here by n equal
+ * backward-Euler pseudo-steps, each an implicit solve of the finite-volume
+ * Laplacian system (M + dtau K) e^{n+1} = M e^n (Section 5.1 describes the
+ * spatial discretisation; the paper integrates with Crank-Nicolson).
+ *
+ * Conventions shared by every entry point:
+ *  - All particle and field arrays are DEVICE pointers owned by the caller;
+ *    the library never frees them.  Positions are float32 [n, 3] (x, y, z
+ *    interleaved); per-particle values are float32 [F, n]; cell fields are
+ *    float32 [F, cells].  Hex cells are numbered x fastest:
+ *    k = ix + nx * (iy + ny * iz).  Tet cells follow the caller's tet order.
+ *  - A cell field is a density: the value summed over the cell's particles
+ *    divided by the cell volume, so sum_k field_k V_k = sum_p value_p
+ *    (eq. conserve).
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL is the
+ *    default stream) on the device the mesh was created on.
+ *  - Arguments are validated on the host before anything is enqueued; a
+ *    negative status means nothing was written.  No C++ exception or abort
+ *    crosses this boundary.  cgd_last_error() gives a text for the last
+ *    failing call on the calling thread.
+ *  - A mesh must not be used by two calls at the same time (it owns the
+ *    workspace the calls use).
+ */
+#ifndef CGD_H
+#define CGD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cgd_status;
+
+#define CGD_OK                  0
+#define CGD_NOT_CONVERGED       1   /* a solve hit max_iter; result = last iterate */
+#define CGD_WARMSTART_FALLBACK  2   /* a learned initial guess was rejected; zero guess used */
+#define CGD_E_INVALID          -1   /* bad argument (null, size, shape, b <= 0, n_steps < 1 ...) */
+#define CGD_E_NONFINITE        -2   /* NaN/Inf among positions or values (those particles skipped) */
+#define CGD_E_NOMEM            -3   /* device or pinned-host allocation failed */
+#define CGD_E_HIP              -4   /* a HIP runtime call failed; cgd_last_error() has its text */
+#define CGD_E_BREAKDOWN        -5   /* CG breakdown: p.Ap <= 0 or a non-finite scalar */
+#define CGD_E_UNSUPPORTED      -6   /* operation not available for this mesh kind */
+
+#define CGD_MAX_FIELDS 16
+#define CGD_MAX_STEPS  64
+
+typedef struct cgd_mesh_s* cgd_mesh;
+
+/* Uniform hex mesh of the box [lo, hi] with nx * ny * nz cells (zero-flux
+ * walls on all six faces).  lo, hi are host arrays of 3 doubles, hi > lo.
+ * The mesh lives on the current HIP device.  Returns CGD_E_INVALID for
+ * non-positive sizes or an empty box. */
+cgd_status cgd_mesh_create_hex(int32_t nx, int32_t ny, int32_t nz,
+                               const double lo[3], const double hi[3], cgd_mesh* out);
+
+/* Tetrahedral mesh (Section 2.1 item 4: arbitrary unstructured meshes).
+ * xyz: host float64 [n_vert, 3]; tv: host int32 [n_tet, 4] vertex ids, each
+ * tet with positive orientation det[v1-v0, v2-v0, v3-v0] > 0 (checked:
+ * CGD_E_INVALID otherwise).  Builds on the host, once: tet volumes, the
+ * two-point-flux Laplacian a_f = |A_f| / |c_N - c_P| over interior faces
+ * (boundary faces carry no flux) as CSR (float32 values, int32 columns),
+ * face adjacency and a point-location grid; then copies them to the device. */
+cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz,
+                               int64_t n_tet, const int32_t* tv, cgd_mesh* out);
+
+void    cgd_mesh_destroy(cgd_mesh m);
+int64_t cgd_mesh_num_cells(cgd_mesh m);
+/* 0 = hex, 1 = tet, -1 = NULL mesh */
+int32_t cgd_mesh_kind(cgd_mesh m);
+/* Tet meshes: number of stored non-zeros of the CSR matrix (0 for hex). */
+int64_t cgd_mesh_nnz(cgd_mesh m);
+
+typedef struct {
+    double  rtol;         /* stop when ||r||_2 <= rtol ||b||_2 (per field, per step); <= 0: 1e-6 */
+    int32_t max_iter;     /* per step; <= 0: 1000 */
+    int32_t x0_mode;      /* 0: zero initial guess; 1: previous pseudo-step's solution;
+                             2: caller's guess x0 for the first step (zero after) */
+    const float* x0;      /* device [F, cells] when x0_mode == 2, else NULL */
+    int32_t check_every;  /* iterations enqueued between convergence read-backs; <= 0: 4 */
+    int32_t reserved;
+} cgd_solver_opts;
+
+typedef struct {
+    int32_t n_steps, n_fields;
+    int32_t iters[CGD_MAX_STEPS][CGD_MAX_FIELDS];     /* CG iterations per step and field */
+    double  rel_res[CGD_MAX_STEPS][CGD_MAX_FIELDS];   /* recursive ||r|| / ||b|| at exit */
+    double  mass_before[CGD_MAX_FIELDS];              /* sum_k V_k field_k before diffusion */
+    double  mass_after[CGD_MAX_FIELDS];               /* ... and after (equal up to rtol) */
+    int32_t frac_bits[CGD_MAX_FIELDS];                /* fixed-point scale S used by deposit */
+    int64_t n_dropped;                                /* particles outside the mesh / non-finite */
+    int64_t n_nonfinite;                              /* non-finite positions or values */
+    int32_t status;
+    int32_t reserved;
+} cgd_solve_stats;
+
+/* Particle centroid method (Section 2.2, eq. pcm-k), bit-exact.
+ *
+ * Each particle p with a finite position inside the closed mesh domain is
+ * assigned to the cell containing its centroid (hex: i_a = floor((x_a - lo_a)
+ * * s_a), s_a = N_a / (hi_a - lo_a) in float64, clamped to [0, N_a - 1]; a
+ * point on an interior face goes to the upper cell; tet: the containing tet,
+ * lowest id on ties).  Its value v of field f is quantised to
+ * q = rint(v * 2^S_f) (int64, round half to even) with S_f = 62 - e_max - e_N
+ * (max_p |v_p| <= 2^e_max over finite values, e_N = ceil(log2 n)), so that no
+ * sum can overflow, and added with integer atomics: the sums are exact and
+ * independent of particle order.  Then field[f, k] = float32(acc * 2^-S_f / V_k).
+ *
+ *  n:       number of particles (>= 0)
+ *  pos:     device float32 [n, 3]
+ *  F:       number of fields, 1..CGD_MAX_FIELDS
+ *  values:  device float32 [F, n]
+ *  field:   device float32 [F, cells], written
+ *  acc:     device int64 [F, cells] (written: the raw fixed-point sums) or NULL
+ *  st:      host, nullable.  Non-NULL makes the call wait for the stream and
+ *           fill frac_bits / n_dropped / n_nonfinite; the call then returns
+ *           CGD_E_NONFINITE if any non-finite position or value was seen.
+ *           With st == NULL the call is asynchronous and non-finite particles
+ *           are skipped silently. */
+cgd_status cgd_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F,
+                       const float* values, float* field, int64_t* acc,
+                       cgd_solve_stats* st, void* stream);
+
+/* Diffusion of F cell fields in place (Sections 3.1, 3.2, 5.1).
+ *
+ * T = bandwidth^2 / 4, dtau = T / n_steps; each of the n_steps backward-Euler
+ * steps solves (M + dtau K) e^{n+1} = M e^n by conjugate gradients with float32
+ * vectors and float64 inner products (hex: matrix-free 7-point stencil;
+ * tet: CSR with Jacobi preconditioning).  Zero-flux walls: wall faces carry
+ * no flux.  Fields are independent solves (Section 3.2.1: each component is
+ * diffused on its own).
+ *
+ *  field:     device float32 [F, cells], in: deposited field, out: diffused field
+ *  bandwidth: Gaussian-kernel bandwidth b > 0 in domain length units
+ *  n_steps:   1..CGD_MAX_STEPS
+ *  o:         solver options, nullable (defaults)
+ *  st:        host, nullable: iteration counts, residuals, mass before/after
+ *
+ * The convergence test is read back every o->check_every iterations, so the
+ * call returns to the host about when the last step has converged.  Returns
+ * CGD_NOT_CONVERGED if some solve hit max_iter (result = last iterate) and
+ * CGD_E_BREAKDOWN on a breakdown. */
+cgd_status cgd_diffuse(cgd_mesh m, int32_t F, float* field, double bandwidth,
+                       int32_t n_steps, const cgd_solver_opts* o,
+                       cgd_solve_stats* st, void* stream);
+
+/* cgd_deposit followed by cgd_diffuse (Section 2.6): the whole method.
+ * field: device float32 [F, cells], written. */
+cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F,
+                            const float* values, double bandwidth, int32_t n_steps,
+                            const cgd_solver_opts* o, float* field,
+                            cgd_solve_stats* st, void* stream);
+
+/* Kernel timing, for roofline measurement.  While enabled, each launch of the
+ * timed kernels is bracketed by two HIP events recorded on the caller's
+ * stream; the elapsed times are collected when the call synchronises (every
+ * cgd_diffuse / cgd_coarse_grain does at its end).  Kinds:
+ *   0  CG sweep 1 (p = r + beta p_old, A p, p.Ap), hex stencil
+ *   1  CG sweep 2 (x += alpha p, r -= alpha A p, r.r), hex stencil
+ *   2  centroid binning + fixed-point atomic deposit (hex)
+ *   3  CSR sweep of the tet Jacobi-PCG (SpMV + dots)
+ *   4  CSR update sweep of the tet Jacobi-PCG
+ * bytes_per_launch is the algorithmic byte count of the last timed launch of
+ * that kind (what the method must move, not what the hardware moved). */
+#define CGD_TIMING_KINDS 8
+typedef struct {
+    int64_t launches[CGD_TIMING_KINDS];
+    double  total_ms[CGD_TIMING_KINDS];
+    double  bytes_per_launch[CGD_TIMING_KINDS];
+} cgd_kernel_timing;
+
+cgd_status cgd_timing_enable(cgd_mesh m, int32_t on);
+/* Copies the accumulated timings to *out; reset != 0 clears them. */
+cgd_status cgd_timing_read(cgd_mesh m, cgd_kernel_timing* out, int32_t reset);
+
+const char* cgd_status_string(cgd_status s);
+const char* cgd_last_error(void);
+/* Library version as an integer (major * 10000 + minor * 100 + patch). */
+int32_t     cgd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CGD_H */

@@ -1,1 +1,232 @@
-"""MI355X-native diffusion-based coarse graining (placeholder; binding below)."""
+"""MI355X-native diffusion-based coarse graining (Sun & Xiao).
+
+Thin Python binding over the libcgd C-ABI (include/cgd.h).  It only checks
+and marshals arguments: every step of the method runs in the library's HIP
+kernels.  torch tensors provide device memory and the current stream.
+
+    import paper_1409_0001_amd as cgd
+    mesh = cgd.HexMesh((256, 256, 512), lo=(0, 0, 0), hi=(1, 1, 2))
+    field, stats = cgd.coarse_grain(mesh, pos, values, bandwidth=4/256, n_steps=4)
+
+There is no CPU fallback: the calls raise if libcgd.so is missing or no GPU
+is visible.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+from . import _abi
+
+load = _abi.load
+
+
+class CgdError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = _abi.load()
+        name = lib.cgd_status_string(status).decode()
+        msg = lib.cgd_last_error().decode()
+        super().__init__(f"{where}: {name} ({status}): {msg}")
+        self.status = status
+
+
+@dataclasses.dataclass
+class Stats:
+    status: int
+    iters: list           # [n_steps][F]
+    rel_res: list         # [n_steps][F]
+    mass_before: list     # [F]
+    mass_after: list      # [F]
+    frac_bits: list       # [F]
+    n_dropped: int
+    n_nonfinite: int
+
+
+def _stats(st: _abi.SolveStats, F: int, n_steps: int, status: int) -> Stats:
+    return Stats(status=status,
+                 iters=[[st.iters[s][f] for f in range(F)] for s in range(n_steps)],
+                 rel_res=[[st.rel_res[s][f] for f in range(F)] for s in range(n_steps)],
+                 mass_before=[st.mass_before[f] for f in range(F)],
+                 mass_after=[st.mass_after[f] for f in range(F)],
+                 frac_bits=[st.frac_bits[f] for f in range(F)],
+                 n_dropped=int(st.n_dropped), n_nonfinite=int(st.n_nonfinite))
+
+
+def _check(status: int, where: str, allow=(_abi.OK, _abi.NOT_CONVERGED, _abi.WARMSTART_FALLBACK)):
+    if status not in allow:
+        raise CgdError(status, where)
+    return status
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_1409_0001_amd needs a visible HIP GPU (no CPU fallback)")
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, shape, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor on the GPU")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """Owner of a cgd_mesh handle (device topology + workspace)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        lib = _abi.load()
+        self.cells = int(lib.cgd_mesh_num_cells(handle))
+        self.kind = int(lib.cgd_mesh_kind(handle))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _abi.load().cgd_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HexMesh(Mesh):
+    """Uniform hex mesh of the box [lo, hi] with shape = (nx, ny, nz) cells."""
+
+    def __init__(self, shape, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+        _torch()
+        lib = _abi.load()
+        lo_a = (ctypes.c_double * 3)(*[float(v) for v in lo])
+        hi_a = (ctypes.c_double * 3)(*[float(v) for v in hi])
+        h = _abi.c_mesh()
+        _check(lib.cgd_mesh_create_hex(int(shape[0]), int(shape[1]), int(shape[2]), lo_a, hi_a,
+                                       ctypes.byref(h)), "cgd_mesh_create_hex", allow=(0,))
+        self.shape = tuple(int(s) for s in shape)
+        self.lo = tuple(float(v) for v in lo)
+        self.hi = tuple(float(v) for v in hi)
+        super().__init__(h)
+
+
+class TetMesh(Mesh):
+    """Tetrahedral mesh from host arrays xyz float64 [V, 3] and tets int32 [T, 4]."""
+
+    def __init__(self, xyz, tets):
+        import numpy as np
+        _torch()
+        lib = _abi.load()
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        if xyz.ndim != 2 or xyz.shape[1] != 3 or tets.ndim != 2 or tets.shape[1] != 4:
+            raise ValueError("xyz must be [V, 3] and tets [T, 4]")
+        h = _abi.c_mesh()
+        _check(lib.cgd_mesh_create_tet(xyz.shape[0], xyz.ctypes.data, tets.shape[0], tets.ctypes.data,
+                                       ctypes.byref(h)), "cgd_mesh_create_tet", allow=(0,))
+        super().__init__(h)
+        self.nnz = int(lib.cgd_mesh_nnz(h))
+
+
+def _opts(rtol, max_iter, x0_mode, x0, check_every):
+    o = _abi.SolverOpts()
+    o.rtol = float(rtol)
+    o.max_iter = int(max_iter)
+    o.x0_mode = int(x0_mode)
+    o.x0 = x0.data_ptr() if x0 is not None else None
+    o.check_every = int(check_every)
+    return o
+
+
+def deposit(mesh: Mesh, pos, values, field=None, acc=None, stats=False, stream=None):
+    """Particle centroid method (bit-exact).  pos [N, 3] f32, values [F, N] f32.
+
+    Returns field [F, cells] (and Stats when stats=True, which synchronises)."""
+    torch = _torch()
+    lib = _abi.load()
+    n = int(pos.shape[0])
+    F = int(values.shape[0])
+    p_pos = _dev(pos, torch.float32, (n, 3), "pos")
+    p_val = _dev(values, torch.float32, (F, n), "values")
+    if field is None:
+        field = torch.empty((F, mesh.cells), dtype=torch.float32, device=pos.device)
+    p_field = _dev(field, torch.float32, (F, mesh.cells), "field")
+    p_acc = _dev(acc, torch.int64, (F, mesh.cells), "acc") if acc is not None else None
+    st = _abi.SolveStats() if stats else None
+    rc = lib.cgd_deposit(mesh.handle, n, p_pos, F, p_val, p_field, p_acc,
+                         ctypes.byref(st) if st is not None else None, _stream_ptr(stream))
+    _check(rc, "cgd_deposit", allow=(0,) if not stats else (0, _abi.E_NONFINITE))
+    if stats:
+        return field, _stats(st, F, 0, rc)
+    return field
+
+
+def diffuse(mesh: Mesh, field, bandwidth, n_steps, rtol=1e-6, max_iter=1000, x0_mode=0, x0=None,
+            check_every=4, stats=False, stream=None):
+    """Diffuses field [F, cells] in place for T = bandwidth^2 / 4 in n_steps
+    backward-Euler steps.  Returns (field, Stats or None)."""
+    torch = _torch()
+    lib = _abi.load()
+    F = int(field.shape[0])
+    p_field = _dev(field, torch.float32, (F, mesh.cells), "field")
+    if x0 is not None:
+        _dev(x0, torch.float32, (F, mesh.cells), "x0")
+    o = _opts(rtol, max_iter, x0_mode, x0, check_every)
+    st = _abi.SolveStats() if stats else None
+    rc = lib.cgd_diffuse(mesh.handle, F, p_field, float(bandwidth), int(n_steps), ctypes.byref(o),
+                         ctypes.byref(st) if st is not None else None, _stream_ptr(stream))
+    _check(rc, "cgd_diffuse")
+    return field, (_stats(st, F, n_steps, rc) if stats else None)
+
+
+def coarse_grain(mesh: Mesh, pos, values, bandwidth, n_steps, rtol=1e-6, max_iter=1000, x0_mode=0,
+                 check_every=4, field=None, stats=False, stream=None):
+    """The whole method (Section 2.6): PCM deposition, then diffusion.
+    Returns (field [F, cells], Stats or None)."""
+    torch = _torch()
+    lib = _abi.load()
+    n = int(pos.shape[0])
+    F = int(values.shape[0])
+    p_pos = _dev(pos, torch.float32, (n, 3), "pos")
+    p_val = _dev(values, torch.float32, (F, n), "values")
+    if field is None:
+        field = torch.empty((F, mesh.cells), dtype=torch.float32, device=pos.device)
+    p_field = _dev(field, torch.float32, (F, mesh.cells), "field")
+    o = _opts(rtol, max_iter, x0_mode, None, check_every)
+    st = _abi.SolveStats() if stats else None
+    rc = lib.cgd_coarse_grain(mesh.handle, n, p_pos, F, p_val, float(bandwidth), int(n_steps),
+                              ctypes.byref(o), p_field, ctypes.byref(st) if st is not None else None,
+                              _stream_ptr(stream))
+    _check(rc, "cgd_coarse_grain")
+    return field, (_stats(st, F, n_steps, rc) if stats else None)
+
+
+TIMING_KINDS = {0: "cg_sweep1", 1: "cg_sweep2", 2: "deposit", 3: "pcg_spmv_sweep", 4: "pcg_update_sweep"}
+
+
+def timing_enable(mesh: Mesh, on: bool = True):
+    """Brackets the timed kernels of later calls on this mesh with HIP events."""
+    _check(_abi.load().cgd_timing_enable(mesh.handle, int(bool(on))), "cgd_timing_enable", allow=(0,))
+
+
+def timing_read(mesh: Mesh, reset: bool = False) -> dict:
+    """{kind name: (launches, total_ms, algorithmic bytes per launch)}."""
+    t = _abi.KernelTiming()
+    _check(_abi.load().cgd_timing_read(mesh.handle, ctypes.byref(t), int(bool(reset))),
+           "cgd_timing_read", allow=(0,))
+    return {name: (int(t.launches[k]), float(t.total_ms[k]), float(t.bytes_per_launch[k]))
+            for k, name in TIMING_KINDS.items()}

@@ -1,0 +1,416 @@
+// C-ABI entry points of libcgd: argument validation, mesh objects and their
+// workspace, and the order of device work.  No exception crosses the ABI.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "cgd_internal.h"
+
+namespace cgd {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+cgd_status ensure_workspace(cgd_mesh m, size_t bytes) {
+    if (m->ws.bytes >= bytes) return CGD_OK;
+    if (m->ws.ptr) {
+        CGD_HIP_TRY(hipDeviceSynchronize());
+        CGD_HIP_TRY(hipFree(m->ws.ptr));
+        m->ws.ptr = nullptr;
+        m->ws.bytes = 0;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("workspace allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+        return CGD_E_NOMEM;
+    }
+    m->ws.ptr = p;
+    m->ws.bytes = bytes;
+    return CGD_OK;
+}
+
+cgd_status ensure_pinned(cgd_mesh m, size_t bytes) {
+    if (m->pinned_bytes >= bytes) return CGD_OK;
+    if (m->pinned) {
+        CGD_HIP_TRY(hipDeviceSynchronize());
+        CGD_HIP_TRY(hipHostFree(m->pinned));
+        m->pinned = nullptr;
+        m->pinned_bytes = 0;
+    }
+    void* p = nullptr;
+    hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(std::string("pinned host allocation failed: ") + hipGetErrorString(e));
+        return CGD_E_NOMEM;
+    }
+    memset(p, 0, bytes);
+    m->pinned = p;
+    m->pinned_bytes = bytes;
+    return CGD_OK;
+}
+
+int timing_begin(Timing* t, hipStream_t s) {
+    if (!t->on) return -1;
+    hipEvent_t e[2];
+    for (int i = 0; i < 2; ++i) {
+        if (t->pool.empty()) {
+            if (hipEventCreate(&e[i]) != hipSuccess) return -1;
+        } else {
+            e[i] = t->pool.back();
+            t->pool.pop_back();
+        }
+    }
+    (void)hipEventRecord(e[0], s);
+    t->used.push_back(e[0]);
+    t->used.push_back(e[1]);
+    return (int)t->used.size() - 2;
+}
+
+void timing_end(Timing* t, int idx, int kind, double bytes, hipStream_t s) {
+    if (idx < 0) return;
+    (void)hipEventRecord(t->used[idx + 1], s);
+    t->kinds.push_back(kind);
+    t->bytes.push_back(bytes);
+}
+
+void timing_collect(Timing* t) {
+    for (size_t p = 0; p < t->kinds.size(); ++p) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t->used[2 * p], t->used[2 * p + 1]) == hipSuccess) {
+            int k = t->kinds[p];
+            t->launches[k] += 1;
+            t->total_ms[k] += ms;
+            t->bytes_per_launch[k] = t->bytes[p];
+        }
+    }
+    for (hipEvent_t e : t->used) t->pool.push_back(e);
+    t->used.clear();
+    t->kinds.clear();
+    t->bytes.clear();
+}
+
+// Device of the mesh made current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev) {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Workspace use of a deposit: the counters sit at byte 48 K (a part of the
+// small region the diffusion does not use), the int64 accumulators (when the
+// caller passes none) from byte 64 K on.  The diffusion that follows in
+// cgd_coarse_grain reuses that memory only after the finalising kernel has
+// read it, in stream order.
+static cgd_status deposit_buffers(cgd_mesh m, int32_t F, int64_t* user_acc, int64_t** acc,
+                                  DepositInfo** info) {
+    size_t acc_bytes = user_acc ? 0 : (size_t)F * m->cells * sizeof(int64_t);
+    size_t need = 64 * 1024 + acc_bytes;
+    size_t diff = diffuse_hex_workspace(m, F);
+    cgd_status rc = ensure_workspace(m, need > diff ? need : diff);
+    if (rc != CGD_OK) return rc;
+    char* base = static_cast<char*>(m->ws.ptr);
+    *info = reinterpret_cast<DepositInfo*>(base + 48 * 1024);
+    *acc = user_acc ? user_acc : reinterpret_cast<int64_t*>(base + 64 * 1024);
+    return CGD_OK;
+}
+
+}  // namespace cgd
+
+using namespace cgd;
+
+extern "C" {
+
+const char* cgd_last_error(void) { return g_last_error.c_str(); }
+
+int32_t cgd_version(void) { return 100; }
+
+const char* cgd_status_string(cgd_status s) {
+    switch (s) {
+        case CGD_OK: return "CGD_OK";
+        case CGD_NOT_CONVERGED: return "CGD_NOT_CONVERGED";
+        case CGD_WARMSTART_FALLBACK: return "CGD_WARMSTART_FALLBACK";
+        case CGD_E_INVALID: return "CGD_E_INVALID";
+        case CGD_E_NONFINITE: return "CGD_E_NONFINITE";
+        case CGD_E_NOMEM: return "CGD_E_NOMEM";
+        case CGD_E_HIP: return "CGD_E_HIP";
+        case CGD_E_BREAKDOWN: return "CGD_E_BREAKDOWN";
+        case CGD_E_UNSUPPORTED: return "CGD_E_UNSUPPORTED";
+        default: return "unknown cgd_status";
+    }
+}
+
+cgd_status cgd_mesh_create_hex(int32_t nx, int32_t ny, int32_t nz, const double lo[3],
+                               const double hi[3], cgd_mesh* out) {
+    if (!out || !lo || !hi) {
+        set_error("cgd_mesh_create_hex: null pointer");
+        return CGD_E_INVALID;
+    }
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) {
+        set_error("cgd_mesh_create_hex: sizes must be >= 1");
+        return CGD_E_INVALID;
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (!isfinite(lo[a]) || !isfinite(hi[a]) || !(hi[a] > lo[a])) {
+            set_error("cgd_mesh_create_hex: need finite lo < hi on every axis");
+            return CGD_E_INVALID;
+        }
+    }
+    if ((int64_t)nx * ny * nz > (int64_t)1 << 33) {
+        set_error("cgd_mesh_create_hex: too many cells");
+        return CGD_E_INVALID;
+    }
+    cgd_mesh m = new (std::nothrow) cgd_mesh_s();
+    if (!m) return CGD_E_NOMEM;
+    m->kind = 0;
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        set_error("cgd_mesh_create_hex: no HIP device");
+        delete m;
+        return CGD_E_HIP;
+    }
+    m->cells = (int64_t)nx * ny * nz;
+    HexGeom& g = m->hex;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    const int32_t n[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = lo[a];
+        g.hi[a] = hi[a];
+        g.s[a] = (double)n[a] / (hi[a] - lo[a]);
+        g.h[a] = (hi[a] - lo[a]) / (double)n[a];
+    }
+    g.vol = (g.h[0] * g.h[1]) * g.h[2];
+    for (int i = 0; i < 2; ++i) {
+        if (hipEventCreateWithFlags(&m->ev[i], hipEventDisableTiming) != hipSuccess) {
+            set_error("cgd_mesh_create_hex: hipEventCreate failed");
+            cgd_mesh_destroy(m);
+            return CGD_E_HIP;
+        }
+    }
+    *out = m;
+    return CGD_OK;
+}
+
+void cgd_mesh_destroy(cgd_mesh m) {
+    if (!m) return;
+    DeviceGuard dg(m->device);
+    (void)hipDeviceSynchronize();
+    if (m->ws.ptr) (void)hipFree(m->ws.ptr);
+    if (m->pinned) (void)hipHostFree(m->pinned);
+    for (int i = 0; i < 2; ++i)
+        if (m->ev[i]) (void)hipEventDestroy(m->ev[i]);
+    for (hipEvent_t e : m->timing.pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : m->timing.used) (void)hipEventDestroy(e);
+    destroy_tet_data(m);
+    delete m;
+}
+
+int64_t cgd_mesh_num_cells(cgd_mesh m) { return m ? m->cells : 0; }
+
+int32_t cgd_mesh_kind(cgd_mesh m) { return m ? m->kind : -1; }
+
+int64_t cgd_mesh_nnz(cgd_mesh m) { return m ? tet_nnz(m) : 0; }
+
+cgd_status cgd_timing_enable(cgd_mesh m, int32_t on) {
+    if (!m) {
+        set_error("cgd_timing_enable: null mesh");
+        return CGD_E_INVALID;
+    }
+    m->timing.on = on != 0;
+    return CGD_OK;
+}
+
+cgd_status cgd_timing_read(cgd_mesh m, cgd_kernel_timing* out, int32_t reset) {
+    if (!m || !out) {
+        set_error("cgd_timing_read: null argument");
+        return CGD_E_INVALID;
+    }
+    DeviceGuard dg(m->device);
+    if (!m->timing.used.empty()) {
+        CGD_HIP_TRY(hipDeviceSynchronize());
+        timing_collect(&m->timing);
+    }
+    for (int k = 0; k < CGD_TIMING_KINDS; ++k) {
+        out->launches[k] = m->timing.launches[k];
+        out->total_ms[k] = m->timing.total_ms[k];
+        out->bytes_per_launch[k] = m->timing.bytes_per_launch[k];
+        if (reset) {
+            m->timing.launches[k] = 0;
+            m->timing.total_ms[k] = 0.0;
+        }
+    }
+    return CGD_OK;
+}
+
+static cgd_status check_common(cgd_mesh m, int32_t F, const char* who) {
+    if (!m) {
+        set_error(std::string(who) + ": null mesh");
+        return CGD_E_INVALID;
+    }
+    if (F < 1 || F > CGD_MAX_FIELDS) {
+        set_error(std::string(who) + ": F must be in 1.." + std::to_string(CGD_MAX_FIELDS));
+        return CGD_E_INVALID;
+    }
+    return CGD_OK;
+}
+
+static cgd_status do_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
+                             float* field, int64_t* acc, cgd_solve_stats* st, hipStream_t s) {
+    int64_t* acc_buf;
+    DepositInfo* info;
+    cgd_status rc = deposit_buffers(m, F, acc, &acc_buf, &info);
+    if (rc != CGD_OK) return rc;
+    if (m->kind == 0)
+        rc = deposit_hex(m, n, pos, F, values, field, acc_buf, info, s);
+    else
+        rc = deposit_tet(m, n, pos, F, values, field, acc_buf, info, s);
+    if (rc != CGD_OK || !st) return rc;
+    cgd_status prc = ensure_pinned(m, 64 * 1024);
+    if (prc != CGD_OK) return prc;
+    DepositInfo* h = reinterpret_cast<DepositInfo*>(static_cast<char*>(m->pinned) + 60 * 1024);
+    CGD_HIP_TRY(hipMemcpyAsync(h, info, sizeof(DepositInfo), hipMemcpyDeviceToHost, s));
+    CGD_HIP_TRY(hipStreamSynchronize(s));
+    const int e_n = ceil_log2_count(n);
+    unsigned long long nf = h->nonfinite_pos;
+    for (int f = 0; f < F; ++f) {
+        uint32_t mb = h->maxbits[f];
+        int S = 0;
+        if (mb) {
+            float mv;
+            memcpy(&mv, &mb, 4);
+            int e;
+            (void)frexp((double)mv, &e);
+            S = 62 - e - e_n;
+        }
+        st->frac_bits[f] = S;
+        nf += h->nonfinite_val[f];
+    }
+    st->n_dropped = (int64_t)h->dropped;
+    st->n_nonfinite = (int64_t)nf;
+    if (nf) {
+        set_error("non-finite particle positions or values were skipped");
+        return CGD_E_NONFINITE;
+    }
+    return CGD_OK;
+}
+
+cgd_status cgd_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
+                       float* field, int64_t* acc, cgd_solve_stats* st, void* stream) {
+    cgd_status rc = check_common(m, F, "cgd_deposit");
+    if (rc != CGD_OK) return rc;
+    if (n < 0 || (n > 0 && (!pos || !values)) || !field) {
+        set_error("cgd_deposit: need n >= 0 and non-null pos/values (n > 0) and field");
+        return CGD_E_INVALID;
+    }
+    if (reinterpret_cast<uintptr_t>(acc) % 8 || reinterpret_cast<uintptr_t>(pos) % 4 ||
+        reinterpret_cast<uintptr_t>(values) % 4 || reinterpret_cast<uintptr_t>(field) % 4) {
+        set_error("cgd_deposit: misaligned pointer");
+        return CGD_E_INVALID;
+    }
+    DeviceGuard dg(m->device);
+    if (dg.err != hipSuccess) {
+        set_error(std::string("cgd_deposit: ") + hipGetErrorString(dg.err));
+        return CGD_E_HIP;
+    }
+    if (st) memset(st, 0, sizeof(*st));
+    return do_deposit(m, n, pos, F, values, field, acc, st, static_cast<hipStream_t>(stream));
+}
+
+static cgd_status fill_opts(const cgd_solver_opts* o, int32_t F, float* field, double bandwidth,
+                            int32_t n_steps, DiffuseArgs* a, const char* who) {
+    if (!field) {
+        set_error(std::string(who) + ": null field");
+        return CGD_E_INVALID;
+    }
+    if (!(bandwidth > 0.0) || !isfinite(bandwidth)) {
+        set_error(std::string(who) + ": bandwidth must be finite and > 0");
+        return CGD_E_INVALID;
+    }
+    if (n_steps < 1 || n_steps > CGD_MAX_STEPS) {
+        set_error(std::string(who) + ": n_steps must be in 1.." + std::to_string(CGD_MAX_STEPS));
+        return CGD_E_INVALID;
+    }
+    a->F = F;
+    a->field = field;
+    a->bandwidth = bandwidth;
+    a->n_steps = n_steps;
+    a->rtol = (o && o->rtol > 0.0) ? o->rtol : 1e-6;
+    a->max_iter = (o && o->max_iter > 0) ? o->max_iter : 1000;
+    a->x0_mode = o ? o->x0_mode : 0;
+    a->x0 = o ? o->x0 : nullptr;
+    a->check_every = (o && o->check_every > 0) ? o->check_every : 4;
+    if (a->x0_mode < 0 || a->x0_mode > 2 || (a->x0_mode == 2 && !a->x0) || !isfinite(a->rtol)) {
+        set_error(std::string(who) + ": bad solver options (x0_mode 0..2, x0 needed for mode 2)");
+        return CGD_E_INVALID;
+    }
+    return CGD_OK;
+}
+
+static cgd_status do_diffuse(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hipStream_t s) {
+    if (m->kind == 0) return diffuse_hex(m, a, st, s);
+    return diffuse_tet(m, a, st, s);
+}
+
+cgd_status cgd_diffuse(cgd_mesh m, int32_t F, float* field, double bandwidth, int32_t n_steps,
+                       const cgd_solver_opts* o, cgd_solve_stats* st, void* stream) {
+    cgd_status rc = check_common(m, F, "cgd_diffuse");
+    if (rc != CGD_OK) return rc;
+    DiffuseArgs a;
+    rc = fill_opts(o, F, field, bandwidth, n_steps, &a, "cgd_diffuse");
+    if (rc != CGD_OK) return rc;
+    DeviceGuard dg(m->device);
+    if (dg.err != hipSuccess) {
+        set_error(std::string("cgd_diffuse: ") + hipGetErrorString(dg.err));
+        return CGD_E_HIP;
+    }
+    if (st) memset(st, 0, sizeof(*st));
+    return do_diffuse(m, a, st, static_cast<hipStream_t>(stream));
+}
+
+cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
+                            double bandwidth, int32_t n_steps, const cgd_solver_opts* o, float* field,
+                            cgd_solve_stats* st, void* stream) {
+    cgd_status rc = check_common(m, F, "cgd_coarse_grain");
+    if (rc != CGD_OK) return rc;
+    if (n < 0 || (n > 0 && (!pos || !values))) {
+        set_error("cgd_coarse_grain: need n >= 0 and non-null pos/values when n > 0");
+        return CGD_E_INVALID;
+    }
+    DiffuseArgs a;
+    rc = fill_opts(o, F, field, bandwidth, n_steps, &a, "cgd_coarse_grain");
+    if (rc != CGD_OK) return rc;
+    if (a.x0_mode == 2) {
+        set_error("cgd_coarse_grain: x0_mode 2 needs cgd_diffuse");
+        return CGD_E_INVALID;
+    }
+    DeviceGuard dg(m->device);
+    if (dg.err != hipSuccess) {
+        set_error(std::string("cgd_coarse_grain: ") + hipGetErrorString(dg.err));
+        return CGD_E_HIP;
+    }
+    if (st) memset(st, 0, sizeof(*st));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = do_deposit(m, n, pos, F, values, field, nullptr, st, s);
+    cgd_status dep_rc = rc;
+    if (rc < 0 && rc != CGD_E_NONFINITE) return rc;
+    rc = do_diffuse(m, a, st, s);
+    if (rc < 0) return rc;
+    if (dep_rc == CGD_E_NONFINITE) return dep_rc;
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,135 @@
+// Internal declarations of libcgd (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/cgd.h"
+
+namespace cgd {
+
+// Thread-local error text for cgd_last_error().
+void set_error(const std::string& msg);
+
+#define CGD_HIP_TRY(expr)                                                        \
+    do {                                                                         \
+        hipError_t e__ = (expr);                                                 \
+        if (e__ != hipSuccess) {                                                 \
+            ::cgd::set_error(std::string(#expr) + ": " + hipGetErrorString(e__)); \
+            return CGD_E_HIP;                                                    \
+        }                                                                        \
+    } while (0)
+
+// Per-field CG state kept on the device.  Written only by the single-block
+// finisher kernels, read by every sweep.
+struct CgField {
+    double bb;      // ||b||^2 of the current step
+    double rr;      // ||r||^2 of the current iterate
+    double alpha;   // step length of the current iteration
+    double beta;    // direction update of the next iteration
+    double sum_b;   // sum_k b_k (mass before, divided by V) for stats
+    int32_t iter;   // iterations done in the current step
+    int32_t done;   // 1 once converged / stopped
+    int32_t status; // CGD_OK, CGD_NOT_CONVERGED or CGD_E_BREAKDOWN
+    int32_t pad;
+};
+
+// Counters the deposit kernels fill (device).
+struct DepositInfo {
+    uint32_t maxbits[CGD_MAX_FIELDS];       // max |v| bit pattern over finite values
+    unsigned long long nonfinite_val[CGD_MAX_FIELDS];
+    unsigned long long dropped;             // non-finite or outside the domain
+    unsigned long long nonfinite_pos;
+};
+
+struct HexGeom {
+    int32_t nx, ny, nz;
+    double lo[3], hi[3];
+    double s[3];   // N_a / (hi_a - lo_a)
+    double h[3];   // (hi_a - lo_a) / N_a
+    double vol;    // (h_x h_y) h_z
+};
+
+struct TetData;  // defined in tet.cpp
+
+// Event-pair timing of selected kernels (cgd_timing_enable).
+struct Timing {
+    bool on = false;
+    std::vector<hipEvent_t> pool;          // free events
+    std::vector<hipEvent_t> used;          // recorded pairs (start, end)
+    std::vector<int> kinds;                // kind of each pair
+    std::vector<double> bytes;             // algorithmic bytes of each pair
+    int64_t launches[CGD_TIMING_KINDS] = {};
+    double total_ms[CGD_TIMING_KINDS] = {};
+    double bytes_per_launch[CGD_TIMING_KINDS] = {};
+};
+
+// Records the start event of a timed launch (no-op when timing is off).
+// Returns an opaque index to pass to timing_end.
+int timing_begin(Timing* t, hipStream_t s);
+void timing_end(Timing* t, int idx, int kind, double bytes, hipStream_t s);
+// Adds the elapsed times of all recorded pairs (the stream must be synchronised).
+void timing_collect(Timing* t);
+
+// Device workspace owned by a mesh, grown on demand.
+struct Workspace {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace cgd
+
+struct cgd_mesh_s {
+    int32_t kind;     // 0 hex, 1 tet
+    int32_t device;
+    int64_t cells;
+    cgd::HexGeom hex;
+    cgd::TetData* tet = nullptr;
+    cgd::Workspace ws;
+    void* pinned = nullptr;        // small pinned host buffer for read-backs
+    size_t pinned_bytes = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    cgd::Timing timing;
+};
+
+namespace cgd {
+
+// Grows m->ws to at least `bytes`.  Synchronises the device before freeing.
+cgd_status ensure_workspace(cgd_mesh m, size_t bytes);
+cgd_status ensure_pinned(cgd_mesh m, size_t bytes);
+
+// deposit.hip
+cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
+                       float* field, int64_t* acc, DepositInfo* info_dev, hipStream_t s);
+
+// cg_hex.hip
+struct DiffuseArgs {
+    int32_t F;
+    float* field;
+    double bandwidth;
+    int32_t n_steps;
+    double rtol;
+    int32_t max_iter;
+    int32_t x0_mode;
+    const float* x0;
+    int32_t check_every;
+};
+cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hipStream_t s);
+
+// Bytes of workspace the hex diffusion needs for F fields.
+size_t diffuse_hex_workspace(const cgd_mesh m, int32_t F);
+
+// ceil(log2 n) for n >= 2, 0 for n <= 1 (the e_N of the fixed-point scale).
+int ceil_log2_count(int64_t n);
+
+// tet.cpp / tet.hip
+cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
+                       float* field, int64_t* acc, DepositInfo* info_dev, hipStream_t s);
+cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hipStream_t s);
+void destroy_tet_data(cgd_mesh m);
+int64_t tet_nnz(cgd_mesh m);
+
+}  // namespace cgd
