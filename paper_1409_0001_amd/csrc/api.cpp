@@ -72,16 +72,18 @@ int timing_begin(Timing* t, hipStream_t s) {
     return (int)t->used.size() - 2;
 }
 
-void timing_end(Timing* t, int idx, int kind, double bytes, hipStream_t s) {
+void timing_end(Timing* t, int idx, int kind, double bytes, hipStream_t s, int64_t tag) {
     if (idx < 0) return;
     (void)hipEventRecord(t->used[idx + 1], s);
     t->kinds.push_back(kind);
     t->bytes.push_back(bytes);
+    t->tags.push_back(tag);
 }
 
-void timing_collect(Timing* t) {
+void timing_collect(Timing* t, const std::function<bool(int64_t)>& keep) {
     for (size_t p = 0; p < t->kinds.size(); ++p) {
         float ms = 0.f;
+        if (keep && !keep(t->tags[p])) continue;
         if (hipEventElapsedTime(&ms, t->used[2 * p], t->used[2 * p + 1]) == hipSuccess) {
             int k = t->kinds[p];
             t->launches[k] += 1;
@@ -93,6 +95,7 @@ void timing_collect(Timing* t) {
     t->used.clear();
     t->kinds.clear();
     t->bytes.clear();
+    t->tags.clear();
 }
 
 // Device of the mesh made current for the duration of a call.

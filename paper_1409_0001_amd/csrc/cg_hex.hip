@@ -7,21 +7,21 @@
 // c_a = dtau / h_a^2, where a missing neighbour at a wall is replaced by p_k
 // itself (zero flux through wall faces, Section 3.2.2).
 //
-// One CG iteration is two streaming sweeps over the grid, 32 bytes per cell:
+// One CG iteration k is two streaming sweeps over the grid, 32 bytes per cell:
 //   sweep 1: p = r + beta p_old (also recomputed at neighbours), A p, p.Ap
 //            reads r, p_old; writes p
 //   sweep 2: x += alpha p, r -= alpha A p (A p recomputed), r.r
 //            reads p, x, r; writes x, r
-// Each sweep is followed by a one-block finisher per field that reduces the
-// float64 block partials in a fixed order (deterministic) and updates the
-// field's alpha / beta / convergence state on the device.
+// Global scalars need no extra launches: every block of a sweep first sums
+// the float64 block partials of the sweep before it, in one fixed order, so
+// all blocks obtain bit-identical alpha / beta; the first block also records
+// the convergence state for later kernels and for the host.
 //
-// Sweep layout: a wave owns 64 consecutive x (one lane each) times TY rows
-// of y, and marches over a chunk of z planes keeping the planes z-1, z, z+1
-// in registers.  x-neighbours come from lane shuffles (the two wave-edge
-// lanes load theirs), y-neighbours from the wave's own rows plus one halo row
-// on each side.  Blocks of 4 waves are spread so that consecutive tiles land
-// on the same XCD (workgroups are dealt round-robin over the 8 XCDs), which
+// Sweep layout: a wave owns 64 * VEC consecutive x (VEC per lane) times TY
+// rows of y and marches over a chunk of z planes, keeping planes z-1, z, z+1
+// (with one halo row on each side) in registers.  x-neighbours come from lane
+// shuffles.  Blocks of 4 waves are spread so that consecutive tiles land on
+// the same XCD (workgroups are dealt round-robin over the 8 XCDs), which
 // keeps halo rows in that XCD's L2.
 #include <algorithm>
 
@@ -33,7 +33,7 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kBlock = 64 * kWaves;
 
-enum Mode { S1_FIRST = 0, S1 = 1, S2_FIRST = 2, S2 = 3, S_RES = 4 };
+enum Mode { S1_FIRST = 0, S1 = 1, S2_FIRST = 2, S2 = 3, S_RES = 4, S1_B0 = 5 };
 
 struct SweepArgs {
     const float* B;     // right-hand side of the step (zero-guess first iteration: p = b)
@@ -41,38 +41,155 @@ struct SweepArgs {
     const float* Pold;  // previous direction (sweep 1)
     float* Pnew;        // new direction (sweep 1 writes, sweep 2 reads)
     float* X;           // iterate
-    const CgField* st;
-    double* partials;   // [F][2][bpf]
+    CgField* st;        // [F]
+    double* P1;         // [F][2][bpf]: slot 0 p.Ap, slot 1 b.b
+    double* P2;         // [F][2][bpf]: r.r of r_k in slot k % 2
+    int* ndone;
+    int32_t* iters;     // [CGD_MAX_STEPS][CGD_MAX_FIELDS]
+    double* relres;     // [CGD_MAX_STEPS][CGD_MAX_FIELDS]
+    int32_t* status;    // [CGD_MAX_STEPS][CGD_MAX_FIELDS]
+    double rtol2;
     int64_t cells;
     int nx, ny, nz;
     float cx, cy, cz;
     int xsegs, ygroups, zc;
     int wpf, bpf, nblocks;
-    int beta_zero;
+    int k;              // iteration index within the step
+    int step;
 };
 
-template <int MODE>
-__device__ __forceinline__ float load_p(const SweepArgs& a, size_t i, float beta) {
-    if constexpr (MODE == S1_FIRST || MODE == S2_FIRST) {
-        return a.B[i];
-    } else if constexpr (MODE == S1) {
-        float r = a.R[i];
-        return a.beta_zero ? r : fmaf(beta, a.Pold[i], r);
-    } else if constexpr (MODE == S2) {
-        return a.Pnew[i];
+// Sum of n float64 values in one fixed order (thread t adds t, t+256, ...;
+// then a fixed shuffle tree and a fixed sum over the 4 waves).  Every thread
+// of the block returns the same value, bit for bit, in every block.
+__device__ inline double block_sum_fixed(const double* p, int n, double* sh) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) s += p[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+__device__ inline void finish_field(const SweepArgs& a, int f, int status) {
+    a.st[f].status = status;
+    a.st[f].done = 1;
+    a.status[a.step * CGD_MAX_FIELDS + f] = status;
+    atomicAdd(a.ndone, 1);
+}
+
+template <int VEC>
+struct Vec {
+    float f[VEC];
+};
+
+template <int VEC>
+__device__ __forceinline__ Vec<VEC> ldv(const float* p) {
+    Vec<VEC> v;
+    if constexpr (VEC == 4) {
+        const float4 t = *reinterpret_cast<const float4*>(p);
+        v.f[0] = t.x; v.f[1] = t.y; v.f[2] = t.z; v.f[3] = t.w;
+    } else if constexpr (VEC == 2) {
+        const float2 t = *reinterpret_cast<const float2*>(p);
+        v.f[0] = t.x; v.f[1] = t.y;
     } else {
-        return a.X[i];
+        v.f[0] = *p;
+    }
+    return v;
+}
+
+template <int VEC>
+__device__ __forceinline__ void stv(float* p, const Vec<VEC>& v) {
+    if constexpr (VEC == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(v.f[0], v.f[1], v.f[2], v.f[3]);
+    } else if constexpr (VEC == 2) {
+        *reinterpret_cast<float2*>(p) = make_float2(v.f[0], v.f[1]);
+    } else {
+        *p = v.f[0];
     }
 }
 
-template <int TY, int MODE>
+// The direction vector p at VEC consecutive cells starting at i (always an
+// in-bounds address; the caller clamps).
+template <int VEC, int MODE>
+__device__ __forceinline__ Vec<VEC> load_p(const SweepArgs& a, size_t i, float beta) {
+    if constexpr (MODE == S1_FIRST || MODE == S2_FIRST) {
+        return ldv<VEC>(a.B + i);
+    } else if constexpr (MODE == S1) {
+        Vec<VEC> r = ldv<VEC>(a.R + i);
+        const Vec<VEC> q = ldv<VEC>(a.Pold + i);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) r.f[e] = fmaf(beta, q.f[e], r.f[e]);
+        return r;
+    } else if constexpr (MODE == S1_B0) {
+        return ldv<VEC>(a.R + i);
+    } else if constexpr (MODE == S2) {
+        return ldv<VEC>(a.Pnew + i);
+    } else {
+        return ldv<VEC>(a.X + i);
+    }
+}
+
+// One sweep.  A wave owns 64*VEC consecutive x (VEC per lane) times TY rows
+// and marches over a z chunk.  Every load is issued unconditionally at a
+// clamped, in-bounds address; out-of-range values are replaced afterwards
+// (walls: the cell's own value, i.e. zero flux).  EDGE: the row is wider
+// than one wave (VEC = 1), so lanes 0 and 63 also load the cell beyond the
+// wave's ends; every other lane loads its own cell at that instruction.
+template <int VEC, int TY, int MODE, bool EDGE>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     int b = blockIdx.x;
     if ((a.nblocks & 7) == 0) b = (b & 7) * (a.nblocks >> 3) + (b >> 3);
     const int f = b / a.bpf;
     const int blk = b - f * a.bpf;
-    const CgField* stf = a.st + f;
-    if (stf->done) return;  // uniform over the block
+    CgField* stf = a.st + f;
+    // S2_FIRST must write x and r even when its first block flags a breakdown.
+    if (MODE != S2_FIRST && stf->done) return;  // uniform over the block
+
+    __shared__ double sh[kWaves];
+    const bool lead = blk == 0 && threadIdx.x == 0;
+    float alpha = 0.f, beta = 0.f;
+    if constexpr (MODE == S1 || MODE == S1_B0) {
+        // r_k . r_k from the previous sweep 2 (or the residual sweep)
+        const double rrk = block_sum_fixed(a.P2 + ((size_t)f * 2 + (a.k & 1)) * a.bpf, a.bpf, sh);
+        double bb;
+        if constexpr (MODE == S1_B0) bb = block_sum_fixed(a.P1 + ((size_t)f * 2 + 1) * a.bpf, a.bpf, sh);
+        else bb = stf->bb;
+        const bool broken = !isfinite(rrk) || !isfinite(bb);
+        const bool conv = !broken && rrk <= a.rtol2 * bb;
+        if (lead) {
+            a.iters[a.step * CGD_MAX_FIELDS + f] = a.k;
+            a.relres[a.step * CGD_MAX_FIELDS + f] = bb > 0.0 ? sqrt(rrk / bb) : 0.0;
+            stf->rr_par[a.k & 1] = rrk;
+            if (MODE == S1_B0) stf->bb = bb;
+            if (broken || conv) finish_field(a, f, broken ? CGD_E_BREAKDOWN : CGD_OK);
+        }
+        if (broken || conv) return;
+        if constexpr (MODE == S1) beta = (float)(rrk / stf->rr_par[(a.k - 1) & 1]);
+    } else if constexpr (MODE == S2 || MODE == S2_FIRST) {
+        const double pap = block_sum_fixed(a.P1 + ((size_t)f * 2 + 0) * a.bpf, a.bpf, sh);
+        if constexpr (MODE == S2_FIRST) {
+            const double bb = block_sum_fixed(a.P1 + ((size_t)f * 2 + 1) * a.bpf, a.bpf, sh);
+            const bool broken = !isfinite(bb) || !isfinite(pap) || (bb > 0.0 && !(pap > 0.0));
+            if (lead) {
+                stf->bb = bb;
+                stf->rr_par[0] = bb;
+                if (broken) finish_field(a, f, CGD_E_BREAKDOWN);
+            }
+            // b = 0 or a breakdown: alpha = 0 gives x = 0, r = b
+            alpha = (broken || bb == 0.0) ? 0.f : (float)(bb / pap);
+        } else {
+            const double rrk = stf->rr_par[a.k & 1];
+            if (!(pap > 0.0) || !isfinite(pap)) {
+                if (lead) finish_field(a, f, CGD_E_BREAKDOWN);
+                return;
+            }
+            alpha = (float)(rrk / pap);
+        }
+    }
 
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -80,98 +197,149 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     double acc0 = 0.0, acc1 = 0.0;
 
     if (w < a.wpf) {
-        const float alpha = (float)stf->alpha;
-        const float beta = (float)stf->beta;
         const int xs = w % a.xsegs;
         const int t = w / a.xsegs;
         const int yg = t % a.ygroups;
         const int zci = t / a.ygroups;
-        const int x = xs * 64 + lane;
-        const bool xin = x < a.nx;
-        const bool has_l = x > 0, has_r = x + 1 < a.nx;
+        const int nx = a.nx, ny = a.ny, nz = a.nz;
+        const int x0 = xs * 64 * VEC + lane * VEC;
+        const bool xin = x0 < nx;
+        const int xc = xin ? x0 : nx - VEC;
+        const bool wall_l = x0 == 0;
+        const bool wall_r = x0 + VEC >= nx;
         const int y0 = yg * TY;
         const int zb = zci * a.zc;
-        const int ze = min(zb + a.zc, a.nz);
-        const size_t plane = (size_t)a.nx * a.ny;
-        const size_t fo = (size_t)f * a.cells + x;
+        const int ze = min(zb + a.zc, nz);
+        const size_t plane = (size_t)nx * ny;
+        const size_t base = (size_t)f * a.cells + xc;
         const float cx = a.cx, cy = a.cy, cz = a.cz;
+        int eoff = 0;
+        if constexpr (EDGE) eoff = (lane == 0 && x0 > 0) ? -1 : ((lane == 63 && x0 + 1 < nx) ? 1 : 0);
 
-        auto idx = [&](int z, int y) -> size_t { return fo + (size_t)z * plane + (size_t)y * a.nx; };
-        auto ld = [&](int z, int y) -> float {
-            return (xin && y >= 0 && y < a.ny) ? load_p<MODE>(a, idx(z, y), beta) : 0.f;
+        auto at = [&](int z, int y) -> size_t {
+            z = z < 0 ? 0 : (z >= nz ? nz - 1 : z);
+            y = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+            return base + (size_t)z * plane + (size_t)y * nx;
         };
 
-        float pm[TY], pc[TY], pn[TY];
+        Vec<VEC> pm[TY], pc[TY + 2], pn[TY + 2];
+        float ec[TY], en[TY];
 #pragma unroll
-        for (int j = 0; j < TY; ++j) {
-            pm[j] = zb > 0 ? ld(zb - 1, y0 + j) : 0.f;
-            pc[j] = ld(zb, y0 + j);
+        for (int j = 0; j < TY; ++j) pm[j] = load_p<VEC, MODE>(a, at(zb - 1, y0 + j), beta);
+#pragma unroll
+        for (int j = 0; j < TY + 2; ++j) pc[j] = load_p<VEC, MODE>(a, at(zb, y0 - 1 + j), beta);
+        if constexpr (EDGE) {
+#pragma unroll
+            for (int j = 0; j < TY; ++j) ec[j] = load_p<1, MODE>(a, at(zb, y0 + j) + eoff, beta).f[0];
         }
         for (int z = zb; z < ze; ++z) {
-            const bool has_zu = z + 1 < a.nz, has_zd = z > 0;
 #pragma unroll
-            for (int j = 0; j < TY; ++j) pn[j] = has_zu ? ld(z + 1, y0 + j) : 0.f;
-            const float hlo = ld(z, y0 - 1);
-            const float hhi = ld(z, y0 + TY);
+            for (int j = 0; j < TY + 2; ++j) pn[j] = load_p<VEC, MODE>(a, at(z + 1, y0 - 1 + j), beta);
+            if constexpr (EDGE) {
+#pragma unroll
+                for (int j = 0; j < TY; ++j) en[j] = load_p<1, MODE>(a, at(z + 1, y0 + j) + eoff, beta).f[0];
+            }
+            const bool has_zd = z > 0, has_zu = z + 1 < nz;
 #pragma unroll
             for (int j = 0; j < TY; ++j) {
                 const int y = y0 + j;
-                const float c = pc[j];
-                float l = __shfl_up(c, 1);
-                float r = __shfl_down(c, 1);
-                if (lane == 0 && has_l && y < a.ny) l = load_p<MODE>(a, idx(z, y) - 1, beta);
-                if (lane == 63 && has_r && y < a.ny) r = load_p<MODE>(a, idx(z, y) + 1, beta);
-                l = has_l ? l : c;
-                r = has_r ? r : c;
-                const float yl = y > 0 ? (j > 0 ? pc[j - 1] : hlo) : c;
-                const float yh = y + 1 < a.ny ? (j + 1 < TY ? pc[j + 1] : hhi) : c;
-                const float zl = has_zd ? pm[j] : c;
-                const float zh = has_zu ? pn[j] : c;
-                const float c2 = c + c;
-                float Ap = fmaf(cx, (c2 - l) - r, c);
-                Ap = fmaf(cy, (c2 - yl) - yh, Ap);
-                Ap = fmaf(cz, (c2 - zl) - zh, Ap);
-                if (xin && y < a.ny) {
-                    const size_t i = idx(z, y);
-                    if constexpr (MODE == S1_FIRST) {
-                        acc0 = fma((double)c, (double)Ap, acc0);
-                        acc1 = fma((double)c, (double)c, acc1);
-                    } else if constexpr (MODE == S1) {
-                        a.Pnew[i] = c;
-                        acc0 = fma((double)c, (double)Ap, acc0);
-                    } else if constexpr (MODE == S2_FIRST) {
-                        const float xn = alpha * c;
-                        const float rn = fmaf(-alpha, Ap, c);
-                        a.X[i] = xn;
-                        a.R[i] = rn;
-                        acc0 = fma((double)rn, (double)rn, acc0);
-                    } else if constexpr (MODE == S2) {
-                        const float xn = fmaf(alpha, c, a.X[i]);
-                        const float rn = fmaf(-alpha, Ap, a.R[i]);
-                        a.X[i] = xn;
-                        a.R[i] = rn;
-                        acc0 = fma((double)rn, (double)rn, acc0);
-                    } else {  // S_RES: r = b - A x0
-                        const float bv = a.B[i];
-                        const float rn = bv - Ap;
-                        a.R[i] = rn;
-                        acc0 = fma((double)rn, (double)rn, acc0);
-                        acc1 = fma((double)bv, (double)bv, acc1);
+                const bool valid = xin && y < ny;
+                const size_t i = at(z, y);
+                const Vec<VEC>& c = pc[j + 1];
+                const bool has_yd = y > 0, has_yu = y + 1 < ny;
+                float lft = __shfl_up(c.f[VEC - 1], 1);
+                float rgt = __shfl_down(c.f[0], 1);
+                if constexpr (EDGE) {
+                    lft = lane == 0 ? ec[j] : lft;
+                    rgt = lane == 63 ? ec[j] : rgt;
+                }
+                Vec<VEC> ap;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const float ce = c.f[e];
+                    float l = e > 0 ? c.f[e - 1] : (wall_l ? ce : lft);
+                    float r = e + 1 < VEC ? c.f[e + 1] : (wall_r ? ce : rgt);
+                    const float yl = has_yd ? pc[j].f[e] : ce;
+                    const float yh = has_yu ? pc[j + 2].f[e] : ce;
+                    const float zl = has_zd ? pm[j].f[e] : ce;
+                    const float zh = has_zu ? pn[j + 1].f[e] : ce;
+                    const float c2 = ce + ce;
+                    float v = fmaf(cx, (c2 - l) - r, ce);
+                    v = fmaf(cy, (c2 - yl) - yh, v);
+                    ap.f[e] = fmaf(cz, (c2 - zl) - zh, v);
+                }
+                if constexpr (MODE == S1_FIRST) {
+                    if (valid) {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) {
+                            acc0 = fma((double)c.f[e], (double)ap.f[e], acc0);
+                            acc1 = fma((double)c.f[e], (double)c.f[e], acc1);
+                        }
+                    }
+                } else if constexpr (MODE == S1 || MODE == S1_B0) {
+                    if (valid) {
+                        stv<VEC>(a.Pnew + i, c);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) acc0 = fma((double)c.f[e], (double)ap.f[e], acc0);
+                    }
+                } else if constexpr (MODE == S2_FIRST) {
+                    Vec<VEC> xn, rn;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        xn.f[e] = alpha * c.f[e];
+                        rn.f[e] = fmaf(-alpha, ap.f[e], c.f[e]);
+                    }
+                    if (valid) {
+                        stv<VEC>(a.X + i, xn);
+                        stv<VEC>(a.R + i, rn);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) acc0 = fma((double)rn.f[e], (double)rn.f[e], acc0);
+                    }
+                } else if constexpr (MODE == S2) {
+                    Vec<VEC> xv = ldv<VEC>(a.X + i);
+                    Vec<VEC> rv = ldv<VEC>(a.R + i);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        xv.f[e] = fmaf(alpha, c.f[e], xv.f[e]);
+                        rv.f[e] = fmaf(-alpha, ap.f[e], rv.f[e]);
+                    }
+                    if (valid) {
+                        stv<VEC>(a.X + i, xv);
+                        stv<VEC>(a.R + i, rv);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) acc0 = fma((double)rv.f[e], (double)rv.f[e], acc0);
+                    }
+                } else {  // S_RES: r = b - A x0
+                    const Vec<VEC> bv = ldv<VEC>(a.B + i);
+                    Vec<VEC> rn;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) rn.f[e] = bv.f[e] - ap.f[e];
+                    if (valid) {
+                        stv<VEC>(a.R + i, rn);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) {
+                            acc0 = fma((double)rn.f[e], (double)rn.f[e], acc0);
+                            acc1 = fma((double)bv.f[e], (double)bv.f[e], acc1);
+                        }
                     }
                 }
             }
 #pragma unroll
-            for (int j = 0; j < TY; ++j) {
-                pm[j] = pc[j];
-                pc[j] = pn[j];
+            for (int j = 0; j < TY; ++j) pm[j] = pc[j + 1];
+#pragma unroll
+            for (int j = 0; j < TY + 2; ++j) pc[j] = pn[j];
+            if constexpr (EDGE) {
+#pragma unroll
+                for (int j = 0; j < TY; ++j) ec[j] = en[j];
             }
         }
     }
 
     // block reduction of the float64 partials, fixed order
+    constexpr bool kTwo = (MODE == S1_FIRST || MODE == S_RES);
     for (int o = 32; o > 0; o >>= 1) {
         acc0 += __shfl_xor(acc0, o);
-        acc1 += __shfl_xor(acc1, o);
+        if (kTwo) acc1 += __shfl_xor(acc1, o);
     }
     __shared__ double s0[kWaves], s1[kWaves];
     if (lane == 0) {
@@ -186,110 +354,17 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
             t0 += s0[i];
             t1 += s1[i];
         }
-        a.partials[((size_t)f * 2 + 0) * a.bpf + blk] = t0;
-        a.partials[((size_t)f * 2 + 1) * a.bpf + blk] = t1;
-    }
-}
-
-enum Finish { F1_FIRST = 0, F1 = 1, F2 = 2, F_RES = 3 };
-
-struct FinishArgs {
-    const double* partials;
-    int bpf;
-    CgField* st;
-    int* ndone;
-    int step;
-    double rtol2;
-    int max_iter;
-    int32_t* iters;    // [CGD_MAX_STEPS][CGD_MAX_FIELDS]
-    double* relres;    // [CGD_MAX_STEPS][CGD_MAX_FIELDS]
-    int32_t* status;   // [CGD_MAX_STEPS][CGD_MAX_FIELDS], final status of each solve
-};
-
-// Sums one field's partials in a fixed order: thread t adds t, t+256, ...,
-// then a fixed shuffle tree and a fixed sum over the 4 waves.
-__device__ inline double block_sum_fixed(const double* p, int n) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) s += p[i];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    __shared__ double sh[kWaves];
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    double t = 0.0;
-#pragma unroll
-    for (int i = 0; i < kWaves; ++i) t += sh[i];
-    __syncthreads();
-    return t;
-}
-
-__device__ inline void mark_done(CgField& s, const FinishArgs& a, int f) {
-    s.done = 1;
-    a.status[a.step * CGD_MAX_FIELDS + f] = s.status;
-    atomicAdd(a.ndone, 1);
-}
-
-template <int KIND>
-__global__ __launch_bounds__(kBlock) void k_finish(FinishArgs a) {
-    const int f = blockIdx.x;
-    CgField* st = a.st + f;
-    if (KIND != F1_FIRST && KIND != F_RES && st->done) return;
-    const double s0 = block_sum_fixed(a.partials + ((size_t)f * 2 + 0) * a.bpf, a.bpf);
-    double s1 = 0.0;
-    if (KIND == F1_FIRST || KIND == F_RES) s1 = block_sum_fixed(a.partials + ((size_t)f * 2 + 1) * a.bpf, a.bpf);
-    if (threadIdx.x != 0) return;
-    CgField s = *st;
-    if constexpr (KIND == F1_FIRST) {
-        // s0 = b.Ab, s1 = b.b
-        s.bb = s1;
-        s.rr = s1;
-        if (s1 == 0.0) {
-            s.alpha = 0.0;  // b = 0: x = 0, detected as converged after sweep 2
-        } else if (!(s0 > 0.0) || !isfinite(s0) || !isfinite(s1)) {
-            s.alpha = 0.0;
-            s.status = CGD_E_BREAKDOWN;
-        } else {
-            s.alpha = s1 / s0;
-        }
-    } else if constexpr (KIND == F1) {
-        if (!(s0 > 0.0) || !isfinite(s0)) {
-            s.status = CGD_E_BREAKDOWN;
-            s.alpha = 0.0;
-            mark_done(s, a, f);
-        } else {
-            s.alpha = s.rr / s0;
-        }
-    } else if constexpr (KIND == F_RES) {
-        // s0 = r.r, s1 = b.b
-        s.bb = s1;
-        s.rr = s0;
-        s.beta = 0.0;
-        if (!isfinite(s0) || !isfinite(s1)) {
-            s.status = CGD_E_BREAKDOWN;
-            mark_done(s, a, f);
-        } else if (s0 <= a.rtol2 * s1) {
-            mark_done(s, a, f);  // the initial guess already meets the tolerance
-        }
-        a.relres[a.step * CGD_MAX_FIELDS + f] = s1 > 0.0 ? sqrt(s0 / s1) : 0.0;
-        a.iters[a.step * CGD_MAX_FIELDS + f] = 0;
-    } else {  // F2: s0 = r_new . r_new
-        s.iter += 1;
-        const double rel = s.bb > 0.0 ? sqrt(s0 / s.bb) : 0.0;
-        a.iters[a.step * CGD_MAX_FIELDS + f] = s.iter;
-        a.relres[a.step * CGD_MAX_FIELDS + f] = rel;
-        if (!isfinite(s0)) {
-            s.status = CGD_E_BREAKDOWN;
-            mark_done(s, a, f);
-        } else if (s.status != CGD_OK || s0 <= a.rtol2 * s.bb) {
-            mark_done(s, a, f);
-        } else if (s.iter >= a.max_iter) {
-            s.status = CGD_NOT_CONVERGED;
-            mark_done(s, a, f);
-        } else {
-            s.beta = s0 / s.rr;
-            s.rr = s0;
+        // where each mode's sums go (see SweepArgs)
+        if constexpr (MODE == S1_FIRST || MODE == S1 || MODE == S1_B0) {
+            a.P1[((size_t)f * 2 + 0) * a.bpf + blk] = t0;
+            if (MODE == S1_FIRST) a.P1[((size_t)f * 2 + 1) * a.bpf + blk] = t1;
+        } else if constexpr (MODE == S2_FIRST || MODE == S2) {
+            a.P2[((size_t)f * 2 + ((a.k + 1) & 1)) * a.bpf + blk] = t0;
+        } else {  // S_RES: r_0 . r_0 and b . b
+            a.P2[((size_t)f * 2 + 0) * a.bpf + blk] = t0;
+            a.P1[((size_t)f * 2 + 1) * a.bpf + blk] = t1;
         }
     }
-    *st = s;
 }
 
 __global__ void k_step_init(CgField* st, int F, int* ndone, int32_t* status_row) {
@@ -301,6 +376,24 @@ __global__ void k_step_init(CgField* st, int F, int* ndone, int32_t* status_row)
         status_row[f] = CGD_OK;
     }
     if (threadIdx.x == 0) *ndone = 0;
+}
+
+// After the last enqueued iteration (k_end iterations done): settles the
+// fields that did not stop inside the loop (converged or not).
+__global__ __launch_bounds__(kBlock) void k_step_end(SweepArgs a, int k_end, int max_iter) {
+    const int f = blockIdx.x;
+    CgField* stf = a.st + f;
+    if (stf->done) return;
+    __shared__ double sh[kWaves];
+    const double rrk = block_sum_fixed(a.P2 + ((size_t)f * 2 + (k_end & 1)) * a.bpf, a.bpf, sh);
+    if (threadIdx.x != 0) return;
+    const double bb = stf->bb;
+    a.iters[a.step * CGD_MAX_FIELDS + f] = k_end;
+    a.relres[a.step * CGD_MAX_FIELDS + f] = bb > 0.0 ? sqrt(rrk / bb) : 0.0;
+    int status = CGD_OK;
+    if (!isfinite(rrk)) status = CGD_E_BREAKDOWN;
+    else if (!(rrk <= a.rtol2 * bb)) status = CGD_NOT_CONVERGED;
+    finish_field(a, f, status);
 }
 
 // x0 paths: a field whose right-hand side is zero has solution zero.
@@ -334,21 +427,38 @@ __global__ __launch_bounds__(kBlock) void k_field_sum(const float* v, int64_t ce
 
 __global__ __launch_bounds__(kBlock) void k_sum_finish(const double* partials, int bpf, double* out) {
     const int f = blockIdx.x;
-    double t = block_sum_fixed(partials + (size_t)f * bpf, bpf);
+    __shared__ double sh[kWaves];
+    double t = block_sum_fixed(partials + (size_t)f * bpf, bpf, sh);
     if (threadIdx.x == 0) out[f] = t;
 }
 
 // ---------------------------------------------------------------- host side
 
 struct Plan {
-    int ty, zc, xsegs, ygroups, zchunks, wpf, bpf, nblocks;
+    int vec, ty, zc, xsegs, ygroups, zchunks, wpf, bpf, nblocks;
+    bool edge;
 };
 
-Plan make_plan(const HexGeom& g, int F, int ty, int zc) {
+// VEC: cells per lane.  A wave covers a whole x-row when nx = 64 * VEC for
+// VEC in {4, 2, 1}; any other nx runs with VEC = 1 and edge loads.
+int pick_vec(int nx) {
+    if (nx == 256) return 4;
+    if (nx == 128) return 2;
+    return 1;
+}
+
+bool ty_supported(int vec, int ty) {
+    if (vec == 4) return ty == 2 || ty == 4;
+    return ty == 4 || ty == 8;
+}
+
+Plan make_plan(const HexGeom& g, int F, int vec, int ty, int zc) {
     Plan p;
+    p.vec = vec;
+    p.edge = (vec == 1 && g.nx != 64);
     p.ty = ty;
     p.zc = std::max(1, std::min(zc, g.nz));
-    p.xsegs = (g.nx + 63) / 64;
+    p.xsegs = (g.nx + 64 * vec - 1) / (64 * vec);
     p.ygroups = (g.ny + ty - 1) / ty;
     p.zchunks = (g.nz + p.zc - 1) / p.zc;
     p.wpf = p.xsegs * p.ygroups * p.zchunks;
@@ -357,42 +467,43 @@ Plan make_plan(const HexGeom& g, int F, int ty, int zc) {
     return p;
 }
 
-// Default tiling: TY = 8 rows and a z chunk that gives about 16 waves per
-// compute unit (256 CUs), but never fewer than 8 planes per chunk.
-Plan default_plan(const HexGeom& g, int F) {
-    const int ty = g.ny >= 8 ? 8 : 4;
-    const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + ty - 1) / ty) * F;
+// Default tiling: about 4096 waves in flight (16 per compute unit) with
+// z chunks of at least 8 planes.
+Plan default_plan(const HexGeom& g, int F, int vec) {
+    const int ty = vec == 4 ? 2 : (vec == 2 ? 4 : (g.ny >= 8 ? 8 : 4));
+    const int64_t cols = (int64_t)((g.nx + 64 * vec - 1) / (64 * vec)) * ((g.ny + ty - 1) / ty) * F;
     const int64_t target_waves = 4096;
     int64_t chunks = std::max<int64_t>(1, target_waves / std::max<int64_t>(1, cols));
     int zc = (int)std::max<int64_t>(8, (g.nz + chunks - 1) / chunks);
-    return make_plan(g, F, ty, zc);
+    return make_plan(g, F, vec, ty, zc);
 }
 
-template <int MODE>
-void launch_sweep_mode(const Plan& p, const SweepArgs& a, hipStream_t s) {
-    switch (p.ty) {
-        case 4: hipLaunchKernelGGL((k_sweep<4, MODE>), dim3(p.nblocks), dim3(kBlock), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((k_sweep<8, MODE>), dim3(p.nblocks), dim3(kBlock), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_sweep<16, MODE>), dim3(p.nblocks), dim3(kBlock), 0, s, a); break;
+template <int VEC, int TY, bool EDGE>
+void launch_sweep_t(int mode, const Plan& p, const SweepArgs& a, hipStream_t s) {
+    const dim3 grid(p.nblocks), block(kBlock);
+    switch (mode) {
+        case S1_FIRST: hipLaunchKernelGGL((k_sweep<VEC, TY, S1_FIRST, EDGE>), grid, block, 0, s, a); break;
+        case S1: hipLaunchKernelGGL((k_sweep<VEC, TY, S1, EDGE>), grid, block, 0, s, a); break;
+        case S1_B0: hipLaunchKernelGGL((k_sweep<VEC, TY, S1_B0, EDGE>), grid, block, 0, s, a); break;
+        case S2_FIRST: hipLaunchKernelGGL((k_sweep<VEC, TY, S2_FIRST, EDGE>), grid, block, 0, s, a); break;
+        case S2: hipLaunchKernelGGL((k_sweep<VEC, TY, S2, EDGE>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_sweep<VEC, TY, S_RES, EDGE>), grid, block, 0, s, a); break;
     }
 }
 
 void launch_sweep(int mode, const Plan& p, const SweepArgs& a, hipStream_t s) {
-    switch (mode) {
-        case S1_FIRST: launch_sweep_mode<S1_FIRST>(p, a, s); break;
-        case S1: launch_sweep_mode<S1>(p, a, s); break;
-        case S2_FIRST: launch_sweep_mode<S2_FIRST>(p, a, s); break;
-        case S2: launch_sweep_mode<S2>(p, a, s); break;
-        default: launch_sweep_mode<S_RES>(p, a, s); break;
-    }
-}
-
-void launch_finish(int kind, int F, const FinishArgs& a, hipStream_t s) {
-    switch (kind) {
-        case F1_FIRST: hipLaunchKernelGGL(k_finish<F1_FIRST>, dim3(F), dim3(kBlock), 0, s, a); break;
-        case F1: hipLaunchKernelGGL(k_finish<F1>, dim3(F), dim3(kBlock), 0, s, a); break;
-        case F2: hipLaunchKernelGGL(k_finish<F2>, dim3(F), dim3(kBlock), 0, s, a); break;
-        default: hipLaunchKernelGGL(k_finish<F_RES>, dim3(F), dim3(kBlock), 0, s, a); break;
+    if (p.vec == 4) {
+        if (p.ty == 2) launch_sweep_t<4, 2, false>(mode, p, a, s);
+        else launch_sweep_t<4, 4, false>(mode, p, a, s);
+    } else if (p.vec == 2) {
+        if (p.ty == 4) launch_sweep_t<2, 4, false>(mode, p, a, s);
+        else launch_sweep_t<2, 8, false>(mode, p, a, s);
+    } else if (p.edge) {
+        if (p.ty == 4) launch_sweep_t<1, 4, true>(mode, p, a, s);
+        else launch_sweep_t<1, 8, true>(mode, p, a, s);
+    } else {
+        if (p.ty == 4) launch_sweep_t<1, 4, false>(mode, p, a, s);
+        else launch_sweep_t<1, 8, false>(mode, p, a, s);
     }
 }
 
@@ -403,7 +514,7 @@ constexpr size_t kOffIters = 8192;                  // int32 [STEPS][FIELDS]
 constexpr size_t kOffRelres = kOffIters + 4096;     // double [STEPS][FIELDS]
 constexpr size_t kOffStatus = kOffRelres + 8192;    // int32 [STEPS][FIELDS]
 constexpr size_t kOffSums = kOffStatus + 4096;      // double [2][FIELDS]
-constexpr size_t kSmallFixed = 64 * 1024;           // partials follow
+constexpr size_t kSmallFixed = 64 * 1024;           // P1 and P2 partials follow
 
 // Layout of the pinned host buffer (bytes).
 constexpr size_t kPinFlags = 0;                     // int[2]
@@ -414,28 +525,38 @@ constexpr size_t kPinSums = kPinStatus + 4096;
 constexpr size_t kPinBytes = kPinSums + 4096;
 
 size_t small_bytes(int F, int bpf) {
-    size_t b = kSmallFixed + (size_t)F * 2 * (size_t)bpf * sizeof(double);
+    size_t b = kSmallFixed + 2 * (size_t)F * 2 * (size_t)bpf * sizeof(double);
     return (b + 255) & ~(size_t)255;
 }
 
 }  // namespace
 
+// Largest partial count any plan can use for this mesh (VEC = 1, TY = 4, one
+// plane per chunk), so the workspace never has to grow between plans.
+static size_t max_bpf(const HexGeom& g, int F) {
+    Plan p = make_plan(g, F, 1, 4, 1);
+    return (size_t)p.bpf;
+}
+
 size_t diffuse_hex_workspace(const cgd_mesh m, int32_t F) {
-    Plan p = default_plan(m->hex, F);
-    return small_bytes(F, p.bpf) + 4 * (size_t)F * m->cells * sizeof(float);
+    return small_bytes(F, (int)max_bpf(m->hex, F)) + 4 * (size_t)F * m->cells * sizeof(float);
 }
 
 cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s) {
     const HexGeom& g = m->hex;
     const int F = da.F;
     const int64_t cells = m->cells;
-    Plan p = default_plan(g, F);
+    // vector width: rows must be 16 / 8 byte aligned in every buffer touched
+    int vec = pick_vec(g.nx);
+    const uintptr_t align = (uintptr_t)da.field | (uintptr_t)(da.x0_mode == 2 ? da.x0 : nullptr);
+    if (align % (4 * vec)) vec = 1;
+    Plan p = default_plan(g, F, vec);
     if (const char* e = getenv("CGD_HEX_TILE")) {  // "TY,ZC" for tuning runs
         int ty = 0, zc = 0;
-        if (sscanf(e, "%d,%d", &ty, &zc) == 2 && (ty == 4 || ty == 8 || ty == 16) && zc > 0)
-            p = make_plan(g, F, ty, zc);
+        if (sscanf(e, "%d,%d", &ty, &zc) == 2 && ty_supported(vec, ty) && zc > 0)
+            p = make_plan(g, F, vec, ty, zc);
     }
-    const size_t small = small_bytes(F, p.bpf);
+    const size_t small = small_bytes(F, (int)max_bpf(g, F));
     cgd_status rc = ensure_workspace(m, small + 4 * (size_t)F * cells * sizeof(float));
     if (rc != CGD_OK) return rc;
     rc = ensure_pinned(m, kPinBytes);
@@ -448,7 +569,9 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     double* d_relres = reinterpret_cast<double*>(base + kOffRelres);
     int32_t* d_status = reinterpret_cast<int32_t*>(base + kOffStatus);
     double* d_sums = reinterpret_cast<double*>(base + kOffSums);
-    double* d_partials = reinterpret_cast<double*>(base + kSmallFixed);
+    const size_t pmax = (size_t)F * 2 * max_bpf(g, F);
+    double* d_P1 = reinterpret_cast<double*>(base + kSmallFixed);
+    double* d_P2 = d_P1 + pmax;
     float* W0 = reinterpret_cast<float*>(base + small);
     float* R = W0 + (size_t)F * cells;
     float* PA = R + (size_t)F * cells;
@@ -472,52 +595,47 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     a.bpf = p.bpf;
     a.nblocks = p.nblocks;
     a.st = d_state;
-    a.partials = d_partials;
+    a.P1 = d_P1;
+    a.P2 = d_P2;
+    a.ndone = d_ndone;
+    a.iters = d_iters;
+    a.relres = d_relres;
+    a.status = d_status;
+    a.rtol2 = da.rtol * da.rtol;
     a.R = R;
-
-    FinishArgs fa = {};
-    fa.partials = d_partials;
-    fa.bpf = p.bpf;
-    fa.st = d_state;
-    fa.ndone = d_ndone;
-    fa.rtol2 = da.rtol * da.rtol;
-    fa.max_iter = da.max_iter;
-    fa.iters = d_iters;
-    fa.relres = d_relres;
-    fa.status = d_status;
 
     int* pinned_flags = reinterpret_cast<int*>(pin + kPinFlags);
     const int chunk = std::max(1, da.check_every);
     const int sum_bpf = (int)std::min<int64_t>(1024, (cells + kBlock - 1) / kBlock);
+    double* d_sum_part = d_P2;  // free outside the solves
 
     if (out) {  // mass before diffusion
-        hipLaunchKernelGGL(k_field_sum, dim3(sum_bpf, F), dim3(kBlock), 0, s, da.field, cells, d_partials, sum_bpf);
-        hipLaunchKernelGGL(k_sum_finish, dim3(F), dim3(kBlock), 0, s, d_partials, sum_bpf, d_sums);
+        hipLaunchKernelGGL(k_field_sum, dim3(sum_bpf, F), dim3(kBlock), 0, s, da.field, cells, d_sum_part, sum_bpf);
+        hipLaunchKernelGGL(k_sum_finish, dim3(F), dim3(kBlock), 0, s, d_sum_part, sum_bpf, d_sums);
     }
 
     float* cur = da.field;  // b of the current step
     float* nxt = W0;        // x of the current step
     for (int step = 0; step < da.n_steps; ++step) {
-        fa.step = step;
+        a.step = step;
         a.B = cur;
         a.X = nxt;
         hipLaunchKernelGGL(k_step_init, dim3(1), dim3(64), 0, s, d_state, F, d_ndone, d_status + step * CGD_MAX_FIELDS);
         const bool use_x0 = (da.x0_mode == 1) || (da.x0_mode == 2 && step == 0);
         int it;  // index of the next iteration to enqueue
         if (!use_x0) {
+            a.k = 0;
             launch_sweep(S1_FIRST, p, a, s);
-            launch_finish(F1_FIRST, F, fa, s);
             launch_sweep(S2_FIRST, p, a, s);
-            launch_finish(F2, F, fa, s);
             it = 1;
         } else {
             const float* x0 = da.x0_mode == 1 ? cur : da.x0;
             CGD_HIP_TRY(hipMemcpyAsync(nxt, x0, (size_t)F * cells * sizeof(float), hipMemcpyDeviceToDevice, s));
+            a.k = 0;
             launch_sweep(S_RES, p, a, s);
-            launch_finish(F_RES, F, fa, s);
             it = 0;
         }
-        // Iterations are enqueued `chunk` at a time; the number of converged
+        // Iterations are enqueued `chunk` at a time; the number of stopped
         // fields is copied back after each chunk and checked one chunk later,
         // so the device always has queued work while the host waits.
         int slot = 0;
@@ -525,23 +643,23 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         for (;;) {
             const int todo = std::min(chunk, da.max_iter - it);
             for (int c = 0; c < todo; ++c, ++it) {
+                int mode1 = S1;
                 if (!use_x0) {
                     a.Pold = it == 1 ? cur : ((it & 1) ? PB : PA);
                     a.Pnew = (it & 1) ? PA : PB;
-                    a.beta_zero = 0;
                 } else {
                     a.Pold = (it & 1) ? PA : PB;
                     a.Pnew = (it & 1) ? PB : PA;
-                    a.beta_zero = it == 0;
+                    if (it == 0) mode1 = S1_B0;
                 }
+                a.k = it;
+                const int64_t tag = (int64_t)step * 65536 + it;
                 int t1 = timing_begin(&m->timing, s);
-                launch_sweep(S1, p, a, s);
-                timing_end(&m->timing, t1, 0, 12.0 * (double)F * cells, s);
-                launch_finish(F1, F, fa, s);
+                launch_sweep(mode1, p, a, s);
+                timing_end(&m->timing, t1, 0, 12.0 * (double)F * cells, s, tag);
                 int t2 = timing_begin(&m->timing, s);
                 launch_sweep(S2, p, a, s);
-                timing_end(&m->timing, t2, 1, 20.0 * (double)F * cells, s);
-                launch_finish(F2, F, fa, s);
+                timing_end(&m->timing, t2, 1, 20.0 * (double)F * cells, s, tag);
             }
             CGD_HIP_TRY(hipMemcpyAsync(&pinned_flags[slot], d_ndone, sizeof(int), hipMemcpyDeviceToHost, s));
             CGD_HIP_TRY(hipEventRecord(m->ev[slot], s));
@@ -556,6 +674,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             have_prev = true;
             slot ^= 1;
         }
+        hipLaunchKernelGGL(k_step_end, dim3(F), dim3(kBlock), 0, s, a, it, da.max_iter);
         if (use_x0) {
             int blocks = (int)std::min<int64_t>(2048, (cells + kBlock - 1) / kBlock);
             hipLaunchKernelGGL(k_zero_if_rhs_zero, dim3(blocks, F), dim3(kBlock), 0, s, nxt, cells, d_state);
@@ -566,8 +685,8 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         CGD_HIP_TRY(hipMemcpyAsync(da.field, cur, (size_t)F * cells * sizeof(float), hipMemcpyDeviceToDevice, s));
     }
     if (out) {
-        hipLaunchKernelGGL(k_field_sum, dim3(sum_bpf, F), dim3(kBlock), 0, s, da.field, cells, d_partials, sum_bpf);
-        hipLaunchKernelGGL(k_sum_finish, dim3(F), dim3(kBlock), 0, s, d_partials, sum_bpf, d_sums + CGD_MAX_FIELDS);
+        hipLaunchKernelGGL(k_field_sum, dim3(sum_bpf, F), dim3(kBlock), 0, s, da.field, cells, d_sum_part, sum_bpf);
+        hipLaunchKernelGGL(k_sum_finish, dim3(F), dim3(kBlock), 0, s, d_sum_part, sum_bpf, d_sums + CGD_MAX_FIELDS);
     }
     CGD_HIP_TRY(hipGetLastError());
     int32_t* h_iters = reinterpret_cast<int32_t*>(pin + kPinIters);
@@ -575,13 +694,24 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     int32_t* h_status = reinterpret_cast<int32_t*>(pin + kPinStatus);
     double* h_sums = reinterpret_cast<double*>(pin + kPinSums);
     CGD_HIP_TRY(hipMemcpyAsync(h_status, d_status, 4096, hipMemcpyDeviceToHost, s));
+    CGD_HIP_TRY(hipMemcpyAsync(h_iters, d_iters, 4096, hipMemcpyDeviceToHost, s));
     if (out) {
-        CGD_HIP_TRY(hipMemcpyAsync(h_iters, d_iters, 4096, hipMemcpyDeviceToHost, s));
         CGD_HIP_TRY(hipMemcpyAsync(h_rel, d_relres, 8192, hipMemcpyDeviceToHost, s));
         CGD_HIP_TRY(hipMemcpyAsync(h_sums, d_sums, 2 * CGD_MAX_FIELDS * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     CGD_HIP_TRY(hipStreamSynchronize(s));
-    timing_collect(&m->timing);
+    {
+        // an enqueued iteration did work iff its index is below the step's
+        // final iteration count (largest over the fields)
+        std::vector<int> ran(da.n_steps, 0);
+        for (int st = 0; st < da.n_steps; ++st)
+            for (int f = 0; f < F; ++f) ran[st] = std::max(ran[st], (int)h_iters[st * CGD_MAX_FIELDS + f]);
+        timing_collect(&m->timing, [&](int64_t tag) {
+            if (tag < 0) return true;  // not a CG iteration
+            const int st = (int)(tag / 65536), it = (int)(tag % 65536);
+            return st < da.n_steps && it < ran[st];
+        });
+    }
     cgd_status worst = CGD_OK;
     for (int st = 0; st < da.n_steps; ++st)
         for (int f = 0; f < F; ++f) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -23,18 +24,15 @@ void set_error(const std::string& msg);
         }                                                                        \
     } while (0)
 
-// Per-field CG state kept on the device.  Written only by the single-block
-// finisher kernels, read by every sweep.
+// Per-field CG state kept on the device.  Each field is written only by
+// the first block of a kernel and read only by later kernels (the two rr
+// slots alternate by iteration parity so that a kernel never reads a slot
+// its own first block is writing).
 struct CgField {
-    double bb;      // ||b||^2 of the current step
-    double rr;      // ||r||^2 of the current iterate
-    double alpha;   // step length of the current iteration
-    double beta;    // direction update of the next iteration
-    double sum_b;   // sum_k b_k (mass before, divided by V) for stats
-    int32_t iter;   // iterations done in the current step
-    int32_t done;   // 1 once converged / stopped
-    int32_t status; // CGD_OK, CGD_NOT_CONVERGED or CGD_E_BREAKDOWN
-    int32_t pad;
+    double bb;         // ||b||^2 of the current step
+    double rr_par[2];  // ||r_k||^2, slot k % 2
+    int32_t done;      // 1 once converged / stopped
+    int32_t status;    // CGD_OK, CGD_NOT_CONVERGED or CGD_E_BREAKDOWN
 };
 
 // Counters the deposit kernels fill (device).
@@ -62,6 +60,7 @@ struct Timing {
     std::vector<hipEvent_t> used;          // recorded pairs (start, end)
     std::vector<int> kinds;                // kind of each pair
     std::vector<double> bytes;             // algorithmic bytes of each pair
+    std::vector<int64_t> tags;             // caller's label of each pair
     int64_t launches[CGD_TIMING_KINDS] = {};
     double total_ms[CGD_TIMING_KINDS] = {};
     double bytes_per_launch[CGD_TIMING_KINDS] = {};
@@ -70,9 +69,12 @@ struct Timing {
 // Records the start event of a timed launch (no-op when timing is off).
 // Returns an opaque index to pass to timing_end.
 int timing_begin(Timing* t, hipStream_t s);
-void timing_end(Timing* t, int idx, int kind, double bytes, hipStream_t s);
-// Adds the elapsed times of all recorded pairs (the stream must be synchronised).
-void timing_collect(Timing* t);
+// tag: caller's label of the launch, passed back to the filter of timing_collect.
+void timing_end(Timing* t, int idx, int kind, double bytes, hipStream_t s, int64_t tag = -1);
+// Adds the elapsed times of the recorded pairs (the stream must be
+// synchronised); pairs whose tag the filter rejects (launches that found
+// nothing to do) are dropped.
+void timing_collect(Timing* t, const std::function<bool(int64_t)>& keep = nullptr);
 
 // Device workspace owned by a mesh, grown on demand.
 struct Workspace {
