@@ -103,6 +103,15 @@ typedef struct {
     int32_t reserved;
 } cgd_solve_stats;
 
+/* Centroid binning alone (the first half of cgd_deposit): the host cell of
+ * each particle, i.e. the hex cell index (rule of cgd_deposit) or the lowest
+ * id among the tets containing the centroid, and -1 when the position is not
+ * finite or lies outside the mesh.
+ *  pos:  device float32 [n, 3]
+ *  cell: device int32 [n], written
+ * Asynchronous on `stream`. */
+cgd_status cgd_locate(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, void* stream);
+
 /* Particle centroid method (Section 2.2, eq. pcm-k), bit-exact.
  *
  * Each particle p with a finite position inside the closed mesh domain is

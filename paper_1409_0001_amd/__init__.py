@@ -152,6 +152,19 @@ def _opts(rtol, max_iter, x0_mode, x0, check_every):
     return o
 
 
+def locate(mesh: Mesh, pos, cell=None, stream=None):
+    """Host cell of each particle centroid (int32 [N]; -1 when dropped)."""
+    torch = _torch()
+    n = int(pos.shape[0])
+    p_pos = _dev(pos, torch.float32, (n, 3), "pos")
+    if cell is None:
+        cell = torch.empty((n,), dtype=torch.int32, device=pos.device)
+    p_cell = _dev(cell, torch.int32, (n,), "cell")
+    _check(_abi.load().cgd_locate(mesh.handle, n, p_pos, p_cell, _stream_ptr(stream)), "cgd_locate",
+           allow=(0,))
+    return cell
+
+
 def deposit(mesh: Mesh, pos, values, field=None, acc=None, stats=False, stream=None):
     """Particle centroid method (bit-exact).  pos [N, 3] f32, values [F, N] f32.
 

@@ -60,6 +60,8 @@ SIGNATURES = {
     "cgd_mesh_num_cells": (ctypes.c_int64, [c_mesh]),
     "cgd_mesh_kind": (ctypes.c_int32, [c_mesh]),
     "cgd_mesh_nnz": (ctypes.c_int64, [c_mesh]),
+    "cgd_locate": (ctypes.c_int32, [c_mesh, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p]),
     "cgd_deposit": (ctypes.c_int32, [c_mesh, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.POINTER(SolveStats), ctypes.c_void_p]),

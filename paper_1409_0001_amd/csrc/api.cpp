@@ -6,7 +6,8 @@
 #include <new>
 #include <string>
 
-#include "cgd_internal.h"
+#include "cg_common.h"
+#include "tet_data.h"
 
 namespace cgd {
 
@@ -112,21 +113,21 @@ struct DeviceGuard {
     }
 };
 
-// Workspace use of a deposit: the counters sit at byte 48 K (a part of the
-// small region the diffusion does not use), the int64 accumulators (when the
-// caller passes none) from byte 64 K on.  The diffusion that follows in
+// Workspace use of a deposit: the counters sit at kOffDeposit (a part of
+// the small region the diffusion does not use), the int64 accumulators (when
+// the caller passes none) from kSmallFixed on.  The diffusion that follows in
 // cgd_coarse_grain reuses that memory only after the finalising kernel has
 // read it, in stream order.
 static cgd_status deposit_buffers(cgd_mesh m, int32_t F, int64_t* user_acc, int64_t** acc,
                                   DepositInfo** info) {
     size_t acc_bytes = user_acc ? 0 : (size_t)F * m->cells * sizeof(int64_t);
-    size_t need = 64 * 1024 + acc_bytes;
-    size_t diff = diffuse_hex_workspace(m, F);
+    size_t need = kSmallFixed + acc_bytes;
+    size_t diff = m->kind == 0 ? diffuse_hex_workspace(m, F) : diffuse_tet_workspace(m, F);
     cgd_status rc = ensure_workspace(m, need > diff ? need : diff);
     if (rc != CGD_OK) return rc;
     char* base = static_cast<char*>(m->ws.ptr);
-    *info = reinterpret_cast<DepositInfo*>(base + 48 * 1024);
-    *acc = user_acc ? user_acc : reinterpret_cast<int64_t*>(base + 64 * 1024);
+    *info = reinterpret_cast<DepositInfo*>(base + kOffDeposit);
+    *acc = user_acc ? user_acc : reinterpret_cast<int64_t*>(base + kSmallFixed);
     return CGD_OK;
 }
 
@@ -282,9 +283,9 @@ static cgd_status do_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F,
     else
         rc = deposit_tet(m, n, pos, F, values, field, acc_buf, info, s);
     if (rc != CGD_OK || !st) return rc;
-    cgd_status prc = ensure_pinned(m, 64 * 1024);
+    cgd_status prc = ensure_pinned(m, kPinBytes);
     if (prc != CGD_OK) return prc;
-    DepositInfo* h = reinterpret_cast<DepositInfo*>(static_cast<char*>(m->pinned) + 60 * 1024);
+    DepositInfo* h = reinterpret_cast<DepositInfo*>(static_cast<char*>(m->pinned) + kPinDeposit);
     CGD_HIP_TRY(hipMemcpyAsync(h, info, sizeof(DepositInfo), hipMemcpyDeviceToHost, s));
     CGD_HIP_TRY(hipStreamSynchronize(s));
     const int e_n = ceil_log2_count(n);
@@ -309,6 +310,24 @@ static cgd_status do_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F,
         return CGD_E_NONFINITE;
     }
     return CGD_OK;
+}
+
+cgd_status cgd_locate(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, void* stream) {
+    if (!m || n < 0 || (n > 0 && (!pos || !cell))) {
+        set_error("cgd_locate: need a mesh, n >= 0 and non-null pos / cell");
+        return CGD_E_INVALID;
+    }
+    if (reinterpret_cast<uintptr_t>(pos) % 4 || reinterpret_cast<uintptr_t>(cell) % 4) {
+        set_error("cgd_locate: misaligned pointer");
+        return CGD_E_INVALID;
+    }
+    DeviceGuard dg(m->device);
+    if (dg.err != hipSuccess) {
+        set_error(std::string("cgd_locate: ") + hipGetErrorString(dg.err));
+        return CGD_E_HIP;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return m->kind == 0 ? locate_hex(m, n, pos, cell, s) : locate_tet(m, n, pos, cell, s);
 }
 
 cgd_status cgd_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,

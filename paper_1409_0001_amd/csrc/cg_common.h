@@ -1,0 +1,116 @@
+// Pieces shared by the hex (stencil) and tet (CSR) conjugate-gradient solvers.
+#pragma once
+
+#include <algorithm>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "cgd_internal.h"
+
+namespace cgd {
+
+constexpr int kCgWaves = 4;
+constexpr int kCgBlock = 64 * kCgWaves;
+
+// Layout of the small region at the start of a mesh workspace (bytes).
+constexpr size_t kOffState = 0;                   // CgField[CGD_MAX_FIELDS]
+constexpr size_t kOffNdone = 4096;                // int
+constexpr size_t kOffIters = 8192;                // int32 [STEPS][FIELDS]
+constexpr size_t kOffRelres = kOffIters + 4096;   // double [STEPS][FIELDS]
+constexpr size_t kOffStatus = kOffRelres + 8192;  // int32 [STEPS][FIELDS]
+constexpr size_t kOffSums = kOffStatus + 4096;    // double [2][FIELDS]
+constexpr size_t kOffDeposit = 48 * 1024;         // DepositInfo
+constexpr size_t kSmallFixed = 64 * 1024;         // partial sums follow
+
+// Layout of the pinned host buffer (bytes).
+constexpr size_t kPinFlags = 0;  // int[2]
+constexpr size_t kPinIters = 4096;
+constexpr size_t kPinRelres = kPinIters + 4096;
+constexpr size_t kPinStatus = kPinRelres + 8192;
+constexpr size_t kPinSums = kPinStatus + 4096;
+constexpr size_t kPinDeposit = kPinSums + 4096;
+constexpr size_t kPinBytes = kPinDeposit + 4096;
+
+// Convergence bookkeeping written by the first block of a sweep.
+struct CgCtl {
+    CgField* st;       // [F]
+    int* ndone;
+    int32_t* iters;    // [CGD_MAX_STEPS][CGD_MAX_FIELDS]
+    double* relres;
+    int32_t* status;
+    double rtol2;
+    int step;
+};
+
+#ifdef __HIPCC__
+// Sum of n float64 values in one fixed order (thread t adds t, t+256, ...;
+// then a fixed shuffle tree and a fixed sum over the 4 waves).  Every thread
+// of the block returns the same value, bit for bit, in every block.
+__device__ inline double block_sum_fixed(const double* p, int n, double* sh) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kCgBlock) s += p[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kCgWaves; ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+// Block-wide float64 sum in fixed order; the result is valid in thread 0.
+__device__ inline double block_reduce_fixed(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kCgWaves; ++i) t += sh[i];
+    }
+    __syncthreads();
+    return t;
+}
+
+__device__ inline void finish_field(const CgCtl& c, int f, int status) {
+    c.st[f].status = status;
+    c.st[f].done = 1;
+    c.status[c.step * CGD_MAX_FIELDS + f] = status;
+    atomicAdd(c.ndone, 1);
+}
+
+// Records iteration k's residual and, when it meets the tolerance or is not
+// finite, stops the field.  Returns true when the field stops.
+__device__ inline bool check_stop(const CgCtl& c, int f, int k, double rrk, double bb, bool lead) {
+    const bool broken = !isfinite(rrk) || !isfinite(bb);
+    const bool conv = !broken && rrk <= c.rtol2 * bb;
+    if (lead) {
+        c.iters[c.step * CGD_MAX_FIELDS + f] = k;
+        c.relres[c.step * CGD_MAX_FIELDS + f] = bb > 0.0 ? sqrt(rrk / bb) : 0.0;
+        if (broken || conv) finish_field(c, f, broken ? CGD_E_BREAKDOWN : CGD_OK);
+    }
+    return broken || conv;
+}
+
+__global__ void k_cg_step_init(CgField* st, int F, int* ndone, int32_t* status_row);
+// Settles the fields still running after k_end iterations, from the r.r
+// partial sums of the last sweep (rr_part: [F][slot stride] with stride).
+__global__ void k_cg_step_end(CgCtl c, const double* rr_part, size_t field_stride, int bpf, int k_end);
+#endif
+
+// Host: enqueues iterations `chunk` at a time through `enqueue(it)` until the
+// device reports all F fields stopped (read back one chunk late, so the
+// device always has queued work) or max_iter iterations are queued.
+// Returns the index of the next iteration that would have been enqueued.
+cgd_status cg_lookahead_loop(cgd_mesh m, int F, int it0, int max_iter, int chunk, const int* d_ndone,
+                             hipStream_t s, const std::function<void(int)>& enqueue, int* it_end);
+
+// Host: after the steps, copies statuses / iterations / residuals back,
+// fills `out`, drops timing pairs of launches that found nothing to do, and
+// returns the worst status.
+cgd_status cg_finish_call(cgd_mesh m, int F, int n_steps, double vol_scale, hipStream_t s,
+                          cgd_solve_stats* out);
+
+}  // namespace cgd

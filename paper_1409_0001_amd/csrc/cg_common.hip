@@ -1,0 +1,118 @@
+// Shared CG bookkeeping kernels and host loops (see cg_common.h).
+#include "cg_common.h"
+
+namespace cgd {
+
+__global__ void k_cg_step_init(CgField* st, int F, int* ndone, int32_t* status_row) {
+    int f = threadIdx.x;
+    if (f < F) {
+        CgField s = {};
+        s.status = CGD_OK;
+        st[f] = s;
+        status_row[f] = CGD_OK;
+    }
+    if (threadIdx.x == 0) *ndone = 0;
+}
+
+__global__ __launch_bounds__(kCgBlock) void k_cg_step_end(CgCtl c, const double* rr_part, size_t field_stride,
+                                                         int bpf, int k_end) {
+    const int f = blockIdx.x;
+    CgField* stf = c.st + f;
+    if (stf->done) return;
+    __shared__ double sh[kCgWaves];
+    const double rrk = block_sum_fixed(rr_part + (size_t)f * field_stride, bpf, sh);
+    if (threadIdx.x != 0) return;
+    const double bb = stf->bb;
+    c.iters[c.step * CGD_MAX_FIELDS + f] = k_end;
+    c.relres[c.step * CGD_MAX_FIELDS + f] = bb > 0.0 ? sqrt(rrk / bb) : 0.0;
+    int status = CGD_OK;
+    if (!isfinite(rrk)) status = CGD_E_BREAKDOWN;
+    else if (!(rrk <= c.rtol2 * bb)) status = CGD_NOT_CONVERGED;
+    finish_field(c, f, status);
+}
+
+cgd_status cg_lookahead_loop(cgd_mesh m, int F, int it0, int max_iter, int chunk, const int* d_ndone,
+                             hipStream_t s, const std::function<void(int)>& enqueue, int* it_end) {
+    int* pinned_flags = reinterpret_cast<int*>(static_cast<char*>(m->pinned) + kPinFlags);
+    int it = it0;
+    int slot = 0;
+    bool have_prev = false;
+    chunk = std::max(1, chunk);
+    for (;;) {
+        const int todo = std::min(chunk, max_iter - it);
+        for (int c = 0; c < todo; ++c, ++it) enqueue(it);
+        CGD_HIP_TRY(hipMemcpyAsync(&pinned_flags[slot], d_ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+        CGD_HIP_TRY(hipEventRecord(m->ev[slot], s));
+        if (have_prev) {
+            CGD_HIP_TRY(hipEventSynchronize(m->ev[slot ^ 1]));
+            if (pinned_flags[slot ^ 1] >= F) break;
+        }
+        if (it >= max_iter) {
+            CGD_HIP_TRY(hipEventSynchronize(m->ev[slot]));
+            break;
+        }
+        have_prev = true;
+        slot ^= 1;
+    }
+    *it_end = it;
+    return CGD_OK;
+}
+
+cgd_status cg_finish_call(cgd_mesh m, int F, int n_steps, double vol_scale, hipStream_t s,
+                          cgd_solve_stats* out) {
+    char* base = static_cast<char*>(m->ws.ptr);
+    char* pin = static_cast<char*>(m->pinned);
+    int32_t* h_iters = reinterpret_cast<int32_t*>(pin + kPinIters);
+    double* h_rel = reinterpret_cast<double*>(pin + kPinRelres);
+    int32_t* h_status = reinterpret_cast<int32_t*>(pin + kPinStatus);
+    double* h_sums = reinterpret_cast<double*>(pin + kPinSums);
+    CGD_HIP_TRY(hipGetLastError());
+    CGD_HIP_TRY(hipMemcpyAsync(h_status, base + kOffStatus, 4096, hipMemcpyDeviceToHost, s));
+    CGD_HIP_TRY(hipMemcpyAsync(h_iters, base + kOffIters, 4096, hipMemcpyDeviceToHost, s));
+    if (out) {
+        CGD_HIP_TRY(hipMemcpyAsync(h_rel, base + kOffRelres, 8192, hipMemcpyDeviceToHost, s));
+        CGD_HIP_TRY(hipMemcpyAsync(h_sums, base + kOffSums, 2 * CGD_MAX_FIELDS * sizeof(double),
+                                   hipMemcpyDeviceToHost, s));
+    }
+    CGD_HIP_TRY(hipStreamSynchronize(s));
+    {
+        // an enqueued iteration did work iff its index is below the step's
+        // final iteration count (largest over the fields)
+        std::vector<int> ran(n_steps, 0);
+        for (int st = 0; st < n_steps; ++st)
+            for (int f = 0; f < F; ++f) ran[st] = std::max(ran[st], (int)h_iters[st * CGD_MAX_FIELDS + f]);
+        timing_collect(&m->timing, [&](int64_t tag) {
+            if (tag < 0) return true;  // not a CG iteration
+            const int st = (int)(tag / 65536), it = (int)(tag % 65536);
+            return st < n_steps && it < ran[st];
+        });
+    }
+    cgd_status worst = CGD_OK;
+    for (int st = 0; st < n_steps; ++st)
+        for (int f = 0; f < F; ++f) {
+            int32_t v = h_status[st * CGD_MAX_FIELDS + f];
+            if (v == CGD_E_BREAKDOWN) {
+                set_error("CG breakdown in pseudo-step " + std::to_string(st) + ", field " + std::to_string(f));
+                worst = CGD_E_BREAKDOWN;
+            } else if (v == CGD_NOT_CONVERGED && worst == CGD_OK) {
+                worst = CGD_NOT_CONVERGED;
+            }
+        }
+    if (out) {
+        out->n_steps = n_steps;
+        out->n_fields = F;
+        for (int st = 0; st < n_steps; ++st)
+            for (int f = 0; f < F; ++f) {
+                out->iters[st][f] = h_iters[st * CGD_MAX_FIELDS + f];
+                out->rel_res[st][f] = h_rel[st * CGD_MAX_FIELDS + f];
+            }
+        for (int f = 0; f < F; ++f) {
+            out->mass_before[f] = h_sums[f] * vol_scale;
+            out->mass_after[f] = h_sums[CGD_MAX_FIELDS + f] * vol_scale;
+        }
+        out->status = worst;
+    }
+    return worst;
+}
+
+}  // namespace cgd

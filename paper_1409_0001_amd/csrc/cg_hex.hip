@@ -25,13 +25,13 @@
 // keeps halo rows in that XCD's L2.
 #include <algorithm>
 
-#include "cgd_internal.h"
+#include "cg_common.h"
 
 namespace cgd {
 namespace {
 
-constexpr int kWaves = 4;
-constexpr int kBlock = 64 * kWaves;
+constexpr int kWaves = kCgWaves;
+constexpr int kBlock = kCgBlock;
 
 enum Mode { S1_FIRST = 0, S1 = 1, S2_FIRST = 2, S2 = 3, S_RES = 4, S1_B0 = 5 };
 
@@ -41,45 +41,16 @@ struct SweepArgs {
     const float* Pold;  // previous direction (sweep 1)
     float* Pnew;        // new direction (sweep 1 writes, sweep 2 reads)
     float* X;           // iterate
-    CgField* st;        // [F]
+    CgCtl c;
     double* P1;         // [F][2][bpf]: slot 0 p.Ap, slot 1 b.b
     double* P2;         // [F][2][bpf]: r.r of r_k in slot k % 2
-    int* ndone;
-    int32_t* iters;     // [CGD_MAX_STEPS][CGD_MAX_FIELDS]
-    double* relres;     // [CGD_MAX_STEPS][CGD_MAX_FIELDS]
-    int32_t* status;    // [CGD_MAX_STEPS][CGD_MAX_FIELDS]
-    double rtol2;
     int64_t cells;
     int nx, ny, nz;
     float cx, cy, cz;
     int xsegs, ygroups, zc;
     int wpf, bpf, nblocks;
     int k;              // iteration index within the step
-    int step;
 };
-
-// Sum of n float64 values in one fixed order (thread t adds t, t+256, ...;
-// then a fixed shuffle tree and a fixed sum over the 4 waves).  Every thread
-// of the block returns the same value, bit for bit, in every block.
-__device__ inline double block_sum_fixed(const double* p, int n, double* sh) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) s += p[i];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    double t = 0.0;
-#pragma unroll
-    for (int i = 0; i < kWaves; ++i) t += sh[i];
-    __syncthreads();
-    return t;
-}
-
-__device__ inline void finish_field(const SweepArgs& a, int f, int status) {
-    a.st[f].status = status;
-    a.st[f].done = 1;
-    a.status[a.step * CGD_MAX_FIELDS + f] = status;
-    atomicAdd(a.ndone, 1);
-}
 
 template <int VEC>
 struct Vec {
@@ -145,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     if ((a.nblocks & 7) == 0) b = (b & 7) * (a.nblocks >> 3) + (b >> 3);
     const int f = b / a.bpf;
     const int blk = b - f * a.bpf;
-    CgField* stf = a.st + f;
+    CgField* stf = a.c.st + f;
     // S2_FIRST must write x and r even when its first block flags a breakdown.
     if (MODE != S2_FIRST && stf->done) return;  // uniform over the block
 
@@ -158,16 +129,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
         double bb;
         if constexpr (MODE == S1_B0) bb = block_sum_fixed(a.P1 + ((size_t)f * 2 + 1) * a.bpf, a.bpf, sh);
         else bb = stf->bb;
-        const bool broken = !isfinite(rrk) || !isfinite(bb);
-        const bool conv = !broken && rrk <= a.rtol2 * bb;
         if (lead) {
-            a.iters[a.step * CGD_MAX_FIELDS + f] = a.k;
-            a.relres[a.step * CGD_MAX_FIELDS + f] = bb > 0.0 ? sqrt(rrk / bb) : 0.0;
             stf->rr_par[a.k & 1] = rrk;
             if (MODE == S1_B0) stf->bb = bb;
-            if (broken || conv) finish_field(a, f, broken ? CGD_E_BREAKDOWN : CGD_OK);
         }
-        if (broken || conv) return;
+        if (check_stop(a.c, f, a.k, rrk, bb, lead)) return;
         if constexpr (MODE == S1) beta = (float)(rrk / stf->rr_par[(a.k - 1) & 1]);
     } else if constexpr (MODE == S2 || MODE == S2_FIRST) {
         const double pap = block_sum_fixed(a.P1 + ((size_t)f * 2 + 0) * a.bpf, a.bpf, sh);
@@ -177,14 +143,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
             if (lead) {
                 stf->bb = bb;
                 stf->rr_par[0] = bb;
-                if (broken) finish_field(a, f, CGD_E_BREAKDOWN);
+                if (broken) finish_field(a.c, f, CGD_E_BREAKDOWN);
             }
             // b = 0 or a breakdown: alpha = 0 gives x = 0, r = b
             alpha = (broken || bb == 0.0) ? 0.f : (float)(bb / pap);
         } else {
             const double rrk = stf->rr_par[a.k & 1];
             if (!(pap > 0.0) || !isfinite(pap)) {
-                if (lead) finish_field(a, f, CGD_E_BREAKDOWN);
+                if (lead) finish_field(a.c, f, CGD_E_BREAKDOWN);
                 return;
             }
             alpha = (float)(rrk / pap);
@@ -367,35 +333,6 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     }
 }
 
-__global__ void k_step_init(CgField* st, int F, int* ndone, int32_t* status_row) {
-    int f = threadIdx.x;
-    if (f < F) {
-        CgField s = {};
-        s.status = CGD_OK;
-        st[f] = s;
-        status_row[f] = CGD_OK;
-    }
-    if (threadIdx.x == 0) *ndone = 0;
-}
-
-// After the last enqueued iteration (k_end iterations done): settles the
-// fields that did not stop inside the loop (converged or not).
-__global__ __launch_bounds__(kBlock) void k_step_end(SweepArgs a, int k_end, int max_iter) {
-    const int f = blockIdx.x;
-    CgField* stf = a.st + f;
-    if (stf->done) return;
-    __shared__ double sh[kWaves];
-    const double rrk = block_sum_fixed(a.P2 + ((size_t)f * 2 + (k_end & 1)) * a.bpf, a.bpf, sh);
-    if (threadIdx.x != 0) return;
-    const double bb = stf->bb;
-    a.iters[a.step * CGD_MAX_FIELDS + f] = k_end;
-    a.relres[a.step * CGD_MAX_FIELDS + f] = bb > 0.0 ? sqrt(rrk / bb) : 0.0;
-    int status = CGD_OK;
-    if (!isfinite(rrk)) status = CGD_E_BREAKDOWN;
-    else if (!(rrk <= a.rtol2 * bb)) status = CGD_NOT_CONVERGED;
-    finish_field(a, f, status);
-}
-
 // x0 paths: a field whose right-hand side is zero has solution zero.
 __global__ void k_zero_if_rhs_zero(float* X, int64_t cells, const CgField* st) {
     const int f = blockIdx.y;
@@ -507,23 +444,6 @@ void launch_sweep(int mode, const Plan& p, const SweepArgs& a, hipStream_t s) {
     }
 }
 
-// Layout of the small region at the start of the workspace (bytes).
-constexpr size_t kOffState = 0;                     // CgField[CGD_MAX_FIELDS]
-constexpr size_t kOffNdone = 4096;                  // int
-constexpr size_t kOffIters = 8192;                  // int32 [STEPS][FIELDS]
-constexpr size_t kOffRelres = kOffIters + 4096;     // double [STEPS][FIELDS]
-constexpr size_t kOffStatus = kOffRelres + 8192;    // int32 [STEPS][FIELDS]
-constexpr size_t kOffSums = kOffStatus + 4096;      // double [2][FIELDS]
-constexpr size_t kSmallFixed = 64 * 1024;           // P1 and P2 partials follow
-
-// Layout of the pinned host buffer (bytes).
-constexpr size_t kPinFlags = 0;                     // int[2]
-constexpr size_t kPinIters = 4096;
-constexpr size_t kPinRelres = kPinIters + 4096;
-constexpr size_t kPinStatus = kPinRelres + 8192;
-constexpr size_t kPinSums = kPinStatus + 4096;
-constexpr size_t kPinBytes = kPinSums + 4096;
-
 size_t small_bytes(int F, int bpf) {
     size_t b = kSmallFixed + 2 * (size_t)F * 2 * (size_t)bpf * sizeof(double);
     return (b + 255) & ~(size_t)255;
@@ -563,11 +483,14 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     if (rc != CGD_OK) return rc;
 
     char* base = static_cast<char*>(m->ws.ptr);
-    CgField* d_state = reinterpret_cast<CgField*>(base + kOffState);
-    int* d_ndone = reinterpret_cast<int*>(base + kOffNdone);
-    int32_t* d_iters = reinterpret_cast<int32_t*>(base + kOffIters);
-    double* d_relres = reinterpret_cast<double*>(base + kOffRelres);
-    int32_t* d_status = reinterpret_cast<int32_t*>(base + kOffStatus);
+    CgCtl ctl;
+    ctl.st = reinterpret_cast<CgField*>(base + kOffState);
+    ctl.ndone = reinterpret_cast<int*>(base + kOffNdone);
+    ctl.iters = reinterpret_cast<int32_t*>(base + kOffIters);
+    ctl.relres = reinterpret_cast<double*>(base + kOffRelres);
+    ctl.status = reinterpret_cast<int32_t*>(base + kOffStatus);
+    ctl.rtol2 = da.rtol * da.rtol;
+    ctl.step = 0;
     double* d_sums = reinterpret_cast<double*>(base + kOffSums);
     const size_t pmax = (size_t)F * 2 * max_bpf(g, F);
     double* d_P1 = reinterpret_cast<double*>(base + kSmallFixed);
@@ -576,7 +499,6 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     float* R = W0 + (size_t)F * cells;
     float* PA = R + (size_t)F * cells;
     float* PB = PA + (size_t)F * cells;
-    char* pin = static_cast<char*>(m->pinned);
 
     const double T = da.bandwidth * da.bandwidth / 4.0;
     const double dtau = T / da.n_steps;
@@ -594,18 +516,11 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     a.wpf = p.wpf;
     a.bpf = p.bpf;
     a.nblocks = p.nblocks;
-    a.st = d_state;
+    a.c = ctl;
     a.P1 = d_P1;
     a.P2 = d_P2;
-    a.ndone = d_ndone;
-    a.iters = d_iters;
-    a.relres = d_relres;
-    a.status = d_status;
-    a.rtol2 = da.rtol * da.rtol;
     a.R = R;
 
-    int* pinned_flags = reinterpret_cast<int*>(pin + kPinFlags);
-    const int chunk = std::max(1, da.check_every);
     const int sum_bpf = (int)std::min<int64_t>(1024, (cells + kBlock - 1) / kBlock);
     double* d_sum_part = d_P2;  // free outside the solves
 
@@ -617,67 +532,53 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     float* cur = da.field;  // b of the current step
     float* nxt = W0;        // x of the current step
     for (int step = 0; step < da.n_steps; ++step) {
-        a.step = step;
+        a.c.step = step;
         a.B = cur;
         a.X = nxt;
-        hipLaunchKernelGGL(k_step_init, dim3(1), dim3(64), 0, s, d_state, F, d_ndone, d_status + step * CGD_MAX_FIELDS);
+        hipLaunchKernelGGL(k_cg_step_init, dim3(1), dim3(64), 0, s, ctl.st, F, ctl.ndone,
+                           ctl.status + step * CGD_MAX_FIELDS);
         const bool use_x0 = (da.x0_mode == 1) || (da.x0_mode == 2 && step == 0);
-        int it;  // index of the next iteration to enqueue
+        int it0;
+        a.k = 0;
         if (!use_x0) {
-            a.k = 0;
             launch_sweep(S1_FIRST, p, a, s);
             launch_sweep(S2_FIRST, p, a, s);
-            it = 1;
+            it0 = 1;
         } else {
             const float* x0 = da.x0_mode == 1 ? cur : da.x0;
             CGD_HIP_TRY(hipMemcpyAsync(nxt, x0, (size_t)F * cells * sizeof(float), hipMemcpyDeviceToDevice, s));
-            a.k = 0;
             launch_sweep(S_RES, p, a, s);
-            it = 0;
+            it0 = 0;
         }
-        // Iterations are enqueued `chunk` at a time; the number of stopped
-        // fields is copied back after each chunk and checked one chunk later,
-        // so the device always has queued work while the host waits.
-        int slot = 0;
-        bool have_prev = false;
-        for (;;) {
-            const int todo = std::min(chunk, da.max_iter - it);
-            for (int c = 0; c < todo; ++c, ++it) {
-                int mode1 = S1;
-                if (!use_x0) {
-                    a.Pold = it == 1 ? cur : ((it & 1) ? PB : PA);
-                    a.Pnew = (it & 1) ? PA : PB;
-                } else {
-                    a.Pold = (it & 1) ? PA : PB;
-                    a.Pnew = (it & 1) ? PB : PA;
-                    if (it == 0) mode1 = S1_B0;
-                }
-                a.k = it;
-                const int64_t tag = (int64_t)step * 65536 + it;
-                int t1 = timing_begin(&m->timing, s);
-                launch_sweep(mode1, p, a, s);
-                timing_end(&m->timing, t1, 0, 12.0 * (double)F * cells, s, tag);
-                int t2 = timing_begin(&m->timing, s);
-                launch_sweep(S2, p, a, s);
-                timing_end(&m->timing, t2, 1, 20.0 * (double)F * cells, s, tag);
+        auto enqueue = [&](int it) {
+            int mode1 = S1;
+            if (!use_x0) {
+                a.Pold = it == 1 ? cur : ((it & 1) ? PB : PA);
+                a.Pnew = (it & 1) ? PA : PB;
+            } else {
+                a.Pold = (it & 1) ? PA : PB;
+                a.Pnew = (it & 1) ? PB : PA;
+                if (it == 0) mode1 = S1_B0;
             }
-            CGD_HIP_TRY(hipMemcpyAsync(&pinned_flags[slot], d_ndone, sizeof(int), hipMemcpyDeviceToHost, s));
-            CGD_HIP_TRY(hipEventRecord(m->ev[slot], s));
-            if (have_prev) {
-                CGD_HIP_TRY(hipEventSynchronize(m->ev[slot ^ 1]));
-                if (pinned_flags[slot ^ 1] >= F) break;
-            }
-            if (it >= da.max_iter) {
-                CGD_HIP_TRY(hipEventSynchronize(m->ev[slot]));
-                break;
-            }
-            have_prev = true;
-            slot ^= 1;
-        }
-        hipLaunchKernelGGL(k_step_end, dim3(F), dim3(kBlock), 0, s, a, it, da.max_iter);
+            a.k = it;
+            const int64_t tag = (int64_t)step * 65536 + it;
+            int t1 = timing_begin(&m->timing, s);
+            launch_sweep(mode1, p, a, s);
+            timing_end(&m->timing, t1, 0, 12.0 * (double)F * cells, s, tag);
+            int t2 = timing_begin(&m->timing, s);
+            launch_sweep(S2, p, a, s);
+            timing_end(&m->timing, t2, 1, 20.0 * (double)F * cells, s, tag);
+        };
+        int it_end = it0;
+        cgd_status rc2 = cg_lookahead_loop(m, F, it0, da.max_iter, da.check_every, ctl.ndone, s, enqueue, &it_end);
+        if (rc2 != CGD_OK) return rc2;
+        CgCtl c2 = ctl;
+        c2.step = step;
+        hipLaunchKernelGGL(k_cg_step_end, dim3(F), dim3(kBlock), 0, s, c2, d_P2 + (size_t)(it_end & 1) * p.bpf,
+                           (size_t)2 * p.bpf, p.bpf, it_end);
         if (use_x0) {
             int blocks = (int)std::min<int64_t>(2048, (cells + kBlock - 1) / kBlock);
-            hipLaunchKernelGGL(k_zero_if_rhs_zero, dim3(blocks, F), dim3(kBlock), 0, s, nxt, cells, d_state);
+            hipLaunchKernelGGL(k_zero_if_rhs_zero, dim3(blocks, F), dim3(kBlock), 0, s, nxt, cells, ctl.st);
         }
         std::swap(cur, nxt);
     }
@@ -688,56 +589,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         hipLaunchKernelGGL(k_field_sum, dim3(sum_bpf, F), dim3(kBlock), 0, s, da.field, cells, d_sum_part, sum_bpf);
         hipLaunchKernelGGL(k_sum_finish, dim3(F), dim3(kBlock), 0, s, d_sum_part, sum_bpf, d_sums + CGD_MAX_FIELDS);
     }
-    CGD_HIP_TRY(hipGetLastError());
-    int32_t* h_iters = reinterpret_cast<int32_t*>(pin + kPinIters);
-    double* h_rel = reinterpret_cast<double*>(pin + kPinRelres);
-    int32_t* h_status = reinterpret_cast<int32_t*>(pin + kPinStatus);
-    double* h_sums = reinterpret_cast<double*>(pin + kPinSums);
-    CGD_HIP_TRY(hipMemcpyAsync(h_status, d_status, 4096, hipMemcpyDeviceToHost, s));
-    CGD_HIP_TRY(hipMemcpyAsync(h_iters, d_iters, 4096, hipMemcpyDeviceToHost, s));
-    if (out) {
-        CGD_HIP_TRY(hipMemcpyAsync(h_rel, d_relres, 8192, hipMemcpyDeviceToHost, s));
-        CGD_HIP_TRY(hipMemcpyAsync(h_sums, d_sums, 2 * CGD_MAX_FIELDS * sizeof(double), hipMemcpyDeviceToHost, s));
-    }
-    CGD_HIP_TRY(hipStreamSynchronize(s));
-    {
-        // an enqueued iteration did work iff its index is below the step's
-        // final iteration count (largest over the fields)
-        std::vector<int> ran(da.n_steps, 0);
-        for (int st = 0; st < da.n_steps; ++st)
-            for (int f = 0; f < F; ++f) ran[st] = std::max(ran[st], (int)h_iters[st * CGD_MAX_FIELDS + f]);
-        timing_collect(&m->timing, [&](int64_t tag) {
-            if (tag < 0) return true;  // not a CG iteration
-            const int st = (int)(tag / 65536), it = (int)(tag % 65536);
-            return st < da.n_steps && it < ran[st];
-        });
-    }
-    cgd_status worst = CGD_OK;
-    for (int st = 0; st < da.n_steps; ++st)
-        for (int f = 0; f < F; ++f) {
-            int32_t v = h_status[st * CGD_MAX_FIELDS + f];
-            if (v == CGD_E_BREAKDOWN) {
-                set_error("CG breakdown in pseudo-step " + std::to_string(st) + ", field " + std::to_string(f));
-                worst = CGD_E_BREAKDOWN;
-            } else if (v == CGD_NOT_CONVERGED && worst == CGD_OK) {
-                worst = CGD_NOT_CONVERGED;
-            }
-        }
-    if (out) {
-        out->n_steps = da.n_steps;
-        out->n_fields = F;
-        for (int st = 0; st < da.n_steps; ++st)
-            for (int f = 0; f < F; ++f) {
-                out->iters[st][f] = h_iters[st * CGD_MAX_FIELDS + f];
-                out->rel_res[st][f] = h_rel[st * CGD_MAX_FIELDS + f];
-            }
-        for (int f = 0; f < F; ++f) {
-            out->mass_before[f] = h_sums[f] * g.vol;
-            out->mass_after[f] = h_sums[CGD_MAX_FIELDS + f] * g.vol;
-        }
-        out->status = worst;
-    }
-    return worst;
+    return cg_finish_call(m, F, da.n_steps, g.vol, s, out);
 }
 
 }  // namespace cgd

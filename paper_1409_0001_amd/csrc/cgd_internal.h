@@ -127,6 +127,24 @@ size_t diffuse_hex_workspace(const cgd_mesh m, int32_t F);
 // ceil(log2 n) for n >= 2, 0 for n <= 1 (the e_N of the fixed-point scale).
 int ceil_log2_count(int64_t n);
 
+// Resets the counters, clears acc [F, cells] and computes max |v| per field.
+void deposit_prologue(int64_t n, int32_t F, const float* values, int64_t* acc, int64_t cells,
+                      DepositInfo* info, hipStream_t s);
+
+#ifdef __HIPCC__
+// Fixed-point scale S = 62 - e_max - e_N, max |v| = m 2^e_max, m in [0.5, 1).
+__device__ inline int frac_bits_of(uint32_t maxbits, int e_n) {
+    if (maxbits == 0u) return 0;
+    int e;
+    (void)frexp((double)__uint_as_float(maxbits), &e);
+    return 62 - e - e_n;
+}
+#endif
+
+// Host cell of each particle (-1: outside / non-finite); device int32 [n].
+cgd_status locate_hex(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hipStream_t s);
+cgd_status locate_tet(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hipStream_t s);
+
 // tet.cpp / tet.hip
 cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
                        float* field, int64_t* acc, DepositInfo* info_dev, hipStream_t s);

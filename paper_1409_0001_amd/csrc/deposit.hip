@@ -78,14 +78,6 @@ __global__ void k_absmax(const float* __restrict__ values, int64_t n, DepositInf
     }
 }
 
-// S = 62 - e_max - e_N, with max |v| = m * 2^e_max, m in [0.5, 1).
-__device__ inline int frac_bits_of(uint32_t maxbits, int e_n) {
-    if (maxbits == 0u) return 0;
-    int e;
-    (void)frexp((double)__uint_as_float(maxbits), &e);
-    return 62 - e - e_n;
-}
-
 struct HexBin {
     double lo[3], hi[3], s[3];
     int32_t n[3];
@@ -147,6 +139,15 @@ __global__ __launch_bounds__(kBlock) void k_deposit_hex(
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_locate_hex(const float* __restrict__ pos, int64_t n, HexBin g,
+                                                       int32_t* __restrict__ cell) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        bool nf;
+        const int64_t k = hex_cell(g, pos[3 * p], pos[3 * p + 1], pos[3 * p + 2], &nf);
+        cell[p] = (int32_t)k;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_finalize(const long long* __restrict__ acc,
                                                      float* __restrict__ field, int64_t cells,
                                                      double vol, int e_n, const DepositInfo* info) {
@@ -163,15 +164,25 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const long long* __restrict
 
 }  // namespace
 
+void deposit_prologue(int64_t n, int32_t F, const float* values, int64_t* acc, int64_t cells,
+                      DepositInfo* info, hipStream_t s) {
+    hipLaunchKernelGGL(k_dep_init, dim3(1), dim3(64), 0, s, info);
+    const int64_t words = (int64_t)F * cells;
+    int zblocks = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (words + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_zero64, dim3(zblocks), dim3(kBlock), 0, s, reinterpret_cast<unsigned long long*>(acc),
+                       words);
+    if (n > 0) {
+        int blocks = (int)std::min<int64_t>(4096, (n + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_absmax, dim3(blocks, F), dim3(kBlock), 0, s, values, n, info);
+    }
+}
+
 int ceil_log2_count(int64_t n) {
     if (n <= 1) return 0;
     return 64 - __builtin_clzll((unsigned long long)(n - 1));
 }
 
-cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
-                       float* field, int64_t* acc, DepositInfo* info, hipStream_t s) {
-    const int64_t cells = m->cells;
-    const int e_n = ceil_log2_count(n);
+static HexBin hex_bin(const cgd_mesh m) {
     HexBin g;
     for (int a = 0; a < 3; ++a) {
         g.lo[a] = m->hex.lo[a];
@@ -181,17 +192,25 @@ cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
     g.n[0] = m->hex.nx;
     g.n[1] = m->hex.ny;
     g.n[2] = m->hex.nz;
+    return g;
+}
 
-    hipLaunchKernelGGL(k_dep_init, dim3(1), dim3(64), 0, s, info);
-    const int64_t words = (int64_t)F * cells;
-    {
-        int blocks = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (words + kBlock - 1) / kBlock));
-        hipLaunchKernelGGL(k_zero64, dim3(blocks), dim3(kBlock), 0, s,
-                           reinterpret_cast<unsigned long long*>(acc), words);
-    }
+cgd_status locate_hex(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hipStream_t s) {
     if (n > 0) {
-        int blocks = (int)std::min<int64_t>(4096, (n + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(k_absmax, dim3(blocks, F), dim3(kBlock), 0, s, values, n, info);
+        const int blocks = (int)std::min<int64_t>(16384, (n + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_locate_hex, dim3(blocks), dim3(kBlock), 0, s, pos, n, hex_bin(m), cell);
+    }
+    CGD_HIP_TRY(hipGetLastError());
+    return CGD_OK;
+}
+
+cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
+                       float* field, int64_t* acc, DepositInfo* info, hipStream_t s) {
+    const int64_t cells = m->cells;
+    const int e_n = ceil_log2_count(n);
+    const HexBin g = hex_bin(m);
+    deposit_prologue(n, F, values, acc, cells, info, s);
+    if (n > 0) {
         int dblocks = (int)std::min<int64_t>(16384, (n + kBlock - 1) / kBlock);
         int t = timing_begin(&m->timing, s);
         hipLaunchKernelGGL(k_deposit_hex, dim3(dblocks), dim3(kBlock), 0, s, pos, values, n, F, g,

@@ -1,0 +1,598 @@
+// Unstructured tetrahedral meshes: centroid location + fixed-point deposit
+// (Section 2.2 on arbitrary cells) and backward-Euler diffusion with the
+// two-point-flux finite-volume Laplacian by Jacobi-preconditioned CG over an
+// LDS-staged CSR SpMV (Sections 2.1 item 4, 4.3, 5.1).
+//
+// Point location: the tets listed in the particle's bucket are tested in
+// ascending id order; a tet contains the point when, for each face, the
+// float64 orientation of the point relative to the face (evaluated on the
+// face's vertices in increasing global-id order, so both tets sharing a face
+// compute the identical number) is not strictly on the opposite side from
+// the tet's fourth vertex.  The first hit is the lowest containing id.
+//
+// Diffusion step: (M + dtau K) x = M e with M = diag(V), K the CSR Laplacian;
+// Jacobi preconditioner D = diag(M + dtau K).  One iteration k is two sweeps:
+//   sweep 1: p = D^-1 r + beta p_old (recomputed at the columns it gathers),
+//            q = A p via the CSR rows staged in LDS, p.q;  writes p, q
+//   sweep 2: x += alpha p, r -= alpha q, z = D^-1 r; r.z and r.r;  writes x, r
+// Scalars come from the previous sweep's float64 block partials, summed by
+// every block in one fixed order (cg_common.h).
+#pragma clang fp contract(off)
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "cg_common.h"
+#include "tet_data.h"
+
+namespace cgd {
+namespace {
+
+constexpr int kBlock = kCgBlock;
+constexpr int kWaves = kCgWaves;
+constexpr int kStage = 8;  // LDS-staged rows hold at most this many entries
+
+// det[b - a, c - a, p - a], the same expression for every caller
+__device__ inline double orient(const double* a, const double* b, const double* c, const double* p) {
+    const double u0 = b[0] - a[0], u1 = b[1] - a[1], u2 = b[2] - a[2];
+    const double v0 = c[0] - a[0], v1 = c[1] - a[1], v2 = c[2] - a[2];
+    const double w0 = p[0] - a[0], w1 = p[1] - a[1], w2 = p[2] - a[2];
+    return u0 * (v1 * w2 - v2 * w1) - u1 * (v0 * w2 - v2 * w0) + u2 * (v0 * w1 - v1 * w0);
+}
+
+__device__ inline bool tet_contains(const double* __restrict__ xyz, const int32_t* __restrict__ tv, int t,
+                                    const double* p) {
+    const int4 v4 = *reinterpret_cast<const int4*>(tv + (size_t)t * 4);
+    const int ids[4] = {v4.x, v4.y, v4.z, v4.w};
+    for (int j = 0; j < 4; ++j) {
+        int f[3], k = 0;
+        for (int i = 0; i < 4; ++i)
+            if (i != j) f[k++] = ids[i];
+        // sort the three ids
+        if (f[0] > f[1]) { int tmp = f[0]; f[0] = f[1]; f[1] = tmp; }
+        if (f[1] > f[2]) { int tmp = f[1]; f[1] = f[2]; f[2] = tmp; }
+        if (f[0] > f[1]) { int tmp = f[0]; f[0] = f[1]; f[1] = tmp; }
+        const double* a = xyz + 3 * (size_t)f[0];
+        const double* b = xyz + 3 * (size_t)f[1];
+        const double* c = xyz + 3 * (size_t)f[2];
+        const double sp = orient(a, b, c, p);
+        const double sd = orient(a, b, c, xyz + 3 * (size_t)ids[j]);
+        const double sg = sd > 0.0 ? 1.0 : (sd < 0.0 ? -1.0 : 0.0);
+        if (!(sp * sg >= 0.0)) return false;
+    }
+    return true;
+}
+
+struct LocArgs {
+    const double* xyz;
+    const int32_t* tv;
+    const double* bbox;
+    const int64_t* bstart;
+    const int32_t* blist;
+    int32_t nb[3];
+    double glo[3], ghi[3], ginv[3];
+};
+
+// Containing tet of a point, -1 when none (outside the mesh or non-finite).
+__device__ inline int locate(const LocArgs& g, const double* p) {
+    int bi[3];
+    for (int a = 0; a < 3; ++a) {
+        if (!(p[a] >= g.glo[a] && p[a] <= g.ghi[a])) return -1;
+        int b = (int)floor((p[a] - g.glo[a]) * g.ginv[a]);
+        bi[a] = b < 0 ? 0 : (b >= g.nb[a] ? g.nb[a] - 1 : b);
+    }
+    const size_t bk = (size_t)bi[0] + (size_t)g.nb[0] * ((size_t)bi[1] + (size_t)g.nb[1] * bi[2]);
+    const int64_t e = g.bstart[bk + 1];
+    for (int64_t i = g.bstart[bk]; i < e; ++i) {
+        const int t = g.blist[i];
+        const double* bb = g.bbox + (size_t)t * 6;
+        if (p[0] < bb[0] || p[1] < bb[1] || p[2] < bb[2] || p[0] > bb[3] || p[1] > bb[4] || p[2] > bb[5]) continue;
+        if (tet_contains(g.xyz, g.tv, t, p)) return t;
+    }
+    return -1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_locate_deposit_tet(const float* __restrict__ pos,
+                                                               const float* __restrict__ values, int64_t n, int F,
+                                                               LocArgs g, int e_n, unsigned long long* __restrict__ acc,
+                                                               int64_t cells, DepositInfo* info, int32_t* cell_out) {
+    __shared__ int S[CGD_MAX_FIELDS];
+    if (threadIdx.x < F) S[threadIdx.x] = frac_bits_of(info->maxbits[threadIdx.x], e_n);
+    __syncthreads();
+    unsigned long long dropped = 0ull, nfpos = 0ull;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const double p[3] = {(double)pos[3 * q], (double)pos[3 * q + 1], (double)pos[3 * q + 2]};
+        int t = -1;
+        if (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) {
+            t = locate(g, p);
+        } else {
+            ++nfpos;
+        }
+        if (cell_out) cell_out[q] = t;
+        if (t < 0) {
+            ++dropped;
+            continue;
+        }
+        for (int f = 0; f < F; ++f) {
+            const float v = values[(size_t)f * n + q];
+            if (!isfinite(v)) continue;
+            const long long qv = __double2ll_rn(ldexp((double)v, S[f]));
+            if (qv != 0) atomicAdd(&acc[(size_t)f * cells + t], (unsigned long long)qv);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        dropped += __shfl_xor(dropped, o);
+        nfpos += __shfl_xor(nfpos, o);
+    }
+    if ((threadIdx.x & 63) == 0 && dropped) {
+        atomicAdd(&info->dropped, dropped);
+        if (nfpos) atomicAdd(&info->nonfinite_pos, nfpos);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize_vol(const long long* __restrict__ acc, float* __restrict__ field,
+                                                         int64_t cells, const double* __restrict__ vol, int e_n,
+                                                         const DepositInfo* info) {
+    const int f = blockIdx.y;
+    const int S = frac_bits_of(info->maxbits[f], e_n);
+    const long long* a = acc + (size_t)f * cells;
+    float* out = field + (size_t)f * cells;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < cells; k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = (float)(ldexp((double)a[k], -S) / vol[k]);
+}
+
+// ---------------------------------------------------------------- PCG
+
+enum TMode { T1_FIRST = 0, T1 = 1, T2_FIRST = 2, T2 = 3 };
+
+struct TetArgs {
+    const int32_t* rowptr;
+    const int32_t* col;
+    const float* val;     // K
+    const float* volf;    // V (float)
+    const float* dinv;    // 1 / (V + dtau K_ii)
+    const float* B;       // e^n (the step's input field)
+    float* R;
+    float* X;
+    const float* Pold;
+    float* Pnew;
+    float* Q;
+    CgCtl c;
+    double* P1;           // [F][3][bpf]: p.q, r.z (k = 0), r.r (k = 0)
+    double* P2;           // [F][2][2][bpf]: parity, (r.z, r.r)
+    int n;                // rows
+    int bpf, nblocks, nchunks;
+    float dtau;
+    int k;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_tet_sweep(TetArgs a) {
+    int b = blockIdx.x;
+    if ((a.nblocks & 7) == 0) b = (b & 7) * (a.nblocks >> 3) + (b >> 3);
+    const int f = b / a.bpf;
+    const int blk = b - f * a.bpf;
+    CgField* stf = a.c.st + f;
+    if (MODE != T2_FIRST && stf->done) return;
+
+    __shared__ double sh[kWaves];
+    const bool lead = blk == 0 && threadIdx.x == 0;
+    float alpha = 0.f, beta = 0.f;
+    if constexpr (MODE == T1) {
+        const double* p2 = a.P2 + ((size_t)f * 4 + (a.k & 1) * 2) * a.bpf;
+        const double rz = block_sum_fixed(p2, a.bpf, sh);
+        const double rr = block_sum_fixed(p2 + a.bpf, a.bpf, sh);
+        if (lead) stf->rr_par[a.k & 1] = rz;
+        if (check_stop(a.c, f, a.k, rr, stf->bb, lead)) return;
+        beta = (float)(rz / stf->rr_par[(a.k - 1) & 1]);
+    } else if constexpr (MODE == T2 || MODE == T2_FIRST) {
+        const double* p1 = a.P1 + (size_t)f * 3 * a.bpf;
+        const double pq = block_sum_fixed(p1, a.bpf, sh);
+        if constexpr (MODE == T2_FIRST) {
+            const double rz = block_sum_fixed(p1 + a.bpf, a.bpf, sh);
+            const double bb = block_sum_fixed(p1 + 2 * a.bpf, a.bpf, sh);
+            const bool broken = !isfinite(bb) || !isfinite(pq) || !isfinite(rz) || (bb > 0.0 && !(pq > 0.0));
+            if (lead) {
+                stf->bb = bb;
+                stf->rr_par[0] = rz;
+                if (broken) finish_field(a.c, f, CGD_E_BREAKDOWN);
+            }
+            alpha = (broken || bb == 0.0) ? 0.f : (float)(rz / pq);
+        } else {
+            if (!(pq > 0.0) || !isfinite(pq)) {
+                if (lead) finish_field(a.c, f, CGD_E_BREAKDOWN);
+                return;
+            }
+            alpha = (float)(stf->rr_par[a.k & 1] / pq);
+        }
+    }
+
+    const size_t fo = (size_t)f * a.n;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+
+    for (int chunk = blk; chunk < a.nchunks; chunk += a.bpf) {
+        const int r0 = chunk * kBlock;
+        const int i = r0 + threadIdx.x;
+        const bool valid = i < a.n;
+        if constexpr (MODE == T1_FIRST || MODE == T1) {
+            __shared__ int s_col[kBlock * kStage];
+            __shared__ float s_val[kBlock * kStage];
+            // stage the chunk's CSR entries in LDS (coalesced)
+            const int r1 = min(r0 + kBlock, a.n);
+            const int e0 = a.rowptr[r0], e1 = a.rowptr[r1];
+            for (int e = e0 + threadIdx.x; e < e1; e += kBlock) {
+                s_col[e - e0] = a.col[e];
+                s_val[e - e0] = a.val[e];
+            }
+            __syncthreads();
+            if (valid) {
+                auto pval = [&](int j) -> float {
+                    if constexpr (MODE == T1_FIRST) return a.dinv[j] * (a.volf[j] * a.B[fo + j]);
+                    else return fmaf(beta, a.Pold[fo + j], a.dinv[j] * a.R[fo + j]);
+                };
+                const float pi = pval(i);
+                float kp = 0.f;
+                const int b0 = a.rowptr[i] - e0, b1 = a.rowptr[i + 1] - e0;
+                for (int e = b0; e < b1; ++e) {
+                    const int j = s_col[e];
+                    kp = fmaf(s_val[e], j == i ? pi : pval(j), kp);
+                }
+                const float q = fmaf(a.dtau, kp, a.volf[i] * pi);
+                a.Pnew[fo + i] = pi;
+                a.Q[fo + i] = q;
+                acc0 = fma((double)pi, (double)q, acc0);
+                if constexpr (MODE == T1_FIRST) {
+                    const float r = a.volf[i] * a.B[fo + i];
+                    a.R[fo + i] = r;
+                    acc1 = fma((double)r, (double)pi, acc1);  // r.z with z = p
+                    acc2 = fma((double)r, (double)r, acc2);
+                }
+            }
+            __syncthreads();
+        } else {
+            if (valid) {
+                const float p = a.Pnew[fo + i];
+                const float q = a.Q[fo + i];
+                const float x = MODE == T2_FIRST ? alpha * p : fmaf(alpha, p, a.X[fo + i]);
+                const float r = fmaf(-alpha, q, a.R[fo + i]);
+                a.X[fo + i] = x;
+                a.R[fo + i] = r;
+                const float z = a.dinv[i] * r;
+                acc0 = fma((double)r, (double)z, acc0);
+                acc1 = fma((double)r, (double)r, acc1);
+            }
+        }
+    }
+    const double t0 = block_reduce_fixed(acc0, sh);
+    const double t1 = block_reduce_fixed(acc1, sh);
+    const double t2 = (MODE == T1_FIRST) ? block_reduce_fixed(acc2, sh) : 0.0;
+    if (threadIdx.x == 0) {
+        if constexpr (MODE == T1_FIRST || MODE == T1) {
+            double* p1 = a.P1 + (size_t)f * 3 * a.bpf;
+            p1[blk] = t0;
+            if (MODE == T1_FIRST) {
+                p1[a.bpf + blk] = t1;
+                p1[2 * a.bpf + blk] = t2;
+            }
+        } else {
+            double* p2 = a.P2 + ((size_t)f * 4 + ((a.k + 1) & 1) * 2) * a.bpf;
+            p2[blk] = t0;
+            p2[a.bpf + blk] = t1;
+        }
+    }
+}
+
+__global__ void k_tet_dinv(const float* volf, const float* kdiag, float dtau, float* dinv, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        dinv[i] = (float)(1.0 / ((double)volf[i] + (double)dtau * (double)kdiag[i]));
+}
+
+// Sum of V_k e_k per field (mass), into partials [F][bpf].
+__global__ __launch_bounds__(kBlock) void k_tet_mass(const float* e, const double* vol, int n, double* part, int bpf) {
+    const int f = blockIdx.y;
+    __shared__ double sh[kWaves];
+    double s = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        s += vol[i] * (double)e[(size_t)f * n + i];
+    const double t = block_reduce_fixed(s, sh);
+    if (threadIdx.x == 0) part[(size_t)f * bpf + blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_tet_sum_finish(const double* part, int bpf, double* out) {
+    __shared__ double sh[kWaves];
+    const double t = block_sum_fixed(part + (size_t)blockIdx.x * bpf, bpf, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+struct TetPlan {
+    int bpf, nblocks, nchunks;
+};
+
+TetPlan tet_plan(int n, int F) {
+    TetPlan p;
+    p.nchunks = (n + kBlock - 1) / kBlock;
+    p.bpf = std::min(p.nchunks, 2048);
+    p.nblocks = p.bpf * F;
+    return p;
+}
+
+template <typename T>
+cgd_status upload(const std::vector<T>& h, T** d) {
+    if (h.empty()) {
+        *d = nullptr;
+        return CGD_OK;
+    }
+    hipError_t e = hipMalloc(d, h.size() * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(std::string("tet mesh device allocation failed: ") + hipGetErrorString(e));
+        return CGD_E_NOMEM;
+    }
+    CGD_HIP_TRY(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return CGD_OK;
+}
+
+size_t tet_small(int F, int bpf) {
+    size_t b = kSmallFixed + (size_t)F * 7 * (size_t)bpf * sizeof(double);
+    return (b + 255) & ~(size_t)255;
+}
+
+}  // namespace
+
+void destroy_tet_data(cgd_mesh m) {
+    TetData* t = m->tet;
+    if (!t) return;
+    void* ptrs[] = {t->xyz, t->tv, t->vol, t->volf, t->bbox, t->rowptr, t->col, t->val, t->kdiag, t->bstart, t->blist};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    delete t;
+    m->tet = nullptr;
+}
+
+int64_t tet_nnz(cgd_mesh m) { return m->tet ? m->tet->nnz : 0; }
+
+namespace {
+__global__ __launch_bounds__(kBlock) void k_locate_tet(const float* __restrict__ pos, int64_t n, LocArgs g,
+                                                       int32_t* __restrict__ cell) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const double p[3] = {(double)pos[3 * q], (double)pos[3 * q + 1], (double)pos[3 * q + 2]};
+        cell[q] = (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) ? locate(g, p) : -1;
+    }
+}
+
+LocArgs loc_args(const TetData* t) {
+    LocArgs g;
+    g.xyz = t->xyz;
+    g.tv = t->tv;
+    g.bbox = t->bbox;
+    g.bstart = t->bstart;
+    g.blist = t->blist;
+    for (int a = 0; a < 3; ++a) {
+        g.nb[a] = t->nb[a];
+        g.glo[a] = t->glo[a];
+        g.ghi[a] = t->ghi[a];
+        g.ginv[a] = t->ginv[a];
+    }
+    return g;
+}
+}  // namespace
+
+cgd_status locate_tet(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hipStream_t s) {
+    if (n > 0) {
+        const int blocks = (int)std::min<int64_t>(16384, (n + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_locate_tet, dim3(blocks), dim3(kBlock), 0, s, pos, n, loc_args(m->tet), cell);
+    }
+    CGD_HIP_TRY(hipGetLastError());
+    return CGD_OK;
+}
+
+size_t diffuse_tet_workspace(const cgd_mesh m, int32_t F) {
+    const TetPlan p = tet_plan(m->tet->n_tet, F);
+    return tet_small(F, p.bpf) + (5 * (size_t)F + 1) * (size_t)m->tet->n_tet * sizeof(float) + 256;
+}
+
+cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values, float* field,
+                       int64_t* acc, DepositInfo* info, hipStream_t s) {
+    const TetData* t = m->tet;
+    const int64_t cells = t->n_tet;
+    const int e_n = ceil_log2_count(n);
+    deposit_prologue(n, F, values, acc, cells, info, s);
+    if (n > 0) {
+        const LocArgs g = loc_args(t);
+        const int blocks = (int)std::min<int64_t>(16384, (n + kBlock - 1) / kBlock);
+        int tm = timing_begin(&m->timing, s);
+        hipLaunchKernelGGL(k_locate_deposit_tet, dim3(blocks), dim3(kBlock), 0, s, pos, values, n, F, g, e_n,
+                           reinterpret_cast<unsigned long long*>(acc), cells, info, nullptr);
+        timing_end(&m->timing, tm, 2, (12.0 + 12.0 * F) * (double)n, s);
+    }
+    const int blocks = (int)std::min<int64_t>(8192, (cells + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_finalize_vol, dim3(blocks, F), dim3(kBlock), 0, s, reinterpret_cast<const long long*>(acc),
+                       field, cells, t->vol, e_n, info);
+    CGD_HIP_TRY(hipGetLastError());
+    return CGD_OK;
+}
+
+cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s) {
+    if (da.x0_mode != 0) {
+        set_error("cgd_diffuse: tet meshes support x0_mode 0 only");
+        return CGD_E_UNSUPPORTED;
+    }
+    const TetData* t = m->tet;
+    const int F = da.F;
+    const int n = t->n_tet;
+    const TetPlan p = tet_plan(n, F);
+    const size_t small = tet_small(F, p.bpf);
+    cgd_status rc = ensure_workspace(m, diffuse_tet_workspace(m, F));
+    if (rc != CGD_OK) return rc;
+    rc = ensure_pinned(m, kPinBytes);
+    if (rc != CGD_OK) return rc;
+    char* base = static_cast<char*>(m->ws.ptr);
+    CgCtl ctl;
+    ctl.st = reinterpret_cast<CgField*>(base + kOffState);
+    ctl.ndone = reinterpret_cast<int*>(base + kOffNdone);
+    ctl.iters = reinterpret_cast<int32_t*>(base + kOffIters);
+    ctl.relres = reinterpret_cast<double*>(base + kOffRelres);
+    ctl.status = reinterpret_cast<int32_t*>(base + kOffStatus);
+    ctl.rtol2 = da.rtol * da.rtol;
+    ctl.step = 0;
+    double* d_sums = reinterpret_cast<double*>(base + kOffSums);
+    double* d_P1 = reinterpret_cast<double*>(base + kSmallFixed);
+    double* d_P2 = d_P1 + (size_t)F * 3 * p.bpf;
+    float* W0 = reinterpret_cast<float*>(base + small);
+    const size_t fn = (size_t)F * n;
+    float* R = W0 + fn;
+    float* PA = R + fn;
+    float* PB = PA + fn;
+    float* Q = PB + fn;
+    float* dinv = Q + fn;
+
+    const double dtau = da.bandwidth * da.bandwidth / 4.0 / da.n_steps;
+    const int eblocks = std::min(4096, (n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_tet_dinv, dim3(eblocks), dim3(kBlock), 0, s, t->volf, t->kdiag, (float)dtau, dinv, n);
+
+    TetArgs a = {};
+    a.rowptr = t->rowptr;
+    a.col = t->col;
+    a.val = t->val;
+    a.volf = t->volf;
+    a.dinv = dinv;
+    a.c = ctl;
+    a.P1 = d_P1;
+    a.P2 = d_P2;
+    a.n = n;
+    a.bpf = p.bpf;
+    a.nblocks = p.nblocks;
+    a.nchunks = p.nchunks;
+    a.dtau = (float)dtau;
+    a.R = R;
+    a.Q = Q;
+    const int mbpf = std::min(1024, (n + kBlock - 1) / kBlock);
+    double* d_mpart = d_P2;  // free outside the solves
+    if (out) {
+        hipLaunchKernelGGL(k_tet_mass, dim3(mbpf, F), dim3(kBlock), 0, s, da.field, t->vol, n, d_mpart, mbpf);
+        hipLaunchKernelGGL(k_tet_sum_finish, dim3(F), dim3(kBlock), 0, s, d_mpart, mbpf, d_sums);
+    }
+    const double b1 = 4.0 * (n + 1) + 8.0 * (double)t->nnz + 20.0 * n;  // sweep 1, one field
+    const double b2 = 28.0 * n;                                           // sweep 2, one field
+    const dim3 grid(p.nblocks), block(kBlock);
+    float* cur = da.field;
+    float* nxt = W0;
+    for (int step = 0; step < da.n_steps; ++step) {
+        a.c.step = step;
+        a.B = cur;
+        a.X = nxt;
+        hipLaunchKernelGGL(k_cg_step_init, dim3(1), dim3(64), 0, s, ctl.st, F, ctl.ndone,
+                           ctl.status + step * CGD_MAX_FIELDS);
+        a.k = 0;
+        a.Pnew = PA;
+        a.Pold = PB;
+        hipLaunchKernelGGL(k_tet_sweep<T1_FIRST>, grid, block, 0, s, a);
+        hipLaunchKernelGGL(k_tet_sweep<T2_FIRST>, grid, block, 0, s, a);
+        auto enqueue = [&](int it) {
+            a.k = it;
+            a.Pold = (it & 1) ? PA : PB;
+            a.Pnew = (it & 1) ? PB : PA;
+            const int64_t tag = (int64_t)step * 65536 + it;
+            int t1 = timing_begin(&m->timing, s);
+            hipLaunchKernelGGL(k_tet_sweep<T1>, grid, block, 0, s, a);
+            timing_end(&m->timing, t1, 3, b1 * F, s, tag);
+            int t2 = timing_begin(&m->timing, s);
+            hipLaunchKernelGGL(k_tet_sweep<T2>, grid, block, 0, s, a);
+            timing_end(&m->timing, t2, 4, b2 * F, s, tag);
+        };
+        int it_end = 1;
+        rc = cg_lookahead_loop(m, F, 1, da.max_iter, da.check_every, ctl.ndone, s, enqueue, &it_end);
+        if (rc != CGD_OK) return rc;
+        CgCtl c2 = ctl;
+        c2.step = step;
+        // r.r of the last sweep 2: parity (it_end & 1), second slot
+        hipLaunchKernelGGL(k_cg_step_end, dim3(F), dim3(kBlock), 0, s, c2,
+                           d_P2 + ((size_t)(it_end & 1) * 2 + 1) * p.bpf, (size_t)4 * p.bpf, p.bpf, it_end);
+        std::swap(cur, nxt);
+    }
+    if (cur != da.field)
+        CGD_HIP_TRY(hipMemcpyAsync(da.field, cur, fn * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (out) {
+        hipLaunchKernelGGL(k_tet_mass, dim3(mbpf, F), dim3(kBlock), 0, s, da.field, t->vol, n, d_mpart, mbpf);
+        hipLaunchKernelGGL(k_tet_sum_finish, dim3(F), dim3(kBlock), 0, s, d_mpart, mbpf, d_sums + CGD_MAX_FIELDS);
+    }
+    return cg_finish_call(m, F, da.n_steps, 1.0, s, out);
+}
+
+}  // namespace cgd
+
+using namespace cgd;
+
+extern "C" cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tv,
+                                          cgd_mesh* out) {
+    if (!out || !xyz || !tv) {
+        set_error("cgd_mesh_create_tet: null pointer");
+        return CGD_E_INVALID;
+    }
+    *out = nullptr;
+    TetHost h;
+    cgd_status rc;
+    try {
+        rc = build_tet_host(n_vert, xyz, n_tet, tv, &h);
+    } catch (const std::bad_alloc&) {
+        set_error("cgd_mesh_create_tet: host allocation failed");
+        return CGD_E_NOMEM;
+    }
+    if (rc != CGD_OK) return rc;
+    if (h.max_row > kStage) {
+        set_error("cgd_mesh_create_tet: a CSR row exceeds the staged row length");
+        return CGD_E_INVALID;
+    }
+    cgd_mesh m = new (std::nothrow) cgd_mesh_s();
+    if (!m) return CGD_E_NOMEM;
+    m->kind = 1;
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        set_error("cgd_mesh_create_tet: no HIP device");
+        return CGD_E_HIP;
+    }
+    m->cells = h.n_tet;
+    m->tet = new (std::nothrow) TetData();
+    if (!m->tet) {
+        delete m;
+        return CGD_E_NOMEM;
+    }
+    TetData* t = m->tet;
+    t->n_tet = h.n_tet;
+    t->n_vert = h.n_vert;
+    t->nnz = (int64_t)h.col.size();
+    t->max_row = h.max_row;
+    for (int a = 0; a < 3; ++a) {
+        t->nb[a] = h.nb[a];
+        t->glo[a] = h.glo[a];
+        t->ghi[a] = h.ghi[a];
+        t->ginv[a] = h.ginv[a];
+    }
+    std::vector<double> hx(xyz, xyz + n_vert * 3);
+    std::vector<int32_t> htv(tv, tv + n_tet * 4);
+    std::vector<float> volf(h.vol.size());
+    for (size_t i = 0; i < volf.size(); ++i) volf[i] = (float)h.vol[i];
+    std::vector<cgd_status> st = {upload(hx, &t->xyz),         upload(htv, &t->tv),       upload(h.vol, &t->vol),
+                                  upload(volf, &t->volf),      upload(h.bbox, &t->bbox),  upload(h.rowptr, &t->rowptr),
+                                  upload(h.col, &t->col),      upload(h.val, &t->val),    upload(h.kdiag, &t->kdiag),
+                                  upload(h.bstart, &t->bstart), upload(h.blist, &t->blist)};
+    for (cgd_status r : st) {
+        if (r != CGD_OK) {
+            cgd_mesh_destroy(m);
+            return r;
+        }
+    }
+    for (int i = 0; i < 2; ++i) {
+        if (hipEventCreateWithFlags(&m->ev[i], hipEventDisableTiming) != hipSuccess) {
+            cgd_mesh_destroy(m);
+            set_error("cgd_mesh_create_tet: hipEventCreate failed");
+            return CGD_E_HIP;
+        }
+    }
+    *out = m;
+    return CGD_OK;
+}

@@ -1,0 +1,52 @@
+// Tetrahedral mesh data: host build products and their device copies.
+#pragma once
+
+#include <vector>
+
+#include "cgd_internal.h"
+
+namespace cgd {
+
+struct TetHost {
+    int64_t n_vert = 0;
+    int32_t n_tet = 0;
+    int64_t n_interior_faces = 0;
+    int32_t max_row = 0;
+    int64_t max_bucket = 0;
+    std::vector<double> vol;      // [n_tet]
+    std::vector<double> bbox;     // [n_tet][6]: min xyz, max xyz
+    std::vector<int32_t> rowptr;  // [n_tet + 1]
+    std::vector<int32_t> col;     // [nnz]
+    std::vector<float> val;       // [nnz]: the Laplacian K
+    std::vector<float> kdiag;     // [n_tet]: K_ii
+    int32_t nb[3] = {1, 1, 1};    // bucket grid
+    double glo[3] = {0, 0, 0}, ghi[3] = {0, 0, 0}, ginv[3] = {0, 0, 0};
+    std::vector<int64_t> bstart;  // [nb + 1]
+    std::vector<int32_t> blist;   // tets per bucket, ascending ids
+};
+
+struct TetData {
+    int32_t n_tet = 0;
+    int64_t n_vert = 0;
+    int64_t nnz = 0;
+    int32_t max_row = 0;
+    int32_t nb[3] = {1, 1, 1};
+    double glo[3], ghi[3], ginv[3];
+    double* xyz = nullptr;      // [n_vert][3]
+    int32_t* tv = nullptr;      // [n_tet][4]
+    double* vol = nullptr;      // [n_tet]
+    float* volf = nullptr;      // [n_tet]
+    double* bbox = nullptr;     // [n_tet][6]
+    int32_t* rowptr = nullptr;  // [n_tet + 1]
+    int32_t* col = nullptr;
+    float* val = nullptr;
+    float* kdiag = nullptr;
+    int64_t* bstart = nullptr;
+    int32_t* blist = nullptr;
+};
+
+cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tv, TetHost* out);
+
+size_t diffuse_tet_workspace(const cgd_mesh m, int32_t F);
+
+}  // namespace cgd

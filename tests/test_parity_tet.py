@@ -1,0 +1,144 @@
+"""GPU parity of the unstructured (tet) path against the CPU oracle.
+
+Point location and deposition are bit-exact (cell ids, int64 sums, float32
+fields); the diffused field is within relative L2 1e-5 of the float64 oracle
+at sizes the oracle solves directly.  At the full 100^3 x 6 mesh the check is
+per step, through properties that hold at any size: the residual of each
+backward-Euler solve in the oracle's own float64 operator, and the error that
+residual leaves, found by solving the error equation in float64.
+"""
+import numpy as np
+import pytest
+
+from oracle import cgd_oracle as O
+from paper_1409_0001_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-5
+
+
+def _t(a, torch):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("n_hex,jitter", [(6, 0.2), (9, 0.0)])
+def test_locate_and_deposit_bit_exact(gpu_lib, n_hex, jitter):
+    import torch
+    cgd = gpu_lib
+    xyz, tets = inputs.kuhn_tet_mesh(n_hex, jitter, seed=51)
+    rng = np.random.default_rng(52)
+    pos = rng.random((20_000, 3)).astype(np.float32)
+    # on vertices, on the hex grid planes, on the main diagonal and outside
+    pos[:50] = xyz[rng.integers(0, len(xyz), 50)].astype(np.float32)
+    pos[50:100, 0] = np.float32(0.5)
+    pos[100:150, 1] = pos[100:150, 0]
+    pos[150:155] = [[1.5, 0.5, 0.5], [-0.1, 0.2, 0.3], [0.5, 0.5, 2.0], [np.nan, 0.1, 0.1], [0.2, np.inf, 0.3]]
+    vals = np.stack([np.full(len(pos), 3.3e-8, np.float32), rng.normal(size=len(pos)).astype(np.float32)])
+    print(f"case: tet {n_hex}^3x6 jitter {jitter}", flush=True)
+    mesh = cgd.TetMesh(xyz, tets)
+    assert mesh.cells == len(tets)
+    P, N, _ = O.tet_faces(tets)
+    assert mesh.nnz == len(tets) + 2 * len(P)
+    cell = cgd.locate(mesh, _t(pos, torch)).cpu().numpy()
+    ref_cell = O.locate_tets(xyz, tets, pos.astype(np.float64))
+    assert np.array_equal(cell, ref_cell)
+    acc = torch.empty((2, mesh.cells), dtype=torch.int64, device="cuda")
+    field, st = cgd.deposit(mesh, _t(pos, torch), _t(vals, torch), acc=acc, stats=True)
+    ref = O.deposit_tet(xyz, tets, pos, vals, cells=ref_cell)
+    assert st.n_dropped == ref["n_dropped"]
+    assert st.frac_bits[:2] == ref["S"]
+    assert np.array_equal(acc.cpu().numpy(), ref["acc"])
+    assert np.array_equal(field.cpu().numpy().view(np.uint32), ref["field32"].view(np.uint32))
+
+
+@pytest.mark.parametrize("n_hex,jitter,steps", [(8, 0.2, 4), (5, 0.0, 2), (12, 0.2, 1)])
+def test_coarse_grain_tet_matches_oracle(gpu_lib, n_hex, jitter, steps):
+    import torch
+    cgd = gpu_lib
+    xyz, tets = inputs.kuhn_tet_mesh(n_hex, jitter, seed=53)
+    rng = np.random.default_rng(54)
+    pos = rng.random((30_000, 3)).astype(np.float32)
+    vals = np.stack([np.full(len(pos), 3.3e-8, np.float32), rng.normal(size=len(pos)).astype(np.float32)])
+    b = 4.0 / n_hex
+    print(f"case: tet coarse_grain {n_hex}^3x6 jitter {jitter} steps {steps}", flush=True)
+    mesh = cgd.TetMesh(xyz, tets)
+    out, st = cgd.coarse_grain(mesh, _t(pos, torch), _t(vals, torch), b, steps, rtol=1e-7, stats=True)
+    dep = O.deposit_tet(xyz, tets, pos, vals)
+    ref = O.diffuse_tet(dep["field64"], xyz, tets, b, steps, solver="direct")
+    o = out.cpu().numpy()
+    V, _ = O.tet_volumes(xyz, tets)
+    for f in range(2):
+        assert rel_l2(o[f], ref[f]) <= REL_L2, (f, rel_l2(o[f], ref[f]))
+        # conservation (eq. conserve) up to the solver tolerance
+        m0 = (dep["field64"][f] * V).sum()
+        assert abs(st.mass_after[f] - m0) <= 1e-5 * np.abs(dep["field64"][f] * V).sum()
+    assert st.status == 0
+
+
+def test_tet_invalid_meshes(gpu_lib):
+    cgd = gpu_lib
+    xyz, tets = inputs.kuhn_tet_mesh(2, 0.0)
+    bad = tets.copy()
+    bad[3, [1, 2]] = bad[3, [2, 1]]  # negative orientation
+    with pytest.raises(cgd.CgdError):
+        cgd.TetMesh(xyz, bad)
+    bad = tets.copy()
+    bad[0, 0] = len(xyz)  # vertex id out of range
+    with pytest.raises(cgd.CgdError):
+        cgd.TetMesh(xyz, bad)
+    with pytest.raises(cgd.CgdError):
+        cgd.TetMesh(xyz, np.concatenate([tets, tets[:1]]))  # a face shared by three tets
+
+
+def test_unstructured_full_size_per_step_residuals(gpu_lib):
+    """The unstructured workload at full size: 100^3 hexes x 6 jittered tets,
+    5M particles, b = 0.04, 4 steps, Jacobi-PCG rtol 1e-6."""
+    import scipy.sparse as sp
+    import torch
+    cgd = gpu_lib
+    xyz, tets, parts, b, steps, rtol = inputs.unstructured()
+    print("case: unstructured 6M tets, 5M particles", flush=True)
+    mesh = cgd.TetMesh(xyz, tets)
+    pos = _t(parts.pos, torch)
+    vals = _t(parts.values, torch)
+    # point location on a sample, one particle at a time in the oracle
+    cell = cgd.locate(mesh, pos).cpu().numpy()
+    sample = np.random.default_rng(55).choice(len(parts.pos), 1000, replace=False)
+    ref_cell = O.locate_tets(xyz, tets, parts.pos[sample].astype(np.float64))
+    assert np.array_equal(cell[sample], ref_cell)
+    assert (cell >= 0).all()
+    # deposition given the located cells: exact sums
+    acc = torch.empty((1, mesh.cells), dtype=torch.int64, device="cuda")
+    field, st = cgd.deposit(mesh, pos, vals, acc=acc, stats=True)
+    S = O.frac_bits(parts.values[0], len(parts.pos))
+    assert st.frac_bits[0] == S
+    q = O.quantise(parts.values[0], S)
+    want = np.bincount(cell, weights=None, minlength=mesh.cells) * int(q[0])  # equal values
+    assert np.array_equal(acc.cpu().numpy()[0], want)
+    # diffusion one step at a time (b / 2 per call gives the same dtau)
+    K, V = O.tet_tpfa(xyz, tets)
+    dtau = b * b / 4.0 / steps
+    A = (sp.diags(V) + dtau * K).tocsr()
+    e = field.cpu().numpy()[0].astype(np.float64)
+    for s in range(steps):
+        _, st = cgd.diffuse(mesh, field, b / np.sqrt(steps), 1, rtol=rtol, stats=True)
+        x = field.cpu().numpy()[0].astype(np.float64)
+        rhs = V * e
+        r = rhs - A @ x
+        res = np.linalg.norm(r) / np.linalg.norm(rhs)
+        # the solver meets rtol on its float32 operator; the float64 residual
+        # also carries the float32 rounding of A and b (cell volumes span 27x)
+        assert res <= 20 * rtol, (s, res)
+        # error of this step's solve: A d = r solved in float64 (30 CG
+        # iterations fix d to far better than the 1e-5 being tested)
+        d, _ = O.cg(A, r, rtol=1e-4, maxiter=60)
+        assert np.linalg.norm(d) / np.linalg.norm(x) <= REL_L2, (s, np.linalg.norm(d) / np.linalg.norm(x))
+        assert abs((V * x).sum() - (V * e).sum()) <= 1e-5 * (V * np.abs(e)).sum()
+        e = x
