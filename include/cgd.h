@@ -169,6 +169,43 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F,
                             const cgd_solver_opts* o, float* field,
                             cgd_solve_stats* st, void* stream);
 
+/* Batched coarse graining of n_snap independent snapshots on one hex mesh
+ * (each snapshot its own particles; F fields each, e.g. solid volume plus
+ * three drag components), each field diffused on its own (Section 3.2.1).
+ *
+ * Deposition follows cgd_deposit per snapshot (its own fixed-point scale per
+ * snapshot and field).  All n_snap * F right-hand sides are then solved by
+ * zero-guess CG (float32 vectors, float64 inner products, same stencil and
+ * stopping rule as cgd_diffuse) in ONE persistent launch in which each
+ * workgroup takes one right-hand side at a time from a device counter.  The
+ * call is captured in a hipGraph on first use for a given argument set and
+ * replayed afterwards; the tile shape is chosen by cgd_autotune_batched (run
+ * automatically on first use).
+ *
+ *  n_snap:  1.. ; n_snap * F <= 4096
+ *  offsets: HOST int64 [n_snap + 1]; snapshot j owns particles
+ *           offsets[j] .. offsets[j+1]-1; offsets[0] = 0, non-decreasing
+ *  pos:     device float32 [offsets[n_snap], 3]
+ *  values:  device float32 [F, offsets[n_snap]]
+ *  fields:  device float32 [n_snap, F, cells], written
+ *  o:       rtol / max_iter as in cgd_diffuse; x0_mode must be 0
+ *  iters:   HOST int32 [n_snap, F, n_steps] or NULL: CG iterations
+ * Hex meshes with nx in {64, 128, 256} only (CGD_E_UNSUPPORTED otherwise).
+ * The call waits for its stream before returning. */
+cgd_status cgd_coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offsets,
+                                    const float* pos, int32_t F, const float* values,
+                                    double bandwidth, int32_t n_steps, const cgd_solver_opts* o,
+                                    float* fields, int32_t* iters, void* stream);
+
+/* Autotuner of the batched solver: times each candidate tile shape (rows per
+ * wave, waves per workgroup) on n_rhs synthetic right-hand sides and keeps
+ * the fastest for this mesh shape (also appended to the file named by the
+ * environment variable CGD_AUTOTUNE_CACHE, when set, and read from it).
+ *  chosen: host, written with the chosen candidate index
+ *  ms:     host double [8] or NULL: time of each candidate (forces a re-run)
+ *  n_cand: host, written with the number of candidates (nullable) */
+cgd_status cgd_autotune_batched(cgd_mesh m, int32_t n_rhs, int32_t* chosen, double* ms, int32_t* n_cand);
+
 /* Kernel timing, for roofline measurement.  While enabled, each launch of the
  * timed kernels is bracketed by two HIP events recorded on the caller's
  * stream; the elapsed times are collected when the call synchronises (every

@@ -228,6 +228,43 @@ def coarse_grain(mesh: Mesh, pos, values, bandwidth, n_steps, rtol=1e-6, max_ite
     return field, (_stats(st, F, n_steps, rc) if stats else None)
 
 
+def coarse_grain_batched(mesh: HexMesh, offsets, pos, values, bandwidth, n_steps, rtol=1e-6, max_iter=1000,
+                         fields=None, return_iters=False, stream=None):
+    """All snapshots at once.  offsets: host int64 [S + 1]; pos [N, 3]; values
+    [F, N].  Returns fields [S, F, cells] (and iterations [S, F, n_steps])."""
+    import numpy as np
+    torch = _torch()
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    n_snap = len(off) - 1
+    n = int(pos.shape[0])
+    F = int(values.shape[0])
+    if off[-1] != n:
+        raise ValueError("offsets[-1] must equal the number of particles")
+    p_pos = _dev(pos, torch.float32, (n, 3), "pos")
+    p_val = _dev(values, torch.float32, (F, n), "values")
+    if fields is None:
+        fields = torch.empty((n_snap, F, mesh.cells), dtype=torch.float32, device=pos.device)
+    p_f = _dev(fields, torch.float32, (n_snap, F, mesh.cells), "fields")
+    o = _opts(rtol, max_iter, 0, None, 4)
+    iters = np.zeros((n_snap, F, n_steps), dtype=np.int32)
+    rc = _abi.load().cgd_coarse_grain_batched(mesh.handle, n_snap, off.ctypes.data, p_pos, F, p_val,
+                                              float(bandwidth), int(n_steps), ctypes.byref(o), p_f,
+                                              iters.ctypes.data, _stream_ptr(stream))
+    _check(rc, "cgd_coarse_grain_batched")
+    return (fields, iters) if return_iters else fields
+
+
+def autotune_batched(mesh: HexMesh, n_rhs: int):
+    """Times the batched solver's tile candidates; returns (chosen, [ms per candidate])."""
+    _torch()
+    ms = (ctypes.c_double * 8)()
+    chosen = ctypes.c_int32()
+    nc = ctypes.c_int32()
+    _check(_abi.load().cgd_autotune_batched(mesh.handle, int(n_rhs), ctypes.byref(chosen), ms,
+                                            ctypes.byref(nc)), "cgd_autotune_batched", allow=(0,))
+    return chosen.value, [ms[i] for i in range(nc.value)]
+
+
 TIMING_KINDS = {0: "cg_sweep1", 1: "cg_sweep2", 2: "deposit", 3: "pcg_spmv_sweep", 4: "pcg_update_sweep"}
 
 

@@ -72,6 +72,12 @@ SIGNATURES = {
                                           ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
                                           ctypes.POINTER(SolverOpts), ctypes.c_void_p,
                                           ctypes.POINTER(SolveStats), ctypes.c_void_p]),
+    "cgd_coarse_grain_batched": (ctypes.c_int32, [c_mesh, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
+                                                  ctypes.c_int32, ctypes.POINTER(SolverOpts), ctypes.c_void_p,
+                                                  ctypes.c_void_p, ctypes.c_void_p]),
+    "cgd_autotune_batched": (ctypes.c_int32, [c_mesh, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "cgd_timing_enable": (ctypes.c_int32, [c_mesh, ctypes.c_int32]),
     "cgd_timing_read": (ctypes.c_int32, [c_mesh, ctypes.POINTER(KernelTiming), ctypes.c_int32]),
     "cgd_status_string": (ctypes.c_char_p, [ctypes.c_int32]),

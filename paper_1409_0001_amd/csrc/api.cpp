@@ -217,6 +217,7 @@ void cgd_mesh_destroy(cgd_mesh m) {
     if (m->pinned) (void)hipHostFree(m->pinned);
     for (int i = 0; i < 2; ++i)
         if (m->ev[i]) (void)hipEventDestroy(m->ev[i]);
+    destroy_batched(m);
     for (hipEvent_t e : m->timing.pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : m->timing.used) (void)hipEventDestroy(e);
     destroy_tet_data(m);
@@ -433,6 +434,68 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, 
     if (rc < 0) return rc;
     if (dep_rc == CGD_E_NONFINITE) return dep_rc;
     return rc;
+}
+
+cgd_status cgd_coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offsets, const float* pos,
+                                    int32_t F, const float* values, double bandwidth, int32_t n_steps,
+                                    const cgd_solver_opts* o, float* fields, int32_t* iters, void* stream) {
+    cgd_status rc = check_common(m, F, "cgd_coarse_grain_batched");
+    if (rc != CGD_OK) return rc;
+    if (m->kind != 0) {
+        set_error("cgd_coarse_grain_batched: hex meshes only");
+        return CGD_E_UNSUPPORTED;
+    }
+    if (n_snap < 1 || (int64_t)n_snap * F > 4096 || !offsets) {
+        set_error("cgd_coarse_grain_batched: need 1 <= n_snap, n_snap * F <= 4096 and offsets");
+        return CGD_E_INVALID;
+    }
+    if (offsets[0] != 0) {
+        set_error("cgd_coarse_grain_batched: offsets[0] must be 0");
+        return CGD_E_INVALID;
+    }
+    for (int j = 0; j < n_snap; ++j) {
+        if (offsets[j + 1] < offsets[j]) {
+            set_error("cgd_coarse_grain_batched: offsets must not decrease");
+            return CGD_E_INVALID;
+        }
+    }
+    if (offsets[n_snap] > 0 && (!pos || !values)) {
+        set_error("cgd_coarse_grain_batched: null pos / values");
+        return CGD_E_INVALID;
+    }
+    DiffuseArgs a;
+    rc = fill_opts(o, F, fields, bandwidth, n_steps, &a, "cgd_coarse_grain_batched");
+    if (rc != CGD_OK) return rc;
+    if (a.x0_mode != 0) {
+        set_error("cgd_coarse_grain_batched: x0_mode must be 0");
+        return CGD_E_INVALID;
+    }
+    if (reinterpret_cast<uintptr_t>(fields) % 16 || reinterpret_cast<uintptr_t>(pos) % 4 ||
+        reinterpret_cast<uintptr_t>(values) % 4) {
+        set_error("cgd_coarse_grain_batched: fields must be 16-byte aligned, pos / values 4-byte aligned");
+        return CGD_E_INVALID;
+    }
+    DeviceGuard dg(m->device);
+    if (dg.err != hipSuccess) {
+        set_error(std::string("cgd_coarse_grain_batched: ") + hipGetErrorString(dg.err));
+        return CGD_E_HIP;
+    }
+    return coarse_grain_batched(m, n_snap, offsets, pos, F, values, a, fields, iters,
+                                static_cast<hipStream_t>(stream));
+}
+
+cgd_status cgd_autotune_batched(cgd_mesh m, int32_t n_rhs, int32_t* chosen, double* ms, int32_t* n_cand) {
+    if (!m || m->kind != 0 || n_rhs < 1 || !chosen) {
+        set_error("cgd_autotune_batched: need a hex mesh, n_rhs >= 1 and chosen");
+        return CGD_E_INVALID;
+    }
+    DeviceGuard dg(m->device);
+    int c = 0, nc = 0;
+    cgd_status rc = autotune_batched(m, n_rhs, &c, ms, &nc);
+    if (rc != CGD_OK) return rc;
+    *chosen = c;
+    if (n_cand) *n_cand = nc;
+    return CGD_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,666 @@
+// Batched coarse graining: many independent snapshots and fields on one hex
+// mesh (Section 3.2.1: each field component is diffused on its own).
+//
+// Deposition is segmented by snapshot (each snapshot and field gets its own
+// fixed-point scale, exactly as a single-snapshot deposit would).  The
+// diffusion of all right-hand sides (snapshots x fields) is ONE persistent
+// launch: each workgroup runs every pseudo-step of the zero-guess CG of its
+// right-hand sides (dealt statically, blockIdx.x + i * gridDim.x) alone,
+// with workgroup-level reductions only (no grid-wide synchronisation, so no
+// co-residency is assumed).  Its waves
+// use the same stencil tiles as the per-launch solver.  The whole call
+// (offset upload, deposit, solve, status read-back) is captured once in a
+// hipGraph per argument set and replayed.  The tile shape (rows per wave,
+// waves per workgroup) comes from an autotuner that times every candidate on
+// the device and caches the choice per mesh shape (and in the file named by
+// CGD_AUTOTUNE_CACHE, when set).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "cg_common.h"
+#include "hex_bin.h"
+#include "stencil_tile.h"
+
+namespace cgd {
+namespace {
+
+using namespace stencil;
+
+constexpr int kDBlock = 256;
+constexpr int kItems = 16;                  // particles per thread per deposit block
+constexpr int kChunk = kDBlock * kItems;    // particles per deposit block
+constexpr int kMaxRhs = 4096;
+
+// ---------------------------------------------------------------- deposit
+
+struct BDep {
+    const int64_t* off;       // [n_snap + 1] device
+    const float* pos;
+    const float* values;      // [F][total]
+    int64_t total;
+    int n_snap, F;
+    uint32_t* maxbits;        // [n_snap][F]
+    unsigned long long* acc;  // [n_snap][F][cells]
+    float* fields;            // [n_snap][F][cells]
+    unsigned long long* counters;  // [0] dropped, [1] non-finite
+    int64_t cells;
+    double vol;
+    HexBin g;
+};
+
+__device__ inline int e_n_of(int64_t n) { return n <= 1 ? 0 : 64 - __clzll((unsigned long long)(n - 1)); }
+
+__global__ void k_bdep_init(BDep d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.n_snap * d.F) d.maxbits[i] = 0u;
+    if (i < 2) d.counters[i] = 0ull;
+}
+
+__global__ void k_bzero(unsigned long long* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+// grid: (chunks, n_snap * F); block (c, j * F + f) covers particles
+// [off[j] + c * kChunk, ...) of snapshot j.
+__global__ __launch_bounds__(kDBlock) void k_babsmax(BDep d) {
+    const int j = blockIdx.y / d.F, f = blockIdx.y % d.F;
+    const int64_t p0 = d.off[j], p1 = d.off[j + 1];
+    const int64_t b = p0 + (int64_t)blockIdx.x * kChunk;
+    uint32_t m = 0u;
+    unsigned long long bad = 0ull;
+    const uint32_t* v = reinterpret_cast<const uint32_t*>(d.values + (size_t)f * d.total);
+    for (int t = 0; t < kItems; ++t) {
+        const int64_t i = b + (int64_t)t * kDBlock + threadIdx.x;
+        if (i < p1) {
+            const uint32_t a = v[i] & 0x7fffffffu;
+            if (a >= 0x7f800000u) ++bad;
+            else m = a > m ? a : m;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t mo = __shfl_xor(m, o);
+        m = mo > m ? mo : m;
+        bad += __shfl_xor(bad, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (m) atomicMax(&d.maxbits[j * d.F + f], m);
+        if (bad) atomicAdd(&d.counters[1], bad);
+    }
+}
+
+__global__ __launch_bounds__(kDBlock) void k_bdeposit(BDep d) {
+    const int j = blockIdx.y;
+    const int64_t p0 = d.off[j], p1 = d.off[j + 1];
+    const int e_n = e_n_of(p1 - p0);
+    __shared__ int S[CGD_MAX_FIELDS];
+    if (threadIdx.x < d.F) S[threadIdx.x] = frac_bits_of(d.maxbits[j * d.F + threadIdx.x], e_n);
+    __syncthreads();
+    const int64_t b = p0 + (int64_t)blockIdx.x * kChunk;
+    unsigned long long dropped = 0ull, nf = 0ull;
+    for (int t = 0; t < kItems; ++t) {
+        const int64_t i = b + (int64_t)t * kDBlock + threadIdx.x;
+        if (i >= p1) break;
+        bool nonfinite;
+        const int64_t k = hex_cell(d.g, d.pos[3 * i], d.pos[3 * i + 1], d.pos[3 * i + 2], &nonfinite);
+        if (k < 0) {
+            ++dropped;
+            nf += nonfinite ? 1ull : 0ull;
+            continue;
+        }
+        for (int f = 0; f < d.F; ++f) {
+            const float v = d.values[(size_t)f * d.total + i];
+            if (!isfinite(v)) continue;
+            const long long q = __double2ll_rn(ldexp((double)v, S[f]));
+            if (q != 0) atomicAdd(&d.acc[((size_t)j * d.F + f) * d.cells + k], (unsigned long long)q);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        dropped += __shfl_xor(dropped, o);
+        nf += __shfl_xor(nf, o);
+    }
+    if ((threadIdx.x & 63) == 0 && dropped) {
+        atomicAdd(&d.counters[0], dropped);
+        if (nf) atomicAdd(&d.counters[1], nf);
+    }
+}
+
+__global__ __launch_bounds__(kDBlock) void k_bfinalize(BDep d) {
+    const int jf = blockIdx.y;
+    const int j = jf / d.F;
+    const int S = frac_bits_of(d.maxbits[jf], e_n_of(d.off[j + 1] - d.off[j]));
+    const long long* a = reinterpret_cast<const long long*>(d.acc) + (size_t)jf * d.cells;
+    float* out = d.fields + (size_t)jf * d.cells;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < d.cells; k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = (float)(ldexp((double)a[k], -S) / d.vol);
+}
+
+// ---------------------------------------------------------------- solver
+
+struct BSolve {
+    float* fields;      // [n_rhs][cells]: in deposited, out diffused
+    float* ws;          // [grid][4][cells]
+    int n_rhs;
+    int64_t cells;
+    Geom g;
+    int xsegs, ygroups;
+    int n_steps;
+    double rtol2;
+    int max_iter;
+    int32_t* iters;     // [n_rhs][n_steps]
+    int32_t* status;    // [n_rhs]
+};
+
+// A value every lane of the wave holds identically, handed to the compiler as
+// a wave-uniform (scalar) value so that branches on it are scalar branches.
+__device__ inline double wave_uniform(double v) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// Workgroup-wide float64 sums of two values in one fixed order; every thread
+// returns the same pair, as wave-uniform values.
+template <int NW>
+__device__ inline void wg_sum2(double& a, double& b, double (*sh)[2]) {
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[w][0] = a;
+        sh[w][1] = b;
+    }
+    __syncthreads();
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        s0 += sh[i][0];
+        s1 += sh[i][1];
+    }
+    __syncthreads();
+    a = wave_uniform(s0);
+    b = wave_uniform(s1);
+}
+
+template <int VEC, int TY, int NW, int MODE>
+__device__ inline void wg_sweep(const BSolve& a, const Ptrs& p, float alpha, float beta, double& s0, double& s1,
+                                double (*sh)[2]) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    double acc0 = 0.0, acc1 = 0.0;
+    const int tiles = a.xsegs * a.ygroups;
+    for (int t = wave; t < tiles; t += NW)
+        tile_sweep<VEC, TY, MODE, false>(p, a.g, 0, t % a.xsegs, t / a.xsegs, 0, a.g.nz, lane, alpha, beta, acc0,
+                                         acc1);
+    wg_sum2<NW>(acc0, acc1, sh);  // includes the barrier that publishes this sweep's writes
+    s0 = acc0;
+    s1 = acc1;
+}
+
+// Right-hand sides are dealt to workgroups statically (rhs = blockIdx.x,
+// blockIdx.x + gridDim.x, ...), so every loop of this kernel is controlled by
+// wave-uniform values: no lane of a wave ever waits at a barrier for another
+// lane of the same wave that took a different path.
+template <int VEC, int TY, int NW>
+__global__ __launch_bounds__(64 * NW) void k_batched_cg(BSolve a) {
+    __shared__ double sh[NW][2];
+    const size_t cells = (size_t)a.cells;
+    float* W0 = a.ws + (size_t)blockIdx.x * 4 * cells;
+    float* R = W0 + cells;
+    float* PA = R + cells;
+    float* PB = PA + cells;
+    for (int rhs = blockIdx.x; rhs < a.n_rhs; rhs += gridDim.x) {
+        float* field = a.fields + (size_t)rhs * cells;
+        float* cur = field;
+        float* nxt = W0;
+        int worst = CGD_OK;
+        for (int step = 0; step < a.n_steps; ++step) {
+            Ptrs p{cur, R, nullptr, nullptr, nxt};
+            double bab, bb, rr, dummy;
+            wg_sweep<VEC, TY, NW, S1_FIRST>(a, p, 0.f, 0.f, bab, bb, sh);
+            bool broken = !isfinite(bb) || !isfinite(bab) || (bb > 0.0 && !(bab > 0.0));
+            const float alpha0 = (broken || bb == 0.0) ? 0.f : (float)(bb / bab);
+            wg_sweep<VEC, TY, NW, S2_FIRST>(a, p, alpha0, 0.f, rr, dummy, sh);
+            double rr_prev = bb;
+            int k = 1;
+            int st = CGD_OK;
+            for (;;) {
+                if (broken || !isfinite(rr)) {
+                    st = CGD_E_BREAKDOWN;
+                    break;
+                }
+                if (rr <= a.rtol2 * bb) break;
+                if (k >= a.max_iter) {
+                    st = CGD_NOT_CONVERGED;
+                    break;
+                }
+                p.Pold = k == 1 ? cur : ((k & 1) ? PB : PA);
+                p.Pnew = (k & 1) ? PA : PB;
+                const float beta = (float)(rr / rr_prev);
+                double pap;
+                wg_sweep<VEC, TY, NW, S1>(a, p, 0.f, beta, pap, dummy, sh);
+                if (!(pap > 0.0) || !isfinite(pap)) {
+                    broken = true;
+                    continue;
+                }
+                const float alpha = (float)(rr / pap);
+                double rr_new;
+                wg_sweep<VEC, TY, NW, S2>(a, p, alpha, 0.f, rr_new, dummy, sh);
+                rr_prev = rr;
+                rr = rr_new;
+                ++k;
+            }
+            if (threadIdx.x == 0) a.iters[(size_t)rhs * a.n_steps + step] = k;
+            if (st == CGD_E_BREAKDOWN || (st == CGD_NOT_CONVERGED && worst == CGD_OK)) worst = st;
+            float* t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        if (cur != field) {  // odd number of steps: the result is in the scratch vector
+            for (size_t i = threadIdx.x; i < cells; i += blockDim.x) field[i] = cur[i];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) a.status[rhs] = worst;
+    }
+}
+
+// Fills n_rhs synthetic right-hand sides (a hash of the index, values in
+// [0, 1)) for autotuning.
+__global__ void k_fill_synthetic(float* f, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)i * 2654435761u;
+        h ^= h >> 15;
+        h *= 2246822519u;
+        h ^= h >> 13;
+        f[i] = (float)(h >> 8) * (1.0f / 16777216.0f);
+    }
+}
+
+// ---------------------------------------------------------------- configs
+
+struct Cfg {
+    int vec, ty, nw;
+    const void* fn;
+};
+
+template <int VEC, int TY, int NW>
+Cfg make_cfg() {
+    return Cfg{VEC, TY, NW, reinterpret_cast<const void*>(&k_batched_cg<VEC, TY, NW>)};
+}
+
+std::vector<Cfg> candidates(int vec) {
+    if (vec == 4) return {make_cfg<4, 2, 8>(), make_cfg<4, 2, 16>(), make_cfg<4, 4, 8>(), make_cfg<4, 4, 16>()};
+    if (vec == 2) return {make_cfg<2, 4, 8>(), make_cfg<2, 4, 16>(), make_cfg<2, 8, 8>(), make_cfg<2, 8, 16>()};
+    return {make_cfg<1, 4, 8>(), make_cfg<1, 4, 16>(), make_cfg<1, 8, 8>(), make_cfg<1, 8, 16>()};
+}
+
+int batched_vec(const HexGeom& g) {
+    if (g.nx == 256) return 4;
+    if (g.nx == 128) return 2;
+    return g.nx == 64 ? 1 : 0;  // 0: unsupported width
+}
+
+// Resident workgroups of a configuration on this device.
+int grid_for(const Cfg& c, int n_rhs) {
+    int dev = 0, cus = 256, per = 1;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, c.fn, 64 * c.nw, 0) != hipSuccess || per < 1) per = 1;
+    return std::max(1, std::min(n_rhs, cus * per));
+}
+
+cgd_status launch_solver(const Cfg& c, const BSolve& a, int grid, hipStream_t s) {
+    void* args[] = {const_cast<BSolve*>(&a)};
+    CGD_HIP_TRY(hipLaunchKernel(c.fn, dim3(grid), dim3(64 * c.nw), args, 0, s));
+    return CGD_OK;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;  // shape key -> candidate index
+
+std::string tune_key(const HexGeom& g, int n_rhs) {
+    char name[64] = "gpu";
+    hipDeviceProp_t prop;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        snprintf(name, sizeof name, "%s", prop.gcnArchName);
+    for (char* q = name; *q; ++q)
+        if (*q == ' ' || *q == ':') *q = '_';
+    return std::string(name) + "/" + std::to_string(g.nx) + "x" + std::to_string(g.ny) + "x" +
+           std::to_string(g.nz) + "/rhs" + std::to_string(std::min(n_rhs, 1024));
+}
+
+void load_tune_file() {
+    const char* path = getenv("CGD_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE* fp = fopen(path, "r");
+    if (!fp) return;
+    char key[256];
+    int idx;
+    double ms;
+    while (fscanf(fp, "%255s %d %lf", key, &idx, &ms) == 3) g_tune[key] = idx;
+    fclose(fp);
+}
+
+void save_tune_file(const std::string& key, int idx, double ms) {
+    const char* path = getenv("CGD_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE* fp = fopen(path, "a");
+    if (!fp) return;
+    fprintf(fp, "%s %d %.4f\n", key.c_str(), idx, ms);
+    fclose(fp);
+}
+
+}  // namespace
+
+// Workspace of the batched call: a small region (fixed part, then the
+// per-right-hand-side arrays at 256-byte aligned offsets), then
+// max(int64 accumulators, solver scratch).
+struct BLayout {
+    size_t maxbits, off, status, small;  // byte offsets; status is followed by iters
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static BLayout batched_layout(int n_rhs, int n_snap, int n_steps) {
+    BLayout L;
+    L.maxbits = kSmallFixed;
+    L.off = align256(L.maxbits + 4 * (size_t)n_rhs);
+    L.status = align256(L.off + 8 * ((size_t)n_snap + 1));
+    L.small = align256(L.status + 4 * (size_t)n_rhs * (1 + n_steps)) + 4096;
+    return L;
+}
+
+// Pinned staging of the batched call (bytes after kPinBytes).
+struct BPin {
+    size_t off, status, counters, total;
+};
+
+static BPin batched_pin(int n_rhs, int n_snap, int n_steps) {
+    BPin P;
+    P.off = kPinBytes;
+    P.status = align256(P.off + 8 * ((size_t)n_snap + 1));
+    P.counters = align256(P.status + 4 * (size_t)n_rhs * (1 + n_steps));
+    P.total = P.counters + 256;
+    return P;
+}
+
+struct BatchedGraph {
+    std::string key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t ws_gen = 0;
+};
+
+}  // namespace cgd
+
+namespace cgd {
+
+static std::mutex g_graph_mu;
+static std::map<cgd_mesh, BatchedGraph> g_graphs;
+
+void destroy_batched(cgd_mesh m) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(m);
+    if (it == g_graphs.end()) return;
+    if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+    if (it->second.graph) (void)hipGraphDestroy(it->second.graph);
+    g_graphs.erase(it);
+}
+
+// Times every candidate on min(n_rhs, resident) synthetic right-hand sides
+// (one backward-Euler step, a fixed 12 iterations) and returns the fastest.
+cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, int* n_cand) {
+    const HexGeom& g = m->hex;
+    const int vec = batched_vec(g);
+    if (!vec) {
+        set_error("batched solver: nx must be 64, 128 or 256");
+        return CGD_E_UNSUPPORTED;
+    }
+    std::vector<Cfg> cs = candidates(vec);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        static bool loaded = false;
+        if (!loaded) {
+            load_tune_file();
+            loaded = true;
+        }
+        auto it = g_tune.find(tune_key(g, n_rhs));
+        if (it != g_tune.end() && it->second >= 0 && it->second < (int)cs.size() && !ms_out) {
+            *chosen = it->second;
+            if (n_cand) *n_cand = (int)cs.size();
+            return CGD_OK;
+        }
+    }
+    int gmax = 1;
+    for (const Cfg& c : cs) gmax = std::max(gmax, grid_for(c, n_rhs));
+    const int nr = std::min(n_rhs, gmax);
+    const size_t cells = (size_t)m->cells;
+    CGD_HIP_TRY(hipDeviceSynchronize());
+    const BLayout L = batched_layout(nr, 1, 1);
+    const size_t small = L.small;
+    cgd_status rc = ensure_workspace(m, small + (size_t)nr * cells * 4 + (size_t)gmax * 4 * cells * 4);
+    if (rc != CGD_OK) return rc;
+    char* base = static_cast<char*>(m->ws.ptr);
+    float* fields = reinterpret_cast<float*>(base + small);
+    float* scratch = fields + (size_t)nr * cells;
+    int32_t* status = reinterpret_cast<int32_t*>(base + L.status);
+    int32_t* iters = status + nr;
+    hipStream_t s = nullptr;
+    CGD_HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    hipEvent_t e0, e1;
+    CGD_HIP_TRY(hipEventCreate(&e0));
+    CGD_HIP_TRY(hipEventCreate(&e1));
+    BSolve a = {};
+    a.fields = fields;
+    a.ws = scratch;
+    a.n_rhs = nr;
+    a.cells = (int64_t)cells;
+    a.g.nx = g.nx;
+    a.g.ny = g.ny;
+    a.g.nz = g.nz;
+    a.g.cx = a.g.cy = a.g.cz = 1.0f;
+    a.n_steps = 1;
+    a.rtol2 = 0.0;  // run the full iteration budget
+    a.max_iter = 12;
+    a.iters = iters;
+    a.status = status;
+    double best = 1e30;
+    int best_i = 0;
+    for (size_t i = 0; i < cs.size(); ++i) {
+        const Cfg& c = cs[i];
+        a.xsegs = 1;
+        a.ygroups = (g.ny + c.ty - 1) / c.ty;
+        const int grid = grid_for(c, nr);
+        double ms_best = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+            hipLaunchKernelGGL(k_fill_synthetic, dim3(2048), dim3(256), 0, s, fields, (int64_t)(nr * cells));
+            CGD_HIP_TRY(hipEventRecord(e0, s));
+            rc = launch_solver(c, a, grid, s);
+            if (rc != CGD_OK) break;
+            CGD_HIP_TRY(hipEventRecord(e1, s));
+            CGD_HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            CGD_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) ms_best = std::min(ms_best, (double)ms);
+        }
+        if (rc != CGD_OK) break;
+        if (ms_out) ms_out[i] = ms_best;
+        if (ms_best < best) {
+            best = ms_best;
+            best_i = (int)i;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
+    if (rc != CGD_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const std::string key = tune_key(g, n_rhs);
+        g_tune[key] = best_i;
+        save_tune_file(key, best_i, best);
+    }
+    *chosen = best_i;
+    if (n_cand) *n_cand = (int)cs.size();
+    return CGD_OK;
+}
+
+cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offsets, const float* pos, int32_t F,
+                                const float* values, const DiffuseArgs& da, float* fields, int32_t* iters_out,
+                                hipStream_t s) {
+    const HexGeom& g = m->hex;
+    const int n_rhs = n_snap * F;
+    const int64_t total = offsets[n_snap];
+    const size_t cells = (size_t)m->cells;
+    int ci = 0;
+    cgd_status rc = autotune_batched(m, n_rhs, &ci, nullptr, nullptr);
+    if (rc != CGD_OK) return rc;
+    const Cfg c = candidates(batched_vec(g))[ci];
+    const int grid = grid_for(c, n_rhs);
+    const BLayout L = batched_layout(n_rhs, n_snap, da.n_steps);
+    const size_t small = L.small;
+    const size_t acc_bytes = (size_t)n_rhs * cells * 8;
+    const size_t solver_bytes = (size_t)grid * 4 * cells * 4;
+    rc = ensure_workspace(m, small + std::max(acc_bytes, solver_bytes));
+    if (rc != CGD_OK) return rc;
+    const BPin P = batched_pin(n_rhs, n_snap, da.n_steps);
+    rc = ensure_pinned(m, P.total);
+    if (rc != CGD_OK) return rc;
+
+    char* base = static_cast<char*>(m->ws.ptr);
+    char* pin = static_cast<char*>(m->pinned);
+    unsigned long long* d_counters = reinterpret_cast<unsigned long long*>(base + kOffSums);
+    uint32_t* d_maxbits = reinterpret_cast<uint32_t*>(base + L.maxbits);
+    int64_t* d_off = reinterpret_cast<int64_t*>(base + L.off);
+    int32_t* d_status = reinterpret_cast<int32_t*>(base + L.status);
+    int32_t* d_iters = d_status + n_rhs;
+    void* big = base + small;
+    int64_t* h_off = reinterpret_cast<int64_t*>(pin + P.off);
+    int32_t* h_status = reinterpret_cast<int32_t*>(pin + P.status);
+    int32_t* h_iters = h_status + n_rhs;
+    unsigned long long* h_counters = reinterpret_cast<unsigned long long*>(pin + P.counters);
+    memcpy(h_off, offsets, 8 * ((size_t)n_snap + 1));
+
+    BDep d = {};
+    d.off = d_off;
+    d.pos = pos;
+    d.values = values;
+    d.total = total;
+    d.n_snap = n_snap;
+    d.F = F;
+    d.maxbits = d_maxbits;
+    d.acc = static_cast<unsigned long long*>(big);
+    d.fields = fields;
+    d.counters = d_counters;
+    d.cells = (int64_t)cells;
+    d.vol = g.vol;
+    for (int a = 0; a < 3; ++a) {
+        d.g.lo[a] = g.lo[a];
+        d.g.hi[a] = g.hi[a];
+        d.g.s[a] = g.s[a];
+    }
+    d.g.n[0] = g.nx;
+    d.g.n[1] = g.ny;
+    d.g.n[2] = g.nz;
+    int64_t max_n = 0;
+    for (int j = 0; j < n_snap; ++j) max_n = std::max(max_n, offsets[j + 1] - offsets[j]);
+    const int chunks = (int)std::max<int64_t>(1, (max_n + kChunk - 1) / kChunk);
+
+    const double dtau = da.bandwidth * da.bandwidth / 4.0 / da.n_steps;
+    BSolve a = {};
+    a.fields = fields;
+    a.ws = static_cast<float*>(big);
+    a.n_rhs = n_rhs;
+    a.cells = (int64_t)cells;
+    a.g.nx = g.nx;
+    a.g.ny = g.ny;
+    a.g.nz = g.nz;
+    a.g.cx = (float)(dtau / (g.h[0] * g.h[0]));
+    a.g.cy = (float)(dtau / (g.h[1] * g.h[1]));
+    a.g.cz = (float)(dtau / (g.h[2] * g.h[2]));
+    a.xsegs = 1;
+    a.ygroups = (g.ny + c.ty - 1) / c.ty;
+    a.n_steps = da.n_steps;
+    a.rtol2 = da.rtol * da.rtol;
+    a.max_iter = da.max_iter;
+    a.iters = d_iters;
+    a.status = d_status;
+
+    // everything the call does, in stream order
+    auto enqueue_all = [&](hipStream_t q) -> cgd_status {
+        CGD_HIP_TRY(hipMemcpyAsync(d_off, h_off, 8 * ((size_t)n_snap + 1), hipMemcpyHostToDevice, q));
+        hipLaunchKernelGGL(k_bdep_init, dim3((n_rhs + 255) / 256), dim3(256), 0, q, d);
+        hipLaunchKernelGGL(k_bzero, dim3(8192), dim3(256), 0, q, d.acc, (int64_t)(n_rhs * cells));
+        if (total > 0) {
+            hipLaunchKernelGGL(k_babsmax, dim3(chunks, n_rhs), dim3(kDBlock), 0, q, d);
+            hipLaunchKernelGGL(k_bdeposit, dim3(chunks, n_snap), dim3(kDBlock), 0, q, d);
+        }
+        hipLaunchKernelGGL(k_bfinalize, dim3(512, n_rhs), dim3(kDBlock), 0, q, d);
+        cgd_status r = launch_solver(c, a, grid, q);
+        if (r != CGD_OK) return r;
+        CGD_HIP_TRY(hipMemcpyAsync(h_status, d_status, 4 * (size_t)n_rhs * (1 + da.n_steps), hipMemcpyDeviceToHost, q));
+        CGD_HIP_TRY(hipMemcpyAsync(h_counters, d_counters, 16, hipMemcpyDeviceToHost, q));
+        return CGD_OK;
+    };
+
+    const bool use_graph = getenv("CGD_NO_GRAPH") == nullptr;
+    if (use_graph) {
+        char keybuf[512];
+        snprintf(keybuf, sizeof keybuf, "%p %p %p %d %d %lld %d %d %.17g %.17g %d %d %p %zu %p", (const void*)pos,
+                 (const void*)values, (void*)fields, n_snap, F, (long long)total, chunks, da.n_steps, da.bandwidth,
+                 da.rtol, da.max_iter, ci, m->ws.ptr, m->ws.bytes, m->pinned);
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        BatchedGraph& bg = g_graphs[m];
+        if (bg.key != keybuf || !bg.exec) {
+            if (bg.exec) (void)hipGraphExecDestroy(bg.exec);
+            if (bg.graph) (void)hipGraphDestroy(bg.graph);
+            bg.exec = nullptr;
+            bg.graph = nullptr;
+            hipStream_t cap = nullptr;
+            CGD_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            CGD_HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+            cgd_status r = enqueue_all(cap);
+            hipGraph_t graph = nullptr;
+            hipError_t ee = hipStreamEndCapture(cap, &graph);
+            (void)hipStreamDestroy(cap);
+            if (r != CGD_OK) return r;
+            if (ee != hipSuccess) {
+                set_error(std::string("batched graph capture failed: ") + hipGetErrorString(ee));
+                return CGD_E_HIP;
+            }
+            bg.graph = graph;
+            CGD_HIP_TRY(hipGraphInstantiate(&bg.exec, graph, nullptr, nullptr, 0));
+            bg.key = keybuf;
+        }
+        CGD_HIP_TRY(hipGraphLaunch(bg.exec, s));
+    } else {
+        rc = enqueue_all(s);
+        if (rc != CGD_OK) return rc;
+    }
+    CGD_HIP_TRY(hipStreamSynchronize(s));
+    cgd_status worst = CGD_OK;
+    for (int r = 0; r < n_rhs; ++r) {
+        if (h_status[r] == CGD_E_BREAKDOWN) {
+            set_error("CG breakdown in right-hand side " + std::to_string(r));
+            worst = CGD_E_BREAKDOWN;
+        } else if (h_status[r] == CGD_NOT_CONVERGED && worst == CGD_OK) {
+            worst = CGD_NOT_CONVERGED;
+        }
+    }
+    if (iters_out) memcpy(iters_out, h_iters, 4 * (size_t)n_rhs * da.n_steps);
+    if (worst == CGD_OK && h_counters[1]) {
+        set_error("non-finite particle positions or values were skipped");
+        worst = CGD_E_NONFINITE;
+    }
+    return worst;
+}
+
+}  // namespace cgd

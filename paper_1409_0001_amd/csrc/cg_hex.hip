@@ -26,6 +26,7 @@
 #include <algorithm>
 
 #include "cg_common.h"
+#include "stencil_tile.h"
 
 namespace cgd {
 namespace {
@@ -33,83 +34,22 @@ namespace {
 constexpr int kWaves = kCgWaves;
 constexpr int kBlock = kCgBlock;
 
-enum Mode { S1_FIRST = 0, S1 = 1, S2_FIRST = 2, S2 = 3, S_RES = 4, S1_B0 = 5 };
+using namespace stencil;
 
 struct SweepArgs {
-    const float* B;     // right-hand side of the step (zero-guess first iteration: p = b)
-    float* R;           // residual
-    const float* Pold;  // previous direction (sweep 1)
-    float* Pnew;        // new direction (sweep 1 writes, sweep 2 reads)
-    float* X;           // iterate
+    Ptrs p;
+    Geom g;
     CgCtl c;
     double* P1;         // [F][2][bpf]: slot 0 p.Ap, slot 1 b.b
     double* P2;         // [F][2][bpf]: r.r of r_k in slot k % 2
     int64_t cells;
     int nx, ny, nz;
-    float cx, cy, cz;
     int xsegs, ygroups, zc;
     int wpf, bpf, nblocks;
     int k;              // iteration index within the step
 };
 
-template <int VEC>
-struct Vec {
-    float f[VEC];
-};
-
-template <int VEC>
-__device__ __forceinline__ Vec<VEC> ldv(const float* p) {
-    Vec<VEC> v;
-    if constexpr (VEC == 4) {
-        const float4 t = *reinterpret_cast<const float4*>(p);
-        v.f[0] = t.x; v.f[1] = t.y; v.f[2] = t.z; v.f[3] = t.w;
-    } else if constexpr (VEC == 2) {
-        const float2 t = *reinterpret_cast<const float2*>(p);
-        v.f[0] = t.x; v.f[1] = t.y;
-    } else {
-        v.f[0] = *p;
-    }
-    return v;
-}
-
-template <int VEC>
-__device__ __forceinline__ void stv(float* p, const Vec<VEC>& v) {
-    if constexpr (VEC == 4) {
-        *reinterpret_cast<float4*>(p) = make_float4(v.f[0], v.f[1], v.f[2], v.f[3]);
-    } else if constexpr (VEC == 2) {
-        *reinterpret_cast<float2*>(p) = make_float2(v.f[0], v.f[1]);
-    } else {
-        *p = v.f[0];
-    }
-}
-
-// The direction vector p at VEC consecutive cells starting at i (always an
-// in-bounds address; the caller clamps).
-template <int VEC, int MODE>
-__device__ __forceinline__ Vec<VEC> load_p(const SweepArgs& a, size_t i, float beta) {
-    if constexpr (MODE == S1_FIRST || MODE == S2_FIRST) {
-        return ldv<VEC>(a.B + i);
-    } else if constexpr (MODE == S1) {
-        Vec<VEC> r = ldv<VEC>(a.R + i);
-        const Vec<VEC> q = ldv<VEC>(a.Pold + i);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) r.f[e] = fmaf(beta, q.f[e], r.f[e]);
-        return r;
-    } else if constexpr (MODE == S1_B0) {
-        return ldv<VEC>(a.R + i);
-    } else if constexpr (MODE == S2) {
-        return ldv<VEC>(a.Pnew + i);
-    } else {
-        return ldv<VEC>(a.X + i);
-    }
-}
-
-// One sweep.  A wave owns 64*VEC consecutive x (VEC per lane) times TY rows
-// and marches over a z chunk.  Every load is issued unconditionally at a
-// clamped, in-bounds address; out-of-range values are replaced afterwards
-// (walls: the cell's own value, i.e. zero flux).  EDGE: the row is wider
-// than one wave (VEC = 1), so lanes 0 and 63 also load the cell beyond the
-// wave's ends; every other lane loads its own cell at that instruction.
+// One sweep over all fields: each wave takes one tile (stencil_tile.h).
 template <int VEC, int TY, int MODE, bool EDGE>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     int b = blockIdx.x;
@@ -167,138 +107,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
         const int t = w / a.xsegs;
         const int yg = t % a.ygroups;
         const int zci = t / a.ygroups;
-        const int nx = a.nx, ny = a.ny, nz = a.nz;
-        const int x0 = xs * 64 * VEC + lane * VEC;
-        const bool xin = x0 < nx;
-        const int xc = xin ? x0 : nx - VEC;
-        const bool wall_l = x0 == 0;
-        const bool wall_r = x0 + VEC >= nx;
-        const int y0 = yg * TY;
         const int zb = zci * a.zc;
-        const int ze = min(zb + a.zc, nz);
-        const size_t plane = (size_t)nx * ny;
-        const size_t base = (size_t)f * a.cells + xc;
-        const float cx = a.cx, cy = a.cy, cz = a.cz;
-        int eoff = 0;
-        if constexpr (EDGE) eoff = (lane == 0 && x0 > 0) ? -1 : ((lane == 63 && x0 + 1 < nx) ? 1 : 0);
-
-        auto at = [&](int z, int y) -> size_t {
-            z = z < 0 ? 0 : (z >= nz ? nz - 1 : z);
-            y = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
-            return base + (size_t)z * plane + (size_t)y * nx;
-        };
-
-        Vec<VEC> pm[TY], pc[TY + 2], pn[TY + 2];
-        float ec[TY], en[TY];
-#pragma unroll
-        for (int j = 0; j < TY; ++j) pm[j] = load_p<VEC, MODE>(a, at(zb - 1, y0 + j), beta);
-#pragma unroll
-        for (int j = 0; j < TY + 2; ++j) pc[j] = load_p<VEC, MODE>(a, at(zb, y0 - 1 + j), beta);
-        if constexpr (EDGE) {
-#pragma unroll
-            for (int j = 0; j < TY; ++j) ec[j] = load_p<1, MODE>(a, at(zb, y0 + j) + eoff, beta).f[0];
-        }
-        for (int z = zb; z < ze; ++z) {
-#pragma unroll
-            for (int j = 0; j < TY + 2; ++j) pn[j] = load_p<VEC, MODE>(a, at(z + 1, y0 - 1 + j), beta);
-            if constexpr (EDGE) {
-#pragma unroll
-                for (int j = 0; j < TY; ++j) en[j] = load_p<1, MODE>(a, at(z + 1, y0 + j) + eoff, beta).f[0];
-            }
-            const bool has_zd = z > 0, has_zu = z + 1 < nz;
-#pragma unroll
-            for (int j = 0; j < TY; ++j) {
-                const int y = y0 + j;
-                const bool valid = xin && y < ny;
-                const size_t i = at(z, y);
-                const Vec<VEC>& c = pc[j + 1];
-                const bool has_yd = y > 0, has_yu = y + 1 < ny;
-                float lft = __shfl_up(c.f[VEC - 1], 1);
-                float rgt = __shfl_down(c.f[0], 1);
-                if constexpr (EDGE) {
-                    lft = lane == 0 ? ec[j] : lft;
-                    rgt = lane == 63 ? ec[j] : rgt;
-                }
-                Vec<VEC> ap;
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) {
-                    const float ce = c.f[e];
-                    float l = e > 0 ? c.f[e - 1] : (wall_l ? ce : lft);
-                    float r = e + 1 < VEC ? c.f[e + 1] : (wall_r ? ce : rgt);
-                    const float yl = has_yd ? pc[j].f[e] : ce;
-                    const float yh = has_yu ? pc[j + 2].f[e] : ce;
-                    const float zl = has_zd ? pm[j].f[e] : ce;
-                    const float zh = has_zu ? pn[j + 1].f[e] : ce;
-                    const float c2 = ce + ce;
-                    float v = fmaf(cx, (c2 - l) - r, ce);
-                    v = fmaf(cy, (c2 - yl) - yh, v);
-                    ap.f[e] = fmaf(cz, (c2 - zl) - zh, v);
-                }
-                if constexpr (MODE == S1_FIRST) {
-                    if (valid) {
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e) {
-                            acc0 = fma((double)c.f[e], (double)ap.f[e], acc0);
-                            acc1 = fma((double)c.f[e], (double)c.f[e], acc1);
-                        }
-                    }
-                } else if constexpr (MODE == S1 || MODE == S1_B0) {
-                    if (valid) {
-                        stv<VEC>(a.Pnew + i, c);
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e) acc0 = fma((double)c.f[e], (double)ap.f[e], acc0);
-                    }
-                } else if constexpr (MODE == S2_FIRST) {
-                    Vec<VEC> xn, rn;
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) {
-                        xn.f[e] = alpha * c.f[e];
-                        rn.f[e] = fmaf(-alpha, ap.f[e], c.f[e]);
-                    }
-                    if (valid) {
-                        stv<VEC>(a.X + i, xn);
-                        stv<VEC>(a.R + i, rn);
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e) acc0 = fma((double)rn.f[e], (double)rn.f[e], acc0);
-                    }
-                } else if constexpr (MODE == S2) {
-                    Vec<VEC> xv = ldv<VEC>(a.X + i);
-                    Vec<VEC> rv = ldv<VEC>(a.R + i);
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) {
-                        xv.f[e] = fmaf(alpha, c.f[e], xv.f[e]);
-                        rv.f[e] = fmaf(-alpha, ap.f[e], rv.f[e]);
-                    }
-                    if (valid) {
-                        stv<VEC>(a.X + i, xv);
-                        stv<VEC>(a.R + i, rv);
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e) acc0 = fma((double)rv.f[e], (double)rv.f[e], acc0);
-                    }
-                } else {  // S_RES: r = b - A x0
-                    const Vec<VEC> bv = ldv<VEC>(a.B + i);
-                    Vec<VEC> rn;
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) rn.f[e] = bv.f[e] - ap.f[e];
-                    if (valid) {
-                        stv<VEC>(a.R + i, rn);
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e) {
-                            acc0 = fma((double)rn.f[e], (double)rn.f[e], acc0);
-                            acc1 = fma((double)bv.f[e], (double)bv.f[e], acc1);
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < TY; ++j) pm[j] = pc[j + 1];
-#pragma unroll
-            for (int j = 0; j < TY + 2; ++j) pc[j] = pn[j];
-            if constexpr (EDGE) {
-#pragma unroll
-                for (int j = 0; j < TY; ++j) ec[j] = en[j];
-            }
-        }
+        const int ze = min(zb + a.zc, a.nz);
+        tile_sweep<VEC, TY, MODE, EDGE>(a.p, a.g, (size_t)f * a.cells, xs, yg, zb, ze, lane, alpha, beta, acc0, acc1);
     }
 
     // block reduction of the float64 partials, fixed order
@@ -507,9 +318,12 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     a.nx = g.nx;
     a.ny = g.ny;
     a.nz = g.nz;
-    a.cx = (float)(dtau / (g.h[0] * g.h[0]));
-    a.cy = (float)(dtau / (g.h[1] * g.h[1]));
-    a.cz = (float)(dtau / (g.h[2] * g.h[2]));
+    a.g.nx = g.nx;
+    a.g.ny = g.ny;
+    a.g.nz = g.nz;
+    a.g.cx = (float)(dtau / (g.h[0] * g.h[0]));
+    a.g.cy = (float)(dtau / (g.h[1] * g.h[1]));
+    a.g.cz = (float)(dtau / (g.h[2] * g.h[2]));
     a.xsegs = p.xsegs;
     a.ygroups = p.ygroups;
     a.zc = p.zc;
@@ -519,7 +333,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     a.c = ctl;
     a.P1 = d_P1;
     a.P2 = d_P2;
-    a.R = R;
+    a.p.R = R;
 
     const int sum_bpf = (int)std::min<int64_t>(1024, (cells + kBlock - 1) / kBlock);
     double* d_sum_part = d_P2;  // free outside the solves
@@ -533,8 +347,8 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     float* nxt = W0;        // x of the current step
     for (int step = 0; step < da.n_steps; ++step) {
         a.c.step = step;
-        a.B = cur;
-        a.X = nxt;
+        a.p.B = cur;
+        a.p.X = nxt;
         hipLaunchKernelGGL(k_cg_step_init, dim3(1), dim3(64), 0, s, ctl.st, F, ctl.ndone,
                            ctl.status + step * CGD_MAX_FIELDS);
         const bool use_x0 = (da.x0_mode == 1) || (da.x0_mode == 2 && step == 0);
@@ -553,11 +367,11 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         auto enqueue = [&](int it) {
             int mode1 = S1;
             if (!use_x0) {
-                a.Pold = it == 1 ? cur : ((it & 1) ? PB : PA);
-                a.Pnew = (it & 1) ? PA : PB;
+                a.p.Pold = it == 1 ? cur : ((it & 1) ? PB : PA);
+                a.p.Pnew = (it & 1) ? PA : PB;
             } else {
-                a.Pold = (it & 1) ? PA : PB;
-                a.Pnew = (it & 1) ? PB : PA;
+                a.p.Pold = (it & 1) ? PA : PB;
+                a.p.Pnew = (it & 1) ? PB : PA;
                 if (it == 0) mode1 = S1_B0;
             }
             a.k = it;

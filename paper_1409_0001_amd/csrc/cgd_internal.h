@@ -145,6 +145,13 @@ __device__ inline int frac_bits_of(uint32_t maxbits, int e_n) {
 cgd_status locate_hex(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hipStream_t s);
 cgd_status locate_tet(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hipStream_t s);
 
+// batched.hip
+cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offsets, const float* pos, int32_t F,
+                                const float* values, const DiffuseArgs& da, float* fields, int32_t* iters_out,
+                                hipStream_t s);
+cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, int* n_cand);
+void destroy_batched(cgd_mesh m);
+
 // tet.cpp / tet.hip
 cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
                        float* field, int64_t* acc, DepositInfo* info_dev, hipStream_t s);

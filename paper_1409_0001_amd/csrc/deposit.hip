@@ -14,6 +14,7 @@
 #pragma clang fp contract(off)
 
 #include "cgd_internal.h"
+#include "hex_bin.h"
 
 namespace cgd {
 namespace {
@@ -76,34 +77,6 @@ __global__ void k_absmax(const float* __restrict__ values, int64_t n, DepositInf
         if (mm) atomicMax(&info->maxbits[f], mm);
         if (bb) atomicAdd(&info->nonfinite_val[f], bb);
     }
-}
-
-struct HexBin {
-    double lo[3], hi[3], s[3];
-    int32_t n[3];
-};
-
-// Host cell of one centroid; -1 if the point is not finite or outside the
-// closed box.  u = (x - lo) * s, i = floor(u), clamped to [0, N-1].
-__device__ inline int64_t hex_cell(const HexBin& g, float fx, float fy, float fz, bool* nonfinite) {
-    const float xs[3] = {fx, fy, fz};
-    int64_t idx[3];
-    *nonfinite = false;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double x = (double)xs[a];
-        if (!isfinite(x)) {
-            *nonfinite = true;
-            return -1;
-        }
-        if (!(x >= g.lo[a] && x <= g.hi[a])) return -1;
-        double u = (x - g.lo[a]) * g.s[a];
-        int64_t i = (int64_t)floor(u);
-        i = i < 0 ? 0 : i;
-        i = i > g.n[a] - 1 ? g.n[a] - 1 : i;
-        idx[a] = i;
-    }
-    return idx[0] + (int64_t)g.n[0] * (idx[1] + (int64_t)g.n[1] * idx[2]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_deposit_hex(

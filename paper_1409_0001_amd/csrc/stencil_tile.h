@@ -1,0 +1,235 @@
+// One wave's tile of a 7-point-stencil CG sweep on a uniform hex grid (used
+// by the per-launch sweeps of cg_hex.hip and the persistent batched solver).
+//
+// The operator is A = I + dtau K / V: (A p)_k = p_k + sum_a c_a (2 p_k -
+// p_k-1 - p_k+1), c_a = dtau / h_a^2, with a missing neighbour at a wall
+// replaced by p_k itself (zero flux through wall faces).
+//
+// A wave owns 64 * VEC consecutive x (VEC per lane) times TY rows of y and
+// marches over the planes [zb, ze), keeping planes z-1, z, z+1 (with one halo
+// row on each side) in registers; x-neighbours come from lane shuffles.
+// Every load is issued unconditionally at a clamped, in-bounds address and
+// out-of-range values are replaced afterwards, so the loads of a plane are
+// issued together.  EDGE: the row is wider than one wave (VEC = 1), so lanes
+// 0 and 63 also load the cell beyond the wave's ends (every other lane loads
+// its own cell at that instruction).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace cgd {
+namespace stencil {
+
+//   S1_FIRST  p = b;                 b.Ab and b.b
+//   S1        p = r + beta p_old;    writes p; p.Ap
+//   S1_B0     p = r;                 writes p; p.Ap
+//   S2_FIRST  x = alpha b, r = b - alpha A b;  r.r
+//   S2        x += alpha p, r -= alpha A p;   r.r
+//   S_RES     r = b - A x;           r.r and b.b
+enum Mode { S1_FIRST = 0, S1 = 1, S2_FIRST = 2, S2 = 3, S_RES = 4, S1_B0 = 5 };
+
+struct Ptrs {
+    const float* B;     // right-hand side of the step
+    float* R;           // residual
+    const float* Pold;  // previous direction
+    float* Pnew;        // new direction
+    float* X;           // iterate
+};
+
+struct Geom {
+    int nx, ny, nz;
+    float cx, cy, cz;
+};
+
+template <int VEC>
+struct Vec {
+    float f[VEC];
+};
+
+template <int VEC>
+__device__ __forceinline__ Vec<VEC> ldv(const float* q) {
+    Vec<VEC> v;
+    if constexpr (VEC == 4) {
+        const float4 t = *reinterpret_cast<const float4*>(q);
+        v.f[0] = t.x; v.f[1] = t.y; v.f[2] = t.z; v.f[3] = t.w;
+    } else if constexpr (VEC == 2) {
+        const float2 t = *reinterpret_cast<const float2*>(q);
+        v.f[0] = t.x; v.f[1] = t.y;
+    } else {
+        v.f[0] = *q;
+    }
+    return v;
+}
+
+template <int VEC>
+__device__ __forceinline__ void stv(float* q, const Vec<VEC>& v) {
+    if constexpr (VEC == 4) {
+        *reinterpret_cast<float4*>(q) = make_float4(v.f[0], v.f[1], v.f[2], v.f[3]);
+    } else if constexpr (VEC == 2) {
+        *reinterpret_cast<float2*>(q) = make_float2(v.f[0], v.f[1]);
+    } else {
+        *q = v.f[0];
+    }
+}
+
+// The direction vector at VEC consecutive cells starting at i (an in-bounds
+// address; the caller clamps).
+template <int VEC, int MODE>
+__device__ __forceinline__ Vec<VEC> load_p(const Ptrs& p, size_t i, float beta) {
+    if constexpr (MODE == S1_FIRST || MODE == S2_FIRST) {
+        return ldv<VEC>(p.B + i);
+    } else if constexpr (MODE == S1) {
+        Vec<VEC> r = ldv<VEC>(p.R + i);
+        const Vec<VEC> q = ldv<VEC>(p.Pold + i);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) r.f[e] = fmaf(beta, q.f[e], r.f[e]);
+        return r;
+    } else if constexpr (MODE == S1_B0) {
+        return ldv<VEC>(p.R + i);
+    } else if constexpr (MODE == S2) {
+        return ldv<VEC>(p.Pnew + i);
+    } else {
+        return ldv<VEC>(p.X + i);
+    }
+}
+
+// One wave: x segment xs, row group yg (rows yg*TY ...), planes [zb, ze) of
+// the field starting at element fo.  Adds this wave's dot products to acc0 /
+// acc1 (see Mode).
+template <int VEC, int TY, int MODE, bool EDGE>
+__device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t fo, int xs, int yg, int zb, int ze,
+                                           int lane, float alpha, float beta, double& acc0, double& acc1) {
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int x0 = xs * 64 * VEC + lane * VEC;
+    const bool xin = x0 < nx;
+    const int xc = xin ? x0 : nx - VEC;
+    const bool wall_l = x0 == 0;
+    const bool wall_r = x0 + VEC >= nx;
+    const int y0 = yg * TY;
+    const size_t plane = (size_t)nx * ny;
+    const size_t base = fo + xc;
+    const float cx = g.cx, cy = g.cy, cz = g.cz;
+    int eoff = 0;
+    if constexpr (EDGE) eoff = (lane == 0 && x0 > 0) ? -1 : ((lane == 63 && x0 + 1 < nx) ? 1 : 0);
+
+    auto at = [&](int z, int y) -> size_t {
+        z = z < 0 ? 0 : (z >= nz ? nz - 1 : z);
+        y = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+        return base + (size_t)z * plane + (size_t)y * nx;
+    };
+
+    Vec<VEC> pm[TY], pc[TY + 2], pn[TY + 2];
+    float ec[TY], en[TY];
+#pragma unroll
+    for (int j = 0; j < TY; ++j) pm[j] = load_p<VEC, MODE>(p, at(zb - 1, y0 + j), beta);
+#pragma unroll
+    for (int j = 0; j < TY + 2; ++j) pc[j] = load_p<VEC, MODE>(p, at(zb, y0 - 1 + j), beta);
+    if constexpr (EDGE) {
+#pragma unroll
+        for (int j = 0; j < TY; ++j) ec[j] = load_p<1, MODE>(p, at(zb, y0 + j) + eoff, beta).f[0];
+    }
+    for (int z = zb; z < ze; ++z) {
+#pragma unroll
+        for (int j = 0; j < TY + 2; ++j) pn[j] = load_p<VEC, MODE>(p, at(z + 1, y0 - 1 + j), beta);
+        if constexpr (EDGE) {
+#pragma unroll
+            for (int j = 0; j < TY; ++j) en[j] = load_p<1, MODE>(p, at(z + 1, y0 + j) + eoff, beta).f[0];
+        }
+        const bool has_zd = z > 0, has_zu = z + 1 < nz;
+#pragma unroll
+        for (int j = 0; j < TY; ++j) {
+            const int y = y0 + j;
+            const bool valid = xin && y < ny;
+            const size_t i = at(z, y);
+            const Vec<VEC>& c = pc[j + 1];
+            const bool has_yd = y > 0, has_yu = y + 1 < ny;
+            float lft = __shfl_up(c.f[VEC - 1], 1);
+            float rgt = __shfl_down(c.f[0], 1);
+            if constexpr (EDGE) {
+                lft = lane == 0 ? ec[j] : lft;
+                rgt = lane == 63 ? ec[j] : rgt;
+            }
+            Vec<VEC> ap;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const float ce = c.f[e];
+                float l = e > 0 ? c.f[e - 1] : (wall_l ? ce : lft);
+                float r = e + 1 < VEC ? c.f[e + 1] : (wall_r ? ce : rgt);
+                const float yl = has_yd ? pc[j].f[e] : ce;
+                const float yh = has_yu ? pc[j + 2].f[e] : ce;
+                const float zl = has_zd ? pm[j].f[e] : ce;
+                const float zh = has_zu ? pn[j + 1].f[e] : ce;
+                const float c2 = ce + ce;
+                float v = fmaf(cx, (c2 - l) - r, ce);
+                v = fmaf(cy, (c2 - yl) - yh, v);
+                ap.f[e] = fmaf(cz, (c2 - zl) - zh, v);
+            }
+            if constexpr (MODE == S1_FIRST) {
+                if (valid) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        acc0 = fma((double)c.f[e], (double)ap.f[e], acc0);
+                        acc1 = fma((double)c.f[e], (double)c.f[e], acc1);
+                    }
+                }
+            } else if constexpr (MODE == S1 || MODE == S1_B0) {
+                if (valid) {
+                    stv<VEC>(p.Pnew + i, c);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc0 = fma((double)c.f[e], (double)ap.f[e], acc0);
+                }
+            } else if constexpr (MODE == S2_FIRST) {
+                Vec<VEC> xn, rn;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    xn.f[e] = alpha * c.f[e];
+                    rn.f[e] = fmaf(-alpha, ap.f[e], c.f[e]);
+                }
+                if (valid) {
+                    stv<VEC>(p.X + i, xn);
+                    stv<VEC>(p.R + i, rn);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc0 = fma((double)rn.f[e], (double)rn.f[e], acc0);
+                }
+            } else if constexpr (MODE == S2) {
+                Vec<VEC> xv = ldv<VEC>(p.X + i);
+                Vec<VEC> rv = ldv<VEC>(p.R + i);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    xv.f[e] = fmaf(alpha, c.f[e], xv.f[e]);
+                    rv.f[e] = fmaf(-alpha, ap.f[e], rv.f[e]);
+                }
+                if (valid) {
+                    stv<VEC>(p.X + i, xv);
+                    stv<VEC>(p.R + i, rv);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc0 = fma((double)rv.f[e], (double)rv.f[e], acc0);
+                }
+            } else {  // S_RES: r = b - A x0
+                const Vec<VEC> bv = ldv<VEC>(p.B + i);
+                Vec<VEC> rn;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) rn.f[e] = bv.f[e] - ap.f[e];
+                if (valid) {
+                    stv<VEC>(p.R + i, rn);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        acc0 = fma((double)rn.f[e], (double)rn.f[e], acc0);
+                        acc1 = fma((double)bv.f[e], (double)bv.f[e], acc1);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < TY; ++j) pm[j] = pc[j + 1];
+#pragma unroll
+        for (int j = 0; j < TY + 2; ++j) pc[j] = pn[j];
+        if constexpr (EDGE) {
+#pragma unroll
+            for (int j = 0; j < TY; ++j) ec[j] = en[j];
+        }
+    }
+}
+
+}  // namespace stencil
+}  // namespace cgd

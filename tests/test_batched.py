@@ -1,0 +1,128 @@
+"""GPU checks of the batched path (many snapshots x fields in one persistent
+launch under a hipGraph) against the CPU oracle and the single-snapshot path.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cgd_oracle as O
+from paper_1409_0001_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-5
+
+
+def _t(a, torch):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _batch(shape, counts, seed):
+    box = inputs.HexBox((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), shape)
+    parts = [inputs.uniform_bed(box, n, 4, seed=seed + j) for j, n in enumerate(counts)]
+    pos = np.concatenate([p.pos for p in parts]) if parts else np.zeros((0, 3), np.float32)
+    vals = np.concatenate([p.values for p in parts], axis=1)
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    return box, parts, pos, vals, off
+
+
+@pytest.mark.parametrize("shape", [(64, 40, 24), (128, 32, 20)])
+def test_batched_matches_oracle_and_single_path(gpu_lib, shape):
+    import torch
+    cgd = gpu_lib
+    counts = [20_000, 0, 7_000, 33_000, 1]
+    box, parts, pos, vals, off = _batch(shape, counts, seed=71)
+    b, steps = 4.0 / shape[0], 4
+    print(f"case: batched {shape} snapshots {counts}", flush=True)
+    mesh = cgd.HexMesh(shape, box.lo, box.hi)
+    fields, iters = cgd.coarse_grain_batched(mesh, off, _t(pos, torch), _t(vals, torch), b, steps, rtol=1e-7,
+                                             return_iters=True)
+    out = fields.cpu().numpy()
+    for j, p in enumerate(parts):
+        dep = O.deposit_hex(p.pos, p.values, box.lo, box.hi, shape)
+        ref = O.diffuse_hex_dct(dep["field64"], box.lo, box.hi, shape, b, steps)
+        single, _ = cgd.coarse_grain(mesh, _t(p.pos, torch), _t(p.values, torch), b, steps, rtol=1e-7)
+        single = single.cpu().numpy()
+        for f in range(4):
+            if counts[j] == 0:
+                assert not out[j, f].any()
+                continue
+            assert rel_l2(out[j, f], ref[f]) <= REL_L2, (j, f, rel_l2(out[j, f], ref[f]))
+            assert rel_l2(out[j, f], single[f]) <= REL_L2
+    assert (iters[[0, 2, 3]] >= 1).all()
+
+
+def test_batched_conserves_each_snapshot(gpu_lib):
+    """Each snapshot's total (eq. conserve) survives the batched deposit and
+    diffusion; the single-snapshot deposit of the same particles is
+    bit-exact against the oracle."""
+    import torch
+    cgd = gpu_lib
+    shape = (64, 16, 8)
+    counts = [5_000, 12_000, 3]
+    box, parts, pos, vals, off = _batch(shape, counts, seed=81)
+    mesh = cgd.HexMesh(shape, box.lo, box.hi)
+    fields = cgd.coarse_grain_batched(mesh, off, _t(pos, torch), _t(vals, torch), 0.1, 2, rtol=1e-7)
+    out = fields.cpu().numpy().astype(np.float64)
+    V = O.hex_cell_volume(box.lo, box.hi, shape)
+    for j, p in enumerate(parts):
+        dep = cgd.deposit(mesh, _t(p.pos, torch), _t(p.values, torch)).cpu().numpy().astype(np.float64)
+        ref = O.deposit_hex(p.pos, p.values, box.lo, box.hi, shape)
+        assert np.array_equal(dep.astype(np.float32).view(np.uint32), ref["field32"].view(np.uint32))
+        for f in range(4):
+            m_in = ref["field64"][f].sum() * V
+            scale = np.abs(ref["field64"][f]).sum() * V
+            assert abs(out[j, f].sum() * V - m_in) <= 1e-5 * scale
+
+
+def test_graph_replays_equal_eager(gpu_lib):
+    """The captured graph, replayed several times with eager work and
+    synchronisations in between, gives the eager result bit for bit."""
+    import torch
+    cgd = gpu_lib
+    shape = (128, 24, 16)
+    counts = [9_000, 15_000, 4_000]
+    box, parts, pos, vals, off = _batch(shape, counts, seed=91)
+    mesh = cgd.HexMesh(shape, box.lo, box.hi)
+    dpos, dvals = _t(pos, torch), _t(vals, torch)
+    os.environ["CGD_NO_GRAPH"] = "1"
+    try:
+        eager = cgd.coarse_grain_batched(mesh, off, dpos, dvals, 0.04, 3, rtol=1e-7).clone()
+    finally:
+        del os.environ["CGD_NO_GRAPH"]
+    out = torch.empty_like(eager)
+    for rep in range(4):
+        out.fill_(float("nan"))
+        cgd.coarse_grain_batched(mesh, off, dpos, dvals, 0.04, 3, rtol=1e-7, fields=out)
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(out.view(torch.int32), eager.view(torch.int32)), rep
+        assert torch.isfinite(junk)
+
+
+def test_autotune_reports_candidates(gpu_lib):
+    cgd = gpu_lib
+    mesh = cgd.HexMesh((128, 64, 32))
+    chosen, ms = cgd.autotune_batched(mesh, 32)
+    assert len(ms) == 4 and all(t > 0 for t in ms)
+    assert chosen == int(np.argmin(ms))
+
+
+def test_batched_invalid(gpu_lib):
+    import torch
+    cgd = gpu_lib
+    mesh = cgd.HexMesh((96, 8, 8))  # width not supported by the batched solver
+    pos = torch.rand((10, 3), device="cuda")
+    vals = torch.rand((1, 10), device="cuda")
+    with pytest.raises(cgd.CgdError):
+        cgd.coarse_grain_batched(mesh, [0, 10], pos, vals, 0.1, 2)
+    mesh = cgd.HexMesh((64, 8, 8))
+    with pytest.raises(cgd.CgdError):
+        cgd.coarse_grain_batched(mesh, [0, 6, 4, 10], pos, vals, 0.1, 2)  # decreasing offsets
