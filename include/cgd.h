@@ -80,14 +80,20 @@ int32_t cgd_mesh_kind(cgd_mesh m);
 /* Tet meshes: number of stored non-zeros of the CSR matrix (0 for hex). */
 int64_t cgd_mesh_nnz(cgd_mesh m);
 
+/* Learned initial-guess network (cgd_unet_create below). */
+typedef struct cgd_unet_s* cgd_unet;
+
 typedef struct {
     double  rtol;         /* stop when ||r||_2 <= rtol ||b||_2 (per field, per step); <= 0: 1e-6 */
     int32_t max_iter;     /* per step; <= 0: 1000 */
     int32_t x0_mode;      /* 0: zero initial guess; 1: previous pseudo-step's solution;
-                             2: caller's guess x0 for the first step (zero after) */
+                             2: caller's guess x0 for the first step (zero after);
+                             3: the network `model`'s prediction from the previous
+                                pseudo-step's field, every step (hex meshes) */
     const float* x0;      /* device [F, cells] when x0_mode == 2, else NULL */
     int32_t check_every;  /* iterations enqueued between convergence read-backs; <= 0: 4 */
     int32_t reserved;
+    cgd_unet model;       /* x0_mode 3: a network created for this mesh's grid, else NULL */
 } cgd_solver_opts;
 
 typedef struct {
@@ -100,7 +106,8 @@ typedef struct {
     int64_t n_dropped;                                /* particles outside the mesh / non-finite */
     int64_t n_nonfinite;                              /* non-finite positions or values */
     int32_t status;
-    int32_t reserved;
+    int32_t n_fallback;                               /* x0_mode 3: (step, field) solves whose
+                                                         learned guess was rejected */
 } cgd_solve_stats;
 
 /* Centroid binning alone (the first half of cgd_deposit): the host cell of
@@ -205,6 +212,76 @@ cgd_status cgd_coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* o
  *  ms:     host double [8] or NULL: time of each candidate (forces a re-run)
  *  n_cand: host, written with the number of candidates (nullable) */
 cgd_status cgd_autotune_batched(cgd_mesh m, int32_t n_rhs, int32_t* chosen, double* ms, int32_t* n_cand);
+
+/* ------------------------------------------------------------------------
+ * Learned initial guess (an addition to the method, not in the paper).
+ *
+ * A three-level 3-D convolutional U-Net f that maps the field of one
+ * backward-Euler pseudo-step to an estimate of the next, f(e^n) ~ e^{n+1}
+ * (Section 3.2: every step solves the same system, so one network serves all
+ * steps).  With cgd_solver_opts.x0_mode = 3, cgd_diffuse seeds each step's
+ * CG solve with f(e^n); the solve and its stopping rule are unchanged, so
+ * the result is the same discrete solution, only reached in fewer
+ * iterations when the guess is good.  A guess whose residual is not finite
+ * or exceeds ||b|| is rejected and the step starts from zero (counted in
+ * cgd_solve_stats.n_fallback; the call then returns CGD_WARMSTART_FALLBACK
+ * unless something worse happened).
+ *
+ * Architecture (base width 16, zero padding, ReLU after each 3x3x3 conv):
+ * two convs per level at 16 / 32 / 64 channels, 2x2x2 average pooling down,
+ * nearest 2x upsampling + conv up, skip connections by channel
+ * concatenation, a 1x1x1 head, and a residual output
+ *   y = x + s * head(U(x / s)),  s = sqrt(mean(x^2)).
+ * Activations and weights in bfloat16 on the matrix cores with float32
+ * accumulation; master weights, gradients, Adam state and loss in float32 /
+ * float64.  Every reduction runs in a fixed order (deterministic training).
+ *
+ * Parameters, flat float32, in this order: for each conv layer (e1a, e1b,
+ * e2a, e2b, e3a, e3b, u2, d2a, d2b, u1, d1a, d1b) its weights [co][27][ci]
+ * (tap = (dz+1)*9 + (dy+1)*3 + (dx+1), a cross-correlation) then its biases
+ * [co]; then the head's 16 weights and its bias.
+ * The network lives on the device current at creation and owns its
+ * activations; a network must not be used by two calls at the same time.
+ * ---------------------------------------------------------------------- */
+
+/* nx, ny, nz: the hex grid the network works on, each a multiple of 4.
+ * Weights He-normal from `seed` (splitmix64 + Box-Muller), biases zero and
+ * head zero, so the untrained network returns its input. */
+cgd_status cgd_unet_create(int32_t nx, int32_t ny, int32_t nz, uint64_t seed, cgd_unet* out);
+void       cgd_unet_destroy(cgd_unet u);
+int64_t    cgd_unet_num_params(cgd_unet u);
+/* Host float32 [n] copies of the parameters (set resets the Adam state) and
+ * of the gradient of the last cgd_unet_loss_grad / cgd_unet_train_step.
+ * These wait for the device. */
+cgd_status cgd_unet_get_params(cgd_unet u, float* host, int64_t n);
+cgd_status cgd_unet_set_params(cgd_unet u, const float* host, int64_t n);
+cgd_status cgd_unet_get_grads(cgd_unet u, float* host, int64_t n);
+/* y = f(x); x, y: device float32 [nz][ny][nx] (one field).  Asynchronous. */
+cgd_status cgd_unet_forward(cgd_unet u, const float* x, float* y, void* stream);
+/* Loss mean((f(x) - target)^2) / s^2 and its gradient with respect to the
+ * parameters (kept on the device; cgd_unet_get_grads copies it out).
+ * loss: host, nullable; non-NULL makes the call wait for the stream. */
+cgd_status cgd_unet_loss_grad(cgd_unet u, const float* x, const float* target, double* loss, void* stream);
+/* cgd_unet_loss_grad followed by one Adam step (beta1 0.9, beta2 0.999,
+ * eps 1e-8, learning rate lr > 0) on the float32 master weights. */
+cgd_status cgd_unet_train_step(cgd_unet u, const float* x, const float* target, double lr, double* loss,
+                               void* stream);
+
+/* Single 3x3x3 convolutions with zero padding on caller buffers, the kernels
+ * the network runs (bfloat16 tensors passed as uint16_t bit patterns,
+ * channels last: x [nz][ny][nx][ci]; weights [co][27][ci]):
+ *   forward: y = conv(x, w) + bias (bias nullable), ReLU when relu != 0;
+ *            ci in {1, 16, 32, 64}, co in {16, 32, 64}
+ *   dgrad:   dx = gradient of sum(g * conv(x, w)) with respect to x;
+ *            ci, co in {16, 32, 64}
+ *   wgrad:   dw [co][27][ci] and db [co] (float32) of sum(g * (conv(x, w) + b))
+ * These allocate scratch memory and wait for the stream. */
+cgd_status cgd_conv3_forward(int32_t nx, int32_t ny, int32_t nz, int32_t ci, int32_t co, const uint16_t* x,
+                             const uint16_t* w, const float* bias, int32_t relu, uint16_t* y, void* stream);
+cgd_status cgd_conv3_dgrad(int32_t nx, int32_t ny, int32_t nz, int32_t ci, int32_t co, const uint16_t* g,
+                           const uint16_t* w, uint16_t* dx, void* stream);
+cgd_status cgd_conv3_wgrad(int32_t nx, int32_t ny, int32_t nz, int32_t ci, int32_t co, const uint16_t* x,
+                           const uint16_t* g, float* dw, float* db, void* stream);
 
 /* Kernel timing, for roofline measurement.  While enabled, each launch of the
  * timed kernels is bracketed by two HIP events recorded on the caller's

@@ -98,20 +98,30 @@ def unet_layers(c=16):
             ("d1a", 2 * c, c), ("d1b", c, c)]
 
 
-def unet_forward(x, params, c=16):
+def _same(a):
+    return a
+
+
+def unet_forward(x, params, c=16, x_res=None, rnd=_same):
     """x [D,H,W,1] -> y [D,H,W,1] = x + head(U(x)).  params: name -> (w, b),
-    with w [Co,27,Ci] for the 3x3x3 layers and w [1,Ci] for 'head'."""
+    with w [Co,27,Ci] for the 3x3x3 layers and w [1,Ci] for 'head'.
+    x_res, when given, replaces x as the residual term (y = x_res + head(U(x))).
+    rnd: applied to every stored intermediate tensor (layer outputs and
+    pooled tensors); the identity by default, a rounding function to model
+    an implementation that stores them at reduced precision."""
     P = params
-    L = lambda name, t: relu(conv3_fwd(t, *P[name]))
+    L = lambda name, t: rnd(relu(conv3_fwd(t, *P[name])))
+    pool = lambda t: rnd(avgpool2(t))
     e1 = L("e1b", L("e1a", x))
-    e2 = L("e2b", L("e2a", avgpool2(e1)))
-    e3 = L("e3b", L("e3a", avgpool2(e2)))
+    e2 = L("e2b", L("e2a", pool(e1)))
+    e3 = L("e3b", L("e3a", pool(e2)))
     u2 = L("u2", up2(e3))
     d2 = L("d2b", L("d2a", np.concatenate([u2, e2], axis=3)))
     u1 = L("u1", up2(d2))
     d1 = L("d1b", L("d1a", np.concatenate([u1, e1], axis=3)))
     hw, hb = P["head"]
-    return x + (d1 @ np.asarray(hw, dtype=np.float64).T + hb)
+    base = x if x_res is None else np.asarray(x_res, dtype=np.float64)
+    return base + (d1 @ np.asarray(hw, dtype=np.float64).T + hb)
 
 
 def head_fwd(d1, hw, hb):
@@ -120,37 +130,39 @@ def head_fwd(d1, hw, hb):
     return d1 @ hw.T + np.asarray(hb, dtype=np.float64).reshape(1)
 
 
-def unet_loss_and_grads(x, target, params, c=16):
+def unet_loss_and_grads(x, target, params, c=16, x_res=None, rnd=_same):
     """Mean-squared error of the residual U-Net against `target` and its
     gradients with respect to every parameter, by reverse-mode chain rule
     through the layers of unet_forward (written out one layer at a time).
 
-    x, target: [D,H,W,1].  Returns (loss, grads) with grads[name] = (dw, db)
-    in the shapes of params[name]."""
+    x, target: [D,H,W,1]; x_res and rnd as in unet_forward (rnd also applies
+    to every stored gradient tensor: each layer's gradient at its output
+    before the convolution, and each input gradient).  Returns (loss, grads)
+    with grads[name] = (dw, db) in the shapes of params[name]."""
     P = params
     x = np.asarray(x, dtype=np.float64)
-    conv = lambda name, t: conv3_fwd(t, *P[name])
+    conv = lambda name, t: rnd(relu(conv3_fwd(t, *P[name])))
     # forward, keeping every activation
-    a1 = relu(conv("e1a", x))
-    e1 = relu(conv("e1b", a1))
-    p1 = avgpool2(e1)
-    a2 = relu(conv("e2a", p1))
-    e2 = relu(conv("e2b", a2))
-    p2 = avgpool2(e2)
-    a3 = relu(conv("e3a", p2))
-    e3 = relu(conv("e3b", a3))
+    a1 = conv("e1a", x)
+    e1 = conv("e1b", a1)
+    p1 = rnd(avgpool2(e1))
+    a2 = conv("e2a", p1)
+    e2 = conv("e2b", a2)
+    p2 = rnd(avgpool2(e2))
+    a3 = conv("e3a", p2)
+    e3 = conv("e3b", a3)
     q3 = up2(e3)
-    u2 = relu(conv("u2", q3))
+    u2 = conv("u2", q3)
     c2 = np.concatenate([u2, e2], axis=3)
-    a4 = relu(conv("d2a", c2))
-    d2 = relu(conv("d2b", a4))
+    a4 = conv("d2a", c2)
+    d2 = conv("d2b", a4)
     q2 = up2(d2)
-    u1 = relu(conv("u1", q2))
+    u1 = conv("u1", q2)
     c1 = np.concatenate([u1, e1], axis=3)
-    a5 = relu(conv("d1a", c1))
-    d1 = relu(conv("d1b", a5))
+    a5 = conv("d1a", c1)
+    d1 = conv("d1b", a5)
     hw, hb = P["head"]
-    y = x + head_fwd(d1, hw, hb)
+    y = (x if x_res is None else np.asarray(x_res, dtype=np.float64)) + head_fwd(d1, hw, hb)
     diff = y - np.asarray(target, dtype=np.float64)
     n = diff.size
     loss = float((diff ** 2).sum() / n)
@@ -164,10 +176,10 @@ def unet_loss_and_grads(x, target, params, c=16):
     def back(name, t_in, t_out, g_out):
         """Through relu(conv(name, t_in)) = t_out: records the parameter
         gradients and returns dL/d t_in."""
-        g_pre = g_out * (t_out > 0)
+        g_pre = rnd(g_out * (t_out > 0))
         dw, db = conv3_wgrad(t_in, g_pre)
         G[name] = (dw, db)
-        return conv3_dgrad(g_pre, P[name][0])
+        return rnd(conv3_dgrad(g_pre, P[name][0]))
 
     g = back("d1b", a5, d1, g)
     g = back("d1a", c1, a5, g)

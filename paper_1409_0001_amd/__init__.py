@@ -40,10 +40,11 @@ class Stats:
     frac_bits: list       # [F]
     n_dropped: int
     n_nonfinite: int
+    n_fallback: int = 0   # x0_mode 3: solves whose learned guess was rejected
 
 
 def _stats(st: _abi.SolveStats, F: int, n_steps: int, status: int) -> Stats:
-    return Stats(status=status,
+    return Stats(status=status, n_fallback=int(st.n_fallback),
                  iters=[[st.iters[s][f] for f in range(F)] for s in range(n_steps)],
                  rel_res=[[st.rel_res[s][f] for f in range(F)] for s in range(n_steps)],
                  mass_before=[st.mass_before[f] for f in range(F)],
@@ -142,13 +143,14 @@ class TetMesh(Mesh):
         self.nnz = int(lib.cgd_mesh_nnz(h))
 
 
-def _opts(rtol, max_iter, x0_mode, x0, check_every):
+def _opts(rtol, max_iter, x0_mode, x0, check_every, model=None):
     o = _abi.SolverOpts()
     o.rtol = float(rtol)
     o.max_iter = int(max_iter)
     o.x0_mode = int(x0_mode)
     o.x0 = x0.data_ptr() if x0 is not None else None
     o.check_every = int(check_every)
+    o.model = model.handle if model is not None else None
     return o
 
 
@@ -189,16 +191,17 @@ def deposit(mesh: Mesh, pos, values, field=None, acc=None, stats=False, stream=N
 
 
 def diffuse(mesh: Mesh, field, bandwidth, n_steps, rtol=1e-6, max_iter=1000, x0_mode=0, x0=None,
-            check_every=4, stats=False, stream=None):
+            check_every=4, stats=False, stream=None, model=None):
     """Diffuses field [F, cells] in place for T = bandwidth^2 / 4 in n_steps
-    backward-Euler steps.  Returns (field, Stats or None)."""
+    backward-Euler steps.  x0_mode 3 seeds every step with model(e^n) (a
+    UNet made for this mesh's grid).  Returns (field, Stats or None)."""
     torch = _torch()
     lib = _abi.load()
     F = int(field.shape[0])
     p_field = _dev(field, torch.float32, (F, mesh.cells), "field")
     if x0 is not None:
         _dev(x0, torch.float32, (F, mesh.cells), "x0")
-    o = _opts(rtol, max_iter, x0_mode, x0, check_every)
+    o = _opts(rtol, max_iter, x0_mode, x0, check_every, model)
     st = _abi.SolveStats() if stats else None
     rc = lib.cgd_diffuse(mesh.handle, F, p_field, float(bandwidth), int(n_steps), ctypes.byref(o),
                          ctypes.byref(st) if st is not None else None, _stream_ptr(stream))
@@ -207,7 +210,7 @@ def diffuse(mesh: Mesh, field, bandwidth, n_steps, rtol=1e-6, max_iter=1000, x0_
 
 
 def coarse_grain(mesh: Mesh, pos, values, bandwidth, n_steps, rtol=1e-6, max_iter=1000, x0_mode=0,
-                 check_every=4, field=None, stats=False, stream=None):
+                 check_every=4, field=None, stats=False, stream=None, model=None):
     """The whole method (Section 2.6): PCM deposition, then diffusion.
     Returns (field [F, cells], Stats or None)."""
     torch = _torch()
@@ -219,7 +222,7 @@ def coarse_grain(mesh: Mesh, pos, values, bandwidth, n_steps, rtol=1e-6, max_ite
     if field is None:
         field = torch.empty((F, mesh.cells), dtype=torch.float32, device=pos.device)
     p_field = _dev(field, torch.float32, (F, mesh.cells), "field")
-    o = _opts(rtol, max_iter, x0_mode, None, check_every)
+    o = _opts(rtol, max_iter, x0_mode, None, check_every, model)
     st = _abi.SolveStats() if stats else None
     rc = lib.cgd_coarse_grain(mesh.handle, n, p_pos, F, p_val, float(bandwidth), int(n_steps),
                               ctypes.byref(o), p_field, ctypes.byref(st) if st is not None else None,
@@ -280,3 +283,132 @@ def timing_read(mesh: Mesh, reset: bool = False) -> dict:
            "cgd_timing_read", allow=(0,))
     return {name: (int(t.launches[k]), float(t.total_ms[k]), float(t.bytes_per_launch[k]))
             for k, name in TIMING_KINDS.items()}
+
+
+class UNet:
+    """Learned initial guess f(e^n) ~ e^{n+1} for an (nx, ny, nz) hex grid
+    (include/cgd.h documents the network).  Parameters and gradients are flat
+    float32 numpy arrays in the library's order."""
+
+    def __init__(self, shape, seed=0):
+        _torch()
+        h = _abi.c_unet()
+        _check(_abi.load().cgd_unet_create(int(shape[0]), int(shape[1]), int(shape[2]), int(seed),
+                                           ctypes.byref(h)), "cgd_unet_create", allow=(0,))
+        self._h = h
+        self.shape = tuple(int(v) for v in shape)
+        self.cells = self.shape[0] * self.shape[1] * self.shape[2]
+        self.n_params = int(_abi.load().cgd_unet_num_params(h))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _abi.load().cgd_unet_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import numpy as np
+        v = np.empty(self.n_params, dtype=np.float32)
+        _check(_abi.load().cgd_unet_get_params(self._h, v.ctypes.data, v.size), "cgd_unet_get_params", allow=(0,))
+        return v
+
+    def set_params(self, v):
+        import numpy as np
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        if v.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {v.size}")
+        _check(_abi.load().cgd_unet_set_params(self._h, v.ctypes.data, v.size), "cgd_unet_set_params", allow=(0,))
+
+    def get_grads(self):
+        import numpy as np
+        v = np.empty(self.n_params, dtype=np.float32)
+        _check(_abi.load().cgd_unet_get_grads(self._h, v.ctypes.data, v.size), "cgd_unet_get_grads", allow=(0,))
+        return v
+
+    def forward(self, x, y=None, stream=None):
+        """y = f(x) for one field x: float32 [cells] on the GPU."""
+        torch = _torch()
+        px = _dev(x, torch.float32, (self.cells,), "x")
+        if y is None:
+            y = torch.empty_like(x)
+        py = _dev(y, torch.float32, (self.cells,), "y")
+        _check(_abi.load().cgd_unet_forward(self._h, px, py, _stream_ptr(stream)), "cgd_unet_forward", allow=(0,))
+        return y
+
+    def loss_grad(self, x, target, stream=None):
+        """Loss (float) and, on the device, its gradient (get_grads copies it)."""
+        torch = _torch()
+        px = _dev(x, torch.float32, (self.cells,), "x")
+        pt = _dev(target, torch.float32, (self.cells,), "target")
+        loss = ctypes.c_double()
+        _check(_abi.load().cgd_unet_loss_grad(self._h, px, pt, ctypes.byref(loss), _stream_ptr(stream)),
+               "cgd_unet_loss_grad", allow=(0,))
+        return loss.value
+
+    def train_step(self, x, target, lr, sync=True, stream=None):
+        """One Adam step on (x, target); returns the loss before the step when sync."""
+        torch = _torch()
+        px = _dev(x, torch.float32, (self.cells,), "x")
+        pt = _dev(target, torch.float32, (self.cells,), "target")
+        loss = ctypes.c_double()
+        _check(_abi.load().cgd_unet_train_step(self._h, px, pt, float(lr), ctypes.byref(loss) if sync else None,
+                                               _stream_ptr(stream)), "cgd_unet_train_step", allow=(0,))
+        return loss.value if sync else None
+
+
+def _bf16(t, shape, name):
+    torch = _torch()
+    return _dev(t, torch.bfloat16, shape, name)
+
+
+def conv3_forward(x, w, bias=None, relu=False, stream=None):
+    """3x3x3 zero-padded convolution: x bf16 [nz, ny, nx, ci], w bf16 [co, 27, ci],
+    bias float32 [co] or None -> y bf16 [nz, ny, nx, co]."""
+    torch = _torch()
+    nz, ny, nx, ci = (int(v) for v in x.shape)
+    co = int(w.shape[0])
+    px = _bf16(x, (nz, ny, nx, ci), "x")
+    pw = _bf16(w, (co, 27, ci), "w")
+    pb = _dev(bias, torch.float32, (co,), "bias") if bias is not None else None
+    y = torch.empty((nz, ny, nx, co), dtype=torch.bfloat16, device=x.device)
+    _check(_abi.load().cgd_conv3_forward(nx, ny, nz, ci, co, px, pw, pb, int(bool(relu)),
+                                         ctypes.c_void_p(y.data_ptr()), _stream_ptr(stream)),
+           "cgd_conv3_forward", allow=(0,))
+    return y
+
+
+def conv3_dgrad(g, w, stream=None):
+    """Input gradient of conv3_forward: g bf16 [nz, ny, nx, co], w [co, 27, ci] -> bf16 [.., ci]."""
+    torch = _torch()
+    nz, ny, nx, co = (int(v) for v in g.shape)
+    ci = int(w.shape[2])
+    pg = _bf16(g, (nz, ny, nx, co), "g")
+    pw = _bf16(w, (co, 27, ci), "w")
+    dx = torch.empty((nz, ny, nx, ci), dtype=torch.bfloat16, device=g.device)
+    _check(_abi.load().cgd_conv3_dgrad(nx, ny, nz, ci, co, pg, pw, ctypes.c_void_p(dx.data_ptr()),
+                                       _stream_ptr(stream)), "cgd_conv3_dgrad", allow=(0,))
+    return dx
+
+
+def conv3_wgrad(x, g, stream=None):
+    """Weight and bias gradients of conv3_forward: float32 dw [co, 27, ci], db [co]."""
+    torch = _torch()
+    nz, ny, nx, ci = (int(v) for v in x.shape)
+    co = int(g.shape[3])
+    px = _bf16(x, (nz, ny, nx, ci), "x")
+    pg = _bf16(g, (nz, ny, nx, co), "g")
+    dw = torch.empty((co, 27, ci), dtype=torch.float32, device=x.device)
+    db = torch.empty((co,), dtype=torch.float32, device=x.device)
+    _check(_abi.load().cgd_conv3_wgrad(nx, ny, nz, ci, co, px, pg, ctypes.c_void_p(dw.data_ptr()),
+                                       ctypes.c_void_p(db.data_ptr()), _stream_ptr(stream)),
+           "cgd_conv3_wgrad", allow=(0,))
+    return dw, db

@@ -20,12 +20,14 @@ E_BREAKDOWN = -5
 E_UNSUPPORTED = -6
 
 c_mesh = ctypes.c_void_p
+c_unet = ctypes.c_void_p
 
 
 class SolverOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("x0_mode", ctypes.c_int32), ("x0", ctypes.c_void_p),
-                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("model", ctypes.c_void_p)]
 
 
 class SolveStats(ctypes.Structure):
@@ -36,7 +38,7 @@ class SolveStats(ctypes.Structure):
                 ("mass_after", ctypes.c_double * MAX_FIELDS),
                 ("frac_bits", ctypes.c_int32 * MAX_FIELDS),
                 ("n_dropped", ctypes.c_int64), ("n_nonfinite", ctypes.c_int64),
-                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("n_fallback", ctypes.c_int32)]
 
 
 TIMING_KINDS = 8
@@ -78,6 +80,27 @@ SIGNATURES = {
                                                   ctypes.c_void_p, ctypes.c_void_p]),
     "cgd_autotune_batched": (ctypes.c_int32, [c_mesh, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                               ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "cgd_unet_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                         ctypes.POINTER(c_unet)]),
+    "cgd_unet_destroy": (None, [c_unet]),
+    "cgd_unet_num_params": (ctypes.c_int64, [c_unet]),
+    "cgd_unet_get_params": (ctypes.c_int32, [c_unet, ctypes.c_void_p, ctypes.c_int64]),
+    "cgd_unet_set_params": (ctypes.c_int32, [c_unet, ctypes.c_void_p, ctypes.c_int64]),
+    "cgd_unet_get_grads": (ctypes.c_int32, [c_unet, ctypes.c_void_p, ctypes.c_int64]),
+    "cgd_unet_forward": (ctypes.c_int32, [c_unet, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cgd_unet_loss_grad": (ctypes.c_int32, [c_unet, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "cgd_unet_train_step": (ctypes.c_int32, [c_unet, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                             ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "cgd_conv3_forward": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "cgd_conv3_dgrad": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+    "cgd_conv3_wgrad": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
     "cgd_timing_enable": (ctypes.c_int32, [c_mesh, ctypes.c_int32]),
     "cgd_timing_read": (ctypes.c_int32, [c_mesh, ctypes.POINTER(KernelTiming), ctypes.c_int32]),
     "cgd_status_string": (ctypes.c_char_p, [ctypes.c_int32]),

@@ -376,14 +376,21 @@ static cgd_status fill_opts(const cgd_solver_opts* o, int32_t F, float* field, d
     a->x0_mode = o ? o->x0_mode : 0;
     a->x0 = o ? o->x0 : nullptr;
     a->check_every = (o && o->check_every > 0) ? o->check_every : 4;
-    if (a->x0_mode < 0 || a->x0_mode > 2 || (a->x0_mode == 2 && !a->x0) || !isfinite(a->rtol)) {
-        set_error(std::string(who) + ": bad solver options (x0_mode 0..2, x0 needed for mode 2)");
+    a->model = o ? o->model : nullptr;
+    if (a->x0_mode < 0 || a->x0_mode > 3 || (a->x0_mode == 2 && !a->x0) || (a->x0_mode == 3 && !a->model) ||
+        !isfinite(a->rtol)) {
+        set_error(std::string(who) + ": bad solver options (x0_mode 0..3, x0 needed for mode 2, model for mode 3)");
         return CGD_E_INVALID;
     }
     return CGD_OK;
 }
 
 static cgd_status do_diffuse(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hipStream_t s) {
+    if (a.x0_mode == 3 &&
+        (m->kind != 0 || !unet::unet_matches(a.model, m->hex.nx, m->hex.ny, m->hex.nz, m->device))) {
+        set_error("x0_mode 3: the network must be created for this hex mesh's grid, on its device");
+        return CGD_E_INVALID;
+    }
     if (m->kind == 0) return diffuse_hex(m, a, st, s);
     return diffuse_tet(m, a, st, s);
 }

@@ -20,6 +20,7 @@ constexpr size_t kOffIters = 8192;                // int32 [STEPS][FIELDS]
 constexpr size_t kOffRelres = kOffIters + 4096;   // double [STEPS][FIELDS]
 constexpr size_t kOffStatus = kOffRelres + 8192;  // int32 [STEPS][FIELDS]
 constexpr size_t kOffSums = kOffStatus + 4096;    // double [2][FIELDS]
+constexpr size_t kOffFallback = kOffSums + 4096;  // int32 [STEPS][FIELDS]: learned guess rejected
 constexpr size_t kOffDeposit = 48 * 1024;         // DepositInfo
 constexpr size_t kSmallFixed = 64 * 1024;         // partial sums follow
 
@@ -30,7 +31,8 @@ constexpr size_t kPinRelres = kPinIters + 4096;
 constexpr size_t kPinStatus = kPinRelres + 8192;
 constexpr size_t kPinSums = kPinStatus + 4096;
 constexpr size_t kPinDeposit = kPinSums + 4096;
-constexpr size_t kPinBytes = kPinDeposit + 4096;
+constexpr size_t kPinFallback = kPinDeposit + 4096;
+constexpr size_t kPinBytes = kPinFallback + 4096;
 
 // Convergence bookkeeping written by the first block of a sweep.
 struct CgCtl {
@@ -109,8 +111,10 @@ cgd_status cg_lookahead_loop(cgd_mesh m, int F, int it0, int max_iter, int chunk
 
 // Host: after the steps, copies statuses / iterations / residuals back,
 // fills `out`, drops timing pairs of launches that found nothing to do, and
-// returns the worst status.
+// returns the worst status.  warm: the steps were seeded by the learned
+// guess, whose rejections (kOffFallback) are counted and reported as
+// CGD_WARMSTART_FALLBACK when nothing worse happened.
 cgd_status cg_finish_call(cgd_mesh m, int F, int n_steps, double vol_scale, hipStream_t s,
-                          cgd_solve_stats* out);
+                          cgd_solve_stats* out, bool warm = false);
 
 }  // namespace cgd

@@ -59,7 +59,7 @@ cgd_status cg_lookahead_loop(cgd_mesh m, int F, int it0, int max_iter, int chunk
 }
 
 cgd_status cg_finish_call(cgd_mesh m, int F, int n_steps, double vol_scale, hipStream_t s,
-                          cgd_solve_stats* out) {
+                          cgd_solve_stats* out, bool warm) {
     char* base = static_cast<char*>(m->ws.ptr);
     char* pin = static_cast<char*>(m->pinned);
     int32_t* h_iters = reinterpret_cast<int32_t*>(pin + kPinIters);
@@ -69,6 +69,8 @@ cgd_status cg_finish_call(cgd_mesh m, int F, int n_steps, double vol_scale, hipS
     CGD_HIP_TRY(hipGetLastError());
     CGD_HIP_TRY(hipMemcpyAsync(h_status, base + kOffStatus, 4096, hipMemcpyDeviceToHost, s));
     CGD_HIP_TRY(hipMemcpyAsync(h_iters, base + kOffIters, 4096, hipMemcpyDeviceToHost, s));
+    int32_t* h_fb = reinterpret_cast<int32_t*>(pin + kPinFallback);
+    if (warm) CGD_HIP_TRY(hipMemcpyAsync(h_fb, base + kOffFallback, 4096, hipMemcpyDeviceToHost, s));
     if (out) {
         CGD_HIP_TRY(hipMemcpyAsync(h_rel, base + kOffRelres, 8192, hipMemcpyDeviceToHost, s));
         CGD_HIP_TRY(hipMemcpyAsync(h_sums, base + kOffSums, 2 * CGD_MAX_FIELDS * sizeof(double),
@@ -98,7 +100,13 @@ cgd_status cg_finish_call(cgd_mesh m, int F, int n_steps, double vol_scale, hipS
                 worst = CGD_NOT_CONVERGED;
             }
         }
+    int n_fallback = 0;
+    if (warm)
+        for (int st = 0; st < n_steps; ++st)
+            for (int f = 0; f < F; ++f) n_fallback += h_fb[st * CGD_MAX_FIELDS + f] != 0;
+    if (n_fallback > 0 && worst == CGD_OK) worst = CGD_WARMSTART_FALLBACK;
     if (out) {
+        out->n_fallback = n_fallback;
         out->n_steps = n_steps;
         out->n_fields = F;
         for (int st = 0; st < n_steps; ++st)

@@ -154,6 +154,36 @@ __global__ void k_zero_if_rhs_zero(float* X, int64_t cells, const CgField* st) {
         x[k] = 0.f;
 }
 
+// Learned initial guess (x0_mode 3): after the residual sweep, a field
+// whose guess residual is not finite or exceeds ||b|| (||r0||^2 > ||b||^2)
+// restarts from zero.  One block per field sums the two partial arrays of
+// the residual sweep in the fixed order; on rejection the r.r partials are
+// replaced by the b.b partials, so the following sweeps see r = b.
+__global__ __launch_bounds__(kBlock) void k_warm_check(const double* P1, double* P2, int bpf, int32_t* fb_row) {
+    const int f = blockIdx.x;
+    __shared__ double sh[kWaves];
+    double* rr_p = P2 + ((size_t)f * 2 + 0) * bpf;
+    const double* bb_p = P1 + ((size_t)f * 2 + 1) * bpf;
+    const double rr = block_sum_fixed(rr_p, bpf, sh);
+    const double bb = block_sum_fixed(bb_p, bpf, sh);
+    const bool fb = !(rr <= bb);
+    if (threadIdx.x == 0) fb_row[f] = fb ? 1 : 0;
+    if (fb)
+        for (int i = threadIdx.x; i < bpf; i += kBlock) rr_p[i] = bb_p[i];
+}
+
+// ... and its vectors become x = 0, r = b.
+__global__ void k_warm_reset(float* X, float* R, const float* B, int64_t cells, const int32_t* fb_row) {
+    const int f = blockIdx.y;
+    if (!fb_row[f]) return;
+    const size_t o = (size_t)f * cells;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < cells;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        X[o + k] = 0.f;
+        R[o + k] = B[o + k];
+    }
+}
+
 // Sum of each field (float64), for the mass statistics.
 __global__ __launch_bounds__(kBlock) void k_field_sum(const float* v, int64_t cells, double* partials, int bpf) {
     const int f = blockIdx.y;
@@ -343,6 +373,8 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         hipLaunchKernelGGL(k_sum_finish, dim3(F), dim3(kBlock), 0, s, d_sum_part, sum_bpf, d_sums);
     }
 
+    if (da.x0_mode == 3) CGD_HIP_TRY(hipMemsetAsync(base + kOffFallback, 0, 4096, s));
+
     float* cur = da.field;  // b of the current step
     float* nxt = W0;        // x of the current step
     for (int step = 0; step < da.n_steps; ++step) {
@@ -351,7 +383,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         a.p.X = nxt;
         hipLaunchKernelGGL(k_cg_step_init, dim3(1), dim3(64), 0, s, ctl.st, F, ctl.ndone,
                            ctl.status + step * CGD_MAX_FIELDS);
-        const bool use_x0 = (da.x0_mode == 1) || (da.x0_mode == 2 && step == 0);
+        const bool use_x0 = (da.x0_mode == 1) || (da.x0_mode == 2 && step == 0) || da.x0_mode == 3;
         int it0;
         a.k = 0;
         if (!use_x0) {
@@ -359,9 +391,22 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             launch_sweep(S2_FIRST, p, a, s);
             it0 = 1;
         } else {
-            const float* x0 = da.x0_mode == 1 ? cur : da.x0;
-            CGD_HIP_TRY(hipMemcpyAsync(nxt, x0, (size_t)F * cells * sizeof(float), hipMemcpyDeviceToDevice, s));
+            if (da.x0_mode == 3) {
+                for (int f = 0; f < F; ++f) {
+                    cgd_status rg = unet::unet_guess(da.model, cur + (size_t)f * cells, nxt + (size_t)f * cells, s);
+                    if (rg != CGD_OK) return rg;
+                }
+            } else {
+                const float* x0 = da.x0_mode == 1 ? cur : da.x0;
+                CGD_HIP_TRY(hipMemcpyAsync(nxt, x0, (size_t)F * cells * sizeof(float), hipMemcpyDeviceToDevice, s));
+            }
             launch_sweep(S_RES, p, a, s);
+            if (da.x0_mode == 3) {
+                int32_t* fb_row = reinterpret_cast<int32_t*>(base + kOffFallback) + step * CGD_MAX_FIELDS;
+                hipLaunchKernelGGL(k_warm_check, dim3(F), dim3(kBlock), 0, s, d_P1, d_P2, p.bpf, fb_row);
+                const int blocks = (int)std::min<int64_t>(2048, (cells + kBlock - 1) / kBlock);
+                hipLaunchKernelGGL(k_warm_reset, dim3(blocks, F), dim3(kBlock), 0, s, nxt, R, cur, cells, fb_row);
+            }
             it0 = 0;
         }
         auto enqueue = [&](int it) {
@@ -403,7 +448,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         hipLaunchKernelGGL(k_field_sum, dim3(sum_bpf, F), dim3(kBlock), 0, s, da.field, cells, d_sum_part, sum_bpf);
         hipLaunchKernelGGL(k_sum_finish, dim3(F), dim3(kBlock), 0, s, d_sum_part, sum_bpf, d_sums + CGD_MAX_FIELDS);
     }
-    return cg_finish_call(m, F, da.n_steps, g.vol, s, out);
+    return cg_finish_call(m, F, da.n_steps, g.vol, s, out, da.x0_mode == 3);
 }
 
 }  // namespace cgd

@@ -118,6 +118,7 @@ struct DiffuseArgs {
     int32_t x0_mode;
     const float* x0;
     int32_t check_every;
+    cgd_unet model;  // x0_mode 3
 };
 cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hipStream_t s);
 
@@ -144,6 +145,13 @@ __device__ inline int frac_bits_of(uint32_t maxbits, int e_n) {
 // Host cell of each particle (-1: outside / non-finite); device int32 [n].
 cgd_status locate_hex(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hipStream_t s);
 cgd_status locate_tet(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hipStream_t s);
+
+// unet.hip: y = f(x) for one field on the network's grid (asynchronous);
+// whether the network was made for this grid and device.
+namespace unet {
+cgd_status unet_guess(cgd_unet u, const float* x, float* y, hipStream_t s);
+bool unet_matches(cgd_unet u, int nx, int ny, int nz, int device);
+}  // namespace unet
 
 // batched.hip
 cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offsets, const float* pos, int32_t F,

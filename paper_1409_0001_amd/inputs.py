@@ -208,3 +208,83 @@ def unstructured(n_hex: int = 100, n_particles: int = 5_000_000, seed: int = SEE
     d = np.full(n_particles, 0.004)
     vals = sphere_volume(d).astype(np.float32)[None, :]
     return xyz, tets, Particles(pos, vals, d), 4.0 / n_hex, 4, 1e-6
+
+
+# ---------------------------------------------------------------- advected beds
+# Inputs of the learned initial-guess workload: one particle bed carried by a
+# steady divergence-free flow, sampled every few time steps.  The flow is an
+# input generator only (the coarse graining never sees velocities).
+
+@dataclasses.dataclass(frozen=True)
+class FourierFlow:
+    """u(x) = sum_m a_m cos(k_m . x + phi_m) with a_m perpendicular to k_m,
+    so div u = 0; sum_m |a_m| = 1 bounds max |u|."""
+    k: np.ndarray    # float64 [M, 3]
+    a: np.ndarray    # float64 [M, 3]
+    phi: np.ndarray  # float64 [M]
+
+
+def fourier_flow(seed: int = SEED_BASE + 5, n_modes: int = 16, max_wavenumber: int = 4) -> FourierFlow:
+    """n_modes random modes with |k_m| = 2 pi j_m, j_m uniform in 1..max_wavenumber."""
+    rng = np.random.default_rng(seed)
+    dirs = rng.normal(size=(n_modes, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    j = rng.integers(1, max_wavenumber + 1, size=n_modes)
+    k = 2.0 * math.pi * j[:, None] * dirs
+    a = rng.normal(size=(n_modes, 3))
+    a -= (a * dirs).sum(axis=1, keepdims=True) * dirs
+    a /= np.linalg.norm(a, axis=1).sum()
+    return FourierFlow(k, a, rng.uniform(0.0, 2.0 * math.pi, size=n_modes))
+
+
+def bed_in_unit_cube(n_particles: int, seed: int, median_diam: float = 0.003):
+    """The dense bed's recipe scaled to the unit cube: 70 % uniform in
+    [0,1]^2 x [0,0.25], 30 % in 50 Gaussian clumps (sigma 0.05); lognormal
+    diameters.  Returns (pos float64 [N, 3], volumes float32 [1, N])."""
+    rng = np.random.default_rng(seed)
+    n_bed = int(round(0.7 * n_particles))
+    bed = rng.random((n_bed, 3)) * np.array([1.0, 1.0, 0.25])
+    cl = _clumps(rng, n_particles - n_bed, 50, 0.05, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    d = _lognormal_diam(rng, n_particles, median=median_diam)
+    return np.concatenate([bed, cl]), sphere_volume(d).astype(np.float32)[None, :]
+
+
+class AdvectedSnapshots:
+    """Snapshots j = 0, 1, ... of a bed (bed_in_unit_cube) advected through
+    the unit cube by fourier_flow, with forward-Euler sub-steps of length
+    dt = 0.5 h / sum|a_m| (no particle moves more than half a cell of the
+    grid of `n_cells_x` cells per sub-step), `stride` sub-steps between
+    snapshots, and specular reflection at the walls.
+
+    Runs in torch float64 on `device` (CPU or GPU); positions are handed out
+    as float32 [N, 3] tensors on that device, volumes as float32 [1, N]."""
+
+    def __init__(self, n_particles: int = 2_000_000, n_cells_x: int = 128, stride: int = 4,
+                 seed: int = SEED_BASE + 5, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device) if device is not None else torch.device("cpu")
+        pos, vol = bed_in_unit_cube(n_particles, seed)
+        flow = fourier_flow(seed + 1)
+        self.pos = torch.from_numpy(pos).to(self.device)
+        self.values = torch.from_numpy(vol).to(self.device)
+        self.k = torch.from_numpy(flow.k).to(self.device)
+        self.a = torch.from_numpy(flow.a).to(self.device)
+        self.phi = torch.from_numpy(flow.phi).to(self.device)
+        self.dt = 0.5 / n_cells_x / float(np.linalg.norm(flow.a, axis=1).sum())
+        self.stride = stride
+        self.index = 0
+
+    def velocity(self, x):
+        return self.torch.cos(x @ self.k.T + self.phi) @ self.a
+
+    def current(self):
+        return self.pos.float().contiguous(), self.values
+
+    def advance(self):
+        """Moves to the next snapshot."""
+        for _ in range(self.stride):
+            self.pos = self.pos + self.dt * self.velocity(self.pos)
+            self.pos = self.torch.where(self.pos < 0.0, -self.pos, self.pos)
+            self.pos = self.torch.where(self.pos > 1.0, 2.0 - self.pos, self.pos)
+        self.index += 1
