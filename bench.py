@@ -40,10 +40,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", default="dense", choices=["dense", "batched", "unstructured"],
+    ap.add_argument("--workload", default="dense", choices=["dense", "batched", "unstructured", "learned"],
                     help="dense: the headline metric; batched: 64 snapshots x 4 fields on 128^3 in one "
-                         "persistent launch; unstructured: 100^3 x 6 jittered tets")
+                         "persistent launch; unstructured: 100^3 x 6 jittered tets; learned: train the "
+                         "initial-guess network on advected snapshots, then compare initial guesses")
     ap.add_argument("--snapshots", type=int, default=64)
+    ap.add_argument("--train-snapshots", type=int, default=1500)
+    ap.add_argument("--test-snapshots", type=int, default=500)
+    ap.add_argument("--lr", type=float, default=1e-3)
     return ap.parse_args()
 
 
@@ -204,11 +208,80 @@ def bench_unstructured(args):
     print(json.dumps(line))
 
 
+def bench_learned(args):
+    """Learned initial guess on 128^3 (unit cube, 2M particles advected by a
+    divergence-free flow, b = 4h, 4 backward-Euler steps, rtol 1e-6): train
+    on the step pairs of the first snapshots, then coarse-grain the next
+    ones with the zero, previous-step and network guesses."""
+    import numpy as np
+    import torch
+
+    import paper_1409_0001_amd as cgd
+    from paper_1409_0001_amd import inputs, warmstart
+    n, steps, rtol = 128, 4, args.rtol
+    b = 4.0 / n
+    mesh = cgd.HexMesh((n, n, n))
+    net = cgd.UNet((n, n, n), seed=14090105)
+    snaps = inputs.AdvectedSnapshots(n_particles=2_000_000, n_cells_x=n, stride=4, device="cuda")
+    t0 = time.perf_counter()
+    losses = warmstart.train(net, mesh, snaps, args.train_snapshots, b, steps, lr=args.lr, lr_final=args.lr / 10,
+                             log_every=400, log=lambda m: print(m, file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    print(f"[bench] trained on {args.train_snapshots} snapshots in {t_train:.1f}s", file=sys.stderr, flush=True)
+    # parity sample: the first test snapshot against the float64 oracle
+    first = snaps.current()
+    first_pos, first_vals = first[0].cpu().numpy(), first[1].cpu().numpy()
+    t0 = time.perf_counter()
+    res = warmstart.evaluate(mesh, net, snaps, args.test_snapshots, b, steps, rtol=rtol)
+    print(f"[bench] evaluated {args.test_snapshots} snapshots x 3 guesses in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    rel = None
+    if not args.no_check:
+        from oracle import cgd_oracle as O
+        lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+        dep = O.deposit_hex(first_pos, first_vals, lo, hi, (n, n, n))
+        ref = O.diffuse_hex_dct(dep["field64"], lo, hi, (n, n, n), b, steps)[0]
+        rel = {m: float(np.linalg.norm(res[m]["fields"][0].cpu().numpy() - ref) / np.linalg.norm(ref))
+               for m in res}
+    names = {0: "zero", 1: "previous_step", 3: "network"}
+    ntest = args.test_snapshots
+    modes = {names[m]: {"cg_iters_per_step": [round(v / ntest, 2) for v in r["iters"]],
+                        "cg_iters_total_per_field": round(sum(r["iters"]) / ntest, 2),
+                        "ms_per_field": round(r["ms"] / ntest, 3), "fallbacks": r["fallbacks"]}
+             for m, r in res.items()}
+    t_fwd = []
+    x = res[0]["fields"][0]
+    y = torch.empty_like(x)
+    for _ in range(20):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        net.forward(x, y)
+        torch.cuda.synchronize()
+        t_fwd.append(time.perf_counter() - t)
+    net_ms = res[3]["ms"] / ntest
+    line = {"metric": "coarse-grained fields/sec, learned-guess workload 128^3, 2M particles",
+            "value": round(1e3 / net_ms, 3), "unit": "fields/s", "n_gpus": 1, "steps": ntest,
+            "warmup": 0, "ms_per_step": round(net_ms, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32 (solver), bf16 (network)", "data": "synthetic",
+            "config": {"workload": "unit cube 128^3 hex, 2M particles advected by a 16-mode divergence-free "
+                                   "flow (4 sub-steps between snapshots), b=4h, 4 backward-Euler steps, "
+                                   f"CG rtol {rtol:g}; network trained on {args.train_snapshots} snapshots "
+                                   f"({args.train_snapshots * steps} step pairs), tested on the next {ntest}",
+                       "cells": n ** 3, "train_snapshots": args.train_snapshots, "test_snapshots": ntest},
+            "guesses": modes,
+            "network_forward_ms": round(1e3 * float(np.median(t_fwd)), 3),
+            "train": {"seconds": round(t_train, 1), "loss_first": losses[0][1], "loss_last": losses[-1][1],
+                      "pairs": args.train_snapshots * steps},
+            "rel_l2_first_test_snapshot": rel}
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the multi-GPU layout of the "
+              "path is a design, not built", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -220,6 +293,8 @@ def main():
         return bench_batched(args)
     if args.workload == "unstructured":
         return bench_unstructured(args)
+    if args.workload == "learned":
+        return bench_learned(args)
     if args.profile_copy:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)

@@ -388,29 +388,49 @@ __global__ __launch_bounds__(kThreads) void k_wgrad(WgArgs a) {
     }
 }
 
-// Sums the weight-gradient partials of nblk blocks in block order and writes
-// dW in the canonical layout [co][tap][ci].
-__global__ void k_wgrad_reduce(const float* part, int nblk, int cc, int co_n, int np, int ci_n, float* dw) {
+// Sums the weight-gradient partials of nblk blocks and writes dW in the
+// canonical layout [co][tap][ci].  A block takes 32 consecutive outputs; its
+// 8 thread rows each add the partials b = r, r + 8, ... in increasing b, and
+// row 0 adds the 8 row sums in order (a fixed order for every run).
+constexpr int kRedCols = 32, kRedRows = kThreads / kRedCols;
+
+__device__ inline float reduce_rows_fixed(const float* part, int nblk, size_t total, size_t idx, bool valid,
+                                          float (*sh)[kRedCols]) {
+    const int c = threadIdx.x % kRedCols, r = threadIdx.x / kRedCols;
+    float s = 0.f;
+    if (valid) {
+#pragma unroll 4
+        for (int b = r; b < nblk; b += kRedRows) s += part[(size_t)b * total + idx];
+    }
+    sh[r][c] = s;
+    __syncthreads();
+    float t = 0.f;
+    if (r == 0)
+        for (int i = 0; i < kRedRows; ++i) t += sh[i][c];
+    return t;
+}
+
+__global__ __launch_bounds__(kThreads) void k_wgrad_reduce(const float* part, int nblk, int cc, int co_n, int np,
+                                                          int ci_n, float* dw) {
+    __shared__ float sh[kRedRows][kRedCols];
     const int ncot = co_n / 16;
     const int ncit = cc == 1 ? 2 : cc / 16;
     const int T = cc == 1 ? ncit * ncot : 27 * ncit * ncot;
-    const int npt = np * T;
-    const int total = npt * 256;
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
-        float s = 0.f;
-        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * total + idx];
-        const int ptile = idx >> 8, i = (idx >> 4) & 15, jc = idx & 15;
-        const int pass = ptile / T, tile = ptile % T;
-        const int co = 16 * (tile % ncot) + i;
-        if (cc == 1) {
-            const int tap = 16 * (tile / ncot) + jc;
-            if (tap < 27) dw[(size_t)co * 27 + tap] = s;
-        } else {
-            const int rest = tile / ncot;
-            const int cit = rest % ncit, tap = rest / ncit;
-            const int ci = pass * cc + 16 * cit + jc;
-            dw[((size_t)co * 27 + tap) * ci_n + ci] = s;
-        }
+    const int total = np * T * 256;
+    const int idx = blockIdx.x * kRedCols + threadIdx.x % kRedCols;
+    const float s = reduce_rows_fixed(part, nblk, total, idx, idx < total, sh);
+    if (threadIdx.x >= kRedCols || idx >= total) return;
+    const int ptile = idx >> 8, i = (idx >> 4) & 15, jc = idx & 15;
+    const int pass = ptile / T, tile = ptile % T;
+    const int co = 16 * (tile % ncot) + i;
+    if (cc == 1) {
+        const int tap = 16 * (tile / ncot) + jc;
+        if (tap < 27) dw[(size_t)co * 27 + tap] = s;
+    } else {
+        const int rest = tile / ncot;
+        const int cit = rest % ncit, tap = rest / ncit;
+        const int ci = pass * cc + 16 * cit + jc;
+        dw[((size_t)co * 27 + tap) * ci_n + ci] = s;
     }
 }
 
@@ -441,13 +461,23 @@ __global__ __launch_bounds__(kThreads) void k_bias_part(const bf16* g, int ldg, 
     }
 }
 
-// ... added over the blocks in order.
-__global__ void k_bias_reduce(const float* part, int nblk, int co_n, float* db) {
-    const int c = threadIdx.x;
-    if (c >= co_n) return;
-    float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * co_n + c];
-    db[c] = s;
+// ... added over the blocks (fixed order, as k_wgrad_reduce).
+__global__ __launch_bounds__(kThreads) void k_bias_reduce(const float* part, int nblk, int co_n, float* db) {
+    __shared__ float sh[kRedRows][kRedCols];
+    const int idx = blockIdx.x * kRedCols + threadIdx.x % kRedCols;
+    const float s = reduce_rows_fixed(part, nblk, co_n, idx, idx < co_n, sh);
+    if (threadIdx.x < kRedCols && idx < co_n) db[idx] = s;
+}
+
+// Sum of nblk float64 values in a fixed order: thread t adds t, t + 256, ...,
+// then a fixed shuffle tree and the 4 wave sums in order.  Valid in thread 0.
+__device__ inline double block_sum_f64(const double* p, int nblk, size_t stride, double* sh) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) s += p[(size_t)b * stride];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    return ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
 // 2x2x2 average pooling (fine grid nx, ny, nz; C channels).
@@ -562,10 +592,10 @@ __global__ __launch_bounds__(kThreads) void k_sumsq_part(const float* x, int64_t
     if (threadIdx.x == 0) part[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
-__global__ void k_norm_finish(const double* part, int nblk, int64_t n, float* sc) {
+__global__ __launch_bounds__(kThreads) void k_norm_finish(const double* part, int nblk, int64_t n, float* sc) {
+    __shared__ double sh[4];
+    const double s = block_sum_f64(part, nblk, 1, sh);
     if (threadIdx.x != 0) return;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[b];
     const double rms = sqrt(s / (double)n);
     const float sf = (float)rms;
     sc[0] = sf;
@@ -661,12 +691,14 @@ __global__ __launch_bounds__(kThreads) void k_head(HeadArgs a) {
     }
 }
 
-// Sums the head partials in block order: grad of hw / hb, loss (double).
-__global__ void k_head_finish(const double* part, int nblk, int64_t n, float* ghead, double* loss) {
-    const int c = threadIdx.x;
-    if (c >= kBase + 2) return;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * (kBase + 2) + c];
+// Sums the head partials (one block per value, fixed order): loss (double),
+// gradient of hw and hb.
+__global__ __launch_bounds__(kThreads) void k_head_finish(const double* part, int nblk, int64_t n, float* ghead,
+                                                         double* loss) {
+    __shared__ double sh[4];
+    const int c = blockIdx.x;
+    const double s = block_sum_f64(part + c, nblk, kBase + 2, sh);
+    if (threadIdx.x != 0) return;
     if (c == 0) *loss = s / (double)n;
     else ghead[c - 1] = (float)s;
 }
@@ -784,9 +816,9 @@ bool launch_conv(int cc, int co, int np, ConvArgs a, hipStream_t s) {
 int wgrad_tiles(int cc, int co) { return cc == 1 ? 2 * (co / 16) : 27 * (cc / 16) * (co / 16); }
 
 // Blocks along x of a weight-gradient launch (partials per block), chosen so
-// that about 2048 blocks run in all.
+// that about 1024 blocks run in all.
 int wgrad_nblk(int64_t nbricks, int groups, int np) {
-    return (int)std::max<int64_t>(1, std::min<int64_t>(nbricks, 2048 / std::max(1, groups * np)));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nbricks, 1024 / std::max(1, groups * np)));
 }
 
 size_t wgrad_part_floats(int nx, int ny, int nz, int cc, int co, int np) {
@@ -832,14 +864,15 @@ bool launch_wgrad(int cc, int co, int np, const Src& src, const bf16* g, int ldg
     if (!ok) return false;
     const int ci_n = cc == 1 ? 1 : cc * np;
     const int total = np * T * 256;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(grid_blocks(total)), dim3(kThreads), 0, s, part, nblk, cc, co, np, ci_n, dw);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((total + kRedCols - 1) / kRedCols), dim3(kThreads), 0, s, part, nblk, cc,
+                       co, np, ci_n, dw);
     // bias: partials reuse the start of `part` (the reduce above has read it: same stream)
     const int64_t nvox = (int64_t)nx * ny * nz;
     const int bnb = grid_blocks(nvox / 8 + 1, kThreads, 1024);
     if (co == 16) hipLaunchKernelGGL(k_bias_part<16>, dim3(bnb), dim3(kThreads), 0, s, g, ldg, nvox, part);
     else if (co == 32) hipLaunchKernelGGL(k_bias_part<32>, dim3(bnb), dim3(kThreads), 0, s, g, ldg, nvox, part);
     else hipLaunchKernelGGL(k_bias_part<64>, dim3(bnb), dim3(kThreads), 0, s, g, ldg, nvox, part);
-    hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(64), 0, s, part, bnb, co, db);
+    hipLaunchKernelGGL(k_bias_reduce, dim3((co + kRedCols - 1) / kRedCols), dim3(kThreads), 0, s, part, bnb, co, db);
     return true;
 }
 
@@ -885,7 +918,7 @@ cgd_status forward(cgd_unet_s* u, const float* x, hipStream_t s) {
     const int64_t n0 = u->nvox[0];
     const int nb = grid_blocks(n0, kThreads, 1024);
     hipLaunchKernelGGL(k_sumsq_part, dim3(nb), dim3(kThreads), 0, s, x, n0, u->dpart);
-    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(64), 0, s, u->dpart, nb, n0, u->sc);
+    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(kThreads), 0, s, u->dpart, nb, n0, u->sc);
     hipLaunchKernelGGL(k_prep_input, dim3(grid_blocks(n0)), dim3(kThreads), 0, s, x, u->sc, n0, u->x0.p);
     for (int l = 0; l < kLayers; ++l) {
         const Layer& L = u->L[l];
@@ -953,7 +986,8 @@ void backward(cgd_unet_s* u, const float* x, const float* t, hipStream_t s) {
     h.part = u->dpart;
     h.n = n0;
     hipLaunchKernelGGL(k_head, dim3(nb), dim3(kThreads), 0, s, h);
-    hipLaunchKernelGGL(k_head_finish, dim3(1), dim3(64), 0, s, u->dpart, nb, n0, u->grads + u->head_off, u->loss);
+    hipLaunchKernelGGL(k_head_finish, dim3(kBase + 2), dim3(kThreads), 0, s, u->dpart, nb, n0, u->grads + u->head_off,
+                       u->loss);
 
     Tensor* A = u->act;
     auto up_bwd = [&](const Tensor& gup, const Tensor& act, const Tensor& out, int lev) {
