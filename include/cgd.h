@@ -92,7 +92,10 @@ typedef struct {
                                 pseudo-step's field, every step (hex meshes) */
     const float* x0;      /* device [F, cells] when x0_mode == 2, else NULL */
     int32_t check_every;  /* iterations enqueued between convergence read-backs; <= 0: 4 */
-    int32_t reserved;
+    int32_t precond;      /* hex meshes: 0 (default) conjugate gradients preconditioned by
+                             the degree-1 Chebyshev polynomial of A on its spectrum
+                             [1, 1 + 4 sum_a c_a]; 1 plain CG.  Tet meshes use Jacobi
+                             either way.  The stopping rule is the same for all. */
     cgd_unet model;       /* x0_mode 3: a network created for this mesh's grid, else NULL */
 } cgd_solver_opts;
 
@@ -150,8 +153,9 @@ cgd_status cgd_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F,
  *
  * T = bandwidth^2 / 4, dtau = T / n_steps; each of the n_steps backward-Euler
  * steps solves (M + dtau K) e^{n+1} = M e^n by conjugate gradients with float32
- * vectors and float64 inner products (hex: matrix-free 7-point stencil;
- * tet: CSR with Jacobi preconditioning).  Zero-flux walls: wall faces carry
+ * vectors and float64 inner products (hex: matrix-free 7-point stencil with a
+ * polynomial preconditioner, see cgd_solver_opts.precond; tet: CSR with
+ * Jacobi preconditioning).  Zero-flux walls: wall faces carry
  * no flux.  Fields are independent solves (Section 3.2.1: each component is
  * diffused on its own).
  *
@@ -292,6 +296,7 @@ cgd_status cgd_conv3_wgrad(int32_t nx, int32_t ny, int32_t nz, int32_t ci, int32
  *   2  centroid binning + fixed-point atomic deposit (hex)
  *   3  CSR sweep of the tet Jacobi-PCG (SpMV + dots)
  *   4  CSR update sweep of the tet Jacobi-PCG
+ *   5  hex preconditioning sweep (z = M r, r.z)
  * bytes_per_launch is the algorithmic byte count of the last timed launch of
  * that kind (what the method must move, not what the hardware moved). */
 #define CGD_TIMING_KINDS 8

@@ -377,6 +377,11 @@ static cgd_status fill_opts(const cgd_solver_opts* o, int32_t F, float* field, d
     a->x0 = o ? o->x0 : nullptr;
     a->check_every = (o && o->check_every > 0) ? o->check_every : 4;
     a->model = o ? o->model : nullptr;
+    a->precond = o ? o->precond : 0;
+    if (a->precond < 0 || a->precond > 1) {
+        set_error(std::string(who) + ": precond must be 0 (default preconditioner) or 1 (none)");
+        return CGD_E_INVALID;
+    }
     if (a->x0_mode < 0 || a->x0_mode > 3 || (a->x0_mode == 2 && !a->x0) || (a->x0_mode == 3 && !a->model) ||
         !isfinite(a->rtol)) {
         set_error(std::string(who) + ": bad solver options (x0_mode 0..3, x0 needed for mode 2, model for mode 3)");

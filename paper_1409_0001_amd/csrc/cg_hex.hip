@@ -42,6 +42,8 @@ struct SweepArgs {
     CgCtl c;
     double* P1;         // [F][2][bpf]: slot 0 p.Ap, slot 1 b.b
     double* P2;         // [F][2][bpf]: r.r of r_k in slot k % 2
+    double* P3;         // [F][2][bpf]: preconditioned CG, r.z of r_k in slot k % 2
+    int pcg;            // 1: preconditioned CG (the S1 modes read z; alpha, beta from r.z)
     int64_t cells;
     int nx, ny, nz;
     int xsegs, ygroups, zc;
@@ -57,13 +59,39 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     const int f = b / a.bpf;
     const int blk = b - f * a.bpf;
     CgField* stf = a.c.st + f;
-    // S2_FIRST must write x and r even when its first block flags a breakdown.
-    if (MODE != S2_FIRST && stf->done) return;  // uniform over the block
+    // S2_FIRST / S2P_FIRST must write x and r even when their first block
+    // flags a breakdown.
+    if (MODE != S2_FIRST && MODE != S2P_FIRST && stf->done) return;  // uniform over the block
 
     __shared__ double sh[kWaves];
     const bool lead = blk == 0 && threadIdx.x == 0;
     float alpha = 0.f, beta = 0.f;
-    if constexpr (MODE == S1 || MODE == S1_B0) {
+    if constexpr (MODE == SZ) {
+        // preconditioned CG: convergence test on r_k . r_k from the previous
+        // sweep 2 (or, at k = 0, the residual sweep, which also gave b.b)
+        const double rrk = block_sum_fixed(a.P2 + ((size_t)f * 2 + (a.k & 1)) * a.bpf, a.bpf, sh);
+        double bb;
+        if (a.k == 0) bb = block_sum_fixed(a.P1 + ((size_t)f * 2 + 1) * a.bpf, a.bpf, sh);
+        else bb = stf->bb;
+        if (lead) {
+            stf->rr_par[a.k & 1] = rrk;
+            if (a.k == 0) stf->bb = bb;
+        }
+        if (check_stop(a.c, f, a.k, rrk, bb, lead)) return;
+    } else if ((MODE == S1 || MODE == S1_B0) && a.pcg) {
+        // rho_k = r_k . z_k from the preconditioning sweep
+        const double rho = block_sum_fixed(a.P3 + ((size_t)f * 2 + (a.k & 1)) * a.bpf, a.bpf, sh);
+        double bb = 0.0;
+        if (MODE == S1_B0) bb = block_sum_fixed(a.P1 + ((size_t)f * 2 + 1) * a.bpf, a.bpf, sh);
+        if (lead) {
+            stf->rho_par[a.k & 1] = rho;
+            if (MODE == S1_B0) {
+                stf->bb = bb;
+                stf->rr_par[0] = bb;
+            }
+        }
+        if (MODE == S1) beta = (float)(rho / stf->rho_par[(a.k - 1) & 1]);
+    } else if constexpr (MODE == S1 || MODE == S1_B0) {
         // r_k . r_k from the previous sweep 2 (or the residual sweep)
         const double rrk = block_sum_fixed(a.P2 + ((size_t)f * 2 + (a.k & 1)) * a.bpf, a.bpf, sh);
         double bb;
@@ -75,6 +103,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
         }
         if (check_stop(a.c, f, a.k, rrk, bb, lead)) return;
         if constexpr (MODE == S1) beta = (float)(rrk / stf->rr_par[(a.k - 1) & 1]);
+    } else if constexpr (MODE == S2P_FIRST) {
+        // preconditioned CG, zero initial guess: alpha = rho_0 / p.Ap; b = 0 or
+        // a breakdown gives alpha = 0, i.e. x = 0 and r = b
+        const double pap = block_sum_fixed(a.P1 + ((size_t)f * 2 + 0) * a.bpf, a.bpf, sh);
+        const double bb = stf->bb, rho = stf->rho_par[0];
+        const bool broken = !isfinite(bb) || !isfinite(pap) || !isfinite(rho) || (bb > 0.0 && !(pap > 0.0));
+        if (lead && broken) finish_field(a.c, f, CGD_E_BREAKDOWN);
+        alpha = (broken || bb == 0.0) ? 0.f : (float)(rho / pap);
     } else if constexpr (MODE == S2 || MODE == S2_FIRST) {
         const double pap = block_sum_fixed(a.P1 + ((size_t)f * 2 + 0) * a.bpf, a.bpf, sh);
         if constexpr (MODE == S2_FIRST) {
@@ -88,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
             // b = 0 or a breakdown: alpha = 0 gives x = 0, r = b
             alpha = (broken || bb == 0.0) ? 0.f : (float)(bb / pap);
         } else {
-            const double rrk = stf->rr_par[a.k & 1];
+            const double rrk = a.pcg ? stf->rho_par[a.k & 1] : stf->rr_par[a.k & 1];
             if (!(pap > 0.0) || !isfinite(pap)) {
                 if (lead) finish_field(a.c, f, CGD_E_BREAKDOWN);
                 return;
@@ -113,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     }
 
     // block reduction of the float64 partials, fixed order
-    constexpr bool kTwo = (MODE == S1_FIRST || MODE == S_RES);
+    constexpr bool kTwo = (MODE == S1_FIRST || MODE == S_RES || MODE == SZ_FIRST);
     for (int o = 32; o > 0; o >>= 1) {
         acc0 += __shfl_xor(acc0, o);
         if (kTwo) acc1 += __shfl_xor(acc1, o);
@@ -135,8 +171,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
         if constexpr (MODE == S1_FIRST || MODE == S1 || MODE == S1_B0) {
             a.P1[((size_t)f * 2 + 0) * a.bpf + blk] = t0;
             if (MODE == S1_FIRST) a.P1[((size_t)f * 2 + 1) * a.bpf + blk] = t1;
-        } else if constexpr (MODE == S2_FIRST || MODE == S2) {
+        } else if constexpr (MODE == S2_FIRST || MODE == S2 || MODE == S2P_FIRST) {
             a.P2[((size_t)f * 2 + ((a.k + 1) & 1)) * a.bpf + blk] = t0;
+        } else if constexpr (MODE == SZ_FIRST || MODE == SZ) {
+            a.P3[((size_t)f * 2 + (a.k & 1)) * a.bpf + blk] = t0;
+            if (MODE == SZ_FIRST) a.P1[((size_t)f * 2 + 1) * a.bpf + blk] = t1;
         } else {  // S_RES: r_0 . r_0 and b . b
             a.P2[((size_t)f * 2 + 0) * a.bpf + blk] = t0;
             a.P1[((size_t)f * 2 + 1) * a.bpf + blk] = t1;
@@ -265,6 +304,9 @@ void launch_sweep_t(int mode, const Plan& p, const SweepArgs& a, hipStream_t s) 
         case S1_B0: hipLaunchKernelGGL((k_sweep<VEC, TY, S1_B0, EDGE>), grid, block, 0, s, a); break;
         case S2_FIRST: hipLaunchKernelGGL((k_sweep<VEC, TY, S2_FIRST, EDGE>), grid, block, 0, s, a); break;
         case S2: hipLaunchKernelGGL((k_sweep<VEC, TY, S2, EDGE>), grid, block, 0, s, a); break;
+        case SZ_FIRST: hipLaunchKernelGGL((k_sweep<VEC, TY, SZ_FIRST, EDGE>), grid, block, 0, s, a); break;
+        case SZ: hipLaunchKernelGGL((k_sweep<VEC, TY, SZ, EDGE>), grid, block, 0, s, a); break;
+        case S2P_FIRST: hipLaunchKernelGGL((k_sweep<VEC, TY, S2P_FIRST, EDGE>), grid, block, 0, s, a); break;
         default: hipLaunchKernelGGL((k_sweep<VEC, TY, S_RES, EDGE>), grid, block, 0, s, a); break;
     }
 }
@@ -286,7 +328,7 @@ void launch_sweep(int mode, const Plan& p, const SweepArgs& a, hipStream_t s) {
 }
 
 size_t small_bytes(int F, int bpf) {
-    size_t b = kSmallFixed + 2 * (size_t)F * 2 * (size_t)bpf * sizeof(double);
+    size_t b = kSmallFixed + 3 * (size_t)F * 2 * (size_t)bpf * sizeof(double);
     return (b + 255) & ~(size_t)255;
 }
 
@@ -300,7 +342,7 @@ static size_t max_bpf(const HexGeom& g, int F) {
 }
 
 size_t diffuse_hex_workspace(const cgd_mesh m, int32_t F) {
-    return small_bytes(F, (int)max_bpf(m->hex, F)) + 4 * (size_t)F * m->cells * sizeof(float);
+    return small_bytes(F, (int)max_bpf(m->hex, F)) + 5 * (size_t)F * m->cells * sizeof(float);
 }
 
 cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s) {
@@ -318,7 +360,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             p = make_plan(g, F, vec, ty, zc);
     }
     const size_t small = small_bytes(F, (int)max_bpf(g, F));
-    cgd_status rc = ensure_workspace(m, small + 4 * (size_t)F * cells * sizeof(float));
+    cgd_status rc = ensure_workspace(m, small + 5 * (size_t)F * cells * sizeof(float));
     if (rc != CGD_OK) return rc;
     rc = ensure_pinned(m, kPinBytes);
     if (rc != CGD_OK) return rc;
@@ -336,10 +378,12 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     const size_t pmax = (size_t)F * 2 * max_bpf(g, F);
     double* d_P1 = reinterpret_cast<double*>(base + kSmallFixed);
     double* d_P2 = d_P1 + pmax;
+    double* d_P3 = d_P2 + pmax;
     float* W0 = reinterpret_cast<float*>(base + small);
     float* R = W0 + (size_t)F * cells;
     float* PA = R + (size_t)F * cells;
     float* PB = PA + (size_t)F * cells;
+    float* Z = PB + (size_t)F * cells;
 
     const double T = da.bandwidth * da.bandwidth / 4.0;
     const double dtau = T / da.n_steps;
@@ -363,7 +407,24 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     a.c = ctl;
     a.P1 = d_P1;
     a.P2 = d_P2;
+    a.P3 = d_P3;
     a.p.R = R;
+    a.p.Z = Z;
+    // Preconditioned CG (default): M = c0 I - c1 A, the degree-1 polynomial
+    // that makes the residual polynomial 1 - lambda M(lambda) the scaled
+    // Chebyshev polynomial T_2 on the spectrum [1, lmax] of A (lambda_min = 1:
+    // the constant field; lambda_max < 1 + 4 sum_a c_a).  With s = lmax + 1,
+    // d = lmax - 1: c0 = 8 s / (2 s^2 - d^2), c1 = 8 / (2 s^2 - d^2); the
+    // condition number drops from lmax to (1 + e) / (1 - e), e = 1 / T_2(s / d)
+    // (13 -> 3.8 at dtau / h^2 = 1).
+    const bool pcg = da.precond == 0;
+    a.pcg = pcg ? 1 : 0;
+    {
+        const double lmax = 1.0 + 4.0 * ((double)a.g.cx + (double)a.g.cy + (double)a.g.cz);
+        const double sp = lmax + 1.0, dm = lmax - 1.0, den = 2.0 * sp * sp - dm * dm;
+        a.g.c0 = (float)(8.0 * sp / den);
+        a.g.c1 = (float)(8.0 / den);
+    }
 
     const int sum_bpf = (int)std::min<int64_t>(1024, (cells + kBlock - 1) / kBlock);
     double* d_sum_part = d_P2;  // free outside the solves
@@ -386,7 +447,9 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         const bool use_x0 = (da.x0_mode == 1) || (da.x0_mode == 2 && step == 0) || da.x0_mode == 3;
         int it0;
         a.k = 0;
-        if (!use_x0) {
+        if (!use_x0 && pcg) {
+            it0 = 0;  // iteration 0 (z = M b, p = z, x = alpha p) is enqueued by the loop
+        } else if (!use_x0) {
             launch_sweep(S1_FIRST, p, a, s);
             launch_sweep(S2_FIRST, p, a, s);
             it0 = 1;
@@ -409,7 +472,28 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             }
             it0 = 0;
         }
+        auto enqueue_pcg = [&](int it) {
+            // iteration it: z = M r (convergence test first), p = z + beta p_old, x, r update
+            const bool first = it == 0 && !use_x0;
+            const int64_t tag = (int64_t)step * 65536 + it;
+            a.k = it;
+            a.p.R = R;
+            int t0 = first ? -1 : timing_begin(&m->timing, s);
+            launch_sweep(first ? SZ_FIRST : SZ, p, a, s);
+            if (!first) timing_end(&m->timing, t0, 5, 8.0 * (double)F * cells, s, tag);
+            a.p.R = Z;
+            a.p.Pold = (it & 1) ? PA : PB;
+            a.p.Pnew = (it & 1) ? PB : PA;
+            int t1 = first ? -1 : timing_begin(&m->timing, s);
+            launch_sweep(it == 0 ? S1_B0 : S1, p, a, s);
+            if (!first) timing_end(&m->timing, t1, 0, 12.0 * (double)F * cells, s, tag);
+            a.p.R = R;
+            int t2 = first ? -1 : timing_begin(&m->timing, s);
+            launch_sweep(first ? S2P_FIRST : S2, p, a, s);
+            if (!first) timing_end(&m->timing, t2, 1, 20.0 * (double)F * cells, s, tag);
+        };
         auto enqueue = [&](int it) {
+            if (pcg) return enqueue_pcg(it);
             int mode1 = S1;
             if (!use_x0) {
                 a.p.Pold = it == 1 ? cur : ((it & 1) ? PB : PA);

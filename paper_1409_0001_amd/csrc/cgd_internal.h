@@ -31,6 +31,7 @@ void set_error(const std::string& msg);
 struct CgField {
     double bb;         // ||b||^2 of the current step
     double rr_par[2];  // ||r_k||^2, slot k % 2
+    double rho_par[2]; // preconditioned CG: r_k . z_k, slot k % 2
     int32_t done;      // 1 once converged / stopped
     int32_t status;    // CGD_OK, CGD_NOT_CONVERGED or CGD_E_BREAKDOWN
 };
@@ -118,7 +119,8 @@ struct DiffuseArgs {
     int32_t x0_mode;
     const float* x0;
     int32_t check_every;
-    cgd_unet model;  // x0_mode 3
+    int32_t precond;  // hex: 0 polynomial-preconditioned CG, 1 plain CG
+    cgd_unet model;   // x0_mode 3
 };
 cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hipStream_t s);
 

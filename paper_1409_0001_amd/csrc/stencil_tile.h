@@ -26,19 +26,26 @@ namespace stencil {
 //   S2_FIRST  x = alpha b, r = b - alpha A b;  r.r
 //   S2        x += alpha p, r -= alpha A p;   r.r
 //   S_RES     r = b - A x;           r.r and b.b
-enum Mode { S1_FIRST = 0, S1 = 1, S2_FIRST = 2, S2 = 3, S_RES = 4, S1_B0 = 5 };
+// Preconditioned CG (z = M r with the polynomial M = c0 I - c1 A; the S1
+// modes then read z through Ptrs::R):
+//   SZ_FIRST  z = M b;               writes z; b.z and b.b
+//   SZ        z = M r;               writes z; r.z
+//   S2P_FIRST x = alpha p, r = b - alpha A p;  r.r   (zero initial guess)
+enum Mode { S1_FIRST = 0, S1 = 1, S2_FIRST = 2, S2 = 3, S_RES = 4, S1_B0 = 5, SZ_FIRST = 6, SZ = 7, S2P_FIRST = 8 };
 
 struct Ptrs {
     const float* B;     // right-hand side of the step
-    float* R;           // residual
+    float* R;           // residual (the S1 modes of preconditioned CG: z)
     const float* Pold;  // previous direction
     float* Pnew;        // new direction
     float* X;           // iterate
+    float* Z;           // preconditioned residual (SZ modes)
 };
 
 struct Geom {
     int nx, ny, nz;
     float cx, cy, cz;
+    float c0, c1;       // preconditioner M = c0 I - c1 A
 };
 
 template <int VEC>
@@ -76,8 +83,10 @@ __device__ __forceinline__ void stv(float* q, const Vec<VEC>& v) {
 // address; the caller clamps).
 template <int VEC, int MODE>
 __device__ __forceinline__ Vec<VEC> load_p(const Ptrs& p, size_t i, float beta) {
-    if constexpr (MODE == S1_FIRST || MODE == S2_FIRST) {
+    if constexpr (MODE == S1_FIRST || MODE == S2_FIRST || MODE == SZ_FIRST) {
         return ldv<VEC>(p.B + i);
+    } else if constexpr (MODE == SZ) {
+        return ldv<VEC>(p.R + i);
     } else if constexpr (MODE == S1) {
         Vec<VEC> r = ldv<VEC>(p.R + i);
         const Vec<VEC> q = ldv<VEC>(p.Pold + i);
@@ -86,7 +95,7 @@ __device__ __forceinline__ Vec<VEC> load_p(const Ptrs& p, size_t i, float beta) 
         return r;
     } else if constexpr (MODE == S1_B0) {
         return ldv<VEC>(p.R + i);
-    } else if constexpr (MODE == S2) {
+    } else if constexpr (MODE == S2 || MODE == S2P_FIRST) {
         return ldv<VEC>(p.Pnew + i);
     } else {
         return ldv<VEC>(p.X + i);
@@ -204,6 +213,32 @@ __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t 
                     stv<VEC>(p.R + i, rv);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) acc0 = fma((double)rv.f[e], (double)rv.f[e], acc0);
+                }
+            } else if constexpr (MODE == SZ_FIRST || MODE == SZ) {
+                Vec<VEC> zv;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) zv.f[e] = fmaf(-g.c1, ap.f[e], g.c0 * c.f[e]);
+                if (valid) {
+                    stv<VEC>(p.Z + i, zv);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        acc0 = fma((double)c.f[e], (double)zv.f[e], acc0);
+                        if (MODE == SZ_FIRST) acc1 = fma((double)c.f[e], (double)c.f[e], acc1);
+                    }
+                }
+            } else if constexpr (MODE == S2P_FIRST) {
+                const Vec<VEC> bv = ldv<VEC>(p.B + i);
+                Vec<VEC> xn, rn;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    xn.f[e] = alpha * c.f[e];
+                    rn.f[e] = fmaf(-alpha, ap.f[e], bv.f[e]);
+                }
+                if (valid) {
+                    stv<VEC>(p.X + i, xn);
+                    stv<VEC>(p.R + i, rn);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc0 = fma((double)rn.f[e], (double)rn.f[e], acc0);
                 }
             } else {  // S_RES: r = b - A x0
                 const Vec<VEC> bv = ldv<VEC>(p.B + i);

@@ -79,16 +79,17 @@ def test_deposit_signed_multifield_ragged_and_dropped(gpu_lib):
     ((1, 1, 1), (0, 0, 0), (1, 1, 1), 0.3, 2),               # one cell: A = I
     ((64, 1, 1), (0, 0, 0), (1, 1, 1), 0.1, 4),              # 1-D
 ])
-def test_coarse_grain_matches_oracle(gpu_lib, shape, lo, hi, b, steps):
+@pytest.mark.parametrize("precond", [0, 1])  # polynomial-preconditioned CG, plain CG
+def test_coarse_grain_matches_oracle(gpu_lib, shape, lo, hi, b, steps, precond):
     import torch
     cgd = gpu_lib
     box = inputs.HexBox(lo, hi, shape)
     n = 20_000
     p = inputs.uniform_bed(box, n, 2, seed=31, diam=0.01)
-    print(f"case: coarse_grain {shape} b={b} steps={steps}", flush=True)
+    print(f"case: coarse_grain {shape} b={b} steps={steps} precond={precond}", flush=True)
     mesh = cgd.HexMesh(shape, lo, hi)
     field, st = cgd.coarse_grain(mesh, _t(p.pos, torch), _t(p.values, torch), b, steps,
-                                 rtol=1e-7, stats=True)
+                                 rtol=1e-7, stats=True, precond=precond)
     out = field.cpu().numpy()
     ref, dep = O.coarse_grain_hex(p.pos, p.values, lo, hi, shape, b, steps, solver="direct")
     for f in range(2):
@@ -212,3 +213,15 @@ def test_dense_bed_reduced_against_dct(gpu_lib):
     o = out.cpu().numpy()
     for f in range(4):
         assert rel_l2(o[f], ref[f]) <= REL_L2, (f, rel_l2(o[f], ref[f]))
+    # plain CG reaches the same result in more iterations: at dtau/h^2 = 1 the
+    # polynomial preconditioner takes the condition number from 13 to 3.8,
+    # and the CG bound from ~25 to ~12 iterations per step at rtol 1e-6
+    out1, st1 = cgd.coarse_grain(mesh, _t(w.particles.pos, torch), _t(w.particles.values, torch),
+                                 w.bandwidth, w.n_steps, rtol=w.rtol, stats=True, precond=1)
+    o1 = out1.cpu().numpy()
+    for f in range(4):
+        assert rel_l2(o1[f], ref[f]) <= REL_L2
+    it0 = sum(sum(r) for r in st.iters)
+    it1 = sum(sum(r) for r in st1.iters)
+    print(f"iterations: preconditioned {st.iters}, plain {st1.iters}", flush=True)
+    assert it0 <= 0.7 * it1, (it0, it1)
