@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     __shared__ double sh[kWaves];
     const bool lead = blk == 0 && threadIdx.x == 0;
     float alpha = 0.f, beta = 0.f;
-    if constexpr (MODE == SZ) {
+    if constexpr (MODE == SZ || MODE == SZ2) {
         // preconditioned CG: convergence test on r_k . r_k from the previous
         // sweep 2 (or, at k = 0, the residual sweep, which also gave b.b)
         const double rrk = block_sum_fixed(a.P2 + ((size_t)f * 2 + (a.k & 1)) * a.bpf, a.bpf, sh);
@@ -145,11 +145,17 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
         const int zci = t / a.ygroups;
         const int zb = zci * a.zc;
         const int ze = min(zb + a.zc, a.nz);
-        tile_sweep<VEC, TY, MODE, EDGE>(a.p, a.g, (size_t)f * a.cells, xs, yg, zb, ze, lane, alpha, beta, acc0, acc1);
+        if constexpr (MODE == SZ2_FIRST || MODE == SZ2) {
+            if constexpr (!EDGE)
+                tile_precond2<VEC, TY, MODE == SZ2_FIRST>(a.p, a.g, (size_t)f * a.cells, yg, zb, ze, lane, acc0, acc1);
+        } else {
+            tile_sweep<VEC, TY, MODE, EDGE>(a.p, a.g, (size_t)f * a.cells, xs, yg, zb, ze, lane, alpha, beta, acc0,
+                                            acc1);
+        }
     }
 
     // block reduction of the float64 partials, fixed order
-    constexpr bool kTwo = (MODE == S1_FIRST || MODE == S_RES || MODE == SZ_FIRST);
+    constexpr bool kTwo = (MODE == S1_FIRST || MODE == S_RES || MODE == SZ_FIRST || MODE == SZ2_FIRST);
     for (int o = 32; o > 0; o >>= 1) {
         acc0 += __shfl_xor(acc0, o);
         if (kTwo) acc1 += __shfl_xor(acc1, o);
@@ -173,9 +179,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
             if (MODE == S1_FIRST) a.P1[((size_t)f * 2 + 1) * a.bpf + blk] = t1;
         } else if constexpr (MODE == S2_FIRST || MODE == S2 || MODE == S2P_FIRST) {
             a.P2[((size_t)f * 2 + ((a.k + 1) & 1)) * a.bpf + blk] = t0;
-        } else if constexpr (MODE == SZ_FIRST || MODE == SZ) {
+        } else if constexpr (MODE == SZ_FIRST || MODE == SZ || MODE == SZ2_FIRST || MODE == SZ2) {
             a.P3[((size_t)f * 2 + (a.k & 1)) * a.bpf + blk] = t0;
-            if (MODE == SZ_FIRST) a.P1[((size_t)f * 2 + 1) * a.bpf + blk] = t1;
+            if (MODE == SZ_FIRST || MODE == SZ2_FIRST) a.P1[((size_t)f * 2 + 1) * a.bpf + blk] = t1;
         } else {  // S_RES: r_0 . r_0 and b . b
             a.P2[((size_t)f * 2 + 0) * a.bpf + blk] = t0;
             a.P1[((size_t)f * 2 + 1) * a.bpf + blk] = t1;
@@ -307,6 +313,8 @@ void launch_sweep_t(int mode, const Plan& p, const SweepArgs& a, hipStream_t s) 
         case SZ_FIRST: hipLaunchKernelGGL((k_sweep<VEC, TY, SZ_FIRST, EDGE>), grid, block, 0, s, a); break;
         case SZ: hipLaunchKernelGGL((k_sweep<VEC, TY, SZ, EDGE>), grid, block, 0, s, a); break;
         case S2P_FIRST: hipLaunchKernelGGL((k_sweep<VEC, TY, S2P_FIRST, EDGE>), grid, block, 0, s, a); break;
+        case SZ2_FIRST: hipLaunchKernelGGL((k_sweep<VEC, TY, SZ2_FIRST, EDGE>), grid, block, 0, s, a); break;
+        case SZ2: hipLaunchKernelGGL((k_sweep<VEC, TY, SZ2, EDGE>), grid, block, 0, s, a); break;
         default: hipLaunchKernelGGL((k_sweep<VEC, TY, S_RES, EDGE>), grid, block, 0, s, a); break;
     }
 }
@@ -417,14 +425,33 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     // d = lmax - 1: c0 = 8 s / (2 s^2 - d^2), c1 = 8 / (2 s^2 - d^2); the
     // condition number drops from lmax to (1 + e) / (1 - e), e = 1 / T_2(s / d)
     // (13 -> 3.8 at dtau / h^2 = 1).
+    //
+    // Where one wave covers a row (no EDGE tiles), the degree-2 polynomial is
+    // used instead (residual polynomial T_3; the sweep keeps two halo rows and
+    // planes, tile_precond2): with s, d as above, c0 = 2 (12 s^2 - 3 d^2) /
+    // (4 s^3 - 3 s d^2), c1 = -48 / (4 s^2 - 3 d^2), c2 = 32 / (4 s^3 - 3 s d^2);
+    // condition number 13 -> 2.1 at dtau / h^2 = 1.  The coefficients stay
+    // finite as d -> 0 (tiny dtau: M -> a multiple of the identity).
     const bool pcg = da.precond == 0;
+    const int deg = (pcg && !p.edge && p.xsegs == 1 && g.nx == 64 * p.vec) ? 2 : 1;
     a.pcg = pcg ? 1 : 0;
     {
         const double lmax = 1.0 + 4.0 * ((double)a.g.cx + (double)a.g.cy + (double)a.g.cz);
-        const double sp = lmax + 1.0, dm = lmax - 1.0, den = 2.0 * sp * sp - dm * dm;
-        a.g.c0 = (float)(8.0 * sp / den);
-        a.g.c1 = (float)(8.0 / den);
+        const double sp = lmax + 1.0, dm = lmax - 1.0;
+        if (deg == 1) {
+            const double den = 2.0 * sp * sp - dm * dm;
+            a.g.c0 = (float)(8.0 * sp / den);
+            a.g.c1 = (float)(-8.0 / den);
+            a.g.c2 = 0.f;
+        } else {
+            const double den3 = 4.0 * sp * sp * sp - 3.0 * sp * dm * dm;
+            a.g.c0 = (float)(2.0 * (12.0 * sp * sp - 3.0 * dm * dm) / den3);
+            a.g.c1 = (float)(-48.0 / (4.0 * sp * sp - 3.0 * dm * dm));
+            a.g.c2 = (float)(32.0 / den3);
+        }
     }
+    const int mode_z_first = deg == 2 ? SZ2_FIRST : SZ_FIRST;
+    const int mode_z = deg == 2 ? SZ2 : SZ;
 
     const int sum_bpf = (int)std::min<int64_t>(1024, (cells + kBlock - 1) / kBlock);
     double* d_sum_part = d_P2;  // free outside the solves
@@ -479,7 +506,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             a.k = it;
             a.p.R = R;
             int t0 = first ? -1 : timing_begin(&m->timing, s);
-            launch_sweep(first ? SZ_FIRST : SZ, p, a, s);
+            launch_sweep(first ? mode_z_first : mode_z, p, a, s);
             if (!first) timing_end(&m->timing, t0, 5, 8.0 * (double)F * cells, s, tag);
             a.p.R = Z;
             a.p.Pold = (it & 1) ? PA : PB;

@@ -26,12 +26,16 @@ namespace stencil {
 //   S2_FIRST  x = alpha b, r = b - alpha A b;  r.r
 //   S2        x += alpha p, r -= alpha A p;   r.r
 //   S_RES     r = b - A x;           r.r and b.b
-// Preconditioned CG (z = M r with the polynomial M = c0 I - c1 A; the S1
-// modes then read z through Ptrs::R):
-//   SZ_FIRST  z = M b;               writes z; b.z and b.b
-//   SZ        z = M r;               writes z; r.z
+// Preconditioned CG (z = M r with a polynomial M = c0 I + c1 A + c2 A^2; the
+// S1 modes then read z through Ptrs::R):
+//   SZ_FIRST  z = M b;               writes z; b.z and b.b   (degree 1)
+//   SZ        z = M r;               writes z; r.z           (degree 1)
 //   S2P_FIRST x = alpha p, r = b - alpha A p;  r.r   (zero initial guess)
-enum Mode { S1_FIRST = 0, S1 = 1, S2_FIRST = 2, S2 = 3, S_RES = 4, S1_B0 = 5, SZ_FIRST = 6, SZ = 7, S2P_FIRST = 8 };
+//   SZ2_FIRST, SZ2: as SZ_FIRST, SZ with the degree-2 polynomial (tile_precond2)
+enum Mode {
+    S1_FIRST = 0, S1 = 1, S2_FIRST = 2, S2 = 3, S_RES = 4, S1_B0 = 5,
+    SZ_FIRST = 6, SZ = 7, S2P_FIRST = 8, SZ2_FIRST = 9, SZ2 = 10
+};
 
 struct Ptrs {
     const float* B;     // right-hand side of the step
@@ -45,7 +49,7 @@ struct Ptrs {
 struct Geom {
     int nx, ny, nz;
     float cx, cy, cz;
-    float c0, c1;       // preconditioner M = c0 I - c1 A
+    float c0, c1, c2;   // preconditioner M = c0 I + c1 A + c2 A^2
 };
 
 template <int VEC>
@@ -217,7 +221,7 @@ __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t 
             } else if constexpr (MODE == SZ_FIRST || MODE == SZ) {
                 Vec<VEC> zv;
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) zv.f[e] = fmaf(-g.c1, ap.f[e], g.c0 * c.f[e]);
+                for (int e = 0; e < VEC; ++e) zv.f[e] = fmaf(g.c1, ap.f[e], g.c0 * c.f[e]);
                 if (valid) {
                     stv<VEC>(p.Z + i, zv);
 #pragma unroll
@@ -262,6 +266,128 @@ __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t 
         if constexpr (EDGE) {
 #pragma unroll
             for (int j = 0; j < TY; ++j) ec[j] = en[j];
+        }
+    }
+}
+
+// (A v) along one row of VEC-wide lanes: c the row itself, yl / yh the rows
+// below / above in the same plane, zl / zh the same row in the planes below /
+// above; a missing neighbour (wall) is replaced by the cell itself.  The row
+// is covered by one wave (x-neighbours of the end elements from the adjacent
+// lanes; walls at lanes 0 and 63).
+template <int VEC>
+__device__ __forceinline__ Vec<VEC> apply_row(const Geom& g, const Vec<VEC>& c, const Vec<VEC>& yl,
+                                              const Vec<VEC>& yh, const Vec<VEC>& zl, const Vec<VEC>& zh,
+                                              bool hyd, bool hyu, bool hzd, bool hzu, bool wall_l, bool wall_r) {
+    const float lft = __shfl_up(c.f[VEC - 1], 1);
+    const float rgt = __shfl_down(c.f[0], 1);
+    Vec<VEC> out;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        const float ce = c.f[e];
+        const float l = e > 0 ? c.f[e - 1] : (wall_l ? ce : lft);
+        const float r = e + 1 < VEC ? c.f[e + 1] : (wall_r ? ce : rgt);
+        const float ylo = hyd ? yl.f[e] : ce;
+        const float yhi = hyu ? yh.f[e] : ce;
+        const float zlo = hzd ? zl.f[e] : ce;
+        const float zhi = hzu ? zh.f[e] : ce;
+        const float c2 = ce + ce;
+        float v = fmaf(g.cx, (c2 - l) - r, ce);
+        v = fmaf(g.cy, (c2 - ylo) - yhi, v);
+        out.f[e] = fmaf(g.cz, (c2 - zlo) - zhi, v);
+    }
+    return out;
+}
+
+// Preconditioning sweep of degree 2: z = c0 r + c1 A r + c2 A (A r), both
+// products matrix-free.  The wave marches over z keeping r for planes z ..
+// z+2 with two halo rows on each side and A r for planes z-1 .. z+1 with one
+// halo row: when plane z+2 of r arrives, A r of plane z+1 is formed, and then
+// A (A r) of plane z.  Values at clamped rows or planes beyond a wall are
+// never used (the wall rule substitutes the cell itself).  One wave covers a
+// row (nx = 64 VEC).  FIRST: the input is b (zero initial guess) and b.b is
+// accumulated as well.
+template <int VEC, int TY, bool FIRST>
+__device__ __forceinline__ void tile_precond2(const Ptrs& p, const Geom& g, size_t fo, int yg, int zb, int ze,
+                                              int lane, double& acc0, double& acc1) {
+    constexpr int RR = TY + 4;  // rows of r: y0 - 2 .. y0 + TY + 1
+    constexpr int RA = TY + 2;  // rows of A r: y0 - 1 .. y0 + TY
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int x0 = lane * VEC;
+    const bool wall_l = x0 == 0, wall_r = x0 + VEC >= nx;
+    const int y0 = yg * TY;
+    const size_t plane = (size_t)nx * ny;
+    const size_t base = fo + x0;
+    const float* src = FIRST ? p.B : p.R;
+    auto at = [&](int z, int y) -> size_t {
+        z = z < 0 ? 0 : (z >= nz ? nz - 1 : z);
+        y = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+        return base + (size_t)z * plane + (size_t)y * nx;
+    };
+    auto load_plane = [&](Vec<VEC>* dst, int z) {
+#pragma unroll
+        for (int i = 0; i < RR; ++i) dst[i] = ldv<VEC>(src + at(z, y0 - 2 + i));
+    };
+    // A r for the RA rows of plane q, from r planes q-1 (lo), q (c), q+1 (hi)
+    auto ar_plane = [&](Vec<VEC>* dst, const Vec<VEC>* lo, const Vec<VEC>* c, const Vec<VEC>* hi, int q) {
+        const bool hzd = q > 0, hzu = q + 1 < nz;
+#pragma unroll
+        for (int jj = 0; jj < RA; ++jj) {
+            const int y = y0 - 1 + jj;
+            dst[jj] = apply_row<VEC>(g, c[jj + 1], c[jj], c[jj + 2], lo[jj + 1], hi[jj + 1], y > 0, y + 1 < ny, hzd,
+                                     hzu, wall_l, wall_r);
+        }
+    };
+
+    Vec<VEC> r0[RR], r1[RR], r2[RR];  // r of planes z, z+1, z+2 (in the loop)
+    Vec<VEC> a0[RA], a1[RA], a2[RA];  // A r of planes z-1, z, z+1
+    {
+        Vec<VEC> rm[RR];
+        load_plane(rm, zb - 2);
+        load_plane(r0, zb - 1);
+        load_plane(r1, zb);
+        load_plane(r2, zb + 1);
+        ar_plane(a0, rm, r0, r1, zb - 1);
+        ar_plane(a1, r0, r1, r2, zb);
+        // shift so that r0, r1 hold planes zb, zb + 1
+#pragma unroll
+        for (int i = 0; i < RR; ++i) {
+            r0[i] = r1[i];
+            r1[i] = r2[i];
+        }
+    }
+    for (int z = zb; z < ze; ++z) {
+        load_plane(r2, z + 2);
+        ar_plane(a2, r0, r1, r2, z + 1);
+        const bool hzd = z > 0, hzu = z + 1 < nz;
+#pragma unroll
+        for (int j = 0; j < TY; ++j) {
+            const int y = y0 + j;
+            const Vec<VEC> aar = apply_row<VEC>(g, a1[j + 1], a1[j], a1[j + 2], a0[j + 1], a2[j + 1], y > 0,
+                                                y + 1 < ny, hzd, hzu, wall_l, wall_r);
+            const Vec<VEC>& rv = r0[j + 2];
+            Vec<VEC> zv;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                zv.f[e] = fmaf(g.c2, aar.f[e], fmaf(g.c1, a1[j + 1].f[e], g.c0 * rv.f[e]));
+            if (y < ny) {
+                stv<VEC>(p.Z + at(z, y), zv);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    acc0 = fma((double)rv.f[e], (double)zv.f[e], acc0);
+                    if (FIRST) acc1 = fma((double)rv.f[e], (double)rv.f[e], acc1);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RR; ++i) {
+            r0[i] = r1[i];
+            r1[i] = r2[i];
+        }
+#pragma unroll
+        for (int jj = 0; jj < RA; ++jj) {
+            a0[jj] = a1[jj];
+            a1[jj] = a2[jj];
         }
     }
 }
