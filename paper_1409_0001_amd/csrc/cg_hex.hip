@@ -40,10 +40,16 @@ struct SweepArgs {
     Ptrs p;
     Geom g;
     CgCtl c;
-    double* P1;         // [F][2][bpf]: slot 0 p.Ap, slot 1 b.b
-    double* P2;         // [F][2][bpf]: r.r of r_k in slot k % 2
-    double* P3;         // [F][2][bpf]: preconditioned CG, r.z of r_k in slot k % 2
+    // Block partial sums, [F][2][pstride] each; a sweep writes one entry per
+    // block (bpf of its own plan) and the next sweep's prologue adds the
+    // bpf_in entries the producing sweep wrote (each kind of sweep has its
+    // own tile plan).
+    double* P1;         // slot 0 p.Ap, slot 1 b.b
+    double* P2;         // r.r of r_k in slot k % 2
+    double* P3;         // preconditioned CG: r.z of r_k in slot k % 2
+    int pstride, bpf_in;
     int pcg;            // 1: preconditioned CG (the S1 modes read z; alpha, beta from r.z)
+    int x0_zero;        // the step started from a zero initial guess
     int64_t cells;
     int nx, ny, nz;
     int xsegs, ygroups, zc;
@@ -69,9 +75,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     if constexpr (MODE == SZ || MODE == SZ2) {
         // preconditioned CG: convergence test on r_k . r_k from the previous
         // sweep 2 (or, at k = 0, the residual sweep, which also gave b.b)
-        const double rrk = block_sum_fixed(a.P2 + ((size_t)f * 2 + (a.k & 1)) * a.bpf, a.bpf, sh);
+        const double rrk = block_sum_fixed(a.P2 + ((size_t)f * 2 + (a.k & 1)) * a.pstride, a.bpf_in, sh);
         double bb;
-        if (a.k == 0) bb = block_sum_fixed(a.P1 + ((size_t)f * 2 + 1) * a.bpf, a.bpf, sh);
+        if (a.k == 0) bb = block_sum_fixed(a.P1 + ((size_t)f * 2 + 1) * a.pstride, a.bpf_in, sh);
         else bb = stf->bb;
         if (lead) {
             stf->rr_par[a.k & 1] = rrk;
@@ -80,12 +86,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
         if (check_stop(a.c, f, a.k, rrk, bb, lead)) return;
     } else if ((MODE == S1 || MODE == S1_B0) && a.pcg) {
         // rho_k = r_k . z_k from the preconditioning sweep
-        const double rho = block_sum_fixed(a.P3 + ((size_t)f * 2 + (a.k & 1)) * a.bpf, a.bpf, sh);
+        const double rho = block_sum_fixed(a.P3 + ((size_t)f * 2 + (a.k & 1)) * a.pstride, a.bpf_in, sh);
         double bb = 0.0;
-        if (MODE == S1_B0) bb = block_sum_fixed(a.P1 + ((size_t)f * 2 + 1) * a.bpf, a.bpf, sh);
+        // zero initial guess: b.b comes from the first preconditioning sweep
+        // (a warm start had it from the residual sweep, in the SZ prologue)
+        const bool need_bb = MODE == S1_B0 && a.x0_zero;
+        if (need_bb) bb = block_sum_fixed(a.P1 + ((size_t)f * 2 + 1) * a.pstride, a.bpf_in, sh);
         if (lead) {
             stf->rho_par[a.k & 1] = rho;
-            if (MODE == S1_B0) {
+            if (need_bb) {
                 stf->bb = bb;
                 stf->rr_par[0] = bb;
             }
@@ -93,9 +102,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
         if (MODE == S1) beta = (float)(rho / stf->rho_par[(a.k - 1) & 1]);
     } else if constexpr (MODE == S1 || MODE == S1_B0) {
         // r_k . r_k from the previous sweep 2 (or the residual sweep)
-        const double rrk = block_sum_fixed(a.P2 + ((size_t)f * 2 + (a.k & 1)) * a.bpf, a.bpf, sh);
+        const double rrk = block_sum_fixed(a.P2 + ((size_t)f * 2 + (a.k & 1)) * a.pstride, a.bpf_in, sh);
         double bb;
-        if constexpr (MODE == S1_B0) bb = block_sum_fixed(a.P1 + ((size_t)f * 2 + 1) * a.bpf, a.bpf, sh);
+        if constexpr (MODE == S1_B0) bb = block_sum_fixed(a.P1 + ((size_t)f * 2 + 1) * a.pstride, a.bpf_in, sh);
         else bb = stf->bb;
         if (lead) {
             stf->rr_par[a.k & 1] = rrk;
@@ -106,15 +115,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     } else if constexpr (MODE == S2P_FIRST) {
         // preconditioned CG, zero initial guess: alpha = rho_0 / p.Ap; b = 0 or
         // a breakdown gives alpha = 0, i.e. x = 0 and r = b
-        const double pap = block_sum_fixed(a.P1 + ((size_t)f * 2 + 0) * a.bpf, a.bpf, sh);
+        const double pap = block_sum_fixed(a.P1 + ((size_t)f * 2 + 0) * a.pstride, a.bpf_in, sh);
         const double bb = stf->bb, rho = stf->rho_par[0];
         const bool broken = !isfinite(bb) || !isfinite(pap) || !isfinite(rho) || (bb > 0.0 && !(pap > 0.0));
         if (lead && broken) finish_field(a.c, f, CGD_E_BREAKDOWN);
         alpha = (broken || bb == 0.0) ? 0.f : (float)(rho / pap);
     } else if constexpr (MODE == S2 || MODE == S2_FIRST) {
-        const double pap = block_sum_fixed(a.P1 + ((size_t)f * 2 + 0) * a.bpf, a.bpf, sh);
+        const double pap = block_sum_fixed(a.P1 + ((size_t)f * 2 + 0) * a.pstride, a.bpf_in, sh);
         if constexpr (MODE == S2_FIRST) {
-            const double bb = block_sum_fixed(a.P1 + ((size_t)f * 2 + 1) * a.bpf, a.bpf, sh);
+            const double bb = block_sum_fixed(a.P1 + ((size_t)f * 2 + 1) * a.pstride, a.bpf_in, sh);
             const bool broken = !isfinite(bb) || !isfinite(pap) || (bb > 0.0 && !(pap > 0.0));
             if (lead) {
                 stf->bb = bb;
@@ -175,16 +184,16 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
         }
         // where each mode's sums go (see SweepArgs)
         if constexpr (MODE == S1_FIRST || MODE == S1 || MODE == S1_B0) {
-            a.P1[((size_t)f * 2 + 0) * a.bpf + blk] = t0;
-            if (MODE == S1_FIRST) a.P1[((size_t)f * 2 + 1) * a.bpf + blk] = t1;
+            a.P1[((size_t)f * 2 + 0) * a.pstride + blk] = t0;
+            if (MODE == S1_FIRST) a.P1[((size_t)f * 2 + 1) * a.pstride + blk] = t1;
         } else if constexpr (MODE == S2_FIRST || MODE == S2 || MODE == S2P_FIRST) {
-            a.P2[((size_t)f * 2 + ((a.k + 1) & 1)) * a.bpf + blk] = t0;
+            a.P2[((size_t)f * 2 + ((a.k + 1) & 1)) * a.pstride + blk] = t0;
         } else if constexpr (MODE == SZ_FIRST || MODE == SZ || MODE == SZ2_FIRST || MODE == SZ2) {
-            a.P3[((size_t)f * 2 + (a.k & 1)) * a.bpf + blk] = t0;
-            if (MODE == SZ_FIRST || MODE == SZ2_FIRST) a.P1[((size_t)f * 2 + 1) * a.bpf + blk] = t1;
+            a.P3[((size_t)f * 2 + (a.k & 1)) * a.pstride + blk] = t0;
+            if (MODE == SZ_FIRST || MODE == SZ2_FIRST) a.P1[((size_t)f * 2 + 1) * a.pstride + blk] = t1;
         } else {  // S_RES: r_0 . r_0 and b . b
-            a.P2[((size_t)f * 2 + 0) * a.bpf + blk] = t0;
-            a.P1[((size_t)f * 2 + 1) * a.bpf + blk] = t1;
+            a.P2[((size_t)f * 2 + 0) * a.pstride + blk] = t0;
+            a.P1[((size_t)f * 2 + 1) * a.pstride + blk] = t1;
         }
     }
 }
@@ -204,11 +213,12 @@ __global__ void k_zero_if_rhs_zero(float* X, int64_t cells, const CgField* st) {
 // restarts from zero.  One block per field sums the two partial arrays of
 // the residual sweep in the fixed order; on rejection the r.r partials are
 // replaced by the b.b partials, so the following sweeps see r = b.
-__global__ __launch_bounds__(kBlock) void k_warm_check(const double* P1, double* P2, int bpf, int32_t* fb_row) {
+__global__ __launch_bounds__(kBlock) void k_warm_check(const double* P1, double* P2, int pstride, int bpf,
+                                                       int32_t* fb_row) {
     const int f = blockIdx.x;
     __shared__ double sh[kWaves];
-    double* rr_p = P2 + ((size_t)f * 2 + 0) * bpf;
-    const double* bb_p = P1 + ((size_t)f * 2 + 1) * bpf;
+    double* rr_p = P2 + ((size_t)f * 2 + 0) * pstride;
+    const double* bb_p = P1 + ((size_t)f * 2 + 1) * pstride;
     const double rr = block_sum_fixed(rr_p, bpf, sh);
     const double bb = block_sum_fixed(bb_p, bpf, sh);
     const bool fb = !(rr <= bb);
@@ -361,12 +371,26 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     int vec = pick_vec(g.nx);
     const uintptr_t align = (uintptr_t)da.field | (uintptr_t)(da.x0_mode == 2 ? da.x0 : nullptr);
     if (align % (4 * vec)) vec = 1;
+    // Tile plans: p for the update sweeps (sweep 2, residual), p1 for the
+    // direction sweeps (sweep 1), pz for the preconditioning sweeps.  With
+    // 4 cells per lane, sweep 1 takes z chunks twice as deep and the
+    // preconditioning sweep 4 rows per wave (its two halo rows then cost 1.5x
+    // instead of 2x in loads); both measured faster on the dense bed.
     Plan p = default_plan(g, F, vec);
-    if (const char* e = getenv("CGD_HEX_TILE")) {  // "TY,ZC" for tuning runs
-        int ty = 0, zc = 0;
-        if (sscanf(e, "%d,%d", &ty, &zc) == 2 && ty_supported(vec, ty) && zc > 0)
-            p = make_plan(g, F, vec, ty, zc);
-    }
+    Plan p1 = vec == 4 ? make_plan(g, F, vec, p.ty, 2 * p.zc) : p;
+    Plan pz = vec == 4 ? make_plan(g, F, vec, 4, p.zc) : p;
+    auto tile_env = [&](const char* name, Plan& q) {  // "TY,ZC" for tuning runs
+        if (const char* e = getenv(name)) {
+            int ty = 0, zc = 0;
+            if (sscanf(e, "%d,%d", &ty, &zc) == 2 && ty_supported(vec, ty) && zc > 0) q = make_plan(g, F, vec, ty, zc);
+        }
+    };
+    tile_env("CGD_HEX_TILE", p);
+    tile_env("CGD_HEX_TILE", p1);
+    tile_env("CGD_HEX_TILE", pz);
+    tile_env("CGD_HEX_TILE1", p1);
+    tile_env("CGD_HEX_TILE2", p);
+    tile_env("CGD_HEX_TILEZ", pz);
     const size_t small = small_bytes(F, (int)max_bpf(g, F));
     cgd_status rc = ensure_workspace(m, small + 5 * (size_t)F * cells * sizeof(float));
     if (rc != CGD_OK) return rc;
@@ -406,12 +430,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     a.g.cx = (float)(dtau / (g.h[0] * g.h[0]));
     a.g.cy = (float)(dtau / (g.h[1] * g.h[1]));
     a.g.cz = (float)(dtau / (g.h[2] * g.h[2]));
-    a.xsegs = p.xsegs;
-    a.ygroups = p.ygroups;
-    a.zc = p.zc;
-    a.wpf = p.wpf;
-    a.bpf = p.bpf;
-    a.nblocks = p.nblocks;
+    a.pstride = (int)max_bpf(g, F);
     a.c = ctl;
     a.P1 = d_P1;
     a.P2 = d_P2;
@@ -453,6 +472,24 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     const int mode_z_first = deg == 2 ? SZ2_FIRST : SZ_FIRST;
     const int mode_z = deg == 2 ? SZ2 : SZ;
 
+    // One sweep: its own plan, and the block count of the sweep whose
+    // partial sums its prologue adds.
+    auto launch = [&](int mode) {
+        const bool is_z = mode == SZ_FIRST || mode == SZ || mode == SZ2_FIRST || mode == SZ2;
+        const bool is_1 = mode == S1_FIRST || mode == S1 || mode == S1_B0;
+        const Plan& q = is_z ? pz : (is_1 ? p1 : p);
+        a.xsegs = q.xsegs;
+        a.ygroups = q.ygroups;
+        a.zc = q.zc;
+        a.wpf = q.wpf;
+        a.bpf = q.bpf;
+        a.nblocks = q.nblocks;
+        if (is_z) a.bpf_in = p.bpf;                   // r.r (and b.b) of sweep 2 / the residual sweep
+        else if (is_1) a.bpf_in = a.pcg ? pz.bpf : p.bpf;  // r.z of the preconditioning sweep, or r.r
+        else a.bpf_in = p1.bpf;                       // p.Ap (and b.b) of sweep 1
+        launch_sweep(mode, q, a, s);
+    };
+
     const int sum_bpf = (int)std::min<int64_t>(1024, (cells + kBlock - 1) / kBlock);
     double* d_sum_part = d_P2;  // free outside the solves
 
@@ -472,13 +509,14 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         hipLaunchKernelGGL(k_cg_step_init, dim3(1), dim3(64), 0, s, ctl.st, F, ctl.ndone,
                            ctl.status + step * CGD_MAX_FIELDS);
         const bool use_x0 = (da.x0_mode == 1) || (da.x0_mode == 2 && step == 0) || da.x0_mode == 3;
+        a.x0_zero = use_x0 ? 0 : 1;
         int it0;
         a.k = 0;
         if (!use_x0 && pcg) {
             it0 = 0;  // iteration 0 (z = M b, p = z, x = alpha p) is enqueued by the loop
         } else if (!use_x0) {
-            launch_sweep(S1_FIRST, p, a, s);
-            launch_sweep(S2_FIRST, p, a, s);
+            launch(S1_FIRST);
+            launch(S2_FIRST);
             it0 = 1;
         } else {
             if (da.x0_mode == 3) {
@@ -490,10 +528,10 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
                 const float* x0 = da.x0_mode == 1 ? cur : da.x0;
                 CGD_HIP_TRY(hipMemcpyAsync(nxt, x0, (size_t)F * cells * sizeof(float), hipMemcpyDeviceToDevice, s));
             }
-            launch_sweep(S_RES, p, a, s);
+            launch(S_RES);
             if (da.x0_mode == 3) {
                 int32_t* fb_row = reinterpret_cast<int32_t*>(base + kOffFallback) + step * CGD_MAX_FIELDS;
-                hipLaunchKernelGGL(k_warm_check, dim3(F), dim3(kBlock), 0, s, d_P1, d_P2, p.bpf, fb_row);
+                hipLaunchKernelGGL(k_warm_check, dim3(F), dim3(kBlock), 0, s, d_P1, d_P2, a.pstride, p.bpf, fb_row);
                 const int blocks = (int)std::min<int64_t>(2048, (cells + kBlock - 1) / kBlock);
                 hipLaunchKernelGGL(k_warm_reset, dim3(blocks, F), dim3(kBlock), 0, s, nxt, R, cur, cells, fb_row);
             }
@@ -506,17 +544,17 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             a.k = it;
             a.p.R = R;
             int t0 = first ? -1 : timing_begin(&m->timing, s);
-            launch_sweep(first ? mode_z_first : mode_z, p, a, s);
+            launch(first ? mode_z_first : mode_z);
             if (!first) timing_end(&m->timing, t0, 5, 8.0 * (double)F * cells, s, tag);
             a.p.R = Z;
             a.p.Pold = (it & 1) ? PA : PB;
             a.p.Pnew = (it & 1) ? PB : PA;
             int t1 = first ? -1 : timing_begin(&m->timing, s);
-            launch_sweep(it == 0 ? S1_B0 : S1, p, a, s);
+            launch(it == 0 ? S1_B0 : S1);
             if (!first) timing_end(&m->timing, t1, 0, 12.0 * (double)F * cells, s, tag);
             a.p.R = R;
             int t2 = first ? -1 : timing_begin(&m->timing, s);
-            launch_sweep(first ? S2P_FIRST : S2, p, a, s);
+            launch(first ? S2P_FIRST : S2);
             if (!first) timing_end(&m->timing, t2, 1, 20.0 * (double)F * cells, s, tag);
         };
         auto enqueue = [&](int it) {
@@ -533,10 +571,10 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             a.k = it;
             const int64_t tag = (int64_t)step * 65536 + it;
             int t1 = timing_begin(&m->timing, s);
-            launch_sweep(mode1, p, a, s);
+            launch(mode1);
             timing_end(&m->timing, t1, 0, 12.0 * (double)F * cells, s, tag);
             int t2 = timing_begin(&m->timing, s);
-            launch_sweep(S2, p, a, s);
+            launch(S2);
             timing_end(&m->timing, t2, 1, 20.0 * (double)F * cells, s, tag);
         };
         int it_end = it0;
@@ -544,8 +582,8 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         if (rc2 != CGD_OK) return rc2;
         CgCtl c2 = ctl;
         c2.step = step;
-        hipLaunchKernelGGL(k_cg_step_end, dim3(F), dim3(kBlock), 0, s, c2, d_P2 + (size_t)(it_end & 1) * p.bpf,
-                           (size_t)2 * p.bpf, p.bpf, it_end);
+        hipLaunchKernelGGL(k_cg_step_end, dim3(F), dim3(kBlock), 0, s, c2, d_P2 + (size_t)(it_end & 1) * a.pstride,
+                           (size_t)2 * a.pstride, p.bpf, it_end);
         if (use_x0) {
             int blocks = (int)std::min<int64_t>(2048, (cells + kBlock - 1) / kBlock);
             hipLaunchKernelGGL(k_zero_if_rhs_zero, dim3(blocks, F), dim3(kBlock), 0, s, nxt, cells, ctl.st);
