@@ -185,10 +185,12 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F,
  * three drag components), each field diffused on its own (Section 3.2.1).
  *
  * Deposition follows cgd_deposit per snapshot (its own fixed-point scale per
- * snapshot and field).  All n_snap * F right-hand sides are then solved by
- * zero-guess CG (float32 vectors, float64 inner products, same stencil and
- * stopping rule as cgd_diffuse) in ONE persistent launch in which each
- * workgroup takes one right-hand side at a time from a device counter.  The
+ * snapshot and field).  All n_snap * F right-hand sides are then solved from
+ * a zero initial guess by CG preconditioned with the degree-2 Chebyshev
+ * polynomial of the operator (o->precond = 1: plain CG), with float32
+ * vectors, float64 inner products, and the stencil and stopping rule of
+ * cgd_diffuse, in ONE persistent launch in which each workgroup solves its
+ * share of the right-hand sides one after the other.  The
  * call is captured in a hipGraph on first use for a given argument set and
  * replayed afterwards; the tile shape is chosen by cgd_autotune_batched (run
  * automatically on first use).
@@ -199,7 +201,7 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F,
  *  pos:     device float32 [offsets[n_snap], 3]
  *  values:  device float32 [F, offsets[n_snap]]
  *  fields:  device float32 [n_snap, F, cells], written
- *  o:       rtol / max_iter as in cgd_diffuse; x0_mode must be 0
+ *  o:       rtol / max_iter / precond as in cgd_diffuse; x0_mode must be 0
  *  iters:   HOST int32 [n_snap, F, n_steps] or NULL: CG iterations
  * Hex meshes with nx in {64, 128, 256} only (CGD_E_UNSUPPORTED otherwise).
  * The call waits for its stream before returning. */

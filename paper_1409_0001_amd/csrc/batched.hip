@@ -145,7 +145,8 @@ __global__ __launch_bounds__(kDBlock) void k_bfinalize(BDep d) {
 
 struct BSolve {
     float* fields;      // [n_rhs][cells]: in deposited, out diffused
-    float* ws;          // [grid][4][cells]
+    float* ws;          // [grid][5][cells]
+    int pcg;            // 1: CG preconditioned by the degree-2 polynomial (Geom c0, c1, c2)
     int n_rhs;
     int64_t cells;
     Geom g;
@@ -204,6 +205,18 @@ __device__ inline void wg_sweep(const BSolve& a, const Ptrs& p, float alpha, flo
     s1 = acc1;
 }
 
+// z = M r over the workgroup's grid (one wave per row), r.z (and r.r when FIRST).
+template <int VEC, int TY, int NW, bool FIRST>
+__device__ inline void wg_precond(const BSolve& a, const Ptrs& p, double& s0, double& s1, double (*sh)[2]) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int t = wave; t < a.ygroups; t += NW)
+        tile_precond2<VEC, TY, FIRST>(p, a.g, 0, t, 0, a.g.nz, lane, acc0, acc1);
+    wg_sum2<NW>(acc0, acc1, sh);
+    s0 = acc0;
+    s1 = acc1;
+}
+
 // Right-hand sides are dealt to workgroups statically (rhs = blockIdx.x,
 // blockIdx.x + gridDim.x, ...), so every loop of this kernel is controlled by
 // wave-uniform values: no lane of a wave ever waits at a barrier for another
@@ -212,17 +225,63 @@ template <int VEC, int TY, int NW>
 __global__ __launch_bounds__(64 * NW) void k_batched_cg(BSolve a) {
     __shared__ double sh[NW][2];
     const size_t cells = (size_t)a.cells;
-    float* W0 = a.ws + (size_t)blockIdx.x * 4 * cells;
+    float* W0 = a.ws + (size_t)blockIdx.x * 5 * cells;
     float* R = W0 + cells;
     float* PA = R + cells;
     float* PB = PA + cells;
+    float* Z = PB + cells;
     for (int rhs = blockIdx.x; rhs < a.n_rhs; rhs += gridDim.x) {
         float* field = a.fields + (size_t)rhs * cells;
         float* cur = field;
         float* nxt = W0;
         int worst = CGD_OK;
         for (int step = 0; step < a.n_steps; ++step) {
-            Ptrs p{cur, R, nullptr, nullptr, nxt};
+            if (a.pcg) {
+                // preconditioned CG from x = 0: z = M b, p = z, x = alpha p, r = b - alpha A p
+                Ptrs p{cur, R, nullptr, PA, nxt, Z};
+                Ptrs q = p;  // the direction sweeps read z through Ptrs::R
+                q.R = Z;
+                double rho, bb, pap, rr, dummy;
+                wg_precond<VEC, TY, NW, true>(a, p, rho, bb, sh);
+                wg_sweep<VEC, TY, NW, S1_B0>(a, q, 0.f, 0.f, pap, dummy, sh);
+                bool broken = !isfinite(bb) || !isfinite(pap) || !isfinite(rho) || (bb > 0.0 && !(pap > 0.0));
+                float alpha = (broken || bb == 0.0) ? 0.f : (float)(rho / pap);
+                wg_sweep<VEC, TY, NW, S2P_FIRST>(a, p, alpha, 0.f, rr, dummy, sh);
+                int k = 1;
+                int st = CGD_OK;
+                for (;;) {
+                    if (broken || !isfinite(rr)) {
+                        st = CGD_E_BREAKDOWN;
+                        break;
+                    }
+                    if (rr <= a.rtol2 * bb) break;
+                    if (k >= a.max_iter) {
+                        st = CGD_NOT_CONVERGED;
+                        break;
+                    }
+                    double rho_new;
+                    wg_precond<VEC, TY, NW, false>(a, p, rho_new, dummy, sh);
+                    q.Pold = (k & 1) ? PA : PB;
+                    q.Pnew = (k & 1) ? PB : PA;
+                    wg_sweep<VEC, TY, NW, S1>(a, q, 0.f, (float)(rho_new / rho), pap, dummy, sh);
+                    if (!(pap > 0.0) || !isfinite(pap)) {
+                        broken = true;
+                        continue;
+                    }
+                    alpha = (float)(rho_new / pap);
+                    p.Pnew = q.Pnew;
+                    wg_sweep<VEC, TY, NW, S2>(a, p, alpha, 0.f, rr, dummy, sh);
+                    rho = rho_new;
+                    ++k;
+                }
+                if (threadIdx.x == 0) a.iters[(size_t)rhs * a.n_steps + step] = k;
+                if (st == CGD_E_BREAKDOWN || (st == CGD_NOT_CONVERGED && worst == CGD_OK)) worst = st;
+                float* t = cur;
+                cur = nxt;
+                nxt = t;
+                continue;
+            }
+            Ptrs p{cur, R, nullptr, nullptr, nxt, nullptr};
             double bab, bb, rr, dummy;
             wg_sweep<VEC, TY, NW, S1_FIRST>(a, p, 0.f, 0.f, bab, bb, sh);
             bool broken = !isfinite(bb) || !isfinite(bab) || (bb > 0.0 && !(bab > 0.0));
@@ -296,8 +355,10 @@ Cfg make_cfg() {
 }
 
 std::vector<Cfg> candidates(int vec) {
-    if (vec == 4) return {make_cfg<4, 2, 8>(), make_cfg<4, 2, 16>(), make_cfg<4, 4, 8>(), make_cfg<4, 4, 16>()};
-    if (vec == 2) return {make_cfg<2, 4, 8>(), make_cfg<2, 4, 16>(), make_cfg<2, 8, 8>(), make_cfg<2, 8, 16>()};
+    // rows per wave are kept small enough that the preconditioning sweep's
+    // register queues fit without spilling at 16 waves (1024 threads)
+    if (vec == 4) return {make_cfg<4, 1, 8>(), make_cfg<4, 1, 16>(), make_cfg<4, 2, 8>(), make_cfg<4, 2, 12>()};
+    if (vec == 2) return {make_cfg<2, 2, 8>(), make_cfg<2, 2, 16>(), make_cfg<2, 4, 8>(), make_cfg<2, 4, 12>()};
     return {make_cfg<1, 4, 8>(), make_cfg<1, 4, 16>(), make_cfg<1, 8, 8>(), make_cfg<1, 8, 16>()};
 }
 
@@ -446,7 +507,7 @@ cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, 
     CGD_HIP_TRY(hipDeviceSynchronize());
     const BLayout L = batched_layout(nr, 1, 1);
     const size_t small = L.small;
-    cgd_status rc = ensure_workspace(m, small + (size_t)nr * cells * 4 + (size_t)gmax * 4 * cells * 4);
+    cgd_status rc = ensure_workspace(m, small + (size_t)nr * cells * 4 + (size_t)gmax * 5 * cells * 4);
     if (rc != CGD_OK) return rc;
     char* base = static_cast<char*>(m->ws.ptr);
     float* fields = reinterpret_cast<float*>(base + small);
@@ -467,6 +528,8 @@ cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, 
     a.g.ny = g.ny;
     a.g.nz = g.nz;
     a.g.cx = a.g.cy = a.g.cz = 1.0f;
+    a.pcg = 1;  // the default solver is what gets tuned
+    poly_precond_coeffs(1.0, 1.0, 1.0, 2, &a.g.c0, &a.g.c1, &a.g.c2);
     a.n_steps = 1;
     a.rtol2 = 0.0;  // run the full iteration budget
     a.max_iter = 12;
@@ -528,7 +591,7 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     const BLayout L = batched_layout(n_rhs, n_snap, da.n_steps);
     const size_t small = L.small;
     const size_t acc_bytes = (size_t)n_rhs * cells * 8;
-    const size_t solver_bytes = (size_t)grid * 4 * cells * 4;
+    const size_t solver_bytes = (size_t)grid * 5 * cells * 4;
     rc = ensure_workspace(m, small + std::max(acc_bytes, solver_bytes));
     if (rc != CGD_OK) return rc;
     const BPin P = batched_pin(n_rhs, n_snap, da.n_steps);
@@ -586,6 +649,8 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     a.g.cx = (float)(dtau / (g.h[0] * g.h[0]));
     a.g.cy = (float)(dtau / (g.h[1] * g.h[1]));
     a.g.cz = (float)(dtau / (g.h[2] * g.h[2]));
+    a.pcg = da.precond == 0 ? 1 : 0;
+    poly_precond_coeffs(a.g.cx, a.g.cy, a.g.cz, 2, &a.g.c0, &a.g.c1, &a.g.c2);
     a.xsegs = 1;
     a.ygroups = (g.ny + c.ty - 1) / c.ty;
     a.n_steps = da.n_steps;
@@ -614,9 +679,9 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     const bool use_graph = getenv("CGD_NO_GRAPH") == nullptr;
     if (use_graph) {
         char keybuf[512];
-        snprintf(keybuf, sizeof keybuf, "%p %p %p %d %d %lld %d %d %.17g %.17g %d %d %p %zu %p", (const void*)pos,
+        snprintf(keybuf, sizeof keybuf, "%p %p %p %d %d %lld %d %d %.17g %.17g %d %d %p %zu %p %d", (const void*)pos,
                  (const void*)values, (void*)fields, n_snap, F, (long long)total, chunks, da.n_steps, da.bandwidth,
-                 da.rtol, da.max_iter, ci, m->ws.ptr, m->ws.bytes, m->pinned);
+                 da.rtol, da.max_iter, ci, m->ws.ptr, m->ws.bytes, m->pinned, a.pcg);
         std::lock_guard<std::mutex> lk(g_graph_mu);
         BatchedGraph& bg = g_graphs[m];
         if (bg.key != keybuf || !bg.exec) {

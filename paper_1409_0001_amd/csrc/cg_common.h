@@ -102,6 +102,14 @@ __global__ void k_cg_step_init(CgField* st, int F, int* ndone, int32_t* status_r
 __global__ void k_cg_step_end(CgCtl c, const double* rr_part, size_t field_stride, int bpf, int k_end);
 #endif
 
+// Host: coefficients of the polynomial preconditioner M = c0 I + c1 A + c2 A^2
+// of degree 1 or 2 for the hex operator A = I + sum_a c_a L_a, whose
+// spectrum lies in [1, lmax], lmax = 1 + 4 sum_a c_a (the constant field
+// gives exactly 1).  1 - lambda M(lambda) is the Chebyshev polynomial
+// T_{deg+1} scaled to that interval, so the preconditioned condition number
+// is (1 + e) / (1 - e) with e = 1 / T_{deg+1}((lmax + 1) / (lmax - 1)).
+void poly_precond_coeffs(double cx, double cy, double cz, int deg, float* c0, float* c1, float* c2);
+
 // Host: enqueues iterations `chunk` at a time through `enqueue(it)` until the
 // device reports all F fields stopped (read back one chunk late, so the
 // device always has queued work) or max_iter iterations are queued.

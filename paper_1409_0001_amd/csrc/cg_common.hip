@@ -31,6 +31,27 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_step_end(CgCtl c, const double*
     finish_field(c, f, status);
 }
 
+void poly_precond_coeffs(double cx, double cy, double cz, int deg, float* c0, float* c1, float* c2) {
+    // with s = lmax + 1 and d = lmax - 1 (finite as d -> 0, where M tends to a
+    // multiple of the identity):
+    //   degree 1 (T_2): c0 = 8 s / (2 s^2 - d^2), c1 = -8 / (2 s^2 - d^2)
+    //   degree 2 (T_3): c0 = 2 (12 s^2 - 3 d^2) / (4 s^3 - 3 s d^2),
+    //                   c1 = -48 / (4 s^2 - 3 d^2), c2 = 32 / (4 s^3 - 3 s d^2)
+    const double lmax = 1.0 + 4.0 * (cx + cy + cz);
+    const double sp = lmax + 1.0, dm = lmax - 1.0;
+    if (deg == 1) {
+        const double den = 2.0 * sp * sp - dm * dm;
+        *c0 = (float)(8.0 * sp / den);
+        *c1 = (float)(-8.0 / den);
+        *c2 = 0.f;
+    } else {
+        const double den3 = 4.0 * sp * sp * sp - 3.0 * sp * dm * dm;
+        *c0 = (float)(2.0 * (12.0 * sp * sp - 3.0 * dm * dm) / den3);
+        *c1 = (float)(-48.0 / (4.0 * sp * sp - 3.0 * dm * dm));
+        *c2 = (float)(32.0 / den3);
+    }
+}
+
 cgd_status cg_lookahead_loop(cgd_mesh m, int F, int it0, int max_iter, int chunk, const int* d_ndone,
                              hipStream_t s, const std::function<void(int)>& enqueue, int* it_end) {
     int* pinned_flags = reinterpret_cast<int*>(static_cast<char*>(m->pinned) + kPinFlags);

@@ -437,38 +437,14 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     a.P3 = d_P3;
     a.p.R = R;
     a.p.Z = Z;
-    // Preconditioned CG (default): M = c0 I - c1 A, the degree-1 polynomial
-    // that makes the residual polynomial 1 - lambda M(lambda) the scaled
-    // Chebyshev polynomial T_2 on the spectrum [1, lmax] of A (lambda_min = 1:
-    // the constant field; lambda_max < 1 + 4 sum_a c_a).  With s = lmax + 1,
-    // d = lmax - 1: c0 = 8 s / (2 s^2 - d^2), c1 = 8 / (2 s^2 - d^2); the
-    // condition number drops from lmax to (1 + e) / (1 - e), e = 1 / T_2(s / d)
-    // (13 -> 3.8 at dtau / h^2 = 1).
-    //
-    // Where one wave covers a row (no EDGE tiles), the degree-2 polynomial is
-    // used instead (residual polynomial T_3; the sweep keeps two halo rows and
-    // planes, tile_precond2): with s, d as above, c0 = 2 (12 s^2 - 3 d^2) /
-    // (4 s^3 - 3 s d^2), c1 = -48 / (4 s^2 - 3 d^2), c2 = 32 / (4 s^3 - 3 s d^2);
-    // condition number 13 -> 2.1 at dtau / h^2 = 1.  The coefficients stay
-    // finite as d -> 0 (tiny dtau: M -> a multiple of the identity).
+    // Preconditioned CG (default) with the Chebyshev polynomial preconditioner
+    // of poly_precond_coeffs: degree 2 where one wave covers a row (the sweep
+    // keeps two halo rows and planes, tile_precond2; condition number 13 ->
+    // 2.1 at dtau / h^2 = 1), degree 1 otherwise (13 -> 3.8).
     const bool pcg = da.precond == 0;
     const int deg = (pcg && !p.edge && p.xsegs == 1 && g.nx == 64 * p.vec) ? 2 : 1;
     a.pcg = pcg ? 1 : 0;
-    {
-        const double lmax = 1.0 + 4.0 * ((double)a.g.cx + (double)a.g.cy + (double)a.g.cz);
-        const double sp = lmax + 1.0, dm = lmax - 1.0;
-        if (deg == 1) {
-            const double den = 2.0 * sp * sp - dm * dm;
-            a.g.c0 = (float)(8.0 * sp / den);
-            a.g.c1 = (float)(-8.0 / den);
-            a.g.c2 = 0.f;
-        } else {
-            const double den3 = 4.0 * sp * sp * sp - 3.0 * sp * dm * dm;
-            a.g.c0 = (float)(2.0 * (12.0 * sp * sp - 3.0 * dm * dm) / den3);
-            a.g.c1 = (float)(-48.0 / (4.0 * sp * sp - 3.0 * dm * dm));
-            a.g.c2 = (float)(32.0 / den3);
-        }
-    }
+    poly_precond_coeffs(a.g.cx, a.g.cy, a.g.cz, deg, &a.g.c0, &a.g.c1, &a.g.c2);
     const int mode_z_first = deg == 2 ? SZ2_FIRST : SZ_FIRST;
     const int mode_z = deg == 2 ? SZ2 : SZ;
 

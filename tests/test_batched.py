@@ -59,6 +59,32 @@ def test_batched_matches_oracle_and_single_path(gpu_lib, shape):
     assert (iters[[0, 2, 3]] >= 1).all()
 
 
+def test_batched_plain_and_preconditioned_cg_agree(gpu_lib):
+    """Both solvers of the batched launch meet the oracle gate; the default
+    polynomial-preconditioned CG needs at most 0.6 of plain CG's iterations
+    (condition number 13 -> 2.1 at dtau / h^2 = 1)."""
+    import torch
+    cgd = gpu_lib
+    shape = (128, 24, 40)
+    counts = [30_000, 12_000, 50_000]
+    box, parts, pos, vals, off = _batch(shape, counts, seed=77)
+    b, steps = 4.0 / shape[0], 4
+    mesh = cgd.HexMesh(shape, box.lo, box.hi)
+    out = {}
+    for pc in (0, 1):
+        f, it = cgd.coarse_grain_batched(mesh, off, _t(pos, torch), _t(vals, torch), b, steps, rtol=1e-7,
+                                         return_iters=True, precond=pc)
+        out[pc] = (f.cpu().numpy(), it)
+    for j, p in enumerate(parts):
+        dep = O.deposit_hex(p.pos, p.values, box.lo, box.hi, shape)
+        ref = O.diffuse_hex_dct(dep["field64"], box.lo, box.hi, shape, b, steps)
+        for pc in (0, 1):
+            for f in range(4):
+                assert rel_l2(out[pc][0][j, f], ref[f]) <= REL_L2, (pc, j, f)
+    print("iterations preconditioned", out[0][1].sum(), "plain", out[1][1].sum(), flush=True)
+    assert out[0][1].sum() <= 0.6 * out[1][1].sum()
+
+
 def test_batched_conserves_each_snapshot(gpu_lib):
     """Each snapshot's total (eq. conserve) survives the batched deposit and
     diffusion; the single-snapshot deposit of the same particles is
