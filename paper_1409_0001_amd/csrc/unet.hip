@@ -388,6 +388,174 @@ __global__ __launch_bounds__(kThreads) void k_wgrad(WgArgs a) {
     }
 }
 
+// Weight gradient for CC in {16, 32}: the same brick, partial-sum layout and
+// tile numbering as k_wgrad, with wide LDS reads.  The input halo is staged
+// transposed, XT[ci][hz][hy][e] with the x of halo voxel hx at element
+// e = hx + 7 (so interior x lands 16-byte aligned at e = x + 8), and the
+// output gradient as GT[co][v].  A lane's 8 consecutive voxels are then one
+// 16-byte read; the taps dx = -1 and +1 are the aligned read shifted by one
+// element either way, built from the neighbouring aligned chunk with
+// v_alignbyte.  A wave owns whole tap rows (dz, dy) of one channel tile
+// (a unit) and multiplies the three dx fragments, read once, by every output
+// channel tile.
+constexpr int kXRow = 32;                       // elements per (hz, hy) row of XT
+constexpr int kXStride = 4 * HY * kXRow + 8;    // per channel (padding shifts banks by 4)
+constexpr int kGStride = WV + 8;                // per output channel of GT
+
+__device__ inline uint32_t align2(uint32_t hi, uint32_t lo) { return __builtin_amdgcn_alignbyte(hi, lo, 2); }
+
+template <int CC, int CO>
+__global__ __launch_bounds__(kThreads) void k_wgrad2(WgArgs a) {
+    constexpr int NCOT = CO / 16;
+    constexpr int NCIT = CC / 16;
+    constexpr int UPW = NCOT == 1 ? 4 : (NCOT == 2 ? 2 : 1);  // units per wave
+    constexpr int UNITS = 9 * NCIT;
+    __shared__ uint4 xs[CC * kXStride / 8];
+    __shared__ uint4 gs[CO * kGStride / 8];
+    uint16_t* x16 = reinterpret_cast<uint16_t*>(xs);
+    uint16_t* g16 = reinterpret_cast<uint16_t*>(gs);
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, xl = lane & 15;
+    const int pass = blockIdx.z;
+    const int u0 = (blockIdx.y * 4 + wave) * UPW;
+
+    f32x4 acc[UPW][3][NCOT];
+#pragma unroll
+    for (int i = 0; i < UPW; ++i)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int t = 0; t < NCOT; ++t) acc[i][d][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int br = blockIdx.x; br < a.nbricks; br += gridDim.x) {
+        int b = br;
+        const int bx = b % a.bnx;
+        b /= a.bnx;
+        const int by = b % a.bny, bz = b / a.bny;
+        const int x0 = bx * BX, y0 = by * BY, z0 = bz * WBZ;
+        __syncthreads();  // the previous brick's reads are done
+        // input: quads of 4 halo voxels along x (e = 4q .. 4q+3, q = 1..6) x 8 channels
+        for (int i = threadIdx.x; i < (WBZ + 2) * HY * 6 * (CC / 8); i += kThreads) {
+            int r = i;
+            const int j = r % (CC / 8);
+            r /= CC / 8;
+            const int q = 1 + r % 6;
+            r /= 6;
+            const int hy = r % HY, hz = r / HY;
+            uint32_t w[4][4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int hx = 4 * q + k - 7;
+                const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (hx >= 0 && hx < HX && (unsigned)gx < (unsigned)a.nx && (unsigned)gy < (unsigned)a.ny &&
+                    (unsigned)gz < (unsigned)a.nz)
+                    v = load_src8(a.src, pass * CC + 8 * j, gx, gy, gz, a.nx, a.ny);
+                w[k][0] = v.x;
+                w[k][1] = v.y;
+                w[k][2] = v.z;
+                w[k][3] = v.w;
+            }
+            // channel c = 2m + h of voxel k sits in half h of w[k][m]
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int m = c >> 1, sh = 16 * (c & 1);
+                uint2 o;
+                o.x = ((w[0][m] >> sh) & 0xFFFFu) | (((w[1][m] >> sh) & 0xFFFFu) << 16);
+                o.y = ((w[2][m] >> sh) & 0xFFFFu) | (((w[3][m] >> sh) & 0xFFFFu) << 16);
+                *reinterpret_cast<uint2*>(x16 + (size_t)(8 * j + c) * kXStride + (hz * HY + hy) * kXRow + 4 * q) = o;
+            }
+        }
+        // output gradient: quads of 4 voxels x 8 channels
+        for (int i = threadIdx.x; i < (WV / 4) * (CO / 8); i += kThreads) {
+            const int j = i % (CO / 8), vq = i / (CO / 8);
+            uint32_t w[4][4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int vi = 4 * vq + k;
+                const int x = x0 + (vi & 15), y = y0 + ((vi >> 4) & 3), z = z0 + (vi >> 6);
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (x < a.nx && y < a.ny && z < a.nz)
+                    v = *reinterpret_cast<const uint4*>(a.g + (((size_t)z * a.ny + y) * a.nx + x) * a.ldg + 8 * j);
+                w[k][0] = v.x;
+                w[k][1] = v.y;
+                w[k][2] = v.z;
+                w[k][3] = v.w;
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int m = c >> 1, sh = 16 * (c & 1);
+                uint2 o;
+                o.x = ((w[0][m] >> sh) & 0xFFFFu) | (((w[1][m] >> sh) & 0xFFFFu) << 16);
+                o.y = ((w[2][m] >> sh) & 0xFFFFu) | (((w[3][m] >> sh) & 0xFFFFu) << 16);
+                *reinterpret_cast<uint2*>(g16 + (size_t)(8 * j + c) * kGStride + 4 * vq) = o;
+            }
+        }
+        __syncthreads();
+
+#pragma unroll 1
+        for (int c = 0; c < WV / 32; ++c) {
+            const int vi0 = 32 * c + 8 * g;  // this lane's 8 voxels (one half row)
+            const int row = vi0 >> 4, xo = vi0 & 15;
+            const int ty = row & 3, tz = row >> 2;
+            bf16x8 af[NCOT];
+#pragma unroll
+            for (int t = 0; t < NCOT; ++t)
+                af[t] = *reinterpret_cast<const bf16x8*>(g16 + (size_t)(16 * t + xl) * kGStride + vi0);
+#pragma unroll
+            for (int i = 0; i < UPW; ++i) {
+                const int u = u0 + i;
+                if (u >= UNITS) continue;  // uniform over the wave
+                const int cit = u % NCIT, tr = u / NCIT;
+                const int dz = tr / 3 - 1, dy = tr % 3 - 1;
+                const uint16_t* rowp = x16 + (size_t)(16 * cit + xl) * kXStride +
+                                       ((tz + 1 + dz) * HY + ty + 1 + dy) * kXRow + xo;
+                const uint4 A = *reinterpret_cast<const uint4*>(rowp);
+                const uint4 B = *reinterpret_cast<const uint4*>(rowp + 8);
+                const uint4 C = *reinterpret_cast<const uint4*>(rowp + 16);
+                uint4 fm, fp;  // dx = -1: elements xo+7 .. xo+14; dx = +1: xo+9 .. xo+16
+                fm.x = align2(B.x, A.w);
+                fm.y = align2(B.y, B.x);
+                fm.z = align2(B.z, B.y);
+                fm.w = align2(B.w, B.z);
+                fp.x = align2(B.y, B.x);
+                fp.y = align2(B.z, B.y);
+                fp.z = align2(B.w, B.z);
+                fp.w = align2(C.x, B.w);
+                const bf16x8 bm = __builtin_bit_cast(bf16x8, fm);
+                const bf16x8 b0 = __builtin_bit_cast(bf16x8, B);
+                const bf16x8 bp = __builtin_bit_cast(bf16x8, fp);
+#pragma unroll
+                for (int t = 0; t < NCOT; ++t) {
+                    acc[i][0][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[t], bm, acc[i][0][t], 0, 0, 0);
+                    acc[i][1][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[t], b0, acc[i][1][t], 0, 0, 0);
+                    acc[i][2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[t], bp, acc[i][2][t], 0, 0, 0);
+                }
+            }
+        }
+    }
+
+    // tile numbering of k_wgrad: tile = (tap * NCIT + cit) * NCOT + cot, tap = tr * 3 + dx + 1
+    constexpr int T = 27 * NCIT * NCOT;
+    const size_t npt = (size_t)a.np * T;
+#pragma unroll
+    for (int i = 0; i < UPW; ++i) {
+        const int u = u0 + i;
+        if (u >= UNITS) continue;
+        const int cit = u % NCIT, tr = u / NCIT;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int t = 0; t < NCOT; ++t) {
+                const int tile = ((tr * 3 + d) * NCIT + cit) * NCOT + t;
+                float* o = a.part + ((size_t)blockIdx.x * npt + (size_t)pass * T + tile) * 256;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) o[(4 * g + e) * 16 + xl] = acc[i][d][t][e];
+            }
+    }
+}
+
 // Sums the weight-gradient partials of nblk blocks and writes dW in the
 // canonical layout [co][tap][ci].  A block takes 32 consecutive outputs; its
 // 8 thread rows each add the partials b = r, r + 8, ... in increasing b, and
@@ -821,16 +989,30 @@ int wgrad_nblk(int64_t nbricks, int groups, int np) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(nbricks, 1024 / std::max(1, groups * np)));
 }
 
+// Block groups along y of a weight-gradient launch: k_wgrad (CC = 1) takes
+// kTilesPerGroup tiles per group, k_wgrad2 four waves of whole tap-row units.
+int wgrad_groups(int cc, int co) {
+    if (cc == 1) return (wgrad_tiles(cc, co) + kTilesPerGroup - 1) / kTilesPerGroup;
+    const int ncot = co / 16, units = 9 * (cc / 16);
+    const int upw = ncot == 1 ? 4 : (ncot == 2 ? 2 : 1);
+    return (units + 4 * upw - 1) / (4 * upw);
+}
+
 size_t wgrad_part_floats(int nx, int ny, int nz, int cc, int co, int np) {
     const int64_t nbr = (int64_t)((nx + BX - 1) / BX) * ((ny + BY - 1) / BY) * ((nz + WBZ - 1) / WBZ);
     const int T = wgrad_tiles(cc, co);
-    const int groups = (T + kTilesPerGroup - 1) / kTilesPerGroup;
+    const int groups = wgrad_groups(cc, co);
     return (size_t)wgrad_nblk(nbr, groups, np) * np * T * 256;
 }
 
 template <int CC, int CO>
 void launch_wgrad_t(const WgArgs& a, dim3 grid, hipStream_t s) {
     hipLaunchKernelGGL((k_wgrad<CC, CO>), grid, dim3(kThreads), 0, s, a);
+}
+
+template <int CC, int CO>
+void launch_wgrad2_t(const WgArgs& a, dim3 grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_wgrad2<CC, CO>), grid, dim3(kThreads), 0, s, a);
 }
 
 // Weight and bias gradients of one convolution into dw [co][27][ci], db [co].
@@ -849,17 +1031,17 @@ bool launch_wgrad(int cc, int co, int np, const Src& src, const bf16* g, int ldg
     a.nbricks = a.bnx * a.bny * ((nz + WBZ - 1) / WBZ);
     a.np = np;
     const int T = wgrad_tiles(cc, co);
-    const int groups = (T + kTilesPerGroup - 1) / kTilesPerGroup;
+    const int groups = wgrad_groups(cc, co);
     const int nblk = wgrad_nblk(a.nbricks, groups, np);
     const dim3 grid(nblk, groups, np);
     bool ok = true;
     if (cc == 1 && co == 16) launch_wgrad_t<1, 16>(a, grid, s);
-    else if (cc == 16 && co == 16) launch_wgrad_t<16, 16>(a, grid, s);
-    else if (cc == 16 && co == 32) launch_wgrad_t<16, 32>(a, grid, s);
-    else if (cc == 16 && co == 64) launch_wgrad_t<16, 64>(a, grid, s);
-    else if (cc == 32 && co == 16) launch_wgrad_t<32, 16>(a, grid, s);
-    else if (cc == 32 && co == 32) launch_wgrad_t<32, 32>(a, grid, s);
-    else if (cc == 32 && co == 64) launch_wgrad_t<32, 64>(a, grid, s);
+    else if (cc == 16 && co == 16) launch_wgrad2_t<16, 16>(a, grid, s);
+    else if (cc == 16 && co == 32) launch_wgrad2_t<16, 32>(a, grid, s);
+    else if (cc == 16 && co == 64) launch_wgrad2_t<16, 64>(a, grid, s);
+    else if (cc == 32 && co == 16) launch_wgrad2_t<32, 16>(a, grid, s);
+    else if (cc == 32 && co == 32) launch_wgrad2_t<32, 32>(a, grid, s);
+    else if (cc == 32 && co == 64) launch_wgrad2_t<32, 64>(a, grid, s);
     else ok = false;
     if (!ok) return false;
     const int ci_n = cc == 1 ? 1 : cc * np;
