@@ -3,12 +3,18 @@
 // two-point-flux finite-volume Laplacian by Jacobi-preconditioned CG over an
 // LDS-staged CSR SpMV (Sections 2.1 item 4, 4.3, 5.1).
 //
-// Point location: the tets listed in the particle's bucket are tested in
-// ascending id order; a tet contains the point when, for each face, the
-// float64 orientation of the point relative to the face (evaluated on the
-// face's vertices in increasing global-id order, so both tets sharing a face
-// compute the identical number) is not strictly on the opposite side from
-// the tet's fourth vertex.  The first hit is the lowest containing id.
+// Point location: a tet contains the point when, for each face, the float64
+// orientation of the point relative to the face (evaluated on the face's
+// vertices in increasing global-id order, so both tets sharing a face compute
+// the identical number) is not strictly on the opposite side from the tet's
+// fourth vertex; the result is the lowest containing id.  The search walks
+// from the seed tet of the point's bucket across faces the point lies
+// strictly beyond (orientation walk over face neighbours).  A tet that has
+// the point strictly inside all four faces is the only tet containing it (a
+// conforming mesh), so the walk's answer is the definition's.  When the walk
+// meets a zero orientation (the point on a face, edge or vertex), leaves the
+// mesh, or exceeds a step limit, the bucket's tets are tested in ascending
+// id order and the first hit is returned (the same definition, exhaustively).
 //
 // Diffusion step: (M + dtau K) x = M e with M = diag(V), K the CSR Laplacian;
 // Jacobi preconditioner D = diag(M + dtau K).  One iteration k is two sweeps:
@@ -72,9 +78,43 @@ struct LocArgs {
     const double* bbox;
     const int64_t* bstart;
     const int32_t* blist;
+    const int32_t* bseed;
+    const int32_t* nbr;
     int32_t nb[3];
     double glo[3], ghi[3], ginv[3];
 };
+
+constexpr int kWalkSteps = 64;
+
+// One step of the walk: 1 if the point is strictly inside all four faces of
+// t, 0 if it is on a face (some orientation zero, none negative), else -1
+// with *exit the local index of the first face the point lies beyond.
+__device__ inline int walk_test(const double* __restrict__ xyz, const int32_t* __restrict__ tv, int t, const double* p,
+                                int* exit) {
+    const int4 v4 = *reinterpret_cast<const int4*>(tv + (size_t)t * 4);
+    const int ids[4] = {v4.x, v4.y, v4.z, v4.w};
+    bool zero = false;
+    for (int j = 0; j < 4; ++j) {
+        int f[3], k = 0;
+        for (int i = 0; i < 4; ++i)
+            if (i != j) f[k++] = ids[i];
+        if (f[0] > f[1]) { int tmp = f[0]; f[0] = f[1]; f[1] = tmp; }
+        if (f[1] > f[2]) { int tmp = f[1]; f[1] = f[2]; f[2] = tmp; }
+        if (f[0] > f[1]) { int tmp = f[0]; f[0] = f[1]; f[1] = tmp; }
+        const double* a = xyz + 3 * (size_t)f[0];
+        const double* b = xyz + 3 * (size_t)f[1];
+        const double* c = xyz + 3 * (size_t)f[2];
+        const double sp = orient(a, b, c, p);
+        const double sd = orient(a, b, c, xyz + 3 * (size_t)ids[j]);
+        const double v = sp * (sd > 0.0 ? 1.0 : (sd < 0.0 ? -1.0 : 0.0));
+        if (!(v >= 0.0)) {
+            *exit = j;
+            return -1;
+        }
+        if (v == 0.0) zero = true;
+    }
+    return zero ? 0 : 1;
+}
 
 // Containing tet of a point, -1 when none (outside the mesh or non-finite).
 __device__ inline int locate(const LocArgs& g, const double* p) {
@@ -85,6 +125,16 @@ __device__ inline int locate(const LocArgs& g, const double* p) {
         bi[a] = b < 0 ? 0 : (b >= g.nb[a] ? g.nb[a] - 1 : b);
     }
     const size_t bk = (size_t)bi[0] + (size_t)g.nb[0] * ((size_t)bi[1] + (size_t)g.nb[1] * bi[2]);
+    int t = g.bseed[bk];
+    if (t < 0) return -1;  // no tet's bounding box reaches this bucket
+    for (int step = 0; step < kWalkSteps; ++step) {
+        int exit = -1;
+        const int r = walk_test(g.xyz, g.tv, t, p, &exit);
+        if (r > 0) return t;
+        if (r == 0) break;  // on a face: several tets may contain the point
+        t = g.nbr[(size_t)t * 4 + exit];
+        if (t < 0) break;   // walked out of the mesh
+    }
     const int64_t e = g.bstart[bk + 1];
     for (int64_t i = g.bstart[bk]; i < e; ++i) {
         const int t = g.blist[i];
@@ -346,7 +396,8 @@ size_t tet_small(int F, int bpf) {
 void destroy_tet_data(cgd_mesh m) {
     TetData* t = m->tet;
     if (!t) return;
-    void* ptrs[] = {t->xyz, t->tv, t->vol, t->volf, t->bbox, t->rowptr, t->col, t->val, t->kdiag, t->bstart, t->blist};
+    void* ptrs[] = {t->xyz,   t->tv,  t->vol,    t->volf,  t->bbox,  t->rowptr, t->col,
+                    t->val,   t->kdiag, t->bstart, t->blist, t->bseed, t->nbr};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete t;
@@ -371,6 +422,8 @@ LocArgs loc_args(const TetData* t) {
     g.bbox = t->bbox;
     g.bstart = t->bstart;
     g.blist = t->blist;
+    g.bseed = t->bseed;
+    g.nbr = t->nbr;
     for (int a = 0; a < 3; ++a) {
         g.nb[a] = t->nb[a];
         g.glo[a] = t->glo[a];
@@ -579,7 +632,8 @@ extern "C" cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz, int
     std::vector<cgd_status> st = {upload(hx, &t->xyz),         upload(htv, &t->tv),       upload(h.vol, &t->vol),
                                   upload(volf, &t->volf),      upload(h.bbox, &t->bbox),  upload(h.rowptr, &t->rowptr),
                                   upload(h.col, &t->col),      upload(h.val, &t->val),    upload(h.kdiag, &t->kdiag),
-                                  upload(h.bstart, &t->bstart), upload(h.blist, &t->blist)};
+                                  upload(h.bstart, &t->bstart), upload(h.blist, &t->blist),
+                                  upload(h.bseed, &t->bseed),   upload(h.nbr, &t->nbr)};
     for (cgd_status r : st) {
         if (r != CGD_OK) {
             cgd_mesh_destroy(m);

@@ -23,6 +23,8 @@ struct TetHost {
     double glo[3] = {0, 0, 0}, ghi[3] = {0, 0, 0}, ginv[3] = {0, 0, 0};
     std::vector<int64_t> bstart;  // [nb + 1]
     std::vector<int32_t> blist;   // tets per bucket, ascending ids
+    std::vector<int32_t> bseed;   // [nb]: walk start per bucket (-1: empty bucket)
+    std::vector<int32_t> nbr;     // [n_tet][4]: tet across the face opposite vertex j (-1: boundary)
 };
 
 struct TetData {
@@ -43,6 +45,8 @@ struct TetData {
     float* kdiag = nullptr;
     int64_t* bstart = nullptr;
     int32_t* blist = nullptr;
+    int32_t* bseed = nullptr;
+    int32_t* nbr = nullptr;
 };
 
 cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tv, TetHost* out);

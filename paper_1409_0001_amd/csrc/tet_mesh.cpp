@@ -12,7 +12,8 @@
 //     no flux; CSR with float32 values and int32 column indices, columns in
 //     increasing order, diagonal = sum of the row's a_f
 //   - per-tet bounding boxes and a uniform bucket grid listing, for every
-//     bucket, the tets whose bounding box overlaps it (point location).
+//     bucket, the tets whose bounding box overlaps it, the tet across each
+//     face, and per bucket a seed tet for point location by walking
 #pragma clang fp contract(off)
 
 #include <math.h>
@@ -31,7 +32,34 @@ namespace {
 struct Face {
     int32_t v[3];
     int32_t tet;
+    int32_t j;  // local index of the vertex opposite the face
 };
+
+// det[b - a, c - a, p - a] (the device's orientation expression)
+inline double orient_h(const double* a, const double* b, const double* c, const double* p) {
+    const double u0 = b[0] - a[0], u1 = b[1] - a[1], u2 = b[2] - a[2];
+    const double v0 = c[0] - a[0], v1 = c[1] - a[1], v2 = c[2] - a[2];
+    const double w0 = p[0] - a[0], w1 = p[1] - a[1], w2 = p[2] - a[2];
+    return u0 * (v1 * w2 - v2 * w1) - u1 * (v0 * w2 - v2 * w0) + u2 * (v0 * w1 - v1 * w0);
+}
+
+// Whether p lies in the closed tet t (each face evaluated on its vertices in
+// increasing id order, as on the device).
+bool contains_h(const double* xyz, const int32_t* tv, int32_t t, const double* p) {
+    const int32_t* ids = tv + (size_t)t * 4;
+    for (int j = 0; j < 4; ++j) {
+        int32_t f[3], k = 0;
+        for (int i = 0; i < 4; ++i)
+            if (i != j) f[k++] = ids[i];
+        std::sort(f, f + 3);
+        const double sp = orient_h(xyz + 3 * (size_t)f[0], xyz + 3 * (size_t)f[1], xyz + 3 * (size_t)f[2], p);
+        const double sd = orient_h(xyz + 3 * (size_t)f[0], xyz + 3 * (size_t)f[1], xyz + 3 * (size_t)f[2],
+                                   xyz + 3 * (size_t)ids[j]);
+        const double sg = sd > 0.0 ? 1.0 : (sd < 0.0 ? -1.0 : 0.0);
+        if (!(sp * sg >= 0.0)) return false;
+    }
+    return true;
+}
 
 inline double det3(const double* a, const double* b, const double* c, const double* d) {
     const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
@@ -103,6 +131,7 @@ cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, cons
                 if (i != j) f.v[k++] = v[i];
             std::sort(f.v, f.v + 3);
             f.tet = t;
+            f.j = j;
         }
     }
     std::sort(faces.begin(), faces.end(), [](const Face& a, const Face& b) {
@@ -119,6 +148,7 @@ cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, cons
     };
     std::vector<Link> links;
     links.reserve((size_t)nt * 2);
+    out->nbr.assign((size_t)nt * 4, -1);
     const size_t nf = faces.size();
     for (size_t i = 0; i < nf;) {
         size_t j = i + 1;
@@ -131,6 +161,8 @@ cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, cons
         }
         if (j - i == 2) {
             const int32_t P = faces[i].tet, N = faces[i + 1].tet;
+            out->nbr[(size_t)P * 4 + faces[i].j] = N;
+            out->nbr[(size_t)N * 4 + faces[i + 1].j] = P;
             const double* a = xyz + 3 * (size_t)faces[i].v[0];
             const double* b = xyz + 3 * (size_t)faces[i].v[1];
             const double* c = xyz + 3 * (size_t)faces[i].v[2];
@@ -234,6 +266,30 @@ cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, cons
     int64_t maxb = 0;
     for (int64_t b = 0; b < nbt; ++b) maxb = std::max<int64_t>(maxb, cnt[b + 1] - cnt[b]);
     out->max_bucket = maxb;
+    // walk seeds: per bucket, the first listed tet that contains the bucket's
+    // centre (else the first listed tet; -1 for an empty bucket)
+    out->bseed.assign(nbt, -1);
+    for (int z = 0; z < out->nb[2]; ++z)
+        for (int y = 0; y < out->nb[1]; ++y)
+            for (int x = 0; x < out->nb[0]; ++x) {
+                const size_t b = (size_t)x + out->nb[0] * ((size_t)y + (size_t)out->nb[1] * z);
+                if (cnt[b] == cnt[b + 1]) continue;
+                const double c[3] = {lo[0] + (x + 0.5) * (span[0] / out->nb[0]),
+                                     lo[1] + (y + 0.5) * (span[1] / out->nb[1]),
+                                     lo[2] + (z + 0.5) * (span[2] / out->nb[2])};
+                int32_t seed = out->blist[cnt[b]];
+                for (int64_t k = cnt[b]; k < cnt[b + 1]; ++k) {
+                    const int32_t t = out->blist[k];
+                    const double* bb = &out->bbox[(size_t)t * 6];
+                    if (c[0] < bb[0] || c[1] < bb[1] || c[2] < bb[2] || c[0] > bb[3] || c[1] > bb[4] || c[2] > bb[5])
+                        continue;
+                    if (contains_h(xyz, tv, t, c)) {
+                        seed = t;
+                        break;
+                    }
+                }
+                out->bseed[b] = seed;
+            }
     return CGD_OK;
 }
 

@@ -58,6 +58,33 @@ def test_locate_and_deposit_bit_exact(gpu_lib, n_hex, jitter):
     assert np.array_equal(field.cpu().numpy().view(np.uint32), ref["field32"].view(np.uint32))
 
 
+def test_locate_non_convex_mesh_bit_exact(gpu_lib):
+    """An L-shaped mesh (the Kuhn tets of hexes with x > 1/2 and y > 1/2
+    removed): walks that leave the mesh through the notch fall back to the
+    exhaustive test; points in the notch are outside."""
+    import torch
+    cgd = gpu_lib
+    n = 8
+    xyz, tets = inputs.kuhn_tet_mesh(n, 0.2, seed=55)
+    cen = xyz[tets].mean(axis=1)
+    keep = ~((cen[:, 0] > 0.5) & (cen[:, 1] > 0.5))
+    tets = np.ascontiguousarray(tets[keep])
+    used = np.unique(tets)
+    remap = -np.ones(len(xyz), dtype=np.int64)
+    remap[used] = np.arange(len(used))
+    xyz = np.ascontiguousarray(xyz[used])
+    tets = remap[tets].astype(np.int32)
+    rng = np.random.default_rng(56)
+    pos = rng.random((20_000, 3)).astype(np.float32)
+    pos[:40] = xyz[rng.integers(0, len(xyz), 40)].astype(np.float32)
+    print("case: tet L-shaped 8^3x6", flush=True)
+    mesh = cgd.TetMesh(xyz, tets)
+    cell = cgd.locate(mesh, _t(pos, torch)).cpu().numpy()
+    ref = O.locate_tets(xyz, tets, pos.astype(np.float64))
+    assert np.array_equal(cell, ref)
+    assert (ref < 0).sum() > 3000  # the notch is a quarter of the box
+
+
 @pytest.mark.parametrize("n_hex,jitter,steps", [(8, 0.2, 4), (5, 0.0, 2), (12, 0.2, 1)])
 def test_coarse_grain_tet_matches_oracle(gpu_lib, n_hex, jitter, steps):
     import torch
