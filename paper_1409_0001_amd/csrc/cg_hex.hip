@@ -301,13 +301,15 @@ Plan make_plan(const HexGeom& g, int F, int vec, int ty, int zc) {
 }
 
 // Default tiling: about 4096 waves in flight (16 per compute unit) with
-// z chunks of at least 8 planes.
+// z chunks of at least 2 planes (a chunk re-reads its two halo planes, so
+// small grids trade that for filling the machine: 128^3 runs 23 % faster
+// with 2-plane chunks than with 8).
 Plan default_plan(const HexGeom& g, int F, int vec) {
     const int ty = vec == 4 ? 2 : (vec == 2 ? 4 : (g.ny >= 8 ? 8 : 4));
     const int64_t cols = (int64_t)((g.nx + 64 * vec - 1) / (64 * vec)) * ((g.ny + ty - 1) / ty) * F;
     const int64_t target_waves = 4096;
     int64_t chunks = std::max<int64_t>(1, target_waves / std::max<int64_t>(1, cols));
-    int zc = (int)std::max<int64_t>(8, (g.nz + chunks - 1) / chunks);
+    int zc = (int)std::max<int64_t>(2, (g.nz + chunks - 1) / chunks);
     return make_plan(g, F, vec, ty, zc);
 }
 
