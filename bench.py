@@ -52,16 +52,28 @@ def parse():
     return ap.parse_args()
 
 
-def traffic_from_profiles(kernel_src):
+# Sources the hex sweep kernels are built from, in the order their bytes are
+# hashed for the counter summary's source_sha256.
+SWEEP_SOURCES = ("cg_hex.hip", "stencil_tile.h", "cg_common.h", "cg_common.hip")
+
+
+def sweep_source_sha():
+    h = hashlib.sha256()
+    for name in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_1409_0001_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_from_profiles():
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source (else None)."""
+    taken on the current sweep sources (else None)."""
     path = os.path.join(ROOT, "profiles", "cg_sweep_traffic_dense_bed.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    if d.get("source_sha256") != sha:
+    if d.get("source_sha256") != sweep_source_sha():
         return None
     return d
 
@@ -343,8 +355,7 @@ def main():
     launches, total_ms, bpl = tim[dom]
     avg_ms = total_ms / max(launches, 1)
     achieved = bpl / (avg_ms * 1e-3) / 1e9
-    kernel_src = os.path.join(ROOT, "paper_1409_0001_amd", "csrc", "cg_hex.hip")
-    tr = traffic_from_profiles(kernel_src)
+    tr = traffic_from_profiles()
     traffic = None
     if tr and dom in tr.get("kernels", {}):
         traffic = tr["kernels"][dom]["hbm_bytes_per_launch"]
