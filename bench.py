@@ -133,6 +133,15 @@ def bench_batched(args):
         cgd.coarse_grain_batched(mesh, off, pos, vals, b, steps, rtol=args.rtol, fields=fields)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t) / args.steps
+    # the same batched call with plain (unpreconditioned) CG
+    _, iters_plain = cgd.coarse_grain_batched(mesh, off, pos, vals, b, steps, rtol=args.rtol, fields=fields,
+                                              return_iters=True, precond=1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        cgd.coarse_grain_batched(mesh, off, pos, vals, b, steps, rtol=args.rtol, fields=fields, precond=1)
+    torch.cuda.synchronize()
+    dt_plain = (time.perf_counter() - t) / args.steps
     # the same right-hand sides, one cgd_coarse_grain call per snapshot
     single = torch.empty((F, mesh.cells), dtype=torch.float32, device="cuda")
     p0 = [pos[off[j]:off[j + 1]].contiguous() for j in range(args.snapshots)]
@@ -172,6 +181,10 @@ def bench_batched(args):
                        "autotune_choice": chosen, "autotune_ms": [round(x, 3) for x in tune_ms]},
             "looped_single_calls": {"value": round(n_rhs / dt_loop, 2), "unit": "fields/s",
                                     "ms": round(dt_loop * 1e3, 2)},
+            "batched_plain_cg": {"value": round(n_rhs / dt_plain, 2), "unit": "fields/s",
+                                 "ms": round(dt_plain * 1e3, 2),
+                                 "cg_iters_per_rhs_step_mean": round(int(iters_plain.sum()) / (n_rhs * steps), 2)},
+            "speedup_vs_plain_cg": round(dt_plain / dt, 3),
             "speedup_vs_looped": round(dt_loop / dt, 3),
             "solver_GBs_algorithmic_over_whole_call": round(alg_bytes / dt / 1e9, 1),
             "rel_l2_sampled": rel}
@@ -248,25 +261,31 @@ def bench_learned(args):
     first = snaps.current()
     first_pos, first_vals = first[0].cpu().numpy(), first[1].cpu().numpy()
     t0 = time.perf_counter()
-    res = warmstart.evaluate(mesh, net, snaps, args.test_snapshots, b, steps, rtol=rtol)
-    print(f"[bench] evaluated {args.test_snapshots} snapshots x 3 guesses in {time.perf_counter() - t0:.1f}s",
-          file=sys.stderr, flush=True)
+    cases = [(m, pc) for pc in (0, 1) for m in (0, 1, 3)]
+    res = warmstart.evaluate(mesh, net, snaps, args.test_snapshots, b, steps, rtol=rtol, cases=cases,
+                             keep_fields=1)
+    print(f"[bench] evaluated {args.test_snapshots} snapshots x {len(cases)} (guess, solver) cases in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     rel = None
+    names = {0: "zero", 1: "previous_step", 3: "network"}
+    solvers = {0: "preconditioned_cg", 1: "plain_cg"}
     if not args.no_check:
         from oracle import cgd_oracle as O
         lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
         dep = O.deposit_hex(first_pos, first_vals, lo, hi, (n, n, n))
         ref = O.diffuse_hex_dct(dep["field64"], lo, hi, (n, n, n), b, steps)[0]
-        rel = {m: float(np.linalg.norm(res[m]["fields"][0].cpu().numpy() - ref) / np.linalg.norm(ref))
-               for m in res}
-    names = {0: "zero", 1: "previous_step", 3: "network"}
+        rel = {f"{solvers[pc]}/{names[m]}":
+               float(np.linalg.norm(res[(m, pc)]["fields"][0].cpu().numpy() - ref) / np.linalg.norm(ref))
+               for m, pc in cases}
     ntest = args.test_snapshots
-    modes = {names[m]: {"cg_iters_per_step": [round(v / ntest, 2) for v in r["iters"]],
-                        "cg_iters_total_per_field": round(sum(r["iters"]) / ntest, 2),
-                        "ms_per_field": round(r["ms"] / ntest, 3), "fallbacks": r["fallbacks"]}
-             for m, r in res.items()}
+    modes = {solvers[pc]: {names[m]: {"cg_iters_per_step": [round(v / ntest, 2) for v in res[(m, pc)]["iters"]],
+                                      "cg_iters_total_per_field": round(sum(res[(m, pc)]["iters"]) / ntest, 2),
+                                      "ms_per_field": round(res[(m, pc)]["ms"] / ntest, 3),
+                                      "fallbacks": res[(m, pc)]["fallbacks"]}
+                           for m in (0, 1, 3)}
+             for pc in (0, 1)}
     t_fwd = []
-    x = res[0]["fields"][0]
+    x = res[(0, 0)]["fields"][0]
     y = torch.empty_like(x)
     for _ in range(20):
         torch.cuda.synchronize()
@@ -274,14 +293,15 @@ def bench_learned(args):
         net.forward(x, y)
         torch.cuda.synchronize()
         t_fwd.append(time.perf_counter() - t)
-    net_ms = res[3]["ms"] / ntest
+    net_ms = res[(3, 0)]["ms"] / ntest
     line = {"metric": "coarse-grained fields/sec, learned-guess workload 128^3, 2M particles",
             "value": round(1e3 / net_ms, 3), "unit": "fields/s", "n_gpus": 1, "steps": ntest,
             "warmup": 0, "ms_per_step": round(net_ms, 3), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32 (solver), bf16 (network)", "data": "synthetic",
             "config": {"workload": "unit cube 128^3 hex, 2M particles advected by a 16-mode divergence-free "
                                    "flow (4 sub-steps between snapshots), b=4h, 4 backward-Euler steps, "
-                                   f"CG rtol {rtol:g}; network trained on {args.train_snapshots} snapshots "
+                                   f"polynomial-preconditioned CG rtol {rtol:g} seeded by the network; "
+                                   f"network trained on {args.train_snapshots} snapshots "
                                    f"({args.train_snapshots * steps} step pairs), tested on the next {ntest}",
                        "cells": n ** 3, "train_snapshots": args.train_snapshots, "test_snapshots": ntest},
             "guesses": modes,

@@ -68,8 +68,12 @@ cgd_status cgd_mesh_create_hex(int32_t nx, int32_t ny, int32_t nz,
  * tet with positive orientation det[v1-v0, v2-v0, v3-v0] > 0 (checked:
  * CGD_E_INVALID otherwise).  Builds on the host, once: tet volumes, the
  * two-point-flux Laplacian a_f = |A_f| / |c_N - c_P| over interior faces
- * (boundary faces carry no flux) as CSR (float32 values, int32 columns),
- * face adjacency and a point-location grid; then copies them to the device. */
+ * (boundary faces carry no flux), stored per tet in its four face slots
+ * (float32 a_f, int32 id of the tet across the face, which also serves point
+ * location): a sparse matrix with rows padded to four off-diagonal entries;
+ * and a point-location grid;
+ * then copies them to the device.  Every face must be shared by at most two
+ * tets (CGD_E_INVALID otherwise). */
 cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz,
                                int64_t n_tet, const int32_t* tv, cgd_mesh* out);
 
@@ -77,7 +81,8 @@ void    cgd_mesh_destroy(cgd_mesh m);
 int64_t cgd_mesh_num_cells(cgd_mesh m);
 /* 0 = hex, 1 = tet, -1 = NULL mesh */
 int32_t cgd_mesh_kind(cgd_mesh m);
-/* Tet meshes: number of stored non-zeros of the CSR matrix (0 for hex). */
+/* Tet meshes: number of non-zeros of M + dtau K, n_tet + 2 x interior faces
+ * (0 for hex). */
 int64_t cgd_mesh_nnz(cgd_mesh m);
 
 /* Learned initial-guess network (cgd_unet_create below). */
@@ -154,8 +159,8 @@ cgd_status cgd_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F,
  * T = bandwidth^2 / 4, dtau = T / n_steps; each of the n_steps backward-Euler
  * steps solves (M + dtau K) e^{n+1} = M e^n by conjugate gradients with float32
  * vectors and float64 inner products (hex: matrix-free 7-point stencil with a
- * polynomial preconditioner, see cgd_solver_opts.precond; tet: CSR with
- * Jacobi preconditioning).  Zero-flux walls: wall faces carry
+ * polynomial preconditioner, see cgd_solver_opts.precond; tet: Jacobi
+ * preconditioning, A p from the face slots in flux form).  Zero-flux walls: wall faces carry
  * no flux.  Fields are independent solves (Section 3.2.1: each component is
  * diffused on its own).
  *
@@ -296,8 +301,8 @@ cgd_status cgd_conv3_wgrad(int32_t nx, int32_t ny, int32_t nz, int32_t ci, int32
  *   0  CG sweep 1 (p = r + beta p_old, A p, p.Ap), hex stencil
  *   1  CG sweep 2 (x += alpha p, r -= alpha A p, r.r), hex stencil
  *   2  centroid binning + fixed-point atomic deposit (hex)
- *   3  CSR sweep of the tet Jacobi-PCG (SpMV + dots)
- *   4  CSR update sweep of the tet Jacobi-PCG
+ *   3  matrix sweep of the tet Jacobi-PCG (p, A p, p.Ap)
+ *   4  update sweep of the tet Jacobi-PCG (x, r, r.z, r.r)
  *   5  hex preconditioning sweep (z = M r, r.z)
  * bytes_per_launch is the algorithmic byte count of the last timed launch of
  * that kind (what the method must move, not what the hardware moved). */

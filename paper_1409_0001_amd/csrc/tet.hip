@@ -1,7 +1,8 @@
 // Unstructured tetrahedral meshes: centroid location + fixed-point deposit
 // (Section 2.2 on arbitrary cells) and backward-Euler diffusion with the
-// two-point-flux finite-volume Laplacian by Jacobi-preconditioned CG over an
-// LDS-staged CSR SpMV (Sections 2.1 item 4, 4.3, 5.1).
+// two-point-flux finite-volume Laplacian by Jacobi-preconditioned CG over a
+// sparse operator with rows padded to a tet's four face slots (Sections 2.1
+// item 4, 4.3, 5.1).
 //
 // Point location: a tet contains the point when, for each face, the float64
 // orientation of the point relative to the face (evaluated on the face's
@@ -16,11 +17,18 @@
 // mesh, or exceeds a step limit, the bucket's tets are tested in ascending
 // id order and the first hit is returned (the same definition, exhaustively).
 //
-// Diffusion step: (M + dtau K) x = M e with M = diag(V), K the CSR Laplacian;
-// Jacobi preconditioner D = diag(M + dtau K).  One iteration k is two sweeps:
-//   sweep 1: p = D^-1 r + beta p_old (recomputed at the columns it gathers),
-//            q = A p via the CSR rows staged in LDS, p.q;  writes p, q
-//   sweep 2: x += alpha p, r -= alpha q, z = D^-1 r; r.z and r.r;  writes x, r
+// Diffusion step: (M + dtau K) x = M e with M = diag(V), K the two-point-flux
+// Laplacian; Jacobi-preconditioned CG, D = diag(M + dtau K).  A p is
+// evaluated in flux form, (A p)_i = V_i p_i + dtau sum_f a_f (p_i - p_j), from
+// the four face slots of row i (one 16-byte load of neighbour ids, one of
+// a_f): each face's flux enters its two rows with opposite signs, so A keeps
+// the conservation of the continuous operator in float32 (a constant p has
+// no flux at all), which the assembled diagonal K_ii = sum a_f does not.
+// One iteration k is two sweeps:
+//   sweep 1: p = z + beta p_old (recomputed at the neighbours it gathers),
+//            q = A p, p.q;  writes p, q
+//   sweep 2: x += alpha p, r -= alpha q, z = D^-1 r; r.z and r.r;
+//            writes x, r, z
 // Scalars come from the previous sweep's float64 block partials, summed by
 // every block in one fixed order (cg_common.h).
 #pragma clang fp contract(off)
@@ -39,7 +47,6 @@ namespace {
 
 constexpr int kBlock = kCgBlock;
 constexpr int kWaves = kCgWaves;
-constexpr int kStage = 8;  // LDS-staged rows hold at most this many entries
 
 // det[b - a, c - a, p - a], the same expression for every caller
 __device__ inline double orient(const double* a, const double* b, const double* c, const double* p) {
@@ -132,8 +139,9 @@ __device__ inline int locate(const LocArgs& g, const double* p) {
         const int r = walk_test(g.xyz, g.tv, t, p, &exit);
         if (r > 0) return t;
         if (r == 0) break;  // on a face: several tets may contain the point
-        t = g.nbr[(size_t)t * 4 + exit];
-        if (t < 0) break;   // walked out of the mesh
+        const int tn = g.nbr[(size_t)t * 4 + exit];
+        if (tn == t) break;  // a boundary face: walked out of the mesh
+        t = tn;
     }
     const int64_t e = g.bstart[bk + 1];
     for (int64_t i = g.bstart[bk]; i < e; ++i) {
@@ -200,13 +208,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize_vol(const long long* __rest
 enum TMode { T1_FIRST = 0, T1 = 1, T2_FIRST = 2, T2 = 3 };
 
 struct TetArgs {
-    const int32_t* rowptr;
-    const int32_t* col;
-    const float* val;     // K
+    const int4* col;      // [n]: neighbour across each face slot (own id in a boundary slot)
+    const float4* kf;     // [n]: a_f per face slot (0 in a boundary slot)
     const float* volf;    // V (float)
     const float* dinv;    // 1 / (V + dtau K_ii)
     const float* B;       // e^n (the step's input field)
     float* R;
+    float* Z;             // D^-1 r
     float* X;
     const float* Pold;
     float* Pnew;
@@ -265,56 +273,43 @@ __global__ __launch_bounds__(kBlock) void k_tet_sweep(TetArgs a) {
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
 
     for (int chunk = blk; chunk < a.nchunks; chunk += a.bpf) {
-        const int r0 = chunk * kBlock;
-        const int i = r0 + threadIdx.x;
-        const bool valid = i < a.n;
+        const int i = chunk * kBlock + threadIdx.x;
+        if (i >= a.n) continue;
         if constexpr (MODE == T1_FIRST || MODE == T1) {
-            __shared__ int s_col[kBlock * kStage];
-            __shared__ float s_val[kBlock * kStage];
-            // stage the chunk's CSR entries in LDS (coalesced)
-            const int r1 = min(r0 + kBlock, a.n);
-            const int e0 = a.rowptr[r0], e1 = a.rowptr[r1];
-            for (int e = e0 + threadIdx.x; e < e1; e += kBlock) {
-                s_col[e - e0] = a.col[e];
-                s_val[e - e0] = a.val[e];
-            }
-            __syncthreads();
-            if (valid) {
-                auto pval = [&](int j) -> float {
-                    if constexpr (MODE == T1_FIRST) return a.dinv[j] * (a.volf[j] * a.B[fo + j]);
-                    else return fmaf(beta, a.Pold[fo + j], a.dinv[j] * a.R[fo + j]);
-                };
-                const float pi = pval(i);
-                float kp = 0.f;
-                const int b0 = a.rowptr[i] - e0, b1 = a.rowptr[i + 1] - e0;
-                for (int e = b0; e < b1; ++e) {
-                    const int j = s_col[e];
-                    kp = fmaf(s_val[e], j == i ? pi : pval(j), kp);
-                }
-                const float q = fmaf(a.dtau, kp, a.volf[i] * pi);
-                a.Pnew[fo + i] = pi;
-                a.Q[fo + i] = q;
-                acc0 = fma((double)pi, (double)q, acc0);
-                if constexpr (MODE == T1_FIRST) {
-                    const float r = a.volf[i] * a.B[fo + i];
-                    a.R[fo + i] = r;
-                    acc1 = fma((double)r, (double)pi, acc1);  // r.z with z = p
-                    acc2 = fma((double)r, (double)r, acc2);
-                }
-            }
-            __syncthreads();
-        } else {
-            if (valid) {
-                const float p = a.Pnew[fo + i];
-                const float q = a.Q[fo + i];
-                const float x = MODE == T2_FIRST ? alpha * p : fmaf(alpha, p, a.X[fo + i]);
-                const float r = fmaf(-alpha, q, a.R[fo + i]);
-                a.X[fo + i] = x;
+            // p at a row: z = D^-1 M e on the first iteration, else z + beta p_old
+            auto pval = [&](int j) -> float {
+                if constexpr (MODE == T1_FIRST) return a.dinv[j] * (a.volf[j] * a.B[fo + j]);
+                else return fmaf(beta, a.Pold[fo + j], a.Z[fo + j]);
+            };
+            const int4 c = a.col[i];
+            const float4 w = a.kf[i];
+            const float pi = pval(i);
+            const float p0 = pval(c.x), p1 = pval(c.y), p2 = pval(c.z), p3 = pval(c.w);
+            float fl = w.x * (pi - p0);
+            fl = fmaf(w.y, pi - p1, fl);
+            fl = fmaf(w.z, pi - p2, fl);
+            fl = fmaf(w.w, pi - p3, fl);
+            const float q = fmaf(a.dtau, fl, a.volf[i] * pi);
+            a.Pnew[fo + i] = pi;
+            a.Q[fo + i] = q;
+            acc0 = fma((double)pi, (double)q, acc0);
+            if constexpr (MODE == T1_FIRST) {
+                const float r = a.volf[i] * a.B[fo + i];
                 a.R[fo + i] = r;
-                const float z = a.dinv[i] * r;
-                acc0 = fma((double)r, (double)z, acc0);
-                acc1 = fma((double)r, (double)r, acc1);
+                acc1 = fma((double)r, (double)pi, acc1);  // r.z with z = p
+                acc2 = fma((double)r, (double)r, acc2);
             }
+        } else {
+            const float p = a.Pnew[fo + i];
+            const float q = a.Q[fo + i];
+            const float x = MODE == T2_FIRST ? alpha * p : fmaf(alpha, p, a.X[fo + i]);
+            const float r = fmaf(-alpha, q, a.R[fo + i]);
+            const float z = a.dinv[i] * r;
+            a.X[fo + i] = x;
+            a.R[fo + i] = r;
+            a.Z[fo + i] = z;
+            acc0 = fma((double)r, (double)z, acc0);
+            acc1 = fma((double)r, (double)r, acc1);
         }
     }
     const double t0 = block_reduce_fixed(acc0, sh);
@@ -341,7 +336,6 @@ __global__ void k_tet_dinv(const float* volf, const float* kdiag, float dtau, fl
         dinv[i] = (float)(1.0 / ((double)volf[i] + (double)dtau * (double)kdiag[i]));
 }
 
-// Sum of V_k e_k per field (mass), into partials [F][bpf].
 __global__ __launch_bounds__(kBlock) void k_tet_mass(const float* e, const double* vol, int n, double* part, int bpf) {
     const int f = blockIdx.y;
     __shared__ double sh[kWaves];
@@ -396,8 +390,8 @@ size_t tet_small(int F, int bpf) {
 void destroy_tet_data(cgd_mesh m) {
     TetData* t = m->tet;
     if (!t) return;
-    void* ptrs[] = {t->xyz,   t->tv,  t->vol,    t->volf,  t->bbox,  t->rowptr, t->col,
-                    t->val,   t->kdiag, t->bstart, t->blist, t->bseed, t->nbr};
+    void* ptrs[] = {t->xyz,   t->tv,     t->vol,   t->volf,  t->bbox, t->kface,
+                    t->kdiag, t->bstart, t->blist, t->bseed, t->nbr};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete t;
@@ -445,7 +439,8 @@ cgd_status locate_tet(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hi
 
 size_t diffuse_tet_workspace(const cgd_mesh m, int32_t F) {
     const TetPlan p = tet_plan(m->tet->n_tet, F);
-    return tet_small(F, p.bpf) + (5 * (size_t)F + 1) * (size_t)m->tet->n_tet * sizeof(float) + 256;
+    // 6 vectors per field (x, r, p twice, q, z) and D^-1
+    return tet_small(F, p.bpf) + (6 * (size_t)F + 1) * (size_t)m->tet->n_tet * sizeof(float) + 256;
 }
 
 cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values, float* field,
@@ -501,18 +496,20 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     float* PA = R + fn;
     float* PB = PA + fn;
     float* Q = PB + fn;
-    float* dinv = Q + fn;
+    float* Z = Q + fn;
+    float* dinv = Z + fn;
 
     const double dtau = da.bandwidth * da.bandwidth / 4.0 / da.n_steps;
     const int eblocks = std::min(4096, (n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_tet_dinv, dim3(eblocks), dim3(kBlock), 0, s, t->volf, t->kdiag, (float)dtau, dinv, n);
 
     TetArgs a = {};
-    a.rowptr = t->rowptr;
-    a.col = t->col;
-    a.val = t->val;
+    a.col = reinterpret_cast<const int4*>(t->nbr);
+    a.kf = reinterpret_cast<const float4*>(t->kface);
     a.volf = t->volf;
     a.dinv = dinv;
+    a.dtau = (float)dtau;
+    a.Z = Z;
     a.c = ctl;
     a.P1 = d_P1;
     a.P2 = d_P2;
@@ -520,7 +517,6 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     a.bpf = p.bpf;
     a.nblocks = p.nblocks;
     a.nchunks = p.nchunks;
-    a.dtau = (float)dtau;
     a.R = R;
     a.Q = Q;
     const int mbpf = std::min(1024, (n + kBlock - 1) / kBlock);
@@ -529,8 +525,8 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         hipLaunchKernelGGL(k_tet_mass, dim3(mbpf, F), dim3(kBlock), 0, s, da.field, t->vol, n, d_mpart, mbpf);
         hipLaunchKernelGGL(k_tet_sum_finish, dim3(F), dim3(kBlock), 0, s, d_mpart, mbpf, d_sums);
     }
-    const double b1 = 4.0 * (n + 1) + 8.0 * (double)t->nnz + 20.0 * n;  // sweep 1, one field
-    const double b2 = 28.0 * n;                                           // sweep 2, one field
+    const double b1 = 52.0 * n;  // sweep 1, one field: ids, a_f, z, p_old, V; writes p, q
+    const double b2 = 32.0 * n;  // sweep 2, one field: p, q, x, r, D^-1; writes x, r, z
     const dim3 grid(p.nblocks), block(kBlock);
     float* cur = da.field;
     float* nxt = W0;
@@ -596,10 +592,6 @@ extern "C" cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz, int
         return CGD_E_NOMEM;
     }
     if (rc != CGD_OK) return rc;
-    if (h.max_row > kStage) {
-        set_error("cgd_mesh_create_tet: a CSR row exceeds the staged row length");
-        return CGD_E_INVALID;
-    }
     cgd_mesh m = new (std::nothrow) cgd_mesh_s();
     if (!m) return CGD_E_NOMEM;
     m->kind = 1;
@@ -617,8 +609,7 @@ extern "C" cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz, int
     TetData* t = m->tet;
     t->n_tet = h.n_tet;
     t->n_vert = h.n_vert;
-    t->nnz = (int64_t)h.col.size();
-    t->max_row = h.max_row;
+    t->nnz = h.nnz;
     for (int a = 0; a < 3; ++a) {
         t->nb[a] = h.nb[a];
         t->glo[a] = h.glo[a];
@@ -630,8 +621,8 @@ extern "C" cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz, int
     std::vector<float> volf(h.vol.size());
     for (size_t i = 0; i < volf.size(); ++i) volf[i] = (float)h.vol[i];
     std::vector<cgd_status> st = {upload(hx, &t->xyz),         upload(htv, &t->tv),       upload(h.vol, &t->vol),
-                                  upload(volf, &t->volf),      upload(h.bbox, &t->bbox),  upload(h.rowptr, &t->rowptr),
-                                  upload(h.col, &t->col),      upload(h.val, &t->val),    upload(h.kdiag, &t->kdiag),
+                                  upload(volf, &t->volf),      upload(h.bbox, &t->bbox),  upload(h.kface, &t->kface),
+                                  upload(h.kdiag, &t->kdiag),
                                   upload(h.bstart, &t->bstart), upload(h.blist, &t->blist),
                                   upload(h.bseed, &t->bseed),   upload(h.nbr, &t->nbr)};
     for (cgd_status r : st) {

@@ -11,27 +11,24 @@ struct TetHost {
     int64_t n_vert = 0;
     int32_t n_tet = 0;
     int64_t n_interior_faces = 0;
-    int32_t max_row = 0;
+    int64_t nnz = 0;              // non-zeros of K: n_tet + 2 * n_interior_faces
     int64_t max_bucket = 0;
     std::vector<double> vol;      // [n_tet]
     std::vector<double> bbox;     // [n_tet][6]: min xyz, max xyz
-    std::vector<int32_t> rowptr;  // [n_tet + 1]
-    std::vector<int32_t> col;     // [nnz]
-    std::vector<float> val;       // [nnz]: the Laplacian K
-    std::vector<float> kdiag;     // [n_tet]: K_ii
+    std::vector<float> kface;     // [n_tet][4]: a_f of the face opposite vertex j (0: boundary face)
+    std::vector<float> kdiag;     // [n_tet]: K_ii = sum of the tet's a_f
     int32_t nb[3] = {1, 1, 1};    // bucket grid
     double glo[3] = {0, 0, 0}, ghi[3] = {0, 0, 0}, ginv[3] = {0, 0, 0};
     std::vector<int64_t> bstart;  // [nb + 1]
     std::vector<int32_t> blist;   // tets per bucket, ascending ids
     std::vector<int32_t> bseed;   // [nb]: walk start per bucket (-1: empty bucket)
-    std::vector<int32_t> nbr;     // [n_tet][4]: tet across the face opposite vertex j (-1: boundary)
+    std::vector<int32_t> nbr;     // [n_tet][4]: tet across the face opposite vertex j (own id: boundary)
 };
 
 struct TetData {
     int32_t n_tet = 0;
     int64_t n_vert = 0;
     int64_t nnz = 0;
-    int32_t max_row = 0;
     int32_t nb[3] = {1, 1, 1};
     double glo[3], ghi[3], ginv[3];
     double* xyz = nullptr;      // [n_vert][3]
@@ -39,14 +36,12 @@ struct TetData {
     double* vol = nullptr;      // [n_tet]
     float* volf = nullptr;      // [n_tet]
     double* bbox = nullptr;     // [n_tet][6]
-    int32_t* rowptr = nullptr;  // [n_tet + 1]
-    int32_t* col = nullptr;
-    float* val = nullptr;
+    float* kface = nullptr;     // [n_tet][4]
     float* kdiag = nullptr;
     int64_t* bstart = nullptr;
     int32_t* blist = nullptr;
     int32_t* bseed = nullptr;
-    int32_t* nbr = nullptr;
+    int32_t* nbr = nullptr;     // [n_tet][4]: the padded rows' column indices
 };
 
 cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tv, TetHost* out);

@@ -9,11 +9,13 @@
 //   - interior faces by matching the sorted vertex triples of all tet faces
 //   - the two-point-flux Laplacian K: a_f = |A_f| / |c_N - c_P| between the
 //     centroids of the two tets of each interior face; boundary faces carry
-//     no flux; CSR with float32 values and int32 column indices, columns in
-//     increasing order, diagonal = sum of the row's a_f
+//     no flux.  K is stored as a sparse matrix with rows padded to the four
+//     face slots a tet has: row t's off-diagonal entries are -a_f at columns
+//     nbr[t][j] (float32 values, int32 columns; a boundary slot holds the
+//     tet's own id and 0), the diagonal K_tt = sum of the tet's a_f
 //   - per-tet bounding boxes and a uniform bucket grid listing, for every
-//     bucket, the tets whose bounding box overlaps it, the tet across each
-//     face, and per bucket a seed tet for point location by walking
+//     bucket, the tets whose bounding box overlaps it, and per bucket a seed
+//     tet for point location by walking across the face slots
 #pragma clang fp contract(off)
 
 #include <math.h>
@@ -140,15 +142,14 @@ cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, cons
         if (a.v[2] != b.v[2]) return a.v[2] < b.v[2];
         return a.tet < b.tet;
     });
-    // neighbour lists: (tet, neighbour, coefficient)
-    std::vector<int32_t> deg(nt, 0);
-    struct Link {
-        int32_t p, n;
-        double a;
-    };
-    std::vector<Link> links;
-    links.reserve((size_t)nt * 2);
-    out->nbr.assign((size_t)nt * 4, -1);
+    // face slots: the tet across each face and the face's coefficient a_f;
+    // a boundary face keeps the tet's own id and a_f = 0 (no flux)
+    out->nbr.resize((size_t)nt * 4);
+    for (int32_t t = 0; t < nt; ++t)
+        for (int j = 0; j < 4; ++j) out->nbr[(size_t)t * 4 + j] = t;
+    out->kface.assign((size_t)nt * 4, 0.f);
+    std::vector<double> diag(nt, 0.0);
+    int64_t n_int = 0;
     const size_t nf = faces.size();
     for (size_t i = 0; i < nf;) {
         size_t j = i + 1;
@@ -161,8 +162,6 @@ cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, cons
         }
         if (j - i == 2) {
             const int32_t P = faces[i].tet, N = faces[i + 1].tet;
-            out->nbr[(size_t)P * 4 + faces[i].j] = N;
-            out->nbr[(size_t)N * 4 + faces[i + 1].j] = P;
             const double* a = xyz + 3 * (size_t)faces[i].v[0];
             const double* b = xyz + 3 * (size_t)faces[i].v[1];
             const double* c = xyz + 3 * (size_t)faces[i].v[2];
@@ -173,50 +172,21 @@ cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, cons
             const double dc[3] = {cen[(size_t)N * 3] - cen[(size_t)P * 3], cen[(size_t)N * 3 + 1] - cen[(size_t)P * 3 + 1],
                                   cen[(size_t)N * 3 + 2] - cen[(size_t)P * 3 + 2]};
             const double dist = sqrt(dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2]);
-            links.push_back({P, N, area / dist});
-            deg[P]++;
-            deg[N]++;
+            const double af = area / dist;
+            out->nbr[(size_t)P * 4 + faces[i].j] = N;
+            out->nbr[(size_t)N * 4 + faces[i + 1].j] = P;
+            out->kface[(size_t)P * 4 + faces[i].j] = (float)af;
+            out->kface[(size_t)N * 4 + faces[i + 1].j] = (float)af;
+            diag[P] += af;
+            diag[N] += af;
+            ++n_int;
         }
         i = j;
     }
-    out->n_interior_faces = (int64_t)links.size();
-    // CSR rows: diagonal + neighbours, columns ascending
-    out->rowptr.assign((size_t)nt + 1, 0);
-    for (int32_t t = 0; t < nt; ++t) out->rowptr[t + 1] = out->rowptr[t] + 1 + deg[t];
-    const int64_t nnz = out->rowptr[nt];
-    out->col.assign(nnz, 0);
-    out->val.assign(nnz, 0.f);
-    out->kdiag.assign(nt, 0.f);
-    std::vector<std::vector<std::pair<int32_t, double>>> rows(0);
-    std::vector<int32_t> fill(nt, 0);
-    std::vector<int32_t> ncol((size_t)nnz);
-    std::vector<double> nval((size_t)nnz);
-    std::vector<double> diag(nt, 0.0);
-    for (const Link& l : links) {
-        size_t ip = out->rowptr[l.p] + 1 + fill[l.p]++;
-        ncol[ip] = l.n;
-        nval[ip] = -l.a;
-        size_t in = out->rowptr[l.n] + 1 + fill[l.n]++;
-        ncol[in] = l.p;
-        nval[in] = -l.a;
-        diag[l.p] += l.a;
-        diag[l.n] += l.a;
-    }
-    for (int32_t t = 0; t < nt; ++t) {
-        const int32_t b = out->rowptr[t];
-        ncol[b] = t;
-        nval[b] = diag[t];
-        // sort the row by column
-        std::vector<std::pair<int32_t, double>> r;
-        for (int32_t k = b; k < out->rowptr[t + 1]; ++k) r.push_back({ncol[k], nval[k]});
-        std::sort(r.begin(), r.end());
-        for (size_t k = 0; k < r.size(); ++k) {
-            out->col[b + k] = r[k].first;
-            out->val[b + k] = (float)r[k].second;
-        }
-        out->kdiag[t] = (float)diag[t];
-        out->max_row = std::max<int32_t>(out->max_row, out->rowptr[t + 1] - b);
-    }
+    out->n_interior_faces = n_int;
+    out->nnz = (int64_t)nt + 2 * n_int;
+    out->kdiag.resize(nt);
+    for (int32_t t = 0; t < nt; ++t) out->kdiag[t] = (float)diag[t];
 
     // bucket grid over the vertex bounding box: about one tet-sized cell per
     // 6 tets; every tet is listed in each bucket its bounding box overlaps

@@ -51,26 +51,30 @@ def train(net: UNet, mesh: HexMesh, snapshots, n_snapshots, bandwidth, n_steps, 
 
 
 def evaluate(mesh: HexMesh, net: UNet, snapshots, n_snapshots, bandwidth, n_steps, rtol=1e-6,
-             modes=(0, 1, 3)):
-    """Coarse-grains n_snapshots consecutive snapshots with each initial-guess
-    mode (0 zero, 1 previous step, 3 network) and returns, per mode, the CG
-    iterations per step summed over snapshots, the wall time in ms (whole
-    cgd_coarse_grain calls, synchronised), the fallbacks and the fields."""
+             cases=((0, 0), (1, 0), (3, 0)), keep_fields=None):
+    """Coarse-grains n_snapshots consecutive snapshots once per case
+    (x0_mode, precond): x0_mode 0 zero guess, 1 previous step, 3 network;
+    precond 0 polynomial-preconditioned CG, 1 plain CG.  Returns, per case,
+    the CG iterations per step summed over snapshots, the wall time in ms
+    (whole cgd_coarse_grain calls, synchronised), the fallbacks and the
+    fields of the first keep_fields snapshots (all if None)."""
     import torch
-    res = {m: {"iters": [0] * n_steps, "ms": 0.0, "fallbacks": 0, "fields": []} for m in modes}
-    for _ in range(n_snapshots):
+    res = {c: {"iters": [0] * n_steps, "ms": 0.0, "fallbacks": 0, "fields": []} for c in cases}
+    for j in range(n_snapshots):
         pos, vals = snapshots.current()
-        for m in modes:
+        for c in cases:
+            m, pc = c
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             f, st = coarse_grain(mesh, pos, vals, bandwidth, n_steps, rtol=rtol, x0_mode=m, stats=True,
-                                 model=net if m == 3 else None)
+                                 model=net if m == 3 else None, precond=pc)
             torch.cuda.synchronize()
-            r = res[m]
+            r = res[c]
             r["ms"] += 1e3 * (time.perf_counter() - t0)
             for s in range(n_steps):
                 r["iters"][s] += st.iters[s][0]
             r["fallbacks"] += st.n_fallback
-            r["fields"].append(f[0].clone())
+            if keep_fields is None or j < keep_fields:
+                r["fields"].append(f[0].clone())
         snapshots.advance()
     return res

@@ -85,7 +85,8 @@ def test_trained_network_saves_iterations(gpu_lib):
     """Train on the pairs of 60 advected snapshots (32^3 grid, Delta tau / h^2
     = 1, the dense bed's ratio), then coarse-grain 8 later snapshots: the
     network's guess needs fewer CG iterations than the zero guess and than
-    the previous-step guess, and its fields pass the oracle gate."""
+    the previous-step guess, with the preconditioned and with the plain
+    solver, and its fields pass the oracle gate."""
     import torch
     cgd = gpu_lib
     from paper_1409_0001_amd import warmstart
@@ -99,17 +100,22 @@ def test_trained_network_saves_iterations(gpu_lib):
     assert losses[-1][1] < 0.2 * losses[0][1]
     first_pos = snaps.current()[0].cpu().numpy()
     first_vals = snaps.values.cpu().numpy()
-    res = warmstart.evaluate(mesh, net, snaps, 8, b, steps, rtol=1e-6)
-    it0, it1, it3 = (sum(res[m]["iters"]) for m in (0, 1, 3))
-    print(f"iterations: zero {res[0]['iters']} prev {res[1]['iters']} net {res[3]['iters']}; "
-          f"ms zero {res[0]['ms']:.1f} prev {res[1]['ms']:.1f} net {res[3]['ms']:.1f}", flush=True)
-    assert res[3]["fallbacks"] == 0
-    assert it3 < it1 and it3 < it0, (it0, it1, it3)
+    cases = ((0, 0), (1, 0), (3, 0), (0, 1), (3, 1))
+    res = warmstart.evaluate(mesh, net, snaps, 8, b, steps, rtol=1e-6, cases=cases)
+    it = {c: sum(res[c]["iters"]) for c in cases}
+    for c in cases:
+        print(f"x0_mode {c[0]} precond {c[1]}: iterations {res[c]['iters']} ms {res[c]['ms']:.1f}", flush=True)
+    assert res[(3, 0)]["fallbacks"] == 0 and res[(3, 1)]["fallbacks"] == 0
+    # fewer iterations than the zero and previous-step guesses, with either solver
+    assert it[(3, 0)] < it[(1, 0)] and it[(3, 0)] < it[(0, 0)], it
+    assert it[(3, 1)] < it[(0, 1)], it
     # the same discrete solution: compare with the zero-guess fields and, for
     # the first evaluated snapshot, with the oracle
-    for a, c in zip(res[3]["fields"], res[0]["fields"]):
+    for a, c in zip(res[(3, 0)]["fields"], res[(0, 0)]["fields"]):
+        assert rel_l2(a.cpu().numpy(), c.cpu().numpy()) <= 1e-5
+    for a, c in zip(res[(3, 1)]["fields"], res[(0, 0)]["fields"]):
         assert rel_l2(a.cpu().numpy(), c.cpu().numpy()) <= 1e-5
     lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
     dep = O.deposit_hex(first_pos, first_vals, lo, hi, (n, n, n))
     ref = O.diffuse_hex_dct(dep["field64"], lo, hi, (n, n, n), b, steps)[0]
-    assert rel_l2(res[3]["fields"][0].cpu().numpy(), ref) <= 1e-5
+    assert rel_l2(res[(3, 0)]["fields"][0].cpu().numpy(), ref) <= 1e-5
