@@ -109,6 +109,8 @@ __global__ void k_cg_step_end(CgCtl c, const double* rr_part, size_t field_strid
 // T_{deg+1} scaled to that interval, so the preconditioned condition number
 // is (1 + e) / (1 - e) with e = 1 / T_{deg+1}((lmax + 1) / (lmax - 1)).
 void poly_precond_coeffs(double cx, double cy, double cz, int deg, float* c0, float* c1, float* c2);
+// The same polynomial for any degree 1..6: c[0..deg] (float64).
+void poly_precond_coeffs_n(double cx, double cy, double cz, int deg, double* c);
 
 // Host: enqueues iterations `chunk` at a time through `enqueue(it)` until the
 // device reports all F fields stopped (read back one chunk late, so the

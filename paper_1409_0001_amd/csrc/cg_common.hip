@@ -1,4 +1,6 @@
 // Shared CG bookkeeping kernels and host loops (see cg_common.h).
+#include <algorithm>
+
 #include "cg_common.h"
 
 namespace cgd {
@@ -50,6 +52,31 @@ void poly_precond_coeffs(double cx, double cy, double cz, int deg, float* c0, fl
         *c1 = (float)(-48.0 / (4.0 * sp * sp - 3.0 * dm * dm));
         *c2 = (float)(32.0 / den3);
     }
+}
+
+void poly_precond_coeffs_n(double cx, double cy, double cz, int deg, double* c) {
+    // p(l) = (1 - T_m(sig(l)) / T_m(sig(0))) / l with m = deg + 1 and
+    // sig(l) = (s - 2 l) / d, built from T_{n+1} = 2 sig T_n - T_{n-1} on
+    // monomial coefficient arrays in l.
+    constexpr int kMax = 8;
+    const double lmax = 1.0 + 4.0 * (cx + cy + cz);
+    const double sp = lmax + 1.0, dm = std::max(lmax - 1.0, 1e-12 * sp);
+    const int m = std::min(deg, kMax - 2) + 1;
+    double t0[kMax + 1] = {1.0}, t1[kMax + 1] = {sp / dm, -2.0 / dm};
+    for (int n = 1; n < m; ++n) {
+        double t2[kMax + 1] = {0.0};
+        for (int j = 0; j <= n; ++j) {
+            t2[j] += 2.0 * (sp / dm) * t1[j];
+            t2[j + 1] += 2.0 * (-2.0 / dm) * t1[j];
+        }
+        for (int j = 0; j <= n - 1; ++j) t2[j] -= t0[j];
+        for (int j = 0; j <= kMax; ++j) {
+            t0[j] = t1[j];
+            t1[j] = t2[j];
+        }
+    }
+    // t1 = T_m(sig(l)); T_m(sig(0)) = t1[0]; 1 - t1 / t1[0] has no constant term
+    for (int j = 0; j < m; ++j) c[j] = -t1[j + 1] / t1[0];
 }
 
 cgd_status cg_lookahead_loop(cgd_mesh m, int F, int it0, int max_iter, int chunk, const int* d_ndone,

@@ -23,6 +23,9 @@
 // shuffles.  Blocks of 4 waves are spread so that consecutive tiles land on
 // the same XCD (workgroups are dealt round-robin over the 8 XCDs), which
 // keeps halo rows in that XCD's L2.
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <algorithm>
 
 #include "cg_common.h"
@@ -55,6 +58,7 @@ struct SweepArgs {
     int xsegs, ygroups, zc;
     int wpf, bpf, nblocks;
     int k;              // iteration index within the step
+    float cp[8];        // k_precond_lds: M = sum_j cp[j] A^j
 };
 
 // One sweep over all fields: each wave takes one tile (stencil_tile.h).
@@ -195,6 +199,233 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
             a.P2[((size_t)f * 2 + 0) * a.pstride + blk] = t0;
             a.P1[((size_t)f * 2 + 1) * a.pstride + blk] = t1;
         }
+    }
+}
+
+// LDS barrier that waits only for this wave's LDS operations, so global
+// loads issued ahead (the prefetched planes) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Fixed-order float64 sum of n partials by a block of NT threads (the same
+// value in every thread and every block of the launch).
+template <int NT>
+__device__ inline double block_sum_nt(const double* p, int n, double* sh) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) s += p[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+// Preconditioning sweep of degree D with the intermediate vectors in LDS:
+// z = sum_j cp[j] A^j r, each power matrix-free.  A block of NW waves owns
+// TY rows of y (one wave per x-row, nx = 64 VEC) and marches over its z
+// chunk.  v_k = A^k r is needed at planes and rows k fewer than D away from
+// the block's output (a halo of D - k), so level k (v_0 = r, ..., v_{D-1})
+// keeps 3 planes of TY + 2 (D - k) rows in LDS; v_D is only accumulated.
+// At step t, v_k of plane t - k is formed from v_{k-1} of planes t - k - 1
+// .. t - k + 1 for k = 1..D, each wave adding c_k v_k into the z of the output rows
+// it owns (a register window over planes t - D .. t); z of plane t - D is
+// then complete and stored, and plane t + 1 of r (whose load was issued at
+// the start of the step) enters LDS.  Rows and planes beyond a wall are never read
+// (the wall rule substitutes the cell itself).  FIRST: the input is b (zero
+// initial guess) and b.b is accumulated as well.
+template <int D, int TY>
+__host__ __device__ constexpr int lds_rows_below(int k) {  // rows of levels 0..k-1
+    return k * TY + 2 * k * D - k * (k - 1);
+}
+
+template <int VEC, int D, int TY, int NW, bool FIRST>
+__global__ __launch_bounds__(NW * 64) void k_precond_lds(SweepArgs a) {
+    static_assert(TY <= NW, "each wave owns at most one output row");
+    constexpr int NT = NW * 64;
+    constexpr int NXR = 64 * VEC;
+    constexpr int E0 = TY + 2 * D;
+    constexpr int RPW0 = (E0 + NW - 1) / NW;  // level-0 rows a wave loads
+    __shared__ __align__(16) float lds[3 * NXR * lds_rows_below<D, TY>(D)];
+    __shared__ double sh[NW];
+
+    int b = blockIdx.x;
+    if ((a.nblocks & 7) == 0) b = (b & 7) * (a.nblocks >> 3) + (b >> 3);
+    const int f = b / a.bpf;
+    const int blk = b - f * a.bpf;
+    CgField* stf = a.c.st + f;
+    if (stf->done) return;  // uniform over the block
+    const bool lead = blk == 0 && threadIdx.x == 0;
+    if constexpr (!FIRST) {
+        // convergence test on r_k . r_k from the previous sweep 2 (or, at
+        // k = 0, the residual sweep, which also gave b.b)
+        const double rrk = block_sum_nt<NT>(a.P2 + ((size_t)f * 2 + (a.k & 1)) * a.pstride, a.bpf_in, sh);
+        double bb;
+        if (a.k == 0) bb = block_sum_nt<NT>(a.P1 + ((size_t)f * 2 + 1) * a.pstride, a.bpf_in, sh);
+        else bb = stf->bb;
+        if (lead) {
+            stf->rr_par[a.k & 1] = rrk;
+            if (a.k == 0) stf->bb = bb;
+        }
+        if (check_stop(a.c, f, a.k, rrk, bb, lead)) return;
+    }
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int x0 = lane * VEC;
+    const bool wall_l = lane == 0, wall_r = lane == 63;
+    const int yg = blk % a.ygroups, zci = blk / a.ygroups;
+    const int y0 = yg * TY, zb = zci * a.zc, ze = min(zb + a.zc, nz);
+    const size_t plane = (size_t)nx * ny;
+    const size_t fo = (size_t)f * a.cells + x0;
+    const float* src = (FIRST ? a.p.B : a.p.R) + fo;
+    float* dst = a.p.Z + fo;
+    const Geom& g = a.g;
+
+    // the output row this wave owns (absolute row y = y0 + jo), if any:
+    // level-k row e (row y0 - (D - k) + e) belongs to wave (e + k) % NW
+    const int jo = ((w - D) % NW + NW) % NW;
+    const bool own = jo < TY && y0 + jo < ny;
+
+    auto load_r = [&](Vec<VEC>* dstv, int t) {
+#pragma unroll
+        for (int i = 0; i < RPW0; ++i) {
+            const int e = w + NW * i;
+            int y = y0 - D + (e < E0 ? e : E0 - 1);
+            y = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+            dstv[i] = ldv<VEC>(src + (size_t)t * plane + (size_t)y * nx);
+        }
+    };
+    auto lrow = [&](int k, int q, int e) -> float* {  // level k, plane q, extent row e
+        return lds + 3 * NXR * lds_rows_below<D, TY>(k) + ((q % 3) * (TY + 2 * (D - k)) + e) * NXR + x0;
+    };
+
+    Vec<VEC> zacc[D + 1], rkeep[D + 1];  // [j]: plane t - D + j
+#pragma unroll
+    for (int j = 0; j <= D; ++j)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) zacc[j].f[e] = rkeep[j].f[e] = 0.f;
+    double acc0 = 0.0, acc1 = 0.0;
+
+    const int t0 = max(0, zb - D);
+    const int tl = min(nz, ze + D) - 1;  // last plane of r needed
+    const int t1 = ze - 1 + D;           // last step (plane ze - 1 of z completes)
+
+    // Plane t of r into LDS (and the owned row's share of z), from pf.
+    Vec<VEC> pf[RPW0];
+    auto put_r = [&](int t) {
+#pragma unroll
+        for (int i = 0; i < RPW0; ++i) {
+            const int e = w + NW * i;
+            if (e < E0) stv<VEC>(lrow(0, t, e), pf[i]);
+        }
+        // the owned row's r: level-0 row D + jo, loaded by this wave
+#pragma unroll
+        for (int i = 0; i < RPW0; ++i)
+            if (w + NW * i == D + jo) rkeep[D] = pf[i];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) zacc[D].f[e] = a.cp[0] * rkeep[D].f[e];
+    };
+    if (t0 <= tl) {
+        load_r(pf, t0);
+        put_r(t0);
+    }
+    lds_barrier();
+
+    // Step t: the load of plane t + 1 is issued first and written to LDS
+    // only after the D levels of this step, which hide its latency.  The z
+    // plane completed by the previous step is stored right after that load:
+    // a store still in flight when the load's data is needed would be waited
+    // for as well (loads and stores share the memory counter), so it is
+    // issued a whole step ahead of that wait.
+    Vec<VEC> zo;
+    int qo = -1;  // plane of zo, -1: nothing to store
+    for (int t = t0; t <= t1; ++t) {
+        const bool more = t + 1 <= tl;
+        if (more) load_r(pf, t + 1);
+        if (qo >= 0) {
+            stv<VEC>(dst + (size_t)qo * plane + (size_t)(y0 + jo) * nx, zo);
+            qo = -1;
+        }
+#pragma unroll
+        for (int k = 1; k <= D; ++k) {
+            const int q = t - k;
+            const int qlo = max(0, zb - (D - k)), qhi = min(nz, ze + (D - k));
+            if (q >= qlo && q < qhi) {
+                const int Ek = TY + 2 * (D - k);
+                const bool hzd = q > 0, hzu = q + 1 < nz;
+                for (int e = ((w - k) % NW + NW) % NW; e < Ek; e += NW) {
+                    const int y = y0 - (D - k) + e;
+                    if (y < 0 || y >= ny) continue;
+                    // v_{k-1} rows e, e+1, e+2 of its extent are rows y-1, y, y+1;
+                    // the x-neighbours of the lane's end cells are read from
+                    // LDS too (no dependent shuffle), the cell itself at a wall
+                    // (row starts are 16-byte aligned; the hint keeps every row
+                    // read a single 16-byte LDS access)
+                    auto ld = [](const float* r) {
+                        return ldv<VEC>(static_cast<const float*>(__builtin_assume_aligned(r, 4 * VEC)));
+                    };
+                    const float* rc = lrow(k - 1, q, e + 1);
+                    const Vec<VEC> c = ld(rc);
+                    const float lft = rc[wall_l ? 0 : -1];
+                    const float rgt = rc[wall_r ? VEC - 1 : VEC];
+                    const Vec<VEC> yl = ld(lrow(k - 1, q, y > 0 ? e : e + 1));
+                    const Vec<VEC> yh = ld(lrow(k - 1, q, y + 1 < ny ? e + 2 : e + 1));
+                    const Vec<VEC> zl = ld(lrow(k - 1, hzd ? q - 1 : q, e + 1));
+                    const Vec<VEC> zh = ld(lrow(k - 1, hzu ? q + 1 : q, e + 1));
+                    const Vec<VEC> v = apply_row_lr<VEC>(g, c, lft, rgt, yl, yh, zl, zh);
+                    if (k < D) stv<VEC>(lrow(k, q, e), v);
+                    if (y - y0 == jo) {  // an output row (this wave's)
+#pragma unroll
+                        for (int ee = 0; ee < VEC; ++ee) zacc[D - k].f[ee] = fmaf(a.cp[k], v.f[ee], zacc[D - k].f[ee]);
+                    }
+                }
+            }
+            if (k < D) lds_barrier();
+        }
+
+        const int q = t - D;
+        if (q >= zb && q < ze && own) {
+            zo = zacc[0];
+            qo = q;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                acc0 = fma((double)rkeep[0].f[e], (double)zacc[0].f[e], acc0);
+                if (FIRST) acc1 = fma((double)rkeep[0].f[e], (double)rkeep[0].f[e], acc1);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            zacc[j] = zacc[j + 1];
+            rkeep[j] = rkeep[j + 1];
+        }
+        // plane t + 1 replaces plane t - 2 of r, last read by level 1 above
+        if (more) put_r(t + 1);
+        lds_barrier();
+    }
+    if (qo >= 0) stv<VEC>(dst + (size_t)qo * plane + (size_t)(y0 + jo) * nx, zo);
+
+    // block reduction of the float64 partials, fixed order
+    for (int o = 32; o > 0; o >>= 1) {
+        acc0 += __shfl_xor(acc0, o);
+        if (FIRST) acc1 += __shfl_xor(acc1, o);
+    }
+    __shared__ double s0[NW], s1[NW];
+    if (lane == 0) {
+        s0[w] = acc0;
+        s1[w] = acc1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double u0 = 0.0, u1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            u0 += s0[i];
+            u1 += s1[i];
+        }
+        a.P3[((size_t)f * 2 + (a.k & 1)) * a.pstride + blk] = u0;
+        if (FIRST) a.P1[((size_t)f * 2 + 1) * a.pstride + blk] = u1;
     }
 }
 
@@ -347,6 +578,57 @@ void launch_sweep(int mode, const Plan& p, const SweepArgs& a, hipStream_t s) {
     }
 }
 
+// LDS preconditioning sweep: TY = 8 rows per block of 16 waves (at most
+// one row per wave and level, so a level costs one LDS round trip).
+constexpr int kLdsTY = 8, kLdsNW = 16;
+
+constexpr int lds_precond_bytes(int vec, int deg) {
+    return 3 * 64 * vec * (deg * kLdsTY + deg * (deg + 1)) * 4;
+}
+
+template <int D>
+void launch_precond_lds_d(int vec, bool first, const Plan& q, const SweepArgs& a, hipStream_t s) {
+    const dim3 grid(q.nblocks), block(kLdsNW * 64);
+    if (vec == 4) {
+        if (first) hipLaunchKernelGGL((k_precond_lds<4, D, kLdsTY, kLdsNW, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_precond_lds<4, D, kLdsTY, kLdsNW, false>), grid, block, 0, s, a);
+    } else if (vec == 2) {
+        if (first) hipLaunchKernelGGL((k_precond_lds<2, D, kLdsTY, kLdsNW, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_precond_lds<2, D, kLdsTY, kLdsNW, false>), grid, block, 0, s, a);
+    } else {
+        if (first) hipLaunchKernelGGL((k_precond_lds<1, D, kLdsTY, kLdsNW, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_precond_lds<1, D, kLdsTY, kLdsNW, false>), grid, block, 0, s, a);
+    }
+}
+
+void launch_precond_lds(int deg, int vec, bool first, const Plan& q, const SweepArgs& a, hipStream_t s) {
+    if (deg == 4) launch_precond_lds_d<4>(vec, first, q, a, s);
+    else launch_precond_lds_d<3>(vec, first, q, a, s);
+}
+
+// Tiling of the LDS preconditioning sweep: ceil(ny / TY) row groups times z
+// chunks sized to give every compute unit its share of blocks (as many as
+// its 160 KB of LDS holds).  zc_raw: the chunk depth that fills the machine,
+// before the floor of 4 D planes (a chunk recomputes 2 D halo planes).
+Plan lds_plan(const HexGeom& g, int F, int vec, int deg, int zc_force, int* zc_raw) {
+    Plan p = {};
+    p.vec = vec;
+    p.ty = kLdsTY;
+    p.xsegs = 1;
+    p.ygroups = (g.ny + kLdsTY - 1) / kLdsTY;
+    const int per_cu = std::max(1, std::min(2048 / (kLdsNW * 64), (160 * 1024) / lds_precond_bytes(vec, deg)));
+    const int64_t want_blocks = (int64_t)256 * per_cu;
+    const int64_t cols = (int64_t)p.ygroups * F;
+    *zc_raw = (int)std::max<int64_t>(1, ((int64_t)g.nz * cols + want_blocks - 1) / want_blocks);
+    p.zc = zc_force > 0 ? zc_force : std::max(*zc_raw, 4 * deg);
+    p.zc = std::max(1, std::min(p.zc, g.nz));
+    p.zchunks = (g.nz + p.zc - 1) / p.zc;
+    p.bpf = p.ygroups * p.zchunks;
+    p.wpf = p.bpf * kLdsNW;
+    p.nblocks = p.bpf * F;
+    return p;
+}
+
 size_t small_bytes(int F, int bpf) {
     size_t b = kSmallFixed + 3 * (size_t)F * 2 * (size_t)bpf * sizeof(double);
     return (b + 255) & ~(size_t)255;
@@ -443,12 +725,33 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     // of poly_precond_coeffs: degree 2 where one wave covers a row (the sweep
     // keeps two halo rows and planes, tile_precond2; condition number 13 ->
     // 2.1 at dtau / h^2 = 1), degree 1 otherwise (13 -> 3.8).
+    // On grids large enough to give every compute unit a deep z chunk, the
+    // degree rises to 4 (13 -> 1.26), applied by k_precond_lds with the
+    // intermediate powers in LDS.  CGD_HEX_PRECOND_DEG (2, 3, 4) and
+    // CGD_HEX_LDS_ZC override the choice.
     const bool pcg = da.precond == 0;
-    const int deg = (pcg && !p.edge && p.xsegs == 1 && g.nx == 64 * p.vec) ? 2 : 1;
+    const bool row_wave = !p.edge && p.xsegs == 1 && g.nx == 64 * p.vec;
+    const int deg = (pcg && row_wave) ? 2 : 1;
     a.pcg = pcg ? 1 : 0;
     poly_precond_coeffs(a.g.cx, a.g.cy, a.g.cz, deg, &a.g.c0, &a.g.c1, &a.g.c2);
     const int mode_z_first = deg == 2 ? SZ2_FIRST : SZ_FIRST;
     const int mode_z = deg == 2 ? SZ2 : SZ;
+    int deg_lds = 0;
+    if (deg == 2) {
+        int want = 4, zc_force = 0, zc_raw = 0;
+        if (const char* e = getenv("CGD_HEX_PRECOND_DEG")) want = atoi(e);
+        if (const char* e = getenv("CGD_HEX_LDS_ZC")) zc_force = atoi(e);
+        if (want == 3 || want == 4) {
+            Plan pl = lds_plan(g, F, p.vec, want, zc_force, &zc_raw);
+            if ((zc_force > 0 || zc_raw >= 4 * want) && (size_t)pl.bpf <= max_bpf(g, F)) {
+                deg_lds = want;
+                pz = pl;
+                double c[8];
+                poly_precond_coeffs_n(a.g.cx, a.g.cy, a.g.cz, want, c);
+                for (int j = 0; j <= want; ++j) a.cp[j] = (float)c[j];
+            }
+        }
+    }
 
     // One sweep: its own plan, and the block count of the sweep whose
     // partial sums its prologue adds.
@@ -465,7 +768,8 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         if (is_z) a.bpf_in = p.bpf;                   // r.r (and b.b) of sweep 2 / the residual sweep
         else if (is_1) a.bpf_in = a.pcg ? pz.bpf : p.bpf;  // r.z of the preconditioning sweep, or r.r
         else a.bpf_in = p1.bpf;                       // p.Ap (and b.b) of sweep 1
-        launch_sweep(mode, q, a, s);
+        if (is_z && deg_lds) launch_precond_lds(deg_lds, p.vec, mode == mode_z_first, q, a, s);
+        else launch_sweep(mode, q, a, s);
     };
 
     const int sum_bpf = (int)std::min<int64_t>(1024, (cells + kBlock - 1) / kBlock);

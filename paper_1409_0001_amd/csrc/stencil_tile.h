@@ -299,6 +299,26 @@ __device__ __forceinline__ Vec<VEC> apply_row(const Geom& g, const Vec<VEC>& c, 
     return out;
 }
 
+// The same product with the x-neighbours of the lane's end cells given
+// (lft, rgt: already the cell itself at a wall).
+template <int VEC>
+__device__ __forceinline__ Vec<VEC> apply_row_lr(const Geom& g, const Vec<VEC>& c, float lft, float rgt,
+                                                 const Vec<VEC>& yl, const Vec<VEC>& yh, const Vec<VEC>& zl,
+                                                 const Vec<VEC>& zh) {
+    Vec<VEC> out;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        const float ce = c.f[e];
+        const float l = e > 0 ? c.f[e - 1] : lft;
+        const float r = e + 1 < VEC ? c.f[e + 1] : rgt;
+        const float c2 = ce + ce;
+        float v = fmaf(g.cx, (c2 - l) - r, ce);
+        v = fmaf(g.cy, (c2 - yl.f[e]) - yh.f[e], v);
+        out.f[e] = fmaf(g.cz, (c2 - zl.f[e]) - zh.f[e], v);
+    }
+    return out;
+}
+
 // Preconditioning sweep of degree 2: z = c0 r + c1 A r + c2 A (A r), both
 // products matrix-free.  The wave marches over z keeping r for planes z ..
 // z+2 with two halo rows on each side and A r for planes z-1 .. z+1 with one

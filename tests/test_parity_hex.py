@@ -225,3 +225,38 @@ def test_dense_bed_reduced_against_dct(gpu_lib):
     it1 = sum(sum(r) for r in st1.iters)
     print(f"iterations: preconditioned {st.iters}, plain {st1.iters}", flush=True)
     assert it0 <= 0.7 * it1, (it0, it1)
+
+
+@pytest.mark.parametrize("deg", [3, 4])
+@pytest.mark.parametrize("shape,zc", [((64, 37, 100), 16), ((128, 20, 70), 13), ((256, 13, 40), 7)])
+def test_lds_preconditioner_matches_oracle(gpu_lib, shape, zc, deg, monkeypatch):
+    """The degree-3/4 preconditioning sweep with its powers of A in LDS
+    (one wave per x-row: nx = 64, 128, 256), forced onto small grids with
+    ragged row groups (ny not a multiple of 8) and a ragged last z chunk:
+    the result matches the float64 DCT solution, and the higher degree
+    takes fewer iterations than degree 2."""
+    import torch
+    cgd = gpu_lib
+    nx, ny, nz = shape
+    lo, hi = (0.0, 0.0, 0.0), (nx / 64.0, ny / 64.0, nz / 64.0)
+    box = inputs.HexBox(lo, hi, shape)
+    p = inputs.uniform_bed(box, 50_000, 2, seed=77, diam=0.01)
+    b, steps = 4.0 / 64.0, 4  # dtau / h^2 = 1, as on the dense bed
+    print(f"case: lds preconditioner degree {deg}, {shape}, zc {zc}", flush=True)
+    mesh = cgd.HexMesh(shape, lo, hi)
+    pos, vals = _t(p.pos, torch), _t(p.values, torch)
+    monkeypatch.setenv("CGD_HEX_PRECOND_DEG", "2")
+    f2, st2 = cgd.coarse_grain(mesh, pos, vals, b, steps, rtol=1e-6, stats=True)
+    monkeypatch.setenv("CGD_HEX_PRECOND_DEG", str(deg))
+    monkeypatch.setenv("CGD_HEX_LDS_ZC", str(zc))
+    f4, st4 = cgd.coarse_grain(mesh, pos, vals, b, steps, rtol=1e-6, stats=True)
+    dep = O.deposit_hex(p.pos, p.values, lo, hi, shape)
+    ref = O.diffuse_hex_dct(dep["field64"], lo, hi, shape, b, steps)
+    o = f4.cpu().numpy()
+    for f in range(2):
+        assert rel_l2(o[f], ref[f]) <= REL_L2, (f, rel_l2(o[f], ref[f]))
+    assert st4.status == 0
+    it2 = sum(sum(r) for r in st2.iters)
+    it4 = sum(sum(r) for r in st4.iters)
+    print(f"iterations: degree 2 {st2.iters}, degree {deg} {st4.iters}", flush=True)
+    assert it4 < it2, (it2, it4)
