@@ -96,7 +96,8 @@ typedef struct {
                              3: the network `model`'s prediction from the previous
                                 pseudo-step's field, every step (hex meshes) */
     const float* x0;      /* device [F, cells] when x0_mode == 2, else NULL */
-    int32_t check_every;  /* iterations enqueued between convergence read-backs; <= 0: 4 */
+    int32_t check_every;  /* iterations enqueued between convergence read-backs once a step
+                             runs past the previous solve's count; <= 0: 4 */
     int32_t precond;      /* hex meshes: 0 (default) conjugate gradients preconditioned by
                              the degree-1 Chebyshev polynomial of A on its spectrum
                              [1, 1 + 4 sum_a c_a]; 1 plain CG.  Tet meshes use Jacobi
@@ -170,8 +171,12 @@ cgd_status cgd_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F,
  *  o:         solver options, nullable (defaults)
  *  st:        host, nullable: iteration counts, residuals, mass before/after
  *
- * The convergence test is read back every o->check_every iterations, so the
- * call returns to the host about when the last step has converged.  Returns
+ * The convergence test is read back one chunk of iterations late, so the
+ * device always has queued work: the first chunk of a step runs to the
+ * iteration at which the previous solve on this mesh stopped, the next holds
+ * one iteration, later ones o->check_every iterations (all of them
+ * o->check_every before a first solve).  The call returns to the host about
+ * when the last step has converged.  Returns
  * CGD_NOT_CONVERGED if some solve hit max_iter (result = last iterate) and
  * CGD_E_BREAKDOWN on a breakdown. */
 cgd_status cgd_diffuse(cgd_mesh m, int32_t F, float* field, double bandwidth,

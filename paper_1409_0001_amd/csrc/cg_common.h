@@ -15,7 +15,7 @@ constexpr int kCgBlock = 64 * kCgWaves;
 
 // Layout of the small region at the start of a mesh workspace (bytes).
 constexpr size_t kOffState = 0;                   // CgField[CGD_MAX_FIELDS]
-constexpr size_t kOffNdone = 4096;                // int
+constexpr size_t kOffNdone = 4096;                // int[2]: fields finished, largest stopping iteration
 constexpr size_t kOffIters = 8192;                // int32 [STEPS][FIELDS]
 constexpr size_t kOffRelres = kOffIters + 4096;   // double [STEPS][FIELDS]
 constexpr size_t kOffStatus = kOffRelres + 8192;  // int32 [STEPS][FIELDS]
@@ -25,7 +25,7 @@ constexpr size_t kOffDeposit = 48 * 1024;         // DepositInfo
 constexpr size_t kSmallFixed = 64 * 1024;         // partial sums follow
 
 // Layout of the pinned host buffer (bytes).
-constexpr size_t kPinFlags = 0;  // int[2]
+constexpr size_t kPinFlags = 0;  // int[2][2]: read-back slot, (fields finished, largest stopping iteration)
 constexpr size_t kPinIters = 4096;
 constexpr size_t kPinRelres = kPinIters + 4096;
 constexpr size_t kPinStatus = kPinRelres + 8192;
@@ -91,7 +91,10 @@ __device__ inline bool check_stop(const CgCtl& c, int f, int k, double rrk, doub
     if (lead) {
         c.iters[c.step * CGD_MAX_FIELDS + f] = k;
         c.relres[c.step * CGD_MAX_FIELDS + f] = bb > 0.0 ? sqrt(rrk / bb) : 0.0;
-        if (broken || conv) finish_field(c, f, broken ? CGD_E_BREAKDOWN : CGD_OK);
+        if (broken || conv) {
+            atomicMax(c.ndone + 1, k);
+            finish_field(c, f, broken ? CGD_E_BREAKDOWN : CGD_OK);
+        }
     }
     return broken || conv;
 }
@@ -112,10 +115,15 @@ void poly_precond_coeffs(double cx, double cy, double cz, int deg, float* c0, fl
 // The same polynomial for any degree 1..6: c[0..deg] (float64).
 void poly_precond_coeffs_n(double cx, double cy, double cz, int deg, double* c);
 
-// Host: enqueues iterations `chunk` at a time through `enqueue(it)` until the
-// device reports all F fields stopped (read back one chunk late, so the
-// device always has queued work) or max_iter iterations are queued.
-// Returns the index of the next iteration that would have been enqueued.
+// Host: enqueues iterations through `enqueue(it)` until the device reports
+// all F fields stopped (read back one chunk late, so the device always has
+// queued work) or max_iter iterations are queued.  The first chunk runs to
+// the iteration at which the previous solve on this mesh stopped
+// (m->cg_hint) and the next holds one iteration, so a solve that stops where
+// the last one did leaves one iteration of empty launches; later chunks, and
+// every chunk before a first solve, hold `chunk` iterations.  The stopping
+// iteration read back becomes the new hint.  Returns the index of the next
+// iteration that would have been enqueued.
 cgd_status cg_lookahead_loop(cgd_mesh m, int F, int it0, int max_iter, int chunk, const int* d_ndone,
                              hipStream_t s, const std::function<void(int)>& enqueue, int* it_end);
 

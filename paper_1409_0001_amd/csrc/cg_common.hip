@@ -13,7 +13,10 @@ __global__ void k_cg_step_init(CgField* st, int F, int* ndone, int32_t* status_r
         st[f] = s;
         status_row[f] = CGD_OK;
     }
-    if (threadIdx.x == 0) *ndone = 0;
+    if (threadIdx.x == 0) {
+        ndone[0] = 0;
+        ndone[1] = 0;
+    }
 }
 
 __global__ __launch_bounds__(kCgBlock) void k_cg_step_end(CgCtl c, const double* rr_part, size_t field_stride,
@@ -86,14 +89,21 @@ cgd_status cg_lookahead_loop(cgd_mesh m, int F, int it0, int max_iter, int chunk
     int slot = 0;
     bool have_prev = false;
     chunk = std::max(1, chunk);
-    for (;;) {
-        const int todo = std::min(chunk, max_iter - it);
+    const bool hinted = m->cg_hint >= it0;
+    for (int n = 0;; ++n) {
+        int size = chunk;
+        if (hinted && n == 0) size = m->cg_hint - it0 + 1;
+        else if (hinted && n == 1) size = 1;
+        const int todo = std::min(size, max_iter - it);
         for (int c = 0; c < todo; ++c, ++it) enqueue(it);
-        CGD_HIP_TRY(hipMemcpyAsync(&pinned_flags[slot], d_ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+        CGD_HIP_TRY(hipMemcpyAsync(&pinned_flags[2 * slot], d_ndone, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
         CGD_HIP_TRY(hipEventRecord(m->ev[slot], s));
         if (have_prev) {
             CGD_HIP_TRY(hipEventSynchronize(m->ev[slot ^ 1]));
-            if (pinned_flags[slot ^ 1] >= F) break;
+            if (pinned_flags[2 * (slot ^ 1)] >= F) {
+                m->cg_hint = pinned_flags[2 * (slot ^ 1) + 1];
+                break;
+            }
         }
         if (it >= max_iter) {
             CGD_HIP_TRY(hipEventSynchronize(m->ev[slot]));

@@ -688,7 +688,10 @@ void launch_precond_lds(int deg, int vec, bool first, const Plan& q, const Sweep
 // Tiling of the LDS preconditioning sweep: ceil(ny / TY) row groups times z
 // chunks sized to give every compute unit its share of blocks (as many as
 // its 160 KB of LDS holds).  zc_raw: the chunk depth that fills the machine,
-// before the floor of 4 D planes (a chunk recomputes 2 D halo planes).
+// before the floor of 2 D planes (a chunk recomputes 2 D halo planes).  The
+// sweep is used when zc_raw >= D: at 128^3 (zc 8) degree 4 takes 2.19 ms per
+// field against 2.57 for degree 2 in registers; at 256 x 256 x 512 (zc 64)
+// 6.93 against 10.31.
 Plan lds_plan(const HexGeom& g, int F, int vec, int deg, int zc_force, int* zc_raw) {
     Plan p = {};
     p.vec = vec;
@@ -699,7 +702,7 @@ Plan lds_plan(const HexGeom& g, int F, int vec, int deg, int zc_force, int* zc_r
     const int64_t want_blocks = (int64_t)256 * per_cu;
     const int64_t cols = (int64_t)p.ygroups * F;
     *zc_raw = (int)std::max<int64_t>(1, ((int64_t)g.nz * cols + want_blocks - 1) / want_blocks);
-    p.zc = zc_force > 0 ? zc_force : std::max(*zc_raw, 4 * deg);
+    p.zc = zc_force > 0 ? zc_force : std::max(*zc_raw, 2 * deg);
     p.zc = std::max(1, std::min(p.zc, g.nz));
     p.zchunks = (g.nz + p.zc - 1) / p.zc;
     p.bpf = p.ygroups * p.zchunks;
@@ -804,10 +807,10 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     // of poly_precond_coeffs: degree 2 where one wave covers a row (the sweep
     // keeps two halo rows and planes, tile_precond2; condition number 13 ->
     // 2.1 at dtau / h^2 = 1), degree 1 otherwise (13 -> 3.8).
-    // On grids large enough to give every compute unit a deep z chunk, the
-    // degree rises to 4 (13 -> 1.26), applied by k_precond_lds with the
-    // intermediate powers in LDS.  CGD_HEX_PRECOND_DEG (2, 3, 4) and
-    // CGD_HEX_LDS_ZC override the choice.
+    // Where the grid fills the machine with z chunks of at least D planes
+    // (lds_plan), the degree rises to 4 (13 -> 1.26), applied by
+    // k_precond_lds with the intermediate powers in LDS.
+    // CGD_HEX_PRECOND_DEG (2, 3, 4) and CGD_HEX_LDS_ZC override the choice.
     const bool pcg = da.precond == 0;
     const bool row_wave = !p.edge && p.xsegs == 1 && g.nx == 64 * p.vec;
     const int deg = (pcg && row_wave) ? 2 : 1;
@@ -822,7 +825,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         if (const char* e = getenv("CGD_HEX_LDS_ZC")) zc_force = atoi(e);
         if (want == 3 || want == 4) {
             Plan pl = lds_plan(g, F, p.vec, want, zc_force, &zc_raw);
-            if ((zc_force > 0 || zc_raw >= 4 * want) && (size_t)pl.bpf <= max_bpf(g, F)) {
+            if ((zc_force > 0 || zc_raw >= want) && (size_t)pl.bpf <= max_bpf(g, F)) {
                 deg_lds = want;
                 pz = pl;
                 double c[8];

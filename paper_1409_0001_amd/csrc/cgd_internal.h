@@ -96,6 +96,7 @@ struct cgd_mesh_s {
     size_t pinned_bytes = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
     cgd::Timing timing;
+    int32_t cg_hint = -1;          // iteration at which the last CG solve on this mesh stopped (-1: none yet)
 };
 
 namespace cgd {
