@@ -196,8 +196,9 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F,
  *
  * Deposition follows cgd_deposit per snapshot (its own fixed-point scale per
  * snapshot and field).  All n_snap * F right-hand sides are then solved from
- * a zero initial guess by CG preconditioned with the degree-2 Chebyshev
- * polynomial of the operator (o->precond = 1: plain CG), with float32
+ * a zero initial guess by CG preconditioned with a Chebyshev polynomial of
+ * the operator, of degree 2 or 4 as the autotuner chose (o->precond = 1:
+ * plain CG), with float32
  * vectors, float64 inner products, and the stencil and stopping rule of
  * cgd_diffuse, in ONE persistent launch in which each workgroup solves its
  * share of the right-hand sides one after the other.  The
@@ -220,10 +221,12 @@ cgd_status cgd_coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* o
                                     double bandwidth, int32_t n_steps, const cgd_solver_opts* o,
                                     float* fields, int32_t* iters, void* stream);
 
-/* Autotuner of the batched solver: times each candidate tile shape (rows per
- * wave, waves per workgroup) on n_rhs synthetic right-hand sides and keeps
- * the fastest for this mesh shape (also appended to the file named by the
- * environment variable CGD_AUTOTUNE_CACHE, when set, and read from it).
+/* Autotuner of the batched solver: times each candidate (rows per wave,
+ * waves per workgroup, preconditioner degree 2 or 4) solving n_rhs synthetic
+ * right-hand sides for one backward-Euler step at dtau / h^2 = 1 to rtol
+ * 1e-6, and keeps the fastest for this mesh shape (also appended to the file
+ * named by the environment variable CGD_AUTOTUNE_CACHE, when set, and read
+ * from it).
  *  chosen: host, written with the chosen candidate index
  *  ms:     host double [8] or NULL: time of each candidate (forces a re-run)
  *  n_cand: host, written with the number of candidates (nullable) */

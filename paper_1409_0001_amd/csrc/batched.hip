@@ -11,11 +11,13 @@
 // use the same stencil tiles as the per-launch solver.  The whole call
 // (offset upload, deposit, solve, status read-back) is captured once in a
 // hipGraph per argument set and replayed.  The tile shape (rows per wave,
-// waves per workgroup) comes from an autotuner that times every candidate on
-// the device and caches the choice per mesh shape (and in the file named by
-// CGD_AUTOTUNE_CACHE, when set).
+// waves per workgroup) and the preconditioner's degree (2 in registers, 4
+// through the LDS sweep of precond_lds.h) come from an autotuner that times
+// every candidate on the device and caches the choice per mesh shape (and in
+// the file named by CGD_AUTOTUNE_CACHE, when set).
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -25,6 +27,7 @@
 
 #include "cg_common.h"
 #include "hex_bin.h"
+#include "precond_lds.h"
 #include "stencil_tile.h"
 
 namespace cgd {
@@ -146,7 +149,8 @@ __global__ __launch_bounds__(kDBlock) void k_bfinalize(BDep d) {
 struct BSolve {
     float* fields;      // [n_rhs][cells]: in deposited, out diffused
     float* ws;          // [grid][5][cells]
-    int pcg;            // 1: CG preconditioned by the degree-2 polynomial (Geom c0, c1, c2)
+    int pcg;            // 1: preconditioned CG (degree 2: Geom c0, c1, c2; degree 4: cp)
+    float cp[8];        // degree-4 polynomial (configurations with DEG = 4)
     int n_rhs;
     int64_t cells;
     Geom g;
@@ -217,13 +221,36 @@ __device__ inline void wg_precond(const BSolve& a, const Ptrs& p, double& s0, do
     s1 = acc1;
 }
 
+// z = p(A) r with the degree-4 polynomial, tile by tile (8 rows of y, all of
+// z) through the LDS sweep of precond_lds.h; r.z (and r.r when FIRST).
+template <int VEC, int NW, bool FIRST>
+__device__ inline void wg_precond_lds(float* lds, const BSolve& a, const Ptrs& p, double& s0, double& s1,
+                                      double (*sh)[2]) {
+    double acc0 = 0.0, acc1 = 0.0;
+    const int tiles = (a.g.ny + 7) / 8;
+    for (int t = 0; t < tiles; ++t)
+        precond_lds_tile<VEC, 4, 8, NW, FIRST>(lds, FIRST ? p.B : p.R, p.Z, a.g, a.cp, a.g.ny, a.g.nz, 8 * t, 0,
+                                               a.g.nz, acc0, acc1);
+    wg_sum2<NW>(acc0, acc1, sh);
+    s0 = acc0;
+    s1 = acc1;
+}
+
+template <int VEC, int TY, int NW, int DEG, bool FIRST>
+__device__ inline void wg_precondition(float* lds, const BSolve& a, const Ptrs& p, double& s0, double& s1,
+                                       double (*sh)[2]) {
+    if constexpr (DEG == 4) wg_precond_lds<VEC, NW, FIRST>(lds, a, p, s0, s1, sh);
+    else wg_precond<VEC, TY, NW, FIRST>(a, p, s0, s1, sh);
+}
+
 // Right-hand sides are dealt to workgroups statically (rhs = blockIdx.x,
 // blockIdx.x + gridDim.x, ...), so every loop of this kernel is controlled by
 // wave-uniform values: no lane of a wave ever waits at a barrier for another
 // lane of the same wave that took a different path.
-template <int VEC, int TY, int NW>
+template <int VEC, int TY, int NW, int DEG>
 __global__ __launch_bounds__(64 * NW) void k_batched_cg(BSolve a) {
     __shared__ double sh[NW][2];
+    __shared__ __align__(16) float lds[DEG == 4 ? precond_lds_floats<VEC, 4, 8>() : 4];
     const size_t cells = (size_t)a.cells;
     float* W0 = a.ws + (size_t)blockIdx.x * 5 * cells;
     float* R = W0 + cells;
@@ -236,13 +263,13 @@ __global__ __launch_bounds__(64 * NW) void k_batched_cg(BSolve a) {
         float* nxt = W0;
         int worst = CGD_OK;
         for (int step = 0; step < a.n_steps; ++step) {
-            if (a.pcg) {
+            if (DEG == 4 || a.pcg) {  // degree-4 configurations run preconditioned CG only
                 // preconditioned CG from x = 0: z = M b, p = z, x = alpha p, r = b - alpha A p
                 Ptrs p{cur, R, nullptr, PA, nxt, Z};
                 Ptrs q = p;  // the direction sweeps read z through Ptrs::R
                 q.R = Z;
                 double rho, bb, pap, rr, dummy;
-                wg_precond<VEC, TY, NW, true>(a, p, rho, bb, sh);
+                wg_precondition<VEC, TY, NW, DEG, true>(lds, a, p, rho, bb, sh);
                 wg_sweep<VEC, TY, NW, S1_B0>(a, q, 0.f, 0.f, pap, dummy, sh);
                 bool broken = !isfinite(bb) || !isfinite(pap) || !isfinite(rho) || (bb > 0.0 && !(pap > 0.0));
                 float alpha = (broken || bb == 0.0) ? 0.f : (float)(rho / pap);
@@ -260,7 +287,7 @@ __global__ __launch_bounds__(64 * NW) void k_batched_cg(BSolve a) {
                         break;
                     }
                     double rho_new;
-                    wg_precond<VEC, TY, NW, false>(a, p, rho_new, dummy, sh);
+                    wg_precondition<VEC, TY, NW, DEG, false>(lds, a, p, rho_new, dummy, sh);
                     q.Pold = (k & 1) ? PA : PB;
                     q.Pnew = (k & 1) ? PB : PA;
                     wg_sweep<VEC, TY, NW, S1>(a, q, 0.f, (float)(rho_new / rho), pap, dummy, sh);
@@ -281,6 +308,7 @@ __global__ __launch_bounds__(64 * NW) void k_batched_cg(BSolve a) {
                 nxt = t;
                 continue;
             }
+            if constexpr (DEG == 4) continue;
             Ptrs p{cur, R, nullptr, nullptr, nxt, nullptr};
             double bab, bb, rr, dummy;
             wg_sweep<VEC, TY, NW, S1_FIRST>(a, p, 0.f, 0.f, bab, bb, sh);
@@ -345,21 +373,28 @@ __global__ void k_fill_synthetic(float* f, int64_t n) {
 // ---------------------------------------------------------------- configs
 
 struct Cfg {
-    int vec, ty, nw;
+    int vec, ty, nw, deg;
     const void* fn;
 };
 
-template <int VEC, int TY, int NW>
+template <int VEC, int TY, int NW, int DEG>
 Cfg make_cfg() {
-    return Cfg{VEC, TY, NW, reinterpret_cast<const void*>(&k_batched_cg<VEC, TY, NW>)};
+    return Cfg{VEC, TY, NW, DEG, reinterpret_cast<const void*>(&k_batched_cg<VEC, TY, NW, DEG>)};
 }
 
+// Tile shapes of the CG sweeps (rows per wave, waves per workgroup) and the
+// preconditioner degree: 2 in registers (rows per wave small enough that its
+// queues fit without spilling at 16 waves), or 4 through the LDS sweep (16
+// waves, 8 rows of y per tile).
 std::vector<Cfg> candidates(int vec) {
-    // rows per wave are kept small enough that the preconditioning sweep's
-    // register queues fit without spilling at 16 waves (1024 threads)
-    if (vec == 4) return {make_cfg<4, 1, 8>(), make_cfg<4, 1, 16>(), make_cfg<4, 2, 8>(), make_cfg<4, 2, 12>()};
-    if (vec == 2) return {make_cfg<2, 2, 8>(), make_cfg<2, 2, 16>(), make_cfg<2, 4, 8>(), make_cfg<2, 4, 12>()};
-    return {make_cfg<1, 4, 8>(), make_cfg<1, 4, 16>(), make_cfg<1, 8, 8>(), make_cfg<1, 8, 16>()};
+    if (vec == 4)
+        return {make_cfg<4, 1, 8, 2>(), make_cfg<4, 1, 16, 2>(), make_cfg<4, 2, 8, 2>(), make_cfg<4, 2, 12, 2>(),
+                make_cfg<4, 1, 16, 4>(), make_cfg<4, 2, 16, 4>()};
+    if (vec == 2)
+        return {make_cfg<2, 2, 8, 2>(), make_cfg<2, 2, 16, 2>(), make_cfg<2, 4, 8, 2>(), make_cfg<2, 4, 12, 2>(),
+                make_cfg<2, 2, 16, 4>(), make_cfg<2, 4, 16, 4>()};
+    return {make_cfg<1, 4, 8, 2>(), make_cfg<1, 4, 16, 2>(), make_cfg<1, 8, 8, 2>(), make_cfg<1, 8, 16, 2>(),
+            make_cfg<1, 4, 16, 4>(), make_cfg<1, 8, 16, 4>()};
 }
 
 int batched_vec(const HexGeom& g) {
@@ -477,7 +512,8 @@ void destroy_batched(cgd_mesh m) {
 }
 
 // Times every candidate on min(n_rhs, resident) synthetic right-hand sides
-// (one backward-Euler step, a fixed 12 iterations) and returns the fastest.
+// (one backward-Euler step at dtau / h^2 = 1, solved to rtol 1e-6) and
+// returns the fastest.
 cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, int* n_cand) {
     const HexGeom& g = m->hex;
     const int vec = batched_vec(g);
@@ -530,9 +566,16 @@ cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, 
     a.g.cx = a.g.cy = a.g.cz = 1.0f;
     a.pcg = 1;  // the default solver is what gets tuned
     poly_precond_coeffs(1.0, 1.0, 1.0, 2, &a.g.c0, &a.g.c1, &a.g.c2);
+    {
+        double c4[8];
+        poly_precond_coeffs_n(1.0, 1.0, 1.0, 4, c4);
+        for (int j = 0; j <= 4; ++j) a.cp[j] = (float)c4[j];
+    }
+    // time to solution (rtol 1e-6), so that candidates of different
+    // preconditioner degree compare fairly
     a.n_steps = 1;
-    a.rtol2 = 0.0;  // run the full iteration budget
-    a.max_iter = 12;
+    a.rtol2 = 1e-12;
+    a.max_iter = 100;
     a.iters = iters;
     a.status = status;
     double best = 1e30;
@@ -586,7 +629,24 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     int ci = 0;
     cgd_status rc = autotune_batched(m, n_rhs, &ci, nullptr, nullptr);
     if (rc != CGD_OK) return rc;
-    const Cfg c = candidates(batched_vec(g))[ci];
+    const std::vector<Cfg> cands = candidates(batched_vec(g));
+    if (const char* e = getenv("CGD_BATCHED_CFG")) {  // a fixed candidate, for tests and tuning runs
+        const int v = atoi(e);
+        if (v >= 0 && v < (int)cands.size()) ci = v;
+    }
+    Cfg c = cands[ci];
+    if (da.precond != 0 && c.deg == 4) {
+        // plain CG: the degree-2 configuration of the same shape (else the
+        // 16-wave one), whose kernel carries the unpreconditioned path
+        int alt = -1;
+        for (int i = 0; i < (int)cands.size(); ++i)
+            if (cands[i].deg == 2 && cands[i].ty == c.ty && cands[i].nw == c.nw) alt = i;
+        if (alt < 0)
+            for (int i = 0; i < (int)cands.size(); ++i)
+                if (cands[i].deg == 2 && cands[i].nw == 16) alt = i;
+        ci = alt;
+        c = cands[ci];
+    }
     const int grid = grid_for(c, n_rhs);
     const BLayout L = batched_layout(n_rhs, n_snap, da.n_steps);
     const size_t small = L.small;
@@ -651,6 +711,11 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     a.g.cz = (float)(dtau / (g.h[2] * g.h[2]));
     a.pcg = da.precond == 0 ? 1 : 0;
     poly_precond_coeffs(a.g.cx, a.g.cy, a.g.cz, 2, &a.g.c0, &a.g.c1, &a.g.c2);
+    {
+        double c4[8];
+        poly_precond_coeffs_n(a.g.cx, a.g.cy, a.g.cz, 4, c4);
+        for (int j = 0; j <= 4; ++j) a.cp[j] = (float)c4[j];
+    }
     a.xsegs = 1;
     a.ygroups = (g.ny + c.ty - 1) / c.ty;
     a.n_steps = da.n_steps;

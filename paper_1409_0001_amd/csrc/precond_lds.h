@@ -1,0 +1,259 @@
+// Polynomial preconditioning sweep of a uniform hex grid with the powers of
+// A in LDS: one block's tile (TY rows of y, planes [zb, ze)), shared by the
+// per-launch solver (cg_hex.hip) and the persistent batched one
+// (batched.hip).  Requires nx = 64 VEC (one wave per x-row).
+#pragma once
+
+#include "stencil_tile.h"
+
+namespace cgd {
+namespace stencil {
+
+// LDS barrier that waits only for this wave's LDS operations, so global
+// loads issued ahead (the prefetched planes) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// x-neighbours of a lane's end cells across the wave (DPP wave shifts): the
+// last cell of the lane below and the first cell of the lane above; lanes 0
+// and 63 keep their own end cell (the wall rule).
+template <int VEC>
+__device__ __forceinline__ void x_neighbours(const Vec<VEC>& c, float& lft, float& rgt) {
+    lft = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(c.f[0]), __float_as_int(c.f[VEC - 1]),
+                                                     0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+    rgt = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(c.f[VEC - 1]), __float_as_int(c.f[0]),
+                                                     0x130 /* wave_shl:1 */, 0xf, 0xf, false));
+}
+
+// z = p(A) r with p(l) = sum_j cp[j] l^j,
+// evaluated by Horner's rule, u_D = cp[D] r, u_j = cp[j] r + A u_{j+1},
+// z = u_0, every product matrix-free.  A block of NW waves owns TY rows of y
+// (one wave per x-row, nx = 64 VEC) and marches over its z chunk.  u_{D-j}
+// is needed up to D - j rows and planes away from the block's output, so
+// wave w handles the row y0 - D + w at every level whose extent holds it.
+// At step t, level j forms u_{D-j} of plane q = t - j: the row's own values
+// of the previous level at planes q-1, q, q+1 come from the wave's
+// registers (it formed them at steps t-2, t-1, t), the rows above and below
+// at plane q from LDS, where their waves wrote them at step t-1, and the
+// x-neighbours from DPP shifts; each level's LDS holds two planes (written at
+// steps of one parity, read at the next), so a step needs one barrier.  The
+// steps are unrolled by 6 so that every register ring (r: 6 planes, levels:
+// 3 planes) is indexed at compile time.  r enters LDS through the waves that
+// own no output row: they keep P planes of loads in flight and never store,
+// while the output waves only store, so neither kind waits for the other's
+// memory operations.  Rows and planes beyond a wall take the cell itself
+// (the wall rule): rows by pointing at the cell's own row, planes through
+// per-plane coefficients.  FIRST: the input is b (zero initial guess) and
+// b.b is accumulated as well.
+// First LDS row of level j (rows of TY + 2 (D - i) per plane; 3 planes for
+// levels 0 and 1, 2 planes above).
+template <int D, int TY>
+__host__ __device__ constexpr int lds_level_base(int j) {
+    int rows = 0;
+    for (int i = 0; i < j; ++i) rows += (i <= 1 ? 3 : 2) * (TY + 2 * (D - i));
+    return rows;
+}
+
+// LDS floats a tile needs: levels 0..D-1 (precond_lds_tile's `lds`).
+template <int VEC, int D, int TY>
+__host__ __device__ constexpr int precond_lds_floats() {
+    return lds_level_base<D, TY>(D) * 64 * VEC;
+}
+
+// lds: precond_lds_floats<VEC, D, TY>() floats of LDS, 16-byte aligned.
+template <int VEC, int D, int TY, int NW, bool FIRST>
+__device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __restrict__ src_field,
+                                        float* __restrict__ dst_field, const Geom& g, const float* cp, int ny, int nz,
+                                        int y0, int zb, int ze, double& acc0, double& acc1) {
+    constexpr int NXR = 64 * VEC;
+    constexpr int E0 = TY + 2 * D;
+    constexpr int NL = NW - TY;                  // waves owning no output row: the loaders
+    constexpr int RPL = (E0 + NL - 1) / NL;      // rows of r per loader
+    constexpr int P = 2;                         // planes of r in flight per loader
+    static_assert(E0 <= NW, "one row per wave covers every level");
+    static_assert(RPL <= 2, "loaders hold at most two rows");
+    // LDS: level 0 (r) and level 1 keep 3 planes of TY + 2 (D - j) rows,
+    // levels 2..D-1 two (level 2 reads its own row's level-1 neighbours from
+    // LDS, which saves that level's register ring)
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int nx = NXR;
+    const int x0 = lane * VEC;
+    const size_t plane = (size_t)nx * ny;
+
+    // this wave's row; it is in level j's extent (extent row w - j) iff
+    // j <= w < TY + 2 D - j
+    const int yw = y0 - D + w;
+    const bool in_dom = w < E0 && yw >= 0 && yw < ny;
+    const bool has_yd = yw > 0, has_yu = yw + 1 < ny;
+    const bool owner = w >= D && w < D + TY;  // an output row (written if yw < ny)
+    const int li = w < D ? w : w - TY;        // loader index (non-owners)
+
+    auto row = [&](int j, int q, int e) -> float* {  // level j, plane q, extent row e
+        const int slot = j <= 1 ? q % 3 : (q & 1);
+        return lds + (lds_level_base<D, TY>(j) + slot * (TY + 2 * (D - j)) + e) * NXR + x0;
+    };
+    auto row0 = [&](int q, int e) -> float* { return row(0, q, e); };
+    auto rowj = [&](int j, int q, int e) -> float* { return row(j, q, e); };
+    auto ld = [](const float* r) {  // row starts are 16-byte aligned: one LDS access per row
+        return ldv<VEC>(static_cast<const float*>(__builtin_assume_aligned(r, 4 * VEC)));
+    };
+    const float* src = src_field + x0;
+    auto ysrc = [&](int e) {  // clamped row of extent row e of level 0
+        const int y = min(max(y0 - D + e, 0), ny - 1);
+        return (size_t)y * nx;
+    };
+
+    const int t0 = max(0, zb - D);
+    const int tl = min(nz, ze + D) - 1;  // last plane of r needed
+    const int t1 = ze - 1 + D;           // last step (plane ze - 1 of z completes)
+    const float cx = g.cx, cy = g.cy, cz = g.cz;
+    const float d_in = 1.f + 2.f * (cx + cy + cz);
+
+    Vec<VEC> rk[6];                         // r of this row, plane t0 + s at slot s mod 6
+    Vec<VEC> lv[D > 2 ? D - 2 : 1][3];      // level j >= 2's u of this row, plane t0 + s at slot s mod 3
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) rk[i].f[e] = 0.f;
+#pragma unroll
+    for (int j = 0; j < D - 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) lv[j][i].f[e] = 0.f;
+
+    // one step at t = t0 + S (mod 6); LOADER: the wave feeds r into LDS
+    auto step = [&](auto S_, auto LOADER_, int t, Vec<VEC> (&pf)[P][RPL]) {
+        constexpr int S = decltype(S_)::value;
+        constexpr bool LOADER = decltype(LOADER_)::value;
+        if constexpr (LOADER) {
+            // plane t + 1 (in flight since step t + 1 - P) into LDS, then
+            // the load of plane t + 1 + P into the freed buffer
+            constexpr int B = (S + 1) % P;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int e = li + NL * i;
+                if (e < E0) stv<VEC>(row0(t + 1, e), pf[B][i]);
+            }
+            const int tn = min(t + 1 + P, tl);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int e = min(li + NL * i, E0 - 1);
+                pf[B][i] = ldv<VEC>(src + (size_t)tn * plane + ysrc(e));
+            }
+        }
+        if (w < E0) rk[S % 6] = ld(row0(t, w));  // own row of r at plane t (written at step t - 1)
+
+#pragma unroll
+        for (int j = 1; j <= D; ++j) {
+            const int q = t - j;
+            const bool go = in_dom && j <= w && w < E0 - j && q >= max(0, zb - (D - j)) && q < min(nz, ze + (D - j));
+            Vec<VEC> u;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) u.f[e] = 0.f;
+            if (go) {
+                // previous level's u of this row at planes q - 1, q, q + 1:
+                // r from the register ring, level 1 from LDS, level >= 2 from
+                // its register ring
+                Vec<VEC> c, zl, zh;
+                if (j == 1) {
+                    c = rk[((S - j) % 6 + 6) % 6];
+                    zl = rk[((S - j - 1) % 6 + 6) % 6];
+                    zh = rk[((S - j + 1) % 6 + 6) % 6];
+                } else if (j == 2) {
+                    c = ld(row(1, q, w - 1));
+                    zl = ld(row(1, q > 0 ? q - 1 : q, w - 1));
+                    zh = ld(row(1, q + 1 < nz ? q + 1 : q, w - 1));  // never a plane not formed
+                } else {
+                    const int jr = j >= 3 ? j - 3 : 0;  // ring of level j - 1
+                    c = lv[jr][((S - j) % 3 + 3) % 3];
+                    zl = lv[jr][((S - j - 1) % 3 + 3) % 3];
+                    zh = lv[jr][((S - j + 1) % 3 + 3) % 3];
+                }
+                const Vec<VEC>& rq = rk[((S - j) % 6 + 6) % 6];  // r of this row at plane q
+                // rows y - 1, y + 1 of the previous level at plane q (this row itself at a wall)
+                Vec<VEC> ys = ld(row(j - 1, q, has_yd ? w - j : w - j + 1));
+                {
+                    const Vec<VEC> yh = ld(row(j - 1, q, has_yu ? w - j + 2 : w - j + 1));
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) ys.f[e] += yh.f[e];
+                }
+                float lft, rgt;
+                x_neighbours<VEC>(c, lft, rgt);
+                const bool hzd = q > 0, hzu = q + 1 < nz;
+                const float czd = hzd ? cz : 0.f, czu = hzu ? cz : 0.f;
+                const float dq = d_in - (hzd ? 0.f : cz) - (hzu ? 0.f : cz);
+                const float cr = cp[D - j];
+                const float ca = j == 1 ? cp[D] : 1.f;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const float l = e > 0 ? c.f[e - 1] : lft;
+                    const float r = e + 1 < VEC ? c.f[e + 1] : rgt;
+                    float v = dq * c.f[e];
+                    v = fmaf(-cx, l + r, v);
+                    v = fmaf(-cy, ys.f[e], v);
+                    v = fmaf(-czd, zl.f[e], v);
+                    v = fmaf(-czu, zh.f[e], v);
+                    u.f[e] = fmaf(ca, v, cr * rq.f[e]);  // cp[D-j] r + A u_prev (A (cp[D] r) at j = 1)
+                }
+                if (j < D) stv<VEC>(rowj(j, q, w - j), u);
+            }
+            if (j >= 2 && j < D) lv[j >= 2 ? j - 2 : 0][((S - j) % 3 + 3) % 3] = u;
+            if (j == D && go && owner && q >= zb && q < ze) {
+                // z of plane q complete: store it and add its r.z (and b.b)
+                stv<VEC>(dst_field + x0 + (size_t)q * plane + (size_t)yw * nx, u);
+                const Vec<VEC>& rq = rk[((S - D) % 6 + 6) % 6];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    acc0 = fma((double)rq.f[e], (double)u.f[e], acc0);
+                    if (FIRST) acc1 = fma((double)rq.f[e], (double)rq.f[e], acc1);
+                }
+            }
+        }
+        lds_barrier();
+    };
+
+    auto run = [&](auto LOADER_) {
+        constexpr bool LOADER = decltype(LOADER_)::value;
+        Vec<VEC> pf[P][RPL];
+        if constexpr (LOADER) {
+            // planes t0 .. t0 + P - 1 in flight; plane t0 into LDS; t0 + P replaces it
+#pragma unroll
+            for (int s = 0; s < P; ++s)
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    const int e = min(li + NL * i, E0 - 1);
+                    pf[s][i] = ldv<VEC>(src + (size_t)min(t0 + s, tl) * plane + ysrc(e));
+                }
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int e = li + NL * i;
+                if (e < E0) stv<VEC>(row0(t0, e), pf[0][i]);
+            }
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int e = min(li + NL * i, E0 - 1);
+                pf[0][i] = ldv<VEC>(src + (size_t)min(t0 + P, tl) * plane + ysrc(e));
+            }
+        }
+        lds_barrier();
+        for (int t = t0; t <= t1; t += 6) {
+            step(std::integral_constant<int, 0>{}, LOADER_, t, pf);
+            if (t + 1 > t1) break;
+            step(std::integral_constant<int, 1>{}, LOADER_, t + 1, pf);
+            if (t + 2 > t1) break;
+            step(std::integral_constant<int, 2>{}, LOADER_, t + 2, pf);
+            if (t + 3 > t1) break;
+            step(std::integral_constant<int, 3>{}, LOADER_, t + 3, pf);
+            if (t + 4 > t1) break;
+            step(std::integral_constant<int, 4>{}, LOADER_, t + 4, pf);
+            if (t + 5 > t1) break;
+            step(std::integral_constant<int, 5>{}, LOADER_, t + 5, pf);
+        }
+    };
+    if (owner) run(std::false_type{});
+    else run(std::true_type{});
+
+}
+
+}  // namespace stencil
+}  // namespace cgd

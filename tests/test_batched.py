@@ -137,8 +137,35 @@ def test_autotune_reports_candidates(gpu_lib):
     cgd = gpu_lib
     mesh = cgd.HexMesh((128, 64, 32))
     chosen, ms = cgd.autotune_batched(mesh, 32)
-    assert len(ms) == 4 and all(t > 0 for t in ms)
+    assert len(ms) == 6 and all(t > 0 for t in ms)  # 4 tile shapes at degree 2, 2 at degree 4
     assert chosen == int(np.argmin(ms))
+
+
+@pytest.mark.parametrize("cfg", [1, 4, 5])  # degree 2 (16 waves); degree 4, both tile shapes
+def test_batched_candidates_match_oracle(gpu_lib, cfg, monkeypatch):
+    """Every preconditioner degree of the persistent solver reaches the same
+    fields: forced candidates against the float64 oracle on 128 x 20 x 24
+    (ragged row groups and tiles)."""
+    import torch
+    cgd = gpu_lib
+    shape = (128, 20, 24)
+    box = inputs.HexBox((0.0, 0.0, 0.0), (1.0, 20 / 128, 24 / 128), shape)
+    snaps = [inputs.uniform_bed(box, 3000 + 500 * j, 2, seed=90 + j, diam=0.01) for j in range(3)]
+    off = np.concatenate([[0], np.cumsum([len(p.pos) for p in snaps])]).astype(np.int64)
+    pos = torch.from_numpy(np.concatenate([p.pos for p in snaps])).cuda()
+    vals = torch.from_numpy(np.concatenate([p.values for p in snaps], axis=1)).cuda()
+    mesh = cgd.HexMesh(shape, box.lo, box.hi)
+    monkeypatch.setenv("CGD_BATCHED_CFG", str(cfg))
+    b, steps = 4.0 / 128, 4
+    print(f"case: batched candidate {cfg}, {shape}", flush=True)
+    out, iters = cgd.coarse_grain_batched(mesh, off, pos, vals, b, steps, rtol=1e-7, return_iters=True)
+    o = out.cpu().numpy()
+    for j, p in enumerate(snaps):
+        dep = O.deposit_hex(p.pos, p.values, box.lo, box.hi, shape)
+        ref = O.diffuse_hex_dct(dep["field64"], box.lo, box.hi, shape, b, steps)
+        for f in range(2):
+            assert rel_l2(o[j, f], ref[f]) <= 1e-5, (cfg, j, f, rel_l2(o[j, f], ref[f]))
+    print("iterations per step", iters.reshape(-1, steps).mean(axis=0), flush=True)
 
 
 def test_batched_invalid(gpu_lib):
