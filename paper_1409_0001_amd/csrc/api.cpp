@@ -114,20 +114,23 @@ struct DeviceGuard {
 };
 
 // Workspace use of a deposit: the counters sit at kOffDeposit (a part of
-// the small region the diffusion does not use), the int64 accumulators (when
-// the caller passes none) from kSmallFixed on.  The diffusion that follows in
-// cgd_coarse_grain reuses that memory only after the finalising kernel has
-// read it, in stream order.
-static cgd_status deposit_buffers(cgd_mesh m, int32_t F, int64_t* user_acc, int64_t** acc,
-                                  DepositInfo** info) {
-    size_t acc_bytes = user_acc ? 0 : (size_t)F * m->cells * sizeof(int64_t);
-    size_t need = kSmallFixed + acc_bytes;
+// the small region the diffusion does not use); from kSmallFixed on, either
+// the bucketing scratch of the tiled hex deposit or the int64 accumulators
+// of the direct path (when the caller passes none).  The diffusion that
+// follows in cgd_coarse_grain reuses that memory only after the deposit's
+// last kernel has read it, in stream order.
+static cgd_status deposit_buffers(cgd_mesh m, int64_t n, int32_t F, int64_t* user_acc, int64_t** acc,
+                                  DepositInfo** info, void** temp) {
+    const size_t tiled = m->kind == 0 ? deposit_hex_temp_bytes(m, n, F) : 0;
+    size_t acc_bytes = (user_acc || tiled) ? 0 : (size_t)F * m->cells * sizeof(int64_t);
+    size_t need = kSmallFixed + acc_bytes + tiled;
     size_t diff = m->kind == 0 ? diffuse_hex_workspace(m, F) : diffuse_tet_workspace(m, F);
     cgd_status rc = ensure_workspace(m, need > diff ? need : diff);
     if (rc != CGD_OK) return rc;
     char* base = static_cast<char*>(m->ws.ptr);
     *info = reinterpret_cast<DepositInfo*>(base + kOffDeposit);
-    *acc = user_acc ? user_acc : reinterpret_cast<int64_t*>(base + kSmallFixed);
+    *temp = tiled ? base + kSmallFixed : nullptr;
+    *acc = user_acc ? user_acc : (tiled ? nullptr : reinterpret_cast<int64_t*>(base + kSmallFixed));
     return CGD_OK;
 }
 
@@ -277,10 +280,11 @@ static cgd_status do_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F,
                              float* field, int64_t* acc, cgd_solve_stats* st, hipStream_t s) {
     int64_t* acc_buf;
     DepositInfo* info;
-    cgd_status rc = deposit_buffers(m, F, acc, &acc_buf, &info);
+    void* temp;
+    cgd_status rc = deposit_buffers(m, n, F, acc, &acc_buf, &info, &temp);
     if (rc != CGD_OK) return rc;
     if (m->kind == 0)
-        rc = deposit_hex(m, n, pos, F, values, field, acc_buf, info, s);
+        rc = deposit_hex(m, n, pos, F, values, field, acc_buf, info, temp, s);
     else
         rc = deposit_tet(m, n, pos, F, values, field, acc_buf, info, s);
     if (rc != CGD_OK || !st) return rc;

@@ -13,6 +13,10 @@
 // reordered: (x - lo) * s, floor, clamp; ldexp + round-half-even.
 #pragma clang fp contract(off)
 
+#include <stdlib.h>
+
+#include <algorithm>
+
 #include "cgd_internal.h"
 #include "hex_bin.h"
 
@@ -112,6 +116,167 @@ __global__ __launch_bounds__(kBlock) void k_deposit_hex(
     }
 }
 
+// ---------------------------------------------------------------- tiled deposit
+// The cells are cut into tiles of `cpt` consecutive indices.  The particles
+// are bucketed by tile (a counting sort over fixed chunks of kTChunk
+// particles per block), then one workgroup per tile adds its particles'
+// fixed-point values in LDS and writes the tile's finished field (and
+// accumulators): every int64 sum stays exact, and the device-wide atomics on
+// the accumulators of the direct path are replaced by LDS atomics.
+
+constexpr int kTBlock = 1024;
+constexpr int kTChunk = kTBlock * 16;  // particles per block of the bucketing passes
+constexpr int kTileWords = 16384;      // int64 LDS accumulators of one tile workgroup (128 KB)
+constexpr int kMaxTiles = 8192;        // LDS tile counters of the bucketing passes
+
+struct TileArgs {
+    const float* pos;
+    const float* values;
+    int64_t n;
+    int F;
+    HexBin g;
+    int e_n;
+    int64_t cells;
+    int cpt, ntiles;
+    int32_t* cellbuf;   // [n]: host cell of each particle (-1: dropped)
+    uint32_t* counts;   // [ntiles]: particles per tile
+    uint32_t* offsets;  // [ntiles + 1]
+    uint32_t* cursor;   // [ntiles]
+    uint32_t* rcell;    // [n]: cell within its tile, tile-bucketed
+    long long* rq;      // [F][n]: fixed-point values, tile-bucketed
+    float* field;
+    long long* acc;     // nullable
+    double vol;
+    DepositInfo* info;
+};
+
+__global__ void k_tile_clear(TileArgs a) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < a.ntiles; t += gridDim.x * blockDim.x) a.counts[t] = 0u;
+}
+
+// Pass 1: host cells (stored), dropped counts, particles per tile.
+__global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
+    __shared__ uint32_t hist[kMaxTiles];
+    for (int t = threadIdx.x; t < a.ntiles; t += kTBlock) hist[t] = 0u;
+    __syncthreads();
+    const int64_t p0 = (int64_t)blockIdx.x * kTChunk;
+    const int64_t p1 = min(p0 + kTChunk, a.n);
+    unsigned long long dropped = 0ull, nfpos = 0ull;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += kTBlock) {
+        bool nf;
+        const int64_t k = hex_cell(a.g, a.pos[3 * p], a.pos[3 * p + 1], a.pos[3 * p + 2], &nf);
+        a.cellbuf[p] = (int32_t)k;
+        if (k < 0) {
+            ++dropped;
+            nfpos += nf ? 1ull : 0ull;
+            continue;
+        }
+        atomicAdd(&hist[(int)(k / a.cpt)], 1u);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        dropped += __shfl_xor(dropped, o);
+        nfpos += __shfl_xor(nfpos, o);
+    }
+    if ((threadIdx.x & 63) == 0 && dropped) {
+        atomicAdd(&a.info->dropped, dropped);
+        if (nfpos) atomicAdd(&a.info->nonfinite_pos, nfpos);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < a.ntiles; t += kTBlock)
+        if (hist[t]) atomicAdd(&a.counts[t], hist[t]);
+}
+
+// Pass 2: offsets = exclusive prefix sum of the counts (one block).
+__global__ __launch_bounds__(kTBlock) void k_tile_scan(TileArgs a) {
+    __shared__ uint32_t part[kTBlock];
+    const int per = (a.ntiles + kTBlock - 1) / kTBlock;
+    const int t0 = threadIdx.x * per, t1 = min(t0 + per, a.ntiles);
+    uint32_t s = 0u;
+    for (int t = t0; t < t1; ++t) s += a.counts[t];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0u;
+        for (int i = 0; i < kTBlock; ++i) {
+            const uint32_t v = part[i];
+            part[i] = run;
+            run += v;
+        }
+        a.offsets[a.ntiles] = run;
+    }
+    __syncthreads();
+    uint32_t run = part[threadIdx.x];
+    for (int t = t0; t < t1; ++t) {
+        a.offsets[t] = run;
+        a.cursor[t] = run;
+        run += a.counts[t];
+    }
+}
+
+// Pass 3: each block reserves, per tile, one range for its chunk's
+// particles, then writes their cell-in-tile and fixed-point values there.
+__global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
+    __shared__ uint32_t hist[kMaxTiles];
+    __shared__ uint32_t base[kMaxTiles];
+    __shared__ int S[CGD_MAX_FIELDS];
+    for (int t = threadIdx.x; t < a.ntiles; t += kTBlock) hist[t] = 0u;
+    if (threadIdx.x < a.F) S[threadIdx.x] = frac_bits_of(a.info->maxbits[threadIdx.x], a.e_n);
+    __syncthreads();
+    const int64_t p0 = (int64_t)blockIdx.x * kTChunk;
+    const int64_t p1 = min(p0 + kTChunk, a.n);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += kTBlock) {
+        const int32_t k = a.cellbuf[p];
+        if (k >= 0) atomicAdd(&hist[k / a.cpt], 1u);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < a.ntiles; t += kTBlock) {
+        const uint32_t c = hist[t];
+        base[t] = c ? atomicAdd(&a.cursor[t], c) : 0u;
+        hist[t] = 0u;  // reused as the in-block rank counter
+    }
+    __syncthreads();
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += kTBlock) {
+        const int32_t k = a.cellbuf[p];
+        if (k < 0) continue;
+        const int t = k / a.cpt;
+        const uint32_t slot = base[t] + atomicAdd(&hist[t], 1u);
+        a.rcell[slot] = (uint32_t)(k - t * a.cpt);
+        for (int f = 0; f < a.F; ++f) {
+            const float v = a.values[(size_t)f * a.n + p];
+            a.rq[(size_t)f * a.n + slot] = isfinite(v) ? __double2ll_rn(ldexp((double)v, S[f])) : 0ll;
+        }
+    }
+}
+
+// Pass 4: one workgroup per tile: exact int64 sums in LDS, then the tile's
+// field = float32((acc 2^-S) / V) (and the accumulators when asked for).
+__global__ __launch_bounds__(kTBlock) void k_tile_accum(TileArgs a) {
+    __shared__ unsigned long long lacc[kTileWords];
+    const int t = blockIdx.x;
+    const int64_t c0 = (int64_t)t * a.cpt;
+    const int nc = (int)min<int64_t>(a.cpt, a.cells - c0);
+    for (int i = threadIdx.x; i < a.F * a.cpt; i += kTBlock) lacc[i] = 0ull;
+    __syncthreads();
+    const uint32_t r0 = a.offsets[t], r1 = a.offsets[t + 1];
+    for (uint32_t r = r0 + threadIdx.x; r < r1; r += kTBlock) {
+        const uint32_t c = a.rcell[r];
+        for (int f = 0; f < a.F; ++f) {
+            const long long q = a.rq[(size_t)f * a.n + r];
+            if (q != 0) atomicAdd(&lacc[f * a.cpt + c], (unsigned long long)q);
+        }
+    }
+    __syncthreads();
+    for (int f = 0; f < a.F; ++f) {
+        const int S = frac_bits_of(a.info->maxbits[f], a.e_n);
+        float* out = a.field + (size_t)f * a.cells + c0;
+        for (int i = threadIdx.x; i < nc; i += kTBlock) {
+            const long long v = (long long)lacc[f * a.cpt + i];
+            out[i] = (float)(ldexp((double)v, -S) / a.vol);
+            if (a.acc) a.acc[(size_t)f * a.cells + c0 + i] = v;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_locate_hex(const float* __restrict__ pos, int64_t n, HexBin g,
                                                        int32_t* __restrict__ cell) {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
@@ -177,11 +342,72 @@ cgd_status locate_hex(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hi
     return CGD_OK;
 }
 
+// Tiling of the tiled deposit; false when the direct (atomic) path is used:
+// more tiles than the bucketing passes count in LDS, more particles than
+// 32-bit offsets hold, or CGD_DEPOSIT_DIRECT set.
+bool tile_plan(int64_t cells, int64_t n, int32_t F, int* cpt, int* ntiles) {
+    if (getenv("CGD_DEPOSIT_DIRECT") || n <= 0 || n >= (int64_t)UINT32_MAX) return false;
+    const int c = kTileWords / F;
+    const int64_t t = (cells + c - 1) / c;
+    if (t > kMaxTiles) return false;
+    *cpt = c;
+    *ntiles = (int)t;
+    return true;
+}
+
+size_t deposit_hex_temp_bytes(const cgd_mesh m, int64_t n, int32_t F) {
+    int cpt, nt;
+    if (!tile_plan(m->cells, n, F, &cpt, &nt)) return 0;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return al(4 * (size_t)n) + al(4 * (size_t)n) + al(8 * (size_t)F * n) + al(4 * (3 * (size_t)nt + 1));
+}
+
 cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
-                       float* field, int64_t* acc, DepositInfo* info, hipStream_t s) {
+                       float* field, int64_t* acc, DepositInfo* info, void* temp, hipStream_t s) {
     const int64_t cells = m->cells;
     const int e_n = ceil_log2_count(n);
     const HexBin g = hex_bin(m);
+    int cpt = 0, nt = 0;
+    if (temp && tile_plan(cells, n, F, &cpt, &nt)) {
+        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        char* t = static_cast<char*>(temp);
+        TileArgs a = {};
+        a.pos = pos;
+        a.values = values;
+        a.n = n;
+        a.F = F;
+        a.g = g;
+        a.e_n = e_n;
+        a.cells = cells;
+        a.cpt = cpt;
+        a.ntiles = nt;
+        a.cellbuf = reinterpret_cast<int32_t*>(t);
+        t += al(4 * (size_t)n);
+        a.rcell = reinterpret_cast<uint32_t*>(t);
+        t += al(4 * (size_t)n);
+        a.rq = reinterpret_cast<long long*>(t);
+        t += al(8 * (size_t)F * n);
+        a.counts = reinterpret_cast<uint32_t*>(t);
+        a.offsets = a.counts + nt;
+        a.cursor = a.offsets + nt + 1;
+        a.field = field;
+        a.acc = reinterpret_cast<long long*>(acc);
+        a.vol = m->hex.vol;
+        a.info = info;
+        hipLaunchKernelGGL(k_dep_init, dim3(1), dim3(64), 0, s, info);
+        hipLaunchKernelGGL(k_tile_clear, dim3((nt + 255) / 256), dim3(256), 0, s, a);
+        const int ablocks = (int)std::min<int64_t>(4096, (n + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_absmax, dim3(ablocks, F), dim3(kBlock), 0, s, values, n, info);
+        const int cblocks = (int)((n + kTChunk - 1) / kTChunk);
+        int tm = timing_begin(&m->timing, s);
+        hipLaunchKernelGGL(k_tile_bin, dim3(cblocks), dim3(kTBlock), 0, s, a);
+        hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kTBlock), 0, s, a);
+        hipLaunchKernelGGL(k_tile_scatter, dim3(cblocks), dim3(kTBlock), 0, s, a);
+        hipLaunchKernelGGL(k_tile_accum, dim3(nt), dim3(kTBlock), 0, s, a);
+        timing_end(&m->timing, tm, 2, (12.0 + 12.0 * F) * (double)n, s);
+        CGD_HIP_TRY(hipGetLastError());
+        return CGD_OK;
+    }
     deposit_prologue(n, F, values, acc, cells, info, s);
     if (n > 0) {
         int dblocks = (int)std::min<int64_t>(16384, (n + kBlock - 1) / kBlock);

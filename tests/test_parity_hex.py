@@ -48,9 +48,31 @@ def test_deposit_tiny_bit_exact(gpu_lib):
     assert torch.equal(field3.view(torch.int32), field.view(torch.int32))
 
 
-def test_deposit_signed_multifield_ragged_and_dropped(gpu_lib):
+def test_deposit_many_tiles_clustered_bit_exact(gpu_lib):
+    """The dense-bed recipe on 96 x 80 x 200 (1.5M cells; with F = 2, 188
+    tiles of 8192 cells, the upper ones empty): the tiled deposit's fields
+    and accumulators are bit-identical to the oracle's."""
     import torch
     cgd = gpu_lib
+    w = inputs.dense_bed(n_particles=400_000, shape=(96, 80, 200), n_fields=2)
+    print(f"case: {w.name}", flush=True)
+    mesh = cgd.HexMesh(w.box.shape, w.box.lo, w.box.hi)
+    acc = torch.empty((2, mesh.cells), dtype=torch.int64, device="cuda")
+    field, st = cgd.deposit(mesh, _t(w.particles.pos, torch), _t(w.particles.values, torch), acc=acc, stats=True)
+    ref = O.deposit_hex(w.particles.pos, w.particles.values, w.box.lo, w.box.hi, w.box.shape)
+    assert st.frac_bits[:2] == ref["S"]
+    assert np.array_equal(acc.cpu().numpy(), ref["acc"])
+    assert np.array_equal(field.cpu().numpy().view(np.uint32), ref["field32"].view(np.uint32))
+
+
+@pytest.mark.parametrize("path", ["tiled", "direct"])
+def test_deposit_signed_multifield_ragged_and_dropped(gpu_lib, path, monkeypatch):
+    """Both deposit paths: tile-bucketed sums in LDS (default) and direct
+    device-wide atomics (CGD_DEPOSIT_DIRECT)."""
+    import torch
+    cgd = gpu_lib
+    if path == "direct":
+        monkeypatch.setenv("CGD_DEPOSIT_DIRECT", "1")
     box = inputs.HexBox((-0.3, 0.1, 2.0), (0.7, 0.35, 2.9), (37, 29, 11))
     rng = np.random.default_rng(21)
     n = 50_000
@@ -60,7 +82,7 @@ def test_deposit_signed_multifield_ragged_and_dropped(gpu_lib):
     pos[50, 1] = np.nan
     vals = p.values.copy()
     vals[2, 60] = np.inf
-    print("case: ragged 37x29x11, F=4, dropped/non-finite", flush=True)
+    print(f"case: ragged 37x29x11, F=4, dropped/non-finite, {path} deposit", flush=True)
     mesh = cgd.HexMesh(box.shape, box.lo, box.hi)
     acc = torch.empty((4, mesh.cells), dtype=torch.int64, device="cuda")
     field, st = cgd.deposit(mesh, _t(pos, torch), _t(vals, torch), acc=acc, stats=True)
