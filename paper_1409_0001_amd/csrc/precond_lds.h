@@ -34,16 +34,19 @@ __device__ __forceinline__ void x_neighbours(const Vec<VEC>& c, float& lft, floa
 // of the previous level at planes q-1, q, q+1 come from the wave's
 // registers (it formed them at steps t-2, t-1, t), the rows above and below
 // at plane q from LDS, where their waves wrote them at step t-1, and the
-// x-neighbours from DPP shifts; each level's LDS holds two planes (written at
-// steps of one parity, read at the next), so a step needs one barrier.  The
-// steps are unrolled by 6 so that every register ring (r: 6 planes, levels:
-// 3 planes) is indexed at compile time.  r enters LDS through the waves that
+// x-neighbours from DPP shifts.  LDS holds three planes of r and of level 1
+// (level 2 reads its own row's level-1 planes there, which saves a register
+// ring) and two of each higher level (written at steps of one parity, read
+// at the next), so a step needs one barrier.  The steps are unrolled by 6 so
+// that every register ring (r: 6 planes, levels >= 2: 3 planes) is indexed
+// at compile time.  r enters LDS through the waves that
 // own no output row: they keep P planes of loads in flight and never store,
 // while the output waves only store, so neither kind waits for the other's
 // memory operations.  Rows and planes beyond a wall take the cell itself
 // (the wall rule): rows by pointing at the cell's own row, planes through
 // per-plane coefficients.  FIRST: the input is b (zero initial guess) and
 // b.b is accumulated as well.
+
 // First LDS row of level j (rows of TY + 2 (D - i) per plane; 3 planes for
 // levels 0 and 1, 2 planes above).
 template <int D, int TY>
@@ -71,9 +74,6 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     constexpr int P = 2;                         // planes of r in flight per loader
     static_assert(E0 <= NW, "one row per wave covers every level");
     static_assert(RPL <= 2, "loaders hold at most two rows");
-    // LDS: level 0 (r) and level 1 keep 3 planes of TY + 2 (D - j) rows,
-    // levels 2..D-1 two (level 2 reads its own row's level-1 neighbours from
-    // LDS, which saves that level's register ring)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     constexpr int nx = NXR;
     const int x0 = lane * VEC;
@@ -179,21 +179,36 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 }
                 float lft, rgt;
                 x_neighbours<VEC>(c, lft, rgt);
+                // u = cp[D-j] r + ca A u_prev (ca = cp[D] at j = 1, else 1), with
+                // ca folded into the stencil's coefficients: 7 operations per cell
+                // (8 when h_x != h_y)
                 const bool hzd = q > 0, hzu = q + 1 < nz;
-                const float czd = hzd ? cz : 0.f, czu = hzu ? cz : 0.f;
-                const float dq = d_in - (hzd ? 0.f : cz) - (hzu ? 0.f : cz);
-                const float cr = cp[D - j];
                 const float ca = j == 1 ? cp[D] : 1.f;
+                const float kzd = hzd ? ca * cz : 0.f, kzu = hzu ? ca * cz : 0.f;
+                const float kd = ca * (d_in - (hzd ? 0.f : cz) - (hzu ? 0.f : cz));
+                const float kx = ca * cx, ky = ca * cy;
+                const float cr = cp[D - j];
+                if (cx == cy) {
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) {
-                    const float l = e > 0 ? c.f[e - 1] : lft;
-                    const float r = e + 1 < VEC ? c.f[e + 1] : rgt;
-                    float v = dq * c.f[e];
-                    v = fmaf(-cx, l + r, v);
-                    v = fmaf(-cy, ys.f[e], v);
-                    v = fmaf(-czd, zl.f[e], v);
-                    v = fmaf(-czu, zh.f[e], v);
-                    u.f[e] = fmaf(ca, v, cr * rq.f[e]);  // cp[D-j] r + A u_prev (A (cp[D] r) at j = 1)
+                    for (int e = 0; e < VEC; ++e) {
+                        const float l = e > 0 ? c.f[e - 1] : lft;
+                        const float r = e + 1 < VEC ? c.f[e + 1] : rgt;
+                        float v = fmaf(kd, c.f[e], cr * rq.f[e]);
+                        v = fmaf(-kx, (l + r) + ys.f[e], v);
+                        v = fmaf(-kzd, zl.f[e], v);
+                        u.f[e] = fmaf(-kzu, zh.f[e], v);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const float l = e > 0 ? c.f[e - 1] : lft;
+                        const float r = e + 1 < VEC ? c.f[e + 1] : rgt;
+                        float v = fmaf(kd, c.f[e], cr * rq.f[e]);
+                        v = fmaf(-kx, l + r, v);
+                        v = fmaf(-ky, ys.f[e], v);
+                        v = fmaf(-kzd, zl.f[e], v);
+                        u.f[e] = fmaf(-kzu, zh.f[e], v);
+                    }
                 }
                 if (j < D) stv<VEC>(rowj(j, q, w - j), u);
             }
