@@ -54,7 +54,7 @@ def parse():
 
 # Sources the hex sweep kernels are built from, in the order their bytes are
 # hashed for the counter summary's source_sha256.
-SWEEP_SOURCES = ("cg_hex.hip", "stencil_tile.h", "cg_common.h", "cg_common.hip")
+SWEEP_SOURCES = ("cg_hex.hip", "stencil_tile.h", "precond_lds.h", "cg_common.h", "cg_common.hip")
 
 
 def sweep_source_sha():

@@ -1,7 +1,8 @@
 // Particle centroid method on uniform hex grids (Section 2.2, eq. pcm-k),
 // bit-exact through 64-bit fixed point.
 //
-// Pipeline (all on the caller's stream, no host synchronisation):
+// Direct pipeline (all on the caller's stream, no host synchronisation; the
+// tiled pipeline below replaces the last three steps):
 //   k_dep_init   reset the per-call counters
 //   k_zero64     clear the int64 accumulators
 //   k_absmax     max |v| per field over finite values -> fixed-point scale S_f
@@ -118,16 +119,20 @@ __global__ __launch_bounds__(kBlock) void k_deposit_hex(
 
 // ---------------------------------------------------------------- tiled deposit
 // The cells are cut into tiles of `cpt` consecutive indices.  The particles
-// are bucketed by tile (a counting sort over fixed chunks of kTChunk
-// particles per block), then one workgroup per tile adds its particles'
-// fixed-point values in LDS and writes the tile's finished field (and
-// accumulators): every int64 sum stays exact, and the device-wide atomics on
-// the accumulators of the direct path are replaced by LDS atomics.
+// are bucketed by tile (a counting sort over fixed chunks of particles per
+// block), then one workgroup per tile adds its particles' fixed-point values
+// in LDS and writes the tile's finished field (and accumulators): every int64
+// sum stays exact, and the device-wide atomics on the accumulators of the
+// direct path are replaced by LDS atomics.  A bucketed record is 8 bytes,
+// (cell within the tile, bits of the first field's value); further fields'
+// values follow in their own arrays, and the values are quantised in the
+// accumulate pass.
 
 constexpr int kTBlock = 1024;
-constexpr int kTChunk = kTBlock * 16;  // particles per block of the bucketing passes
-constexpr int kTileWords = 16384;      // int64 LDS accumulators of one tile workgroup (128 KB)
-constexpr int kMaxTiles = 8192;        // LDS tile counters of the bucketing passes
+constexpr int kTPer = 16;                  // particles per thread and pass, held in registers
+constexpr int kTChunk = kTBlock * kTPer;   // particles per block of the counting pass
+constexpr int kTileWords = 16384;          // int64 LDS accumulators of one tile workgroup (128 KB)
+constexpr int kMaxTiles = 8192;            // LDS tile counters of the bucketing passes
 
 struct TileArgs {
     const float* pos;
@@ -138,12 +143,15 @@ struct TileArgs {
     int e_n;
     int64_t cells;
     int cpt, ntiles;
+    int cpt_log2;       // cpt = 2^cpt_log2
+    int nsub;           // kTChunk-particle passes per block of the scatter
+    int nsub_bin;       // ... and of the counting pass
     int32_t* cellbuf;   // [n]: host cell of each particle (-1: dropped)
     uint32_t* counts;   // [ntiles]: particles per tile
     uint32_t* offsets;  // [ntiles + 1]
     uint32_t* cursor;   // [ntiles]
-    uint32_t* rcell;    // [n]: cell within its tile, tile-bucketed
-    long long* rq;      // [F][n]: fixed-point values, tile-bucketed
+    uint2* rec;         // [n]: (cell within its tile, bits of field 0's value), tile-bucketed
+    float* rv;          // [F - 1][n]: values of fields 1.., tile-bucketed
     float* field;
     long long* acc;     // nullable
     double vol;
@@ -154,24 +162,76 @@ __global__ void k_tile_clear(TileArgs a) {
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < a.ntiles; t += gridDim.x * blockDim.x) a.counts[t] = 0u;
 }
 
-// Pass 1: host cells (stored), dropped counts, particles per tile.
+// Pass 1: host cells (stored), dropped counts, particles per tile, and the
+// max |v| / non-finite count of every field over the block's chunk of
+// nsub_bin * kTChunk particles (the values of the direct path's k_absmax,
+// folded into this pass).
 __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
     __shared__ uint32_t hist[kMaxTiles];
+    __shared__ uint32_t bmax[CGD_MAX_FIELDS];
+    __shared__ unsigned long long bbad[CGD_MAX_FIELDS];
     for (int t = threadIdx.x; t < a.ntiles; t += kTBlock) hist[t] = 0u;
+    if (threadIdx.x < CGD_MAX_FIELDS) {
+        bmax[threadIdx.x] = 0u;
+        bbad[threadIdx.x] = 0ull;
+    }
     __syncthreads();
-    const int64_t p0 = (int64_t)blockIdx.x * kTChunk;
-    const int64_t p1 = min(p0 + kTChunk, a.n);
     unsigned long long dropped = 0ull, nfpos = 0ull;
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += kTBlock) {
-        bool nf;
-        const int64_t k = hex_cell(a.g, a.pos[3 * p], a.pos[3 * p + 1], a.pos[3 * p + 2], &nf);
-        a.cellbuf[p] = (int32_t)k;
-        if (k < 0) {
-            ++dropped;
-            nfpos += nf ? 1ull : 0ull;
-            continue;
+    for (int sub = 0; sub < a.nsub_bin; ++sub) {
+        const int64_t p0 = ((int64_t)blockIdx.x * a.nsub_bin + sub) * kTChunk + threadIdx.x;
+        float px[kTPer], py[kTPer], pz[kTPer];
+#pragma unroll
+        for (int i = 0; i < kTPer; ++i) {
+            const int64_t p = min(p0 + (int64_t)i * kTBlock, a.n - 1);
+            px[i] = a.pos[3 * p];
+            py[i] = a.pos[3 * p + 1];
+            pz[i] = a.pos[3 * p + 2];
         }
-        atomicAdd(&hist[(int)(k / a.cpt)], 1u);
+#pragma unroll
+        for (int i = 0; i < kTPer; ++i) {
+            const int64_t p = p0 + (int64_t)i * kTBlock;
+            if (p >= a.n) continue;
+            bool nf;
+            const int32_t k = (int32_t)hex_cell(a.g, px[i], py[i], pz[i], &nf);
+            a.cellbuf[p] = k;
+            if (k < 0) {
+                ++dropped;
+                nfpos += nf ? 1ull : 0ull;
+            } else {
+                atomicAdd(&hist[k >> a.cpt_log2], 1u);
+            }
+        }
+    }
+    for (int f = 0; f < a.F; ++f) {
+        const uint32_t* v = reinterpret_cast<const uint32_t*>(a.values + (size_t)f * a.n);
+        uint32_t m = 0u;
+        unsigned long long bad = 0ull;
+        for (int sub = 0; sub < a.nsub_bin; ++sub) {
+            const int64_t p0 = ((int64_t)blockIdx.x * a.nsub_bin + sub) * kTChunk + threadIdx.x;
+            uint32_t x[kTPer];
+#pragma unroll
+            for (int i = 0; i < kTPer; ++i) {
+                const int64_t p = p0 + (int64_t)i * kTBlock;
+                x[i] = p < a.n ? v[p] & 0x7fffffffu : 0u;
+            }
+#pragma unroll
+            for (int i = 0; i < kTPer; ++i) {
+                if (x[i] >= 0x7f800000u) {
+                    ++bad;
+                } else {
+                    m = x[i] > m ? x[i] : m;
+                }
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t mo = __shfl_xor(m, o);
+            m = mo > m ? mo : m;
+            bad += __shfl_xor(bad, o);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            if (m) atomicMax(&bmax[f], m);
+            if (bad) atomicAdd(&bbad[f], bad);
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
         dropped += __shfl_xor(dropped, o);
@@ -184,6 +244,10 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
     __syncthreads();
     for (int t = threadIdx.x; t < a.ntiles; t += kTBlock)
         if (hist[t]) atomicAdd(&a.counts[t], hist[t]);
+    if (threadIdx.x < a.F) {
+        if (bmax[threadIdx.x]) atomicMax(&a.info->maxbits[threadIdx.x], bmax[threadIdx.x]);
+        if (bbad[threadIdx.x]) atomicAdd(&a.info->nonfinite_val[threadIdx.x], bbad[threadIdx.x]);
+    }
 }
 
 // Pass 2: offsets = exclusive prefix sum of the counts (one block).
@@ -213,20 +277,28 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scan(TileArgs a) {
     }
 }
 
-// Pass 3: each block reserves, per tile, one range for its chunk's
-// particles, then writes their cell-in-tile and fixed-point values there.
+// Pass 3: each block counts its chunk of nsub * kTChunk particles per tile,
+// reserves one range per tile, then writes the particles' records there, a
+// kTChunk pass at a time with every thread's cells and values in registers.
+// Longer chunks give longer runs of consecutive slots per block and tile,
+// which the L2 merges into whole lines before they are written back.
 __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
     __shared__ uint32_t hist[kMaxTiles];
     __shared__ uint32_t base[kMaxTiles];
-    __shared__ int S[CGD_MAX_FIELDS];
+    const int64_t c0 = (int64_t)blockIdx.x * a.nsub * kTChunk + threadIdx.x;
     for (int t = threadIdx.x; t < a.ntiles; t += kTBlock) hist[t] = 0u;
-    if (threadIdx.x < a.F) S[threadIdx.x] = frac_bits_of(a.info->maxbits[threadIdx.x], a.e_n);
     __syncthreads();
-    const int64_t p0 = (int64_t)blockIdx.x * kTChunk;
-    const int64_t p1 = min(p0 + kTChunk, a.n);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += kTBlock) {
-        const int32_t k = a.cellbuf[p];
-        if (k >= 0) atomicAdd(&hist[k / a.cpt], 1u);
+    for (int sub = 0; sub < a.nsub; ++sub) {
+        const int64_t p0 = c0 + (int64_t)sub * kTChunk;
+        int32_t kk[kTPer];
+#pragma unroll
+        for (int i = 0; i < kTPer; ++i) {
+            const int64_t p = p0 + (int64_t)i * kTBlock;
+            kk[i] = p < a.n ? a.cellbuf[p] : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < kTPer; ++i)
+            if (kk[i] >= 0) atomicAdd(&hist[kk[i] >> a.cpt_log2], 1u);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < a.ntiles; t += kTBlock) {
@@ -235,43 +307,91 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
         hist[t] = 0u;  // reused as the in-block rank counter
     }
     __syncthreads();
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += kTBlock) {
-        const int32_t k = a.cellbuf[p];
-        if (k < 0) continue;
-        const int t = k / a.cpt;
-        const uint32_t slot = base[t] + atomicAdd(&hist[t], 1u);
-        a.rcell[slot] = (uint32_t)(k - t * a.cpt);
-        for (int f = 0; f < a.F; ++f) {
-            const float v = a.values[(size_t)f * a.n + p];
-            a.rq[(size_t)f * a.n + slot] = isfinite(v) ? __double2ll_rn(ldexp((double)v, S[f])) : 0ll;
+    for (int sub = 0; sub < a.nsub; ++sub) {
+        const int64_t p0 = c0 + (int64_t)sub * kTChunk;
+        int32_t kk[kTPer];
+        float v0[kTPer];
+#pragma unroll
+        for (int i = 0; i < kTPer; ++i) {
+            const int64_t p = p0 + (int64_t)i * kTBlock;
+            kk[i] = p < a.n ? a.cellbuf[p] : -1;
+            v0[i] = p < a.n ? a.values[p] : 0.f;
+        }
+        uint32_t slot[kTPer];
+#pragma unroll
+        for (int i = 0; i < kTPer; ++i) {
+            if (kk[i] < 0) continue;
+            const int t = kk[i] >> a.cpt_log2;
+            slot[i] = base[t] + atomicAdd(&hist[t], 1u);
+            a.rec[slot[i]] = make_uint2((uint32_t)(kk[i] & (a.cpt - 1)), __float_as_uint(v0[i]));
+        }
+        for (int f = 1; f < a.F; ++f) {
+            const float* vf = a.values + (size_t)f * a.n;
+            float v[kTPer];
+#pragma unroll
+            for (int i = 0; i < kTPer; ++i) {
+                const int64_t p = p0 + (int64_t)i * kTBlock;
+                v[i] = p < a.n ? vf[p] : 0.f;
+            }
+            float* rvf = a.rv + (size_t)(f - 1) * a.n;
+#pragma unroll
+            for (int i = 0; i < kTPer; ++i)
+                if (kk[i] >= 0) rvf[slot[i]] = v[i];
         }
     }
 }
 
-// Pass 4: one workgroup per tile: exact int64 sums in LDS, then the tile's
-// field = float32((acc 2^-S) / V) (and the accumulators when asked for).
+__device__ inline long long quantise(float v, int S) {
+    return isfinite(v) ? __double2ll_rn(ldexp((double)v, S)) : 0ll;
+}
+
+// Pass 4: one workgroup per tile: exact int64 sums in LDS of the quantised
+// values rint(v 2^S_f), then the tile's field = float32((acc 2^-S_f) / V)
+// (and the accumulators when asked for).
 __global__ __launch_bounds__(kTBlock) void k_tile_accum(TileArgs a) {
     __shared__ unsigned long long lacc[kTileWords];
+    __shared__ int S[CGD_MAX_FIELDS];
     const int t = blockIdx.x;
     const int64_t c0 = (int64_t)t * a.cpt;
     const int nc = (int)min<int64_t>(a.cpt, a.cells - c0);
     for (int i = threadIdx.x; i < a.F * a.cpt; i += kTBlock) lacc[i] = 0ull;
+    if (threadIdx.x < a.F) S[threadIdx.x] = frac_bits_of(a.info->maxbits[threadIdx.x], a.e_n);
     __syncthreads();
     const uint32_t r0 = a.offsets[t], r1 = a.offsets[t + 1];
-    for (uint32_t r = r0 + threadIdx.x; r < r1; r += kTBlock) {
-        const uint32_t c = a.rcell[r];
-        for (int f = 0; f < a.F; ++f) {
-            const long long q = a.rq[(size_t)f * a.n + r];
-            if (q != 0) atomicAdd(&lacc[f * a.cpt + c], (unsigned long long)q);
+    const int S0 = S[0];
+    constexpr int U = 4;  // records per thread whose loads are in flight together
+    for (uint32_t r = r0 + threadIdx.x; r < r1; r += U * kTBlock) {
+        uint2 e[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint32_t rr = r + j * kTBlock;
+            e[j] = rr < r1 ? a.rec[rr] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const long long q = quantise(__uint_as_float(e[j].y), S0);
+            if (q != 0) atomicAdd(&lacc[e[j].x], (unsigned long long)q);
+        }
+        for (int f = 1; f < a.F; ++f) {
+            float v[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const uint32_t rr = r + j * kTBlock;
+                v[j] = rr < r1 ? a.rv[(size_t)(f - 1) * a.n + rr] : 0.f;
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const long long q = quantise(v[j], S[f]);
+                if (q != 0) atomicAdd(&lacc[f * a.cpt + e[j].x], (unsigned long long)q);
+            }
         }
     }
     __syncthreads();
     for (int f = 0; f < a.F; ++f) {
-        const int S = frac_bits_of(a.info->maxbits[f], a.e_n);
         float* out = a.field + (size_t)f * a.cells + c0;
         for (int i = threadIdx.x; i < nc; i += kTBlock) {
             const long long v = (long long)lacc[f * a.cpt + i];
-            out[i] = (float)(ldexp((double)v, -S) / a.vol);
+            out[i] = (float)(ldexp((double)v, -S[f]) / a.vol);
             if (a.acc) a.acc[(size_t)f * a.cells + c0 + i] = v;
         }
     }
@@ -342,12 +462,15 @@ cgd_status locate_hex(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hi
     return CGD_OK;
 }
 
-// Tiling of the tiled deposit; false when the direct (atomic) path is used:
+// Tiling of the tiled deposit (tiles of a power-of-two number of cells, so
+// that tile and cell-in-tile are a shift and a mask); false when the direct
+// (atomic) path is used:
 // more tiles than the bucketing passes count in LDS, more particles than
 // 32-bit offsets hold, or CGD_DEPOSIT_DIRECT set.
 bool tile_plan(int64_t cells, int64_t n, int32_t F, int* cpt, int* ntiles) {
     if (getenv("CGD_DEPOSIT_DIRECT") || n <= 0 || n >= (int64_t)UINT32_MAX) return false;
-    const int c = kTileWords / F;
+    int c = kTileWords;  // the largest power of two with F * c <= kTileWords
+    while (c * F > kTileWords) c >>= 1;
     const int64_t t = (cells + c - 1) / c;
     if (t > kMaxTiles) return false;
     *cpt = c;
@@ -359,7 +482,16 @@ size_t deposit_hex_temp_bytes(const cgd_mesh m, int64_t n, int32_t F) {
     int cpt, nt;
     if (!tile_plan(m->cells, n, F, &cpt, &nt)) return 0;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    return al(4 * (size_t)n) + al(4 * (size_t)n) + al(8 * (size_t)F * n) + al(4 * (3 * (size_t)nt + 1));
+    return al(4 * (size_t)n) + al(8 * (size_t)n) + al(4 * (size_t)(F - 1) * n) + al(4 * (3 * (size_t)nt + 1));
+}
+
+// kTChunk-particle passes per scatter block: as long as the grid still
+// gives every compute unit several blocks.
+static int scatter_nsub(const char* env, int64_t n) {
+    if (const char* e = getenv(env)) return std::max(1, atoi(e));
+    int nsub = 1;
+    while (nsub < 8 && (n + 2 * nsub * (int64_t)kTChunk - 1) / (2 * nsub * (int64_t)kTChunk) >= 1024) nsub *= 2;
+    return nsub;
 }
 
 cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
@@ -380,13 +512,16 @@ cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
         a.e_n = e_n;
         a.cells = cells;
         a.cpt = cpt;
+        a.cpt_log2 = __builtin_ctz((unsigned)cpt);
         a.ntiles = nt;
+        a.nsub = scatter_nsub("CGD_DEPOSIT_NSUB", n);
+        a.nsub_bin = scatter_nsub("CGD_DEPOSIT_BIN_NSUB", n);
         a.cellbuf = reinterpret_cast<int32_t*>(t);
         t += al(4 * (size_t)n);
-        a.rcell = reinterpret_cast<uint32_t*>(t);
-        t += al(4 * (size_t)n);
-        a.rq = reinterpret_cast<long long*>(t);
-        t += al(8 * (size_t)F * n);
+        a.rec = reinterpret_cast<uint2*>(t);
+        t += al(8 * (size_t)n);
+        a.rv = reinterpret_cast<float*>(t);
+        t += al(4 * (size_t)(F - 1) * n);
         a.counts = reinterpret_cast<uint32_t*>(t);
         a.offsets = a.counts + nt;
         a.cursor = a.offsets + nt + 1;
@@ -396,13 +531,12 @@ cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
         a.info = info;
         hipLaunchKernelGGL(k_dep_init, dim3(1), dim3(64), 0, s, info);
         hipLaunchKernelGGL(k_tile_clear, dim3((nt + 255) / 256), dim3(256), 0, s, a);
-        const int ablocks = (int)std::min<int64_t>(4096, (n + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(k_absmax, dim3(ablocks, F), dim3(kBlock), 0, s, values, n, info);
-        const int cblocks = (int)((n + kTChunk - 1) / kTChunk);
+        const int cblocks = (int)((n + (int64_t)a.nsub_bin * kTChunk - 1) / ((int64_t)a.nsub_bin * kTChunk));
         int tm = timing_begin(&m->timing, s);
         hipLaunchKernelGGL(k_tile_bin, dim3(cblocks), dim3(kTBlock), 0, s, a);
         hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kTBlock), 0, s, a);
-        hipLaunchKernelGGL(k_tile_scatter, dim3(cblocks), dim3(kTBlock), 0, s, a);
+        const int sblocks = (int)((n + (int64_t)a.nsub * kTChunk - 1) / ((int64_t)a.nsub * kTChunk));
+        hipLaunchKernelGGL(k_tile_scatter, dim3(sblocks), dim3(kTBlock), 0, s, a);
         hipLaunchKernelGGL(k_tile_accum, dim3(nt), dim3(kTBlock), 0, s, a);
         timing_end(&m->timing, tm, 2, (12.0 + 12.0 * F) * (double)n, s);
         CGD_HIP_TRY(hipGetLastError());

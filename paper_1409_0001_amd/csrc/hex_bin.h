@@ -15,26 +15,29 @@ struct HexBin {
 };
 
 // Host cell of one centroid; -1 if the point is not finite or outside the
-// closed box.  u = (x - lo) * s, i = floor(u), clamped to [0, N-1].
+// closed box.  u = (x - lo) * s, i = floor(u), clamped to [0, N-1].  The axes
+// are tested in order x, y, z and *nonfinite tells whether the first failing
+// axis was a non-finite coordinate.  Written without branches: every axis is
+// evaluated, the clamp is done in float64 (identical to clamping the integer
+// floor) and the in-range value is converted to int32 natively.
 __device__ inline int64_t hex_cell(const HexBin& g, float fx, float fy, float fz, bool* nonfinite) {
 #pragma clang fp contract(off)
     const float xs[3] = {fx, fy, fz};
-    int64_t idx[3];
-    *nonfinite = false;
+    int32_t idx[3];
+    bool done = false, nf = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double x = (double)xs[a];
-        if (!isfinite(x)) {
-            *nonfinite = true;
-            return -1;
-        }
-        if (!(x >= g.lo[a] && x <= g.hi[a])) return -1;
-        double u = (x - g.lo[a]) * g.s[a];
-        int64_t i = (int64_t)floor(u);
-        i = i < 0 ? 0 : i;
-        i = i > g.n[a] - 1 ? g.n[a] - 1 : i;
-        idx[a] = i;
+        const double x = (double)xs[a];
+        const bool fin = isfinite(x);
+        const bool in = x >= g.lo[a] && x <= g.hi[a];
+        nf = nf || (!done && !fin);
+        done = done || !fin || !in;
+        const double u = (x - g.lo[a]) * g.s[a];
+        const double c = fmin(fmax(floor(u), 0.0), (double)(g.n[a] - 1));
+        idx[a] = (int32_t)c;
     }
+    *nonfinite = nf;
+    if (done) return -1;
     return idx[0] + (int64_t)g.n[0] * (idx[1] + (int64_t)g.n[1] * idx[2]);
 }
 
