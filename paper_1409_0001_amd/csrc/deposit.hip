@@ -130,7 +130,9 @@ __global__ __launch_bounds__(kBlock) void k_deposit_hex(
 
 constexpr int kTBlock = 1024;
 constexpr int kTPer = 16;                  // particles per thread and pass, held in registers
-constexpr int kTChunk = kTBlock * kTPer;   // particles per block of the counting pass
+constexpr int kTChunk = kTBlock * 16;      // particles per block and chunk of the bucketing passes
+constexpr int kTPass = kTChunk / (kTBlock * kTPer);  // register passes per chunk
+constexpr int kBPer = 4;                   // particles per thread and register pass of the counting pass
 constexpr int kTileWords = 16384;          // int64 LDS accumulators of one tile workgroup (128 KB)
 constexpr int kMaxTiles = 8192;            // LDS tile counters of the bucketing passes
 
@@ -177,18 +179,19 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
     }
     __syncthreads();
     unsigned long long dropped = 0ull, nfpos = 0ull;
-    for (int sub = 0; sub < a.nsub_bin; ++sub) {
-        const int64_t p0 = ((int64_t)blockIdx.x * a.nsub_bin + sub) * kTChunk + threadIdx.x;
-        float px[kTPer], py[kTPer], pz[kTPer];
+    const int npass = a.nsub_bin * (kTChunk / (kTBlock * kBPer));
+    for (int sub = 0; sub < npass; ++sub) {
+        const int64_t p0 = ((int64_t)blockIdx.x * npass + sub) * (kTBlock * kBPer) + threadIdx.x;
+        float px[kBPer], py[kBPer], pz[kBPer];
 #pragma unroll
-        for (int i = 0; i < kTPer; ++i) {
+        for (int i = 0; i < kBPer; ++i) {
             const int64_t p = min(p0 + (int64_t)i * kTBlock, a.n - 1);
             px[i] = a.pos[3 * p];
             py[i] = a.pos[3 * p + 1];
             pz[i] = a.pos[3 * p + 2];
         }
 #pragma unroll
-        for (int i = 0; i < kTPer; ++i) {
+        for (int i = 0; i < kBPer; ++i) {
             const int64_t p = p0 + (int64_t)i * kTBlock;
             if (p >= a.n) continue;
             bool nf;
@@ -206,16 +209,16 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
         const uint32_t* v = reinterpret_cast<const uint32_t*>(a.values + (size_t)f * a.n);
         uint32_t m = 0u;
         unsigned long long bad = 0ull;
-        for (int sub = 0; sub < a.nsub_bin; ++sub) {
-            const int64_t p0 = ((int64_t)blockIdx.x * a.nsub_bin + sub) * kTChunk + threadIdx.x;
-            uint32_t x[kTPer];
+        for (int sub = 0; sub < npass; ++sub) {
+            const int64_t p0 = ((int64_t)blockIdx.x * npass + sub) * (kTBlock * kBPer) + threadIdx.x;
+            uint32_t x[kBPer];
 #pragma unroll
-            for (int i = 0; i < kTPer; ++i) {
+            for (int i = 0; i < kBPer; ++i) {
                 const int64_t p = p0 + (int64_t)i * kTBlock;
                 x[i] = p < a.n ? v[p] & 0x7fffffffu : 0u;
             }
 #pragma unroll
-            for (int i = 0; i < kTPer; ++i) {
+            for (int i = 0; i < kBPer; ++i) {
                 if (x[i] >= 0x7f800000u) {
                     ++bad;
                 } else {
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scan(TileArgs a) {
 
 // Pass 3: each block counts its chunk of nsub * kTChunk particles per tile,
 // reserves one range per tile, then writes the particles' records there, a
-// kTChunk pass at a time with every thread's cells and values in registers.
+// register pass of kTPer particles per thread at a time.
 // Longer chunks give longer runs of consecutive slots per block and tile,
 // which the L2 merges into whole lines before they are written back.
 __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
@@ -288,8 +291,9 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
     const int64_t c0 = (int64_t)blockIdx.x * a.nsub * kTChunk + threadIdx.x;
     for (int t = threadIdx.x; t < a.ntiles; t += kTBlock) hist[t] = 0u;
     __syncthreads();
-    for (int sub = 0; sub < a.nsub; ++sub) {
-        const int64_t p0 = c0 + (int64_t)sub * kTChunk;
+    const int npass = a.nsub * kTPass;
+    for (int sub = 0; sub < npass; ++sub) {
+        const int64_t p0 = c0 + (int64_t)sub * (kTBlock * kTPer);
         int32_t kk[kTPer];
 #pragma unroll
         for (int i = 0; i < kTPer; ++i) {
@@ -307,8 +311,8 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
         hist[t] = 0u;  // reused as the in-block rank counter
     }
     __syncthreads();
-    for (int sub = 0; sub < a.nsub; ++sub) {
-        const int64_t p0 = c0 + (int64_t)sub * kTChunk;
+    for (int sub = 0; sub < npass; ++sub) {
+        const int64_t p0 = c0 + (int64_t)sub * (kTBlock * kTPer);
         int32_t kk[kTPer];
         float v0[kTPer];
 #pragma unroll
