@@ -650,9 +650,12 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     const int grid = grid_for(c, n_rhs);
     const BLayout L = batched_layout(n_rhs, n_snap, da.n_steps);
     const size_t small = L.small;
-    const size_t acc_bytes = (size_t)n_rhs * cells * 8;
+    // deposit: the tiled path's bucketed records, else int64 accumulators
+    const size_t tile_bytes = tiled_deposit_temp_bytes((int64_t)cells, total, n_snap, F);
+    const bool tiled = tile_bytes > 0;
+    const size_t dep_bytes = tiled ? tile_bytes : (size_t)n_rhs * cells * 8;
     const size_t solver_bytes = (size_t)grid * 5 * cells * 4;
-    rc = ensure_workspace(m, small + std::max(acc_bytes, solver_bytes));
+    rc = ensure_workspace(m, small + std::max(dep_bytes, solver_bytes));
     if (rc != CGD_OK) return rc;
     const BPin P = batched_pin(n_rhs, n_snap, da.n_steps);
     rc = ensure_pinned(m, P.total);
@@ -728,12 +731,33 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     auto enqueue_all = [&](hipStream_t q) -> cgd_status {
         CGD_HIP_TRY(hipMemcpyAsync(d_off, h_off, 8 * ((size_t)n_snap + 1), hipMemcpyHostToDevice, q));
         hipLaunchKernelGGL(k_bdep_init, dim3((n_rhs + 255) / 256), dim3(256), 0, q, d);
-        hipLaunchKernelGGL(k_bzero, dim3(8192), dim3(256), 0, q, d.acc, (int64_t)(n_rhs * cells));
-        if (total > 0) {
-            hipLaunchKernelGGL(k_babsmax, dim3(chunks, n_rhs), dim3(kDBlock), 0, q, d);
-            hipLaunchKernelGGL(k_bdeposit, dim3(chunks, n_snap), dim3(kDBlock), 0, q, d);
+        if (tiled) {
+            TiledDeposit td = {};
+            td.pos = pos;
+            td.values = values;
+            td.total = total;
+            td.max_n = max_n;
+            td.off = d_off;
+            td.n_snap = n_snap;
+            td.F = F;
+            td.maxbits = d_maxbits;
+            td.nf_val = d_counters + 1;  // one count of non-finite positions and values
+            td.nf_val_stride = 0;
+            td.dropped = d_counters;
+            td.nf_pos = d_counters + 1;
+            td.field = fields;
+            td.acc = nullptr;
+            td.temp = big;
+            cgd_status r = tiled_deposit(m, td, nullptr, q);
+            if (r != CGD_OK) return r;
+        } else {
+            hipLaunchKernelGGL(k_bzero, dim3(8192), dim3(256), 0, q, d.acc, (int64_t)(n_rhs * cells));
+            if (total > 0) {
+                hipLaunchKernelGGL(k_babsmax, dim3(chunks, n_rhs), dim3(kDBlock), 0, q, d);
+                hipLaunchKernelGGL(k_bdeposit, dim3(chunks, n_snap), dim3(kDBlock), 0, q, d);
+            }
+            hipLaunchKernelGGL(k_bfinalize, dim3(512, n_rhs), dim3(kDBlock), 0, q, d);
         }
-        hipLaunchKernelGGL(k_bfinalize, dim3(512, n_rhs), dim3(kDBlock), 0, q, d);
         cgd_status r = launch_solver(c, a, grid, q);
         if (r != CGD_OK) return r;
         CGD_HIP_TRY(hipMemcpyAsync(h_status, d_status, 4 * (size_t)n_rhs * (1 + da.n_steps), hipMemcpyDeviceToHost, q));
@@ -744,9 +768,10 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     const bool use_graph = getenv("CGD_NO_GRAPH") == nullptr;
     if (use_graph) {
         char keybuf[512];
-        snprintf(keybuf, sizeof keybuf, "%p %p %p %d %d %lld %d %d %.17g %.17g %d %d %p %zu %p %d", (const void*)pos,
-                 (const void*)values, (void*)fields, n_snap, F, (long long)total, chunks, da.n_steps, da.bandwidth,
-                 da.rtol, da.max_iter, ci, m->ws.ptr, m->ws.bytes, m->pinned, a.pcg);
+        snprintf(keybuf, sizeof keybuf, "%p %p %p %d %d %lld %d %d %.17g %.17g %d %d %p %zu %p %d %d",
+                 (const void*)pos, (const void*)values, (void*)fields, n_snap, F, (long long)total, chunks,
+                 da.n_steps, da.bandwidth, da.rtol, da.max_iter, ci, m->ws.ptr, m->ws.bytes, m->pinned, a.pcg,
+                 (int)tiled);
         std::lock_guard<std::mutex> lk(g_graph_mu);
         BatchedGraph& bg = g_graphs[m];
         if (bg.key != keybuf || !bg.exec) {

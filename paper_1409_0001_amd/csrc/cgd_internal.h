@@ -113,6 +113,30 @@ cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
                        float* field, int64_t* acc, DepositInfo* info_dev, void* temp, hipStream_t s);
 size_t deposit_hex_temp_bytes(const cgd_mesh m, int64_t n, int32_t F);
 
+// Tiled deposit of one or several snapshots on a mesh's hex grid (device
+// pointers; the counters are cleared by the caller).  The fields of snapshot
+// j are those a deposit of snapshot j alone gives.
+struct TiledDeposit {
+    const float* pos;              // [total][3]
+    const float* values;           // [F][total]
+    int64_t total;                 // particles of all snapshots
+    int64_t max_n;                 // particles of the largest snapshot
+    const int64_t* off;            // [n_snap + 1] particle offsets; nullptr: one snapshot
+    int32_t n_snap, F;
+    uint32_t* maxbits;             // [n_snap][F] max |v| bit patterns
+    unsigned long long* nf_val;    // field f's non-finite values are counted at nf_val[f * nf_val_stride]
+    int32_t nf_val_stride;
+    unsigned long long* dropped;   // particles outside the box or with a non-finite coordinate
+    unsigned long long* nf_pos;    // ... of those, the non-finite ones
+    float* field;                  // [n_snap][F][cells]
+    long long* acc;                // nullable: [n_snap][F][cells] int64 accumulators
+    void* temp;                    // tiled_deposit_temp_bytes
+};
+// Bytes of `temp`; 0 when the grid or the particle count rules the tiled
+// deposit out (then the direct atomic deposit is used).
+size_t tiled_deposit_temp_bytes(int64_t cells, int64_t total, int32_t n_snap, int32_t F);
+cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipStream_t s);
+
 // cg_hex.hip
 struct DiffuseArgs {
     int32_t F;

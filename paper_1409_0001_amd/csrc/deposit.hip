@@ -118,15 +118,19 @@ __global__ __launch_bounds__(kBlock) void k_deposit_hex(
 }
 
 // ---------------------------------------------------------------- tiled deposit
-// The cells are cut into tiles of `cpt` consecutive indices.  The particles
-// are bucketed by tile (a counting sort over fixed chunks of particles per
-// block), then one workgroup per tile adds its particles' fixed-point values
-// in LDS and writes the tile's finished field (and accumulators): every int64
-// sum stays exact, and the device-wide atomics on the accumulators of the
-// direct path are replaced by LDS atomics.  A bucketed record is 8 bytes,
-// (cell within the tile, bits of the first field's value); further fields'
-// values follow in their own arrays, and the values are quantised in the
-// accumulate pass.
+// The cells of a grid are cut into tiles of `cpt` consecutive indices.  The
+// particles are bucketed by tile (a counting sort over fixed chunks of
+// particles per block), then one workgroup per tile adds its particles'
+// fixed-point values in LDS and writes the tile's finished field (and
+// accumulators): every int64 sum stays exact, and the device-wide atomics on
+// the accumulators of the direct path are replaced by LDS atomics.  A
+// bucketed record is 8 bytes, (cell within the tile, bits of the first
+// field's value); further fields' values follow in their own arrays, and the
+// values are quantised in the accumulate pass.  Several snapshots on the
+// same grid (particle ranges off[j] .. off[j + 1]) are deposited together:
+// snapshot j's tiles are numbered j * ntiles + t, and its fixed-point scales
+// come from its own max |v| and particle count, so each snapshot's result is
+// the one a deposit of that snapshot alone gives.
 
 constexpr int kTBlock = 1024;
 constexpr int kTPer = 16;                  // particles per thread and pass, held in registers
@@ -134,44 +138,62 @@ constexpr int kTChunk = kTBlock * 16;      // particles per block and chunk of t
 constexpr int kTPass = kTChunk / (kTBlock * kTPer);  // register passes per chunk
 constexpr int kBPer = 4;                   // particles per thread and register pass of the counting pass
 constexpr int kTileWords = 16384;          // int64 LDS accumulators of one tile workgroup (128 KB)
-constexpr int kMaxTiles = 8192;            // LDS tile counters of the bucketing passes
+constexpr int kMaxTiles = 8192;            // LDS tile counters of the bucketing passes (per snapshot)
 
 struct TileArgs {
     const float* pos;
-    const float* values;
-    int64_t n;
-    int F;
+    const float* values;   // [F][total]
+    int64_t total;
+    const int64_t* off;    // [n_snap + 1] particle offsets; nullptr: one snapshot [0, total)
+    int n_snap, F;
     HexBin g;
-    int e_n;
-    int64_t cells;
-    int cpt, ntiles;
-    int cpt_log2;       // cpt = 2^cpt_log2
-    int nsub;           // kTChunk-particle passes per block of the scatter
-    int nsub_bin;       // ... and of the counting pass
-    int32_t* cellbuf;   // [n]: host cell of each particle (-1: dropped)
-    uint32_t* counts;   // [ntiles]: particles per tile
-    uint32_t* offsets;  // [ntiles + 1]
-    uint32_t* cursor;   // [ntiles]
-    uint2* rec;         // [n]: (cell within its tile, bits of field 0's value), tile-bucketed
-    float* rv;          // [F - 1][n]: values of fields 1.., tile-bucketed
-    float* field;
-    long long* acc;     // nullable
+    int64_t cells;         // of one snapshot's grid
+    int cpt, ntiles;       // cells per tile, tiles per snapshot
+    int cpt_log2;          // cpt = 2^cpt_log2
+    int nsub;              // kTChunk-particle chunks per block of the scatter
+    int nsub_bin;          // ... and of the counting pass
+    int32_t* cellbuf;      // [total]: host cell of each particle (-1: dropped)
+    uint32_t* counts;      // [n_snap * ntiles]: particles per tile
+    uint32_t* offsets;     // [n_snap * ntiles + 1]
+    uint32_t* cursor;      // [n_snap * ntiles]
+    uint2* rec;            // [total]: (cell within its tile, bits of field 0's value), tile-bucketed
+    float* rv;             // [F - 1][total]: values of fields 1.., tile-bucketed
+    uint32_t* maxbits;     // [n_snap][F]
+    unsigned long long* nf_val;  // field f's non-finite values counted at nf_val[f * nf_val_stride]
+    int nf_val_stride;
+    unsigned long long* dropped;
+    unsigned long long* nf_pos;
+    float* field;          // [n_snap][F][cells]
+    long long* acc;        // nullable, [n_snap][F][cells]
     double vol;
-    DepositInfo* info;
 };
 
-__global__ void k_tile_clear(TileArgs a) {
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < a.ntiles; t += gridDim.x * blockDim.x) a.counts[t] = 0u;
+__device__ inline void snap_range(const TileArgs& a, int j, int64_t& s0, int64_t& s1) {
+    s0 = a.off ? a.off[j] : 0;
+    s1 = a.off ? a.off[j + 1] : a.total;
 }
 
-// Pass 1: host cells (stored), dropped counts, particles per tile, and the
-// max |v| / non-finite count of every field over the block's chunk of
-// nsub_bin * kTChunk particles (the values of the direct path's k_absmax,
-// folded into this pass).
+__device__ inline int e_n_dev(int64_t n) { return n <= 1 ? 0 : 64 - __clzll((unsigned long long)(n - 1)); }
+
+__global__ void k_tile_clear(TileArgs a) {
+    const int nt = a.n_snap * a.ntiles;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += gridDim.x * blockDim.x) a.counts[t] = 0u;
+}
+
+// Pass 1 (grid: blocks x snapshots): host cells (stored), dropped counts,
+// particles per tile, and the max |v| / non-finite count of every field over
+// the block's chunk of nsub_bin * kTChunk particles (the values of the direct
+// path's k_absmax, folded into this pass).
 __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
     __shared__ uint32_t hist[kMaxTiles];
     __shared__ uint32_t bmax[CGD_MAX_FIELDS];
     __shared__ unsigned long long bbad[CGD_MAX_FIELDS];
+    const int j = blockIdx.y;
+    int64_t s0, s1;
+    snap_range(a, j, s0, s1);
+    const int64_t cb = s0 + (int64_t)blockIdx.x * a.nsub_bin * kTChunk;
+    if (cb >= s1) return;  // the whole block: beyond its snapshot's particles
+    const int64_t ce = min(cb + (int64_t)a.nsub_bin * kTChunk, s1);
     for (int t = threadIdx.x; t < a.ntiles; t += kTBlock) hist[t] = 0u;
     if (threadIdx.x < CGD_MAX_FIELDS) {
         bmax[threadIdx.x] = 0u;
@@ -181,11 +203,11 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
     unsigned long long dropped = 0ull, nfpos = 0ull;
     const int npass = a.nsub_bin * (kTChunk / (kTBlock * kBPer));
     for (int sub = 0; sub < npass; ++sub) {
-        const int64_t p0 = ((int64_t)blockIdx.x * npass + sub) * (kTBlock * kBPer) + threadIdx.x;
+        const int64_t p0 = cb + (int64_t)sub * (kTBlock * kBPer) + threadIdx.x;
         float px[kBPer], py[kBPer], pz[kBPer];
 #pragma unroll
         for (int i = 0; i < kBPer; ++i) {
-            const int64_t p = min(p0 + (int64_t)i * kTBlock, a.n - 1);
+            const int64_t p = min(p0 + (int64_t)i * kTBlock, ce - 1);
             px[i] = a.pos[3 * p];
             py[i] = a.pos[3 * p + 1];
             pz[i] = a.pos[3 * p + 2];
@@ -193,7 +215,7 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
 #pragma unroll
         for (int i = 0; i < kBPer; ++i) {
             const int64_t p = p0 + (int64_t)i * kTBlock;
-            if (p >= a.n) continue;
+            if (p >= ce) continue;
             bool nf;
             const int32_t k = (int32_t)hex_cell(a.g, px[i], py[i], pz[i], &nf);
             a.cellbuf[p] = k;
@@ -206,16 +228,16 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
         }
     }
     for (int f = 0; f < a.F; ++f) {
-        const uint32_t* v = reinterpret_cast<const uint32_t*>(a.values + (size_t)f * a.n);
+        const uint32_t* v = reinterpret_cast<const uint32_t*>(a.values + (size_t)f * a.total);
         uint32_t m = 0u;
         unsigned long long bad = 0ull;
         for (int sub = 0; sub < npass; ++sub) {
-            const int64_t p0 = ((int64_t)blockIdx.x * npass + sub) * (kTBlock * kBPer) + threadIdx.x;
+            const int64_t p0 = cb + (int64_t)sub * (kTBlock * kBPer) + threadIdx.x;
             uint32_t x[kBPer];
 #pragma unroll
             for (int i = 0; i < kBPer; ++i) {
                 const int64_t p = p0 + (int64_t)i * kTBlock;
-                x[i] = p < a.n ? v[p] & 0x7fffffffu : 0u;
+                x[i] = p < ce ? v[p] & 0x7fffffffu : 0u;
             }
 #pragma unroll
             for (int i = 0; i < kBPer; ++i) {
@@ -241,23 +263,26 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
         nfpos += __shfl_xor(nfpos, o);
     }
     if ((threadIdx.x & 63) == 0 && dropped) {
-        atomicAdd(&a.info->dropped, dropped);
-        if (nfpos) atomicAdd(&a.info->nonfinite_pos, nfpos);
+        atomicAdd(a.dropped, dropped);
+        if (nfpos) atomicAdd(a.nf_pos, nfpos);
     }
     __syncthreads();
+    uint32_t* counts = a.counts + (size_t)j * a.ntiles;
     for (int t = threadIdx.x; t < a.ntiles; t += kTBlock)
-        if (hist[t]) atomicAdd(&a.counts[t], hist[t]);
+        if (hist[t]) atomicAdd(&counts[t], hist[t]);
     if (threadIdx.x < a.F) {
-        if (bmax[threadIdx.x]) atomicMax(&a.info->maxbits[threadIdx.x], bmax[threadIdx.x]);
-        if (bbad[threadIdx.x]) atomicAdd(&a.info->nonfinite_val[threadIdx.x], bbad[threadIdx.x]);
+        const int f = threadIdx.x;
+        if (bmax[f]) atomicMax(&a.maxbits[j * a.F + f], bmax[f]);
+        if (bbad[f]) atomicAdd(&a.nf_val[f * a.nf_val_stride], bbad[f]);
     }
 }
 
-// Pass 2: offsets = exclusive prefix sum of the counts (one block).
+// Pass 2: offsets = exclusive prefix sum of the counts of all tiles (one block).
 __global__ __launch_bounds__(kTBlock) void k_tile_scan(TileArgs a) {
     __shared__ uint32_t part[kTBlock];
-    const int per = (a.ntiles + kTBlock - 1) / kTBlock;
-    const int t0 = threadIdx.x * per, t1 = min(t0 + per, a.ntiles);
+    const int nt = a.n_snap * a.ntiles;
+    const int per = (nt + kTBlock - 1) / kTBlock;
+    const int t0 = min(threadIdx.x * per, nt), t1 = min(t0 + per, nt);
     uint32_t s = 0u;
     for (int t = t0; t < t1; ++t) s += a.counts[t];
     part[threadIdx.x] = s;
@@ -269,7 +294,7 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scan(TileArgs a) {
             part[i] = run;
             run += v;
         }
-        a.offsets[a.ntiles] = run;
+        a.offsets[nt] = run;
     }
     __syncthreads();
     uint32_t run = part[threadIdx.x];
@@ -280,15 +305,20 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scan(TileArgs a) {
     }
 }
 
-// Pass 3: each block counts its chunk of nsub * kTChunk particles per tile,
-// reserves one range per tile, then writes the particles' records there, a
-// register pass of kTPer particles per thread at a time.
-// Longer chunks give longer runs of consecutive slots per block and tile,
-// which the L2 merges into whole lines before they are written back.
+// Pass 3 (grid: blocks x snapshots): each block counts its chunk of
+// nsub * kTChunk particles per tile, reserves one range per tile, then
+// writes the particles' records there, a register pass of kTPer particles
+// per thread at a time.
 __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
     __shared__ uint32_t hist[kMaxTiles];
     __shared__ uint32_t base[kMaxTiles];
-    const int64_t c0 = (int64_t)blockIdx.x * a.nsub * kTChunk + threadIdx.x;
+    const int j = blockIdx.y;
+    int64_t s0, s1;
+    snap_range(a, j, s0, s1);
+    const int64_t cb = s0 + (int64_t)blockIdx.x * a.nsub * kTChunk;
+    if (cb >= s1) return;  // the whole block: beyond its snapshot's particles
+    const int64_t ce = min(cb + (int64_t)a.nsub * kTChunk, s1);
+    const int64_t c0 = cb + threadIdx.x;
     for (int t = threadIdx.x; t < a.ntiles; t += kTBlock) hist[t] = 0u;
     __syncthreads();
     const int npass = a.nsub * kTPass;
@@ -298,16 +328,17 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
 #pragma unroll
         for (int i = 0; i < kTPer; ++i) {
             const int64_t p = p0 + (int64_t)i * kTBlock;
-            kk[i] = p < a.n ? a.cellbuf[p] : -1;
+            kk[i] = p < ce ? a.cellbuf[p] : -1;
         }
 #pragma unroll
         for (int i = 0; i < kTPer; ++i)
             if (kk[i] >= 0) atomicAdd(&hist[kk[i] >> a.cpt_log2], 1u);
     }
     __syncthreads();
+    uint32_t* cursor = a.cursor + (size_t)j * a.ntiles;
     for (int t = threadIdx.x; t < a.ntiles; t += kTBlock) {
         const uint32_t c = hist[t];
-        base[t] = c ? atomicAdd(&a.cursor[t], c) : 0u;
+        base[t] = c ? atomicAdd(&cursor[t], c) : 0u;
         hist[t] = 0u;  // reused as the in-block rank counter
     }
     __syncthreads();
@@ -318,8 +349,8 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
 #pragma unroll
         for (int i = 0; i < kTPer; ++i) {
             const int64_t p = p0 + (int64_t)i * kTBlock;
-            kk[i] = p < a.n ? a.cellbuf[p] : -1;
-            v0[i] = p < a.n ? a.values[p] : 0.f;
+            kk[i] = p < ce ? a.cellbuf[p] : -1;
+            v0[i] = p < ce ? a.values[p] : 0.f;
         }
         uint32_t slot[kTPer];
 #pragma unroll
@@ -330,14 +361,14 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
             a.rec[slot[i]] = make_uint2((uint32_t)(kk[i] & (a.cpt - 1)), __float_as_uint(v0[i]));
         }
         for (int f = 1; f < a.F; ++f) {
-            const float* vf = a.values + (size_t)f * a.n;
+            const float* vf = a.values + (size_t)f * a.total;
             float v[kTPer];
 #pragma unroll
             for (int i = 0; i < kTPer; ++i) {
                 const int64_t p = p0 + (int64_t)i * kTBlock;
-                v[i] = p < a.n ? vf[p] : 0.f;
+                v[i] = p < ce ? vf[p] : 0.f;
             }
-            float* rvf = a.rv + (size_t)(f - 1) * a.n;
+            float* rvf = a.rv + (size_t)(f - 1) * a.total;
 #pragma unroll
             for (int i = 0; i < kTPer; ++i)
                 if (kk[i] >= 0) rvf[slot[i]] = v[i];
@@ -349,54 +380,59 @@ __device__ inline long long quantise(float v, int S) {
     return isfinite(v) ? __double2ll_rn(ldexp((double)v, S)) : 0ll;
 }
 
-// Pass 4: one workgroup per tile: exact int64 sums in LDS of the quantised
-// values rint(v 2^S_f), then the tile's field = float32((acc 2^-S_f) / V)
-// (and the accumulators when asked for).
+// Pass 4: one workgroup per tile (of all snapshots): exact int64 sums in LDS
+// of the quantised values rint(v 2^S_f), then the tile's
+// field = float32((acc 2^-S_f) / V) (and the accumulators when asked for).
 __global__ __launch_bounds__(kTBlock) void k_tile_accum(TileArgs a) {
     __shared__ unsigned long long lacc[kTileWords];
     __shared__ int S[CGD_MAX_FIELDS];
-    const int t = blockIdx.x;
+    const int T = blockIdx.x;
+    const int j = T / a.ntiles, t = T - j * a.ntiles;
     const int64_t c0 = (int64_t)t * a.cpt;
     const int nc = (int)min<int64_t>(a.cpt, a.cells - c0);
     for (int i = threadIdx.x; i < a.F * a.cpt; i += kTBlock) lacc[i] = 0ull;
-    if (threadIdx.x < a.F) S[threadIdx.x] = frac_bits_of(a.info->maxbits[threadIdx.x], a.e_n);
+    if (threadIdx.x < a.F) {
+        int64_t s0, s1;
+        snap_range(a, j, s0, s1);
+        S[threadIdx.x] = frac_bits_of(a.maxbits[j * a.F + threadIdx.x], e_n_dev(s1 - s0));
+    }
     __syncthreads();
-    const uint32_t r0 = a.offsets[t], r1 = a.offsets[t + 1];
+    const uint32_t r0 = a.offsets[T], r1 = a.offsets[T + 1];
     const int S0 = S[0];
     constexpr int U = 4;  // records per thread whose loads are in flight together
     for (uint32_t r = r0 + threadIdx.x; r < r1; r += U * kTBlock) {
         uint2 e[U];
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const uint32_t rr = r + j * kTBlock;
-            e[j] = rr < r1 ? a.rec[rr] : make_uint2(0u, 0u);
+        for (int u = 0; u < U; ++u) {
+            const uint32_t rr = r + u * kTBlock;
+            e[u] = rr < r1 ? a.rec[rr] : make_uint2(0u, 0u);
         }
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const long long q = quantise(__uint_as_float(e[j].y), S0);
-            if (q != 0) atomicAdd(&lacc[e[j].x], (unsigned long long)q);
+        for (int u = 0; u < U; ++u) {
+            const long long q = quantise(__uint_as_float(e[u].y), S0);
+            if (q != 0) atomicAdd(&lacc[e[u].x], (unsigned long long)q);
         }
         for (int f = 1; f < a.F; ++f) {
             float v[U];
 #pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const uint32_t rr = r + j * kTBlock;
-                v[j] = rr < r1 ? a.rv[(size_t)(f - 1) * a.n + rr] : 0.f;
+            for (int u = 0; u < U; ++u) {
+                const uint32_t rr = r + u * kTBlock;
+                v[u] = rr < r1 ? a.rv[(size_t)(f - 1) * a.total + rr] : 0.f;
             }
 #pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const long long q = quantise(v[j], S[f]);
-                if (q != 0) atomicAdd(&lacc[f * a.cpt + e[j].x], (unsigned long long)q);
+            for (int u = 0; u < U; ++u) {
+                const long long q = quantise(v[u], S[f]);
+                if (q != 0) atomicAdd(&lacc[f * a.cpt + e[u].x], (unsigned long long)q);
             }
         }
     }
     __syncthreads();
     for (int f = 0; f < a.F; ++f) {
-        float* out = a.field + (size_t)f * a.cells + c0;
+        const size_t o = ((size_t)j * a.F + f) * a.cells + c0;
         for (int i = threadIdx.x; i < nc; i += kTBlock) {
             const long long v = (long long)lacc[f * a.cpt + i];
-            out[i] = (float)(ldexp((double)v, -S[f]) / a.vol);
-            if (a.acc) a.acc[(size_t)f * a.cells + c0 + i] = v;
+            a.field[o + i] = (float)(ldexp((double)v, -S[f]) / a.vol);
+            if (a.acc) a.acc[o + i] = v;
         }
     }
 }
@@ -468,11 +504,10 @@ cgd_status locate_hex(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hi
 
 // Tiling of the tiled deposit (tiles of a power-of-two number of cells, so
 // that tile and cell-in-tile are a shift and a mask); false when the direct
-// (atomic) path is used:
-// more tiles than the bucketing passes count in LDS, more particles than
-// 32-bit offsets hold, or CGD_DEPOSIT_DIRECT set.
-bool tile_plan(int64_t cells, int64_t n, int32_t F, int* cpt, int* ntiles) {
-    if (getenv("CGD_DEPOSIT_DIRECT") || n <= 0 || n >= (int64_t)UINT32_MAX) return false;
+// (atomic) path is used: more tiles per grid than the bucketing passes count
+// in LDS, more particles than 32-bit offsets hold, or CGD_DEPOSIT_DIRECT set.
+static bool tile_plan(int64_t cells, int64_t total, int32_t F, int* cpt, int* ntiles) {
+    if (getenv("CGD_DEPOSIT_DIRECT") || total <= 0 || total >= (int64_t)UINT32_MAX) return false;
     int c = kTileWords;  // the largest power of two with F * c <= kTileWords
     while (c * F > kTileWords) c >>= 1;
     const int64_t t = (cells + c - 1) / c;
@@ -482,20 +517,79 @@ bool tile_plan(int64_t cells, int64_t n, int32_t F, int* cpt, int* ntiles) {
     return true;
 }
 
-size_t deposit_hex_temp_bytes(const cgd_mesh m, int64_t n, int32_t F) {
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t tiled_deposit_temp_bytes(int64_t cells, int64_t total, int32_t n_snap, int32_t F) {
     int cpt, nt;
-    if (!tile_plan(m->cells, n, F, &cpt, &nt)) return 0;
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    return al(4 * (size_t)n) + al(8 * (size_t)n) + al(4 * (size_t)(F - 1) * n) + al(4 * (3 * (size_t)nt + 1));
+    if (!tile_plan(cells, total, F, &cpt, &nt)) return 0;
+    return al256(4 * (size_t)total) + al256(8 * (size_t)total) + al256(4 * (size_t)(F - 1) * total) +
+           al256(4 * (3 * (size_t)n_snap * nt + 1));
 }
 
-// kTChunk-particle passes per scatter block: as long as the grid still
-// gives every compute unit several blocks.
-static int scatter_nsub(const char* env, int64_t n) {
+size_t deposit_hex_temp_bytes(const cgd_mesh m, int64_t n, int32_t F) {
+    return tiled_deposit_temp_bytes(m->cells, n, 1, F);
+}
+
+// kTChunk-particle chunks per block of a bucketing pass: doubled while the
+// grid still gives every compute unit several blocks.
+static int tile_nsub(const char* env, int64_t n) {
     if (const char* e = getenv(env)) return std::max(1, atoi(e));
     int nsub = 1;
     while (nsub < 8 && (n + 2 * nsub * (int64_t)kTChunk - 1) / (2 * nsub * (int64_t)kTChunk) >= 1024) nsub *= 2;
     return nsub;
+}
+
+cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipStream_t s) {
+    int cpt = 0, nt = 0;
+    if (!d.temp || !tile_plan(m->cells, d.total, d.F, &cpt, &nt)) {
+        set_error("tiled deposit: no tiling for this grid and particle count");
+        return CGD_E_INVALID;
+    }
+    char* t = static_cast<char*>(d.temp);
+    TileArgs a = {};
+    a.pos = d.pos;
+    a.values = d.values;
+    a.total = d.total;
+    a.off = d.off;
+    a.n_snap = d.n_snap;
+    a.F = d.F;
+    a.g = hex_bin(m);
+    a.cells = m->cells;
+    a.cpt = cpt;
+    a.cpt_log2 = __builtin_ctz((unsigned)cpt);
+    a.ntiles = nt;
+    a.nsub = tile_nsub("CGD_DEPOSIT_NSUB", d.total);
+    a.nsub_bin = tile_nsub("CGD_DEPOSIT_BIN_NSUB", d.total);
+    a.cellbuf = reinterpret_cast<int32_t*>(t);
+    t += al256(4 * (size_t)d.total);
+    a.rec = reinterpret_cast<uint2*>(t);
+    t += al256(8 * (size_t)d.total);
+    a.rv = reinterpret_cast<float*>(t);
+    t += al256(4 * (size_t)(d.F - 1) * d.total);
+    const int all = d.n_snap * nt;
+    a.counts = reinterpret_cast<uint32_t*>(t);
+    a.offsets = a.counts + all;
+    a.cursor = a.offsets + all + 1;
+    a.maxbits = d.maxbits;
+    a.nf_val = d.nf_val;
+    a.nf_val_stride = d.nf_val_stride;
+    a.dropped = d.dropped;
+    a.nf_pos = d.nf_pos;
+    a.field = d.field;
+    a.acc = d.acc;
+    a.vol = m->hex.vol;
+    hipLaunchKernelGGL(k_tile_clear, dim3((all + 255) / 256), dim3(256), 0, s, a);
+    const int64_t bchunk = (int64_t)a.nsub_bin * kTChunk, schunk = (int64_t)a.nsub * kTChunk;
+    const int cblocks = (int)std::max<int64_t>(1, (d.max_n + bchunk - 1) / bchunk);
+    const int sblocks = (int)std::max<int64_t>(1, (d.max_n + schunk - 1) / schunk);
+    int tm = timing ? timing_begin(timing, s) : -1;
+    hipLaunchKernelGGL(k_tile_bin, dim3(cblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kTBlock), 0, s, a);
+    hipLaunchKernelGGL(k_tile_scatter, dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    hipLaunchKernelGGL(k_tile_accum, dim3(all), dim3(kTBlock), 0, s, a);
+    if (timing) timing_end(timing, tm, 2, (12.0 + 12.0 * d.F) * (double)d.total, s);
+    CGD_HIP_TRY(hipGetLastError());
+    return CGD_OK;
 }
 
 cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
@@ -503,48 +597,25 @@ cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
     const int64_t cells = m->cells;
     const int e_n = ceil_log2_count(n);
     const HexBin g = hex_bin(m);
-    int cpt = 0, nt = 0;
-    if (temp && tile_plan(cells, n, F, &cpt, &nt)) {
-        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-        char* t = static_cast<char*>(temp);
-        TileArgs a = {};
-        a.pos = pos;
-        a.values = values;
-        a.n = n;
-        a.F = F;
-        a.g = g;
-        a.e_n = e_n;
-        a.cells = cells;
-        a.cpt = cpt;
-        a.cpt_log2 = __builtin_ctz((unsigned)cpt);
-        a.ntiles = nt;
-        a.nsub = scatter_nsub("CGD_DEPOSIT_NSUB", n);
-        a.nsub_bin = scatter_nsub("CGD_DEPOSIT_BIN_NSUB", n);
-        a.cellbuf = reinterpret_cast<int32_t*>(t);
-        t += al(4 * (size_t)n);
-        a.rec = reinterpret_cast<uint2*>(t);
-        t += al(8 * (size_t)n);
-        a.rv = reinterpret_cast<float*>(t);
-        t += al(4 * (size_t)(F - 1) * n);
-        a.counts = reinterpret_cast<uint32_t*>(t);
-        a.offsets = a.counts + nt;
-        a.cursor = a.offsets + nt + 1;
-        a.field = field;
-        a.acc = reinterpret_cast<long long*>(acc);
-        a.vol = m->hex.vol;
-        a.info = info;
+    if (temp && deposit_hex_temp_bytes(m, n, F) > 0) {
+        TiledDeposit d = {};
+        d.pos = pos;
+        d.values = values;
+        d.total = n;
+        d.max_n = n;
+        d.off = nullptr;
+        d.n_snap = 1;
+        d.F = F;
+        d.maxbits = info->maxbits;
+        d.nf_val = info->nonfinite_val;
+        d.nf_val_stride = 1;
+        d.dropped = &info->dropped;
+        d.nf_pos = &info->nonfinite_pos;
+        d.field = field;
+        d.acc = reinterpret_cast<long long*>(acc);
+        d.temp = temp;
         hipLaunchKernelGGL(k_dep_init, dim3(1), dim3(64), 0, s, info);
-        hipLaunchKernelGGL(k_tile_clear, dim3((nt + 255) / 256), dim3(256), 0, s, a);
-        const int cblocks = (int)((n + (int64_t)a.nsub_bin * kTChunk - 1) / ((int64_t)a.nsub_bin * kTChunk));
-        int tm = timing_begin(&m->timing, s);
-        hipLaunchKernelGGL(k_tile_bin, dim3(cblocks), dim3(kTBlock), 0, s, a);
-        hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kTBlock), 0, s, a);
-        const int sblocks = (int)((n + (int64_t)a.nsub * kTChunk - 1) / ((int64_t)a.nsub * kTChunk));
-        hipLaunchKernelGGL(k_tile_scatter, dim3(sblocks), dim3(kTBlock), 0, s, a);
-        hipLaunchKernelGGL(k_tile_accum, dim3(nt), dim3(kTBlock), 0, s, a);
-        timing_end(&m->timing, tm, 2, (12.0 + 12.0 * F) * (double)n, s);
-        CGD_HIP_TRY(hipGetLastError());
-        return CGD_OK;
+        return tiled_deposit(m, d, &m->timing, s);
     }
     deposit_prologue(n, F, values, acc, cells, info, s);
     if (n > 0) {

@@ -108,6 +108,27 @@ def test_batched_conserves_each_snapshot(gpu_lib):
             assert abs(out[j, f].sum() * V - m_in) <= 1e-5 * scale
 
 
+def test_batched_tiled_and_direct_deposits_agree_bitwise(gpu_lib, monkeypatch):
+    """The tiled deposit (particles bucketed by tile of every snapshot, sums
+    in LDS) and the direct one (int64 atomics) are both exact, and the solve
+    is deterministic, so the batched results agree bit for bit; snapshots
+    span many tiles, one is empty and one holds a single particle."""
+    import torch
+    cgd = gpu_lib
+    shape = (128, 64, 48)  # 96 tiles of 4096 cells per snapshot at F = 4
+    counts = [60_000, 0, 1, 25_000, 90_000]
+    box, parts, pos, vals, off = _batch(shape, counts, seed=97)
+    print(f"case: batched tiled vs direct deposit {shape} snapshots {counts}", flush=True)
+    mesh = cgd.HexMesh(shape, box.lo, box.hi)
+    dpos, dvals = _t(pos, torch), _t(vals, torch)
+    monkeypatch.delenv("CGD_DEPOSIT_DIRECT", raising=False)
+    tiled = cgd.coarse_grain_batched(mesh, off, dpos, dvals, 4.0 / shape[0], 2, rtol=1e-7).clone()
+    monkeypatch.setenv("CGD_DEPOSIT_DIRECT", "1")
+    direct = cgd.coarse_grain_batched(mesh, off, dpos, dvals, 4.0 / shape[0], 2, rtol=1e-7)
+    assert torch.equal(tiled.view(torch.int32), direct.view(torch.int32))
+    assert not tiled[1].any()
+
+
 def test_graph_replays_equal_eager(gpu_lib):
     """The captured graph, replayed several times with eager work and
     synchronisations in between, gives the eager result bit for bit."""
