@@ -48,19 +48,21 @@ def test_deposit_tiny_bit_exact(gpu_lib):
     assert torch.equal(field3.view(torch.int32), field.view(torch.int32))
 
 
-def test_deposit_many_tiles_clustered_bit_exact(gpu_lib):
-    """The dense-bed recipe on 96 x 80 x 200 (1.5M cells; with F = 2, 188
-    tiles of 8192 cells, the upper ones empty): the tiled deposit's fields
-    and accumulators are bit-identical to the oracle's."""
+@pytest.mark.parametrize("F", [2, 3])
+def test_deposit_many_tiles_clustered_bit_exact(gpu_lib, F):
+    """The dense-bed recipe on 96 x 80 x 200 (1.5M cells; tiles of 8192
+    cells at F = 2 and, rounded down to a power of two, 4096 at F = 3; the
+    upper tiles empty): the tiled deposit's fields and accumulators are
+    bit-identical to the oracle's."""
     import torch
     cgd = gpu_lib
-    w = inputs.dense_bed(n_particles=400_000, shape=(96, 80, 200), n_fields=2)
+    w = inputs.dense_bed(n_particles=400_000, shape=(96, 80, 200), n_fields=F)
     print(f"case: {w.name}", flush=True)
     mesh = cgd.HexMesh(w.box.shape, w.box.lo, w.box.hi)
-    acc = torch.empty((2, mesh.cells), dtype=torch.int64, device="cuda")
+    acc = torch.empty((F, mesh.cells), dtype=torch.int64, device="cuda")
     field, st = cgd.deposit(mesh, _t(w.particles.pos, torch), _t(w.particles.values, torch), acc=acc, stats=True)
     ref = O.deposit_hex(w.particles.pos, w.particles.values, w.box.lo, w.box.hi, w.box.shape)
-    assert st.frac_bits[:2] == ref["S"]
+    assert st.frac_bits[:F] == ref["S"]
     assert np.array_equal(acc.cpu().numpy(), ref["acc"])
     assert np.array_equal(field.cpu().numpy().view(np.uint32), ref["field32"].view(np.uint32))
 
