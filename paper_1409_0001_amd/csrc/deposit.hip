@@ -530,13 +530,12 @@ size_t deposit_hex_temp_bytes(const cgd_mesh m, int64_t n, int32_t F) {
     return tiled_deposit_temp_bytes(m->cells, n, 1, F);
 }
 
-// kTChunk-particle chunks per block of a bucketing pass: doubled while the
-// grid still gives every compute unit several blocks.
-static int tile_nsub(const char* env, int64_t n) {
+// kTChunk-particle chunks per block of a bucketing pass: one (longer chunks
+// measured slower on the dense bed and on the batched launch); an
+// environment override for tuning runs.
+static int tile_nsub(const char* env) {
     if (const char* e = getenv(env)) return std::max(1, atoi(e));
-    int nsub = 1;
-    while (nsub < 8 && (n + 2 * nsub * (int64_t)kTChunk - 1) / (2 * nsub * (int64_t)kTChunk) >= 1024) nsub *= 2;
-    return nsub;
+    return 1;
 }
 
 cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipStream_t s) {
@@ -558,8 +557,8 @@ cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipS
     a.cpt = cpt;
     a.cpt_log2 = __builtin_ctz((unsigned)cpt);
     a.ntiles = nt;
-    a.nsub = tile_nsub("CGD_DEPOSIT_NSUB", d.total);
-    a.nsub_bin = tile_nsub("CGD_DEPOSIT_BIN_NSUB", d.total);
+    a.nsub = tile_nsub("CGD_DEPOSIT_NSUB");
+    a.nsub_bin = tile_nsub("CGD_DEPOSIT_BIN_NSUB");
     a.cellbuf = reinterpret_cast<int32_t*>(t);
     t += al256(4 * (size_t)d.total);
     a.rec = reinterpret_cast<uint2*>(t);
