@@ -137,8 +137,13 @@ cgd_status cgd_locate(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, vo
  * lowest id on ties).  Its value v of field f is quantised to
  * q = rint(v * 2^S_f) (int64, round half to even) with S_f = 62 - e_max - e_N
  * (max_p |v_p| <= 2^e_max over finite values, e_N = ceil(log2 n)), so that no
- * sum can overflow, and added with integer atomics: the sums are exact and
- * independent of particle order.  Then field[f, k] = float32(acc * 2^-S_f / V_k).
+ * sum can overflow, and summed in int64: the sums are exact and independent
+ * of particle order.  Then field[f, k] = float32(acc * 2^-S_f / V_k).  On hex
+ * meshes the particles are bucketed by tile of consecutive cells and each
+ * tile is summed in LDS (the temporary buffers, 8 + 4 F bytes per
+ * particle, come from the mesh workspace); with more than 8192 tiles or 2^32
+ * particles, or CGD_DEPOSIT_DIRECT set in the environment, every particle is
+ * added with a device-wide int64 atomic instead.  Both give the same bits.
  *
  *  n:       number of particles (>= 0)
  *  pos:     device float32 [n, 3]
@@ -304,11 +309,13 @@ cgd_status cgd_conv3_wgrad(int32_t nx, int32_t ny, int32_t nz, int32_t ci, int32
 
 /* Kernel timing, for roofline measurement.  While enabled, each launch of the
  * timed kernels is bracketed by two HIP events recorded on the caller's
- * stream; the elapsed times are collected when the call synchronises (every
- * cgd_diffuse / cgd_coarse_grain does at its end).  Kinds:
+ * stream (events without a system-scope fence, so that timing stalls the
+ * queue as little as possible); the elapsed times are collected when the
+ * call synchronises (every cgd_diffuse / cgd_coarse_grain does at its end).
+ * Kinds:
  *   0  CG sweep 1 (p = r + beta p_old, A p, p.Ap), hex stencil
  *   1  CG sweep 2 (x += alpha p, r -= alpha A p, r.r), hex stencil
- *   2  centroid binning + fixed-point atomic deposit (hex)
+ *   2  hex deposit: centroid binning, bucketing and fixed-point sums
  *   3  matrix sweep of the tet Jacobi-PCG (p, A p, p.Ap)
  *   4  update sweep of the tet Jacobi-PCG (x, r, r.z, r.r)
  *   5  hex preconditioning sweep (z = M r, r.z)

@@ -150,7 +150,7 @@ struct BSolve {
     float* fields;      // [n_rhs][cells]: in deposited, out diffused
     float* ws;          // [grid][5][cells]
     int pcg;            // 1: preconditioned CG (degree 2: Geom c0, c1, c2; degree 4: cp)
-    float cp[8];        // degree-4 polynomial (configurations with DEG = 4)
+    PrecondCoef pc;     // degree-4 polynomial's Horner levels (configurations with DEG = 4)
     int n_rhs;
     int64_t cells;
     Geom g;
@@ -229,7 +229,7 @@ __device__ inline void wg_precond_lds(float* lds, const BSolve& a, const Ptrs& p
     double acc0 = 0.0, acc1 = 0.0;
     const int tiles = (a.g.ny + 7) / 8;
     for (int t = 0; t < tiles; ++t)
-        precond_lds_tile<VEC, 4, 8, NW, FIRST>(lds, FIRST ? p.B : p.R, p.Z, a.g, a.cp, a.g.ny, a.g.nz, 8 * t, 0,
+        precond_lds_tile<VEC, 4, 8, NW, FIRST>(lds, FIRST ? p.B : p.R, p.Z, a.g, a.pc, a.g.ny, a.g.nz, 8 * t, 0,
                                                a.g.nz, acc0, acc1);
     wg_sum2<NW>(acc0, acc1, sh);
     s0 = acc0;
@@ -569,7 +569,7 @@ cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, 
     {
         double c4[8];
         poly_precond_coeffs_n(1.0, 1.0, 1.0, 4, c4);
-        for (int j = 0; j <= 4; ++j) a.cp[j] = (float)c4[j];
+        precond_coef_fill(a.pc, a.g.cx, a.g.cy, a.g.cz, c4, 4);
     }
     // time to solution (rtol 1e-6), so that candidates of different
     // preconditioner degree compare fairly
@@ -717,7 +717,7 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     {
         double c4[8];
         poly_precond_coeffs_n(a.g.cx, a.g.cy, a.g.cz, 4, c4);
-        for (int j = 0; j <= 4; ++j) a.cp[j] = (float)c4[j];
+        precond_coef_fill(a.pc, a.g.cx, a.g.cy, a.g.cz, c4, 4);
     }
     a.xsegs = 1;
     a.ygroups = (g.ny + c.ty - 1) / c.ty;

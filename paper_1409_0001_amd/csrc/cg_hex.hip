@@ -60,7 +60,7 @@ struct SweepArgs {
     int xsegs, ygroups, zc;
     int wpf, bpf, nblocks;
     int k;              // iteration index within the step
-    float cp[8];        // k_precond_lds: M = sum_j cp[j] A^j
+    PrecondCoef pc;     // k_precond_lds: Horner levels of M = sum_j cp[j] A^j
 };
 
 // One sweep over all fields: each wave takes one tile (stencil_tile.h).
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(NW * 64) void k_precond_lds(SweepArgs a) {
     const int zb = zci * a.zc;
     double acc0 = 0.0, acc1 = 0.0;
     const size_t fo = (size_t)f * a.cells;
-    precond_lds_tile<VEC, D, TY, NW, FIRST>(lds, (FIRST ? a.p.B : a.p.R) + fo, a.p.Z + fo, a.g, a.cp, a.ny, a.nz, yg * TY,
+    precond_lds_tile<VEC, D, TY, NW, FIRST>(lds, (FIRST ? a.p.B : a.p.R) + fo, a.p.Z + fo, a.g, a.pc, a.ny, a.nz, yg * TY,
                                             zb, min(zb + a.zc, a.nz), acc0, acc1);
 
     // block reduction of the float64 partials, fixed order
@@ -799,7 +799,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
                 pz = pl;
                 double c[8];
                 poly_precond_coeffs_n(a.g.cx, a.g.cy, a.g.cz, want, c);
-                for (int j = 0; j <= want; ++j) a.cp[j] = (float)c[j];
+                precond_coef_fill(a.pc, a.g.cx, a.g.cy, a.g.cz, c, want);
             }
         }
     }

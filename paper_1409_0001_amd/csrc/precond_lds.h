@@ -47,6 +47,35 @@ __device__ __forceinline__ void x_neighbours(const Vec<VEC>& c, float& lft, floa
 // per-plane coefficients.  FIRST: the input is b (zero initial guess) and
 // b.b is accumulated as well.
 
+// Coefficients of the Horner levels, formed on the host so that a kernel
+// picks them with scalar selects (the vector unit would otherwise recompute
+// the wall-dependent diagonal at every level and step): level j = 1..D forms
+// u = cr r + ca A u_prev, ca = cp[D] at j = 1 and 1 above, as
+// u = kd c + cr r + nkx (x-neighbours) + nky (y-neighbours) + nkz (z-neighbours)
+// with kd[w] = ca (1 + 2 (cx + cy + cz) - cz [no plane below] - cz [no plane
+// above]), w = (no plane below) + 2 (no plane above), and nk = -ca c (stored
+// negated so that every term is one multiply-add with a scalar operand); a
+// missing plane also drops its nkz term.
+constexpr int kPcMaxD = 4;
+struct PrecondCoef {
+    float kd[kPcMaxD][4];
+    float nkx[kPcMaxD], nky[kPcMaxD], nkz[kPcMaxD], cr[kPcMaxD];
+};
+
+// cp: the D + 1 polynomial coefficients (float64, from poly_precond_coeffs_n).
+inline void precond_coef_fill(PrecondCoef& pc, float cx, float cy, float cz, const double* cp, int D) {
+    pc = PrecondCoef{};
+    const float d_in = 1.f + 2.f * (cx + cy + cz);
+    for (int j = 1; j <= D && j <= kPcMaxD; ++j) {
+        const float ca = j == 1 ? (float)cp[D] : 1.f;
+        for (int w = 0; w < 4; ++w) pc.kd[j - 1][w] = ca * (d_in - ((w & 1) ? cz : 0.f) - ((w & 2) ? cz : 0.f));
+        pc.nkx[j - 1] = -(ca * cx);
+        pc.nky[j - 1] = -(ca * cy);
+        pc.nkz[j - 1] = -(ca * cz);
+        pc.cr[j - 1] = (float)cp[D - j];
+    }
+}
+
 // First LDS row of level j (rows of TY + 2 (D - i) per plane; 3 planes for
 // levels 0 and 1, 2 planes above).
 template <int D, int TY>
@@ -65,7 +94,7 @@ __host__ __device__ constexpr int precond_lds_floats() {
 // lds: precond_lds_floats<VEC, D, TY>() floats of LDS, 16-byte aligned.
 template <int VEC, int D, int TY, int NW, bool FIRST>
 __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __restrict__ src_field,
-                                        float* __restrict__ dst_field, const Geom& g, const float* cp, int ny, int nz,
+                                        float* __restrict__ dst_field, const Geom& g, const PrecondCoef& pc, int ny, int nz,
                                         int y0, int zb, int ze, double& acc0, double& acc1) {
     constexpr int NXR = 64 * VEC;
     constexpr int E0 = TY + 2 * D;
@@ -105,8 +134,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     const int t0 = max(0, zb - D);
     const int tl = min(nz, ze + D) - 1;  // last plane of r needed
     const int t1 = ze - 1 + D;           // last step (plane ze - 1 of z completes)
-    const float cx = g.cx, cy = g.cy, cz = g.cz;
-    const float d_in = 1.f + 2.f * (cx + cy + cz);
+    (void)g;
 
     Vec<VEC> rk[6];                         // r of this row, plane t0 + s at slot s mod 6
     Vec<VEC> lv[D > 2 ? D - 2 : 1][3];      // level j >= 2's u of this row, plane t0 + s at slot s mod 3
@@ -147,9 +175,6 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
         for (int j = 1; j <= D; ++j) {
             const int q = t - j;
             const bool go = in_dom && j <= w && w < E0 - j && q >= max(0, zb - (D - j)) && q < min(nz, ze + (D - j));
-            Vec<VEC> u;
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) u.f[e] = 0.f;
             if (go) {
                 // previous level's u of this row at planes q - 1, q, q + 1:
                 // r from the register ring, level 1 from LDS, level >= 2 from
@@ -180,47 +205,53 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 float lft, rgt;
                 x_neighbours<VEC>(c, lft, rgt);
                 // u = cp[D-j] r + ca A u_prev (ca = cp[D] at j = 1, else 1), with
-                // ca folded into the stencil's coefficients: 7 operations per cell
-                // (8 when h_x != h_y)
+                // ca folded into the stencil's coefficients (PrecondCoef).
+                // Interior planes of a grid with h_x = h_y take the fast path:
+                // loop-invariant scalar coefficients, 7 operations per cell;
+                // wall planes and h_x != h_y the general one (8, with the
+                // wall's coefficients selected per plane).
                 const bool hzd = q > 0, hzu = q + 1 < nz;
-                const float ca = j == 1 ? cp[D] : 1.f;
-                const float kzd = hzd ? ca * cz : 0.f, kzu = hzu ? ca * cz : 0.f;
-                const float kd = ca * (d_in - (hzd ? 0.f : cz) - (hzu ? 0.f : cz));
-                const float kx = ca * cx, ky = ca * cy;
-                const float cr = cp[D - j];
-                if (cx == cy) {
+                const float cr = pc.cr[j - 1];
+                Vec<VEC> u;
+                if (hzd && hzu && pc.nkx[j - 1] == pc.nky[j - 1]) {
+                    const float kd = pc.kd[j - 1][0], nkx = pc.nkx[j - 1], nkz = pc.nkz[j - 1];
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
                         const float l = e > 0 ? c.f[e - 1] : lft;
                         const float r = e + 1 < VEC ? c.f[e + 1] : rgt;
                         float v = fmaf(kd, c.f[e], cr * rq.f[e]);
-                        v = fmaf(-kx, (l + r) + ys.f[e], v);
-                        v = fmaf(-kzd, zl.f[e], v);
-                        u.f[e] = fmaf(-kzu, zh.f[e], v);
+                        v = fmaf(nkx, (l + r) + ys.f[e], v);
+                        v = fmaf(nkz, zl.f[e], v);
+                        u.f[e] = fmaf(nkz, zh.f[e], v);
                     }
                 } else {
+                    const float kd = pc.kd[j - 1][(hzd ? 0 : 1) + (hzu ? 0 : 2)];
+                    const float nkzd = hzd ? pc.nkz[j - 1] : 0.f, nkzu = hzu ? pc.nkz[j - 1] : 0.f;
+                    const float nkx = pc.nkx[j - 1], nky = pc.nky[j - 1];
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
                         const float l = e > 0 ? c.f[e - 1] : lft;
                         const float r = e + 1 < VEC ? c.f[e + 1] : rgt;
                         float v = fmaf(kd, c.f[e], cr * rq.f[e]);
-                        v = fmaf(-kx, l + r, v);
-                        v = fmaf(-ky, ys.f[e], v);
-                        v = fmaf(-kzd, zl.f[e], v);
-                        u.f[e] = fmaf(-kzu, zh.f[e], v);
+                        v = fmaf(nkx, l + r, v);
+                        v = fmaf(nky, ys.f[e], v);
+                        v = fmaf(nkzd, zl.f[e], v);
+                        u.f[e] = fmaf(nkzu, zh.f[e], v);
                     }
                 }
                 if (j < D) stv<VEC>(rowj(j, q, w - j), u);
-            }
-            if (j >= 2 && j < D) lv[j >= 2 ? j - 2 : 0][((S - j) % 3 + 3) % 3] = u;
-            if (j == D && go && owner && q >= zb && q < ze) {
-                // z of plane q complete: store it and add its r.z (and b.b)
-                stv<VEC>(dst_field + x0 + (size_t)q * plane + (size_t)yw * nx, u);
-                const Vec<VEC>& rq = rk[((S - D) % 6 + 6) % 6];
+                // levels >= 2 keep their planes in a register ring; a slot
+                // not written here keeps an older, finite plane that is only
+                // ever read with a zero coefficient (beyond a wall)
+                if (j >= 2 && j < D) lv[j >= 2 ? j - 2 : 0][((S - j) % 3 + 3) % 3] = u;
+                if (j == D && owner && q >= zb && q < ze) {
+                    // z of plane q complete: store it and add its r.z (and b.b)
+                    stv<VEC>(dst_field + x0 + (size_t)q * plane + (size_t)yw * nx, u);
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) {
-                    acc0 = fma((double)rq.f[e], (double)u.f[e], acc0);
-                    if (FIRST) acc1 = fma((double)rq.f[e], (double)rq.f[e], acc1);
+                    for (int e = 0; e < VEC; ++e) {
+                        acc0 = fma((double)rq.f[e], (double)u.f[e], acc0);
+                        if (FIRST) acc1 = fma((double)rq.f[e], (double)rq.f[e], acc1);
+                    }
                 }
             }
         }
