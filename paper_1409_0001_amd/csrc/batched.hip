@@ -229,7 +229,7 @@ __device__ inline void wg_precond_lds(float* lds, const BSolve& a, const Ptrs& p
     double acc0 = 0.0, acc1 = 0.0;
     const int tiles = (a.g.ny + 7) / 8;
     for (int t = 0; t < tiles; ++t)
-        precond_lds_tile<VEC, 4, 8, NW, FIRST>(lds, FIRST ? p.B : p.R, p.Z, a.g, a.pc, a.g.ny, a.g.nz, 8 * t, 0,
+        precond_lds_tile<VEC, 4, 8, NW, FIRST, true>(lds, FIRST ? p.B : p.R, p.Z, a.g, a.pc, a.g.ny, a.g.nz, 8 * t, 0,
                                                a.g.nz, acc0, acc1);
     wg_sum2<NW>(acc0, acc1, sh);
     s0 = acc0;

@@ -92,7 +92,7 @@ __host__ __device__ constexpr int precond_lds_floats() {
 }
 
 // lds: precond_lds_floats<VEC, D, TY>() floats of LDS, 16-byte aligned.
-template <int VEC, int D, int TY, int NW, bool FIRST>
+template <int VEC, int D, int TY, int NW, bool FIRST, bool PF = false>
 __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __restrict__ src_field,
                                         float* __restrict__ dst_field, const Geom& g, const PrecondCoef& pc, int ny, int nz,
                                         int y0, int zb, int ze, double& acc0, double& acc1) {
@@ -138,6 +138,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
 
     Vec<VEC> rk[6];                         // r of this row, plane t0 + s at slot s mod 6
     Vec<VEC> lv[D > 2 ? D - 2 : 1][3];      // level j >= 2's u of this row, plane t0 + s at slot s mod 3
+    Vec<VEC> u1;                            // level 1's u of this row formed at the current step
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -148,6 +149,8 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int e = 0; e < VEC; ++e) lv[j][i].f[e] = 0.f;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) u1.f[e] = 0.f;
 
     // one step at t = t0 + S (mod 6); LOADER: the wave feeds r into LDS
     auto step = [&](auto S_, auto LOADER_, int t, Vec<VEC> (&pf)[P][RPL]) {
@@ -171,23 +174,58 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
         }
         if (w < E0) rk[S % 6] = ld(row0(t, w));  // own row of r at plane t (written at step t - 1)
 
+        // Level j's rows y - 1 and y + 1 (level j - 1 at plane t - j, this
+        // row itself at a wall) and level 2's planes q, q - 1 of level 1 were
+        // all written at earlier steps.  PF: each level issues the next
+        // level's LDS reads before its own arithmetic, so they are in flight
+        // while it computes (faster in the persistent batched kernel at
+        // nx = 128, slower at nx = 256, where it costs registers).  Level 2's
+        // plane q + 1 of level 1 is the u that level 1 has just formed in
+        // this wave (u1).
+        auto go_of = [&](int j) {
+            const int q = t - j;
+            return in_dom && j <= w && w < E0 - j && q >= max(0, zb - (D - j)) && q < min(nz, ze + (D - j));
+        };
+        auto ys_rows = [&](int j, Vec<VEC>& yd, Vec<VEC>& yu) {
+            const int q = t - j;
+            yd = ld(row(j - 1, q, has_yd ? w - j : w - j + 1));
+            yu = ld(row(j - 1, q, has_yu ? w - j + 2 : w - j + 1));
+        };
+        Vec<VEC> yd, yu, c2, zl2;
+        if (PF && go_of(1)) ys_rows(1, yd, yu);
 #pragma unroll
         for (int j = 1; j <= D; ++j) {
             const int q = t - j;
-            const bool go = in_dom && j <= w && w < E0 - j && q >= max(0, zb - (D - j)) && q < min(nz, ze + (D - j));
+            const bool go = go_of(j);
+            Vec<VEC> ydn, yun;
+            if (PF && j < D && go_of(j + 1)) {
+                ys_rows(j + 1, ydn, yun);
+                if (j == 1) {
+                    c2 = ld(row(1, t - 2, w - 1));
+                    zl2 = ld(row(1, t - 2 > 0 ? t - 3 : t - 2, w - 1));
+                }
+            }
+            if (!PF && go) {
+                // the same reads, issued just before their use
+                ys_rows(j, yd, yu);
+                if (j == 2) {
+                    c2 = ld(row(1, q, w - 1));
+                    zl2 = ld(row(1, q > 0 ? q - 1 : q, w - 1));
+                }
+            }
             if (go) {
                 // previous level's u of this row at planes q - 1, q, q + 1:
-                // r from the register ring, level 1 from LDS, level >= 2 from
-                // its register ring
+                // r from the register ring, level 1 from LDS and u1, level >= 2
+                // from its register ring
                 Vec<VEC> c, zl, zh;
                 if (j == 1) {
                     c = rk[((S - j) % 6 + 6) % 6];
                     zl = rk[((S - j - 1) % 6 + 6) % 6];
                     zh = rk[((S - j + 1) % 6 + 6) % 6];
                 } else if (j == 2) {
-                    c = ld(row(1, q, w - 1));
-                    zl = ld(row(1, q > 0 ? q - 1 : q, w - 1));
-                    zh = ld(row(1, q + 1 < nz ? q + 1 : q, w - 1));  // never a plane not formed
+                    c = c2;
+                    zl = zl2;
+                    zh = u1;  // formed at this step when q + 1 < nz; else weighted by zero
                 } else {
                     const int jr = j >= 3 ? j - 3 : 0;  // ring of level j - 1
                     c = lv[jr][((S - j) % 3 + 3) % 3];
@@ -195,13 +233,9 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                     zh = lv[jr][((S - j + 1) % 3 + 3) % 3];
                 }
                 const Vec<VEC>& rq = rk[((S - j) % 6 + 6) % 6];  // r of this row at plane q
-                // rows y - 1, y + 1 of the previous level at plane q (this row itself at a wall)
-                Vec<VEC> ys = ld(row(j - 1, q, has_yd ? w - j : w - j + 1));
-                {
-                    const Vec<VEC> yh = ld(row(j - 1, q, has_yu ? w - j + 2 : w - j + 1));
+                Vec<VEC> ys = yd;
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) ys.f[e] += yh.f[e];
-                }
+                for (int e = 0; e < VEC; ++e) ys.f[e] += yu.f[e];
                 float lft, rgt;
                 x_neighbours<VEC>(c, lft, rgt);
                 // u = cp[D-j] r + ca A u_prev (ca = cp[D] at j = 1, else 1), with
@@ -239,6 +273,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                         u.f[e] = fmaf(nkzu, zh.f[e], v);
                     }
                 }
+                if (j == 1) u1 = u;
                 if (j < D) stv<VEC>(rowj(j, q, w - j), u);
                 // levels >= 2 keep their planes in a register ring; a slot
                 // not written here keeps an older, finite plane that is only
@@ -253,6 +288,10 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                         if (FIRST) acc1 = fma((double)rq.f[e], (double)rq.f[e], acc1);
                     }
                 }
+            }
+            if (PF && j < D) {
+                yd = ydn;
+                yu = yun;
             }
         }
         lds_barrier();
