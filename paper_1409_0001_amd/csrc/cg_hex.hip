@@ -221,7 +221,8 @@ __device__ inline double block_sum_nt(const double* p, int n, double* sh) {
 }
 
 // Direction sweep of preconditioned CG with the rows shared through LDS:
-// p = z + beta p_old (p = z when B0), A p and p.Ap, writing p.  A block of NW
+// p = z + beta p_old, A p and p.Ap, writing p; when B0, p = z, which is not
+// written again (the caller uses z's buffer as p).  A block of NW
 // waves owns NW - 2 rows of y (one wave per x-row, nx = 64 VEC; the first
 // and last wave carry the halo rows) and marches over its z chunk; each row
 // is loaded once, so the halo costs 2 / (NW - 2) in L2 reads instead of the
@@ -319,7 +320,8 @@ __global__ __launch_bounds__(NW * 64) void k_dir_lds(SweepArgs a) {
             load(t + 1);
             if (in_dom) {
                 stv<VEC>(row(t, w), pv);
-                if (owner && t >= zb && t < ze) stv<VEC>(pdst + (size_t)t * plane, pv);
+                // B0: p_0 = z_0, which the caller keeps in place of p
+                if (!B0 && owner && t >= zb && t < ze) stv<VEC>(pdst + (size_t)t * plane, pv);
             }
         }
         ring[S % 3] = pv;
@@ -894,14 +896,30 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             // iteration it: z = M r (convergence test first), p = z + beta p_old, x, r update
             const bool first = it == 0 && !use_x0;
             const int64_t tag = (int64_t)step * 65536 + it;
+            // Buffers: z of iteration it in zb, p_old and p in Pold / Pnew.
+            // With the LDS direction sweep, p_0 = z_0 stays in Z (S1_B0 only
+            // reads it), z_1 goes to PA and p_1 to PB; from iteration 2 on z
+            // is in Z and p alternates between PA and PB.  Otherwise p_0 is a
+            // copy of z_0 in PA.
+            float* zb = Z;
+            float* pold = (it & 1) ? PA : PB;
+            float* pnew = (it & 1) ? PB : PA;
+            if (dir_nw && it == 0) {
+                pnew = Z;
+            } else if (dir_nw && it == 1) {
+                zb = PA;
+                pold = Z;
+            }
             a.k = it;
             a.p.R = R;
+            a.p.Z = zb;
             int t0 = first ? -1 : timing_begin(&m->timing, s);
             launch(first ? mode_z_first : mode_z);
             if (!first) timing_end(&m->timing, t0, 5, 8.0 * (double)F * cells, s, tag);
-            a.p.R = Z;
-            a.p.Pold = (it & 1) ? PA : PB;
-            a.p.Pnew = (it & 1) ? PB : PA;
+            a.p.Z = Z;
+            a.p.R = zb;
+            a.p.Pold = pold;
+            a.p.Pnew = pnew;
             int t1 = first ? -1 : timing_begin(&m->timing, s);
             launch(it == 0 ? S1_B0 : S1);
             if (!first) timing_end(&m->timing, t1, 0, 12.0 * (double)F * cells, s, tag);
