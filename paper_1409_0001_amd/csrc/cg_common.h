@@ -38,6 +38,7 @@ constexpr size_t kPinBytes = kPinFallback + 4096;
 struct CgCtl {
     CgField* st;       // [F]
     int* ndone;
+    int* host_flags;   // nullable: the launch that ends a read-back chunk copies ndone[0..1] here (pinned host memory)
     int32_t* iters;    // [CGD_MAX_STEPS][CGD_MAX_FIELDS]
     double* relres;
     int32_t* status;
@@ -46,6 +47,19 @@ struct CgCtl {
 };
 
 #ifdef __HIPCC__
+// The last sweep of a read-back chunk hands the host the finished-field count
+// and the largest stopping iteration (written by the convergence tests of
+// earlier launches), in place of a device-to-host copy after it.  Called
+// before any early return, so a launch whose fields are all done still posts.
+__device__ inline void post_ndone(const CgCtl& c) {
+    if (c.host_flags && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int n0 = __atomic_load_n(c.ndone, __ATOMIC_RELAXED);
+        const int n1 = __atomic_load_n(c.ndone + 1, __ATOMIC_RELAXED);
+        c.host_flags[0] = n0;
+        c.host_flags[1] = n1;
+    }
+}
+
 // Sum of n float64 values in one fixed order (thread t adds t, t+256, ...;
 // then a fixed shuffle tree and a fixed sum over the 4 waves).  Every thread
 // of the block returns the same value, bit for bit, in every block.
@@ -125,7 +139,7 @@ void poly_precond_coeffs_n(double cx, double cy, double cz, int deg, double* c);
 // iteration read back becomes the new hint.  Returns the index of the next
 // iteration that would have been enqueued.
 cgd_status cg_lookahead_loop(cgd_mesh m, int F, int it0, int max_iter, int chunk, const int* d_ndone,
-                             hipStream_t s, const std::function<void(int)>& enqueue, int* it_end);
+                             hipStream_t s, const std::function<void(int, int*)>& enqueue, int* it_end);
 
 // Host: after the steps, copies statuses / iterations / residuals back,
 // fills `out`, drops timing pairs of launches that found nothing to do, and

@@ -83,7 +83,7 @@ void poly_precond_coeffs_n(double cx, double cy, double cz, int deg, double* c) 
 }
 
 cgd_status cg_lookahead_loop(cgd_mesh m, int F, int it0, int max_iter, int chunk, const int* d_ndone,
-                             hipStream_t s, const std::function<void(int)>& enqueue, int* it_end) {
+                             hipStream_t s, const std::function<void(int, int*)>& enqueue, int* it_end) {
     int* pinned_flags = reinterpret_cast<int*>(static_cast<char*>(m->pinned) + kPinFlags);
     int it = it0;
     int slot = 0;
@@ -95,8 +95,10 @@ cgd_status cg_lookahead_loop(cgd_mesh m, int F, int it0, int max_iter, int chunk
         if (hinted && n == 0) size = m->cg_hint - it0 + 1;
         else if (hinted && n == 1) size = 1;
         const int todo = std::min(size, max_iter - it);
-        for (int c = 0; c < todo; ++c, ++it) enqueue(it);
-        CGD_HIP_TRY(hipMemcpyAsync(&pinned_flags[2 * slot], d_ndone, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        // the chunk's last iteration posts ndone to this slot itself
+        for (int c = 0; c < todo; ++c, ++it) enqueue(it, c + 1 == todo ? &pinned_flags[2 * slot] : nullptr);
+        if (todo <= 0)
+            CGD_HIP_TRY(hipMemcpyAsync(&pinned_flags[2 * slot], d_ndone, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
         CGD_HIP_TRY(hipEventRecord(m->ev[slot], s));
         if (have_prev) {
             CGD_HIP_TRY(hipEventSynchronize(m->ev[slot ^ 1]));

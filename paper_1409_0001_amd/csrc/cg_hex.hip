@@ -71,6 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     const int f = b / a.bpf;
     const int blk = b - f * a.bpf;
     CgField* stf = a.c.st + f;
+    if constexpr (MODE == S2 || MODE == S2_FIRST || MODE == S2P_FIRST) post_ndone(a.c);
     // S2_FIRST / S2P_FIRST must write x and r even when their first block
     // flags a breakdown.
     if (MODE != S2_FIRST && MODE != S2P_FIRST && stf->done) return;  // uniform over the block
@@ -735,7 +736,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     if (rc != CGD_OK) return rc;
 
     char* base = static_cast<char*>(m->ws.ptr);
-    CgCtl ctl;
+    CgCtl ctl = {};
     ctl.st = reinterpret_cast<CgField*>(base + kOffState);
     ctl.ndone = reinterpret_cast<int*>(base + kOffNdone);
     ctl.iters = reinterpret_cast<int32_t*>(base + kOffIters);
@@ -892,7 +893,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             }
             it0 = 0;
         }
-        auto enqueue_pcg = [&](int it) {
+        auto enqueue_pcg = [&](int it, int* host_flags) {
             // iteration it: z = M r (convergence test first), p = z + beta p_old, x, r update
             const bool first = it == 0 && !use_x0;
             const int64_t tag = (int64_t)step * 65536 + it;
@@ -924,12 +925,14 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             launch(it == 0 ? S1_B0 : S1);
             if (!first) timing_end(&m->timing, t1, 0, 12.0 * (double)F * cells, s, tag);
             a.p.R = R;
+            a.c.host_flags = host_flags;
             int t2 = first ? -1 : timing_begin(&m->timing, s);
             launch(first ? S2P_FIRST : S2);
             if (!first) timing_end(&m->timing, t2, 1, 20.0 * (double)F * cells, s, tag);
+            a.c.host_flags = nullptr;
         };
-        auto enqueue = [&](int it) {
-            if (pcg) return enqueue_pcg(it);
+        auto enqueue = [&](int it, int* host_flags) {
+            if (pcg) return enqueue_pcg(it, host_flags);
             int mode1 = S1;
             if (!use_x0) {
                 a.p.Pold = it == 1 ? cur : ((it & 1) ? PB : PA);
@@ -944,9 +947,11 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             int t1 = timing_begin(&m->timing, s);
             launch(mode1);
             timing_end(&m->timing, t1, 0, 12.0 * (double)F * cells, s, tag);
+            a.c.host_flags = host_flags;
             int t2 = timing_begin(&m->timing, s);
             launch(S2);
             timing_end(&m->timing, t2, 1, 20.0 * (double)F * cells, s, tag);
+            a.c.host_flags = nullptr;
         };
         int it_end = it0;
         cgd_status rc2 = cg_lookahead_loop(m, F, it0, da.max_iter, da.check_every, ctl.ndone, s, enqueue, &it_end);

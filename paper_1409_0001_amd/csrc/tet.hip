@@ -236,6 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_sweep(TetArgs a) {
     const int f = b / a.bpf;
     const int blk = b - f * a.bpf;
     CgField* stf = a.c.st + f;
+    if constexpr (MODE == T2 || MODE == T2_FIRST) post_ndone(a.c);
     if (MODE != T2_FIRST && stf->done) return;
 
     __shared__ double sh[kWaves];
@@ -490,7 +491,7 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     rc = ensure_pinned(m, kPinBytes);
     if (rc != CGD_OK) return rc;
     char* base = static_cast<char*>(m->ws.ptr);
-    CgCtl ctl;
+    CgCtl ctl = {};
     ctl.st = reinterpret_cast<CgField*>(base + kOffState);
     ctl.ndone = reinterpret_cast<int*>(base + kOffNdone);
     ctl.iters = reinterpret_cast<int32_t*>(base + kOffIters);
@@ -552,7 +553,7 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         a.Pold = PB;
         hipLaunchKernelGGL(k_tet_sweep<T1_FIRST>, grid, block, 0, s, a);
         hipLaunchKernelGGL(k_tet_sweep<T2_FIRST>, grid, block, 0, s, a);
-        auto enqueue = [&](int it) {
+        auto enqueue = [&](int it, int* host_flags) {
             a.k = it;
             a.Pold = (it & 1) ? PA : PB;
             a.Pnew = (it & 1) ? PB : PA;
@@ -560,9 +561,11 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             int t1 = timing_begin(&m->timing, s);
             hipLaunchKernelGGL(k_tet_sweep<T1>, grid, block, 0, s, a);
             timing_end(&m->timing, t1, 3, b1 * F, s, tag);
+            a.c.host_flags = host_flags;
             int t2 = timing_begin(&m->timing, s);
             hipLaunchKernelGGL(k_tet_sweep<T2>, grid, block, 0, s, a);
             timing_end(&m->timing, t2, 4, b2 * F, s, tag);
+            a.c.host_flags = nullptr;
         };
         int it_end = 1;
         rc = cg_lookahead_loop(m, F, 1, da.max_iter, da.check_every, ctl.ndone, s, enqueue, &it_end);
