@@ -99,9 +99,11 @@ typedef struct {
     int32_t check_every;  /* iterations enqueued between convergence read-backs once a step
                              runs past the previous solve's count; <= 0: 4 */
     int32_t precond;      /* hex meshes: 0 (default) conjugate gradients preconditioned by
-                             the degree-1 Chebyshev polynomial of A on its spectrum
-                             [1, 1 + 4 sum_a c_a]; 1 plain CG.  Tet meshes use Jacobi
-                             either way.  The stopping rule is the same for all. */
+                             a Chebyshev polynomial of A on its spectrum [1, 1 + 4 sum_a c_a]:
+                             degree 8 (two sweeps of two quadratic factors each) where one
+                             wavefront covers an x-row (nx = 64, 128 or 256) and the grid
+                             fills the machine, else degree 2 or 1; 1 plain CG.  Tet meshes
+                             use Jacobi either way.  The stopping rule is the same for all. */
     cgd_unet model;       /* x0_mode 3: a network created for this mesh's grid, else NULL */
 } cgd_solver_opts;
 

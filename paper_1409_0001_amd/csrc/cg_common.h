@@ -128,6 +128,13 @@ __global__ void k_cg_step_end(CgCtl c, const double* rr_part, size_t field_strid
 void poly_precond_coeffs(double cx, double cy, double cz, int deg, float* c0, float* c1, float* c2);
 // The same polynomial for any degree 1..6: c[0..deg] (float64).
 void poly_precond_coeffs_n(double cx, double cy, double cz, int deg, double* c);
+// The even-degree polynomial of poly_precond_coeffs_n as a product of
+// quadratic factors: p(l) = scale prod_k g_k (l^2 + s_k l + q_k), k < deg / 2,
+// each g_k scaling its factor to at most 1 on the spectrum [1, 1 + 4 (cx +
+// cy + cz)].  Returns the number of factors.  The roots are in closed form
+// (those of T_{deg+1}(sig(l)) = T_{deg+1}(sig(0)) other than l = 0).
+int poly_precond_quadratics(double cx, double cy, double cz, int deg, double* s, double* q, double* g,
+                            double* scale);
 
 // Host: enqueues iterations through `enqueue(it)` until the device reports
 // all F fields stopped (read back one chunk late, so the device always has

@@ -1,5 +1,6 @@
 // Shared CG bookkeeping kernels and host loops (see cg_common.h).
 #include <algorithm>
+#include <cmath>
 
 #include "cg_common.h"
 
@@ -80,6 +81,36 @@ void poly_precond_coeffs_n(double cx, double cy, double cz, int deg, double* c) 
     }
     // t1 = T_m(sig(l)); T_m(sig(0)) = t1[0]; 1 - t1 / t1[0] has no constant term
     for (int j = 0; j < m; ++j) c[j] = -t1[j + 1] / t1[0];
+}
+
+int poly_precond_quadratics(double cx, double cy, double cz, int deg, double* s, double* q, double* g,
+                            double* scale) {
+    // p(l) = lead prod_k (l^2 + s_k l + q_k): the roots of p are the l != 0
+    // with T_n(sig(l)) = T_n(sig(0)), n = deg + 1, i.e. sig = cosh(theta + 2 pi i k / n),
+    // theta = acosh(sig(0)), k = 1 .. deg, in conjugate pairs (k, n - k);
+    // l = (sp - sig dm) / 2.  lead is the l^deg coefficient of
+    // -(T_n(sig(l)) - T_n(sig(0))) / (T_n(sig(0)) l): -2^(n-1) (-2 / dm)^n / cosh(n theta).
+    const double lmax = 1.0 + 4.0 * (cx + cy + cz);
+    const double sp = lmax + 1.0, dm = std::max(lmax - 1.0, 1e-12 * sp);
+    const int m = deg & ~1, n = m + 1;
+    const double th = std::acosh(sp / dm);
+    double lead = -std::pow(2.0, n - 1) * std::pow(-2.0 / dm, n) / std::cosh(n * th);
+    const double kPi = 3.14159265358979323846;
+    for (int k = 1; k <= m / 2; ++k) {
+        const double a = 2.0 * kPi * k / n;
+        // sig = cosh(th) cos(a) + i sinh(th) sin(a)
+        const double sr = std::cosh(th) * std::cos(a), si = std::sinh(th) * std::sin(a);
+        const double lr = (sp - sr * dm) / 2.0, li = -si * dm / 2.0;
+        s[k - 1] = -2.0 * lr;
+        q[k - 1] = lr * lr + li * li;
+        // the factor is positive and convex on the spectrum [1, lmax]: its
+        // maximum there is at an end point
+        const double f1 = 1.0 + s[k - 1] + q[k - 1], f2 = lmax * lmax + s[k - 1] * lmax + q[k - 1];
+        g[k - 1] = 1.0 / std::max(f1, f2);
+        lead /= g[k - 1];
+    }
+    *scale = lead;
+    return m / 2;
 }
 
 cgd_status cg_lookahead_loop(cgd_mesh m, int F, int it0, int max_iter, int chunk, const int* d_ndone,

@@ -60,7 +60,8 @@ struct SweepArgs {
     int xsegs, ygroups, zc;
     int wpf, bpf, nblocks;
     int k;              // iteration index within the step
-    PrecondCoef pc;     // k_precond_lds: Horner levels of M = sum_j cp[j] A^j
+    PrecondCoef pc;     // k_precond_lds: Horner levels of M = sum_j cp[j] A^j, or the first product pass
+    PrecondCoef pc2;    // the second product pass (degree 8)
 };
 
 // One sweep over all fields: each wave takes one tile (stencil_tile.h).
@@ -378,12 +379,15 @@ __global__ __launch_bounds__(NW * 64) void k_dir_lds(SweepArgs a) {
 
 // The degree-D preconditioning sweep of preconditioned CG (precond_lds.h):
 // convergence test first (as the register sweeps' SZ prologue), then one tile
-// per block, then the block's r.z (and b.b) partials.
-template <int VEC, int D, int TY, int NW, bool FIRST>
+// per block, then the block's r.z (and b.b) partials.  FORM 1 and 2 are the
+// two passes of the degree-8 product form: the first (r -> U, coefficients
+// pc) has the convergence test and b.b, the second (U -> z, coefficients
+// pc2) the r.z partials.
+template <int VEC, int D, int TY, int NW, bool FIRST, int FORM = 0>
 __global__ __launch_bounds__(NW * 64) void k_precond_lds(SweepArgs a) {
     constexpr int NT = NW * 64;
     __shared__ double sh[NW];
-    __shared__ __align__(16) float lds[precond_lds_floats<VEC, D, TY>()];
+    __shared__ __align__(16) float lds[precond_lds_floats<VEC, D, TY, FORM>()];
 
     int b = blockIdx.x;
     if ((a.nblocks & 7) == 0) b = (b & 7) * (a.nblocks >> 3) + (b >> 3);
@@ -392,7 +396,7 @@ __global__ __launch_bounds__(NW * 64) void k_precond_lds(SweepArgs a) {
     CgField* stf = a.c.st + f;
     if (stf->done) return;  // uniform over the block
     const bool lead = blk == 0 && threadIdx.x == 0;
-    if constexpr (!FIRST) {
+    if constexpr (!FIRST && FORM != 2) {
         // convergence test on r_k . r_k from the previous sweep 2 (or, at
         // k = 0, the residual sweep, which also gave b.b)
         const double rrk = block_sum_nt<NT>(a.P2 + ((size_t)f * 2 + (a.k & 1)) * a.pstride, a.bpf_in, sh);
@@ -411,13 +415,18 @@ __global__ __launch_bounds__(NW * 64) void k_precond_lds(SweepArgs a) {
     const int zb = zci * a.zc;
     double acc0 = 0.0, acc1 = 0.0;
     const size_t fo = (size_t)f * a.cells;
-    precond_lds_tile<VEC, D, TY, NW, FIRST>(lds, (FIRST ? a.p.B : a.p.R) + fo, a.p.Z + fo, a.g, a.pc, a.ny, a.nz, yg * TY,
-                                            zb, min(zb + a.zc, a.nz), acc0, acc1);
+    const float* rsrc = FIRST ? a.p.B : a.p.R;  // r_k (b at a zero first guess)
+    const float* src = FORM == 2 ? a.p.U : rsrc;
+    float* dst = FORM == 1 ? a.p.U : a.p.Z;
+    precond_lds_tile<VEC, D, TY, NW, FIRST, false, FORM>(lds, src + fo, dst + fo, a.g, FORM == 2 ? a.pc2 : a.pc, a.ny,
+                                                         a.nz, yg * TY, zb, min(zb + a.zc, a.nz), acc0, acc1,
+                                                         rsrc + fo);
 
     // block reduction of the float64 partials, fixed order
+    constexpr bool kRz = FORM != 1, kBb = FIRST && FORM != 2;
     for (int o = 32; o > 0; o >>= 1) {
-        acc0 += __shfl_xor(acc0, o);
-        if (FIRST) acc1 += __shfl_xor(acc1, o);
+        if (kRz) acc0 += __shfl_xor(acc0, o);
+        if (kBb) acc1 += __shfl_xor(acc1, o);
     }
     __shared__ double s0[NW], s1[NW];
     if (lane == 0) {
@@ -432,8 +441,8 @@ __global__ __launch_bounds__(NW * 64) void k_precond_lds(SweepArgs a) {
             u0 += s0[i];
             u1 += s1[i];
         }
-        a.P3[((size_t)f * 2 + (a.k & 1)) * a.pstride + blk] = u0;
-        if (FIRST) a.P1[((size_t)f * 2 + 1) * a.pstride + blk] = u1;
+        if (kRz) a.P3[((size_t)f * 2 + (a.k & 1)) * a.pstride + blk] = u0;
+        if (kBb) a.P1[((size_t)f * 2 + 1) * a.pstride + blk] = u1;
     }
 }
 
@@ -594,33 +603,42 @@ constexpr int lds_precond_bytes(int vec, int deg) {
     return (deg == 4 ? lds_level_base<4, kLdsTY>(4) : lds_level_base<3, kLdsTY>(3)) * 64 * vec * 4;
 }
 
-template <int D>
+template <int D, int FORM>
 void launch_precond_lds_d(int vec, bool first, const Plan& q, const SweepArgs& a, hipStream_t s) {
     const dim3 grid(q.nblocks), block(kLdsNW * 64);
     if (vec == 4) {
-        if (first) hipLaunchKernelGGL((k_precond_lds<4, D, kLdsTY, kLdsNW, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_precond_lds<4, D, kLdsTY, kLdsNW, false>), grid, block, 0, s, a);
+        if (first) hipLaunchKernelGGL((k_precond_lds<4, D, kLdsTY, kLdsNW, true, FORM>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_precond_lds<4, D, kLdsTY, kLdsNW, false, FORM>), grid, block, 0, s, a);
     } else if (vec == 2) {
-        if (first) hipLaunchKernelGGL((k_precond_lds<2, D, kLdsTY, kLdsNW, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_precond_lds<2, D, kLdsTY, kLdsNW, false>), grid, block, 0, s, a);
+        if (first) hipLaunchKernelGGL((k_precond_lds<2, D, kLdsTY, kLdsNW, true, FORM>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_precond_lds<2, D, kLdsTY, kLdsNW, false, FORM>), grid, block, 0, s, a);
     } else {
-        if (first) hipLaunchKernelGGL((k_precond_lds<1, D, kLdsTY, kLdsNW, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_precond_lds<1, D, kLdsTY, kLdsNW, false>), grid, block, 0, s, a);
+        if (first) hipLaunchKernelGGL((k_precond_lds<1, D, kLdsTY, kLdsNW, true, FORM>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_precond_lds<1, D, kLdsTY, kLdsNW, false, FORM>), grid, block, 0, s, a);
     }
 }
 
+// Degree 3 or 4: one Horner pass; degree 8: the two product passes, the
+// second reading the first's output U (a.p.U).
 void launch_precond_lds(int deg, int vec, bool first, const Plan& q, const SweepArgs& a, hipStream_t s) {
-    if (deg == 4) launch_precond_lds_d<4>(vec, first, q, a, s);
-    else launch_precond_lds_d<3>(vec, first, q, a, s);
+    if (deg == 8) {
+        launch_precond_lds_d<4, 1>(vec, first, q, a, s);
+        launch_precond_lds_d<4, 2>(vec, first, q, a, s);
+    } else if (deg == 4) {
+        launch_precond_lds_d<4, 0>(vec, first, q, a, s);
+    } else {
+        launch_precond_lds_d<3, 0>(vec, first, q, a, s);
+    }
 }
 
 // Tiling of the LDS preconditioning sweep: ceil(ny / TY) row groups times z
 // chunks sized to give every compute unit its share of blocks (as many as
 // its 160 KB of LDS holds).  zc_raw: the chunk depth that fills the machine,
 // before the floor of 2 D planes (a chunk recomputes 2 D halo planes).  The
-// sweep is used when zc_raw >= D: at 128^3 (zc 8) degree 4 takes 2.19 ms per
-// field against 2.57 for degree 2 in registers; at 256 x 256 x 512 (zc 64)
-// 6.93 against 10.31.
+// sweep is used when zc_raw >= D (D = 4 for degree 8, which runs two passes
+// of the degree-4 tile): at 128^3 (zc 8) degree 8 takes 1.12 ms per field,
+// degree 4 1.44 and degree 2 in registers 2.57 (before the later sweep
+// changes); at 256 x 256 x 512 (zc 64) 4.80, 5.83 and 10.31.
 Plan lds_plan(const HexGeom& g, int F, int vec, int deg, int zc_force, int* zc_raw) {
     Plan p = {};
     p.vec = vec;
@@ -792,17 +810,30 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     const int mode_z = deg == 2 ? SZ2 : SZ;
     int deg_lds = 0;
     if (deg == 2) {
-        int want = 4, zc_force = 0, zc_raw = 0;
+        // Degree 8 (two LDS passes of two quadratic factors) where the LDS
+        // tile applies: 3 iterations per step at dtau / h^2 = 1 against 5 at
+        // degree 4 (one Horner pass); on the 256 x 256 x 512 grid 4.80 ms per
+        // field against 5.83.  CGD_HEX_PRECOND_DEG (3, 4 or 8) overrides.
+        int want = 8, zc_force = 0, zc_raw = 0;
         if (const char* e = getenv("CGD_HEX_PRECOND_DEG")) want = atoi(e);
         if (const char* e = getenv("CGD_HEX_LDS_ZC")) zc_force = atoi(e);
-        if (want == 3 || want == 4) {
-            Plan pl = lds_plan(g, F, p.vec, want, zc_force, &zc_raw);
-            if ((zc_force > 0 || zc_raw >= want) && (size_t)pl.bpf <= max_bpf(g, F)) {
+        if (want == 3 || want == 4 || want == 8) {
+            // degree 8 runs as two passes of the degree-4 tile
+            const int dt = want == 8 ? 4 : want;
+            Plan pl = lds_plan(g, F, p.vec, dt, zc_force, &zc_raw);
+            if ((zc_force > 0 || zc_raw >= dt) && (size_t)pl.bpf <= max_bpf(g, F)) {
                 deg_lds = want;
                 pz = pl;
-                double c[8];
-                poly_precond_coeffs_n(a.g.cx, a.g.cy, a.g.cz, want, c);
-                precond_coef_fill(a.pc, a.g.cx, a.g.cy, a.g.cz, c, want);
+                if (want == 8) {
+                    double qs[4], qq[4], qg[4], scale;
+                    poly_precond_quadratics(a.g.cx, a.g.cy, a.g.cz, 8, qs, qq, qg, &scale);
+                    precond_coef_fill_quadratics(a.pc, a.g.cx, a.g.cy, a.g.cz, qs, qq, qg, 1.0);
+                    precond_coef_fill_quadratics(a.pc2, a.g.cx, a.g.cy, a.g.cz, qs + 2, qq + 2, qg + 2, scale);
+                } else {
+                    double c[8];
+                    poly_precond_coeffs_n(a.g.cx, a.g.cy, a.g.cz, want, c);
+                    precond_coef_fill(a.pc, a.g.cx, a.g.cy, a.g.cz, c, want);
+                }
             }
         }
     }
@@ -914,9 +945,12 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             a.k = it;
             a.p.R = R;
             a.p.Z = zb;
+            // the product form's intermediate: a p buffer that holds nothing
+            // live until sweep 1 writes p_new into it
+            a.p.U = it == 0 ? (dir_nw ? PA : PB) : pnew;
             int t0 = first ? -1 : timing_begin(&m->timing, s);
             launch(first ? mode_z_first : mode_z);
-            if (!first) timing_end(&m->timing, t0, 5, 8.0 * (double)F * cells, s, tag);
+            if (!first) timing_end(&m->timing, t0, 5, (deg_lds == 8 ? 20.0 : 8.0) * (double)F * cells, s, tag);
             a.p.Z = Z;
             a.p.R = zb;
             a.p.Pold = pold;

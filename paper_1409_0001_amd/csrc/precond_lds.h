@@ -76,6 +76,31 @@ inline void precond_coef_fill(PrecondCoef& pc, float cx, float cy, float cz, con
     }
 }
 
+// One pass of the product form of the preconditioner (FORM 1 and 2 below):
+// levels 1..4 apply two quadratic factors to the pass's input v,
+// u1 = A v, u2 = g1 (A u1 + s1 u1 + q1 v), u3 = A u2, u4 = g2 last (A u3 +
+// s2 u3 + q2 u2), in the coefficients above (kd folds s and the walls; cr
+// weights the level's extra term: v at level 2, u2 at level 4, none at odd
+// levels).  s, q, g: the pass's two factors (poly_precond_quadratics); last:
+// the polynomial's overall scale on the final pass, else 1.
+inline void precond_coef_fill_quadratics(PrecondCoef& pc, float cx, float cy, float cz, const double* s,
+                                         const double* q, const double* g, double last) {
+    pc = PrecondCoef{};
+    const double d_in = 1.0 + 2.0 * ((double)cx + (double)cy + (double)cz);
+    for (int j = 1; j <= 4; ++j) {
+        const bool even = (j & 1) == 0;
+        const int k = (j - 1) / 2;
+        const double gg = even ? g[k] * (j == 4 ? last : 1.0) : 1.0;
+        const double sh = even ? s[k] : 0.0;
+        for (int w = 0; w < 4; ++w)
+            pc.kd[j - 1][w] = (float)(gg * (d_in - ((w & 1) ? cz : 0.0) - ((w & 2) ? cz : 0.0) + sh));
+        pc.nkx[j - 1] = (float)(-gg * cx);
+        pc.nky[j - 1] = (float)(-gg * cy);
+        pc.nkz[j - 1] = (float)(-gg * cz);
+        pc.cr[j - 1] = even ? (float)(gg * q[k]) : 0.f;
+    }
+}
+
 // First LDS row of level j (rows of TY + 2 (D - i) per plane; 3 planes for
 // levels 0 and 1, 2 planes above).
 template <int D, int TY>
@@ -85,17 +110,25 @@ __host__ __device__ constexpr int lds_level_base(int j) {
     return rows;
 }
 
-// LDS floats a tile needs: levels 0..D-1 (precond_lds_tile's `lds`).
-template <int VEC, int D, int TY>
+// LDS floats a tile needs: levels 0..D-1 (precond_lds_tile's `lds`), and
+// for FORM 2 two planes of the output rows of r.
+template <int VEC, int D, int TY, int FORM = 0>
 __host__ __device__ constexpr int precond_lds_floats() {
-    return lds_level_base<D, TY>(D) * 64 * VEC;
+    return (lds_level_base<D, TY>(D) + (FORM == 2 ? 2 * TY : 0)) * 64 * VEC;
 }
 
-// lds: precond_lds_floats<VEC, D, TY>() floats of LDS, 16-byte aligned.
-template <int VEC, int D, int TY, int NW, bool FIRST, bool PF = false>
+// lds: precond_lds_floats<VEC, D, TY, FORM>() floats of LDS, 16-byte aligned.
+// FORM 0: z = p(A) r by Horner (src = r); acc0 = r.z (and acc1 = b.b when
+// FIRST).  FORM 1 and 2 (D = 4): one pass of the product form (src = the
+// pass's input v; dst = its output); FORM 1 adds acc1 = v.v when FIRST (v =
+// b), FORM 2 adds acc0 = r.dst with r read from side_field (the loaders feed
+// the output rows of r through LDS).
+template <int VEC, int D, int TY, int NW, bool FIRST, bool PF = false, int FORM = 0>
 __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __restrict__ src_field,
                                         float* __restrict__ dst_field, const Geom& g, const PrecondCoef& pc, int ny, int nz,
-                                        int y0, int zb, int ze, double& acc0, double& acc1) {
+                                        int y0, int zb, int ze, double& acc0, double& acc1,
+                                        const float* __restrict__ side_field = nullptr) {
+    static_assert(FORM == 0 || D == 4, "the product form runs two quadratic factors per pass");
     constexpr int NXR = 64 * VEC;
     constexpr int E0 = TY + 2 * D;
     constexpr int NL = NW - TY;                  // waves owning no output row: the loaders
@@ -131,6 +164,15 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
         return (size_t)y * nx;
     };
 
+    // FORM 2: r of output row i at plane q in side slot q & 1, written by
+    // loader i at step q + D - 1 (loaded one step earlier) and read by the
+    // owner of the row at step q + D
+    float* side_lds = lds + lds_level_base<D, TY>(D) * NXR;
+    auto side_row = [&](int q, int i) -> float* { return side_lds + ((q & 1) * TY + i) * NXR + x0; };
+    const float* side = FORM == 2 ? side_field + x0 : nullptr;
+    const size_t side_y = (size_t)min(y0 + (li < TY ? li : 0), ny - 1) * nx;
+    auto side_load = [&](int q) { return ldv<VEC>(side + (size_t)min(max(q, 0), nz - 1) * plane + side_y); };
+
     const int t0 = max(0, zb - D);
     const int tl = min(nz, ze + D) - 1;  // last plane of r needed
     const int t1 = ze - 1 + D;           // last step (plane ze - 1 of z completes)
@@ -153,9 +195,15 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     for (int e = 0; e < VEC; ++e) u1.f[e] = 0.f;
 
     // one step at t = t0 + S (mod 6); LOADER: the wave feeds r into LDS
-    auto step = [&](auto S_, auto LOADER_, int t, Vec<VEC> (&pf)[P][RPL]) {
+    auto step = [&](auto S_, auto LOADER_, int t, Vec<VEC> (&pf)[P][RPL], Vec<VEC>& sr) {
         constexpr int S = decltype(S_)::value;
         constexpr bool LOADER = decltype(LOADER_)::value;
+        if constexpr (LOADER && FORM == 2) {
+            // side channel: output row li of r at plane t + 1 - D (in flight
+            // since the previous step) into LDS, then the load of the next plane
+            if (li < TY) stv<VEC>(side_row(t + 1 - D, li), sr);
+            sr = side_load(t + 2 - D);
+        }
         if constexpr (LOADER) {
             // plane t + 1 (in flight since step t + 1 - P) into LDS, then
             // the load of plane t + 1 + P into the freed buffer
@@ -232,7 +280,11 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                     zl = lv[jr][((S - j - 1) % 3 + 3) % 3];
                     zh = lv[jr][((S - j + 1) % 3 + 3) % 3];
                 }
-                const Vec<VEC>& rq = rk[((S - j) % 6 + 6) % 6];  // r of this row at plane q
+                const Vec<VEC>& rq = rk[((S - j) % 6 + 6) % 6];  // level 0 (r or v) of this row at plane q
+                // the level's extra term: r (FORM 0), v at level 2 and u2 at
+                // level 4 (FORM 1, 2), none at odd levels of FORM 1, 2
+                const Vec<VEC>& ex = (FORM != 0 && j == 4) ? lv[0][((S - 4) % 3 + 3) % 3] : rq;
+                const bool has_ex = FORM == 0 || (j % 2) == 0;
                 Vec<VEC> ys = yd;
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) ys.f[e] += yu.f[e];
@@ -253,7 +305,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                     for (int e = 0; e < VEC; ++e) {
                         const float l = e > 0 ? c.f[e - 1] : lft;
                         const float r = e + 1 < VEC ? c.f[e + 1] : rgt;
-                        float v = fmaf(kd, c.f[e], cr * rq.f[e]);
+                        float v = has_ex ? fmaf(kd, c.f[e], cr * ex.f[e]) : kd * c.f[e];
                         v = fmaf(nkx, (l + r) + ys.f[e], v);
                         v = fmaf(nkz, zl.f[e], v);
                         u.f[e] = fmaf(nkz, zh.f[e], v);
@@ -266,7 +318,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                     for (int e = 0; e < VEC; ++e) {
                         const float l = e > 0 ? c.f[e - 1] : lft;
                         const float r = e + 1 < VEC ? c.f[e + 1] : rgt;
-                        float v = fmaf(kd, c.f[e], cr * rq.f[e]);
+                        float v = has_ex ? fmaf(kd, c.f[e], cr * ex.f[e]) : kd * c.f[e];
                         v = fmaf(nkx, l + r, v);
                         v = fmaf(nky, ys.f[e], v);
                         v = fmaf(nkzd, zl.f[e], v);
@@ -280,12 +332,17 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 // ever read with a zero coefficient (beyond a wall)
                 if (j >= 2 && j < D) lv[j >= 2 ? j - 2 : 0][((S - j) % 3 + 3) % 3] = u;
                 if (j == D && owner && q >= zb && q < ze) {
-                    // z of plane q complete: store it and add its r.z (and b.b)
+                    // output of plane q complete: store it and add r.z (and b.b)
                     stv<VEC>(dst_field + x0 + (size_t)q * plane + (size_t)yw * nx, u);
+                    if constexpr (FORM == 2) {
+                        const Vec<VEC> rr = ld(side_row(q, w - D));
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) acc0 = fma((double)rr.f[e], (double)u.f[e], acc0);
+                    }
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
-                        acc0 = fma((double)rq.f[e], (double)u.f[e], acc0);
-                        if (FIRST) acc1 = fma((double)rq.f[e], (double)rq.f[e], acc1);
+                        if (FORM == 0) acc0 = fma((double)rq.f[e], (double)u.f[e], acc0);
+                        if (FIRST && FORM != 2) acc1 = fma((double)rq.f[e], (double)rq.f[e], acc1);
                     }
                 }
             }
@@ -300,6 +357,8 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     auto run = [&](auto LOADER_) {
         constexpr bool LOADER = decltype(LOADER_)::value;
         Vec<VEC> pf[P][RPL];
+        Vec<VEC> sr;  // FORM 2 loaders: the side plane in flight (plane t + 1 - D at step t)
+        if constexpr (LOADER && FORM == 2) sr = side_load(t0 + 1 - D);
         if constexpr (LOADER) {
             // planes t0 .. t0 + P - 1 in flight; plane t0 into LDS; t0 + P replaces it
 #pragma unroll
@@ -322,17 +381,17 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
         }
         lds_barrier();
         for (int t = t0; t <= t1; t += 6) {
-            step(std::integral_constant<int, 0>{}, LOADER_, t, pf);
+            step(std::integral_constant<int, 0>{}, LOADER_, t, pf, sr);
             if (t + 1 > t1) break;
-            step(std::integral_constant<int, 1>{}, LOADER_, t + 1, pf);
+            step(std::integral_constant<int, 1>{}, LOADER_, t + 1, pf, sr);
             if (t + 2 > t1) break;
-            step(std::integral_constant<int, 2>{}, LOADER_, t + 2, pf);
+            step(std::integral_constant<int, 2>{}, LOADER_, t + 2, pf, sr);
             if (t + 3 > t1) break;
-            step(std::integral_constant<int, 3>{}, LOADER_, t + 3, pf);
+            step(std::integral_constant<int, 3>{}, LOADER_, t + 3, pf, sr);
             if (t + 4 > t1) break;
-            step(std::integral_constant<int, 4>{}, LOADER_, t + 4, pf);
+            step(std::integral_constant<int, 4>{}, LOADER_, t + 4, pf, sr);
             if (t + 5 > t1) break;
-            step(std::integral_constant<int, 5>{}, LOADER_, t + 5, pf);
+            step(std::integral_constant<int, 5>{}, LOADER_, t + 5, pf, sr);
         }
     };
     if (owner) run(std::false_type{});

@@ -44,6 +44,7 @@ struct Ptrs {
     float* Pnew;        // new direction
     float* X;           // iterate
     float* Z;           // preconditioned residual (SZ modes)
+    float* U;           // product-form preconditioner: output of its first pass
 };
 
 struct Geom {
