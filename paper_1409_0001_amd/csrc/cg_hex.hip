@@ -27,6 +27,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 #include "cg_common.h"
@@ -61,7 +62,8 @@ struct SweepArgs {
     int wpf, bpf, nblocks;
     int k;              // iteration index within the step
     PrecondCoef pc;     // k_precond_lds: Horner levels of M = sum_j cp[j] A^j, or the first product pass
-    PrecondCoef pc2;    // the second product pass (degree 8)
+    PrecondCoef pc2;    // the last product pass (degrees 8 and 12)
+    PrecondCoef pcm;    // the middle product pass (degree 12)
 };
 
 // One sweep over all fields: each wave takes one tile (stencil_tile.h).
@@ -379,10 +381,11 @@ __global__ __launch_bounds__(NW * 64) void k_dir_lds(SweepArgs a) {
 
 // The degree-D preconditioning sweep of preconditioned CG (precond_lds.h):
 // convergence test first (as the register sweeps' SZ prologue), then one tile
-// per block, then the block's r.z (and b.b) partials.  FORM 1 and 2 are the
-// two passes of the degree-8 product form: the first (r -> U, coefficients
-// pc) has the convergence test and b.b, the second (U -> z, coefficients
-// pc2) the r.z partials.
+// per block, then the block's r.z (and b.b) partials.  FORM 1, 3 and 2 are
+// the passes of the product form (two quadratic factors each): the first
+// (r -> U, coefficients pc) has the convergence test and b.b, the middle one
+// of degree 12 (U -> V, pcm) neither, the last (V -> z, pc2) the r.z
+// partials.
 template <int VEC, int D, int TY, int NW, bool FIRST, int FORM = 0>
 __global__ __launch_bounds__(NW * 64) void k_precond_lds(SweepArgs a) {
     constexpr int NT = NW * 64;
@@ -396,7 +399,7 @@ __global__ __launch_bounds__(NW * 64) void k_precond_lds(SweepArgs a) {
     CgField* stf = a.c.st + f;
     if (stf->done) return;  // uniform over the block
     const bool lead = blk == 0 && threadIdx.x == 0;
-    if constexpr (!FIRST && FORM != 2) {
+    if constexpr (!FIRST && (FORM == 0 || FORM == 1)) {
         // convergence test on r_k . r_k from the previous sweep 2 (or, at
         // k = 0, the residual sweep, which also gave b.b)
         const double rrk = block_sum_nt<NT>(a.P2 + ((size_t)f * 2 + (a.k & 1)) * a.pstride, a.bpf_in, sh);
@@ -416,14 +419,16 @@ __global__ __launch_bounds__(NW * 64) void k_precond_lds(SweepArgs a) {
     double acc0 = 0.0, acc1 = 0.0;
     const size_t fo = (size_t)f * a.cells;
     const float* rsrc = FIRST ? a.p.B : a.p.R;  // r_k (b at a zero first guess)
-    const float* src = FORM == 2 ? a.p.U : rsrc;
-    float* dst = FORM == 1 ? a.p.U : a.p.Z;
-    precond_lds_tile<VEC, D, TY, NW, FIRST, false, FORM>(lds, src + fo, dst + fo, a.g, FORM == 2 ? a.pc2 : a.pc, a.ny,
-                                                         a.nz, yg * TY, zb, min(zb + a.zc, a.nz), acc0, acc1,
-                                                         rsrc + fo);
+    const float* src = FORM == 2 ? a.p.V : (FORM == 3 ? a.p.U : rsrc);
+    float* dst = FORM == 1 ? a.p.U : (FORM == 3 ? a.p.V : a.p.Z);
+    constexpr int TF = FORM == 3 ? 1 : FORM;  // the middle pass is a first pass without the partials
+    precond_lds_tile<VEC, D, TY, NW, FIRST && (FORM == 0 || FORM == 1), false, TF>(
+        lds, src + fo, dst + fo, a.g, FORM == 2 ? a.pc2 : (FORM == 3 ? a.pcm : a.pc), a.ny, a.nz, yg * TY, zb,
+        min(zb + a.zc, a.nz), acc0, acc1, rsrc + fo);
+    if constexpr (FORM == 3) return;
 
     // block reduction of the float64 partials, fixed order
-    constexpr bool kRz = FORM != 1, kBb = FIRST && FORM != 2;
+    constexpr bool kRz = FORM == 0 || FORM == 2, kBb = FIRST && (FORM == 0 || FORM == 1);
     for (int o = 32; o > 0; o >>= 1) {
         if (kRz) acc0 += __shfl_xor(acc0, o);
         if (kBb) acc1 += __shfl_xor(acc1, o);
@@ -618,17 +623,48 @@ void launch_precond_lds_d(int vec, bool first, const Plan& q, const SweepArgs& a
     }
 }
 
-// Degree 3 or 4: one Horner pass; degree 8: the two product passes, the
-// second reading the first's output U (a.p.U).
+// Degree 3 or 4: one Horner pass; degree 8: two product passes (r -> U,
+// V = U -> z); degree 12: three (r -> U -> V -> z).
 void launch_precond_lds(int deg, int vec, bool first, const Plan& q, const SweepArgs& a, hipStream_t s) {
-    if (deg == 8) {
+    if (deg == 8 || deg == 12) {
         launch_precond_lds_d<4, 1>(vec, first, q, a, s);
+        if (deg == 12) launch_precond_lds_d<4, 3>(vec, first, q, a, s);
         launch_precond_lds_d<4, 2>(vec, first, q, a, s);
     } else if (deg == 4) {
         launch_precond_lds_d<4, 0>(vec, first, q, a, s);
     } else {
         launch_precond_lds_d<3, 0>(vec, first, q, a, s);
     }
+}
+
+// Degree of the LDS polynomial preconditioner with the least predicted work:
+// for degree m the residual polynomial keeps the preconditioned spectrum in
+// [1 - e, 1 + e], e = 1 / T_{m+1}(sig(0)), so CG needs about
+// k = log(2 / rtol) / log(1 / rho) iterations, rho = (sqrt(K) - 1) / (sqrt(K) + 1),
+// K = (1 + e) / (1 - e); an iteration costs sweeps 1 and 2 plus one pass of
+// the LDS tile per 4 degrees, each pass about 0.43 of the two sweeps.  (The
+// bound is close for degrees 8 and 12 and pessimistic for 4, where CG's
+// superlinear convergence does better; degree 4 wins only where degree 8
+// would need as many iterations.)
+int lds_degree(double cx, double cy, double cz, double rtol) {
+    const double lmax = 1.0 + 4.0 * (cx + cy + cz);
+    const double s0 = (lmax + 1.0) / std::max(lmax - 1.0, 1e-12);
+    const double th = std::acosh(std::max(s0, 1.0 + 1e-12));
+    const double want = std::log(2.0 / std::max(rtol, 1e-300));
+    int best = 4;
+    double best_cost = 1e300;
+    for (int m : {4, 8, 12}) {
+        const double e = 1.0 / std::cosh(std::min((m + 1) * th, 700.0));
+        const double K = (1.0 + e) / std::max(1.0 - e, 1e-300);
+        const double rho = (std::sqrt(K) - 1.0) / (std::sqrt(K) + 1.0);
+        const double k = rho > 0.0 ? std::max(1.0, std::ceil(want / std::log(1.0 / rho))) : 1.0;
+        const double cost = k * (1.0 + 0.43 * (m / 4));
+        if (cost < best_cost * (1.0 - 1e-9)) {
+            best_cost = cost;
+            best = m;
+        }
+    }
+    return best;
 }
 
 // Tiling of the LDS preconditioning sweep: ceil(ny / TY) row groups times z
@@ -716,7 +752,7 @@ static size_t max_bpf(const HexGeom& g, int F) {
 }
 
 size_t diffuse_hex_workspace(const cgd_mesh m, int32_t F) {
-    return small_bytes(F, (int)max_bpf(m->hex, F)) + 5 * (size_t)F * m->cells * sizeof(float);
+    return small_bytes(F, (int)max_bpf(m->hex, F)) + 6 * (size_t)F * m->cells * sizeof(float);
 }
 
 cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s) {
@@ -748,7 +784,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     tile_env("CGD_HEX_TILE2", p);
     tile_env("CGD_HEX_TILEZ", pz);
     const size_t small = small_bytes(F, (int)max_bpf(g, F));
-    cgd_status rc = ensure_workspace(m, small + 5 * (size_t)F * cells * sizeof(float));
+    cgd_status rc = ensure_workspace(m, small + 6 * (size_t)F * cells * sizeof(float));
     if (rc != CGD_OK) return rc;
     rc = ensure_pinned(m, kPinBytes);
     if (rc != CGD_OK) return rc;
@@ -772,6 +808,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     float* PA = R + (size_t)F * cells;
     float* PB = PA + (size_t)F * cells;
     float* Z = PB + (size_t)F * cells;
+    float* PV = Z + (size_t)F * cells;  // the degree-12 preconditioner's middle-pass output
 
     const double T = da.bandwidth * da.bandwidth / 4.0;
     const double dtau = T / da.n_steps;
@@ -810,25 +847,28 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     const int mode_z = deg == 2 ? SZ2 : SZ;
     int deg_lds = 0;
     if (deg == 2) {
-        // Degree 8 (two LDS passes of two quadratic factors) where the LDS
-        // tile applies: 3 iterations per step at dtau / h^2 = 1 against 5 at
-        // degree 4 (one Horner pass); on the 256 x 256 x 512 grid 4.80 ms per
-        // field against 5.83.  CGD_HEX_PRECOND_DEG (3, 4 or 8) overrides.
-        int want = 8, zc_force = 0, zc_raw = 0;
+        // Degree 4, 8 or 12 (one Horner pass; two or three passes of two
+        // quadratic factors) where the LDS tile applies, by predicted cost
+        // (lds_degree).  At dtau / h^2 = 1: 5, 3 and 2 iterations per step;
+        // on the 256 x 256 x 512 grid 5.83, 4.90 and 3.89 ms per field.
+        // CGD_HEX_PRECOND_DEG (3, 4, 8 or 12) overrides.
+        int want = lds_degree(a.g.cx, a.g.cy, a.g.cz, da.rtol), zc_force = 0, zc_raw = 0;
         if (const char* e = getenv("CGD_HEX_PRECOND_DEG")) want = atoi(e);
         if (const char* e = getenv("CGD_HEX_LDS_ZC")) zc_force = atoi(e);
-        if (want == 3 || want == 4 || want == 8) {
-            // degree 8 runs as two passes of the degree-4 tile
-            const int dt = want == 8 ? 4 : want;
+        if (want == 3 || want == 4 || want == 8 || want == 12) {
+            // degrees 8 and 12 run as two and three passes of the degree-4 tile
+            const int dt = want >= 8 ? 4 : want;
             Plan pl = lds_plan(g, F, p.vec, dt, zc_force, &zc_raw);
             if ((zc_force > 0 || zc_raw >= dt) && (size_t)pl.bpf <= max_bpf(g, F)) {
                 deg_lds = want;
                 pz = pl;
-                if (want == 8) {
-                    double qs[4], qq[4], qg[4], scale;
-                    poly_precond_quadratics(a.g.cx, a.g.cy, a.g.cz, 8, qs, qq, qg, &scale);
+                if (want >= 8) {
+                    double qs[6], qq[6], qg[6], scale;
+                    const int nf = poly_precond_quadratics(a.g.cx, a.g.cy, a.g.cz, want, qs, qq, qg, &scale);
                     precond_coef_fill_quadratics(a.pc, a.g.cx, a.g.cy, a.g.cz, qs, qq, qg, 1.0);
-                    precond_coef_fill_quadratics(a.pc2, a.g.cx, a.g.cy, a.g.cz, qs + 2, qq + 2, qg + 2, scale);
+                    if (nf == 6) precond_coef_fill_quadratics(a.pcm, a.g.cx, a.g.cy, a.g.cz, qs + 2, qq + 2, qg + 2, 1.0);
+                    precond_coef_fill_quadratics(a.pc2, a.g.cx, a.g.cy, a.g.cz, qs + nf - 2, qq + nf - 2, qg + nf - 2,
+                                                 scale);
                 } else {
                     double c[8];
                     poly_precond_coeffs_n(a.g.cx, a.g.cy, a.g.cz, want, c);
@@ -948,9 +988,13 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             // the product form's intermediate: a p buffer that holds nothing
             // live until sweep 1 writes p_new into it
             a.p.U = it == 0 ? (dir_nw ? PA : PB) : pnew;
+            a.p.V = deg_lds == 12 ? PV : a.p.U;
             int t0 = first ? -1 : timing_begin(&m->timing, s);
             launch(first ? mode_z_first : mode_z);
-            if (!first) timing_end(&m->timing, t0, 5, (deg_lds == 8 ? 20.0 : 8.0) * (double)F * cells, s, tag);
+            // algorithmic bytes of the preconditioning passes: 8 per cell and
+            // pass, and the last pass's read of r
+            const double zb_cell = deg_lds == 12 ? 28.0 : (deg_lds == 8 ? 20.0 : 8.0);
+            if (!first) timing_end(&m->timing, t0, 5, zb_cell * (double)F * cells, s, tag);
             a.p.Z = Z;
             a.p.R = zb;
             a.p.Pold = pold;

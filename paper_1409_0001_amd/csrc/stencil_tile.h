@@ -45,6 +45,7 @@ struct Ptrs {
     float* X;           // iterate
     float* Z;           // preconditioned residual (SZ modes)
     float* U;           // product-form preconditioner: output of its first pass
+    float* V;           // ... input of its last pass (U, or the middle pass's output)
 };
 
 struct Geom {

@@ -251,17 +251,18 @@ def test_dense_bed_reduced_against_dct(gpu_lib):
     assert it0 <= 0.7 * it1, (it0, it1)
 
 
-@pytest.mark.parametrize("deg", [3, 4, 8])
+@pytest.mark.parametrize("deg", [3, 4, 8, 12])
 @pytest.mark.parametrize("shape,zc", [((64, 37, 100), 16), ((128, 20, 70), 13), ((256, 13, 40), 7)])
 def test_lds_preconditioner_matches_oracle(gpu_lib, shape, zc, deg, monkeypatch):
     """The degree-3/4 preconditioning sweep with its powers of A in LDS
-    (one wave per x-row: nx = 64, 128, 256), and degree 8 as two passes of
-    quadratic factors, forced onto small grids with ragged row groups (ny
-    not a multiple of 8) and a ragged last z chunk: the result matches the
-    float64 DCT solution, and the higher degree takes fewer iterations than
-    degree 2.  At dtau / h^2 = 1 (spectrum [1, 13]) the degree-8 polynomial
-    brings every step to rtol 1e-6 in at most 3 iterations (a float32 model
-    of the method on 48^3 takes 3; a wrong factor would cost iterations)."""
+    (one wave per x-row: nx = 64, 128, 256), and degrees 8 and 12 as two and
+    three passes of quadratic factors, forced onto small grids with ragged
+    row groups (ny not a multiple of 8) and a ragged last z chunk: the result
+    matches the float64 DCT solution, and the higher degree takes fewer
+    iterations than degree 2.  At dtau / h^2 = 1 (spectrum [1, 13]) the
+    degree-8 and degree-12 polynomials bring every step to rtol 1e-6 in at
+    most 3 and 2 iterations (a float32 model of the method on 48^3 takes 3
+    and 2; a wrong factor would cost iterations)."""
     import torch
     cgd = gpu_lib
     nx, ny, nz = shape
@@ -287,5 +288,5 @@ def test_lds_preconditioner_matches_oracle(gpu_lib, shape, zc, deg, monkeypatch)
     it4 = sum(sum(r) for r in st4.iters)
     print(f"iterations: degree 2 {st2.iters}, degree {deg} {st4.iters}", flush=True)
     assert it4 < it2, (it2, it4)
-    if deg == 8:
-        assert max(max(r[:2]) for r in st4.iters[:steps]) <= 3, st4.iters
+    if deg >= 8:
+        assert max(max(r[:2]) for r in st4.iters[:steps]) <= (3 if deg == 8 else 2), st4.iters
