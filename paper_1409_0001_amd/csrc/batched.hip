@@ -151,6 +151,7 @@ struct BSolve {
     float* ws;          // [grid][5][cells]
     int pcg;            // 1: preconditioned CG (degree 2: Geom c0, c1, c2; degree 4: cp)
     PrecondCoef pc;     // degree-4 polynomial's Horner levels (configurations with DEG = 4)
+    PrecondCoef pp[3];  // degree-12 polynomial's three product passes (DEG = 12)
     int n_rhs;
     int64_t cells;
     Geom g;
@@ -236,10 +237,46 @@ __device__ inline void wg_precond_lds(float* lds, const BSolve& a, const Ptrs& p
     s1 = acc1;
 }
 
+// One product pass over all tiles of the workgroup's grid.  Not inlined, so
+// that each pass's tile gets its own register allocation instead of sharing
+// the persistent kernel's (which spilled when all three were inlined).
+template <int VEC, int NW, bool FIRST, int FORM>
+__device__ __attribute__((noinline)) void wg_prod_pass(float* lds, const BSolve& a, const float* src, float* dst,
+                                                       const PrecondCoef& pc, const float* r, double* acc) {
+    double acc0 = 0.0, acc1 = 0.0;
+    const int tiles = (a.g.ny + 7) / 8;
+    for (int t = 0; t < tiles; ++t)
+        precond_lds_tile<VEC, 4, 8, NW, FIRST, false, FORM>(lds, src, dst, a.g, pc, a.g.ny, a.g.nz, 8 * t, 0, a.g.nz,
+                                                            acc0, acc1, r);
+    acc[0] = acc0;
+    acc[1] = acc1;
+}
+
+// z = p(A) r with the degree-12 polynomial: three product passes over all
+// tiles (r -> U -> V -> z, two quadratic factors each), a barrier between
+// passes publishing each pass's output; r.z from the last pass (r read for the
+// output rows through the LDS side channel), r.r from the first when FIRST.
+template <int VEC, int NW, bool FIRST>
+__device__ inline void wg_precond_prod(float* lds, const BSolve& a, const Ptrs& p, double& s0, double& s1,
+                                       double (*sh)[2]) {
+    double first[2], mid[2], last[2];
+    const float* r = FIRST ? p.B : p.R;
+    wg_prod_pass<VEC, NW, FIRST, 1>(lds, a, r, p.U, a.pp[0], r, first);
+    __syncthreads();
+    wg_prod_pass<VEC, NW, false, 1>(lds, a, p.U, p.V, a.pp[1], r, mid);
+    __syncthreads();
+    wg_prod_pass<VEC, NW, false, 2>(lds, a, p.V, p.Z, a.pp[2], r, last);
+    double acc0 = last[0], acc1 = first[1];
+    wg_sum2<NW>(acc0, acc1, sh);
+    s0 = acc0;
+    s1 = acc1;
+}
+
 template <int VEC, int TY, int NW, int DEG, bool FIRST>
 __device__ inline void wg_precondition(float* lds, const BSolve& a, const Ptrs& p, double& s0, double& s1,
                                        double (*sh)[2]) {
-    if constexpr (DEG == 4) wg_precond_lds<VEC, NW, FIRST>(lds, a, p, s0, s1, sh);
+    if constexpr (DEG == 12) wg_precond_prod<VEC, NW, FIRST>(lds, a, p, s0, s1, sh);
+    else if constexpr (DEG == 4) wg_precond_lds<VEC, NW, FIRST>(lds, a, p, s0, s1, sh);
     else wg_precond<VEC, TY, NW, FIRST>(a, p, s0, s1, sh);
 }
 
@@ -250,7 +287,8 @@ __device__ inline void wg_precondition(float* lds, const BSolve& a, const Ptrs& 
 template <int VEC, int TY, int NW, int DEG>
 __global__ __launch_bounds__(64 * NW) void k_batched_cg(BSolve a) {
     __shared__ double sh[NW][2];
-    __shared__ __align__(16) float lds[DEG == 4 ? precond_lds_floats<VEC, 4, 8>() : 4];
+    __shared__ __align__(16) float lds[DEG == 12 ? precond_lds_floats<VEC, 4, 8, 2>()
+                                                 : (DEG == 4 ? precond_lds_floats<VEC, 4, 8>() : 4)];
     const size_t cells = (size_t)a.cells;
     float* W0 = a.ws + (size_t)blockIdx.x * 5 * cells;
     float* R = W0 + cells;
@@ -263,9 +301,13 @@ __global__ __launch_bounds__(64 * NW) void k_batched_cg(BSolve a) {
         float* nxt = W0;
         int worst = CGD_OK;
         for (int step = 0; step < a.n_steps; ++step) {
-            if (DEG == 4 || a.pcg) {  // degree-4 configurations run preconditioned CG only
+            if (DEG >= 4 || a.pcg) {  // degree-4 and -12 configurations run preconditioned CG only
                 // preconditioned CG from x = 0: z = M b, p = z, x = alpha p, r = b - alpha A p
                 Ptrs p{cur, R, nullptr, PA, nxt, Z};
+                // degree 12's intermediates: both p buffers are free before
+                // sweep 1 of the first iteration
+                p.U = PA;
+                p.V = PB;
                 Ptrs q = p;  // the direction sweeps read z through Ptrs::R
                 q.R = Z;
                 double rho, bb, pap, rr, dummy;
@@ -287,9 +329,14 @@ __global__ __launch_bounds__(64 * NW) void k_batched_cg(BSolve a) {
                         break;
                     }
                     double rho_new;
-                    wg_precondition<VEC, TY, NW, DEG, false>(lds, a, p, rho_new, dummy, sh);
                     q.Pold = (k & 1) ? PA : PB;
                     q.Pnew = (k & 1) ? PB : PA;
+                    // degree 12's intermediates: the p buffer sweep 1 is about
+                    // to write, and b's buffer (dead after the first iteration;
+                    // it becomes the next step's iterate)
+                    p.U = q.Pnew;
+                    p.V = cur;
+                    wg_precondition<VEC, TY, NW, DEG, false>(lds, a, p, rho_new, dummy, sh);
                     wg_sweep<VEC, TY, NW, S1>(a, q, 0.f, (float)(rho_new / rho), pap, dummy, sh);
                     if (!(pap > 0.0) || !isfinite(pap)) {
                         broken = true;
@@ -308,7 +355,7 @@ __global__ __launch_bounds__(64 * NW) void k_batched_cg(BSolve a) {
                 nxt = t;
                 continue;
             }
-            if constexpr (DEG == 4) continue;
+            if constexpr (DEG >= 4) continue;
             Ptrs p{cur, R, nullptr, nullptr, nxt, nullptr};
             double bab, bb, rr, dummy;
             wg_sweep<VEC, TY, NW, S1_FIRST>(a, p, 0.f, 0.f, bab, bb, sh);
@@ -377,6 +424,16 @@ struct Cfg {
     const void* fn;
 };
 
+// The degree-12 polynomial's three product passes (two quadratic factors
+// each, the overall scale on the last).
+void fill_prod12(BSolve& a) {
+    double qs[6], qq[6], qg[6], scale;
+    poly_precond_quadratics(a.g.cx, a.g.cy, a.g.cz, 12, qs, qq, qg, &scale);
+    for (int i = 0; i < 3; ++i)
+        precond_coef_fill_quadratics(a.pp[i], a.g.cx, a.g.cy, a.g.cz, qs + 2 * i, qq + 2 * i, qg + 2 * i,
+                                     i == 2 ? scale : 1.0);
+}
+
 template <int VEC, int TY, int NW, int DEG>
 Cfg make_cfg() {
     return Cfg{VEC, TY, NW, DEG, reinterpret_cast<const void*>(&k_batched_cg<VEC, TY, NW, DEG>)};
@@ -384,17 +441,17 @@ Cfg make_cfg() {
 
 // Tile shapes of the CG sweeps (rows per wave, waves per workgroup) and the
 // preconditioner degree: 2 in registers (rows per wave small enough that its
-// queues fit without spilling at 16 waves), or 4 through the LDS sweep (16
-// waves, 8 rows of y per tile).
+// queues fit without spilling at 16 waves), 4 through the LDS sweep (16
+// waves, 8 rows of y per tile), or 12 as three LDS product passes.
 std::vector<Cfg> candidates(int vec) {
     if (vec == 4)
         return {make_cfg<4, 1, 8, 2>(), make_cfg<4, 1, 16, 2>(), make_cfg<4, 2, 8, 2>(), make_cfg<4, 2, 12, 2>(),
-                make_cfg<4, 1, 16, 4>(), make_cfg<4, 2, 16, 4>()};
+                make_cfg<4, 1, 16, 4>(), make_cfg<4, 2, 16, 4>(), make_cfg<4, 1, 16, 12>(), make_cfg<4, 2, 16, 12>()};
     if (vec == 2)
         return {make_cfg<2, 2, 8, 2>(), make_cfg<2, 2, 16, 2>(), make_cfg<2, 4, 8, 2>(), make_cfg<2, 4, 12, 2>(),
-                make_cfg<2, 2, 16, 4>(), make_cfg<2, 4, 16, 4>()};
+                make_cfg<2, 2, 16, 4>(), make_cfg<2, 4, 16, 4>(), make_cfg<2, 2, 16, 12>(), make_cfg<2, 4, 16, 12>()};
     return {make_cfg<1, 4, 8, 2>(), make_cfg<1, 4, 16, 2>(), make_cfg<1, 8, 8, 2>(), make_cfg<1, 8, 16, 2>(),
-            make_cfg<1, 4, 16, 4>(), make_cfg<1, 8, 16, 4>()};
+            make_cfg<1, 4, 16, 4>(), make_cfg<1, 8, 16, 4>(), make_cfg<1, 4, 16, 12>(), make_cfg<1, 8, 16, 12>()};
 }
 
 int batched_vec(const HexGeom& g) {
@@ -570,6 +627,7 @@ cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, 
         double c4[8];
         poly_precond_coeffs_n(1.0, 1.0, 1.0, 4, c4);
         precond_coef_fill(a.pc, a.g.cx, a.g.cy, a.g.cz, c4, 4);
+        fill_prod12(a);
     }
     // time to solution (rtol 1e-6), so that candidates of different
     // preconditioner degree compare fairly
@@ -635,7 +693,7 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
         if (v >= 0 && v < (int)cands.size()) ci = v;
     }
     Cfg c = cands[ci];
-    if (da.precond != 0 && c.deg == 4) {
+    if (da.precond != 0 && c.deg >= 4) {
         // plain CG: the degree-2 configuration of the same shape (else the
         // 16-wave one), whose kernel carries the unpreconditioned path
         int alt = -1;
@@ -718,6 +776,7 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
         double c4[8];
         poly_precond_coeffs_n(a.g.cx, a.g.cy, a.g.cz, 4, c4);
         precond_coef_fill(a.pc, a.g.cx, a.g.cy, a.g.cz, c4, 4);
+        fill_prod12(a);
     }
     a.xsegs = 1;
     a.ygroups = (g.ny + c.ty - 1) / c.ty;

@@ -158,11 +158,11 @@ def test_autotune_reports_candidates(gpu_lib):
     cgd = gpu_lib
     mesh = cgd.HexMesh((128, 64, 32))
     chosen, ms = cgd.autotune_batched(mesh, 32)
-    assert len(ms) == 6 and all(t > 0 for t in ms)  # 4 tile shapes at degree 2, 2 at degree 4
+    assert len(ms) == 8 and all(t > 0 for t in ms)  # 4 tile shapes at degree 2, 2 at degree 4, 2 at degree 12
     assert chosen == int(np.argmin(ms))
 
 
-@pytest.mark.parametrize("cfg", [1, 4, 5])  # degree 2 (16 waves); degree 4, both tile shapes
+@pytest.mark.parametrize("cfg", [1, 4, 5, 6, 7])  # degree 2 (16 waves); degrees 4 and 12, both tile shapes
 def test_batched_candidates_match_oracle(gpu_lib, cfg, monkeypatch):
     """Every preconditioner degree of the persistent solver reaches the same
     fields: forced candidates against the float64 oracle on 128 x 20 x 24
