@@ -416,7 +416,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"dense bed {shape[0]}x{shape[1]}x{shape[2]} hex, box 1x1x2, "
                                f"{args.particles} particles, F={args.fields}, b=4h, 4 backward-Euler "
-                               f"steps, CG preconditioned by a degree-8 Chebyshev polynomial of A, rtol {args.rtol:g}",
+                               f"steps, CG preconditioned by a Chebyshev polynomial of A (degree 4, 8 or 12 by predicted "
+                               f"cost; 12 at dtau/h^2 = 1), rtol {args.rtol:g}",
                    "particles": args.particles, "cells": int(mesh.cells), "fields": args.fields,
                    "cg_iters_per_step": iters},
         "rel_l2": rel,

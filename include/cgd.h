@@ -100,7 +100,9 @@ typedef struct {
                              runs past the previous solve's count; <= 0: 4 */
     int32_t precond;      /* hex meshes: 0 (default) conjugate gradients preconditioned by
                              a Chebyshev polynomial of A on its spectrum [1, 1 + 4 sum_a c_a]:
-                             degree 8 (two sweeps of two quadratic factors each) where one
+                             degree 4, 8 or 12 (one Horner sweep; two or three sweeps of two
+                             quadratic factors each), the one with the least work predicted
+                             from the Chebyshev bound on the iteration count, where one
                              wavefront covers an x-row (nx = 64, 128 or 256) and the grid
                              fills the machine, else degree 2 or 1; 1 plain CG.  Tet meshes
                              use Jacobi either way.  The stopping rule is the same for all. */
@@ -204,7 +206,7 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F,
  * Deposition follows cgd_deposit per snapshot (its own fixed-point scale per
  * snapshot and field).  All n_snap * F right-hand sides are then solved from
  * a zero initial guess by CG preconditioned with a Chebyshev polynomial of
- * the operator, of degree 2 or 4 as the autotuner chose (o->precond = 1:
+ * the operator, of degree 2, 4 or 12 as the autotuner chose (o->precond = 1:
  * plain CG), with float32
  * vectors, float64 inner products, and the stencil and stopping rule of
  * cgd_diffuse, in ONE persistent launch in which each workgroup solves its
@@ -229,7 +231,7 @@ cgd_status cgd_coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* o
                                     float* fields, int32_t* iters, void* stream);
 
 /* Autotuner of the batched solver: times each candidate (rows per wave,
- * waves per workgroup, preconditioner degree 2 or 4) solving n_rhs synthetic
+ * waves per workgroup, preconditioner degree 2, 4 or 12) solving n_rhs synthetic
  * right-hand sides for one backward-Euler step at dtau / h^2 = 1 to rtol
  * 1e-6, and keeps the fastest for this mesh shape (also appended to the file
  * named by the environment variable CGD_AUTOTUNE_CACHE, when set, and read
