@@ -18,10 +18,10 @@ Proposed Diffusion-Based Coarse Graining Method", and Section 3.1):
    the Gaussian kernel of eq. hi with b = sqrt(4T)), with zero-flux walls
    (Section 3.2.2), discretised by the second-order central finite-volume
    Laplacian (Section 5.1) and integrated by backward Euler in n equal
-   pseudo-steps.
+   pseudo-steps, or by the paper's Crank-Nicolson scheme (Section 5.1).
 
 Readings of points the paper leaves open (each has a line in the design
-notes): backward Euler instead of the paper's Crank-Nicolson; T split into
+notes): backward Euler by default, Crank-Nicolson as an option; T split into
 equal steps; the system is taken in symmetric form (M + dtau K) x = M eps;
 ties at cell faces go to the upper cell, points on the upper wall to the
 last cell; out-of-box or non-finite particles are not deposited.
@@ -242,18 +242,49 @@ def backward_euler(M_diag, K, eps0, T, n_steps, solver="cg", rtol=1e-12):
     return eps.reshape(np.shape(eps0))
 
 
-def diffuse_hex(field, lo, hi, shape, bandwidth, n_steps, solver="cg", rtol=1e-12):
-    """Diffuse cell fields [F, cells] on the hex grid for T = b^2/4."""
+def crank_nicolson(M_diag, K, eps0, T, n_steps, solver="cg", rtol=1e-12):
+    """n_steps Crank-Nicolson steps of dtau = T / n_steps for M de/dtau = -K e
+    (the paper's time integrator, Section 5.1).
+
+    Each step solves (M + dtau/2 K) e^{n+1} = (M - dtau/2 K) e^n, the
+    trapezoidal rule in pseudo-time.  Shapes as in backward_euler.
+    """
+    dtau = T / n_steps
+    Md = sp.diags(M_diag)
+    A = (Md + (0.5 * dtau) * K).tocsr()
+    B = (Md - (0.5 * dtau) * K).tocsr()
+    eps = np.atleast_2d(np.asarray(eps0, dtype=np.float64)).copy()
+    lu = spla.splu(A.tocsc()) if solver == "direct" else None
+    for f in range(eps.shape[0]):
+        e = eps[f]
+        for _ in range(n_steps):
+            rhs = B @ e
+            e = lu.solve(rhs) if lu is not None else cg(A, rhs, rtol)[0]
+        eps[f] = e
+    return eps.reshape(np.shape(eps0))
+
+
+def _integrator(scheme):
+    if scheme == "be":
+        return backward_euler
+    if scheme == "cn":
+        return crank_nicolson
+    raise ValueError(f"scheme must be 'be' or 'cn', not {scheme!r}")
+
+
+def diffuse_hex(field, lo, hi, shape, bandwidth, n_steps, solver="cg", rtol=1e-12, scheme="be"):
+    """Diffuse cell fields [F, cells] on the hex grid for T = b^2/4
+    (scheme "be": backward Euler, "cn": Crank-Nicolson)."""
     n = shape[0] * shape[1] * shape[2]
     V = hex_cell_volume(lo, hi, shape)
     K = hex_laplacian(shape, lo, hi)
-    return backward_euler(np.full(n, V), K, field, pseudo_time(bandwidth), n_steps, solver, rtol)
+    return _integrator(scheme)(np.full(n, V), K, field, pseudo_time(bandwidth), n_steps, solver, rtol)
 
 
-def coarse_grain_hex(pos, values, lo, hi, shape, bandwidth, n_steps, solver="cg", rtol=1e-12):
-    """Full method on a uniform hex grid: PCM, then n_steps backward-Euler steps."""
+def coarse_grain_hex(pos, values, lo, hi, shape, bandwidth, n_steps, solver="cg", rtol=1e-12, scheme="be"):
+    """Full method on a uniform hex grid: PCM, then n_steps pseudo-steps."""
     dep = deposit_hex(pos, values, lo, hi, shape)
-    out = diffuse_hex(dep["field64"], lo, hi, shape, bandwidth, n_steps, solver, rtol)
+    out = diffuse_hex(dep["field64"], lo, hi, shape, bandwidth, n_steps, solver, rtol, scheme)
     return out, dep
 
 
@@ -269,10 +300,12 @@ def neumann_eigenvalues(n, h):
     return (4.0 / (h * h)) * np.sin(np.pi * k / (2.0 * n)) ** 2
 
 
-def diffuse_hex_dct(field, lo, hi, shape, bandwidth, n_steps):
-    """Exact backward-Euler result of diffuse_hex, by the DCT-II closed form.
+def diffuse_hex_dct(field, lo, hi, shape, bandwidth, n_steps, scheme="be"):
+    """Exact result of diffuse_hex, by the DCT-II closed form.
 
-    field [..., cells] (x fastest).  e^n = IDCT[ DCT(e^0) (1 + dtau lam)^-n ].
+    field [..., cells] (x fastest).  Backward Euler:
+    e^n = IDCT[ DCT(e^0) (1 + dtau lam)^-n ]; Crank-Nicolson: each mode is
+    multiplied by (1 - dtau lam / 2) / (1 + dtau lam / 2) per step.
     """
     from scipy.fft import dctn, idctn
     nx, ny, nz = shape
@@ -280,7 +313,12 @@ def diffuse_hex_dct(field, lo, hi, shape, bandwidth, n_steps):
     dtau = pseudo_time(bandwidth) / n_steps
     lam = (neumann_eigenvalues(nz, hz)[:, None, None] + neumann_eigenvalues(ny, hy)[None, :, None]
            + neumann_eigenvalues(nx, hx)[None, None, :])
-    damp = (1.0 + dtau * lam) ** (-n_steps)
+    if scheme == "be":
+        damp = (1.0 + dtau * lam) ** (-n_steps)
+    elif scheme == "cn":
+        damp = ((1.0 - 0.5 * dtau * lam) / (1.0 + 0.5 * dtau * lam)) ** n_steps
+    else:
+        raise ValueError(f"scheme must be 'be' or 'cn', not {scheme!r}")
     f = np.atleast_2d(np.asarray(field, dtype=np.float64))
     out = np.empty_like(f)
     for i in range(f.shape[0]):
@@ -314,19 +352,31 @@ def thomas(a, b, c, d):
     return x
 
 
-def diffuse_1d_thomas(field, length, bandwidth, n_steps):
-    """1-D zero-flux backward-Euler diffusion of a cell field by Thomas solves."""
+def diffuse_1d_thomas(field, length, bandwidth, n_steps, scheme="be"):
+    """1-D zero-flux diffusion of a cell field by Thomas solves: backward
+    Euler ("be") or Crank-Nicolson ("cn", whose right-hand side is the
+    explicit half step e_i + c/2 (e_i-1 - 2 e_i + e_i+1), a missing wall
+    neighbour taken as e_i)."""
+    if scheme not in ("be", "cn"):
+        raise ValueError(f"scheme must be 'be' or 'cn', not {scheme!r}")
     n = len(field)
     h = length / n
     c = pseudo_time(bandwidth) / n_steps / (h * h)
-    a = np.full(n, -c)
-    cc = np.full(n, -c)
-    b = np.full(n, 1.0 + 2.0 * c)
-    b[0] -= c
-    b[-1] -= c
+    ci = 0.5 * c if scheme == "cn" else c
+    a = np.full(n, -ci)
+    cc = np.full(n, -ci)
+    b = np.full(n, 1.0 + 2.0 * ci)
+    b[0] -= ci
+    b[-1] -= ci
     e = np.asarray(field, dtype=np.float64).copy()
     for _ in range(n_steps):
-        e = thomas(a, b, cc, e)
+        if scheme == "cn":
+            left = np.concatenate(([e[0]], e[:-1]))
+            right = np.concatenate((e[1:], [e[-1]]))
+            d = e + 0.5 * c * (left - 2.0 * e + right)
+        else:
+            d = e
+        e = thomas(a, b, cc, d)
     return e
 
 
@@ -579,7 +629,8 @@ def deposit_tet(xyz, tets, pos, values, cells=None):
                 n_dropped=int((~mask).sum()))
 
 
-def diffuse_tet(field, xyz, tets, bandwidth, n_steps, solver="cg", rtol=1e-12):
-    """Backward-Euler diffusion of tet-cell fields with the TPFA Laplacian."""
+def diffuse_tet(field, xyz, tets, bandwidth, n_steps, solver="cg", rtol=1e-12, scheme="be"):
+    """Diffusion of tet-cell fields with the TPFA Laplacian (scheme "be":
+    backward Euler, "cn": Crank-Nicolson)."""
     K, V = tet_tpfa(xyz, tets)
-    return backward_euler(V, K, field, pseudo_time(bandwidth), n_steps, solver, rtol)
+    return _integrator(scheme)(V, K, field, pseudo_time(bandwidth), n_steps, solver, rtol)

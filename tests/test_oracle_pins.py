@@ -404,3 +404,120 @@ def test_tet_diffusion_approaches_kernel_closed_form():
         ref = O.kernel_cell_average_hex(pos, [1.0], (0, 0, 0), (1, 1, 1), (n, n, n), b)
         errs.append(np.linalg.norm(hexv - ref) / np.linalg.norm(ref))
     assert errs[1] < 0.5 * errs[0], errs
+
+
+# ---------------------------------------------------------------- Crank-Nicolson (Section 5.1)
+
+
+def _exact_semigroup(M_diag, K, e0, T):
+    """exp(-T M^-1 K) e0 through the symmetric matrix M^-1/2 K M^-1/2 and a
+    dense eigen-decomposition (no time stepping at all)."""
+    s = 1.0 / np.sqrt(M_diag)
+    S = (s[:, None] * K.toarray()) * s[None, :]
+    w, Q = np.linalg.eigh(S)
+    return s * (Q @ (np.exp(-T * w) * (Q.T @ (e0 / s))))
+
+
+@pytest.mark.parametrize("shape,hi", [((17, 1, 1), (1.0, 1, 1)), ((6, 9, 1), (0.6, 1.8, 0.1)),
+                                      ((5, 6, 7), (1.0, 1.0, 1.0)), ((8, 4, 6), (0.8, 0.2, 1.2))])
+def test_cn_cg_and_direct_routes_equal_dct_closed_form(shape, hi):
+    """Crank-Nicolson by sparse CG, by sparse LU, and by the DCT-II closed
+    form (per-mode factor (1 - dtau lam/2) / (1 + dtau lam/2)) agree."""
+    rng = np.random.default_rng(14)
+    n = shape[0] * shape[1] * shape[2]
+    f = rng.random((2, n))
+    f[1] -= 0.5
+    lo = (0.0, 0.0, 0.0)
+    b = 0.3 * max(hi)
+    a = O.diffuse_hex(f, lo, hi, shape, b, 3, solver="cg", scheme="cn")
+    d = O.diffuse_hex(f, lo, hi, shape, b, 3, solver="direct", scheme="cn")
+    c = O.diffuse_hex_dct(f, lo, hi, shape, b, 3, scheme="cn")
+    assert np.abs(a - c).max() <= 1e-10 * np.abs(c).max()
+    assert np.abs(d - c).max() <= 1e-12 * np.abs(c).max()
+    # and it is not the backward-Euler result
+    assert np.abs(c - O.diffuse_hex_dct(f, lo, hi, shape, b, 3)).max() > 1e-3 * np.abs(c).max()
+
+
+def test_cn_thomas_with_explicit_half_step():
+    """1-D: Thomas solves with the explicit half step written per cell equal
+    the sparse-LU route on the assembled Laplacian."""
+    rng = np.random.default_rng(15)
+    n = 40
+    f = rng.random(n)
+    e1 = O.diffuse_1d_thomas(f, 3.0, 0.4, 5, scheme="cn")
+    e2 = O.diffuse_hex(f, (0, 0, 0), (3.0, 1, 1), (n, 1, 1), 0.4, 5, solver="direct", scheme="cn")
+    assert np.allclose(e1, e2, rtol=1e-12, atol=1e-14)
+
+
+def test_cn_is_second_order_and_be_first_order_in_dtau():
+    """Against the exact semi-discrete solution exp(-T M^-1 K) e0 (from an
+    eigen-decomposition, no time stepping), halving dtau divides the
+    Crank-Nicolson error by about 4 and the backward-Euler error by about 2.
+    A dtau instead of dtau/2 on either side of the Crank-Nicolson step, or a
+    sign slip in its explicit half, makes it first order or unstable."""
+    shape, lo, hi = (9, 7, 6), (0.0, 0.0, 0.0), (1.0, 0.8, 0.7)
+    h = O.hex_spacing(lo, hi, shape)
+    c = np.array([[[((z + 0.5) * h[2] - 0.3) ** 2 + ((y + 0.5) * h[1] - 0.45) ** 2 + ((x + 0.5) * h[0] - 0.6) ** 2
+                    for x in range(shape[0])] for y in range(shape[1])] for z in range(shape[2])]).ravel()
+    e0 = np.exp(-c / 0.08)  # a smooth bump: its error is in the asymptotic regime
+    V = O.hex_cell_volume(lo, hi, shape)
+    K = O.hex_laplacian(shape, lo, hi)
+    b = 0.25
+    ref = _exact_semigroup(np.full(e0.size, V), K, e0, O.pseudo_time(b))
+    err = {(s, n): np.linalg.norm(O.diffuse_hex(e0, lo, hi, shape, b, n, solver="direct", scheme=s) - ref)
+           for s in ("be", "cn") for n in (4, 8, 16)}
+    for n in (4, 8):
+        assert 3.6 < err["cn", n] / err["cn", 2 * n] < 4.4, (n, err)
+        assert 1.7 < err["be", n] / err["be", 2 * n] < 2.3, (n, err)
+    assert err["cn", 16] < 0.1 * err["be", 16]
+
+
+def test_cn_conserves_mass_and_can_undershoot():
+    """Zero-flux walls: Crank-Nicolson conserves sum(V e) like backward
+    Euler.  Unlike backward Euler it is not positivity preserving: one step of
+    dtau = T from a single loaded cell with dtau / h^2 >> 1 leaves negative
+    cells (its amplification tends to -1 for stiff modes), which many small
+    steps do not."""
+    shape, lo, hi = (15, 1, 1), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    e0 = np.zeros(15)
+    e0[7] = 1.0
+    b = 0.6  # T = 0.09, dtau / h^2 = 20 in one step
+    one = O.diffuse_hex(e0, lo, hi, shape, b, 1, solver="direct", scheme="cn")
+    many = O.diffuse_hex(e0, lo, hi, shape, b, 400, solver="direct", scheme="cn")
+    be = O.diffuse_hex(e0, lo, hi, shape, b, 1, solver="direct", scheme="be")
+    for e in (one, many, be):
+        assert abs(e.sum() - 1.0) < 1e-13
+    assert one.min() < -0.05
+    assert many.min() >= 0.0 and be.min() >= 0.0
+
+
+def test_time_step_study_cn():
+    """Section 5.1 with the paper's integrator: dtau = T/8 and T/3 agree
+    with a fine-step result to a few percent on the tiny workload.  A single
+    step of dtau = T does not: at this bandwidth the PCM field's stiff modes
+    keep a Crank-Nicolson factor near -1 (the paper reports its one-step
+    field as only qualitatively similar)."""
+    w = inputs.tiny()
+    dep = O.deposit_hex(w.particles.pos, w.particles.values, w.box.lo, w.box.hi, w.box.shape)
+    e0 = dep["field64"][0]
+    r = {k: O.diffuse_hex_dct(e0, w.box.lo, w.box.hi, w.box.shape, 0.1, k, scheme="cn") for k in (1, 3, 8, 64)}
+    d = lambda a, c: np.linalg.norm(r[a] - r[c]) / np.linalg.norm(r[c])
+    assert d(8, 64) < 0.005 and d(3, 64) < 0.05
+    assert d(8, 64) < d(3, 64) < d(1, 64)
+
+
+def test_tet_cn_routes_conservation_and_order():
+    """Tet meshes: Crank-Nicolson by CG equals sparse LU, conserves sum(V e),
+    and is second order in dtau against exp(-T V^-1 K) e0."""
+    xyz, tets = inputs.kuhn_tet_mesh(4, 0.15, seed=16)
+    K, V = O.tet_tpfa(xyz, tets)
+    cen = xyz[tets].mean(axis=1)
+    e0 = np.exp(-((cen - 0.45) ** 2).sum(axis=1) / 0.05)
+    b = 0.3
+    a = O.diffuse_tet(e0, xyz, tets, b, 3, solver="cg", scheme="cn")
+    d = O.diffuse_tet(e0, xyz, tets, b, 3, solver="direct", scheme="cn")
+    assert np.abs(a - d).max() <= 1e-9 * np.abs(d).max()
+    assert abs((V * d).sum() - (V * e0).sum()) <= 1e-13 * (V * e0).sum()
+    ref = _exact_semigroup(V, K, e0, O.pseudo_time(b))
+    e4, e8 = (np.linalg.norm(O.diffuse_tet(e0, xyz, tets, b, n, solver="direct", scheme="cn") - ref) for n in (4, 8))
+    assert 3.5 < e4 / e8 < 4.5, (e4, e8)
