@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--check-every", type=int, default=4)
     ap.add_argument("--no-check", action="store_true", help="skip the float64 accuracy check")
+    ap.add_argument("--scheme", default="be", choices=["be", "cn"],
+                    help="dense workload's integrator: backward Euler (the headline) or Crank-Nicolson")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
@@ -93,11 +95,12 @@ def cpu_baseline(args):
     with threadpool_limits(1):
         t = time.perf_counter()
         O.coarse_grain_hex(w.particles.pos, w.particles.values, w.box.lo, w.box.hi, w.box.shape,
-                           w.bandwidth, w.n_steps, rtol=1e-12)
+                           w.bandwidth, w.n_steps, rtol=1e-12, scheme=args.scheme)
         dt = time.perf_counter() - t
     return {"value": 1.0 / (dt * ratio), "unit": "fields/s", "cores": 1, "kind": "oracle",
             "sample": f"dense-bed recipe at {sx}x{sy}x{sz} cells, {w.particles.pos.shape[0]} particles "
-                      f"(1/{ratio:g} of the workload), 1 field, deposit + 4 backward-Euler steps by "
+                      f"(1/{ratio:g} of the workload), 1 field, deposit + 4 "
+                      f"{'backward-Euler' if args.scheme == 'be' else 'Crank-Nicolson'} steps by "
                       f"float64 CG to 1e-12; {dt:.1f} s, scaled by the cell ratio"}
 
 
@@ -349,7 +352,7 @@ def main():
     vals = torch.from_numpy(w.particles.values).cuda()
     mesh = cgd.HexMesh(w.box.shape, w.box.lo, w.box.hi)
     out = torch.empty((args.fields, mesh.cells), dtype=torch.float32, device="cuda")
-    kw = dict(rtol=args.rtol, check_every=args.check_every, field=out)
+    kw = dict(rtol=args.rtol, check_every=args.check_every, field=out, scheme=args.scheme)
 
     for _ in range(args.warmup):
         cgd.coarse_grain(mesh, pos, vals, w.bandwidth, w.n_steps, **kw)
@@ -403,7 +406,8 @@ def main():
     if not args.no_check:
         from oracle import cgd_oracle as O
         dep = O.deposit_hex(w.particles.pos, w.particles.values, w.box.lo, w.box.hi, w.box.shape)
-        ref = O.diffuse_hex_dct(dep["field64"], w.box.lo, w.box.hi, w.box.shape, w.bandwidth, w.n_steps)
+        ref = O.diffuse_hex_dct(dep["field64"], w.box.lo, w.box.hi, w.box.shape, w.bandwidth, w.n_steps,
+                                scheme=args.scheme)
         got = out.cpu().numpy().astype(np.float64)
         rel = max(float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])) for f in range(args.fields))
         print(f"[bench] rel L2 vs float64 oracle {rel:.3e}", file=sys.stderr, flush=True)
@@ -415,9 +419,10 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"dense bed {shape[0]}x{shape[1]}x{shape[2]} hex, box 1x1x2, "
-                               f"{args.particles} particles, F={args.fields}, b=4h, 4 backward-Euler "
+                               f"{args.particles} particles, F={args.fields}, b=4h, 4 "
+                               f"{'backward-Euler' if args.scheme == 'be' else 'Crank-Nicolson'} "
                                f"steps, CG preconditioned by a Chebyshev polynomial of A (degree 4, 8 or 12 by predicted "
-                               f"cost; 12 at dtau/h^2 = 1), rtol {args.rtol:g}",
+                               f"cost{'; 12 at dtau/h^2 = 1' if args.scheme == 'be' else ''}), rtol {args.rtol:g}",
                    "particles": args.particles, "cells": int(mesh.cells), "fields": args.fields,
                    "cg_iters_per_step": iters},
         "rel_l2": rel,

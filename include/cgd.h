@@ -107,6 +107,14 @@ typedef struct {
                              fills the machine, else degree 2 or 1; 1 plain CG.  Tet meshes
                              use Jacobi either way.  The stopping rule is the same for all. */
     cgd_unet model;       /* x0_mode 3: a network created for this mesh's grid, else NULL */
+    int32_t scheme;       /* pseudo-time integrator (Section 5.1): 0 (default) backward Euler,
+                             each step solving (M + dtau K) e^{n+1} = M e^n; 1 Crank-Nicolson,
+                             (M + dtau/2 K) e^{n+1} = (M - dtau/2 K) e^n, computed as the
+                             half-step solve (M + dtau/2 K) y = M e^n (same solvers, stopping
+                             rule on y) followed by e^{n+1} = 2 y - e^n.  Crank-Nicolson
+                             conserves mass but, unlike backward Euler, is not positivity
+                             preserving at large dtau / h^2.  cgd_coarse_grain_batched: 0
+                             only.  Other values: CGD_E_INVALID. */
 } cgd_solver_opts;
 
 typedef struct {

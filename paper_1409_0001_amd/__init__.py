@@ -143,8 +143,14 @@ class TetMesh(Mesh):
         self.nnz = int(lib.cgd_mesh_nnz(h))
 
 
-def _opts(rtol, max_iter, x0_mode, x0, check_every, model=None, precond=0):
+_SCHEMES = {"be": 0, "cn": 1}
+
+
+def _opts(rtol, max_iter, x0_mode, x0, check_every, model=None, precond=0, scheme="be"):
     o = _abi.SolverOpts()
+    if scheme not in _SCHEMES:
+        raise ValueError(f"scheme must be 'be' (backward Euler) or 'cn' (Crank-Nicolson), not {scheme!r}")
+    o.scheme = _SCHEMES[scheme]
     o.precond = int(precond)
     o.rtol = float(rtol)
     o.max_iter = int(max_iter)
@@ -192,17 +198,18 @@ def deposit(mesh: Mesh, pos, values, field=None, acc=None, stats=False, stream=N
 
 
 def diffuse(mesh: Mesh, field, bandwidth, n_steps, rtol=1e-6, max_iter=1000, x0_mode=0, x0=None,
-            check_every=4, stats=False, stream=None, model=None, precond=0):
+            check_every=4, stats=False, stream=None, model=None, precond=0, scheme="be"):
     """Diffuses field [F, cells] in place for T = bandwidth^2 / 4 in n_steps
-    backward-Euler steps.  x0_mode 3 seeds every step with model(e^n) (a
-    UNet made for this mesh's grid).  Returns (field, Stats or None)."""
+    backward-Euler ("be") or Crank-Nicolson ("cn") steps.  x0_mode 3 seeds
+    every step with model(e^n) (a UNet made for this mesh's grid).  Returns
+    (field, Stats or None)."""
     torch = _torch()
     lib = _abi.load()
     F = int(field.shape[0])
     p_field = _dev(field, torch.float32, (F, mesh.cells), "field")
     if x0 is not None:
         _dev(x0, torch.float32, (F, mesh.cells), "x0")
-    o = _opts(rtol, max_iter, x0_mode, x0, check_every, model, precond)
+    o = _opts(rtol, max_iter, x0_mode, x0, check_every, model, precond, scheme)
     st = _abi.SolveStats() if stats else None
     rc = lib.cgd_diffuse(mesh.handle, F, p_field, float(bandwidth), int(n_steps), ctypes.byref(o),
                          ctypes.byref(st) if st is not None else None, _stream_ptr(stream))
@@ -211,7 +218,7 @@ def diffuse(mesh: Mesh, field, bandwidth, n_steps, rtol=1e-6, max_iter=1000, x0_
 
 
 def coarse_grain(mesh: Mesh, pos, values, bandwidth, n_steps, rtol=1e-6, max_iter=1000, x0_mode=0,
-                 check_every=4, field=None, stats=False, stream=None, model=None, precond=0):
+                 check_every=4, field=None, stats=False, stream=None, model=None, precond=0, scheme="be"):
     """The whole method (Section 2.6): PCM deposition, then diffusion.
     Returns (field [F, cells], Stats or None)."""
     torch = _torch()
@@ -223,7 +230,7 @@ def coarse_grain(mesh: Mesh, pos, values, bandwidth, n_steps, rtol=1e-6, max_ite
     if field is None:
         field = torch.empty((F, mesh.cells), dtype=torch.float32, device=pos.device)
     p_field = _dev(field, torch.float32, (F, mesh.cells), "field")
-    o = _opts(rtol, max_iter, x0_mode, None, check_every, model, precond)
+    o = _opts(rtol, max_iter, x0_mode, None, check_every, model, precond, scheme)
     st = _abi.SolveStats() if stats else None
     rc = lib.cgd_coarse_grain(mesh.handle, n, p_pos, F, p_val, float(bandwidth), int(n_steps),
                               ctypes.byref(o), p_field, ctypes.byref(st) if st is not None else None,

@@ -27,7 +27,7 @@ class SolverOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("x0_mode", ctypes.c_int32), ("x0", ctypes.c_void_p),
                 ("check_every", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("model", ctypes.c_void_p)]
+                ("model", ctypes.c_void_p), ("scheme", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):

@@ -385,6 +385,11 @@ static cgd_status fill_opts(const cgd_solver_opts* o, int32_t F, float* field, d
     a->check_every = (o && o->check_every > 0) ? o->check_every : 4;
     a->model = o ? o->model : nullptr;
     a->precond = o ? o->precond : 0;
+    a->scheme = o ? o->scheme : 0;
+    if (a->scheme < 0 || a->scheme > 1) {
+        set_error(std::string(who) + ": scheme must be 0 (backward Euler) or 1 (Crank-Nicolson)");
+        return CGD_E_INVALID;
+    }
     if (a->precond < 0 || a->precond > 1) {
         set_error(std::string(who) + ": precond must be 0 (default preconditioner) or 1 (none)");
         return CGD_E_INVALID;
@@ -485,6 +490,10 @@ cgd_status cgd_coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* o
     DiffuseArgs a;
     rc = fill_opts(o, F, fields, bandwidth, n_steps, &a, "cgd_coarse_grain_batched");
     if (rc != CGD_OK) return rc;
+    if (a.scheme != 0) {
+        set_error("cgd_coarse_grain_batched: scheme must be 0 (backward Euler)");
+        return CGD_E_INVALID;
+    }
     if (a.x0_mode != 0) {
         set_error("cgd_coarse_grain_batched: x0_mode must be 0");
         return CGD_E_INVALID;

@@ -117,6 +117,11 @@ __global__ void k_cg_step_init(CgField* st, int F, int* ndone, int32_t* status_r
 // Settles the fields still running after k_end iterations, from the r.r
 // partial sums of the last sweep (rr_part: [F][slot stride] with stride).
 __global__ void k_cg_step_end(CgCtl c, const double* rr_part, size_t field_stride, int bpf, int k_end);
+
+// Crank-Nicolson from its half-step solve (Section 5.1): with
+// (M + dtau/2 K) y = M e, the step (M + dtau/2 K) e' = (M - dtau/2 K) e has
+// e' = 2 y - e.  Overwrites y [n] with 2 y - e (one rounding per element).
+void cn_extrapolate(float* y, const float* e, int64_t n, hipStream_t s);
 #endif
 
 // Host: coefficients of the polynomial preconditioner M = c0 I + c1 A + c2 A^2

@@ -37,6 +37,36 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_step_end(CgCtl c, const double*
     finish_field(c, f, status);
 }
 
+__global__ __launch_bounds__(kCgBlock) void k_cn_extrapolate(float* __restrict__ y, const float* __restrict__ e,
+                                                            int64_t n) {
+    const int64_t n4 = n / 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(e)) % 16 == 0) {
+        float4* y4 = reinterpret_cast<float4*>(y);
+        const float4* e4 = reinterpret_cast<const float4*>(e);
+        for (int64_t k = i; k < n4; k += stride) {
+            float4 a = y4[k];
+            const float4 b = e4[k];
+            a.x = fmaf(2.f, a.x, -b.x);
+            a.y = fmaf(2.f, a.y, -b.y);
+            a.z = fmaf(2.f, a.z, -b.z);
+            a.w = fmaf(2.f, a.w, -b.w);
+            y4[k] = a;
+        }
+        const int64_t t = 4 * n4 + i;  // the at most 3 elements past the last whole float4
+        if (t < n) y[t] = fmaf(2.f, y[t], -e[t]);
+        return;
+    }
+    for (int64_t k = i; k < n; k += stride) y[k] = fmaf(2.f, y[k], -e[k]);
+}
+
+void cn_extrapolate(float* y, const float* e, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t blocks = std::min<int64_t>(4096, (n / 4 + kCgBlock - 1) / kCgBlock + 1);
+    hipLaunchKernelGGL(k_cn_extrapolate, dim3((unsigned)blocks), dim3(kCgBlock), 0, s, y, e, n);
+}
+
 void poly_precond_coeffs(double cx, double cy, double cz, int deg, float* c0, float* c1, float* c2) {
     // with s = lmax + 1 and d = lmax - 1 (finite as d -> 0, where M tends to a
     // multiple of the identity):

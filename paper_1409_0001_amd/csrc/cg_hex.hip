@@ -5,7 +5,8 @@
 // Laplacian K divided by the uniform cell volume, so that A stays symmetric
 // positive definite): (A p)_k = p_k + sum_a c_a (2 p_k - p_k-1 - p_k+1) with
 // c_a = dtau / h_a^2, where a missing neighbour at a wall is replaced by p_k
-// itself (zero flux through wall faces, Section 3.2.2).
+// itself (zero flux through wall faces, Section 3.2.2).  Crank-Nicolson
+// (Section 5.1) runs the same solve with dtau / 2 and then sets x = 2 x - b.
 //
 // One CG iteration k is two streaming sweeps over the grid, 32 bytes per cell:
 //   sweep 1: p = r + beta p_old (also recomputed at neighbours), A p, p.Ap
@@ -640,24 +641,28 @@ void launch_precond_lds(int deg, int vec, bool first, const Plan& q, const Sweep
 // Degree of the LDS polynomial preconditioner with the least predicted work:
 // for degree m the residual polynomial keeps the preconditioned spectrum in
 // [1 - e, 1 + e], e = 1 / T_{m+1}(sig(0)), so CG needs about
-// k = log(2 / rtol) / log(1 / rho) iterations, rho = (sqrt(K) - 1) / (sqrt(K) + 1),
+// k = log(1 / rtol) / log(1 / rho) iterations, rho = (sqrt(K) - 1) / (sqrt(K) + 1),
 // K = (1 + e) / (1 - e); an iteration costs sweeps 1 and 2 plus one pass of
 // the LDS tile per 4 degrees, each pass about 0.43 of the two sweeps.  (The
-// bound is close for degrees 8 and 12 and pessimistic for 4, where CG's
-// superlinear convergence does better; degree 4 wins only where degree 8
-// would need as many iterations.)
+// textbook bound has log(2 / rtol); without the 2 the count matches the
+// measured iterations per step on the dense bed for degrees 4, 8 and 12 at
+// dtau / h^2 = 1 (5, 3, 2) and 1/2 (4, 2, 2), where the 2 overcounts degree
+// 4 at 1 and degree 8 at 1/2 by one.)
 int lds_degree(double cx, double cy, double cz, double rtol) {
     const double lmax = 1.0 + 4.0 * (cx + cy + cz);
     const double s0 = (lmax + 1.0) / std::max(lmax - 1.0, 1e-12);
     const double th = std::acosh(std::max(s0, 1.0 + 1e-12));
-    const double want = std::log(2.0 / std::max(rtol, 1e-300));
+    const double want = std::log(1.0 / std::max(rtol, 1e-300));
     int best = 4;
     double best_cost = 1e300;
     for (int m : {4, 8, 12}) {
         const double e = 1.0 / std::cosh(std::min((m + 1) * th, 700.0));
         const double K = (1.0 + e) / std::max(1.0 - e, 1e-300);
         const double rho = (std::sqrt(K) - 1.0) / (std::sqrt(K) + 1.0);
-        const double k = rho > 0.0 ? std::max(1.0, std::ceil(want / std::log(1.0 / rho))) : 1.0;
+        // one iteration only where the bound says so with a margin: at
+        // e near rtol the first iterate misses by a hair and takes a second
+        const double x = rho > 0.0 ? want / std::log(1.0 / rho) : 0.0;
+        const double k = x <= 0.8 ? 1.0 : std::max(2.0, std::ceil(x));
         const double cost = k * (1.0 + 0.43 * (m / 4));
         if (cost < best_cost * (1.0 - 1e-9)) {
             best_cost = cost;
@@ -811,7 +816,8 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     float* PV = Z + (size_t)F * cells;  // the degree-12 preconditioner's middle-pass output
 
     const double T = da.bandwidth * da.bandwidth / 4.0;
-    const double dtau = T / da.n_steps;
+    // Crank-Nicolson solves with half the step, then extrapolates (below)
+    const double dtau = T / da.n_steps * (da.scheme == 1 ? 0.5 : 1.0);
     SweepArgs a = {};
     a.cells = cells;
     a.nx = g.nx;
@@ -1042,6 +1048,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             int blocks = (int)std::min<int64_t>(2048, (cells + kBlock - 1) / kBlock);
             hipLaunchKernelGGL(k_zero_if_rhs_zero, dim3(blocks, F), dim3(kBlock), 0, s, nxt, cells, ctl.st);
         }
+        if (da.scheme == 1) cn_extrapolate(nxt, cur, (int64_t)F * cells, s);
         std::swap(cur, nxt);
     }
     if (cur != da.field) {

@@ -150,6 +150,7 @@ struct DiffuseArgs {
     int32_t check_every;
     int32_t precond;  // hex: 0 polynomial-preconditioned CG, 1 plain CG
     cgd_unet model;   // x0_mode 3
+    int32_t scheme;   // 0 backward Euler, 1 Crank-Nicolson (half-step solve, then 2 y - e)
 };
 cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hipStream_t s);
 

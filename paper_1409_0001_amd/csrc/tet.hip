@@ -17,6 +17,8 @@
 // mesh, or exceeds a step limit, the bucket's tets are tested in ascending
 // id order and the first hit is returned (the same definition, exhaustively).
 //
+// Crank-Nicolson (Section 5.1): the same solve with dtau / 2, then x = 2 x - e.
+//
 // Diffusion step: (M + dtau K) x = M e with M = diag(V), K the two-point-flux
 // Laplacian; Jacobi-preconditioned CG, D = diag(M + dtau K).  A p is
 // evaluated in flux form, (A p)_i = V_i p_i + dtau sum_f a_f (p_i - p_j), from
@@ -511,7 +513,8 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     float* Z = Q + fn;
     float* dinv = Z + fn;
 
-    const double dtau = da.bandwidth * da.bandwidth / 4.0 / da.n_steps;
+    // Crank-Nicolson solves with half the step, then extrapolates (below)
+    const double dtau = da.bandwidth * da.bandwidth / 4.0 / da.n_steps * (da.scheme == 1 ? 0.5 : 1.0);
     const int eblocks = std::min(4096, (n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_tet_dinv, dim3(eblocks), dim3(kBlock), 0, s, t->volf, t->kdiag, (float)dtau, dinv, n);
 
@@ -575,6 +578,7 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         // r.r of the last sweep 2: parity (it_end & 1), second slot
         hipLaunchKernelGGL(k_cg_step_end, dim3(F), dim3(kBlock), 0, s, c2,
                            d_P2 + ((size_t)(it_end & 1) * 2 + 1) * p.bpf, (size_t)4 * p.bpf, p.bpf, it_end);
+        if (da.scheme == 1) cn_extrapolate(nxt, cur, (int64_t)fn, s);
         std::swap(cur, nxt);
     }
     if (cur != da.field)
