@@ -289,6 +289,114 @@ def coarse_grain_hex(pos, values, lo, hi, shape, bandwidth, n_steps, solver="cg"
 
 
 # ---------------------------------------------------------------------------
+# Stretched (rectilinear) hex grids with a cell-wise diffusivity (Sections 4.2
+# and 5.2: stretched meshes; a small local diffusion constant degenerates the
+# method to PCM there while keeping conservation)
+# ---------------------------------------------------------------------------
+
+
+def rect_bin(pos, edges):
+    """Host cell on a rectilinear grid (Section 2.2): along each axis the
+    index i with e_i <= x < e_{i+1} (the upper cell at an interior face), a
+    point on the upper wall in the last cell.  edges: three increasing float64
+    arrays of N_a + 1 node coordinates.  Returns (cell int64 with x fastest,
+    mask of deposited particles, number of non-finite particles); points
+    outside the closed box and non-finite points are not deposited."""
+    x = np.asarray(pos, dtype=np.float64)
+    finite = np.isfinite(x).all(axis=1)
+    inside = finite.copy()
+    idx = []
+    for a in range(3):
+        e = np.asarray(edges[a], dtype=np.float64)
+        n_a = len(e) - 1
+        xa = np.where(finite, x[:, a], e[0])
+        inside &= (xa >= e[0]) & (xa <= e[-1])
+        i = np.searchsorted(e, xa, side="right") - 1
+        idx.append(np.clip(i, 0, n_a - 1).astype(np.int64))
+    nx, ny = len(edges[0]) - 1, len(edges[1]) - 1
+    cell = idx[0] + nx * (idx[1] + ny * idx[2])
+    return cell, inside, int((~finite).sum())
+
+
+def rect_volumes(edges):
+    """V_ijk = hx_i * hy_j * hz_k, evaluated left to right in float64 [cells]."""
+    hx, hy, hz = (np.diff(np.asarray(e, dtype=np.float64)) for e in edges)
+    return ((hx[None, None, :] * hy[None, :, None]) * hz[:, None, None]).ravel()
+
+
+def face_diffusivity(da, db):
+    """Diffusivity at the face between cells with da and db: the harmonic
+    mean 2 da db / (da + db), 0 when either is 0 (no flux through a face of
+    a cell that does not diffuse)."""
+    da = np.asarray(da, dtype=np.float64)
+    db = np.asarray(db, dtype=np.float64)
+    den = da + db
+    return np.where((da > 0) & (db > 0), 2.0 * da * db / np.where(den > 0, den, 1.0), 0.0)
+
+
+def rect_laplacian(edges, diffusivity=None):
+    """K with (K e)_k = sum over the interior faces f of k of
+    D_f (A_f / d_f)(e_k - e_nb): A_f the face area, d_f the distance between
+    the two cell centres, D_f = face_diffusivity of the two cells (1 when
+    diffusivity is None).  Wall faces carry no flux (Section 3.2.2)."""
+    h = [np.diff(np.asarray(e, dtype=np.float64)) for e in edges]
+    nx, ny, nz = (len(v) for v in h)
+    n = nx * ny * nz
+    D = np.ones(n) if diffusivity is None else np.asarray(diffusivity, dtype=np.float64).ravel()
+    idx = lambda i, j, k: i + nx * (j + ny * k)
+    rows, cols, vals = [], [], []
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                me = idx(i, j, k)
+                for a, (ii, jj, kk) in enumerate(((i + 1, j, k), (i, j + 1, k), (i, j, k + 1))):
+                    if ii >= nx or jj >= ny or kk >= nz:
+                        continue
+                    nb = idx(ii, jj, kk)
+                    if a == 0:
+                        area, dist = h[1][j] * h[2][k], 0.5 * (h[0][i] + h[0][ii])
+                    elif a == 1:
+                        area, dist = h[0][i] * h[2][k], 0.5 * (h[1][j] + h[1][jj])
+                    else:
+                        area, dist = h[0][i] * h[1][j], 0.5 * (h[2][k] + h[2][kk])
+                    w = float(face_diffusivity(D[me], D[nb])) * area / dist
+                    rows += [me, nb, me, nb]
+                    cols += [nb, me, me, nb]
+                    vals += [-w, -w, w, w]
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+
+
+def deposit_rect(pos, values, edges):
+    """Particle centroid method on a rectilinear grid: fixed-point sums as
+    deposit_hex, divided by each cell's own volume."""
+    values = np.atleast_2d(values)
+    cell, mask, n_nonfinite = rect_bin(pos, edges)
+    V = rect_volumes(edges)
+    acc, Ss = deposit_cells(cell, mask, values, V.size)
+    f64 = np.empty(acc.shape, dtype=np.float64)
+    f32 = np.empty(acc.shape, dtype=np.float32)
+    for f in range(acc.shape[0]):
+        f64[f], f32[f] = finalise(acc[f], Ss[f], V)
+    return dict(acc=acc, S=Ss, field64=f64, field32=f32, cell=cell, mask=mask,
+                n_dropped=int((~mask).sum()), n_nonfinite=n_nonfinite)
+
+
+def diffuse_rect(field, edges, bandwidth, n_steps, diffusivity=None, solver="cg", rtol=1e-12, scheme="be"):
+    """Diffuse cell fields [F, cells] on a rectilinear grid for T = b^2/4
+    (with the cell-wise diffusivity scaling the face fluxes)."""
+    K = rect_laplacian(edges, diffusivity)
+    return _integrator(scheme)(rect_volumes(edges), K, field, pseudo_time(bandwidth), n_steps, solver, rtol)
+
+
+def coarse_grain_rect(pos, values, edges, bandwidth, n_steps, diffusivity=None, solver="cg", rtol=1e-12,
+                      scheme="be"):
+    """Full method on a rectilinear grid: PCM, then n_steps pseudo-steps."""
+    dep = deposit_rect(pos, values, edges)
+    out = diffuse_rect(dep["field64"], edges, bandwidth, n_steps, diffusivity, solver, rtol, scheme)
+    return out, dep
+
+
+# ---------------------------------------------------------------------------
 # Second route on uniform hex grids: DCT-II diagonalisation (closed form)
 # ---------------------------------------------------------------------------
 
