@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", default="dense", choices=["dense", "batched", "unstructured", "learned"],
+    ap.add_argument("--workload", default="dense", choices=["dense", "batched", "unstructured", "learned", "stretched"],
                     help="dense: the headline metric; batched: 64 snapshots x 4 fields on 128^3 in one "
                          "persistent launch; unstructured: 100^3 x 6 jittered tets; learned: train the "
                          "initial-guess network on advected snapshots, then compare initial guesses")
@@ -240,6 +240,66 @@ def bench_unstructured(args):
     print(json.dumps(line))
 
 
+def bench_stretched(args):
+    """Stretched hex mesh with a cell-wise diffusivity: the dense-bed box and
+    particles (1 x 1 x 2, 20M particles) on 256 x 256 x 512 cells whose x
+    widths grow by 1 % per cell away from the centre plane (3.5 : 1 from the
+    centre to the walls), diffusivity 0 in the outermost cells (|x - 1/2| >
+    0.45: PCM there), b = 4/256, 4 backward-Euler steps, Jacobi-PCG rtol 1e-6."""
+    import numpy as np
+    import torch
+
+    import paper_1409_0001_amd as cgd
+    from paper_1409_0001_amd import inputs
+    t0 = time.perf_counter()
+    w = inputs.dense_bed(n_particles=args.particles, shape=(256, 256, 512), n_fields=1)
+    wx = 1.01 ** np.arange(128)
+    wx *= 0.5 / wx.sum()
+    half = np.concatenate(([0.0], np.cumsum(wx)))
+    ex = np.concatenate((0.5 - half[::-1], 0.5 + half[1:]))
+    ex[0], ex[-1] = 0.0, 1.0
+    ey, ez = np.linspace(0.0, 1.0, 257), np.linspace(0.0, 2.0, 513)
+    xc = 0.5 * (ex[1:] + ex[:-1])
+    D = np.broadcast_to((np.abs(xc - 0.5) <= 0.45).astype(np.float32), (512, 256, 256)).ravel()
+    mesh = cgd.RectMesh(ex, ey, ez, diffusivity=D)
+    print(f"[bench] stretched mesh {mesh.cells} cells, nnz {mesh.nnz}, inputs in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    pos = torch.from_numpy(w.particles.pos).cuda()
+    vals = torch.from_numpy(w.particles.values).cuda()
+    out = torch.empty((1, mesh.cells), dtype=torch.float32, device="cuda")
+    b, steps, rtol = 4.0 / 256.0, 4, args.rtol
+    for _ in range(max(1, args.warmup)):
+        _, st = cgd.coarse_grain(mesh, pos, vals, b, steps, rtol=rtol, field=out, stats=True)
+    cgd.timing_read(mesh, reset=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(args.steps):
+        if i == args.steps - 1:
+            cgd.timing_enable(mesh, True)
+        cgd.coarse_grain(mesh, pos, vals, b, steps, rtol=rtol, field=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    cgd.timing_enable(mesh, False)
+    tim = cgd.timing_read(mesh, reset=True)
+    rl = {}
+    for k in ("pcg_spmv_sweep", "pcg_update_sweep", "deposit"):
+        n, ms, bpl = tim[k]
+        if n:
+            rl[k] = {"launches": n, "avg_us": round(ms / n * 1e3, 2),
+                     "achieved_GBs": round(bpl / (ms / n * 1e-3) / 1e9, 1)}
+    line = {"metric": "coarse-grained fields/sec, stretched hex 256x256x512, 20M particles",
+            "value": round(1.0 / dt, 3), "unit": "fields/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 2), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "dense-bed particles on a 256x256x512 rectilinear mesh, x widths +1 %/cell "
+                                   "from the centre plane, diffusivity 0 where |x - 1/2| > 0.45, b=4/256, "
+                                   f"4 backward-Euler steps, Jacobi-PCG rtol {rtol:g}",
+                       "cells": int(mesh.cells), "nnz": mesh.nnz,
+                       "pcg_iters_per_step": [r[0] for r in st.iters]},
+            "kernels": rl}
+    print(json.dumps(line))
+
+
 def bench_learned(args):
     """Learned initial guess on 128^3 (unit cube, 2M particles advected by a
     divergence-free flow, b = 4h, 4 backward-Euler steps, rtol 1e-6): train
@@ -332,6 +392,8 @@ def main():
         return bench_batched(args)
     if args.workload == "unstructured":
         return bench_unstructured(args)
+    if args.workload == "stretched":
+        return bench_stretched(args)
     if args.workload == "learned":
         return bench_learned(args)
     if args.profile_copy:

@@ -77,12 +77,32 @@ cgd_status cgd_mesh_create_hex(int32_t nx, int32_t ny, int32_t nz,
 cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz,
                                int64_t n_tet, const int32_t* tv, cgd_mesh* out);
 
+/* Stretched (rectilinear) hex mesh with a cell-wise diffusivity (Section
+ * 4.2: stretched meshes; Section 5.2: a small local diffusion constant
+ * degenerates the method to PCM there, conservation kept).  x_edges, y_edges,
+ * z_edges: host float64 node coordinates, nx + 1, ny + 1, nz + 1 of them,
+ * finite and strictly increasing; cells are numbered x fastest.
+ * diffusivity: host float32 [nx * ny * nz], finite and >= 0, or NULL for 1.
+ * A particle goes to the cell with e_i <= x < e_{i+1} on each axis (the
+ * upper cell at an interior face, the last cell on the upper wall; outside
+ * the closed box: dropped); the cell density divides by the cell's own
+ * volume.  The operator is the finite-volume Laplacian with flux
+ * D_f A_f / d_f (e_P - e_N) through each interior face (A_f the face area,
+ * d_f the distance between the two cell centres, D_f the harmonic mean of
+ * the two cells' diffusivities, 0 if either is 0), stored like the tet
+ * operator with six face slots per row and solved by the same
+ * Jacobi-preconditioned CG (x0_mode 0).  nx * ny * nz < 2^28, else
+ * CGD_E_INVALID. */
+cgd_status cgd_mesh_create_rect(int32_t nx, int32_t ny, int32_t nz, const double* x_edges,
+                                const double* y_edges, const double* z_edges, const float* diffusivity,
+                                cgd_mesh* out);
+
 void    cgd_mesh_destroy(cgd_mesh m);
 int64_t cgd_mesh_num_cells(cgd_mesh m);
-/* 0 = hex, 1 = tet, -1 = NULL mesh */
+/* 0 = hex, 1 = tet, 2 = rectilinear hex, -1 = NULL mesh */
 int32_t cgd_mesh_kind(cgd_mesh m);
-/* Tet meshes: number of non-zeros of M + dtau K, n_tet + 2 x interior faces
- * (0 for hex). */
+/* Tet and rectilinear meshes: number of non-zeros of M + dtau K, cells + 2 x
+ * interior faces (0 for uniform hex). */
 int64_t cgd_mesh_nnz(cgd_mesh m);
 
 /* Learned initial-guess network (cgd_unet_create below). */

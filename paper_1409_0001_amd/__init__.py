@@ -143,6 +143,33 @@ class TetMesh(Mesh):
         self.nnz = int(lib.cgd_mesh_nnz(h))
 
 
+class RectMesh(Mesh):
+    """Stretched (rectilinear) hex mesh from its node coordinates per axis
+    (float64, strictly increasing) and an optional cell-wise diffusivity
+    (float32 [nz * ny * nx], x fastest; None: 1 everywhere)."""
+
+    def __init__(self, x_edges, y_edges, z_edges, diffusivity=None):
+        import numpy as np
+        _torch()
+        lib = _abi.load()
+        e = [np.ascontiguousarray(v, dtype=np.float64) for v in (x_edges, y_edges, z_edges)]
+        if any(v.ndim != 1 or v.size < 2 for v in e):
+            raise ValueError("edges must be 1-D with at least two nodes each")
+        n = [v.size - 1 for v in e]
+        d = None
+        if diffusivity is not None:
+            d = np.ascontiguousarray(diffusivity, dtype=np.float32).ravel()
+            if d.size != n[0] * n[1] * n[2]:
+                raise ValueError("diffusivity must hold one value per cell")
+        h = _abi.c_mesh()
+        _check(lib.cgd_mesh_create_rect(n[0], n[1], n[2], e[0].ctypes.data, e[1].ctypes.data, e[2].ctypes.data,
+                                        d.ctypes.data if d is not None else None, ctypes.byref(h)),
+               "cgd_mesh_create_rect", allow=(0,))
+        super().__init__(h)
+        self.shape = tuple(n)
+        self.nnz = int(lib.cgd_mesh_nnz(h))
+
+
 _SCHEMES = {"be": 0, "cn": 1}
 
 

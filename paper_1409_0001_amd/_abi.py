@@ -58,6 +58,9 @@ SIGNATURES = {
                                              ctypes.POINTER(c_mesh)]),
     "cgd_mesh_create_tet": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                              ctypes.c_void_p, ctypes.POINTER(c_mesh)]),
+    "cgd_mesh_create_rect": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.POINTER(c_mesh)]),
     "cgd_mesh_destroy": (None, [c_mesh]),
     "cgd_mesh_num_cells": (ctypes.c_int64, [c_mesh]),
     "cgd_mesh_kind": (ctypes.c_int32, [c_mesh]),

@@ -156,9 +156,41 @@ __device__ inline int locate(const LocArgs& g, const double* p) {
     return -1;
 }
 
+struct TetLoc {
+    LocArgs g;
+    __device__ int operator()(const double* p) const { return locate(g, p); }
+};
+
+// Rectilinear hexes (Section 2.2 with the cell given by the edges): along
+// each axis the largest i < N with e_i <= x (the upper cell at an interior
+// face, the last cell on the upper wall); -1 outside the closed box.
+struct RectLoc {
+    const double* e;  // x edges, then y, then z
+    int n[3];
+    __device__ int operator()(const double* p) const {
+        const double* ea = e;
+        int id[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int na = n[a];
+            if (!(p[a] >= ea[0] && p[a] <= ea[na])) return -1;
+            int lo = 0, hi = na - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (ea[mid] <= p[a]) lo = mid;
+                else hi = mid - 1;
+            }
+            id[a] = lo;
+            ea += na + 1;
+        }
+        return id[0] + n[0] * (id[1] + n[1] * id[2]);
+    }
+};
+
+template <class Loc>
 __global__ __launch_bounds__(kBlock) void k_locate_deposit_tet(const float* __restrict__ pos,
                                                                const float* __restrict__ values, int64_t n, int F,
-                                                               LocArgs g, int e_n, unsigned long long* __restrict__ acc,
+                                                               Loc loc, int e_n, unsigned long long* __restrict__ acc,
                                                                int64_t cells, DepositInfo* info, int32_t* cell_out) {
     __shared__ int S[CGD_MAX_FIELDS];
     if (threadIdx.x < F) S[threadIdx.x] = frac_bits_of(info->maxbits[threadIdx.x], e_n);
@@ -169,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_locate_deposit_tet(const float* __re
         const double p[3] = {(double)pos[3 * q], (double)pos[3 * q + 1], (double)pos[3 * q + 2]};
         int t = -1;
         if (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) {
-            t = locate(g, p);
+            t = loc(p);
         } else {
             ++nfpos;
         }
@@ -213,6 +245,8 @@ enum TMode { T1_FIRST = 0, T1 = 1, T2_FIRST = 2, T2 = 3 };
 struct TetArgs {
     const int4* col;      // [n]: neighbour across each face slot (own id in a boundary slot)
     const float4* kf;     // [n]: a_f per face slot (0 in a boundary slot)
+    const int2* col2;     // [n]: slots 5 and 6 (rectilinear hexes)
+    const float2* kf2;
     const float* volf;    // V (float)
     const float* dinv;    // 1 / (V + dtau K_ii)
     const float* B;       // e^n (the step's input field)
@@ -231,7 +265,7 @@ struct TetArgs {
     int k;
 };
 
-template <int MODE>
+template <int MODE, int NS>
 __global__ __launch_bounds__(kBlock) void k_tet_sweep(TetArgs a) {
     int b = blockIdx.x;
     if ((a.nblocks & 7) == 0) b = (b & 7) * (a.nblocks >> 3) + (b >> 3);
@@ -293,6 +327,13 @@ __global__ __launch_bounds__(kBlock) void k_tet_sweep(TetArgs a) {
             fl = fmaf(w.y, pi - p1, fl);
             fl = fmaf(w.z, pi - p2, fl);
             fl = fmaf(w.w, pi - p3, fl);
+            if constexpr (NS == 6) {
+                const int2 c2 = a.col2[i];
+                const float2 w2 = a.kf2[i];
+                const float p4 = pval(c2.x), p5 = pval(c2.y);
+                fl = fmaf(w2.x, pi - p4, fl);
+                fl = fmaf(w2.y, pi - p5, fl);
+            }
             const float q = fmaf(a.dtau, fl, a.volf[i] * pi);
             a.Pnew[fo + i] = pi;
             a.Q[fo + i] = q;
@@ -404,8 +445,8 @@ size_t tet_small(int F, int bpf) {
 void destroy_tet_data(cgd_mesh m) {
     TetData* t = m->tet;
     if (!t) return;
-    void* ptrs[] = {t->xyz,   t->tv,     t->vol,   t->volf,  t->bbox, t->kface,
-                    t->kdiag, t->bstart, t->blist, t->bseed, t->nbr};
+    void* ptrs[] = {t->xyz,   t->tv,     t->vol,   t->volf,  t->bbox, t->kface, t->kdiag,
+                    t->bstart, t->blist, t->bseed, t->nbr,  t->nbr2, t->kface2, t->redges};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete t;
@@ -415,12 +456,20 @@ void destroy_tet_data(cgd_mesh m) {
 int64_t tet_nnz(cgd_mesh m) { return m->tet ? m->tet->nnz : 0; }
 
 namespace {
-__global__ __launch_bounds__(kBlock) void k_locate_tet(const float* __restrict__ pos, int64_t n, LocArgs g,
+template <class Loc>
+__global__ __launch_bounds__(kBlock) void k_locate_tet(const float* __restrict__ pos, int64_t n, Loc loc,
                                                        int32_t* __restrict__ cell) {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         const double p[3] = {(double)pos[3 * q], (double)pos[3 * q + 1], (double)pos[3 * q + 2]};
-        cell[q] = (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) ? locate(g, p) : -1;
+        cell[q] = (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) ? loc(p) : -1;
     }
+}
+
+RectLoc rect_loc(const TetData* t) {
+    RectLoc r;
+    r.e = t->redges;
+    for (int a = 0; a < 3; ++a) r.n[a] = t->rdim[a];
+    return r;
 }
 
 LocArgs loc_args(const TetData* t) {
@@ -445,7 +494,11 @@ LocArgs loc_args(const TetData* t) {
 cgd_status locate_tet(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hipStream_t s) {
     if (n > 0) {
         const int blocks = (int)std::min<int64_t>(16384, (n + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(k_locate_tet, dim3(blocks), dim3(kBlock), 0, s, pos, n, loc_args(m->tet), cell);
+        if (m->tet->ns == 6)
+            hipLaunchKernelGGL(k_locate_tet<RectLoc>, dim3(blocks), dim3(kBlock), 0, s, pos, n, rect_loc(m->tet), cell);
+        else
+            hipLaunchKernelGGL(k_locate_tet<TetLoc>, dim3(blocks), dim3(kBlock), 0, s, pos, n,
+                               TetLoc{loc_args(m->tet)}, cell);
     }
     CGD_HIP_TRY(hipGetLastError());
     return CGD_OK;
@@ -464,11 +517,15 @@ cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
     const int e_n = ceil_log2_count(n);
     deposit_prologue(n, F, values, acc, cells, info, s);
     if (n > 0) {
-        const LocArgs g = loc_args(t);
         const int blocks = (int)std::min<int64_t>(16384, (n + kBlock - 1) / kBlock);
         int tm = timing_begin(&m->timing, s);
-        hipLaunchKernelGGL(k_locate_deposit_tet, dim3(blocks), dim3(kBlock), 0, s, pos, values, n, F, g, e_n,
-                           reinterpret_cast<unsigned long long*>(acc), cells, info, nullptr);
+        if (t->ns == 6)
+            hipLaunchKernelGGL(k_locate_deposit_tet<RectLoc>, dim3(blocks), dim3(kBlock), 0, s, pos, values, n, F,
+                               rect_loc(t), e_n, reinterpret_cast<unsigned long long*>(acc), cells, info, nullptr);
+        else
+            hipLaunchKernelGGL(k_locate_deposit_tet<TetLoc>, dim3(blocks), dim3(kBlock), 0, s, pos, values, n, F,
+                               TetLoc{loc_args(t)}, e_n, reinterpret_cast<unsigned long long*>(acc), cells, info,
+                               nullptr);
         timing_end(&m->timing, tm, 2, (12.0 + 12.0 * F) * (double)n, s);
     }
     const int blocks = (int)std::min<int64_t>(8192, (cells + kBlock - 1) / kBlock);
@@ -521,6 +578,8 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     TetArgs a = {};
     a.col = reinterpret_cast<const int4*>(t->nbr);
     a.kf = reinterpret_cast<const float4*>(t->kface);
+    a.col2 = reinterpret_cast<const int2*>(t->nbr2);
+    a.kf2 = reinterpret_cast<const float2*>(t->kface2);
     a.volf = t->volf;
     a.dinv = dinv;
     a.dtau = (float)dtau;
@@ -540,9 +599,27 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         hipLaunchKernelGGL(k_tet_mass, dim3(mbpf, F), dim3(kBlock), 0, s, da.field, t->vol, n, d_mpart, mbpf);
         hipLaunchKernelGGL(k_tet_sum_finish, dim3(F), dim3(kBlock), 0, s, d_mpart, mbpf, d_sums);
     }
-    const double b1 = 52.0 * n;  // sweep 1, one field: ids, a_f, z, p_old, V; writes p, q
+    // sweep 1, one field: ids, a_f, z, p_old, V; writes p, q (6 face slots: 16 more)
+    const double b1 = (t->ns == 6 ? 68.0 : 52.0) * n;
     const double b2 = 32.0 * n;  // sweep 2, one field: p, q, x, r, D^-1; writes x, r, z
     const dim3 grid(p.nblocks), block(kBlock);
+    auto sweep = [&](int mode) {
+        if (t->ns == 6) {
+            switch (mode) {
+                case T1_FIRST: hipLaunchKernelGGL((k_tet_sweep<T1_FIRST, 6>), grid, block, 0, s, a); break;
+                case T2_FIRST: hipLaunchKernelGGL((k_tet_sweep<T2_FIRST, 6>), grid, block, 0, s, a); break;
+                case T1: hipLaunchKernelGGL((k_tet_sweep<T1, 6>), grid, block, 0, s, a); break;
+                default: hipLaunchKernelGGL((k_tet_sweep<T2, 6>), grid, block, 0, s, a); break;
+            }
+        } else {
+            switch (mode) {
+                case T1_FIRST: hipLaunchKernelGGL((k_tet_sweep<T1_FIRST, 4>), grid, block, 0, s, a); break;
+                case T2_FIRST: hipLaunchKernelGGL((k_tet_sweep<T2_FIRST, 4>), grid, block, 0, s, a); break;
+                case T1: hipLaunchKernelGGL((k_tet_sweep<T1, 4>), grid, block, 0, s, a); break;
+                default: hipLaunchKernelGGL((k_tet_sweep<T2, 4>), grid, block, 0, s, a); break;
+            }
+        }
+    };
     float* cur = da.field;
     float* nxt = W0;
     for (int step = 0; step < da.n_steps; ++step) {
@@ -554,19 +631,19 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         a.k = 0;
         a.Pnew = PA;
         a.Pold = PB;
-        hipLaunchKernelGGL(k_tet_sweep<T1_FIRST>, grid, block, 0, s, a);
-        hipLaunchKernelGGL(k_tet_sweep<T2_FIRST>, grid, block, 0, s, a);
+        sweep(T1_FIRST);
+        sweep(T2_FIRST);
         auto enqueue = [&](int it, int* host_flags) {
             a.k = it;
             a.Pold = (it & 1) ? PA : PB;
             a.Pnew = (it & 1) ? PB : PA;
             const int64_t tag = (int64_t)step * 65536 + it;
             int t1 = timing_begin(&m->timing, s);
-            hipLaunchKernelGGL(k_tet_sweep<T1>, grid, block, 0, s, a);
+            sweep(T1);
             timing_end(&m->timing, t1, 3, b1 * F, s, tag);
             a.c.host_flags = host_flags;
             int t2 = timing_begin(&m->timing, s);
-            hipLaunchKernelGGL(k_tet_sweep<T2>, grid, block, 0, s, a);
+            sweep(T2);
             timing_end(&m->timing, t2, 4, b2 * F, s, tag);
             a.c.host_flags = nullptr;
         };
@@ -653,6 +730,139 @@ extern "C" cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz, int
         if (hipEventCreateWithFlags(&m->ev[i], hipEventDisableTiming) != hipSuccess) {
             cgd_mesh_destroy(m);
             set_error("cgd_mesh_create_tet: hipEventCreate failed");
+            return CGD_E_HIP;
+        }
+    }
+    *out = m;
+    return CGD_OK;
+}
+
+// Rectilinear (stretched) hex meshes with a cell-wise diffusivity: the padded
+// rows of the tet solver with 6 face slots.  Face coefficient between cells a
+// and b along an axis: D_f A_f / d_f with A_f the face area, d_f the distance
+// between the two cell centres and D_f = 2 D_a D_b / (D_a + D_b) (0 when
+// either is 0), evaluated in float64 and rounded once; volumes
+// (hx_i hy_j) hz_k in float64.
+extern "C" cgd_status cgd_mesh_create_rect(int32_t nx, int32_t ny, int32_t nz, const double* x_edges,
+                                           const double* y_edges, const double* z_edges, const float* diffusivity,
+                                           cgd_mesh* out) {
+    if (!out || !x_edges || !y_edges || !z_edges) {
+        set_error("cgd_mesh_create_rect: null pointer");
+        return CGD_E_INVALID;
+    }
+    *out = nullptr;
+    const int32_t dims[3] = {nx, ny, nz};
+    const double* edges[3] = {x_edges, y_edges, z_edges};
+    if (nx < 1 || ny < 1 || nz < 1 || (int64_t)nx * ny * nz >= (int64_t(1) << 28)) {
+        set_error("cgd_mesh_create_rect: need n_a >= 1 and nx * ny * nz < 2^28");
+        return CGD_E_INVALID;
+    }
+    for (int a = 0; a < 3; ++a) {
+        for (int i = 0; i <= dims[a]; ++i) {
+            if (!std::isfinite(edges[a][i]) || (i > 0 && !(edges[a][i] > edges[a][i - 1]))) {
+                set_error("cgd_mesh_create_rect: edges must be finite and strictly increasing");
+                return CGD_E_INVALID;
+            }
+        }
+    }
+    const int64_t n = (int64_t)nx * ny * nz;
+    std::vector<double> hw[3], hd, vol, redges;
+    std::vector<float> volf, kface, kface2, kdiag, D;
+    std::vector<int32_t> nbr, nbr2;
+    try {
+        if (diffusivity) {
+            D.assign(diffusivity, diffusivity + n);
+            for (float d : D) {
+                if (!std::isfinite(d) || d < 0.f) {
+                    set_error("cgd_mesh_create_rect: diffusivity must be finite and >= 0");
+                    return CGD_E_INVALID;
+                }
+            }
+        }
+        for (int a = 0; a < 3; ++a) {
+            for (int i = 0; i < dims[a]; ++i) hw[a].push_back(edges[a][i + 1] - edges[a][i]);
+            redges.insert(redges.end(), edges[a], edges[a] + dims[a] + 1);
+        }
+        vol.resize(n);
+        volf.resize(n);
+        kface.assign((size_t)n * 4, 0.f);
+        kface2.assign((size_t)n * 2, 0.f);
+        kdiag.assign(n, 0.f);
+        nbr.resize((size_t)n * 4);
+        nbr2.resize((size_t)n * 2);
+    } catch (const std::bad_alloc&) {
+        set_error("cgd_mesh_create_rect: host allocation failed");
+        return CGD_E_NOMEM;
+    }
+    auto dcell = [&](int64_t k) { return D.empty() ? 1.0 : (double)D[k]; };
+    int64_t faces = 0;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int64_t me = i + (int64_t)nx * (j + (int64_t)ny * k);
+                vol[me] = (hw[0][i] * hw[1][j]) * hw[2][k];
+                volf[me] = (float)vol[me];
+                const int c[3] = {i, j, k};
+                const int64_t stride[3] = {1, nx, (int64_t)nx * ny};
+                double diag = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double area = hw[(a + 1) % 3][c[(a + 1) % 3]] * hw[(a + 2) % 3][c[(a + 2) % 3]];
+                    for (int side = 0; side < 2; ++side) {  // 0: lower neighbour, 1: upper
+                        const int slot = 2 * a + side;
+                        const int cn = c[a] + (side ? 1 : -1);
+                        int64_t nb = me;
+                        double w = 0.0;
+                        if (cn >= 0 && cn < dims[a]) {
+                            nb = me + (side ? stride[a] : -stride[a]);
+                            const double da = dcell(me), db = dcell(nb);
+                            const double df = (da > 0.0 && db > 0.0) ? 2.0 * da * db / (da + db) : 0.0;
+                            w = df * area / (0.5 * (hw[a][c[a]] + hw[a][cn]));
+                            if (side) ++faces;
+                        }
+                        if (slot < 4) {
+                            nbr[(size_t)me * 4 + slot] = (int32_t)nb;
+                            kface[(size_t)me * 4 + slot] = (float)w;
+                        } else {
+                            nbr2[(size_t)me * 2 + slot - 4] = (int32_t)nb;
+                            kface2[(size_t)me * 2 + slot - 4] = (float)w;
+                        }
+                        diag += w;
+                    }
+                }
+                kdiag[me] = (float)diag;
+            }
+    cgd_mesh m = new (std::nothrow) cgd_mesh_s();
+    if (!m) return CGD_E_NOMEM;
+    m->kind = 2;
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        set_error("cgd_mesh_create_rect: no HIP device");
+        return CGD_E_HIP;
+    }
+    m->cells = n;
+    m->tet = new (std::nothrow) TetData();
+    if (!m->tet) {
+        delete m;
+        return CGD_E_NOMEM;
+    }
+    TetData* t = m->tet;
+    t->n_tet = (int32_t)n;
+    t->nnz = n + 2 * faces;
+    t->ns = 6;
+    for (int a = 0; a < 3; ++a) t->rdim[a] = dims[a];
+    std::vector<cgd_status> st = {upload(vol, &t->vol),       upload(volf, &t->volf),   upload(kface, &t->kface),
+                                  upload(kface2, &t->kface2), upload(kdiag, &t->kdiag), upload(nbr, &t->nbr),
+                                  upload(nbr2, &t->nbr2),     upload(redges, &t->redges)};
+    for (cgd_status r : st) {
+        if (r != CGD_OK) {
+            cgd_mesh_destroy(m);
+            return r;
+        }
+    }
+    for (int i = 0; i < 2; ++i) {
+        if (hipEventCreateWithFlags(&m->ev[i], hipEventDisableTiming) != hipSuccess) {
+            cgd_mesh_destroy(m);
+            set_error("cgd_mesh_create_rect: hipEventCreate failed");
             return CGD_E_HIP;
         }
     }

@@ -42,6 +42,13 @@ struct TetData {
     int32_t* blist = nullptr;
     int32_t* bseed = nullptr;
     int32_t* nbr = nullptr;     // [n_tet][4]: the padded rows' column indices
+    // Rectilinear hex meshes use the same padded rows with 6 face slots: the
+    // first four in nbr / kface (-x, +x, -y, +y), the last two here (-z, +z).
+    int32_t ns = 4;             // face slots per row: 4 (tets) or 6 (rectilinear hexes)
+    int32_t* nbr2 = nullptr;    // [n][2]
+    float* kface2 = nullptr;    // [n][2]
+    int32_t rdim[3] = {0, 0, 0};
+    double* redges = nullptr;   // node coordinates: x (rdim[0] + 1), then y, then z
 };
 
 cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tv, TetHost* out);

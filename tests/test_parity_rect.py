@@ -1,0 +1,134 @@
+"""GPU parity of stretched (rectilinear) hex meshes with a cell-wise
+diffusivity against the oracle (through the C-ABI).
+
+Binning and deposition are bit-exact (cell ids, int64 sums, float32 fields:
+both sides compare float64 coordinates with the float64 edges and divide by
+the same float64 volume).  Diffusion: relative L2 <= 1e-5 per field against
+float64, mass conserved to the solver tolerance, cells with zero diffusivity
+left at their PCM values.
+"""
+import numpy as np
+import pytest
+
+from oracle import cgd_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-5
+
+
+def _t(a, torch):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _stretched(n_half, ratio, lo, length):
+    w = ratio ** np.arange(n_half)
+    w *= (0.5 * length) / w.sum()
+    half = np.concatenate(([0.0], np.cumsum(w)))
+    e = lo + np.concatenate((0.5 * length - half[::-1], 0.5 * length + half[1:]))
+    e[0], e[-1] = lo, lo + length
+    return e
+
+
+def _mesh_case(seed, shape_y, shape_z):
+    rng = np.random.default_rng(seed)
+    ex = _stretched(20, 1.04, -0.3, 1.1)                       # 40 cells, refined at the centre
+    ey = np.concatenate(([0.1], 0.1 + np.cumsum(rng.random(shape_y) + 0.3) / 40))  # random widths
+    ez = np.linspace(2.0, 2.6, shape_z + 1)
+    return [ex, ey, ez]
+
+
+@pytest.mark.parametrize("seed,ny,nz", [(71, 23, 17), (72, 1, 9)])
+def test_rect_locate_and_deposit_bit_exact(gpu_lib, seed, ny, nz):
+    import torch
+    cgd = gpu_lib
+    e = _mesh_case(seed, ny, nz)
+    rng = np.random.default_rng(seed + 100)
+    lo = np.array([v[0] for v in e])
+    hi = np.array([v[-1] for v in e])
+    pos = (lo + (hi - lo) * rng.uniform(-0.05, 1.05, (30_000, 3))).astype(np.float32)
+    for a in range(3):  # on faces and walls (float32-representable edges only)
+        k = 100 * a
+        cand = e[a][e[a].astype(np.float32).astype(np.float64) == e[a]]
+        if cand.size:
+            pos[k:k + 100, a] = rng.choice(cand, 100)
+    pos[300:303] = [[np.nan, 0.2, 2.1], [0.1, np.inf, 2.2], [0.0, 0.2, 9.0]]
+    vals = np.stack([np.full(len(pos), 3.3e-8, np.float32), rng.normal(size=len(pos)).astype(np.float32)])
+    print(f"case: rect locate/deposit seed {seed} shape {[len(v) - 1 for v in e]}", flush=True)
+    mesh = cgd.RectMesh(*e)
+    assert mesh.kind == 2 and mesh.cells == 40 * ny * nz
+    cell = cgd.locate(mesh, _t(pos, torch)).cpu().numpy()
+    ref_cell, ref_mask, _ = O.rect_bin(pos.astype(np.float64), e)
+    assert np.array_equal(cell, np.where(ref_mask, ref_cell, -1))
+    acc = torch.empty((2, mesh.cells), dtype=torch.int64, device="cuda")
+    field, st = cgd.deposit(mesh, _t(pos, torch), _t(vals, torch), acc=acc, stats=True)
+    ref = O.deposit_rect(pos, vals, e)
+    assert st.n_dropped == ref["n_dropped"]
+    assert np.array_equal(acc.cpu().numpy(), ref["acc"])
+    assert np.array_equal(field.cpu().numpy().view(np.uint32), ref["field32"].view(np.uint32))
+
+
+@pytest.mark.parametrize("scheme", ["be", "cn"])
+@pytest.mark.parametrize("steps", [1, 4])
+def test_rect_coarse_grain_matches_oracle(gpu_lib, scheme, steps):
+    import torch
+    cgd = gpu_lib
+    e = _mesh_case(73, 23, 17)
+    n = 40 * 23 * 17
+    rng = np.random.default_rng(74)
+    D = (0.5 + rng.random(n)).astype(np.float32)
+    D.reshape(17, 23, 40)[:5, :, :7] = 0.0  # a corner block degenerates to PCM (Section 5.2)
+    lo = np.array([v[0] for v in e])
+    hi = np.array([v[-1] for v in e])
+    pos = (lo + (hi - lo) * rng.random((40_000, 3))).astype(np.float32)
+    vals = np.stack([np.full(len(pos), 3.3e-8, np.float32), rng.normal(size=len(pos)).astype(np.float32)])
+    b = 0.12
+    print(f"case: rect coarse_grain {scheme} {steps} steps", flush=True)
+    mesh = cgd.RectMesh(*e, diffusivity=D)
+    out, st = cgd.coarse_grain(mesh, _t(pos, torch), _t(vals, torch), b, steps, rtol=1e-7, stats=True,
+                               scheme=scheme)
+    ref, dep = O.coarse_grain_rect(pos, vals, e, b, steps, diffusivity=D.astype(np.float64), solver="direct",
+                                   scheme=scheme)
+    o = out.cpu().numpy()
+    V = O.rect_volumes(e)
+    frozen = D == 0
+    for f in range(2):
+        assert rel_l2(o[f], ref[f]) <= REL_L2, (f, rel_l2(o[f], ref[f]))
+        m0 = (dep["field64"][f] * V).sum()
+        assert abs(st.mass_after[f] - m0) <= 1e-5 * np.abs(dep["field64"][f] * V).sum()
+        pcm = dep["field64"][f][frozen]
+        assert np.abs(o[f][frozen] - pcm).max() <= 1e-5 * np.abs(dep["field64"][f]).max()
+    assert st.status == 0
+    assert mesh.nnz == n + 2 * (39 * 23 * 17 + 40 * 22 * 17 + 40 * 23 * 16)
+
+
+def test_rect_stretched_2d_and_invalid(gpu_lib):
+    """The paper's stretched mesh shape (90 x 45, ratio 1.04 towards the
+    centre line) with unit diffusivity, against the oracle; invalid edges and
+    diffusivities are refused."""
+    import torch
+    cgd = gpu_lib
+    ex = _stretched(45, 1.04, 0.0, 1.0)
+    ey = np.linspace(0, 0.5, 46)
+    ez = np.array([0.0, 0.02])
+    rng = np.random.default_rng(75)
+    pos = np.column_stack([rng.random(50_000), 0.5 * rng.random(50_000), 0.02 * rng.random(50_000)]).astype(np.float32)
+    vals = np.full((1, len(pos)), 1e-6, np.float32)
+    b = 4 * np.diff(ex).max()
+    print("case: rect 90x45 stretched", flush=True)
+    mesh = cgd.RectMesh(ex, ey, ez)
+    out, st = cgd.coarse_grain(mesh, _t(pos, torch), _t(vals, torch), b, 4, rtol=1e-7, stats=True)
+    ref, _ = O.coarse_grain_rect(pos, vals, [ex, ey, ez], b, 4, solver="direct")
+    assert rel_l2(out.cpu().numpy()[0], ref[0]) <= REL_L2
+    with pytest.raises(cgd.CgdError):
+        cgd.RectMesh(np.array([0.0, 0.5, 0.5, 1.0]), ey, ez)       # not strictly increasing
+    with pytest.raises(cgd.CgdError):
+        cgd.RectMesh(ex, ey, ez, diffusivity=np.full(90 * 45, -1.0))  # negative diffusivity
+    with pytest.raises(cgd.CgdError):
+        cgd.RectMesh(ex, ey, np.array([0.0, np.nan]))
