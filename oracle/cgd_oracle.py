@@ -334,11 +334,14 @@ def face_diffusivity(da, db):
     return np.where((da > 0) & (db > 0), 2.0 * da * db / np.where(den > 0, den, 1.0), 0.0)
 
 
-def rect_laplacian(edges, diffusivity=None):
+def rect_laplacian(edges, diffusivity=None, periodic=(False, False, False)):
     """K with (K e)_k = sum over the interior faces f of k of
     D_f (A_f / d_f)(e_k - e_nb): A_f the face area, d_f the distance between
     the two cell centres, D_f = face_diffusivity of the two cells (1 when
-    diffusivity is None).  Wall faces carry no flux (Section 3.2.2)."""
+    diffusivity is None).  Wall faces carry no flux (Section 3.2.2), except
+    on a periodic axis (Section 3.2.2: periodic conditions there), where the
+    first and last cells share a face at distance (h_first + h_last) / 2
+    (for two cells on that axis, a second face between the same pair)."""
     h = [np.diff(np.asarray(e, dtype=np.float64)) for e in edges]
     nx, ny, nz = (len(v) for v in h)
     n = nx * ny * nz
@@ -351,7 +354,9 @@ def rect_laplacian(edges, diffusivity=None):
                 me = idx(i, j, k)
                 for a, (ii, jj, kk) in enumerate(((i + 1, j, k), (i, j + 1, k), (i, j, k + 1))):
                     if ii >= nx or jj >= ny or kk >= nz:
-                        continue
+                        if not periodic[a] or (nx, ny, nz)[a] < 2:
+                            continue
+                        ii, jj, kk = ii % nx, jj % ny, kk % nz  # the face across the periodic boundary
                     nb = idx(ii, jj, kk)
                     if a == 0:
                         area, dist = h[1][j] * h[2][k], 0.5 * (h[0][i] + h[0][ii])
@@ -381,19 +386,30 @@ def deposit_rect(pos, values, edges):
                 n_dropped=int((~mask).sum()), n_nonfinite=n_nonfinite)
 
 
-def diffuse_rect(field, edges, bandwidth, n_steps, diffusivity=None, solver="cg", rtol=1e-12, scheme="be"):
+def diffuse_rect(field, edges, bandwidth, n_steps, diffusivity=None, solver="cg", rtol=1e-12, scheme="be",
+                 periodic=(False, False, False)):
     """Diffuse cell fields [F, cells] on a rectilinear grid for T = b^2/4
     (with the cell-wise diffusivity scaling the face fluxes)."""
-    K = rect_laplacian(edges, diffusivity)
+    K = rect_laplacian(edges, diffusivity, periodic)
     return _integrator(scheme)(rect_volumes(edges), K, field, pseudo_time(bandwidth), n_steps, solver, rtol)
 
 
 def coarse_grain_rect(pos, values, edges, bandwidth, n_steps, diffusivity=None, solver="cg", rtol=1e-12,
-                      scheme="be"):
+                      scheme="be", periodic=(False, False, False)):
     """Full method on a rectilinear grid: PCM, then n_steps pseudo-steps."""
     dep = deposit_rect(pos, values, edges)
-    out = diffuse_rect(dep["field64"], edges, bandwidth, n_steps, diffusivity, solver, rtol, scheme)
+    out = diffuse_rect(dep["field64"], edges, bandwidth, n_steps, diffusivity, solver, rtol, scheme, periodic)
     return out, dep
+
+
+def velocity_from_momentum(eps, mom, eps_min):
+    """Momentum-consistent velocity (Section 6: diffuse the momentum, not the
+    velocity): U = (eps U) / eps for each component where eps > eps_min, 0
+    elsewhere.  eps [cells] and mom [n_comp, cells] are diffused fields."""
+    eps = np.asarray(eps, dtype=np.float64)
+    mom = np.atleast_2d(np.asarray(mom, dtype=np.float64))
+    ok = eps > eps_min
+    return np.where(ok[None, :], mom / np.where(ok, eps, 1.0)[None, :], 0.0)
 
 
 # ---------------------------------------------------------------------------

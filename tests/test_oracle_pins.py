@@ -656,3 +656,55 @@ def test_stretched_mesh_profile_matches_uniform_mesh():
     inner = (xs > xu[0]) & (xs < xu[-1])
     rel = np.abs(prof_s - prof_u)[inner].max() / np.abs(prof_u).max()
     assert rel < 0.01, rel  # 0.18 % with this seed
+
+
+# ---------------------------------------------------------------- periodic axes, momentum-consistent velocity
+
+
+def test_periodic_axis_fourier_modes_and_translation():
+    """Section 3.2.2: a periodic axis.  On a uniform periodic 1-D grid
+    K / V has the Fourier modes cos(2 pi k (i + 1/2) / n) as eigenvectors with
+    eigenvalues (4 / h^2) sin^2(pi k / n); diffusing a shifted field equals
+    shifting the diffused field; mass is conserved."""
+    n, L = 12, 1.8
+    h = L / n
+    e = [np.linspace(0, L, n + 1), np.array([0.0, 1.0]), np.array([0.0, 1.0])]
+    K = O.rect_laplacian(e, periodic=(True, False, False)).toarray() / h
+    i = np.arange(n)
+    for k in range(n // 2 + 1):
+        v = np.cos(2 * np.pi * k * (i + 0.5) / n)
+        assert np.allclose(K @ v, (4 / h ** 2) * np.sin(np.pi * k / n) ** 2 * v, atol=1e-10)
+    rng = np.random.default_rng(26)
+    f = rng.random(n)
+    g = O.diffuse_rect(f, e, 0.4, 3, solver="direct", periodic=(True, False, False))
+    g5 = O.diffuse_rect(np.roll(f, 5), e, 0.4, 3, solver="direct", periodic=(True, False, False))
+    assert np.allclose(g5, np.roll(g, 5), rtol=1e-12)
+    assert abs(g.sum() - f.sum()) < 1e-13 * f.sum()
+    # two cells on a periodic axis: the pair shares two faces
+    e2 = [np.array([0.0, 1.0, 3.0]), np.array([0.0, 1.0]), np.array([0.0, 1.0])]
+    K2 = O.rect_laplacian(e2, periodic=(True, False, False)).toarray()
+    assert np.allclose(K2, 2 * O.rect_laplacian(e2).toarray())
+
+
+def test_momentum_route_recovers_uniform_velocity_and_conserves_momentum():
+    """Section 6: coarse grain the particle volume and volume times velocity,
+    then divide.  A uniform particle velocity comes back exactly wherever
+    eps > 0, and sum V eps U equals the particles' total momentum.  Diffusing
+    the PCM velocity itself (0 in empty cells) does not give it back."""
+    e = [np.linspace(0, 1, 13), np.linspace(0, 0.5, 7), np.array([0.0, 0.1])]
+    rng = np.random.default_rng(27)
+    pos = np.column_stack([0.45 * rng.random(3000), 0.5 * rng.random(3000), 0.1 * rng.random(3000)])
+    vol = np.full(3000, 2e-6)
+    u0 = np.array([0.3, -1.2])
+    vals = np.vstack([vol, vol * u0[0], vol * u0[1]])
+    out, dep = O.coarse_grain_rect(pos, vals, e, 0.2, 3, solver="direct")
+    U = O.velocity_from_momentum(out[0], out[1:], 0.0)
+    ok = out[0] > 0
+    assert np.allclose(U[:, ok], u0[:, None], rtol=1e-12)
+    V = O.rect_volumes(e)
+    for c in range(2):
+        assert abs((V * out[0] * U[c]).sum() - (vol * u0[c]).sum()) <= 1e-10 * abs((vol * u0[c]).sum())
+    pcm_u = O.velocity_from_momentum(dep["field64"][0], dep["field64"][1:], 0.0)
+    smoothed_u = O.diffuse_rect(pcm_u, e, 0.2, 3, solver="direct")
+    assert np.abs(smoothed_u[0][ok] - u0[0]).max() > 0.05
+    assert np.array_equal(O.velocity_from_momentum(out[0], out[1:], 1e30), np.zeros_like(out[1:]))
