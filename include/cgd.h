@@ -91,11 +91,14 @@ cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz,
  * d_f the distance between the two cell centres, D_f the harmonic mean of
  * the two cells' diffusivities, 0 if either is 0), stored like the tet
  * operator with six face slots per row and solved by the same
- * Jacobi-preconditioned CG (x0_mode 0).  nx * ny * nz < 2^28, else
+ * Jacobi-preconditioned CG (x0_mode 0).  periodic: bit a set makes axis a
+ * (0 x, 1 y, 2 z) periodic (Section 3.2.2): its first and last cells share a
+ * face at distance (h_first + h_last) / 2 instead of two walls (no effect on
+ * an axis of one cell); binning is unchanged.  nx * ny * nz < 2^28, else
  * CGD_E_INVALID. */
 cgd_status cgd_mesh_create_rect(int32_t nx, int32_t ny, int32_t nz, const double* x_edges,
                                 const double* y_edges, const double* z_edges, const float* diffusivity,
-                                cgd_mesh* out);
+                                int32_t periodic, cgd_mesh* out);
 
 void    cgd_mesh_destroy(cgd_mesh m);
 int64_t cgd_mesh_num_cells(cgd_mesh m);
@@ -226,6 +229,19 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F,
                             const float* values, double bandwidth, int32_t n_steps,
                             const cgd_solver_opts* o, float* field,
                             cgd_solve_stats* st, void* stream);
+
+/* Momentum-consistent velocity (Section 6: the diffusion acts on the
+ * momentum, not on the velocity).  Coarse grain F = 1 + n_comp fields
+ * (particle volume, then volume times each velocity component) and divide:
+ * mom[c][k] = mom[c][k] / eps[k] where eps[k] > eps_min, else 0 (one float32
+ * division, correctly rounded).
+ *  cells:  cells of the fields; n_comp: 1..CGD_MAX_FIELDS - 1
+ *  eps:    device float32 [cells], the diffused solid volume fraction
+ *  mom:    device float32 [n_comp, cells], in: diffused eps U; out: U
+ *  eps_min: finite, >= 0
+ * Enqueued on `stream`; CGD_E_INVALID for bad sizes or null pointers. */
+cgd_status cgd_velocity_from_momentum(int64_t cells, int32_t n_comp, const float* eps, float* mom,
+                                      float eps_min, void* stream);
 
 /* Batched coarse graining of n_snap independent snapshots on one hex mesh
  * (each snapshot its own particles; F fields each, e.g. solid volume plus

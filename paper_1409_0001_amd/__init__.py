@@ -146,9 +146,10 @@ class TetMesh(Mesh):
 class RectMesh(Mesh):
     """Stretched (rectilinear) hex mesh from its node coordinates per axis
     (float64, strictly increasing) and an optional cell-wise diffusivity
-    (float32 [nz * ny * nx], x fastest; None: 1 everywhere)."""
+    (float32 [nz * ny * nx], x fastest; None: 1 everywhere).  periodic:
+    three booleans, one per axis (Section 3.2.2)."""
 
-    def __init__(self, x_edges, y_edges, z_edges, diffusivity=None):
+    def __init__(self, x_edges, y_edges, z_edges, diffusivity=None, periodic=(False, False, False)):
         import numpy as np
         _torch()
         lib = _abi.load()
@@ -163,7 +164,8 @@ class RectMesh(Mesh):
                 raise ValueError("diffusivity must hold one value per cell")
         h = _abi.c_mesh()
         _check(lib.cgd_mesh_create_rect(n[0], n[1], n[2], e[0].ctypes.data, e[1].ctypes.data, e[2].ctypes.data,
-                                        d.ctypes.data if d is not None else None, ctypes.byref(h)),
+                                        d.ctypes.data if d is not None else None,
+                                        sum(1 << a for a in range(3) if periodic[a]), ctypes.byref(h)),
                "cgd_mesh_create_rect", allow=(0,))
         super().__init__(h)
         self.shape = tuple(n)
@@ -186,6 +188,20 @@ def _opts(rtol, max_iter, x0_mode, x0, check_every, model=None, precond=0, schem
     o.check_every = int(check_every)
     o.model = model.handle if model is not None else None
     return o
+
+
+def velocity_from_momentum(eps, mom, eps_min=1e-6, stream=None):
+    """Momentum-consistent velocity (Section 6: diffuse the momentum, not the
+    velocity): mom [n_comp, cells] (diffused eps U) becomes U = mom / eps
+    where eps [cells] > eps_min, 0 elsewhere, in place.  Returns mom."""
+    torch = _torch()
+    lib = _abi.load()
+    cells = int(eps.shape[-1])
+    p_eps = _dev(eps, torch.float32, (cells,), "eps")
+    p_mom = _dev(mom, torch.float32, (int(mom.shape[0]), cells), "mom")
+    _check(lib.cgd_velocity_from_momentum(cells, int(mom.shape[0]), p_eps, p_mom, float(eps_min),
+                                          _stream_ptr(stream)), "cgd_velocity_from_momentum")
+    return mom
 
 
 def locate(mesh: Mesh, pos, cell=None, stream=None):

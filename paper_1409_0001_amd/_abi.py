@@ -60,7 +60,7 @@ SIGNATURES = {
                                              ctypes.c_void_p, ctypes.POINTER(c_mesh)]),
     "cgd_mesh_create_rect": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                              ctypes.POINTER(c_mesh)]),
+                                              ctypes.c_int32, ctypes.POINTER(c_mesh)]),
     "cgd_mesh_destroy": (None, [c_mesh]),
     "cgd_mesh_num_cells": (ctypes.c_int64, [c_mesh]),
     "cgd_mesh_kind": (ctypes.c_int32, [c_mesh]),
@@ -81,6 +81,8 @@ SIGNATURES = {
                                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
                                                   ctypes.c_int32, ctypes.POINTER(SolverOpts), ctypes.c_void_p,
                                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "cgd_velocity_from_momentum": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                                    ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
     "cgd_autotune_batched": (ctypes.c_int32, [c_mesh, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                               ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "cgd_unet_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,

@@ -526,4 +526,17 @@ cgd_status cgd_autotune_batched(cgd_mesh m, int32_t n_rhs, int32_t* chosen, doub
     return CGD_OK;
 }
 
+cgd_status cgd_velocity_from_momentum(int64_t cells, int32_t n_comp, const float* eps, float* mom,
+                                      float eps_min, void* stream) {
+    if (cells < 0 || n_comp < 1 || n_comp > CGD_MAX_FIELDS - 1 || (cells > 0 && (!eps || !mom)) ||
+        !isfinite(eps_min) || eps_min < 0.f) {
+        set_error("cgd_velocity_from_momentum: need cells >= 0, 1 <= n_comp < CGD_MAX_FIELDS, eps, mom and a "
+                  "finite eps_min >= 0");
+        return CGD_E_INVALID;
+    }
+    velocity_from_momentum(cells, n_comp, eps, mom, eps_min, static_cast<hipStream_t>(stream));
+    CGD_HIP_TRY(hipGetLastError());
+    return CGD_OK;
+}
+
 }  // extern "C"

@@ -67,6 +67,28 @@ void cn_extrapolate(float* y, const float* e, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_cn_extrapolate, dim3((unsigned)blocks), dim3(kCgBlock), 0, s, y, e, n);
 }
 
+__global__ __launch_bounds__(kCgBlock) void k_velocity_from_momentum(int64_t cells, int n_comp,
+                                                                    const float* __restrict__ eps,
+                                                                    float* __restrict__ mom, float eps_min) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < cells; k += stride) {
+        const float e = eps[k];
+        const bool ok = e > eps_min;
+        for (int c = 0; c < n_comp; ++c) {
+            float* m = mom + (size_t)c * cells + k;
+            *m = ok ? *m / e : 0.f;
+        }
+    }
+}
+
+void velocity_from_momentum(int64_t cells, int n_comp, const float* eps, float* mom, float eps_min,
+                            hipStream_t s) {
+    if (cells <= 0) return;
+    const int64_t blocks = std::min<int64_t>(8192, (cells + kCgBlock - 1) / kCgBlock);
+    hipLaunchKernelGGL(k_velocity_from_momentum, dim3((unsigned)blocks), dim3(kCgBlock), 0, s, cells, n_comp, eps,
+                       mom, eps_min);
+}
+
 void poly_precond_coeffs(double cx, double cy, double cz, int deg, float* c0, float* c1, float* c2) {
     // with s = lmax + 1 and d = lmax - 1 (finite as d -> 0, where M tends to a
     // multiple of the identity):

@@ -154,6 +154,10 @@ struct DiffuseArgs {
 };
 cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hipStream_t s);
 
+// mom[c][k] /= eps[k] where eps[k] > eps_min, else 0 (cg_common.hip).
+void velocity_from_momentum(int64_t cells, int n_comp, const float* eps, float* mom, float eps_min,
+                            hipStream_t s);
+
 // Bytes of workspace the hex diffusion needs for F fields.
 size_t diffuse_hex_workspace(const cgd_mesh m, int32_t F);
 

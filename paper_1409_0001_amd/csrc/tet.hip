@@ -742,10 +742,11 @@ extern "C" cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz, int
 // and b along an axis: D_f A_f / d_f with A_f the face area, d_f the distance
 // between the two cell centres and D_f = 2 D_a D_b / (D_a + D_b) (0 when
 // either is 0), evaluated in float64 and rounded once; volumes
-// (hx_i hy_j) hz_k in float64.
+// (hx_i hy_j) hz_k in float64.  On a periodic axis the first and last cells
+// share a face at distance (h_first + h_last) / 2 (Section 3.2.2).
 extern "C" cgd_status cgd_mesh_create_rect(int32_t nx, int32_t ny, int32_t nz, const double* x_edges,
                                            const double* y_edges, const double* z_edges, const float* diffusivity,
-                                           cgd_mesh* out) {
+                                           int32_t periodic, cgd_mesh* out) {
     if (!out || !x_edges || !y_edges || !z_edges) {
         set_error("cgd_mesh_create_rect: null pointer");
         return CGD_E_INVALID;
@@ -755,6 +756,10 @@ extern "C" cgd_status cgd_mesh_create_rect(int32_t nx, int32_t ny, int32_t nz, c
     const double* edges[3] = {x_edges, y_edges, z_edges};
     if (nx < 1 || ny < 1 || nz < 1 || (int64_t)nx * ny * nz >= (int64_t(1) << 28)) {
         set_error("cgd_mesh_create_rect: need n_a >= 1 and nx * ny * nz < 2^28");
+        return CGD_E_INVALID;
+    }
+    if (periodic & ~7) {
+        set_error("cgd_mesh_create_rect: periodic is a mask of bits 0 (x), 1 (y), 2 (z)");
         return CGD_E_INVALID;
     }
     for (int a = 0; a < 3; ++a) {
@@ -809,11 +814,13 @@ extern "C" cgd_status cgd_mesh_create_rect(int32_t nx, int32_t ny, int32_t nz, c
                     const double area = hw[(a + 1) % 3][c[(a + 1) % 3]] * hw[(a + 2) % 3][c[(a + 2) % 3]];
                     for (int side = 0; side < 2; ++side) {  // 0: lower neighbour, 1: upper
                         const int slot = 2 * a + side;
-                        const int cn = c[a] + (side ? 1 : -1);
+                        int cn = c[a] + (side ? 1 : -1);
+                        if ((cn < 0 || cn >= dims[a]) && ((periodic >> a) & 1) && dims[a] >= 2)
+                            cn = (cn + dims[a]) % dims[a];  // the face across the periodic boundary
                         int64_t nb = me;
                         double w = 0.0;
                         if (cn >= 0 && cn < dims[a]) {
-                            nb = me + (side ? stride[a] : -stride[a]);
+                            nb = me + (int64_t)(cn - c[a]) * stride[a];
                             const double da = dcell(me), db = dcell(nb);
                             const double df = (da > 0.0 && db > 0.0) ? 2.0 * da * db / (da + db) : 0.0;
                             w = df * area / (0.5 * (hw[a][c[a]] + hw[a][cn]));

@@ -132,3 +132,71 @@ def test_rect_stretched_2d_and_invalid(gpu_lib):
         cgd.RectMesh(ex, ey, ez, diffusivity=np.full(90 * 45, -1.0))  # negative diffusivity
     with pytest.raises(cgd.CgdError):
         cgd.RectMesh(ex, ey, np.array([0.0, np.nan]))
+
+
+@pytest.mark.parametrize("scheme", ["be", "cn"])
+def test_rect_periodic_matches_oracle(gpu_lib, scheme):
+    """Periodic x and z (Section 3.2.2) on a stretched grid, against the
+    oracle; mass conserved."""
+    import torch
+    cgd = gpu_lib
+    e = _mesh_case(76, 11, 9)
+    rng = np.random.default_rng(77)
+    lo = np.array([v[0] for v in e])
+    hi = np.array([v[-1] for v in e])
+    pos = (lo + (hi - lo) * rng.random((20_000, 3))).astype(np.float32)
+    pos[:5000, 0] = (lo[0] + 0.02 * (hi[0] - lo[0]) * rng.random(5000)).astype(np.float32)  # load one wall
+    vals = np.stack([np.full(len(pos), 1e-6, np.float32), rng.normal(size=len(pos)).astype(np.float32)])
+    per = (True, False, True)
+    print(f"case: rect periodic x,z {scheme}", flush=True)
+    mesh = cgd.RectMesh(*e, periodic=per)
+    out, st = cgd.coarse_grain(mesh, _t(pos, torch), _t(vals, torch), 0.15, 3, rtol=1e-7, stats=True,
+                               scheme=scheme)
+    ref, dep = O.coarse_grain_rect(pos, vals, e, 0.15, 3, solver="direct", scheme=scheme, periodic=per)
+    o = out.cpu().numpy()
+    V = O.rect_volumes(e)
+    for f in range(2):
+        assert rel_l2(o[f], ref[f]) <= REL_L2, (f, rel_l2(o[f], ref[f]))
+        m0 = (dep["field64"][f] * V).sum()
+        assert abs(st.mass_after[f] - m0) <= 1e-5 * np.abs(dep["field64"][f] * V).sum()
+    # mass crossed the periodic x boundary: the last x cells gained from the loaded first ones
+    walled, _ = O.coarse_grain_rect(pos, vals, e, 0.15, 3, solver="direct", scheme=scheme)
+    last = o[0].reshape(9, 11, 40)[:, :, -1].sum()
+    assert last > 1.5 * walled[0].reshape(9, 11, 40)[:, :, -1].sum()
+
+
+def test_velocity_from_momentum_bit_exact_and_uniform_flow(gpu_lib):
+    import torch
+    cgd = gpu_lib
+    rng = np.random.default_rng(78)
+    cells = 100_003
+    eps = rng.random(cells).astype(np.float32)
+    eps[:1000] = 0.0
+    eps[1000:1100] = 1e-7
+    mom = rng.normal(size=(3, cells)).astype(np.float32)
+    print("case: velocity from momentum, elementwise", flush=True)
+    m = _t(mom, torch)
+    cgd.velocity_from_momentum(_t(eps, torch), m, eps_min=1e-6)
+    ok = eps > np.float32(1e-6)
+    ref = np.where(ok[None, :], (mom.astype(np.float64) / np.where(ok, eps, 1).astype(np.float64)), 0.0)
+    assert np.array_equal(m.cpu().numpy().view(np.uint32), ref.astype(np.float32).view(np.uint32))
+    # the whole route: a uniform particle velocity comes back where eps > eps_min
+    e = _mesh_case(79, 13, 7)
+    lo = np.array([v[0] for v in e])
+    hi = np.array([v[-1] for v in e])
+    pos = (lo + (hi - lo) * rng.random((30_000, 3)) * [0.5, 1, 1]).astype(np.float32)
+    vol = np.full(len(pos), 2e-7, np.float32)
+    u0 = np.array([0.3, -1.2, 0.05], np.float32)
+    vals = np.vstack([vol, vol * u0[0], vol * u0[1], vol * u0[2]]).astype(np.float32)
+    print("case: velocity from momentum, uniform flow on a stretched mesh", flush=True)
+    mesh = cgd.RectMesh(*e)
+    out, _ = cgd.coarse_grain(mesh, _t(pos, torch), _t(vals, torch), 0.1, 3, rtol=1e-7, stats=True)
+    eps_min = 1e-3 * float(out[0].max())
+    U = cgd.velocity_from_momentum(out[0].contiguous(), out[1:].contiguous(), eps_min=eps_min).cpu().numpy()
+    sel = out[0].cpu().numpy() > eps_min
+    assert sel.sum() > 100
+    for c in range(3):
+        assert np.abs(U[c][sel] - u0[c]).max() <= 1e-3 * abs(float(u0[c])) + 1e-6, c
+        assert (U[c][~sel] == 0).all()
+    with pytest.raises(cgd.CgdError):
+        cgd.velocity_from_momentum(_t(eps, torch), _t(mom, torch), eps_min=-1.0)
