@@ -127,8 +127,9 @@ typedef struct {
                              quadratic factors each), the one with the least work predicted
                              from the Chebyshev bound on the iteration count, where one
                              wavefront covers an x-row (nx = 64, 128 or 256) and the grid
-                             fills the machine, else degree 2 or 1; 1 plain CG.  Tet meshes
-                             use Jacobi either way.  The stopping rule is the same for all. */
+                             fills the machine, else degree 2 or 1; 1 plain CG.  Tet and
+                             rectilinear meshes use Jacobi either way.  The stopping rule is
+                             the same for all. */
     cgd_unet model;       /* x0_mode 3: a network created for this mesh's grid, else NULL */
     int32_t scheme;       /* pseudo-time integrator (Section 5.1): 0 (default) backward Euler,
                              each step solving (M + dtau K) e^{n+1} = M e^n; 1 Crank-Nicolson,
