@@ -6,7 +6,8 @@
 // positive definite): (A p)_k = p_k + sum_a c_a (2 p_k - p_k-1 - p_k+1) with
 // c_a = dtau / h_a^2, where a missing neighbour at a wall is replaced by p_k
 // itself (zero flux through wall faces, Section 3.2.2).  Crank-Nicolson
-// (Section 5.1) runs the same solve with dtau / 2 and then sets x = 2 x - b.
+// (Section 5.1) runs the same solve with dtau / 2 and takes 2 x - b: from a
+// zero guess the x updates carry it, after a guess a pass sets it.
 //
 // One CG iteration k is two streaming sweeps over the grid, 32 bytes per cell:
 //   sweep 1: p = r + beta p_old (also recomputed at neighbours), A p, p.Ap
@@ -816,7 +817,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     float* PV = Z + (size_t)F * cells;  // the degree-12 preconditioner's middle-pass output
 
     const double T = da.bandwidth * da.bandwidth / 4.0;
-    // Crank-Nicolson solves with half the step, then extrapolates (below)
+    // Crank-Nicolson solves with half the step and extrapolates (below)
     const double dtau = T / da.n_steps * (da.scheme == 1 ? 0.5 : 1.0);
     SweepArgs a = {};
     a.cells = cells;
@@ -943,6 +944,12 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
                            ctl.status + step * CGD_MAX_FIELDS);
         const bool use_x0 = (da.x0_mode == 1) || (da.x0_mode == 2 && step == 0) || da.x0_mode == 3;
         a.x0_zero = use_x0 ? 0 : 1;
+        // Crank-Nicolson from a zero guess: the x updates carry the
+        // extrapolation (x = 2 y - b at every iterate); from a guess, a pass
+        // after the solve does
+        const bool cn_fused = da.scheme == 1 && !use_x0;
+        a.g.xs1 = cn_fused ? 1.f : 0.f;
+        a.g.xb = cn_fused ? -1.f : 0.f;
         int it0;
         a.k = 0;
         if (!use_x0 && pcg) {
@@ -1048,7 +1055,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             int blocks = (int)std::min<int64_t>(2048, (cells + kBlock - 1) / kBlock);
             hipLaunchKernelGGL(k_zero_if_rhs_zero, dim3(blocks, F), dim3(kBlock), 0, s, nxt, cells, ctl.st);
         }
-        if (da.scheme == 1) cn_extrapolate(nxt, cur, (int64_t)F * cells, s);
+        if (da.scheme == 1 && !cn_fused) cn_extrapolate(nxt, cur, (int64_t)F * cells, s);
         std::swap(cur, nxt);
     }
     if (cur != da.field) {

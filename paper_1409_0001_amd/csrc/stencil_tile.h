@@ -52,6 +52,10 @@ struct Geom {
     int nx, ny, nz;
     float cx, cy, cz;
     float c0, c1, c2;   // preconditioner M = c0 I + c1 A + c2 A^2
+    // Crank-Nicolson folded into the x updates of a zero-guess solve: x
+    // advances by (1 + xs1) alpha p from xb b, so that with xs1 = 1, xb = -1
+    // the iterate is 2 y - b when y solves the half step (0, 0: plain x)
+    float xs1, xb;
 };
 
 template <int VEC>
@@ -195,9 +199,10 @@ __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t 
                 }
             } else if constexpr (MODE == S2_FIRST) {
                 Vec<VEC> xn, rn;
+                const float ax = fmaf(g.xs1, alpha, alpha);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
-                    xn.f[e] = alpha * c.f[e];
+                    xn.f[e] = fmaf(ax, c.f[e], g.xb * c.f[e]);
                     rn.f[e] = fmaf(-alpha, ap.f[e], c.f[e]);
                 }
                 if (valid) {
@@ -209,9 +214,10 @@ __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t 
             } else if constexpr (MODE == S2) {
                 Vec<VEC> xv = ldv<VEC>(p.X + i);
                 Vec<VEC> rv = ldv<VEC>(p.R + i);
+                const float ax = fmaf(g.xs1, alpha, alpha);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
-                    xv.f[e] = fmaf(alpha, c.f[e], xv.f[e]);
+                    xv.f[e] = fmaf(ax, c.f[e], xv.f[e]);
                     rv.f[e] = fmaf(-alpha, ap.f[e], rv.f[e]);
                 }
                 if (valid) {
@@ -235,9 +241,10 @@ __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t 
             } else if constexpr (MODE == S2P_FIRST) {
                 const Vec<VEC> bv = ldv<VEC>(p.B + i);
                 Vec<VEC> xn, rn;
+                const float ax = fmaf(g.xs1, alpha, alpha);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
-                    xn.f[e] = alpha * c.f[e];
+                    xn.f[e] = fmaf(ax, c.f[e], g.xb * bv.f[e]);
                     rn.f[e] = fmaf(-alpha, ap.f[e], bv.f[e]);
                 }
                 if (valid) {
