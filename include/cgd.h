@@ -135,10 +135,10 @@ typedef struct {
                              each step solving (M + dtau K) e^{n+1} = M e^n; 1 Crank-Nicolson,
                              (M + dtau/2 K) e^{n+1} = (M - dtau/2 K) e^n, computed as the
                              half-step solve (M + dtau/2 K) y = M e^n (same solvers, stopping
-                             rule on y) followed by e^{n+1} = 2 y - e^n.  Crank-Nicolson
+                             rule on y) followed by e^{n+1} = 2 y - e^n (on hex meshes from
+                             a zero guess the CG's x updates carry it).  Crank-Nicolson
                              conserves mass but, unlike backward Euler, is not positivity
-                             preserving at large dtau / h^2.  cgd_coarse_grain_batched: 0
-                             only.  Other values: CGD_E_INVALID. */
+                             preserving at large dtau / h^2.  Other values: CGD_E_INVALID. */
 } cgd_solver_opts;
 
 typedef struct {
@@ -266,7 +266,7 @@ cgd_status cgd_velocity_from_momentum(int64_t cells, int32_t n_comp, const float
  *  pos:     device float32 [offsets[n_snap], 3]
  *  values:  device float32 [F, offsets[n_snap]]
  *  fields:  device float32 [n_snap, F, cells], written
- *  o:       rtol / max_iter / precond as in cgd_diffuse; x0_mode must be 0
+ *  o:       rtol / max_iter / precond / scheme as in cgd_diffuse; x0_mode must be 0
  *  iters:   HOST int32 [n_snap, F, n_steps] or NULL: CG iterations
  * Hex meshes with nx in {64, 128, 256} only (CGD_E_UNSUPPORTED otherwise).
  * The call waits for its stream before returning. */

@@ -283,7 +283,7 @@ def coarse_grain(mesh: Mesh, pos, values, bandwidth, n_steps, rtol=1e-6, max_ite
 
 
 def coarse_grain_batched(mesh: HexMesh, offsets, pos, values, bandwidth, n_steps, rtol=1e-6, max_iter=1000,
-                         fields=None, return_iters=False, stream=None, precond=0):
+                         fields=None, return_iters=False, stream=None, precond=0, scheme="be"):
     """All snapshots at once.  offsets: host int64 [S + 1]; pos [N, 3]; values
     [F, N].  Returns fields [S, F, cells] (and iterations [S, F, n_steps])."""
     import numpy as np
@@ -299,7 +299,7 @@ def coarse_grain_batched(mesh: HexMesh, offsets, pos, values, bandwidth, n_steps
     if fields is None:
         fields = torch.empty((n_snap, F, mesh.cells), dtype=torch.float32, device=pos.device)
     p_f = _dev(fields, torch.float32, (n_snap, F, mesh.cells), "fields")
-    o = _opts(rtol, max_iter, 0, None, 4, precond=precond)
+    o = _opts(rtol, max_iter, 0, None, 4, precond=precond, scheme=scheme)
     iters = np.zeros((n_snap, F, n_steps), dtype=np.int32)
     rc = _abi.load().cgd_coarse_grain_batched(mesh.handle, n_snap, off.ctypes.data, p_pos, F, p_val,
                                               float(bandwidth), int(n_steps), ctypes.byref(o), p_f,

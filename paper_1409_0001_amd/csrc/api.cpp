@@ -490,10 +490,6 @@ cgd_status cgd_coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* o
     DiffuseArgs a;
     rc = fill_opts(o, F, fields, bandwidth, n_steps, &a, "cgd_coarse_grain_batched");
     if (rc != CGD_OK) return rc;
-    if (a.scheme != 0) {
-        set_error("cgd_coarse_grain_batched: scheme must be 0 (backward Euler)");
-        return CGD_E_INVALID;
-    }
     if (a.x0_mode != 0) {
         set_error("cgd_coarse_grain_batched: x0_mode must be 0");
         return CGD_E_INVALID;

@@ -758,9 +758,13 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     for (int j = 0; j < n_snap; ++j) max_n = std::max(max_n, offsets[j + 1] - offsets[j]);
     const int chunks = (int)std::max<int64_t>(1, (max_n + kChunk - 1) / kChunk);
 
-    const double dtau = da.bandwidth * da.bandwidth / 4.0 / da.n_steps;
+    // Crank-Nicolson: the half-step solve, its extrapolation carried by the
+    // x updates (every right-hand side starts from a zero guess)
+    const double dtau = da.bandwidth * da.bandwidth / 4.0 / da.n_steps * (da.scheme == 1 ? 0.5 : 1.0);
     BSolve a = {};
     a.fields = fields;
+    a.g.xs1 = da.scheme == 1 ? 1.f : 0.f;
+    a.g.xb = da.scheme == 1 ? -1.f : 0.f;
     a.ws = static_cast<float*>(big);
     a.n_rhs = n_rhs;
     a.cells = (int64_t)cells;
@@ -827,10 +831,10 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     const bool use_graph = getenv("CGD_NO_GRAPH") == nullptr;
     if (use_graph) {
         char keybuf[512];
-        snprintf(keybuf, sizeof keybuf, "%p %p %p %d %d %lld %d %d %.17g %.17g %d %d %p %zu %p %d %d",
+        snprintf(keybuf, sizeof keybuf, "%p %p %p %d %d %lld %d %d %.17g %.17g %d %d %p %zu %p %d %d %d",
                  (const void*)pos, (const void*)values, (void*)fields, n_snap, F, (long long)total, chunks,
                  da.n_steps, da.bandwidth, da.rtol, da.max_iter, ci, m->ws.ptr, m->ws.bytes, m->pinned, a.pcg,
-                 (int)tiled);
+                 (int)tiled, da.scheme);
         std::lock_guard<std::mutex> lk(g_graph_mu);
         BatchedGraph& bg = g_graphs[m];
         if (bg.key != keybuf || !bg.exec) {

@@ -200,3 +200,28 @@ def test_batched_invalid(gpu_lib):
     mesh = cgd.HexMesh((64, 8, 8))
     with pytest.raises(cgd.CgdError):
         cgd.coarse_grain_batched(mesh, [0, 6, 4, 10], pos, vals, 0.1, 2)  # decreasing offsets
+
+
+def test_batched_crank_nicolson_matches_oracle_and_graph_key(gpu_lib):
+    """Crank-Nicolson in the persistent launch (the x updates carry the
+    extrapolation) against the oracle's CN closed form, after a backward-Euler
+    call with the same arguments: the captured graph must not be replayed
+    across schemes."""
+    import torch
+    cgd = gpu_lib
+    shape = (64, 40, 36)
+    counts = [15_000, 9_000, 1]
+    box, parts, pos, vals, off = _batch(shape, counts, seed=91)
+    b, steps = 4.0 / shape[0], 3
+    print(f"case: batched CN {shape} snapshots {counts}", flush=True)
+    mesh = cgd.HexMesh(shape, box.lo, box.hi)
+    args = (mesh, off, _t(pos, torch), _t(vals, torch), b, steps)
+    be = cgd.coarse_grain_batched(*args, rtol=1e-7).cpu().numpy()
+    cn = cgd.coarse_grain_batched(*args, rtol=1e-7, scheme="cn").cpu().numpy()
+    for j, p in enumerate(parts):
+        dep = O.deposit_hex(p.pos, p.values, box.lo, box.hi, shape)
+        ref_cn = O.diffuse_hex_dct(dep["field64"], box.lo, box.hi, shape, b, steps, scheme="cn")
+        ref_be = O.diffuse_hex_dct(dep["field64"], box.lo, box.hi, shape, b, steps)
+        for f in range(4):
+            assert rel_l2(cn[j, f], ref_cn[f]) <= REL_L2, (j, f, rel_l2(cn[j, f], ref_cn[f]))
+            assert rel_l2(be[j, f], ref_be[f]) <= REL_L2, (j, f)

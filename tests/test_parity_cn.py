@@ -150,9 +150,9 @@ def test_cn_tet_matches_oracle(gpu_lib, n_hex, jitter, steps):
     assert st.status == 0
 
 
-def test_cn_invalid_scheme_and_batched_refuses(gpu_lib):
-    """Through the C-ABI: a scheme other than 0 or 1 is CGD_E_INVALID, and the
-    batched entry point takes backward Euler only."""
+def test_cn_invalid_scheme(gpu_lib):
+    """Through the C-ABI: a scheme other than 0 or 1 is CGD_E_INVALID, in the
+    single and the batched entry points."""
     import torch
     from paper_1409_0001_amd import _abi
     cgd = gpu_lib
@@ -163,7 +163,6 @@ def test_cn_invalid_scheme_and_batched_refuses(gpu_lib):
     o = _abi.SolverOpts()
     o.rtol, o.max_iter, o.scheme = 1e-6, 100, 2
     assert lib.cgd_diffuse(mesh.handle, 1, f.data_ptr(), 0.2, 2, ctypes.byref(o), None, None) == _abi.E_INVALID
-    o.scheme = 1
     offsets = (ctypes.c_int64 * 2)(0, 0)
     assert lib.cgd_coarse_grain_batched(mesh.handle, 1, ctypes.cast(offsets, ctypes.c_void_p), None, 1, None,
                                         0.2, 2, ctypes.byref(o), f.data_ptr(), None, None) == _abi.E_INVALID
