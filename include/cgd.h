@@ -173,8 +173,10 @@ cgd_status cgd_locate(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, vo
  * lowest id on ties).  Its value v of field f is quantised to
  * q = rint(v * 2^S_f) (int64, round half to even) with S_f = 62 - e_max - e_N
  * (max_p |v_p| <= 2^e_max over finite values, e_N = ceil(log2 n)), so that no
- * sum can overflow, and summed in int64: the sums are exact and independent
- * of particle order.  Then field[f, k] = float32(acc * 2^-S_f / V_k).  On hex
+ * sum can overflow, or with a scale S_f the caller forces, and summed in
+ * int64: the sums are exact and independent of particle order (eq.
+ * conserve holds exactly in the integers).  Then
+ * field[f, k] = float32(acc * 2^-S_f / V_k).  On hex
  * meshes the particles are bucketed by tile of consecutive cells and each
  * tile is summed in LDS (the temporary buffers, 8 + 4 F bytes per
  * particle, come from the mesh workspace); with more than 8192 tiles or 2^32
@@ -187,14 +189,22 @@ cgd_status cgd_locate(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, vo
  *  values:  device float32 [F, n]
  *  field:   device float32 [F, cells], written
  *  acc:     device int64 [F, cells] (written: the raw fixed-point sums) or NULL
+ *  frac_bits: host int32 [F] or NULL (all automatic).  In: -1 for the
+ *           automatic S_f above, or a scale 0..62 to force (other values:
+ *           CGD_E_INVALID, nothing enqueued).  A forced scale is the caller's
+ *           promise that |v| 2^S_f < 2^62 for every value and that every
+ *           cell's sum of |q| stays below 2^63; the library does not check it
+ *           (beyond it the int64 sums wrap).  Out: the scale used per field;
+ *           when any entry was -1 the call waits for the stream to read it.
  *  st:      host, nullable.  Non-NULL makes the call wait for the stream and
  *           fill frac_bits / n_dropped / n_nonfinite; the call then returns
  *           CGD_E_NONFINITE if any non-finite position or value was seen.
- *           With st == NULL the call is asynchronous and non-finite particles
- *           are skipped silently. */
+ *           With st == NULL the call does not report them and non-finite
+ *           particles are skipped silently; with st == NULL and no
+ *           automatic scale requested through frac_bits it is asynchronous. */
 cgd_status cgd_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F,
                        const float* values, float* field, int64_t* acc,
-                       cgd_solve_stats* st, void* stream);
+                       int32_t* frac_bits, cgd_solve_stats* st, void* stream);
 
 /* Diffusion of F cell fields in place (Sections 3.1, 3.2, 5.1).
  *
@@ -267,13 +277,19 @@ cgd_status cgd_velocity_from_momentum(int64_t cells, int32_t n_comp, const float
  *  values:  device float32 [F, offsets[n_snap]]
  *  fields:  device float32 [n_snap, F, cells], written
  *  o:       rtol / max_iter / precond / scheme as in cgd_diffuse; x0_mode must be 0
- *  iters:   HOST int32 [n_snap, F, n_steps] or NULL: CG iterations
+ *  st:      HOST cgd_solve_stats [n_snap] or NULL: per snapshot, as cgd_coarse_grain
+ *           reports for one call: CG iterations and ||r|| / ||b|| per step and
+ *           field, mass before and after diffusion per field (sum_k V field_k,
+ *           float64; their difference is bounded by the stopping rule), the
+ *           fixed-point scale of each field, dropped and non-finite particles,
+ *           and the snapshot's worst status (n_fallback 0).  Asking for st adds
+ *           two float64 sums over all fields to the launch.
  * Hex meshes with nx in {64, 128, 256} only (CGD_E_UNSUPPORTED otherwise).
  * The call waits for its stream before returning. */
 cgd_status cgd_coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offsets,
                                     const float* pos, int32_t F, const float* values,
                                     double bandwidth, int32_t n_steps, const cgd_solver_opts* o,
-                                    float* fields, int32_t* iters, void* stream);
+                                    float* fields, cgd_solve_stats* st, void* stream);
 
 /* Autotuner of the batched solver: times each candidate (rows per wave,
  * waves per workgroup, preconditioner degree 2, 4 or 12) solving n_rhs synthetic
@@ -361,16 +377,28 @@ cgd_status cgd_conv3_wgrad(int32_t nx, int32_t ny, int32_t nz, int32_t ci, int32
  * stream (events without a system-scope fence, so that timing stalls the
  * queue as little as possible); the elapsed times are collected when the
  * call synchronises (every cgd_diffuse / cgd_coarse_grain does at its end).
- * Kinds:
- *   0  CG sweep 1 (p = r + beta p_old, A p, p.Ap), hex stencil
+ * Kinds (one kernel each unless stated):
+ *   0  CG sweep 1 (p = z + beta p_old, A p, p.Ap), hex stencil
  *   1  CG sweep 2 (x += alpha p, r -= alpha A p, r.r), hex stencil
- *   2  hex deposit: centroid binning, bucketing and fixed-point sums
- *   3  matrix sweep of the tet Jacobi-PCG (p, A p, p.Ap)
- *   4  update sweep of the tet Jacobi-PCG (x, r, r.z, r.r)
- *   5  hex preconditioning sweep (z = M r, r.z)
+ *   2  whole deposit: centroid binning, bucketing and fixed-point sums
+ *      (all kernels of a call; kinds 13..15 split the tiled hex path)
+ *   3  matrix sweep of the Jacobi-PCG on face slots (p, A p, p.Ap)
+ *   4  update sweep of the Jacobi-PCG (x, r, r.z, r.r)
+ *   5  hex preconditioning, degree-4 Horner pass or first product pass
+ *      (r -> U), degree 1 / 2 register sweep
+ *   6  hex preconditioning, middle product pass (U -> V, degree 12)
+ *   7  hex preconditioning, last product pass (V -> z, r.z)
+ *   8  first iteration of a step, direction sweep (p.Ap with p = z)
+ *   9  first iteration of a step, update sweep (x = alpha p, r = b - alpha A p)
+ *  10  first iteration, kind 5's pass reading b (b.b as well)
+ *  11  first iteration, kind 6's pass
+ *  12  first iteration, kind 7's pass
+ *  13  tiled hex deposit: binning and tile counts
+ *  14  tiled hex deposit: prefix sum and scatter of records into tiles
+ *  15  tiled hex deposit: fixed-point sums in LDS and the finished field
  * bytes_per_launch is the algorithmic byte count of the last timed launch of
  * that kind (what the method must move, not what the hardware moved). */
-#define CGD_TIMING_KINDS 8
+#define CGD_TIMING_KINDS 16
 typedef struct {
     int64_t launches[CGD_TIMING_KINDS];
     double  total_ms[CGD_TIMING_KINDS];

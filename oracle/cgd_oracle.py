@@ -106,20 +106,22 @@ def quantise(values_row, S):
     return np.rint(np.ldexp(np.asarray(values_row, dtype=np.float64), S)).astype(np.int64)
 
 
-def deposit_cells(cell, mask, values, n_cells):
+def deposit_cells(cell, mask, values, n_cells, force_bits=None):
     """Fixed-point PCM sums: acc[f, k] = sum over particles in cell k of q_f.
 
     Returns (acc int64 [F, n_cells], S list).  Integer sums: exact, so the
     result does not depend on the particle order (eq. conserve holds exactly
     in the integers).  A particle whose value of field f is not finite is
-    left out of field f.
+    left out of field f.  force_bits: None, or per field a scale to use
+    instead of frac_bits (None or -1 in an entry: the automatic one).
     """
     values = np.atleast_2d(values)
     F, n = values.shape
     acc = np.zeros((F, n_cells), dtype=np.int64)
     Ss = []
     for f in range(F):
-        S = frac_bits(values[f], n)
+        forced = None if force_bits is None else force_bits[f]
+        S = frac_bits(values[f], n) if forced is None or forced < 0 else int(forced)
         Ss.append(S)
         sel = np.nonzero(mask & np.isfinite(values[f]))[0]
         q = quantise(values[f, sel], S)
@@ -133,17 +135,18 @@ def finalise(acc, S, volume):
     return f64, f64.astype(np.float32)
 
 
-def deposit_hex(pos, values, lo, hi, shape):
+def deposit_hex(pos, values, lo, hi, shape, force_bits=None):
     """Particle centroid method on a uniform hex grid.
 
     Returns dict with acc [F, cells] int64, S per field, field64 / field32
     [F, cells] (densities: sum of values in the cell over the cell volume),
-    and counts of dropped / non-finite particles.
+    and counts of dropped / non-finite particles.  force_bits: see
+    deposit_cells.
     """
     values = np.atleast_2d(values)
     nx, ny, nz = shape
     cell, mask, n_nonfinite = bin_hex(pos, lo, hi, shape)
-    acc, Ss = deposit_cells(cell, mask, values, nx * ny * nz)
+    acc, Ss = deposit_cells(cell, mask, values, nx * ny * nz, force_bits)
     V = hex_cell_volume(lo, hi, shape)
     f64 = np.empty(acc.shape, dtype=np.float64)
     f32 = np.empty(acc.shape, dtype=np.float32)

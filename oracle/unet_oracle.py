@@ -17,7 +17,9 @@ kernels are checked against:
 - 2x2x2 average pooling, nearest 2x upsampling, channel concatenation, the
   1x1x1 head and ReLU;
 - the whole 3-level U-Net (16/32/64 channels) with the residual output
-  y = x + head(...), written layer by layer.
+  y = x + head(...), written layer by layer;
+- one step of the Adam optimiser (Kingma and Ba, "Adam: a method for
+  stochastic optimization", ICLR 2015, Algorithm 1), which trains it.
 """
 from __future__ import annotations
 
@@ -241,3 +243,20 @@ def bf16_round(a):
     u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
     return u.astype(np.uint32).view(np.float32).reshape(np.shape(a))
+
+
+def adam_step(params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Step t (1, 2, ...) of Adam, Kingma and Ba (2015), Algorithm 1, in float64.
+
+    m <- beta1 m + (1 - beta1) g;  v <- beta2 v + (1 - beta2) g^2;
+    m_hat = m / (1 - beta1^t);  v_hat = v / (1 - beta2^t);
+    params <- params - lr m_hat / (sqrt(v_hat) + eps).
+    Returns (params, m, v) as new arrays.
+    """
+    g = np.asarray(grads, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    p = np.asarray(params, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return p, m, v

@@ -217,10 +217,13 @@ def locate(mesh: Mesh, pos, cell=None, stream=None):
     return cell
 
 
-def deposit(mesh: Mesh, pos, values, field=None, acc=None, stats=False, stream=None):
+def deposit(mesh: Mesh, pos, values, field=None, acc=None, stats=False, stream=None, frac_bits=None):
     """Particle centroid method (bit-exact).  pos [N, 3] f32, values [F, N] f32.
 
-    Returns field [F, cells] (and Stats when stats=True, which synchronises)."""
+    frac_bits: None (automatic fixed-point scales) or a list of F ints, -1 for
+    automatic or a scale 0..62 to force; a list is overwritten with the
+    scales used.  Returns field [F, cells] (and Stats when stats=True, which
+    synchronises)."""
     torch = _torch()
     lib = _abi.load()
     n = int(pos.shape[0])
@@ -231,9 +234,16 @@ def deposit(mesh: Mesh, pos, values, field=None, acc=None, stats=False, stream=N
         field = torch.empty((F, mesh.cells), dtype=torch.float32, device=pos.device)
     p_field = _dev(field, torch.float32, (F, mesh.cells), "field")
     p_acc = _dev(acc, torch.int64, (F, mesh.cells), "acc") if acc is not None else None
+    fb = None
+    if frac_bits is not None:
+        if len(frac_bits) != F:
+            raise ValueError(f"frac_bits needs {F} entries")
+        fb = (ctypes.c_int32 * F)(*[int(v) for v in frac_bits])
     st = _abi.SolveStats() if stats else None
-    rc = lib.cgd_deposit(mesh.handle, n, p_pos, F, p_val, p_field, p_acc,
+    rc = lib.cgd_deposit(mesh.handle, n, p_pos, F, p_val, p_field, p_acc, fb,
                          ctypes.byref(st) if st is not None else None, _stream_ptr(stream))
+    if fb is not None and rc >= 0 and isinstance(frac_bits, list):
+        frac_bits[:] = list(fb)
     _check(rc, "cgd_deposit", allow=(0,) if not stats else (0, _abi.E_NONFINITE))
     if stats:
         return field, _stats(st, F, 0, rc)
@@ -283,9 +293,10 @@ def coarse_grain(mesh: Mesh, pos, values, bandwidth, n_steps, rtol=1e-6, max_ite
 
 
 def coarse_grain_batched(mesh: HexMesh, offsets, pos, values, bandwidth, n_steps, rtol=1e-6, max_iter=1000,
-                         fields=None, return_iters=False, stream=None, precond=0, scheme="be"):
+                         fields=None, return_iters=False, stream=None, precond=0, scheme="be", stats=False):
     """All snapshots at once.  offsets: host int64 [S + 1]; pos [N, 3]; values
-    [F, N].  Returns fields [S, F, cells] (and iterations [S, F, n_steps])."""
+    [F, N].  Returns fields [S, F, cells], then the iterations [S, F, n_steps]
+    when return_iters, then a list of S Stats when stats."""
     import numpy as np
     torch = _torch()
     off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -300,12 +311,21 @@ def coarse_grain_batched(mesh: HexMesh, offsets, pos, values, bandwidth, n_steps
         fields = torch.empty((n_snap, F, mesh.cells), dtype=torch.float32, device=pos.device)
     p_f = _dev(fields, torch.float32, (n_snap, F, mesh.cells), "fields")
     o = _opts(rtol, max_iter, 0, None, 4, precond=precond, scheme=scheme)
-    iters = np.zeros((n_snap, F, n_steps), dtype=np.int32)
+    want = return_iters or stats
+    st = (_abi.SolveStats * n_snap)() if want else None
     rc = _abi.load().cgd_coarse_grain_batched(mesh.handle, n_snap, off.ctypes.data, p_pos, F, p_val,
                                               float(bandwidth), int(n_steps), ctypes.byref(o), p_f,
-                                              iters.ctypes.data, _stream_ptr(stream))
-    _check(rc, "cgd_coarse_grain_batched")
-    return (fields, iters) if return_iters else fields
+                                              st, _stream_ptr(stream))
+    # with stats, skipped non-finite particles are reported per snapshot
+    _check(rc, "cgd_coarse_grain_batched",
+           allow=(_abi.OK, _abi.NOT_CONVERGED, _abi.E_NONFINITE) if stats else (_abi.OK, _abi.NOT_CONVERGED))
+    out = [fields]
+    if return_iters:
+        out.append(np.array([[[st[j].iters[k][f] for k in range(n_steps)] for f in range(F)]
+                             for j in range(n_snap)], dtype=np.int32))
+    if stats:
+        out.append([_stats(st[j], F, n_steps, int(st[j].status)) for j in range(n_snap)])
+    return out[0] if len(out) == 1 else tuple(out)
 
 
 def autotune_batched(mesh: HexMesh, n_rhs: int):
@@ -320,7 +340,10 @@ def autotune_batched(mesh: HexMesh, n_rhs: int):
 
 
 TIMING_KINDS = {0: "cg_sweep1", 1: "cg_sweep2", 2: "deposit", 3: "pcg_spmv_sweep", 4: "pcg_update_sweep",
-                5: "cg_precond_sweep"}
+                5: "cg_precond_pass1", 6: "cg_precond_pass_mid", 7: "cg_precond_pass_last",
+                8: "cg_first_sweep1", 9: "cg_first_sweep2", 10: "cg_first_precond_pass1",
+                11: "cg_first_precond_pass_mid", 12: "cg_first_precond_pass_last",
+                13: "deposit_bin", 14: "deposit_scatter", 15: "deposit_accum"}
 
 
 def timing_enable(mesh: Mesh, on: bool = True):

@@ -41,7 +41,7 @@ class SolveStats(ctypes.Structure):
                 ("status", ctypes.c_int32), ("n_fallback", ctypes.c_int32)]
 
 
-TIMING_KINDS = 8
+TIMING_KINDS = 16
 
 
 class KernelTiming(ctypes.Structure):
@@ -69,7 +69,7 @@ SIGNATURES = {
                                     ctypes.c_void_p]),
     "cgd_deposit": (ctypes.c_int32, [c_mesh, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                     ctypes.POINTER(SolveStats), ctypes.c_void_p]),
+                                     ctypes.c_void_p, ctypes.POINTER(SolveStats), ctypes.c_void_p]),
     "cgd_diffuse": (ctypes.c_int32, [c_mesh, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
                                      ctypes.c_int32, ctypes.POINTER(SolverOpts),
                                      ctypes.POINTER(SolveStats), ctypes.c_void_p]),
@@ -80,7 +80,7 @@ SIGNATURES = {
     "cgd_coarse_grain_batched": (ctypes.c_int32, [c_mesh, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
                                                   ctypes.c_int32, ctypes.POINTER(SolverOpts), ctypes.c_void_p,
-                                                  ctypes.c_void_p, ctypes.c_void_p]),
+                                                  ctypes.POINTER(SolveStats), ctypes.c_void_p]),
     "cgd_velocity_from_momentum": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                                                     ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
     "cgd_autotune_batched": (ctypes.c_int32, [c_mesh, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),

@@ -80,6 +80,7 @@ void timing_end(Timing* t, int idx, int kind, double bytes, hipStream_t s, int64
     if (idx < 0) return;
     (void)hipEventRecord(t->used[idx + 1], s);
     t->kinds.push_back(kind);
+    t->first.push_back(idx);  // pairs may nest, so they close out of order
     t->bytes.push_back(bytes);
     t->tags.push_back(tag);
 }
@@ -88,7 +89,7 @@ void timing_collect(Timing* t, const std::function<bool(int64_t)>& keep) {
     for (size_t p = 0; p < t->kinds.size(); ++p) {
         float ms = 0.f;
         if (keep && !keep(t->tags[p])) continue;
-        if (hipEventElapsedTime(&ms, t->used[2 * p], t->used[2 * p + 1]) == hipSuccess) {
+        if (hipEventElapsedTime(&ms, t->used[t->first[p]], t->used[t->first[p] + 1]) == hipSuccess) {
             int k = t->kinds[p];
             t->launches[k] += 1;
             t->total_ms[k] += ms;
@@ -98,6 +99,7 @@ void timing_collect(Timing* t, const std::function<bool(int64_t)>& keep) {
     for (hipEvent_t e : t->used) t->pool.push_back(e);
     t->used.clear();
     t->kinds.clear();
+    t->first.clear();
     t->bytes.clear();
     t->tags.clear();
 }
@@ -279,18 +281,25 @@ static cgd_status check_common(cgd_mesh m, int32_t F, const char* who) {
     return CGD_OK;
 }
 
+// frac_bits: host [F] or NULL; in: -1 (automatic) or a forced scale 0..62
+// (validated by the caller), out: the scale used.  The call waits for the
+// stream when st is given or some scale was automatic.
 static cgd_status do_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
-                             float* field, int64_t* acc, cgd_solve_stats* st, hipStream_t s) {
+                             float* field, int64_t* acc, int32_t* frac_bits, cgd_solve_stats* st, hipStream_t s) {
     int64_t* acc_buf;
     DepositInfo* info;
     void* temp;
+    ScaleForce fs;
+    bool need_auto = false;
+    for (int f = 0; f < CGD_MAX_FIELDS; ++f) fs.s[f] = (frac_bits && f < F) ? frac_bits[f] : -1;
+    for (int f = 0; f < F; ++f) need_auto = need_auto || fs.s[f] < 0;
     cgd_status rc = deposit_buffers(m, n, F, acc, &acc_buf, &info, &temp);
     if (rc != CGD_OK) return rc;
     if (m->kind == 0)
-        rc = deposit_hex(m, n, pos, F, values, field, acc_buf, info, temp, s);
+        rc = deposit_hex(m, n, pos, F, values, field, acc_buf, info, temp, fs, s);
     else
-        rc = deposit_tet(m, n, pos, F, values, field, acc_buf, info, s);
-    if (rc != CGD_OK || !st) return rc;
+        rc = deposit_tet(m, n, pos, F, values, field, acc_buf, info, fs, s);
+    if (rc != CGD_OK || !(st || (frac_bits && need_auto))) return rc;
     cgd_status prc = ensure_pinned(m, kPinBytes);
     if (prc != CGD_OK) return prc;
     DepositInfo* h = reinterpret_cast<DepositInfo*>(static_cast<char*>(m->pinned) + kPinDeposit);
@@ -301,16 +310,20 @@ static cgd_status do_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F,
     for (int f = 0; f < F; ++f) {
         uint32_t mb = h->maxbits[f];
         int S = 0;
-        if (mb) {
+        if (fs.s[f] >= 0) {
+            S = fs.s[f];
+        } else if (mb) {
             float mv;
             memcpy(&mv, &mb, 4);
             int e;
             (void)frexp((double)mv, &e);
             S = 62 - e - e_n;
         }
-        st->frac_bits[f] = S;
+        if (st) st->frac_bits[f] = S;
+        if (frac_bits) frac_bits[f] = S;
         nf += h->nonfinite_val[f];
     }
+    if (!st) return CGD_OK;
     st->n_dropped = (int64_t)h->dropped;
     st->n_nonfinite = (int64_t)nf;
     if (nf) {
@@ -339,12 +352,20 @@ cgd_status cgd_locate(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, vo
 }
 
 cgd_status cgd_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
-                       float* field, int64_t* acc, cgd_solve_stats* st, void* stream) {
+                       float* field, int64_t* acc, int32_t* frac_bits, cgd_solve_stats* st, void* stream) {
     cgd_status rc = check_common(m, F, "cgd_deposit");
     if (rc != CGD_OK) return rc;
     if (n < 0 || (n > 0 && (!pos || !values)) || !field) {
         set_error("cgd_deposit: need n >= 0 and non-null pos/values (n > 0) and field");
         return CGD_E_INVALID;
+    }
+    if (frac_bits) {
+        for (int f = 0; f < F; ++f) {
+            if (frac_bits[f] < -1 || frac_bits[f] > 62) {
+                set_error("cgd_deposit: frac_bits entries must be -1 (automatic) or a scale in 0..62");
+                return CGD_E_INVALID;
+            }
+        }
     }
     if (reinterpret_cast<uintptr_t>(acc) % 8 || reinterpret_cast<uintptr_t>(pos) % 4 ||
         reinterpret_cast<uintptr_t>(values) % 4 || reinterpret_cast<uintptr_t>(field) % 4) {
@@ -357,7 +378,7 @@ cgd_status cgd_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
         return CGD_E_HIP;
     }
     if (st) memset(st, 0, sizeof(*st));
-    return do_deposit(m, n, pos, F, values, field, acc, st, static_cast<hipStream_t>(stream));
+    return do_deposit(m, n, pos, F, values, field, acc, frac_bits, st, static_cast<hipStream_t>(stream));
 }
 
 static cgd_status fill_opts(const cgd_solver_opts* o, int32_t F, float* field, double bandwidth,
@@ -451,7 +472,7 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, 
     }
     if (st) memset(st, 0, sizeof(*st));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    rc = do_deposit(m, n, pos, F, values, field, nullptr, st, s);
+    rc = do_deposit(m, n, pos, F, values, field, nullptr, nullptr, st, s);
     cgd_status dep_rc = rc;
     if (rc < 0 && rc != CGD_E_NONFINITE) return rc;
     rc = do_diffuse(m, a, st, s);
@@ -462,7 +483,7 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, 
 
 cgd_status cgd_coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offsets, const float* pos,
                                     int32_t F, const float* values, double bandwidth, int32_t n_steps,
-                                    const cgd_solver_opts* o, float* fields, int32_t* iters, void* stream) {
+                                    const cgd_solver_opts* o, float* fields, cgd_solve_stats* st, void* stream) {
     cgd_status rc = check_common(m, F, "cgd_coarse_grain_batched");
     if (rc != CGD_OK) return rc;
     if (m->kind != 0) {
@@ -504,7 +525,7 @@ cgd_status cgd_coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* o
         set_error(std::string("cgd_coarse_grain_batched: ") + hipGetErrorString(dg.err));
         return CGD_E_HIP;
     }
-    return coarse_grain_batched(m, n_snap, offsets, pos, F, values, a, fields, iters,
+    return coarse_grain_batched(m, n_snap, offsets, pos, F, values, a, fields, st,
                                 static_cast<hipStream_t>(stream));
 }
 

@@ -51,7 +51,7 @@ struct BDep {
     uint32_t* maxbits;        // [n_snap][F]
     unsigned long long* acc;  // [n_snap][F][cells]
     float* fields;            // [n_snap][F][cells]
-    unsigned long long* counters;  // [0] dropped, [1] non-finite
+    unsigned long long* counters;  // [n_snap][2]: dropped, non-finite (positions and values)
     int64_t cells;
     double vol;
     HexBin g;
@@ -62,7 +62,7 @@ __device__ inline int e_n_of(int64_t n) { return n <= 1 ? 0 : 64 - __clzll((unsi
 __global__ void k_bdep_init(BDep d) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < d.n_snap * d.F) d.maxbits[i] = 0u;
-    if (i < 2) d.counters[i] = 0ull;
+    if (i < 2 * d.n_snap) d.counters[i] = 0ull;
 }
 
 __global__ void k_bzero(unsigned long long* p, int64_t n) {
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kDBlock) void k_babsmax(BDep d) {
     }
     if ((threadIdx.x & 63) == 0) {
         if (m) atomicMax(&d.maxbits[j * d.F + f], m);
-        if (bad) atomicAdd(&d.counters[1], bad);
+        if (bad) atomicAdd(&d.counters[2 * j + 1], bad);
     }
 }
 
@@ -129,8 +129,8 @@ __global__ __launch_bounds__(kDBlock) void k_bdeposit(BDep d) {
         nf += __shfl_xor(nf, o);
     }
     if ((threadIdx.x & 63) == 0 && dropped) {
-        atomicAdd(&d.counters[0], dropped);
-        if (nf) atomicAdd(&d.counters[1], nf);
+        atomicAdd(&d.counters[2 * j], dropped);
+        if (nf) atomicAdd(&d.counters[2 * j + 1], nf);
     }
 }
 
@@ -160,8 +160,27 @@ struct BSolve {
     double rtol2;
     int max_iter;
     int32_t* iters;     // [n_rhs][n_steps]
+    double* relres;     // [n_rhs][n_steps]: recursive ||r|| / ||b|| at exit
     int32_t* status;    // [n_rhs]
 };
+
+// Mass of each right-hand side, sum_k V field_k, in float64 (one workgroup
+// per right-hand side, every sum in one fixed order).
+__global__ __launch_bounds__(1024) void k_bmass(const float* __restrict__ fields, int64_t cells, double vol,
+                                                 double* __restrict__ out) {
+    const float* f = fields + (size_t)blockIdx.x * cells;
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < cells; k += 1024) s += (double)f[k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    __shared__ double sh[16];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < 16; ++i) t += sh[i];
+        out[blockIdx.x] = t * vol;
+    }
+}
 
 // A value every lane of the wave holds identically, handed to the compiler as
 // a wave-uniform (scalar) value so that branches on it are scalar branches.
@@ -348,7 +367,10 @@ __global__ __launch_bounds__(64 * NW) void k_batched_cg(BSolve a) {
                     rho = rho_new;
                     ++k;
                 }
-                if (threadIdx.x == 0) a.iters[(size_t)rhs * a.n_steps + step] = k;
+                if (threadIdx.x == 0) {
+                    a.iters[(size_t)rhs * a.n_steps + step] = k;
+                    a.relres[(size_t)rhs * a.n_steps + step] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+                }
                 if (st == CGD_E_BREAKDOWN || (st == CGD_NOT_CONVERGED && worst == CGD_OK)) worst = st;
                 float* t = cur;
                 cur = nxt;
@@ -391,7 +413,10 @@ __global__ __launch_bounds__(64 * NW) void k_batched_cg(BSolve a) {
                 rr = rr_new;
                 ++k;
             }
-            if (threadIdx.x == 0) a.iters[(size_t)rhs * a.n_steps + step] = k;
+            if (threadIdx.x == 0) {
+                a.iters[(size_t)rhs * a.n_steps + step] = k;
+                a.relres[(size_t)rhs * a.n_steps + step] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+            }
             if (st == CGD_E_BREAKDOWN || (st == CGD_NOT_CONVERGED && worst == CGD_OK)) worst = st;
             float* t = cur;
             cur = nxt;
@@ -516,33 +541,31 @@ void save_tune_file(const std::string& key, int idx, double ms) {
 // Workspace of the batched call: a small region (fixed part, then the
 // per-right-hand-side arrays at 256-byte aligned offsets), then
 // max(int64 accumulators, solver scratch).
+// Byte offsets of the per-call arrays, in the device workspace and, from
+// `status` on, mirrored in pinned host memory after kPinBytes: status
+// [n_rhs] then iters [n_rhs][n_steps] (int32), counters [n_snap][2] (dropped,
+// non-finite), maxbits [n_rhs], relres [n_rhs][n_steps], mass [2][n_rhs]
+// (before, after diffusion).
 struct BLayout {
-    size_t maxbits, off, status, small;  // byte offsets; status is followed by iters
+    size_t maxbits, off, status, counters, relres, mass, small;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static BLayout batched_layout(int n_rhs, int n_snap, int n_steps) {
+static BLayout batched_layout_at(size_t start, int n_rhs, int n_snap, int n_steps) {
     BLayout L;
-    L.maxbits = kSmallFixed;
-    L.off = align256(L.maxbits + 4 * (size_t)n_rhs);
+    L.off = start;
     L.status = align256(L.off + 8 * ((size_t)n_snap + 1));
-    L.small = align256(L.status + 4 * (size_t)n_rhs * (1 + n_steps)) + 4096;
+    L.counters = align256(L.status + 4 * (size_t)n_rhs * (1 + n_steps));
+    L.maxbits = align256(L.counters + 16 * (size_t)n_snap);
+    L.relres = align256(L.maxbits + 4 * (size_t)n_rhs);
+    L.mass = align256(L.relres + 8 * (size_t)n_rhs * n_steps);
+    L.small = align256(L.mass + 16 * (size_t)n_rhs) + 4096;
     return L;
 }
 
-// Pinned staging of the batched call (bytes after kPinBytes).
-struct BPin {
-    size_t off, status, counters, total;
-};
-
-static BPin batched_pin(int n_rhs, int n_snap, int n_steps) {
-    BPin P;
-    P.off = kPinBytes;
-    P.status = align256(P.off + 8 * ((size_t)n_snap + 1));
-    P.counters = align256(P.status + 4 * (size_t)n_rhs * (1 + n_steps));
-    P.total = P.counters + 256;
-    return P;
+static BLayout batched_layout(int n_rhs, int n_snap, int n_steps) {
+    return batched_layout_at(kSmallFixed, n_rhs, n_snap, n_steps);
 }
 
 struct BatchedGraph {
@@ -607,6 +630,7 @@ cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, 
     float* scratch = fields + (size_t)nr * cells;
     int32_t* status = reinterpret_cast<int32_t*>(base + L.status);
     int32_t* iters = status + nr;
+    double* relres = reinterpret_cast<double*>(base + L.relres);
     hipStream_t s = nullptr;
     CGD_HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     hipEvent_t e0, e1;
@@ -635,6 +659,7 @@ cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, 
     a.rtol2 = 1e-12;
     a.max_iter = 100;
     a.iters = iters;
+    a.relres = relres;
     a.status = status;
     double best = 1e30;
     int best_i = 0;
@@ -678,7 +703,7 @@ cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, 
 }
 
 cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offsets, const float* pos, int32_t F,
-                                const float* values, const DiffuseArgs& da, float* fields, int32_t* iters_out,
+                                const float* values, const DiffuseArgs& da, float* fields, cgd_solve_stats* st_out,
                                 hipStream_t s) {
     const HexGeom& g = m->hex;
     const int n_rhs = n_snap * F;
@@ -715,23 +740,30 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     const size_t solver_bytes = (size_t)grid * 5 * cells * 4;
     rc = ensure_workspace(m, small + std::max(dep_bytes, solver_bytes));
     if (rc != CGD_OK) return rc;
-    const BPin P = batched_pin(n_rhs, n_snap, da.n_steps);
-    rc = ensure_pinned(m, P.total);
+    // the same arrays in pinned host memory, after the region the other calls use
+    const BLayout P = batched_layout_at(kPinBytes, n_rhs, n_snap, da.n_steps);
+    rc = ensure_pinned(m, P.small);
     if (rc != CGD_OK) return rc;
 
     char* base = static_cast<char*>(m->ws.ptr);
     char* pin = static_cast<char*>(m->pinned);
-    unsigned long long* d_counters = reinterpret_cast<unsigned long long*>(base + kOffSums);
+    unsigned long long* d_counters = reinterpret_cast<unsigned long long*>(base + L.counters);
     uint32_t* d_maxbits = reinterpret_cast<uint32_t*>(base + L.maxbits);
     int64_t* d_off = reinterpret_cast<int64_t*>(base + L.off);
     int32_t* d_status = reinterpret_cast<int32_t*>(base + L.status);
     int32_t* d_iters = d_status + n_rhs;
+    double* d_relres = reinterpret_cast<double*>(base + L.relres);
+    double* d_mass = reinterpret_cast<double*>(base + L.mass);
     void* big = base + small;
     int64_t* h_off = reinterpret_cast<int64_t*>(pin + P.off);
     int32_t* h_status = reinterpret_cast<int32_t*>(pin + P.status);
     int32_t* h_iters = h_status + n_rhs;
     unsigned long long* h_counters = reinterpret_cast<unsigned long long*>(pin + P.counters);
+    uint32_t* h_maxbits = reinterpret_cast<uint32_t*>(pin + P.maxbits);
+    double* h_relres = reinterpret_cast<double*>(pin + P.relres);
+    double* h_mass = reinterpret_cast<double*>(pin + P.mass);
     memcpy(h_off, offsets, 8 * ((size_t)n_snap + 1));
+    const bool want_mass = st_out != nullptr;
 
     BDep d = {};
     d.off = d_off;
@@ -788,12 +820,13 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     a.rtol2 = da.rtol * da.rtol;
     a.max_iter = da.max_iter;
     a.iters = d_iters;
+    a.relres = d_relres;
     a.status = d_status;
 
     // everything the call does, in stream order
     auto enqueue_all = [&](hipStream_t q) -> cgd_status {
         CGD_HIP_TRY(hipMemcpyAsync(d_off, h_off, 8 * ((size_t)n_snap + 1), hipMemcpyHostToDevice, q));
-        hipLaunchKernelGGL(k_bdep_init, dim3((n_rhs + 255) / 256), dim3(256), 0, q, d);
+        hipLaunchKernelGGL(k_bdep_init, dim3((std::max(n_rhs, 2 * n_snap) + 255) / 256), dim3(256), 0, q, d);
         if (tiled) {
             TiledDeposit td = {};
             td.pos = pos;
@@ -804,8 +837,10 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
             td.n_snap = n_snap;
             td.F = F;
             td.maxbits = d_maxbits;
-            td.nf_val = d_counters + 1;  // one count of non-finite positions and values
+            // per snapshot: one count of non-finite positions and values
+            td.nf_val = d_counters + 1;
             td.nf_val_stride = 0;
+            td.cnt_jstride = 2;
             td.dropped = d_counters;
             td.nf_pos = d_counters + 1;
             td.field = fields;
@@ -821,10 +856,14 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
             }
             hipLaunchKernelGGL(k_bfinalize, dim3(512, n_rhs), dim3(kDBlock), 0, q, d);
         }
+        if (want_mass) hipLaunchKernelGGL(k_bmass, dim3(n_rhs), dim3(1024), 0, q, fields, a.cells, g.vol, d_mass);
         cgd_status r = launch_solver(c, a, grid, q);
         if (r != CGD_OK) return r;
-        CGD_HIP_TRY(hipMemcpyAsync(h_status, d_status, 4 * (size_t)n_rhs * (1 + da.n_steps), hipMemcpyDeviceToHost, q));
-        CGD_HIP_TRY(hipMemcpyAsync(h_counters, d_counters, 16, hipMemcpyDeviceToHost, q));
+        if (want_mass)
+            hipLaunchKernelGGL(k_bmass, dim3(n_rhs), dim3(1024), 0, q, fields, a.cells, g.vol, d_mass + n_rhs);
+        // status, iters, counters, maxbits, relres (and mass) in one copy
+        const size_t upto = want_mass ? L.mass + 16 * (size_t)n_rhs : L.relres + 8 * (size_t)n_rhs * da.n_steps;
+        CGD_HIP_TRY(hipMemcpyAsync(pin + P.status, base + L.status, upto - L.status, hipMemcpyDeviceToHost, q));
         return CGD_OK;
     };
 
@@ -834,7 +873,7 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
         snprintf(keybuf, sizeof keybuf, "%p %p %p %d %d %lld %d %d %.17g %.17g %d %d %p %zu %p %d %d %d",
                  (const void*)pos, (const void*)values, (void*)fields, n_snap, F, (long long)total, chunks,
                  da.n_steps, da.bandwidth, da.rtol, da.max_iter, ci, m->ws.ptr, m->ws.bytes, m->pinned, a.pcg,
-                 (int)tiled, da.scheme);
+                 (int)tiled, da.scheme * 2 + (int)want_mass);
         std::lock_guard<std::mutex> lk(g_graph_mu);
         BatchedGraph& bg = g_graphs[m];
         if (bg.key != keybuf || !bg.exec) {
@@ -873,8 +912,43 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
             worst = CGD_NOT_CONVERGED;
         }
     }
-    if (iters_out) memcpy(iters_out, h_iters, 4 * (size_t)n_rhs * da.n_steps);
-    if (worst == CGD_OK && h_counters[1]) {
+    unsigned long long nonfinite = 0;
+    for (int j = 0; j < n_snap; ++j) nonfinite += h_counters[2 * j + 1];
+    if (st_out) {
+        for (int j = 0; j < n_snap; ++j) {
+            cgd_solve_stats& st = st_out[j];
+            memset(&st, 0, sizeof st);
+            st.n_steps = da.n_steps;
+            st.n_fields = F;
+            const int e_n = ceil_log2_count(offsets[j + 1] - offsets[j]);
+            int32_t sworst = CGD_OK;
+            for (int f = 0; f < F; ++f) {
+                const int r = j * F + f;
+                for (int k = 0; k < da.n_steps; ++k) {
+                    st.iters[k][f] = h_iters[(size_t)r * da.n_steps + k];
+                    st.rel_res[k][f] = h_relres[(size_t)r * da.n_steps + k];
+                }
+                st.mass_before[f] = h_mass[r];
+                st.mass_after[f] = h_mass[n_rhs + r];
+                int S = 0;
+                if (const uint32_t mb = h_maxbits[r]) {
+                    float mv;
+                    memcpy(&mv, &mb, 4);
+                    int e;
+                    (void)frexp((double)mv, &e);
+                    S = 62 - e - e_n;
+                }
+                st.frac_bits[f] = S;
+                if (h_status[r] == CGD_E_BREAKDOWN) sworst = CGD_E_BREAKDOWN;
+                else if (h_status[r] == CGD_NOT_CONVERGED && sworst == CGD_OK) sworst = CGD_NOT_CONVERGED;
+            }
+            st.n_dropped = (int64_t)h_counters[2 * j];
+            st.n_nonfinite = (int64_t)h_counters[2 * j + 1];
+            if (sworst == CGD_OK && st.n_nonfinite) sworst = CGD_E_NONFINITE;
+            st.status = sworst;
+        }
+    }
+    if (worst == CGD_OK && nonfinite) {
         set_error("non-finite particle positions or values were skipped");
         worst = CGD_E_NONFINITE;
     }

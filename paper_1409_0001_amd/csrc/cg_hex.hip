@@ -906,7 +906,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
 
     // One sweep: its own plan, and the block count of the sweep whose
     // partial sums its prologue adds.
-    auto launch = [&](int mode) {
+    auto set_plan = [&](int mode) -> const Plan& {
         const bool is_z = mode == SZ_FIRST || mode == SZ || mode == SZ2_FIRST || mode == SZ2;
         const bool is_1 = mode == S1_FIRST || mode == S1 || mode == S1_B0;
         const Plan& q = is_z ? pz : (is_1 ? p1 : p);
@@ -919,9 +919,42 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         if (is_z) a.bpf_in = p.bpf;                   // r.r (and b.b) of sweep 2 / the residual sweep
         else if (is_1) a.bpf_in = a.pcg ? pz.bpf : p.bpf;  // r.z of the preconditioning sweep, or r.r
         else a.bpf_in = p1.bpf;                       // p.Ap (and b.b) of sweep 1
+        return q;
+    };
+    auto launch = [&](int mode) {
+        const bool is_z = mode == SZ_FIRST || mode == SZ || mode == SZ2_FIRST || mode == SZ2;
+        const bool is_1 = mode == S1_FIRST || mode == S1 || mode == S1_B0;
+        const Plan& q = set_plan(mode);
         if (is_z && deg_lds) launch_precond_lds(deg_lds, p.vec, mode == mode_z_first, q, a, s);
         else if (is_1 && dir_nw) launch_dir_lds(dir_nw, p.vec, mode == S1_B0, q, a, s);
         else launch_sweep(mode, q, a, s);
+    };
+    // The preconditioning step z = M r with every pass timed on its own:
+    // kinds 5 / 6 / 7 (10 / 11 / 12 in a step's first iteration, which reads
+    // b) for the first, middle and last pass; 8 bytes per cell and pass (read
+    // its input, write its output), plus the last product pass's read of r.
+    auto launch_precond_timed = [&](bool first, int64_t tag) {
+        const int mode = first ? mode_z_first : mode_z;
+        const double cb = (double)F * cells;
+        const int k0 = first ? 10 : 5;
+        if (deg_lds == 8 || deg_lds == 12) {
+            const Plan& q = set_plan(mode);
+            int t = timing_begin(&m->timing, s);
+            launch_precond_lds_d<4, 1>(p.vec, first, q, a, s);
+            timing_end(&m->timing, t, k0, 8.0 * cb, s, tag);
+            if (deg_lds == 12) {
+                t = timing_begin(&m->timing, s);
+                launch_precond_lds_d<4, 3>(p.vec, first, q, a, s);
+                timing_end(&m->timing, t, k0 + 1, 8.0 * cb, s, tag);
+            }
+            t = timing_begin(&m->timing, s);
+            launch_precond_lds_d<4, 2>(p.vec, first, q, a, s);
+            timing_end(&m->timing, t, k0 + 2, 12.0 * cb, s, tag);
+        } else {
+            int t = timing_begin(&m->timing, s);
+            launch(mode);
+            timing_end(&m->timing, t, k0, 8.0 * cb, s, tag);
+        }
     };
 
     const int sum_bpf = (int)std::min<int64_t>(1024, (cells + kBlock - 1) / kBlock);
@@ -1002,24 +1035,25 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             // live until sweep 1 writes p_new into it
             a.p.U = it == 0 ? (dir_nw ? PA : PB) : pnew;
             a.p.V = deg_lds == 12 ? PV : a.p.U;
-            int t0 = first ? -1 : timing_begin(&m->timing, s);
-            launch(first ? mode_z_first : mode_z);
-            // algorithmic bytes of the preconditioning passes: 8 per cell and
-            // pass, and the last pass's read of r
-            const double zb_cell = deg_lds == 12 ? 28.0 : (deg_lds == 8 ? 20.0 : 8.0);
-            if (!first) timing_end(&m->timing, t0, 5, zb_cell * (double)F * cells, s, tag);
+            launch_precond_timed(first, tag);
             a.p.Z = Z;
             a.p.R = zb;
             a.p.Pold = pold;
             a.p.Pnew = pnew;
-            int t1 = first ? -1 : timing_begin(&m->timing, s);
+            // direction sweep: reads z and p_old, writes p (12 bytes per
+            // cell); p_0 = z_0 reads z only, and is written only by the
+            // register sweep
+            const double b1 = it == 0 ? (dir_nw ? 4.0 : 8.0) : 12.0;
+            int t1 = timing_begin(&m->timing, s);
             launch(it == 0 ? S1_B0 : S1);
-            if (!first) timing_end(&m->timing, t1, 0, 12.0 * (double)F * cells, s, tag);
+            timing_end(&m->timing, t1, it == 0 ? 8 : 0, b1 * (double)F * cells, s, tag);
             a.p.R = R;
             a.c.host_flags = host_flags;
-            int t2 = first ? -1 : timing_begin(&m->timing, s);
+            // update sweep: reads p, x, r, writes x, r (20); from a zero
+            // guess reads p, b, writes x, r (16)
+            int t2 = timing_begin(&m->timing, s);
             launch(first ? S2P_FIRST : S2);
-            if (!first) timing_end(&m->timing, t2, 1, 20.0 * (double)F * cells, s, tag);
+            timing_end(&m->timing, t2, first ? 9 : 1, (first ? 16.0 : 20.0) * (double)F * cells, s, tag);
             a.c.host_flags = nullptr;
         };
         auto enqueue = [&](int it, int* host_flags) {

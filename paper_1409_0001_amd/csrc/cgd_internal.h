@@ -39,9 +39,16 @@ struct CgField {
 // Counters the deposit kernels fill (device).
 struct DepositInfo {
     uint32_t maxbits[CGD_MAX_FIELDS];       // max |v| bit pattern over finite values
+    int32_t force_s[CGD_MAX_FIELDS];        // fixed-point scale set by the caller; -1: automatic
     unsigned long long nonfinite_val[CGD_MAX_FIELDS];
     unsigned long long dropped;             // non-finite or outside the domain
     unsigned long long nonfinite_pos;
+};
+
+// Fixed-point scales a deposit call is asked to use: s[f] in 0..62 forces
+// S_f, -1 leaves it to the rule of frac_bits_of.
+struct ScaleForce {
+    int32_t s[CGD_MAX_FIELDS];
 };
 
 struct HexGeom {
@@ -59,7 +66,8 @@ struct Timing {
     bool on = false;
     std::vector<hipEvent_t> pool;          // free events
     std::vector<hipEvent_t> used;          // recorded pairs (start, end)
-    std::vector<int> kinds;                // kind of each pair
+    std::vector<int> kinds;                // kind of each closed pair
+    std::vector<int> first;                // index in `used` of each closed pair's start event
     std::vector<double> bytes;             // algorithmic bytes of each pair
     std::vector<int64_t> tags;             // caller's label of each pair
     int64_t launches[CGD_TIMING_KINDS] = {};
@@ -110,7 +118,8 @@ cgd_status ensure_pinned(cgd_mesh m, size_t bytes);
 // path (nullptr or 0 bytes: the direct path, which needs acc).  On the tiled
 // path acc may be nullptr (the accumulators are then not written out).
 cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
-                       float* field, int64_t* acc, DepositInfo* info_dev, void* temp, hipStream_t s);
+                       float* field, int64_t* acc, DepositInfo* info_dev, void* temp, const ScaleForce& fs,
+                       hipStream_t s);
 size_t deposit_hex_temp_bytes(const cgd_mesh m, int64_t n, int32_t F);
 
 // Tiled deposit of one or several snapshots on a mesh's hex grid (device
@@ -124,8 +133,10 @@ struct TiledDeposit {
     const int64_t* off;            // [n_snap + 1] particle offsets; nullptr: one snapshot
     int32_t n_snap, F;
     uint32_t* maxbits;             // [n_snap][F] max |v| bit patterns
+    const int32_t* force_s;        // nullable: [F] scales forced by the caller (-1: automatic)
     unsigned long long* nf_val;    // field f's non-finite values are counted at nf_val[f * nf_val_stride]
     int32_t nf_val_stride;
+    int32_t cnt_jstride;           // snapshot j's counts sit at dropped / nf_pos / nf_val + j * cnt_jstride
     unsigned long long* dropped;   // particles outside the box or with a non-finite coordinate
     unsigned long long* nf_pos;    // ... of those, the non-finite ones
     float* field;                  // [n_snap][F][cells]
@@ -164,9 +175,10 @@ size_t diffuse_hex_workspace(const cgd_mesh m, int32_t F);
 // ceil(log2 n) for n >= 2, 0 for n <= 1 (the e_N of the fixed-point scale).
 int ceil_log2_count(int64_t n);
 
-// Resets the counters, clears acc [F, cells] and computes max |v| per field.
+// Resets the counters (and records the forced scales), clears acc [F, cells]
+// and computes max |v| per field.
 void deposit_prologue(int64_t n, int32_t F, const float* values, int64_t* acc, int64_t cells,
-                      DepositInfo* info, hipStream_t s);
+                      DepositInfo* info, const ScaleForce& fs, hipStream_t s);
 
 #ifdef __HIPCC__
 // Fixed-point scale S = 62 - e_max - e_N, max |v| = m 2^e_max, m in [0.5, 1).
@@ -175,6 +187,10 @@ __device__ inline int frac_bits_of(uint32_t maxbits, int e_n) {
     int e;
     (void)frexp((double)__uint_as_float(maxbits), &e);
     return 62 - e - e_n;
+}
+// The scale in use: the caller's, else the automatic one.
+__device__ inline int frac_bits_used(uint32_t maxbits, int32_t force, int e_n) {
+    return force >= 0 ? force : frac_bits_of(maxbits, e_n);
 }
 #endif
 
@@ -191,14 +207,14 @@ bool unet_matches(cgd_unet u, int nx, int ny, int nz, int device);
 
 // batched.hip
 cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offsets, const float* pos, int32_t F,
-                                const float* values, const DiffuseArgs& da, float* fields, int32_t* iters_out,
+                                const float* values, const DiffuseArgs& da, float* fields, cgd_solve_stats* st_out,
                                 hipStream_t s);
 cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, int* n_cand);
 void destroy_batched(cgd_mesh m);
 
 // tet.cpp / tet.hip
 cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
-                       float* field, int64_t* acc, DepositInfo* info_dev, hipStream_t s);
+                       float* field, int64_t* acc, DepositInfo* info_dev, const ScaleForce& fs, hipStream_t s);
 cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hipStream_t s);
 void destroy_tet_data(cgd_mesh m);
 int64_t tet_nnz(cgd_mesh m);

@@ -26,10 +26,11 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__global__ void k_dep_init(DepositInfo* info) {
+__global__ void k_dep_init(DepositInfo* info, ScaleForce fs) {
     int t = threadIdx.x;
     if (t < CGD_MAX_FIELDS) {
         info->maxbits[t] = 0u;
+        info->force_s[t] = fs.s[t];
         info->nonfinite_val[t] = 0ull;
     }
     if (t == 0) {
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit_hex(
     const float* __restrict__ pos, const float* __restrict__ values, int64_t n, int F, HexBin g,
     int e_n, unsigned long long* __restrict__ acc, int64_t cells, DepositInfo* info) {
     __shared__ int S[CGD_MAX_FIELDS];
-    if (threadIdx.x < F) S[threadIdx.x] = frac_bits_of(info->maxbits[threadIdx.x], e_n);
+    if (threadIdx.x < F) S[threadIdx.x] = frac_bits_used(info->maxbits[threadIdx.x], info->force_s[threadIdx.x], e_n);
     __syncthreads();
     unsigned long long dropped = 0ull, nfpos = 0ull;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -159,8 +160,11 @@ struct TileArgs {
     uint2* rec;            // [total]: (cell within its tile, bits of field 0's value), tile-bucketed
     float* rv;             // [F - 1][total]: values of fields 1.., tile-bucketed
     uint32_t* maxbits;     // [n_snap][F]
-    unsigned long long* nf_val;  // field f's non-finite values counted at nf_val[f * nf_val_stride]
+    const int32_t* force_s;  // nullable: [F] scales forced by the caller
+    unsigned long long* nf_val;  // snapshot j's non-finite values of field f counted at
+                                 // nf_val[j * cnt_jstride + f * nf_val_stride]
     int nf_val_stride;
+    int cnt_jstride;       // snapshot stride of the three counters (dropped, nf_pos, nf_val)
     unsigned long long* dropped;
     unsigned long long* nf_pos;
     float* field;          // [n_snap][F][cells]
@@ -275,8 +279,8 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
         nfpos += __shfl_xor(nfpos, o);
     }
     if ((threadIdx.x & 63) == 0 && dropped) {
-        atomicAdd(a.dropped, dropped);
-        if (nfpos) atomicAdd(a.nf_pos, nfpos);
+        atomicAdd(a.dropped + (size_t)j * a.cnt_jstride, dropped);
+        if (nfpos) atomicAdd(a.nf_pos + (size_t)j * a.cnt_jstride, nfpos);
     }
     __syncthreads();
     uint32_t* counts = a.counts + (size_t)j * a.ntiles;
@@ -285,7 +289,7 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
     if (threadIdx.x < a.F) {
         const int f = threadIdx.x;
         if (bmax[f]) atomicMax(&a.maxbits[j * a.F + f], bmax[f]);
-        if (bbad[f]) atomicAdd(&a.nf_val[f * a.nf_val_stride], bbad[f]);
+        if (bbad[f]) atomicAdd(&a.nf_val[(size_t)j * a.cnt_jstride + f * a.nf_val_stride], bbad[f]);
     }
 }
 
@@ -408,7 +412,8 @@ __global__ __launch_bounds__(kTBlock) void k_tile_accum(TileArgs a) {
     if (threadIdx.x < a.F) {
         int64_t s0, s1;
         snap_range(a, j, s0, s1);
-        S[threadIdx.x] = frac_bits_of(a.maxbits[j * a.F + threadIdx.x], e_n_dev(s1 - s0));
+        S[threadIdx.x] = frac_bits_used(a.maxbits[j * a.F + threadIdx.x], a.force_s ? a.force_s[threadIdx.x] : -1,
+                                        e_n_dev(s1 - s0));
     }
     __syncthreads();
     const uint32_t r0 = a.offsets[T], r1 = a.offsets[T + 1];
@@ -464,7 +469,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const long long* __restrict
                                                      float* __restrict__ field, int64_t cells,
                                                      double vol, int e_n, const DepositInfo* info) {
     const int f = blockIdx.y;
-    const int S = frac_bits_of(info->maxbits[f], e_n);
+    const int S = frac_bits_used(info->maxbits[f], info->force_s[f], e_n);
     const long long* a = acc + (size_t)f * cells;
     float* out = field + (size_t)f * cells;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -477,8 +482,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const long long* __restrict
 }  // namespace
 
 void deposit_prologue(int64_t n, int32_t F, const float* values, int64_t* acc, int64_t cells,
-                      DepositInfo* info, hipStream_t s) {
-    hipLaunchKernelGGL(k_dep_init, dim3(1), dim3(64), 0, s, info);
+                      DepositInfo* info, const ScaleForce& fs, hipStream_t s) {
+    hipLaunchKernelGGL(k_dep_init, dim3(1), dim3(64), 0, s, info, fs);
     const int64_t words = (int64_t)F * cells;
     int zblocks = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (words + kBlock - 1) / kBlock));
     hipLaunchKernelGGL(k_zero64, dim3(zblocks), dim3(kBlock), 0, s, reinterpret_cast<unsigned long long*>(acc),
@@ -584,8 +589,10 @@ cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipS
     a.offsets = a.counts + all;
     a.cursor = a.offsets + all + 1;
     a.maxbits = d.maxbits;
+    a.force_s = d.force_s;
     a.nf_val = d.nf_val;
     a.nf_val_stride = d.nf_val_stride;
+    a.cnt_jstride = d.cnt_jstride;
     a.dropped = d.dropped;
     a.nf_pos = d.nf_pos;
     a.field = d.field;
@@ -595,18 +602,34 @@ cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipS
     const int64_t bchunk = (int64_t)a.nsub_bin * kTChunk, schunk = (int64_t)a.nsub * kTChunk;
     const int cblocks = (int)std::max<int64_t>(1, (d.max_n + bchunk - 1) / bchunk);
     const int sblocks = (int)std::max<int64_t>(1, (d.max_n + schunk - 1) / schunk);
+    // Timed as a whole (kind 2: 12 bytes of position and 12 per field and
+    // particle, the direct path's count) and per stage (kinds 13..15, each
+    // with the bytes it must move: binning reads positions and values and
+    // writes the host cell; the scatter reads cell and values and writes
+    // records of 8 + 4 (F - 1) bytes; the accumulation reads the records and
+    // writes the field, 4 bytes per cell and field).
+    const double np_ = (double)d.total;
     int tm = timing ? timing_begin(timing, s) : -1;
+    int t13 = timing ? timing_begin(timing, s) : -1;
     hipLaunchKernelGGL(k_tile_bin, dim3(cblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    if (timing) timing_end(timing, t13, 13, (12.0 + 4.0 * d.F + 4.0) * np_, s);
+    int t14 = timing ? timing_begin(timing, s) : -1;
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kTBlock), 0, s, a);
     hipLaunchKernelGGL(k_tile_scatter, dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    if (timing) timing_end(timing, t14, 14, (4.0 + 4.0 * d.F + 8.0 + 4.0 * (d.F - 1)) * np_, s);
+    int t15 = timing ? timing_begin(timing, s) : -1;
     hipLaunchKernelGGL(k_tile_accum, dim3(all), dim3(kTBlock), 0, s, a);
-    if (timing) timing_end(timing, tm, 2, (12.0 + 12.0 * d.F) * (double)d.total, s);
+    if (timing)
+        timing_end(timing, t15, 15,
+                   (8.0 + 4.0 * (d.F - 1)) * np_ + 4.0 * d.F * (double)m->cells * d.n_snap, s);
+    if (timing) timing_end(timing, tm, 2, (12.0 + 12.0 * d.F) * np_, s);
     CGD_HIP_TRY(hipGetLastError());
     return CGD_OK;
 }
 
 cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
-                       float* field, int64_t* acc, DepositInfo* info, void* temp, hipStream_t s) {
+                       float* field, int64_t* acc, DepositInfo* info, void* temp, const ScaleForce& fs,
+                       hipStream_t s) {
     const int64_t cells = m->cells;
     const int e_n = ceil_log2_count(n);
     const HexBin g = hex_bin(m);
@@ -620,6 +643,7 @@ cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
         d.n_snap = 1;
         d.F = F;
         d.maxbits = info->maxbits;
+        d.force_s = info->force_s;
         d.nf_val = info->nonfinite_val;
         d.nf_val_stride = 1;
         d.dropped = &info->dropped;
@@ -627,10 +651,10 @@ cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
         d.field = field;
         d.acc = reinterpret_cast<long long*>(acc);
         d.temp = temp;
-        hipLaunchKernelGGL(k_dep_init, dim3(1), dim3(64), 0, s, info);
+        hipLaunchKernelGGL(k_dep_init, dim3(1), dim3(64), 0, s, info, fs);
         return tiled_deposit(m, d, &m->timing, s);
     }
-    deposit_prologue(n, F, values, acc, cells, info, s);
+    deposit_prologue(n, F, values, acc, cells, info, fs, s);
     if (n > 0) {
         int dblocks = (int)std::min<int64_t>(16384, (n + kBlock - 1) / kBlock);
         int t = timing_begin(&m->timing, s);

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_locate_deposit_tet(const float* __re
                                                                Loc loc, int e_n, unsigned long long* __restrict__ acc,
                                                                int64_t cells, DepositInfo* info, int32_t* cell_out) {
     __shared__ int S[CGD_MAX_FIELDS];
-    if (threadIdx.x < F) S[threadIdx.x] = frac_bits_of(info->maxbits[threadIdx.x], e_n);
+    if (threadIdx.x < F) S[threadIdx.x] = frac_bits_used(info->maxbits[threadIdx.x], info->force_s[threadIdx.x], e_n);
     __syncthreads();
     unsigned long long dropped = 0ull, nfpos = 0ull;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_vol(const long long* __rest
                                                          int64_t cells, const double* __restrict__ vol, int e_n,
                                                          const DepositInfo* info) {
     const int f = blockIdx.y;
-    const int S = frac_bits_of(info->maxbits[f], e_n);
+    const int S = frac_bits_used(info->maxbits[f], info->force_s[f], e_n);
     const long long* a = acc + (size_t)f * cells;
     float* out = field + (size_t)f * cells;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < cells; k += (int64_t)gridDim.x * blockDim.x)
@@ -511,11 +511,11 @@ size_t diffuse_tet_workspace(const cgd_mesh m, int32_t F) {
 }
 
 cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values, float* field,
-                       int64_t* acc, DepositInfo* info, hipStream_t s) {
+                       int64_t* acc, DepositInfo* info, const ScaleForce& fs, hipStream_t s) {
     const TetData* t = m->tet;
     const int64_t cells = t->n_tet;
     const int e_n = ceil_log2_count(n);
-    deposit_prologue(n, F, values, acc, cells, info, s);
+    deposit_prologue(n, F, values, acc, cells, info, fs, s);
     if (n > 0) {
         const int blocks = (int)std::min<int64_t>(16384, (n + kBlock - 1) / kBlock);
         int tm = timing_begin(&m->timing, s);

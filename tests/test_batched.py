@@ -162,7 +162,7 @@ def test_autotune_reports_candidates(gpu_lib):
     assert chosen == int(np.argmin(ms))
 
 
-@pytest.mark.parametrize("cfg", [1, 4, 5, 6, 7])  # degree 2 (16 waves); degrees 4 and 12, both tile shapes
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7])  # degree 2 (four tile shapes); degrees 4 and 12 (two each)
 def test_batched_candidates_match_oracle(gpu_lib, cfg, monkeypatch):
     """Every preconditioner degree of the persistent solver reaches the same
     fields: forced candidates against the float64 oracle on 128 x 20 x 24
@@ -202,13 +202,18 @@ def test_batched_invalid(gpu_lib):
         cgd.coarse_grain_batched(mesh, [0, 6, 4, 10], pos, vals, 0.1, 2)  # decreasing offsets
 
 
-def test_batched_crank_nicolson_matches_oracle_and_graph_key(gpu_lib):
+@pytest.mark.parametrize("cfg,precond", [(None, 0), (1, 0), (1, 1), (4, 0), (4, 1), (6, 0), (6, 1)])
+def test_batched_crank_nicolson_matches_oracle_and_graph_key(gpu_lib, cfg, precond, monkeypatch):
     """Crank-Nicolson in the persistent launch (the x updates carry the
     extrapolation) against the oracle's CN closed form, after a backward-Euler
     call with the same arguments: the captured graph must not be replayed
-    across schemes."""
+    across schemes.  The autotuner's pick and forced candidates of degree 2,
+    4 and 12, each preconditioned and plain (plain CG runs the degree-2
+    kernel of the same tile shape: the S2_FIRST x update with xb * b)."""
     import torch
     cgd = gpu_lib
+    if cfg is not None:
+        monkeypatch.setenv("CGD_BATCHED_CFG", str(cfg))
     shape = (64, 40, 36)
     counts = [15_000, 9_000, 1]
     box, parts, pos, vals, off = _batch(shape, counts, seed=91)
@@ -216,8 +221,9 @@ def test_batched_crank_nicolson_matches_oracle_and_graph_key(gpu_lib):
     print(f"case: batched CN {shape} snapshots {counts}", flush=True)
     mesh = cgd.HexMesh(shape, box.lo, box.hi)
     args = (mesh, off, _t(pos, torch), _t(vals, torch), b, steps)
-    be = cgd.coarse_grain_batched(*args, rtol=1e-7).cpu().numpy()
-    cn = cgd.coarse_grain_batched(*args, rtol=1e-7, scheme="cn").cpu().numpy()
+    print(f"  candidate {cfg}, precond {precond}", flush=True)
+    be = cgd.coarse_grain_batched(*args, rtol=1e-7, precond=precond).cpu().numpy()
+    cn = cgd.coarse_grain_batched(*args, rtol=1e-7, scheme="cn", precond=precond).cpu().numpy()
     for j, p in enumerate(parts):
         dep = O.deposit_hex(p.pos, p.values, box.lo, box.hi, shape)
         ref_cn = O.diffuse_hex_dct(dep["field64"], box.lo, box.hi, shape, b, steps, scheme="cn")
@@ -225,3 +231,45 @@ def test_batched_crank_nicolson_matches_oracle_and_graph_key(gpu_lib):
         for f in range(4):
             assert rel_l2(cn[j, f], ref_cn[f]) <= REL_L2, (j, f, rel_l2(cn[j, f], ref_cn[f]))
             assert rel_l2(be[j, f], ref_be[f]) <= REL_L2, (j, f)
+
+
+def test_batched_stats_per_snapshot(gpu_lib):
+    """Per-snapshot statistics of the batched call: the fixed-point scales of
+    the oracle's deposit, dropped and non-finite particles of each snapshot
+    (planted in one of them), mass before diffusion equal to the oracle's
+    deposited mass (float32 field, float64 sums), mass after within the
+    stopping rule's bound, residuals at or below rtol, and iterations that
+    agree with the iteration output."""
+    import torch
+    cgd = gpu_lib
+    shape = (64, 24, 20)
+    counts = [9_000, 4_000, 0, 6_000]
+    box, parts, pos, vals, off = _batch(shape, counts, seed=95)
+    pos = pos.copy()
+    vals = vals.copy()
+    k = int(off[1]) + 10  # snapshot 1: three particles outside the box, one non-finite position
+    pos[k:k + 3, 0] = 1.5
+    pos[k + 3, 2] = np.nan
+    parts[1].pos[10:13, 0] = 1.5
+    parts[1].pos[13, 2] = np.nan
+    b, steps, rtol = 4.0 / shape[0], 3, 1e-7
+    print(f"case: batched stats {shape} snapshots {counts}", flush=True)
+    mesh = cgd.HexMesh(shape, box.lo, box.hi)
+    fields, iters, sts = cgd.coarse_grain_batched(mesh, off, _t(pos, torch), _t(vals, torch), b, steps,
+                                                  rtol=rtol, return_iters=True, stats=True)
+    V = O.hex_cell_volume(box.lo, box.hi, shape)
+    for j, p in enumerate(parts):
+        st = sts[j]
+        dep = O.deposit_hex(p.pos, p.values, box.lo, box.hi, shape)
+        assert st.frac_bits == dep["S"], (j, st.frac_bits, dep["S"])
+        assert st.n_dropped == dep["n_dropped"] and st.n_nonfinite == dep["n_nonfinite"], j
+        assert st.status == (-2 if j == 1 else 0), (j, st.status)
+        for f in range(4):
+            m32 = float(dep["field32"][f].astype(np.float64).sum() * V)
+            assert st.mass_before[f] == pytest.approx(m32, rel=1e-12, abs=1e-300), (j, f)
+            scale = float(np.abs(dep["field32"][f].astype(np.float64)).sum() * V)
+            assert abs(st.mass_after[f] - st.mass_before[f]) <= 1e-5 * scale + 1e-300, (j, f)
+            for s_ in range(steps):
+                assert st.iters[s_][f] == iters[j, f, s_]
+                assert st.rel_res[s_][f] <= rtol, (j, f, s_, st.rel_res[s_][f])
+    assert sts[2].n_dropped == 0 and all(m == 0 for m in sts[2].mass_before)

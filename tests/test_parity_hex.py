@@ -67,6 +67,61 @@ def test_deposit_many_tiles_clustered_bit_exact(gpu_lib, F):
     assert np.array_equal(field.cpu().numpy().view(np.uint32), ref["field32"].view(np.uint32))
 
 
+def test_deposit_dense_bed_single_field_many_tiles_bit_exact(gpu_lib):
+    """The dense-bed recipe at one field, the benchmarked deposit: tiles of
+    16384 cells (the largest LDS tile) on 128 x 128 x 256 = 256 tiles, 2.5M
+    particles (the dense bed's per-volume density), 70 % of them packed in
+    the bottom quarter and the rest in clumps, so tiles (here one z-plane
+    each) range from nearly empty to crowded.  Accumulators and float32 field bit-identical to the oracle's
+    (eq. pcm-k; eq. conserve holds exactly in the integers)."""
+    import torch
+    cgd = gpu_lib
+    w = inputs.dense_bed(n_particles=2_500_000, shape=(128, 128, 256), n_fields=1)
+    print(f"case: {w.name}", flush=True)
+    mesh = cgd.HexMesh(w.box.shape, w.box.lo, w.box.hi)
+    acc = torch.empty((1, mesh.cells), dtype=torch.int64, device="cuda")
+    field, st = cgd.deposit(mesh, _t(w.particles.pos, torch), _t(w.particles.values, torch), acc=acc, stats=True)
+    ref = O.deposit_hex(w.particles.pos, w.particles.values, w.box.lo, w.box.hi, w.box.shape)
+    a = acc.cpu().numpy()
+    assert st.frac_bits[0] == ref["S"][0]
+    assert np.array_equal(a, ref["acc"])
+    assert np.array_equal(field.cpu().numpy().view(np.uint32), ref["field32"].view(np.uint32))
+    occupied = np.add.reduceat((a[0] != 0).astype(np.int64), np.arange(0, mesh.cells, 16384))
+    assert occupied.min() < 100 and occupied.max() > 8000  # nearly empty and crowded tiles both present
+    assert int(a.sum()) == int(O.quantise(w.particles.values[0], ref["S"][0]).sum())
+
+
+@pytest.mark.parametrize("path", ["tiled", "direct"])
+def test_deposit_forced_frac_bits(gpu_lib, path, monkeypatch):
+    """cgd_deposit's frac_bits: a forced scale for one field, automatic for
+    the other, against the oracle with the same scales (signed values, two
+    fields, ragged grid); the scales used come back through the array, and
+    scales outside -1..62 are refused before anything is enqueued."""
+    import torch
+    cgd = gpu_lib
+    if path == "direct":
+        monkeypatch.setenv("CGD_DEPOSIT_DIRECT", "1")
+    box = inputs.HexBox((-0.3, 0.1, 2.0), (0.7, 0.35, 2.9), (37, 29, 11))
+    p = inputs.uniform_bed(box, 30_000, 2, seed=23)
+    print(f"case: forced frac_bits, {path} deposit", flush=True)
+    mesh = cgd.HexMesh(box.shape, box.lo, box.hi)
+    auto = O.deposit_hex(p.pos, p.values, box.lo, box.hi, box.shape)["S"]
+    forced = [auto[0] - 9, -1]
+    acc = torch.empty((2, mesh.cells), dtype=torch.int64, device="cuda")
+    fb = list(forced)
+    field = cgd.deposit(mesh, _t(p.pos, torch), _t(p.values, torch), acc=acc, frac_bits=fb)
+    torch.cuda.synchronize()
+    ref = O.deposit_hex(p.pos, p.values, box.lo, box.hi, box.shape, force_bits=forced)
+    assert fb == [auto[0] - 9, auto[1]] == ref["S"]
+    assert np.array_equal(acc.cpu().numpy(), ref["acc"])
+    assert np.array_equal(field.cpu().numpy().view(np.uint32), ref["field32"].view(np.uint32))
+    # a coarser scale changes the sums (so the forced value really was used)
+    assert not np.array_equal(ref["acc"][0], O.deposit_hex(p.pos, p.values, box.lo, box.hi, box.shape)["acc"][0])
+    for bad in ([63, -1], [-2, -1]):
+        with pytest.raises(cgd.CgdError):
+            cgd.deposit(mesh, _t(p.pos, torch), _t(p.values, torch), frac_bits=bad)
+
+
 @pytest.mark.parametrize("path", ["tiled", "direct"])
 def test_deposit_signed_multifield_ragged_and_dropped(gpu_lib, path, monkeypatch):
     """Both deposit paths: tile-bucketed sums in LDS (default) and direct

@@ -124,6 +124,37 @@ def test_tet_invalid_meshes(gpu_lib):
         cgd.TetMesh(xyz, np.concatenate([tets, tets[:1]]))  # a face shared by three tets
 
 
+def _check_location_by_definition(xyz, tets, pos, cell):
+    """Checks a located cell for every particle against the definition of
+    point location (the oracle's point_in_tets predicate: each face's float64
+    orientation on its vertices in increasing id order; inside means no face
+    puts the point strictly on the far side; lowest id on ties), vectorised
+    over (particle, cell) pairs:
+      - the cell contains the particle;
+      - a particle strictly inside its cell (every face value at least 1e-9
+        of the opposite vertex's, far beyond float64 rounding) lies in no
+        other tet of a conforming mesh, so the cell is the lowest containing id;
+      - the rest, near a face, edge or vertex, are located again by the
+        oracle's own search and must agree.
+    Returns the mask of particles near a face."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    T = np.asarray(tets, dtype=np.int64)[cell]
+    p = np.asarray(pos, dtype=np.float64)
+    assert O.point_in_tets(xyz, tets, p, cell).all()
+    margin = np.full(len(p), np.inf)
+    for opp, (i, j, k) in enumerate(((1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2))):
+        f = np.sort(T[:, [i, j, k]], axis=1)
+        a, b, c = xyz[f[:, 0]], xyz[f[:, 1]], xyz[f[:, 2]]
+        sp_ = O._orient(a, b, c, p)
+        sd = O._orient(a, b, c, xyz[T[:, opp]])
+        margin = np.minimum(margin, sp_ * np.sign(sd) / np.abs(sd))
+    assert (margin >= 0).all()
+    near = margin < 1e-9
+    if near.any():
+        assert np.array_equal(cell[near], O.locate_tets(xyz, tets, p[near]))
+    return near
+
+
 def test_unstructured_full_size_per_step_residuals(gpu_lib):
     """The unstructured workload at full size: 100^3 hexes x 6 jittered tets,
     5M particles, b = 0.04, 4 steps, Jacobi-PCG rtol 1e-6."""
@@ -135,20 +166,22 @@ def test_unstructured_full_size_per_step_residuals(gpu_lib):
     mesh = cgd.TetMesh(xyz, tets)
     pos = _t(parts.pos, torch)
     vals = _t(parts.values, torch)
-    # point location on a sample, one particle at a time in the oracle
+    # point location of every particle against the definition (the lowest
+    # id among the tets whose closed set contains the centroid)
     cell = cgd.locate(mesh, pos).cpu().numpy()
+    assert (cell >= 0).all()
+    near = _check_location_by_definition(xyz, tets, parts.pos, cell)
+    print(f"{int(near.sum())} particles near a face located by the oracle's search", flush=True)
     sample = np.random.default_rng(55).choice(len(parts.pos), 1000, replace=False)
     ref_cell = O.locate_tets(xyz, tets, parts.pos[sample].astype(np.float64))
     assert np.array_equal(cell[sample], ref_cell)
-    assert (cell >= 0).all()
-    # deposition given the located cells: exact sums
+    # deposition: the oracle's fixed-point sums over the cells just shown to
+    # be the definition's, bit for bit
     acc = torch.empty((1, mesh.cells), dtype=torch.int64, device="cuda")
     field, st = cgd.deposit(mesh, pos, vals, acc=acc, stats=True)
-    S = O.frac_bits(parts.values[0], len(parts.pos))
-    assert st.frac_bits[0] == S
-    q = O.quantise(parts.values[0], S)
-    want = np.bincount(cell, weights=None, minlength=mesh.cells) * int(q[0])  # equal values
-    assert np.array_equal(acc.cpu().numpy()[0], want)
+    want, S = O.deposit_cells(cell, cell >= 0, parts.values, mesh.cells)
+    assert st.frac_bits[0] == S[0]
+    assert np.array_equal(acc.cpu().numpy(), want)
     # diffusion one step at a time (b / 2 per call gives the same dtau)
     K, V = O.tet_tpfa(xyz, tets)
     dtau = b * b / 4.0 / steps

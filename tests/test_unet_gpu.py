@@ -207,3 +207,34 @@ def test_training_step_is_deterministic_and_descends(gpu_lib):
     assert runs[0][1] == runs[1][1]
     # uncorrelated random targets: the loss can only fall slowly, but it must fall
     assert runs[0][1][-1] < 0.8 * runs[0][1][0], runs[0][1]
+
+
+def test_adam_steps_match_oracle(gpu_lib):
+    """Three training steps: after each, the float32 master weights equal one
+    float64 Adam step (oracle adam_step, Kingma and Ba 2015, Algorithm 1) from
+    the weights before it, with the gradient the library reports for that
+    step and the moments carried over from the oracle's previous step.  The
+    difference allowed is float32 rounding of the weights and of the update:
+    1e-6 of |w| + 1e-4 of the learning rate."""
+    import torch
+    cgd = gpu_lib
+    shape = (16, 16, 16)
+    rng = np.random.default_rng(6001)
+    x = torch.from_numpy((0.5 + rng.random(4096)).astype(np.float32)).cuda()
+    t = torch.from_numpy((0.5 + rng.random(4096)).astype(np.float32)).cuda()
+    net = cgd.UNet(shape, seed=11)
+    lr = 2e-3
+    p = net.get_params().astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for step in range(1, 4):
+        net.train_step(x, t, lr)
+        g = net.get_grads().astype(np.float64)
+        got = net.get_params().astype(np.float64)
+        ref, m, v = U.adam_step(p, g, m, v, step, lr)
+        err = np.abs(got - ref)
+        bound = 1e-6 * np.abs(ref) + 1e-4 * lr
+        print(f"step {step}: max |w - w_ref| {err.max():.3e}, moved {np.abs(got - p).max():.3e}", flush=True)
+        assert (err <= bound).all(), (step, int(np.argmax(err - bound)), float(err.max()))
+        assert np.abs(got - p).max() > 0.5 * lr  # the step did move the weights
+        p = got

@@ -1,6 +1,7 @@
 """Pins of the U-Net oracle (oracle/unet_oracle.py) against things other
 than itself: scipy's n-d correlation, a brute-force loop, exact adjoint
-identities, central finite differences and torch's bfloat16 rounding."""
+identities, central finite differences, torch's bfloat16 rounding, and for
+the optimiser the closed forms of Adam's steps and torch.optim.Adam."""
 import numpy as np
 import pytest
 import scipy.ndimage as ndi
@@ -131,3 +132,38 @@ def test_bf16_round():
     a = _rng(10).standard_normal(100_000).astype(np.float32) * 1e3
     ref = torch.from_numpy(a).to(torch.bfloat16).to(torch.float32).numpy()
     np.testing.assert_array_equal(U.bf16_round(a), ref)
+
+
+def test_adam_closed_forms():
+    """Adam's first step moves every parameter by lr g / (|g| + eps) (the bias
+    corrections undo the zero start exactly), and so does every later step
+    under a constant gradient; a zero gradient leaves the parameter alone."""
+    rng = _rng(30)
+    p0 = rng.standard_normal(50)
+    g = rng.standard_normal(50) * 10.0 ** rng.integers(-6, 3, 50)
+    g[3] = 0.0
+    lr = 3e-3
+    p, m, v = U.adam_step(p0, g, np.zeros(50), np.zeros(50), 1, lr)
+    np.testing.assert_allclose(p, p0 - lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert p[3] == p0[3]
+    for t in range(2, 6):
+        q, m, v = U.adam_step(p, g, m, v, t, lr)
+        np.testing.assert_allclose(q - p, -lr * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-17)
+        p = q
+
+
+def test_adam_matches_torch_optim():
+    """Five steps with changing gradients against torch.optim.Adam (float64)."""
+    import torch
+    rng = _rng(31)
+    p0 = rng.standard_normal(200)
+    grads = [rng.standard_normal(200) * (0.1 + k) for k in range(5)]
+    w = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([w], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    p, m, v = p0.copy(), np.zeros(200), np.zeros(200)
+    for t, g in enumerate(grads, start=1):
+        opt.zero_grad()
+        w.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        p, m, v = U.adam_step(p, g, m, v, t, 1e-2)
+        np.testing.assert_allclose(p, w.detach().numpy(), rtol=1e-13, atol=1e-15)
