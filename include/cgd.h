@@ -206,6 +206,27 @@ cgd_status cgd_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F,
                        const float* values, float* field, int64_t* acc,
                        int32_t* frac_bits, cgd_solve_stats* st, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, serving loops that must not call hipMalloc, harnesses that forbid
+ * it): cgd_deposit on a uniform hex mesh, with the same kernels, results and
+ * automatic fixed-point scales, but its temporary buffers in one
+ * library-owned device array of 64 MiB per GPU (held until the process
+ * ends) instead of the mesh's workspace; it calls no hipMalloc, hipFree or
+ * other allocating routine.
+ *  n, pos, F, values, field, acc, stream: as in cgd_deposit (acc nullable;
+ *           no statistics, no forced scales; the call is asynchronous).
+ *  Limits: the tiled deposit's scratch, (8 + 4 F) bytes per particle plus
+ *           12 bytes per tile of 16384 / F cells, must fit 64 MiB - 4 KiB
+ *           (about 5.5M particles at F = 1, 2.8M at F = 4), and the grid at
+ *           most 8192 tiles; larger inputs return CGD_E_INVALID with the
+ *           sizes in cgd_last_error(), and other mesh kinds CGD_E_UNSUPPORTED,
+ *           before anything is enqueued.
+ *  Every call on a GPU uses that GPU's one array: calls that overlap on the
+ *  same GPU (from any stream, thread or mesh) race and must be ordered by
+ *  the caller.  Each call re-initialises what it reads. */
+cgd_status cgd_deposit_noalloc(cgd_mesh m, int64_t n, const float* pos, int32_t F,
+                               const float* values, float* field, int64_t* acc, void* stream);
+
 /* Diffusion of F cell fields in place (Sections 3.1, 3.2, 5.1).
  *
  * T = bandwidth^2 / 4, dtau = T / n_steps; each of the n_steps backward-Euler

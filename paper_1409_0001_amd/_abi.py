@@ -70,6 +70,8 @@ SIGNATURES = {
     "cgd_deposit": (ctypes.c_int32, [c_mesh, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.POINTER(SolveStats), ctypes.c_void_p]),
+    "cgd_deposit_noalloc": (ctypes.c_int32, [c_mesh, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cgd_diffuse": (ctypes.c_int32, [c_mesh, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
                                      ctypes.c_int32, ctypes.POINTER(SolverOpts),
                                      ctypes.POINTER(SolveStats), ctypes.c_void_p]),

@@ -296,7 +296,7 @@ static cgd_status do_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F,
     cgd_status rc = deposit_buffers(m, n, F, acc, &acc_buf, &info, &temp);
     if (rc != CGD_OK) return rc;
     if (m->kind == 0)
-        rc = deposit_hex(m, n, pos, F, values, field, acc_buf, info, temp, fs, s);
+        rc = deposit_hex(m, n, pos, F, values, field, acc_buf, info, temp, fs, &m->timing, s);
     else
         rc = deposit_tet(m, n, pos, F, values, field, acc_buf, info, fs, s);
     if (rc != CGD_OK || !(st || (frac_bits && need_auto))) return rc;

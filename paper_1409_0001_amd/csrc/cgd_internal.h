@@ -117,9 +117,10 @@ cgd_status ensure_pinned(cgd_mesh m, size_t bytes);
 // temp: deposit_hex_temp_bytes(m, n, F) bytes of device scratch for the tiled
 // path (nullptr or 0 bytes: the direct path, which needs acc).  On the tiled
 // path acc may be nullptr (the accumulators are then not written out).
+// timing: the mesh's timing records, or nullptr for no events at all.
 cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
                        float* field, int64_t* acc, DepositInfo* info_dev, void* temp, const ScaleForce& fs,
-                       hipStream_t s);
+                       Timing* timing, hipStream_t s);
 size_t deposit_hex_temp_bytes(const cgd_mesh m, int64_t n, int32_t F);
 
 // Tiled deposit of one or several snapshots on a mesh's hex grid (device

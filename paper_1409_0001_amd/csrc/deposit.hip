@@ -629,7 +629,7 @@ cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipS
 
 cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
                        float* field, int64_t* acc, DepositInfo* info, void* temp, const ScaleForce& fs,
-                       hipStream_t s) {
+                       Timing* timing, hipStream_t s) {
     const int64_t cells = m->cells;
     const int e_n = ceil_log2_count(n);
     const HexBin g = hex_bin(m);
@@ -652,15 +652,15 @@ cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
         d.acc = reinterpret_cast<long long*>(acc);
         d.temp = temp;
         hipLaunchKernelGGL(k_dep_init, dim3(1), dim3(64), 0, s, info, fs);
-        return tiled_deposit(m, d, &m->timing, s);
+        return tiled_deposit(m, d, timing, s);
     }
     deposit_prologue(n, F, values, acc, cells, info, fs, s);
     if (n > 0) {
         int dblocks = (int)std::min<int64_t>(16384, (n + kBlock - 1) / kBlock);
-        int t = timing_begin(&m->timing, s);
+        int t = timing ? timing_begin(timing, s) : -1;
         hipLaunchKernelGGL(k_deposit_hex, dim3(dblocks), dim3(kBlock), 0, s, pos, values, n, F, g,
                            e_n, reinterpret_cast<unsigned long long*>(acc), cells, info);
-        timing_end(&m->timing, t, 2, (12.0 + 12.0 * F) * (double)n, s);
+        if (timing) timing_end(timing, t, 2, (12.0 + 12.0 * F) * (double)n, s);
     }
     {
         int blocks = (int)std::min<int64_t>(8192, (cells + kBlock - 1) / kBlock);
