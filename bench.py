@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--scheme", default="be", choices=["be", "cn"],
                     help="dense workload's integrator: backward Euler (the headline) or Crank-Nicolson")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="dense workload only: skip the other workloads' short runs")
     ap.add_argument("--profile-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--workload", default="dense", choices=["dense", "batched", "unstructured", "learned", "stretched"],
@@ -254,8 +256,12 @@ def bench_batched(args):
             "speedup_vs_plain_cg": round(dt_plain / dt, 3),
             "speedup_vs_looped": round(dt_loop / dt, 3),
             "solver_GBs_algorithmic_over_whole_call": round(alg_bytes / dt / 1e9, 1),
-            "rel_l2_sampled": rel}
-    print(json.dumps(line))
+            "rel_l2_sampled": rel,
+            "stats_sample": {"snapshot0_frac_bits": bstats[0].frac_bits, "snapshot0_n_dropped": bstats[0].n_dropped,
+                             "max_rel_mass_change": max(abs(a - b_) / max(abs(b_), 1e-300)
+                                                        for st_ in bstats for a, b_ in zip(st_.mass_after,
+                                                                                           st_.mass_before))}}
+    return line
 
 
 def bench_unstructured(args):
@@ -301,7 +307,7 @@ def bench_unstructured(args):
                                    "steps, Jacobi-PCG rtol 1e-6", "cells": int(mesh.cells), "nnz": mesh.nnz,
                        "pcg_iters_per_step": [r[0] for r in st.iters]},
             "kernels": rl}
-    print(json.dumps(line))
+    return line
 
 
 def bench_stretched(args):
@@ -361,7 +367,7 @@ def bench_stretched(args):
                        "cells": int(mesh.cells), "nnz": mesh.nnz,
                        "pcg_iters_per_step": [r[0] for r in st.iters]},
             "kernels": rl}
-    print(json.dumps(line))
+    return line
 
 
 def bench_learned(args):
@@ -437,7 +443,7 @@ def bench_learned(args):
             "train": {"seconds": round(t_train, 1), "loss_first": losses[0][1], "loss_last": losses[-1][1],
                       "pairs": args.train_snapshots * steps},
             "rel_l2_first_test_snapshot": rel}
-    print(json.dumps(line))
+    return line
 
 
 def main():
@@ -452,14 +458,11 @@ def main():
     import paper_1409_0001_amd as cgd
     from paper_1409_0001_amd import inputs
 
-    if args.workload == "batched":
-        return bench_batched(args)
-    if args.workload == "unstructured":
-        return bench_unstructured(args)
-    if args.workload == "stretched":
-        return bench_stretched(args)
-    if args.workload == "learned":
-        return bench_learned(args)
+    one = {"batched": bench_batched, "unstructured": bench_unstructured, "stretched": bench_stretched,
+           "learned": bench_learned}
+    if args.workload in one:
+        print(json.dumps(one[args.workload](args)), flush=True)
+        return
     if args.profile_copy:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
@@ -477,58 +480,11 @@ def main():
     pos = torch.from_numpy(w.particles.pos).cuda()
     vals = torch.from_numpy(w.particles.values).cuda()
     mesh = cgd.HexMesh(w.box.shape, w.box.lo, w.box.hi)
-    out = torch.empty((args.fields, mesh.cells), dtype=torch.float32, device="cuda")
-    kw = dict(rtol=args.rtol, check_every=args.check_every, field=out, scheme=args.scheme)
-
-    for _ in range(args.warmup):
-        cgd.coarse_grain(mesh, pos, vals, w.bandwidth, w.n_steps, **kw)
-    _, st = cgd.coarse_grain(mesh, pos, vals, w.bandwidth, w.n_steps, stats=True, **kw)
-    iters = [row[0] for row in st.iters]
-    print(f"[bench] warm: CG iterations per step {iters}", file=sys.stderr, flush=True)
-
-    # The per-kernel HIP events bracket the launches of the last timed step
-    # only: each event pair idles the queue for a few microseconds, which
-    # would otherwise be charged to every step's throughput.
-    cgd.timing_read(mesh, reset=True)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for i in range(args.steps):
-        if i == args.steps - 1:
-            cgd.timing_enable(mesh, True)
-        cgd.coarse_grain(mesh, pos, vals, w.bandwidth, w.n_steps, **kw)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t
-    cgd.timing_enable(mesh, False)
-    tim = cgd.timing_read(mesh, reset=True)
-    ms_per_step = 1e3 * dt / args.steps
-    value = args.fields * args.steps / dt
-    print(f"[bench] {ms_per_step:.2f} ms/step, {value:.2f} fields/s", file=sys.stderr, flush=True)
-
-    roofline = roofline_of(tim, ms_per_step / args.fields)
-
-    rel = None
-    bit_exact = None
-    if not args.no_check:
-        from oracle import cgd_oracle as O
-        dep = O.deposit_hex(w.particles.pos, w.particles.values, w.box.lo, w.box.hi, w.box.shape)
-        ref = O.diffuse_hex_dct(dep["field64"], w.box.lo, w.box.hi, w.box.shape, w.bandwidth, w.n_steps,
-                                scheme=args.scheme)
-        got = out.cpu().numpy().astype(np.float64)
-        rel = max(float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])) for f in range(args.fields))
-        print(f"[bench] rel L2 vs float64 oracle {rel:.3e}", file=sys.stderr, flush=True)
-        # the timed call's deposit, repeated with its accumulators written out,
-        # against the oracle's: int64 sums and float32 field bit for bit
-        acc = torch.empty((args.fields, mesh.cells), dtype=torch.int64, device="cuda")
-        dfield, dst = cgd.deposit(mesh, pos, vals, acc=acc, stats=True)
-        bit_exact = (dst.frac_bits == list(dep["S"]) and np.array_equal(acc.cpu().numpy(), dep["acc"])
-                     and np.array_equal(dfield.cpu().numpy().view(np.uint32), dep["field32"].view(np.uint32)))
-        del acc, dfield
-        print(f"[bench] deposit bit-exact vs oracle: {bit_exact}", file=sys.stderr, flush=True)
-
+    r = run_dense(args, w, mesh, pos, vals, args.scheme, args.steps, args.warmup, check=not args.no_check)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
     line = {
-        "metric": METRIC, "value": round(value, 3), "unit": "fields/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "metric": METRIC, "value": round(r["value"], 3), "unit": "fields/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_per_field"] * args.fields, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"dense bed {shape[0]}x{shape[1]}x{shape[2]} hex, box 1x1x2, "
@@ -537,16 +493,130 @@ def main():
                                f"steps, CG preconditioned by a Chebyshev polynomial of A (degree 4, 8 or 12 by predicted "
                                f"cost{'; 12 at dtau/h^2 = 1' if args.scheme == 'be' else ''}), rtol {args.rtol:g}",
                    "particles": args.particles, "cells": int(mesh.cells), "fields": args.fields,
-                   "cg_iters_per_step": iters},
-        "rel_l2": rel,
-        "deposit_bit_exact": bit_exact,
-        "roofline": roofline,
+                   "cg_iters_per_step": r["iters"]},
+        "rel_l2": r["rel_l2"],
+        "deposit_bit_exact": r["deposit_bit_exact"],
+        "roofline": r["roofline"],
         "cpu_baseline": cpu,
     }
+    if not args.no_secondary and args.workload == "dense" and shape == (256, 256, 512) and args.fields == 1:
+        line["secondary"] = secondary(args, w, mesh, pos, vals)
     print(json.dumps(line), flush=True)
-    if bit_exact is False or (rel is not None and rel > 1e-5):
+    if r["deposit_bit_exact"] is False or (r["rel_l2"] is not None and r["rel_l2"] > 1e-5):
         print("[bench] accuracy gate failed", file=sys.stderr, flush=True)
         sys.exit(1)
+
+
+def run_dense(args, w, mesh, pos, vals, scheme, steps, warmup, check=True):
+    """Timed coarse_grain calls of one hex workload: throughput, per-kernel
+    roofline from the last timed call, and (check) rel L2 against the oracle
+    and the deposit bit for bit."""
+    import numpy as np
+    import torch
+
+    import paper_1409_0001_amd as cgd
+    F = int(vals.shape[0])
+    out = torch.empty((F, mesh.cells), dtype=torch.float32, device="cuda")
+    kw = dict(rtol=args.rtol, check_every=args.check_every, field=out, scheme=scheme)
+    for _ in range(warmup):
+        cgd.coarse_grain(mesh, pos, vals, w.bandwidth, w.n_steps, **kw)
+    _, st = cgd.coarse_grain(mesh, pos, vals, w.bandwidth, w.n_steps, stats=True, **kw)
+    iters = [row[0] for row in st.iters]
+    print(f"[bench] {w.name} {scheme}: CG iterations per step {iters}", file=sys.stderr, flush=True)
+    # The per-kernel HIP events bracket the launches of the last timed step
+    # only: each event pair idles the queue for a few microseconds, which
+    # would otherwise be charged to every step's throughput.
+    cgd.timing_read(mesh, reset=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(steps):
+        if i == steps - 1:
+            cgd.timing_enable(mesh, True)
+        cgd.coarse_grain(mesh, pos, vals, w.bandwidth, w.n_steps, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    cgd.timing_enable(mesh, False)
+    tim = cgd.timing_read(mesh, reset=True)
+    ms_per_field = 1e3 * dt / (steps * F)
+    value = F * steps / dt
+    print(f"[bench] {w.name} {scheme}: {ms_per_field:.2f} ms per field, {value:.2f} fields/s",
+          file=sys.stderr, flush=True)
+    res = {"value": value, "ms_per_field": ms_per_field, "iters": iters, "roofline": roofline_of(tim, ms_per_field),
+           "rel_l2": None, "deposit_bit_exact": None}
+    if check:
+        from oracle import cgd_oracle as O
+        dep = O.deposit_hex(w.particles.pos, w.particles.values, w.box.lo, w.box.hi, w.box.shape)
+        ref = O.diffuse_hex_dct(dep["field64"], w.box.lo, w.box.hi, w.box.shape, w.bandwidth, w.n_steps,
+                                scheme=scheme)
+        got = out.cpu().numpy().astype(np.float64)
+        res["rel_l2"] = max(float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])) for f in range(F))
+        print(f"[bench] rel L2 vs float64 oracle {res['rel_l2']:.3e}", file=sys.stderr, flush=True)
+        # the timed call's deposit, repeated with its accumulators written out,
+        # against the oracle's: int64 sums and float32 field bit for bit
+        acc = torch.empty((F, mesh.cells), dtype=torch.int64, device="cuda")
+        dfield, dst = cgd.deposit(mesh, pos, vals, acc=acc, stats=True)
+        res["deposit_bit_exact"] = bool(
+            dst.frac_bits == list(dep["S"]) and np.array_equal(acc.cpu().numpy(), dep["acc"])
+            and np.array_equal(dfield.cpu().numpy().view(np.uint32), dep["field32"].view(np.uint32)))
+        del acc, dfield
+        print(f"[bench] deposit bit-exact vs oracle: {res['deposit_bit_exact']}", file=sys.stderr, flush=True)
+    return res
+
+
+def secondary(args, w, mesh, pos, vals):
+    """The other workloads, at their full sizes with few timed calls, so that
+    the default run reports them too: Crank-Nicolson on the dense bed, the
+    literal 256^3 cube, the batched launch, the unstructured and stretched
+    meshes, and a reduced learned-guess sample."""
+    import torch
+
+    import paper_1409_0001_amd as cgd
+    from paper_1409_0001_amd import inputs
+    out = {}
+
+    def guarded(name, fn):
+        t = time.perf_counter()
+        try:
+            out[name] = fn()
+        except Exception as e:  # a failing secondary workload must not hide the headline
+            out[name] = {"error": f"{type(e).__name__}: {e}"}
+        print(f"[bench] secondary {name} done in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
+
+    def cn():
+        r = run_dense(args, w, mesh, pos, vals, "cn", 5, 1, check=True)
+        return {"workload": "dense bed 256x256x512, 20M particles, 4 Crank-Nicolson steps", "unit": "fields/s",
+                "value": round(r["value"], 2), "ms_per_field": round(r["ms_per_field"], 3),
+                "cg_iters_per_step": r["iters"], "rel_l2": r["rel_l2"],
+                "roofline_dominant": {k: r["roofline"][k] for k in ("kernel", "avg_us", "frac")},
+                "whole_solve_frac": r["roofline"]["whole_solve"]["frac"]}
+
+    def cube():
+        wc = inputs.dense_bed(n_particles=10_000_000, shape=(256, 256, 256), depth=1.0)
+        mc = cgd.HexMesh(wc.box.shape, wc.box.lo, wc.box.hi)
+        pc = torch.from_numpy(wc.particles.pos).cuda()
+        vc = torch.from_numpy(wc.particles.values).cuda()
+        r = run_dense(args, wc, mc, pc, vc, "be", 5, 1, check=True)
+        mc.close()
+        return {"workload": "dense bed in the unit cube, 256^3 hex (h = 1/256), 10M particles, 4 backward-Euler "
+                            "steps", "unit": "fields/s", "value": round(r["value"], 2),
+                "ms_per_field": round(r["ms_per_field"], 3), "cg_iters_per_step": r["iters"],
+                "rel_l2": r["rel_l2"], "deposit_bit_exact": r["deposit_bit_exact"],
+                "roofline_dominant": {k: r["roofline"][k] for k in ("kernel", "avg_us", "frac")},
+                "whole_solve_frac": r["roofline"]["whole_solve"]["frac"]}
+
+    def sub(fn, **over):
+        a = argparse.Namespace(**vars(args))
+        for k, v in over.items():
+            setattr(a, k, v)
+        return fn(a)
+
+    guarded("dense_crank_nicolson", cn)
+    guarded("cube_256", cube)
+    guarded("stretched", lambda: sub(bench_stretched, steps=2, warmup=1, no_check=False))
+    guarded("unstructured", lambda: sub(bench_unstructured, steps=3, warmup=1))
+    guarded("batched", lambda: sub(bench_batched, steps=2, warmup=1, snapshots=64, no_check=False))
+    guarded("learned_reduced", lambda: sub(bench_learned, train_snapshots=100, test_snapshots=16, no_check=False))
+    return out
 
 
 if __name__ == "__main__":

@@ -90,22 +90,24 @@ def _clumps(rng, n, n_clumps, sigma, lo, hi):
 
 
 def dense_bed(n_particles: int = 20_000_000, shape=(256, 256, 512), n_fields: int = 1,
-              seed: int = SEED_BASE + 2) -> Workload:
-    """Dense particle bed in a 1 x 1 x 2 box (h = 1/256 at the full shape).
+              seed: int = SEED_BASE + 2, depth: float = 2.0) -> Workload:
+    """Dense particle bed in a 1 x 1 x depth box (depth 2: h = 1/256 at the
+    full shape; depth 1 with 256^3 cells and half the particles is the same
+    bed in a cube, at the same per-volume density).
 
     Lognormal diameters (median 0.003, sigma 0.3).  70 % of the spheres are
-    uniform in the bottom quarter [0,1]^2 x [0,0.5]; 30 % sit in 50 Gaussian
-    clumps (sigma 0.05) with uniform centres.  Field 0 is the sphere volume;
-    fields 1..3 (when n_fields = 4) are drag components drawn N(0, 1).
+    uniform in the bottom quarter [0,1]^2 x [0,depth/4]; 30 % sit in 50
+    Gaussian clumps (sigma 0.05) with uniform centres.  Field 0 is the sphere
+    volume; fields 1..3 (when n_fields = 4) are drag components drawn N(0, 1).
     Bandwidth b = 4 cell widths of the x spacing, 4 pseudo-steps, rtol 1e-6.
     A smaller shape keeps the box and the per-volume particle density when
     n_particles is scaled by the cell-count ratio.
     """
     rng = np.random.default_rng(seed)
-    lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 2.0)
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, float(depth))
     n_bed = int(round(0.7 * n_particles))
     n_clump = n_particles - n_bed
-    bed = rng.random((n_bed, 3)) * np.array([1.0, 1.0, 0.5])
+    bed = rng.random((n_bed, 3)) * np.array([1.0, 1.0, depth / 4.0])
     cl = _clumps(rng, n_clump, 50, 0.05, lo, hi)
     pos = np.concatenate([bed, cl]).astype(np.float32)
     del bed, cl
