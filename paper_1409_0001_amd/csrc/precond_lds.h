@@ -178,11 +178,14 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     const int t1 = ze - 1 + D;           // last step (plane ze - 1 of z completes)
     (void)g;
 
-    Vec<VEC> rk[6];                         // r of this row, plane t0 + s at slot s mod 6
+    // r of this row, plane t0 + s at slot s mod RK: Horner (FORM 0) weights r
+    // at every level (planes t - 1 .. t - D); the product form only at level 2
+    constexpr int RK = FORM == 0 ? 6 : 3;
+    Vec<VEC> rk[RK];
     Vec<VEC> lv[D > 2 ? D - 2 : 1][3];      // level j >= 2's u of this row, plane t0 + s at slot s mod 3
     Vec<VEC> u1;                            // level 1's u of this row formed at the current step
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < RK; ++i)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) rk[i].f[e] = 0.f;
 #pragma unroll
@@ -220,7 +223,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 pf[B][i] = ldv<VEC>(src + (size_t)tn * plane + ysrc(e));
             }
         }
-        if (w < E0) rk[S % 6] = ld(row0(t, w));  // own row of r at plane t (written at step t - 1)
+        if (w < E0) rk[S % RK] = ld(row0(t, w));  // own row of r at plane t (written at step t - 1)
 
         // Level j's rows y - 1 and y + 1 (level j - 1 at plane t - j, this
         // row itself at a wall) and level 2's planes q, q - 1 of level 1 were
@@ -267,9 +270,9 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 // from its register ring
                 Vec<VEC> c, zl, zh;
                 if (j == 1) {
-                    c = rk[((S - j) % 6 + 6) % 6];
-                    zl = rk[((S - j - 1) % 6 + 6) % 6];
-                    zh = rk[((S - j + 1) % 6 + 6) % 6];
+                    c = rk[((S - j) % RK + RK) % RK];
+                    zl = rk[((S - j - 1) % RK + RK) % RK];
+                    zh = rk[((S - j + 1) % RK + RK) % RK];
                 } else if (j == 2) {
                     c = c2;
                     zl = zl2;
@@ -280,7 +283,9 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                     zl = lv[jr][((S - j - 1) % 3 + 3) % 3];
                     zh = lv[jr][((S - j + 1) % 3 + 3) % 3];
                 }
-                const Vec<VEC>& rq = rk[((S - j) % 6 + 6) % 6];  // level 0 (r or v) of this row at plane q
+                // level 0 (r or v) of this row at plane q (FORM 1, 2: used at
+                // levels 1 and 2 only, planes the 3-plane ring holds)
+                const Vec<VEC>& rq = rk[((S - j) % RK + RK) % RK];
                 // the level's extra term: r (FORM 0), v at level 2 and u2 at
                 // level 4 (FORM 1, 2), none at odd levels of FORM 1, 2
                 const Vec<VEC>& ex = (FORM != 0 && j == 4) ? lv[0][((S - 4) % 3 + 3) % 3] : rq;
@@ -326,6 +331,11 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                     }
                 }
                 if (j == 1) u1 = u;
+                if (FIRST && FORM == 1 && j == 1 && owner && q >= zb && q < ze) {
+                    // b.b over the output cells, from this row's b at plane q
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc1 = fma((double)c.f[e], (double)c.f[e], acc1);
+                }
                 if (j < D) stv<VEC>(rowj(j, q, w - j), u);
                 // levels >= 2 keep their planes in a register ring; a slot
                 // not written here keeps an older, finite plane that is only
@@ -342,7 +352,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
                         if (FORM == 0) acc0 = fma((double)rq.f[e], (double)u.f[e], acc0);
-                        if (FIRST && FORM != 2) acc1 = fma((double)rq.f[e], (double)rq.f[e], acc1);
+                        if (FIRST && FORM == 0) acc1 = fma((double)rq.f[e], (double)rq.f[e], acc1);
                     }
                 }
             }
