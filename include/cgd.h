@@ -282,14 +282,22 @@ cgd_status cgd_velocity_from_momentum(int64_t cells, int32_t n_comp, const float
  * Deposition follows cgd_deposit per snapshot (its own fixed-point scale per
  * snapshot and field).  All n_snap * F right-hand sides are then solved from
  * a zero initial guess by CG preconditioned with a Chebyshev polynomial of
- * the operator, of degree 2, 4 or 12 as the autotuner chose (o->precond = 1:
- * plain CG), with float32
- * vectors, float64 inner products, and the stencil and stopping rule of
- * cgd_diffuse, in ONE persistent launch in which each workgroup solves its
- * share of the right-hand sides one after the other.  The
- * call is captured in a hipGraph on first use for a given argument set and
- * replayed afterwards; the tile shape is chosen by cgd_autotune_batched (run
- * automatically on first use).
+ * the operator (o->precond = 1: plain CG), with float32 vectors, float64
+ * inner products, and the stencil and stopping rule of cgd_diffuse, by the
+ * candidate cgd_autotune_batched chose (run automatically on first use):
+ *  - ONE persistent launch in which each workgroup solves its share of the
+ *    right-hand sides one after the other, at a tile shape and a polynomial
+ *    degree of 2, 4 or 12 (nx = 64, 128 or 256); or
+ *  - the launches of cgd_diffuse over groups of up to CGD_MAX_FIELDS
+ *    right-hand sides (any nx; degree 12 where its LDS sweep applies), each
+ *    step with a fixed budget of iterations: the most any right-hand side
+ *    took in the run that made the graph.  A replay that leaves a right-hand
+ *    side above the tolerance is followed by the same call with read-backs
+ *    of the convergence state, so every result meets the stopping rule.
+ * The whole call (offset upload, deposit, solve, statistics read-back) is
+ * captured in a hipGraph for a given argument set and replayed afterwards
+ * (the per-launch candidate first runs once with read-backs to learn its
+ * budgets).
  *
  *  n_snap:  1.. ; n_snap * F <= 4096
  *  offsets: HOST int64 [n_snap + 1]; snapshot j owns particles
@@ -305,21 +313,23 @@ cgd_status cgd_velocity_from_momentum(int64_t cells, int32_t n_comp, const float
  *           fixed-point scale of each field, dropped and non-finite particles,
  *           and the snapshot's worst status (n_fallback 0).  Asking for st adds
  *           two float64 sums over all fields to the launch.
- * Hex meshes with nx in {64, 128, 256} only (CGD_E_UNSUPPORTED otherwise).
- * The call waits for its stream before returning. */
+ * Uniform hex meshes only (CGD_E_UNSUPPORTED otherwise).  The call waits
+ * for its stream before returning. */
 cgd_status cgd_coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offsets,
                                     const float* pos, int32_t F, const float* values,
                                     double bandwidth, int32_t n_steps, const cgd_solver_opts* o,
                                     float* fields, cgd_solve_stats* st, void* stream);
 
-/* Autotuner of the batched solver: times each candidate (rows per wave,
- * waves per workgroup, preconditioner degree 2, 4 or 12) solving n_rhs synthetic
- * right-hand sides for one backward-Euler step at dtau / h^2 = 1 to rtol
- * 1e-6, and keeps the fastest for this mesh shape (also appended to the file
- * named by the environment variable CGD_AUTOTUNE_CACHE, when set, and read
- * from it).
+/* Autotuner of the batched solver: times each candidate solving n_rhs
+ * synthetic right-hand sides for one backward-Euler step at dtau / h^2 = 1
+ * to rtol 1e-6, and keeps the fastest for this mesh shape (also appended to
+ * the file named by the environment variable CGD_AUTOTUNE_CACHE, when set,
+ * and read from it).  Candidates: where nx is 64, 128 or 256, indices 0..7
+ * are the persistent launch (rows per wave, waves per workgroup and
+ * preconditioner degree 2, 2, 2, 2, 4, 4, 12, 12); the last index is the
+ * per-launch solver over groups of right-hand sides.
  *  chosen: host, written with the chosen candidate index
- *  ms:     host double [8] or NULL: time of each candidate (forces a re-run)
+ *  ms:     host double [16] or NULL: time of each candidate (forces a re-run)
  *  n_cand: host, written with the number of candidates (nullable) */
 cgd_status cgd_autotune_batched(cgd_mesh m, int32_t n_rhs, int32_t* chosen, double* ms, int32_t* n_cand);
 

@@ -331,7 +331,7 @@ def coarse_grain_batched(mesh: HexMesh, offsets, pos, values, bandwidth, n_steps
 def autotune_batched(mesh: HexMesh, n_rhs: int):
     """Times the batched solver's tile candidates; returns (chosen, [ms per candidate])."""
     _torch()
-    ms = (ctypes.c_double * 8)()
+    ms = (ctypes.c_double * 16)()
     chosen = ctypes.c_int32()
     nc = ctypes.c_int32()
     _check(_abi.load().cgd_autotune_batched(mesh.handle, int(n_rhs), ctypes.byref(chosen), ms,

@@ -24,6 +24,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "cg_common.h"
 #include "hex_bin.h"
@@ -572,7 +573,7 @@ struct BatchedGraph {
     std::string key;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    uint64_t ws_gen = 0;
+    std::vector<int> budget;  // per-launch candidate: iterations per step in the captured solve
 };
 
 }  // namespace cgd
@@ -591,17 +592,68 @@ void destroy_batched(cgd_mesh m) {
     g_graphs.erase(it);
 }
 
-// Times every candidate on min(n_rhs, resident) synthetic right-hand sides
+// Right-hand sides per call of the per-launch candidate's solver.
+constexpr int kGroup = CGD_MAX_FIELDS;
+
+// Statistics of one group's solve (the small region of its workspace: int32
+// iters / status and double relres, [step][CGD_MAX_FIELDS]) into the batched
+// arrays (iters, relres [rhs][n_steps]; status [rhs], the worst over steps).
+__global__ void k_gather_group(const int32_t* __restrict__ g_iters, const double* __restrict__ g_relres,
+                               const int32_t* __restrict__ g_status, int r0, int nf, int n_steps,
+                               int32_t* __restrict__ iters, double* __restrict__ relres, int32_t* __restrict__ status) {
+    const int f = threadIdx.x;
+    if (f >= nf) return;
+    int worst = CGD_OK;
+    for (int st = 0; st < n_steps; ++st) {
+        iters[(size_t)(r0 + f) * n_steps + st] = g_iters[st * CGD_MAX_FIELDS + f];
+        relres[(size_t)(r0 + f) * n_steps + st] = g_relres[st * CGD_MAX_FIELDS + f];
+        const int v = g_status[st * CGD_MAX_FIELDS + f];
+        if (v == CGD_E_BREAKDOWN || (v == CGD_NOT_CONVERGED && worst == CGD_OK)) worst = v;
+    }
+    status[r0 + f] = worst;
+}
+
+// The per-launch candidate: the single-call solver of cg_hex.hip (degree 12
+// by default on these grids: three LDS product passes, two iterations per
+// step at dtau / h^2 = 1) over groups of up to CGD_MAX_FIELDS right-hand
+// sides, each launch covering all of the group's fields.  fixed: iterations
+// per step (capturable) or nullptr (host read-backs).  Its workspace starts at
+// `base` (diffuse_hex_workspace(m, kGroup) bytes).
+static cgd_status solve_grouped(cgd_mesh m, float* fields, int n_rhs, const DiffuseArgs& da, char* base,
+                                const int* fixed, int32_t* iters, double* relres, int32_t* status, hipStream_t q) {
+    const bool timing = m->timing.on;
+    m->timing.on = false;  // no events inside the batched call (it may be captured)
+    cgd_status rc = CGD_OK;
+    for (int r0 = 0; r0 < n_rhs && rc == CGD_OK; r0 += kGroup) {
+        DiffuseArgs dg = da;
+        dg.F = std::min(kGroup, n_rhs - r0);
+        dg.field = fields + (size_t)r0 * m->cells;
+        dg.x0_mode = 0;
+        dg.x0 = nullptr;
+        dg.model = nullptr;
+        rc = diffuse_hex_enqueue(m, dg, base, fixed, false, q);
+        if (rc == CGD_OK) {
+            hipLaunchKernelGGL(k_gather_group, dim3(1), dim3(64), 0, q, reinterpret_cast<int32_t*>(base + kOffIters),
+                               reinterpret_cast<double*>(base + kOffRelres),
+                               reinterpret_cast<int32_t*>(base + kOffStatus), r0, dg.F, da.n_steps, iters, relres,
+                               status);
+            rc = hipGetLastError() == hipSuccess ? CGD_OK : CGD_E_HIP;
+        }
+    }
+    m->timing.on = timing;
+    return rc;
+}
+
+// Times each candidate on min(n_rhs, resident) synthetic right-hand sides
 // (one backward-Euler step at dtau / h^2 = 1, solved to rtol 1e-6) and
-// returns the fastest.
+// returns the fastest.  Candidates 0..7: the persistent launch (nx = 64, 128
+// or 256 only); the last: the per-launch solver over groups of fields.
 cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, int* n_cand) {
     const HexGeom& g = m->hex;
     const int vec = batched_vec(g);
-    if (!vec) {
-        set_error("batched solver: nx must be 64, 128 or 256");
-        return CGD_E_UNSUPPORTED;
-    }
-    std::vector<Cfg> cs = candidates(vec);
+    const std::vector<Cfg> cs = vec ? candidates(vec) : std::vector<Cfg>();
+    const int nc = (int)cs.size() + 1;
+    const int c_launch = (int)cs.size();
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         static bool loaded = false;
@@ -610,20 +662,23 @@ cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, 
             loaded = true;
         }
         auto it = g_tune.find(tune_key(g, n_rhs));
-        if (it != g_tune.end() && it->second >= 0 && it->second < (int)cs.size() && !ms_out) {
+        if (it != g_tune.end() && it->second >= 0 && it->second < nc && !ms_out) {
             *chosen = it->second;
-            if (n_cand) *n_cand = (int)cs.size();
+            if (n_cand) *n_cand = nc;
             return CGD_OK;
         }
     }
-    int gmax = 1;
+    int gmax = std::min(n_rhs, 4 * kGroup);
     for (const Cfg& c : cs) gmax = std::max(gmax, grid_for(c, n_rhs));
     const int nr = std::min(n_rhs, gmax);
     const size_t cells = (size_t)m->cells;
     CGD_HIP_TRY(hipDeviceSynchronize());
     const BLayout L = batched_layout(nr, 1, 1);
     const size_t small = L.small;
-    cgd_status rc = ensure_workspace(m, small + (size_t)nr * cells * 4 + (size_t)gmax * 5 * cells * 4);
+    const size_t scratch_bytes = std::max((size_t)gmax * 5 * cells * 4, diffuse_hex_workspace(m, kGroup));
+    cgd_status rc = ensure_workspace(m, small + (size_t)nr * cells * 4 + scratch_bytes);
+    if (rc != CGD_OK) return rc;
+    rc = ensure_pinned(m, kPinBytes);
     if (rc != CGD_OK) return rc;
     char* base = static_cast<char*>(m->ws.ptr);
     float* fields = reinterpret_cast<float*>(base + small);
@@ -661,18 +716,29 @@ cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, 
     a.iters = iters;
     a.relres = relres;
     a.status = status;
+    // the per-launch candidate: the same step (dtau = h_x^2, so c_x = 1)
+    DiffuseArgs dl = {};
+    dl.bandwidth = 2.0 * g.h[0];
+    dl.n_steps = 1;
+    dl.rtol = 1e-6;
+    dl.max_iter = 100;
+    dl.check_every = 4;
     double best = 1e30;
     int best_i = 0;
-    for (size_t i = 0; i < cs.size(); ++i) {
-        const Cfg& c = cs[i];
-        a.xsegs = 1;
-        a.ygroups = (g.ny + c.ty - 1) / c.ty;
-        const int grid = grid_for(c, nr);
+    for (int i = 0; i < nc; ++i) {
         double ms_best = 1e30;
         for (int rep = 0; rep < 3; ++rep) {
             hipLaunchKernelGGL(k_fill_synthetic, dim3(2048), dim3(256), 0, s, fields, (int64_t)(nr * cells));
             CGD_HIP_TRY(hipEventRecord(e0, s));
-            rc = launch_solver(c, a, grid, s);
+            if (i == c_launch) {
+                rc = solve_grouped(m, fields, nr, dl, reinterpret_cast<char*>(scratch), nullptr, iters, relres,
+                                   status, s);
+            } else {
+                const Cfg& c = cs[i];
+                a.xsegs = 1;
+                a.ygroups = (g.ny + c.ty - 1) / c.ty;
+                rc = launch_solver(c, a, grid_for(c, nr), s);
+            }
             if (rc != CGD_OK) break;
             CGD_HIP_TRY(hipEventRecord(e1, s));
             CGD_HIP_TRY(hipEventSynchronize(e1));
@@ -684,7 +750,7 @@ cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, 
         if (ms_out) ms_out[i] = ms_best;
         if (ms_best < best) {
             best = ms_best;
-            best_i = (int)i;
+            best_i = i;
         }
     }
     (void)hipEventDestroy(e0);
@@ -698,7 +764,7 @@ cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, 
         save_tune_file(key, best_i, best);
     }
     *chosen = best_i;
-    if (n_cand) *n_cand = (int)cs.size();
+    if (n_cand) *n_cand = nc;
     return CGD_OK;
 }
 
@@ -712,32 +778,39 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     int ci = 0;
     cgd_status rc = autotune_batched(m, n_rhs, &ci, nullptr, nullptr);
     if (rc != CGD_OK) return rc;
-    const std::vector<Cfg> cands = candidates(batched_vec(g));
+    const int vec = batched_vec(g);
+    const std::vector<Cfg> cands = vec ? candidates(vec) : std::vector<Cfg>();
+    const int c_launch = (int)cands.size();
     if (const char* e = getenv("CGD_BATCHED_CFG")) {  // a fixed candidate, for tests and tuning runs
         const int v = atoi(e);
-        if (v >= 0 && v < (int)cands.size()) ci = v;
+        if (v >= 0 && v <= c_launch) ci = v;
     }
-    Cfg c = cands[ci];
-    if (da.precond != 0 && c.deg >= 4) {
-        // plain CG: the degree-2 configuration of the same shape (else the
-        // 16-wave one), whose kernel carries the unpreconditioned path
-        int alt = -1;
-        for (int i = 0; i < (int)cands.size(); ++i)
-            if (cands[i].deg == 2 && cands[i].ty == c.ty && cands[i].nw == c.nw) alt = i;
-        if (alt < 0)
-            for (int i = 0; i < (int)cands.size(); ++i)
-                if (cands[i].deg == 2 && cands[i].nw == 16) alt = i;
-        ci = alt;
+    const bool per_launch = ci == c_launch;
+    Cfg c = {};
+    if (!per_launch) {
         c = cands[ci];
+        if (da.precond != 0 && c.deg >= 4) {
+            // plain CG: the degree-2 configuration of the same shape (else the
+            // 16-wave one), whose kernel carries the unpreconditioned path
+            int alt = -1;
+            for (int i = 0; i < (int)cands.size(); ++i)
+                if (cands[i].deg == 2 && cands[i].ty == c.ty && cands[i].nw == c.nw) alt = i;
+            if (alt < 0)
+                for (int i = 0; i < (int)cands.size(); ++i)
+                    if (cands[i].deg == 2 && cands[i].nw == 16) alt = i;
+            ci = alt;
+            c = cands[ci];
+        }
     }
-    const int grid = grid_for(c, n_rhs);
+    const int grid = per_launch ? 0 : grid_for(c, n_rhs);
     const BLayout L = batched_layout(n_rhs, n_snap, da.n_steps);
     const size_t small = L.small;
     // deposit: the tiled path's bucketed records, else int64 accumulators
     const size_t tile_bytes = tiled_deposit_temp_bytes((int64_t)cells, total, n_snap, F);
     const bool tiled = tile_bytes > 0;
     const size_t dep_bytes = tiled ? tile_bytes : (size_t)n_rhs * cells * 8;
-    const size_t solver_bytes = (size_t)grid * 5 * cells * 4;
+    const size_t solver_bytes = per_launch ? diffuse_hex_workspace(m, std::min(kGroup, n_rhs))
+                                           : (size_t)grid * 5 * cells * 4;
     rc = ensure_workspace(m, small + std::max(dep_bytes, solver_bytes));
     if (rc != CGD_OK) return rc;
     // the same arrays in pinned host memory, after the region the other calls use
@@ -815,7 +888,7 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
         fill_prod12(a);
     }
     a.xsegs = 1;
-    a.ygroups = (g.ny + c.ty - 1) / c.ty;
+    a.ygroups = per_launch ? 1 : (g.ny + c.ty - 1) / c.ty;
     a.n_steps = da.n_steps;
     a.rtol2 = da.rtol * da.rtol;
     a.max_iter = da.max_iter;
@@ -823,8 +896,9 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
     a.relres = d_relres;
     a.status = d_status;
 
-    // everything the call does, in stream order
-    auto enqueue_all = [&](hipStream_t q) -> cgd_status {
+    // everything the call does, in stream order; budget: the per-launch
+    // solver's iterations per step (nullptr: host read-backs, not capturable)
+    auto enqueue_all = [&](hipStream_t q, const int* budget) -> cgd_status {
         CGD_HIP_TRY(hipMemcpyAsync(d_off, h_off, 8 * ((size_t)n_snap + 1), hipMemcpyHostToDevice, q));
         hipLaunchKernelGGL(k_bdep_init, dim3((std::max(n_rhs, 2 * n_snap) + 255) / 256), dim3(256), 0, q, d);
         if (tiled) {
@@ -857,7 +931,9 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
             hipLaunchKernelGGL(k_bfinalize, dim3(512, n_rhs), dim3(kDBlock), 0, q, d);
         }
         if (want_mass) hipLaunchKernelGGL(k_bmass, dim3(n_rhs), dim3(1024), 0, q, fields, a.cells, g.vol, d_mass);
-        cgd_status r = launch_solver(c, a, grid, q);
+        cgd_status r = per_launch ? solve_grouped(m, fields, n_rhs, da, static_cast<char*>(big), budget, d_iters,
+                                                  d_relres, d_status, q)
+                                  : launch_solver(c, a, grid, q);
         if (r != CGD_OK) return r;
         if (want_mass)
             hipLaunchKernelGGL(k_bmass, dim3(n_rhs), dim3(1024), 0, q, fields, a.cells, g.vol, d_mass + n_rhs);
@@ -865,6 +941,19 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
         const size_t upto = want_mass ? L.mass + 16 * (size_t)n_rhs : L.relres + 8 * (size_t)n_rhs * da.n_steps;
         CGD_HIP_TRY(hipMemcpyAsync(pin + P.status, base + L.status, upto - L.status, hipMemcpyDeviceToHost, q));
         return CGD_OK;
+    };
+    // the per-launch solver's iterations per step of a finished eager run:
+    // the most any right-hand side took (the budget of the captured graph)
+    auto budget_of = [&]() {
+        std::vector<int> b(da.n_steps, 1);
+        for (int r = 0; r < n_rhs; ++r)
+            for (int k = 0; k < da.n_steps; ++k) b[k] = std::max(b[k], (int)h_iters[(size_t)r * da.n_steps + k]);
+        return b;
+    };
+    auto not_converged = [&]() {
+        for (int r = 0; r < n_rhs; ++r)
+            if (h_status[r] == CGD_NOT_CONVERGED) return true;
+        return false;
     };
 
     const bool use_graph = getenv("CGD_NO_GRAPH") == nullptr;
@@ -876,19 +965,25 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
                  (int)tiled, da.scheme * 2 + (int)want_mass);
         std::lock_guard<std::mutex> lk(g_graph_mu);
         BatchedGraph& bg = g_graphs[m];
-        if (bg.key != keybuf || !bg.exec) {
+        auto drop = [&]() {
             if (bg.exec) (void)hipGraphExecDestroy(bg.exec);
             if (bg.graph) (void)hipGraphDestroy(bg.graph);
             bg.exec = nullptr;
             bg.graph = nullptr;
+            bg.key.clear();
+        };
+        auto capture = [&](const int* budget) -> cgd_status {
             hipStream_t cap = nullptr;
             CGD_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
             CGD_HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-            cgd_status r = enqueue_all(cap);
+            cgd_status r = enqueue_all(cap, budget);
             hipGraph_t graph = nullptr;
             hipError_t ee = hipStreamEndCapture(cap, &graph);
             (void)hipStreamDestroy(cap);
-            if (r != CGD_OK) return r;
+            if (r != CGD_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return r;
+            }
             if (ee != hipSuccess) {
                 set_error(std::string("batched graph capture failed: ") + hipGetErrorString(ee));
                 return CGD_E_HIP;
@@ -896,13 +991,43 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
             bg.graph = graph;
             CGD_HIP_TRY(hipGraphInstantiate(&bg.exec, graph, nullptr, nullptr, 0));
             bg.key = keybuf;
+            return CGD_OK;
+        };
+        if (bg.key != keybuf || !bg.exec) {
+            drop();
+            if (per_launch) {
+                // one eager run with read-backs learns the iterations per step;
+                // the graph captured after it replays them as fixed budgets
+                rc = enqueue_all(s, nullptr);
+                if (rc != CGD_OK) return rc;
+                CGD_HIP_TRY(hipStreamSynchronize(s));
+                bg.budget = budget_of();
+                rc = capture(bg.budget.data());
+                if (rc != CGD_OK) return rc;
+            } else {
+                rc = capture(nullptr);
+                if (rc != CGD_OK) return rc;
+                CGD_HIP_TRY(hipGraphLaunch(bg.exec, s));
+                CGD_HIP_TRY(hipStreamSynchronize(s));
+            }
+        } else {
+            CGD_HIP_TRY(hipGraphLaunch(bg.exec, s));
+            CGD_HIP_TRY(hipStreamSynchronize(s));
+            if (per_launch && not_converged()) {
+                // a right-hand side needed more iterations than the budget:
+                // the call again with read-backs, and a new graph next time
+                drop();
+                rc = enqueue_all(s, nullptr);
+                if (rc != CGD_OK) return rc;
+                CGD_HIP_TRY(hipStreamSynchronize(s));
+                bg.budget = budget_of();
+            }
         }
-        CGD_HIP_TRY(hipGraphLaunch(bg.exec, s));
     } else {
-        rc = enqueue_all(s);
+        rc = enqueue_all(s, nullptr);
         if (rc != CGD_OK) return rc;
+        CGD_HIP_TRY(hipStreamSynchronize(s));
     }
-    CGD_HIP_TRY(hipStreamSynchronize(s));
     cgd_status worst = CGD_OK;
     for (int r = 0; r < n_rhs; ++r) {
         if (h_status[r] == CGD_E_BREAKDOWN) {

@@ -762,6 +762,17 @@ size_t diffuse_hex_workspace(const cgd_mesh m, int32_t F) {
 }
 
 cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s) {
+    cgd_status rc = ensure_workspace(m, diffuse_hex_workspace(m, da.F));
+    if (rc != CGD_OK) return rc;
+    rc = ensure_pinned(m, kPinBytes);
+    if (rc != CGD_OK) return rc;
+    rc = diffuse_hex_enqueue(m, da, static_cast<char*>(m->ws.ptr), nullptr, out != nullptr, s);
+    if (rc != CGD_OK) return rc;
+    return cg_finish_call(m, da.F, da.n_steps, m->hex.vol, s, out, da.x0_mode == 3);
+}
+
+cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, const int* fixed, bool sums,
+                               hipStream_t s) {
     const HexGeom& g = m->hex;
     const int F = da.F;
     const int64_t cells = m->cells;
@@ -790,12 +801,6 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     tile_env("CGD_HEX_TILE2", p);
     tile_env("CGD_HEX_TILEZ", pz);
     const size_t small = small_bytes(F, (int)max_bpf(g, F));
-    cgd_status rc = ensure_workspace(m, small + 6 * (size_t)F * cells * sizeof(float));
-    if (rc != CGD_OK) return rc;
-    rc = ensure_pinned(m, kPinBytes);
-    if (rc != CGD_OK) return rc;
-
-    char* base = static_cast<char*>(m->ws.ptr);
     CgCtl ctl = {};
     ctl.st = reinterpret_cast<CgField*>(base + kOffState);
     ctl.ndone = reinterpret_cast<int*>(base + kOffNdone);
@@ -960,7 +965,7 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     const int sum_bpf = (int)std::min<int64_t>(1024, (cells + kBlock - 1) / kBlock);
     double* d_sum_part = d_P2;  // free outside the solves
 
-    if (out) {  // mass before diffusion
+    if (sums) {  // mass before diffusion
         hipLaunchKernelGGL(k_field_sum, dim3(sum_bpf, F), dim3(kBlock), 0, s, da.field, cells, d_sum_part, sum_bpf);
         hipLaunchKernelGGL(k_sum_finish, dim3(F), dim3(kBlock), 0, s, d_sum_part, sum_bpf, d_sums);
     }
@@ -1079,8 +1084,15 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             a.c.host_flags = nullptr;
         };
         int it_end = it0;
-        cgd_status rc2 = cg_lookahead_loop(m, F, it0, da.max_iter, da.check_every, ctl.ndone, s, enqueue, &it_end);
-        if (rc2 != CGD_OK) return rc2;
+        if (fixed) {
+            // a fixed budget of iterations, with no read-back (the launches of
+            // a field that has converged return at once)
+            it_end = std::max(it0, std::min(fixed[step], da.max_iter));
+            for (int it = it0; it < it_end; ++it) enqueue(it, nullptr);
+        } else {
+            cgd_status rc2 = cg_lookahead_loop(m, F, it0, da.max_iter, da.check_every, ctl.ndone, s, enqueue, &it_end);
+            if (rc2 != CGD_OK) return rc2;
+        }
         CgCtl c2 = ctl;
         c2.step = step;
         hipLaunchKernelGGL(k_cg_step_end, dim3(F), dim3(kBlock), 0, s, c2, d_P2 + (size_t)(it_end & 1) * a.pstride,
@@ -1095,11 +1107,12 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     if (cur != da.field) {
         CGD_HIP_TRY(hipMemcpyAsync(da.field, cur, (size_t)F * cells * sizeof(float), hipMemcpyDeviceToDevice, s));
     }
-    if (out) {
+    if (sums) {
         hipLaunchKernelGGL(k_field_sum, dim3(sum_bpf, F), dim3(kBlock), 0, s, da.field, cells, d_sum_part, sum_bpf);
         hipLaunchKernelGGL(k_sum_finish, dim3(F), dim3(kBlock), 0, s, d_sum_part, sum_bpf, d_sums + CGD_MAX_FIELDS);
     }
-    return cg_finish_call(m, F, da.n_steps, g.vol, s, out, da.x0_mode == 3);
+    CGD_HIP_TRY(hipGetLastError());
+    return CGD_OK;
 }
 
 }  // namespace cgd

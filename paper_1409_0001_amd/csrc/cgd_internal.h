@@ -165,6 +165,17 @@ struct DiffuseArgs {
     int32_t scheme;   // 0 backward Euler, 1 Crank-Nicolson (half-step solve, then 2 y - e)
 };
 cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hipStream_t s);
+// The device work of diffuse_hex, enqueued on s with its workspace at `base`
+// (diffuse_hex_workspace(m, a.F) bytes, laid out as the mesh workspace: the
+// small region, partial sums, then the vectors).  fixed: nullptr for the
+// look-ahead loop with host read-backs (uses the mesh's pinned buffer), or a
+// budget of iterations per step enqueued without any host interaction (the
+// launches of a field that has converged return at once; a field not
+// converged within its budget is settled by k_cg_step_end as not converged),
+// which may be captured in a graph.  sums: the mass before and after.  The
+// statistics stay in the small region at `base`.
+cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& a, char* base, const int* fixed, bool sums,
+                               hipStream_t s);
 
 // mom[c][k] /= eps[k] where eps[k] > eps_min, else 0 (cg_common.hip).
 void velocity_from_momentum(int64_t cells, int n_comp, const float* eps, float* mom, float eps_min,

@@ -129,11 +129,16 @@ def test_batched_tiled_and_direct_deposits_agree_bitwise(gpu_lib, monkeypatch):
     assert not tiled[1].any()
 
 
-def test_graph_replays_equal_eager(gpu_lib):
+@pytest.mark.parametrize("cfg", [None, 8])
+def test_graph_replays_equal_eager(gpu_lib, cfg, monkeypatch):
     """The captured graph, replayed several times with eager work and
-    synchronisations in between, gives the eager result bit for bit."""
+    synchronisations in between, gives the eager result bit for bit (the
+    autotuner's pick, and the per-launch candidate, whose graph replays
+    the iteration budgets of the eager run before it)."""
     import torch
     cgd = gpu_lib
+    if cfg is not None:
+        monkeypatch.setenv("CGD_BATCHED_CFG", str(cfg))
     shape = (128, 24, 16)
     counts = [9_000, 15_000, 4_000]
     box, parts, pos, vals, off = _batch(shape, counts, seed=91)
@@ -158,11 +163,14 @@ def test_autotune_reports_candidates(gpu_lib):
     cgd = gpu_lib
     mesh = cgd.HexMesh((128, 64, 32))
     chosen, ms = cgd.autotune_batched(mesh, 32)
-    assert len(ms) == 8 and all(t > 0 for t in ms)  # 4 tile shapes at degree 2, 2 at degree 4, 2 at degree 12
+    # persistent launch: 4 tile shapes at degree 2, 2 at degree 4, 2 at degree
+    # 12; then the per-launch solver over groups of fields
+    assert len(ms) == 9 and all(t > 0 for t in ms)
     assert chosen == int(np.argmin(ms))
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7])  # degree 2 (four tile shapes); degrees 4 and 12 (two each)
+# persistent: degree 2 (four tile shapes), degrees 4 and 12 (two each); 8: per-launch
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 def test_batched_candidates_match_oracle(gpu_lib, cfg, monkeypatch):
     """Every preconditioner degree of the persistent solver reaches the same
     fields: forced candidates against the float64 oracle on 128 x 20 x 24
@@ -189,20 +197,74 @@ def test_batched_candidates_match_oracle(gpu_lib, cfg, monkeypatch):
     print("iterations per step", iters.reshape(-1, steps).mean(axis=0), flush=True)
 
 
+def test_batched_any_width(gpu_lib):
+    """A grid width the persistent launch does not cover (nx = 96): the
+    autotuner has only the per-launch solver, which meets the oracle."""
+    import torch
+    cgd = gpu_lib
+    shape = (96, 20, 12)
+    counts = [4_000, 7_000]
+    box, parts, pos, vals, off = _batch(shape, counts, seed=93)
+    mesh = cgd.HexMesh(shape, box.lo, box.hi)
+    chosen, ms = cgd.autotune_batched(mesh, 8)
+    assert len(ms) == 1 and chosen == 0
+    b, steps = 4.0 / 96, 3
+    out = cgd.coarse_grain_batched(mesh, off, _t(pos, torch), _t(vals, torch), b, steps, rtol=1e-7).cpu().numpy()
+    for j, p in enumerate(parts):
+        dep = O.deposit_hex(p.pos, p.values, box.lo, box.hi, shape)
+        ref = O.diffuse_hex_dct(dep["field64"], box.lo, box.hi, shape, b, steps)
+        for f in range(4):
+            assert rel_l2(out[j, f], ref[f]) <= REL_L2, (j, f, rel_l2(out[j, f], ref[f]))
+
+
+def test_per_launch_budget_miss_reruns(gpu_lib, monkeypatch):
+    """The per-launch candidate's graph replays the iteration budget of the
+    run before it; a call whose data needs more (same buffers, new values)
+    finds a right-hand side unconverged after the replay and is run again
+    with read-backs: the result still meets the oracle and no status says
+    not converged."""
+    import torch
+    cgd = gpu_lib
+    monkeypatch.setenv("CGD_BATCHED_CFG", "8")
+    shape = (64, 16, 12)
+    box = inputs.HexBox((0.0, 0.0, 0.0), (1.0, 0.25, 0.1875), shape)
+    # one particle at every cell centre: with equal values the deposited
+    # field is constant, an eigenvector of the operator, solved in one iteration
+    idx = np.indices(shape[::-1]).reshape(3, -1)[::-1].T.astype(np.float64)
+    h = (np.asarray(box.hi) - np.asarray(box.lo)) / np.asarray(shape)
+    centres = (np.asarray(box.lo) + (idx + 0.5) * h).astype(np.float32)
+    n = len(centres)
+    pos = np.concatenate([centres, centres])
+    off = np.array([0, n, 2 * n], dtype=np.int64)
+    mesh = cgd.HexMesh(shape, box.lo, box.hi)
+    dpos = _t(pos, torch)
+    dvals = torch.full((1, 2 * n), 0.5, dtype=torch.float32, device="cuda")
+    b, steps = 4.0 / 64, 2
+    _, it1 = cgd.coarse_grain_batched(mesh, off, dpos, dvals, b, steps, rtol=1e-6, return_iters=True)
+    _, it2 = cgd.coarse_grain_batched(mesh, off, dpos, dvals, b, steps, rtol=1e-6, return_iters=True)
+    assert it1.max() == 1 and np.array_equal(it1, it2), (it1, it2)
+    rv = np.random.default_rng(94).random((1, 2 * n)).astype(np.float32)
+    dvals.copy_(torch.from_numpy(rv))
+    out, it3 = cgd.coarse_grain_batched(mesh, off, dpos, dvals, b, steps, rtol=1e-6, return_iters=True)
+    assert it3.max() >= 2
+    o = out.cpu().numpy()
+    for j in range(2):
+        dep = O.deposit_hex(pos[off[j]:off[j + 1]], rv[:, off[j]:off[j + 1]], box.lo, box.hi, shape)
+        ref = O.diffuse_hex_dct(dep["field64"], box.lo, box.hi, shape, b, steps)
+        assert rel_l2(o[j, 0], ref[0]) <= REL_L2, (j, rel_l2(o[j, 0], ref[0]))
+
+
 def test_batched_invalid(gpu_lib):
     import torch
     cgd = gpu_lib
-    mesh = cgd.HexMesh((96, 8, 8))  # width not supported by the batched solver
     pos = torch.rand((10, 3), device="cuda")
     vals = torch.rand((1, 10), device="cuda")
-    with pytest.raises(cgd.CgdError):
-        cgd.coarse_grain_batched(mesh, [0, 10], pos, vals, 0.1, 2)
     mesh = cgd.HexMesh((64, 8, 8))
     with pytest.raises(cgd.CgdError):
         cgd.coarse_grain_batched(mesh, [0, 6, 4, 10], pos, vals, 0.1, 2)  # decreasing offsets
 
 
-@pytest.mark.parametrize("cfg,precond", [(None, 0), (1, 0), (1, 1), (4, 0), (4, 1), (6, 0), (6, 1)])
+@pytest.mark.parametrize("cfg,precond", [(None, 0), (1, 0), (1, 1), (4, 0), (4, 1), (6, 0), (6, 1), (8, 0), (8, 1)])
 def test_batched_crank_nicolson_matches_oracle_and_graph_key(gpu_lib, cfg, precond, monkeypatch):
     """Crank-Nicolson in the persistent launch (the x updates carry the
     extrapolation) against the oracle's CN closed form, after a backward-Euler
