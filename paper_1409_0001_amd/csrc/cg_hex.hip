@@ -66,10 +66,11 @@ struct SweepArgs {
     PrecondCoef pc;     // k_precond_lds: Horner levels of M = sum_j cp[j] A^j, or the first product pass
     PrecondCoef pc2;    // the last product pass (degrees 8 and 12)
     PrecondCoef pcm;    // the middle product pass (degree 12)
+    int rect;           // the rectilinear operator (Geom's per-axis factors; register sweeps only)
 };
 
 // One sweep over all fields: each wave takes one tile (stencil_tile.h).
-template <int VEC, int TY, int MODE, bool EDGE>
+template <int VEC, int TY, int MODE, bool EDGE, bool RECT = false>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     int b = blockIdx.x;
     if ((a.nblocks & 7) == 0) b = (b & 7) * (a.nblocks >> 3) + (b >> 3);
@@ -168,10 +169,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
         const int ze = min(zb + a.zc, a.nz);
         if constexpr (MODE == SZ2_FIRST || MODE == SZ2) {
             if constexpr (!EDGE)
-                tile_precond2<VEC, TY, MODE == SZ2_FIRST>(a.p, a.g, (size_t)f * a.cells, yg, zb, ze, lane, acc0, acc1);
+                tile_precond2<VEC, TY, MODE == SZ2_FIRST, RECT>(a.p, a.g, (size_t)f * a.cells, yg, zb, ze, lane, acc0,
+                                                                acc1);
         } else {
-            tile_sweep<VEC, TY, MODE, EDGE>(a.p, a.g, (size_t)f * a.cells, xs, yg, zb, ze, lane, alpha, beta, acc0,
-                                            acc1);
+            tile_sweep<VEC, TY, MODE, EDGE, RECT>(a.p, a.g, (size_t)f * a.cells, xs, yg, zb, ze, lane, alpha, beta,
+                                                  acc0, acc1);
         }
     }
 
@@ -568,8 +570,25 @@ Plan default_plan(const HexGeom& g, int F, int vec) {
     return make_plan(g, F, vec, ty, zc);
 }
 
+// The rectilinear operator's sweeps: the modes of Jacobi-preconditioned CG
+// from a zero guess (the SZ modes form z = r / diag(A)).
+template <int VEC, int TY, bool EDGE>
+void launch_sweep_rect(int mode, const Plan& p, const SweepArgs& a, hipStream_t s) {
+    const dim3 grid(p.nblocks), block(kBlock);
+    switch (mode) {
+        case S1: hipLaunchKernelGGL((k_sweep<VEC, TY, S1, EDGE, true>), grid, block, 0, s, a); break;
+        case S1_B0: hipLaunchKernelGGL((k_sweep<VEC, TY, S1_B0, EDGE, true>), grid, block, 0, s, a); break;
+        case S2: hipLaunchKernelGGL((k_sweep<VEC, TY, S2, EDGE, true>), grid, block, 0, s, a); break;
+        case S2P_FIRST: hipLaunchKernelGGL((k_sweep<VEC, TY, S2P_FIRST, EDGE, true>), grid, block, 0, s, a); break;
+        case SZ_FIRST: hipLaunchKernelGGL((k_sweep<VEC, TY, SZ_FIRST, EDGE, true>), grid, block, 0, s, a); break;
+        case SZ: hipLaunchKernelGGL((k_sweep<VEC, TY, SZ, EDGE, true>), grid, block, 0, s, a); break;
+        default: break;  // not used on rectilinear grids
+    }
+}
+
 template <int VEC, int TY, bool EDGE>
 void launch_sweep_t(int mode, const Plan& p, const SweepArgs& a, hipStream_t s) {
+    if (a.rect) return launch_sweep_rect<VEC, TY, EDGE>(mode, p, a, s);
     const dim3 grid(p.nblocks), block(kBlock);
     switch (mode) {
         case S1_FIRST: hipLaunchKernelGGL((k_sweep<VEC, TY, S1_FIRST, EDGE>), grid, block, 0, s, a); break;
@@ -766,13 +785,13 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     if (rc != CGD_OK) return rc;
     rc = ensure_pinned(m, kPinBytes);
     if (rc != CGD_OK) return rc;
-    rc = diffuse_hex_enqueue(m, da, static_cast<char*>(m->ws.ptr), nullptr, out != nullptr, s);
+    rc = diffuse_hex_enqueue(m, da, static_cast<char*>(m->ws.ptr), nullptr, out != nullptr, s, nullptr);
     if (rc != CGD_OK) return rc;
     return cg_finish_call(m, da.F, da.n_steps, m->hex.vol, s, out, da.x0_mode == 3);
 }
 
 cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, const int* fixed, bool sums,
-                               hipStream_t s) {
+                               hipStream_t s, const RectOp* ro) {
     const HexGeom& g = m->hex;
     const int F = da.F;
     const int64_t cells = m->cells;
@@ -835,6 +854,19 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, co
     a.g.cx = (float)(dtau / (g.h[0] * g.h[0]));
     a.g.cy = (float)(dtau / (g.h[1] * g.h[1]));
     a.g.cz = (float)(dtau / (g.h[2] * g.h[2]));
+    if (ro) {
+        // the rectilinear operator (per-axis factors); its spectrum lies in
+        // [1, 1 + dtau lam] with lam the Gershgorin bound of the dtau-free
+        // part, written as equal c_a for the polynomial's interval
+        a.rect = 1;
+        a.g.dt = (float)dtau;
+        for (int ax = 0; ax < 3; ++ax) {
+            a.g.rg[ax] = ro->g[ax];
+            a.g.rs[ax] = ro->s[ax];
+            a.g.rd[ax] = ro->d[ax];
+        }
+        a.g.cx = a.g.cy = a.g.cz = (float)(dtau * ro->lam / 12.0);
+    }
     a.pstride = (int)max_bpf(g, F);
     a.c = ctl;
     a.P1 = d_P1;
@@ -850,15 +882,15 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, co
     // (lds_plan), the degree rises to 4 (13 -> 1.26), applied by
     // k_precond_lds with the intermediate powers in LDS.
     // CGD_HEX_PRECOND_DEG (2, 3, 4) and CGD_HEX_LDS_ZC override the choice.
-    const bool pcg = da.precond == 0;
+    const bool pcg = da.precond == 0 || ro;  // the rectilinear operator runs preconditioned CG only
     const bool row_wave = !p.edge && p.xsegs == 1 && g.nx == 64 * p.vec;
-    const int deg = (pcg && row_wave) ? 2 : 1;
+    const int deg = (pcg && row_wave && !ro) ? 2 : 1;  // rectilinear: Jacobi (the SZ modes)
     a.pcg = pcg ? 1 : 0;
     poly_precond_coeffs(a.g.cx, a.g.cy, a.g.cz, deg, &a.g.c0, &a.g.c1, &a.g.c2);
     const int mode_z_first = deg == 2 ? SZ2_FIRST : SZ_FIRST;
     const int mode_z = deg == 2 ? SZ2 : SZ;
     int deg_lds = 0;
-    if (deg == 2) {
+    if (deg == 2 && !ro) {
         // Degree 4, 8 or 12 (one Horner pass; two or three passes of two
         // quadratic factors) where the LDS tile applies, by predicted cost
         // (lds_degree).  At dtau / h^2 = 1: 5, 3 and 2 iterations per step;
@@ -896,7 +928,7 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, co
     // sweep; at 128^3 both take 11.5 us.  CGD_HEX_DIR (0: the register sweep),
     // CGD_HEX_DIR_NW (8 or 16 waves) and CGD_HEX_DIR_ZC override.
     int dir_nw = 0;
-    if (pcg && row_wave) {
+    if (pcg && row_wave && !ro) {
         dir_nw = 8;
         int zc_force = 0;
         if (const char* e = getenv("CGD_HEX_DIR")) dir_nw = atoi(e) ? 8 : 0;

@@ -60,6 +60,7 @@ struct HexGeom {
 };
 
 struct TetData;  // defined in tet.cpp
+struct RectOp;   // below
 
 // Event-pair timing of selected kernels (cgd_timing_enable).
 struct Timing {
@@ -99,6 +100,7 @@ struct cgd_mesh_s {
     int64_t cells;
     cgd::HexGeom hex;
     cgd::TetData* tet = nullptr;
+    cgd::RectOp* rop = nullptr;    // rectilinear grids with a separable diffusivity: the sweeps' operator
     cgd::Workspace ws;
     void* pinned = nullptr;        // small pinned host buffer for read-backs
     size_t pinned_bytes = 0;
@@ -174,8 +176,24 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hi
 // converged within its budget is settled by k_cg_step_end as not converged),
 // which may be captured in a graph.  sums: the mass before and after.  The
 // statistics stay in the small region at `base`.
+// ro: nullptr for the uniform grid's operator, or a rectilinear grid's
+// (the field then holds M^1/2 e; Jacobi-preconditioned CG in the register
+// sweeps).
 cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& a, char* base, const int* fixed, bool sums,
-                               hipStream_t s);
+                               hipStream_t s, const RectOp* ro = nullptr);
+
+// A rectilinear grid whose diffusivity is a product of per-axis factors
+// (D_ijk = Dx_i Dy_j Dz_k) and that has no periodic axis: the operator
+// A = I + dtau M^-1/2 K M^-1/2 in per-axis factors (device arrays; see
+// stencil::Geom) for the hex sweeps, and the square roots of the cell
+// widths for the change of variable x~ = M^1/2 x.
+struct RectOp {
+    float* g[3];   // face weights [n_a + 1] (0 at walls)
+    float* s[3];   // diagonal sums [n_a]
+    float* d[3];   // diffusivity factors [n_a]
+    float* q[3];   // sqrt of the cell widths [n_a]
+    double lam;    // Gershgorin bound of M^-1/2 K M^-1/2 (times dtau: the spectrum's width)
+};
 
 // mom[c][k] /= eps[k] where eps[k] > eps_min, else 0 (cg_common.hip).
 void velocity_from_momentum(int64_t cells, int n_comp, const float* eps, float* mom, float eps_min,

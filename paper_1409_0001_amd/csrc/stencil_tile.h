@@ -56,7 +56,91 @@ struct Geom {
     // advances by (1 + xs1) alpha p from xb b, so that with xs1 = 1, xb = -1
     // the iterate is 2 y - b when y solves the half step (0, 0: plain x)
     float xs1, xb;
+    // Rectilinear grids with a separable diffusivity (RECT kernels): the
+    // operator is A = I + dt M^-1/2 K M^-1/2 (M the cell volumes, K the
+    // finite-volume Laplacian with harmonic-mean face diffusivities), whose
+    // entries are products of per-axis factors.  Per axis a with n cells:
+    // rg[a] [n + 1] face weights (0 at a wall), rs[a] [n] the cell's own
+    // diagonal sum over its two faces, rd[a] [n] the diffusivity factor.
+    // Cell (i, j, k) with D = Dx_i Dy_j Dz_k:
+    //   (A v) = (1 + dt (Dy Dz sx_i + Dx (Dz sy_j + Dy sz_k))) v
+    //           - dt Dy Dz (gx_i v_{i-1} + gx_{i+1} v_{i+1})
+    //           - dt Dx Dz (gy_j v_{j-1} + gy_{j+1} v_{j+1})
+    //           - dt Dx Dy (gz_k v_{k-1} + gz_{k+1} v_{k+1})
+    const float* rg[3];
+    const float* rs[3];
+    const float* rd[3];
+    float dt;
 };
+
+// RECT: the x factors of a lane's VEC cells (dt folded into the weights),
+// loaded once per tile; lane cells beyond the grid take the last cell's.
+template <int VEC>
+struct RectX {
+    float gl[VEC], gr[VEC], s[VEC], d[VEC];
+};
+
+template <int VEC>
+__device__ __forceinline__ RectX<VEC> rect_x(const Geom& g, int x0) {
+    RectX<VEC> X;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        const int i = min(x0 + e, g.nx - 1);
+        X.gl[e] = g.dt * g.rg[0][i];
+        X.gr[e] = g.dt * g.rg[0][i + 1];
+        X.s[e] = g.dt * g.rs[0][i];
+        X.d[e] = g.rd[0][i];
+    }
+    return X;
+}
+
+// RECT: the y and z factors of one row at one plane (wave-uniform values).
+struct RectYZ {
+    float dyz, a, bd, bu, cd, cu;
+};
+
+// The factors of one row (y) or one plane (z): lower and upper face
+// weights, diagonal sum, diffusivity factor.
+struct RectA {
+    float gd, gu, s, d;
+};
+
+__device__ __forceinline__ RectA rect_a(const Geom& g, int axis, int i, int n) {
+    i = min(max(i, 0), n - 1);
+    return RectA{g.rg[axis][i], g.rg[axis][i + 1], g.rs[axis][i], g.rd[axis][i]};
+}
+
+__device__ __forceinline__ RectYZ rect_yz(const Geom& g, const RectA& Y, const RectA& Z) {
+    RectYZ r;
+    r.dyz = Y.d * Z.d;
+    r.a = g.dt * fmaf(Z.d, Y.s, Y.d * Z.s);
+    r.bd = g.dt * Z.d * Y.gd;
+    r.bu = g.dt * Z.d * Y.gu;
+    r.cd = g.dt * Y.d * Z.gd;
+    r.cu = g.dt * Y.d * Z.gu;
+    return r;
+}
+
+__device__ __forceinline__ RectYZ rect_yz(const Geom& g, int y, int z) {
+    return rect_yz(g, rect_a(g, 1, y, g.ny), rect_a(g, 2, z, g.nz));
+}
+
+// RECT: the diagonal of A at one cell.
+template <int VEC>
+__device__ __forceinline__ float rect_diag(const RectX<VEC>& X, int e, const RectYZ& q) {
+    return fmaf(q.dyz, X.s[e], fmaf(X.d[e], q.a, 1.f));
+}
+
+// RECT: (A v) at one cell (a neighbour across a wall has weight 0, so any
+// finite value may stand there).
+template <int VEC>
+__device__ __forceinline__ float rect_cell(const RectX<VEC>& X, int e, const RectYZ& q, float c, float l, float r,
+                                           float yl, float yh, float zl, float zh) {
+    const float d = rect_diag<VEC>(X, e, q);
+    const float nxv = fmaf(X.gl[e], l, X.gr[e] * r);
+    const float nyz = fmaf(q.bd, yl, fmaf(q.bu, yh, fmaf(q.cd, zl, q.cu * zh)));
+    return fmaf(d, c, -fmaf(X.d[e], nyz, q.dyz * nxv));
+}
 
 template <int VEC>
 struct Vec {
@@ -115,7 +199,7 @@ __device__ __forceinline__ Vec<VEC> load_p(const Ptrs& p, size_t i, float beta) 
 // One wave: x segment xs, row group yg (rows yg*TY ...), planes [zb, ze) of
 // the field starting at element fo.  Adds this wave's dot products to acc0 /
 // acc1 (see Mode).
-template <int VEC, int TY, int MODE, bool EDGE>
+template <int VEC, int TY, int MODE, bool EDGE, bool RECT = false>
 __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t fo, int xs, int yg, int zb, int ze,
                                            int lane, float alpha, float beta, double& acc0, double& acc1) {
     const int nx = g.nx, ny = g.ny, nz = g.nz;
@@ -137,6 +221,40 @@ __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t 
         return base + (size_t)z * plane + (size_t)y * nx;
     };
 
+    if constexpr (RECT && (MODE == SZ_FIRST || MODE == SZ)) {
+        // Jacobi on the rectilinear operator: z = r / diag(A), pointwise
+        // (no neighbours); r.z (and b.b)
+        const RectX<VEC> X = rect_x<VEC>(g, x0);
+        RectA Y[TY];
+#pragma unroll
+        for (int j = 0; j < TY; ++j) Y[j] = rect_a(g, 1, y0 + j, ny);
+        for (int z = zb; z < ze; ++z) {
+            Vec<VEC> rv[TY];
+#pragma unroll
+            for (int j = 0; j < TY; ++j) rv[j] = load_p<VEC, MODE>(p, at(z, y0 + j), beta);
+            const RectA Z = rect_a(g, 2, z, nz);
+#pragma unroll
+            for (int j = 0; j < TY; ++j) {
+                const int y = y0 + j;
+                const RectYZ q = rect_yz(g, Y[j], Z);
+                Vec<VEC> zv;
+                // any positive diagonal preconditions CG: the hardware
+                // reciprocal (1 ulp) in place of a division
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) zv.f[e] = rv[j].f[e] * __builtin_amdgcn_rcpf(rect_diag<VEC>(X, e, q));
+                if (xin && y < ny) {
+                    stv<VEC>(p.Z + at(z, y), zv);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        acc0 = fma((double)rv[j].f[e], (double)zv.f[e], acc0);
+                        if (MODE == SZ_FIRST) acc1 = fma((double)rv[j].f[e], (double)rv[j].f[e], acc1);
+                    }
+                }
+            }
+        }
+        return;
+    }
+
     Vec<VEC> pm[TY], pc[TY + 2], pn[TY + 2];
     float ec[TY], en[TY];
 #pragma unroll
@@ -147,9 +265,18 @@ __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t 
 #pragma unroll
         for (int j = 0; j < TY; ++j) ec[j] = load_p<1, MODE>(p, at(zb, y0 + j) + eoff, beta).f[0];
     }
+    RectX<VEC> X;
+    RectA Y[TY];
+    if constexpr (RECT) {
+        X = rect_x<VEC>(g, x0);
+#pragma unroll
+        for (int j = 0; j < TY; ++j) Y[j] = rect_a(g, 1, y0 + j, ny);
+    }
     for (int z = zb; z < ze; ++z) {
 #pragma unroll
         for (int j = 0; j < TY + 2; ++j) pn[j] = load_p<VEC, MODE>(p, at(z + 1, y0 - 1 + j), beta);
+        RectA Z;
+        if constexpr (RECT) Z = rect_a(g, 2, z, nz);
         if constexpr (EDGE) {
 #pragma unroll
             for (int j = 0; j < TY; ++j) en[j] = load_p<1, MODE>(p, at(z + 1, y0 + j) + eoff, beta).f[0];
@@ -169,6 +296,8 @@ __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t 
                 rgt = lane == 63 ? ec[j] : rgt;
             }
             Vec<VEC> ap;
+            RectYZ q;
+            if constexpr (RECT) q = rect_yz(g, Y[j], Z);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 const float ce = c.f[e];
@@ -178,10 +307,14 @@ __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t 
                 const float yh = has_yu ? pc[j + 2].f[e] : ce;
                 const float zl = has_zd ? pm[j].f[e] : ce;
                 const float zh = has_zu ? pn[j + 1].f[e] : ce;
-                const float c2 = ce + ce;
-                float v = fmaf(cx, (c2 - l) - r, ce);
-                v = fmaf(cy, (c2 - yl) - yh, v);
-                ap.f[e] = fmaf(cz, (c2 - zl) - zh, v);
+                if constexpr (RECT) {
+                    ap.f[e] = rect_cell<VEC>(X, e, q, ce, l, r, yl, yh, zl, zh);
+                } else {
+                    const float c2 = ce + ce;
+                    float v = fmaf(cx, (c2 - l) - r, ce);
+                    v = fmaf(cy, (c2 - yl) - yh, v);
+                    ap.f[e] = fmaf(cz, (c2 - zl) - zh, v);
+                }
             }
             if constexpr (MODE == S1_FIRST) {
                 if (valid) {
@@ -284,10 +417,11 @@ __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t 
 // above; a missing neighbour (wall) is replaced by the cell itself.  The row
 // is covered by one wave (x-neighbours of the end elements from the adjacent
 // lanes; walls at lanes 0 and 63).
-template <int VEC>
+template <int VEC, bool RECT = false>
 __device__ __forceinline__ Vec<VEC> apply_row(const Geom& g, const Vec<VEC>& c, const Vec<VEC>& yl,
                                               const Vec<VEC>& yh, const Vec<VEC>& zl, const Vec<VEC>& zh,
-                                              bool hyd, bool hyu, bool hzd, bool hzu, bool wall_l, bool wall_r) {
+                                              bool hyd, bool hyu, bool hzd, bool hzu, bool wall_l, bool wall_r,
+                                              const RectX<VEC>* X = nullptr, const RectYZ* q = nullptr) {
     const float lft = __shfl_up(c.f[VEC - 1], 1);
     const float rgt = __shfl_down(c.f[0], 1);
     Vec<VEC> out;
@@ -300,10 +434,14 @@ __device__ __forceinline__ Vec<VEC> apply_row(const Geom& g, const Vec<VEC>& c, 
         const float yhi = hyu ? yh.f[e] : ce;
         const float zlo = hzd ? zl.f[e] : ce;
         const float zhi = hzu ? zh.f[e] : ce;
-        const float c2 = ce + ce;
-        float v = fmaf(g.cx, (c2 - l) - r, ce);
-        v = fmaf(g.cy, (c2 - ylo) - yhi, v);
-        out.f[e] = fmaf(g.cz, (c2 - zlo) - zhi, v);
+        if constexpr (RECT) {
+            out.f[e] = rect_cell<VEC>(*X, e, *q, ce, l, r, ylo, yhi, zlo, zhi);
+        } else {
+            const float c2 = ce + ce;
+            float v = fmaf(g.cx, (c2 - l) - r, ce);
+            v = fmaf(g.cy, (c2 - ylo) - yhi, v);
+            out.f[e] = fmaf(g.cz, (c2 - zlo) - zhi, v);
+        }
     }
     return out;
 }
@@ -336,7 +474,7 @@ __device__ __forceinline__ Vec<VEC> apply_row_lr(const Geom& g, const Vec<VEC>& 
 // never used (the wall rule substitutes the cell itself).  One wave covers a
 // row (nx = 64 VEC).  FIRST: the input is b (zero initial guess) and b.b is
 // accumulated as well.
-template <int VEC, int TY, bool FIRST>
+template <int VEC, int TY, bool FIRST, bool RECT = false>
 __device__ __forceinline__ void tile_precond2(const Ptrs& p, const Geom& g, size_t fo, int yg, int zb, int ze,
                                               int lane, double& acc0, double& acc1) {
     constexpr int RR = TY + 4;  // rows of r: y0 - 2 .. y0 + TY + 1
@@ -357,14 +495,18 @@ __device__ __forceinline__ void tile_precond2(const Ptrs& p, const Geom& g, size
 #pragma unroll
         for (int i = 0; i < RR; ++i) dst[i] = ldv<VEC>(src + at(z, y0 - 2 + i));
     };
+    RectX<VEC> X;
+    if constexpr (RECT) X = rect_x<VEC>(g, x0);
     // A r for the RA rows of plane q, from r planes q-1 (lo), q (c), q+1 (hi)
     auto ar_plane = [&](Vec<VEC>* dst, const Vec<VEC>* lo, const Vec<VEC>* c, const Vec<VEC>* hi, int q) {
         const bool hzd = q > 0, hzu = q + 1 < nz;
 #pragma unroll
         for (int jj = 0; jj < RA; ++jj) {
             const int y = y0 - 1 + jj;
-            dst[jj] = apply_row<VEC>(g, c[jj + 1], c[jj], c[jj + 2], lo[jj + 1], hi[jj + 1], y > 0, y + 1 < ny, hzd,
-                                     hzu, wall_l, wall_r);
+            RectYZ yz;
+            if constexpr (RECT) yz = rect_yz(g, y, q);
+            dst[jj] = apply_row<VEC, RECT>(g, c[jj + 1], c[jj], c[jj + 2], lo[jj + 1], hi[jj + 1], y > 0, y + 1 < ny,
+                                           hzd, hzu, wall_l, wall_r, &X, &yz);
         }
     };
 
@@ -392,8 +534,10 @@ __device__ __forceinline__ void tile_precond2(const Ptrs& p, const Geom& g, size
 #pragma unroll
         for (int j = 0; j < TY; ++j) {
             const int y = y0 + j;
-            const Vec<VEC> aar = apply_row<VEC>(g, a1[j + 1], a1[j], a1[j + 2], a0[j + 1], a2[j + 1], y > 0,
-                                                y + 1 < ny, hzd, hzu, wall_l, wall_r);
+            RectYZ yz;
+            if constexpr (RECT) yz = rect_yz(g, y, z);
+            const Vec<VEC> aar = apply_row<VEC, RECT>(g, a1[j + 1], a1[j], a1[j + 2], a0[j + 1], a2[j + 1], y > 0,
+                                                      y + 1 < ny, hzd, hzu, wall_l, wall_r, &X, &yz);
             const Vec<VEC>& rv = r0[j + 2];
             Vec<VEC> zv;
 #pragma unroll

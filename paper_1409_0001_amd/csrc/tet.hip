@@ -40,7 +40,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
+#include <vector>
 
 #include "cg_common.h"
 #include "tet_data.h"
@@ -443,6 +445,13 @@ size_t tet_small(int F, int bpf) {
 }  // namespace
 
 void destroy_tet_data(cgd_mesh m) {
+    if (RectOp* ro = m->rop) {
+        for (int a = 0; a < 3; ++a)
+            for (float* p : {ro->g[a], ro->s[a], ro->d[a], ro->q[a]})
+                if (p) (void)hipFree(p);
+        delete ro;
+        m->rop = nullptr;
+    }
     TetData* t = m->tet;
     if (!t) return;
     void* ptrs[] = {t->xyz,   t->tv,     t->vol,   t->volf,  t->bbox, t->kface, t->kdiag,
@@ -535,11 +544,153 @@ cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
     return CGD_OK;
 }
 
+namespace {
+// The change of variable of the rectilinear fast path: field *= sqrt(V)
+// (dir > 0) or field /= sqrt(V), sqrt(V) = sqrt(hx_i) sqrt(hy_j) sqrt(hz_k)
+// formed the same way both times.
+__global__ __launch_bounds__(kBlock) void k_rect_scale(float* __restrict__ field, int64_t cells, int nx, int ny,
+                                                      const float* __restrict__ qx, const float* __restrict__ qy,
+                                                      const float* __restrict__ qz, int dir) {
+    float* f = field + (size_t)blockIdx.y * cells;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx);
+        const int64_t r = c / nx;
+        const int j = (int)(r % ny);
+        const int k = (int)(r / ny);
+        const float q = (qx[i] * qy[j]) * qz[k];
+        f[c] = dir > 0 ? f[c] * q : f[c] / q;
+    }
+}
+}  // namespace
+
+// Rectilinear grid with a separable diffusivity: the uniform grid's sweeps
+// on A = I + dtau M^-1/2 K M^-1/2 for x~ = M^1/2 x (the same system as
+// (M + dtau K) x = M e, scaled symmetrically), with the polynomial
+// preconditioner on [1, 1 + dtau lam]; the stopping rule applies to the
+// scaled residual.
+static cgd_status diffuse_rect_fast(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s) {
+    const TetData* t = m->tet;
+    const RectOp* ro = m->rop;
+    const int F = da.F;
+    const int n = t->n_tet;
+    cgd_status rc = ensure_workspace(m, diffuse_hex_workspace(m, F));
+    if (rc != CGD_OK) return rc;
+    rc = ensure_pinned(m, kPinBytes);
+    if (rc != CGD_OK) return rc;
+    char* base = static_cast<char*>(m->ws.ptr);
+    double* d_sums = reinterpret_cast<double*>(base + kOffSums);
+    double* d_mpart = reinterpret_cast<double*>(base + kSmallFixed);  // free outside the solve
+    const int mbpf = std::min(1024, (n + kBlock - 1) / kBlock);
+    if (out) {
+        hipLaunchKernelGGL(k_tet_mass, dim3(mbpf, F), dim3(kBlock), 0, s, da.field, t->vol, n, d_mpart, mbpf);
+        hipLaunchKernelGGL(k_tet_sum_finish, dim3(F), dim3(kBlock), 0, s, d_mpart, mbpf, d_sums);
+    }
+    const int sblocks = std::min(4096, (n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_rect_scale, dim3(sblocks, F), dim3(kBlock), 0, s, da.field, (int64_t)n, m->hex.nx,
+                       m->hex.ny, ro->q[0], ro->q[1], ro->q[2], 1);
+    rc = diffuse_hex_enqueue(m, da, base, nullptr, false, s, ro);
+    if (rc != CGD_OK) return rc;
+    hipLaunchKernelGGL(k_rect_scale, dim3(sblocks, F), dim3(kBlock), 0, s, da.field, (int64_t)n, m->hex.nx,
+                       m->hex.ny, ro->q[0], ro->q[1], ro->q[2], -1);
+    if (out) {
+        hipLaunchKernelGGL(k_tet_mass, dim3(mbpf, F), dim3(kBlock), 0, s, da.field, t->vol, n, d_mpart, mbpf);
+        hipLaunchKernelGGL(k_tet_sum_finish, dim3(F), dim3(kBlock), 0, s, d_mpart, mbpf, d_sums + CGD_MAX_FIELDS);
+    }
+    return cg_finish_call(m, F, da.n_steps, 1.0, s, out, false);
+}
+
+// Per-axis factors of a rectilinear grid's operator (RectOp), when the
+// diffusivity is a product of per-axis factors (checked on every cell to a
+// relative 1e-6) and no axis is periodic; otherwise the mesh keeps the
+// face-slot rows only.
+static cgd_status build_rect_op(cgd_mesh m, const int32_t dims[3], const double* const edges[3], const float* D) {
+    const int nx = dims[0], ny = dims[1], nz = dims[2];
+    std::vector<double> fac[3];
+    for (int a = 0; a < 3; ++a) fac[a].assign(dims[a], 1.0);
+    if (D) {
+        int64_t k0 = -1;
+        const int64_t n = (int64_t)nx * ny * nz;
+        for (int64_t k = 0; k < n && k0 < 0; ++k)
+            if (D[k] > 0.f) k0 = k;
+        if (k0 < 0) {
+            fac[0].assign(nx, 0.0);  // no diffusion anywhere
+        } else {
+            const int i0 = (int)(k0 % nx), j0 = (int)((k0 / nx) % ny), z0 = (int)(k0 / ((int64_t)nx * ny));
+            auto at = [&](int i, int j, int k) { return (double)D[i + (int64_t)nx * (j + (int64_t)ny * k)]; };
+            const double d0 = at(i0, j0, z0);
+            for (int i = 0; i < nx; ++i) fac[0][i] = at(i, j0, z0);
+            for (int j = 0; j < ny; ++j) fac[1][j] = at(i0, j, z0) / d0;
+            for (int k = 0; k < nz; ++k) fac[2][k] = at(i0, j0, k) / d0;
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j) {
+                    const double yz = fac[1][j] * fac[2][k];
+                    for (int i = 0; i < nx; ++i) {
+                        const double want = at(i, j, k), got = fac[0][i] * yz;
+                        if (!(std::fabs(got - want) <= 1e-6 * std::fabs(want))) return CGD_OK;  // not separable
+                    }
+                }
+        }
+    }
+    std::vector<float> g[3], sv[3], dv[3], q[3];
+    std::vector<double> rowmax[3];  // per index: diagonal sum plus both face weights (dtau-free)
+    for (int a = 0; a < 3; ++a) {
+        const int na = dims[a];
+        std::vector<double> h(na), gf(na + 1, 0.0), sd(na, 0.0);
+        for (int i = 0; i < na; ++i) h[i] = edges[a][i + 1] - edges[a][i];
+        for (int i = 0; i + 1 < na; ++i) {
+            const double da = fac[a][i], db = fac[a][i + 1];
+            const double hm = (da > 0.0 && db > 0.0) ? 2.0 * da * db / (da + db) : 0.0;
+            const double df = 0.5 * (h[i] + h[i + 1]);
+            gf[i + 1] = hm / (df * std::sqrt(h[i] * h[i + 1]));
+            sd[i] += hm / (df * h[i]);
+            sd[i + 1] += hm / (df * h[i + 1]);
+        }
+        rowmax[a].resize(na);
+        for (int i = 0; i < na; ++i) rowmax[a][i] = sd[i] + gf[i] + gf[i + 1];
+        g[a].assign(gf.begin(), gf.end());
+        sv[a].assign(sd.begin(), sd.end());
+        dv[a].assign(fac[a].begin(), fac[a].end());
+        q[a].resize(na);
+        for (int i = 0; i < na; ++i) q[a][i] = (float)std::sqrt(h[i]);
+    }
+    // Gershgorin bound of M^-1/2 K M^-1/2: the largest row of
+    // Dy Dz rx_i + Dx (Dz ry_j + Dy rz_k)
+    double lam = 0.0;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j) {
+            const double dyz = fac[1][j] * fac[2][k];
+            const double b = fac[2][k] * rowmax[1][j] + fac[1][j] * rowmax[2][k];
+            for (int i = 0; i < nx; ++i) lam = std::max(lam, dyz * rowmax[0][i] + fac[0][i] * b);
+        }
+    RectOp* ro = new (std::nothrow) RectOp();
+    if (!ro) return CGD_E_NOMEM;
+    m->rop = ro;
+    ro->lam = lam;
+    for (int a = 0; a < 3; ++a) {
+        for (cgd_status r : {upload(g[a], &ro->g[a]), upload(sv[a], &ro->s[a]), upload(dv[a], &ro->d[a]),
+                             upload(q[a], &ro->q[a])})
+            if (r != CGD_OK) return r;
+    }
+    HexGeom& hg = m->hex;
+    hg.nx = nx;
+    hg.ny = ny;
+    hg.nz = nz;
+    for (int a = 0; a < 3; ++a) {
+        hg.lo[a] = edges[a][0];
+        hg.hi[a] = edges[a][dims[a]];
+        hg.h[a] = (hg.hi[a] - hg.lo[a]) / dims[a];
+        hg.s[a] = dims[a] / (hg.hi[a] - hg.lo[a]);
+    }
+    hg.vol = (hg.h[0] * hg.h[1]) * hg.h[2];
+    return CGD_OK;
+}
+
 cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s) {
     if (da.x0_mode != 0) {
         set_error("cgd_diffuse: tet meshes support x0_mode 0 only");
         return CGD_E_UNSUPPORTED;
     }
+    if (m->kind == 2 && m->rop && da.precond == 0 && !getenv("CGD_RECT_SLOTS")) return diffuse_rect_fast(m, da, out, s);
     const TetData* t = m->tet;
     const int F = da.F;
     const int n = t->n_tet;
@@ -871,6 +1022,13 @@ extern "C" cgd_status cgd_mesh_create_rect(int32_t nx, int32_t ny, int32_t nz, c
             cgd_mesh_destroy(m);
             set_error("cgd_mesh_create_rect: hipEventCreate failed");
             return CGD_E_HIP;
+        }
+    }
+    if (periodic == 0) {
+        cgd_status r = build_rect_op(m, dims, edges, diffusivity);
+        if (r != CGD_OK) {
+            cgd_mesh_destroy(m);
+            return r;
         }
     }
     *out = m;

@@ -108,6 +108,52 @@ def test_rect_coarse_grain_matches_oracle(gpu_lib, scheme, steps):
     assert mesh.nnz == n + 2 * (39 * 23 * 17 + 40 * 22 * 17 + 40 * 23 * 16)
 
 
+@pytest.mark.parametrize("nx", [40, 64, 128])  # one x segment with edge lanes; one wave per row at 1 and 2 cells per lane
+@pytest.mark.parametrize("scheme,steps", [("be", 1), ("be", 4), ("cn", 3)])
+def test_rect_separable_fast_path_matches_oracle(gpu_lib, nx, scheme, steps, monkeypatch):
+    """A diffusivity that is a product of per-axis factors (here D(x) D(y),
+    zero in an x band: PCM there) takes the stencil sweeps with per-axis
+    factors; against the oracle and against the face-slot rows
+    (CGD_RECT_SLOTS), mass conserved, the band keeps its PCM values."""
+    import torch
+    cgd = gpu_lib
+    rng = np.random.default_rng(76)
+    ex = _stretched(nx // 2, 1.03, -0.3, 1.1)
+    ey = np.concatenate(([0.1], 0.1 + np.cumsum(rng.random(19) + 0.3) / 20))
+    ez = np.linspace(2.0, 2.5, 14)
+    shape = (len(ex) - 1, len(ey) - 1, len(ez) - 1)
+    xc = 0.5 * (ex[1:] + ex[:-1])
+    Dx = np.where(np.abs(xc - 0.25) < 0.1, 0.0, 1.0 + 0.5 * np.cos(3 * xc))
+    Dy = 0.5 + rng.random(shape[1])
+    D = (Dx[None, None, :] * Dy[None, :, None] * np.ones(shape[2])[:, None, None]).astype(np.float32).ravel()
+    lo = np.array([ex[0], ey[0], ez[0]])
+    hi = np.array([ex[-1], ey[-1], ez[-1]])
+    pos = (lo + (hi - lo) * rng.random((30_000, 3))).astype(np.float32)
+    vals = np.stack([np.full(len(pos), 3.3e-8, np.float32), rng.normal(size=len(pos)).astype(np.float32)])
+    b = 0.1
+    print(f"case: rect separable fast path nx={nx} {scheme} {steps} steps", flush=True)
+    mesh = cgd.RectMesh(ex, ey, ez, diffusivity=D)
+    out, st = cgd.coarse_grain(mesh, _t(pos, torch), _t(vals, torch), b, steps, rtol=1e-7, stats=True,
+                               scheme=scheme)
+    monkeypatch.setenv("CGD_RECT_SLOTS", "1")
+    slots, _ = cgd.coarse_grain(mesh, _t(pos, torch), _t(vals, torch), b, steps, rtol=1e-7, stats=True,
+                                scheme=scheme)
+    ref, dep = O.coarse_grain_rect(pos, vals, [ex, ey, ez], b, steps, diffusivity=D.astype(np.float64),
+                                   solver="direct", scheme=scheme)
+    o, sl = out.cpu().numpy(), slots.cpu().numpy()
+    V = O.rect_volumes([ex, ey, ez])
+    frozen = D == 0
+    assert frozen.sum() > 0
+    for f in range(2):
+        assert rel_l2(o[f], ref[f]) <= REL_L2, (f, rel_l2(o[f], ref[f]))
+        assert rel_l2(sl[f], ref[f]) <= REL_L2, (f, rel_l2(sl[f], ref[f]))
+        m0 = (dep["field64"][f] * V).sum()
+        assert abs(st.mass_after[f] - m0) <= 1e-5 * np.abs(dep["field64"][f] * V).sum()
+        pcm = dep["field64"][f][frozen]
+        assert np.abs(o[f][frozen] - pcm).max() <= 1e-5 * np.abs(dep["field64"][f]).max()
+    assert st.status == 0
+
+
 def test_rect_stretched_2d_and_invalid(gpu_lib):
     """The paper's stretched mesh shape (90 x 45, ratio 1.04 towards the
     centre line) with unit diffusivity, against the oracle; invalid edges and
