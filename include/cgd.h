@@ -56,8 +56,11 @@ typedef int32_t cgd_status;
 
 typedef struct cgd_mesh_s* cgd_mesh;
 
-/* Uniform hex mesh of the box [lo, hi] with nx * ny * nz cells (zero-flux
- * walls on all six faces).  lo, hi are host arrays of 3 doubles, hi > lo.
+/* Uniform hex mesh of the box [lo, hi] with nx * ny * nz cells: the CFD mesh
+ * that the centroid deposit bins on and the diffusion equation is solved on
+ * (Section 3.1, eq. pcm-k; zero-flux walls on all six faces, Section 3.2.2;
+ * the uniform meshes of Section 4).  lo, hi are host arrays of 3 doubles,
+ * hi > lo.
  * The mesh lives on the current HIP device.  Returns CGD_E_INVALID for
  * non-positive sizes or an empty box. */
 cgd_status cgd_mesh_create_hex(int32_t nx, int32_t ny, int32_t nz,
@@ -78,7 +81,7 @@ cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz,
                                int64_t n_tet, const int32_t* tv, cgd_mesh* out);
 
 /* Stretched (rectilinear) hex mesh with a cell-wise diffusivity (Section
- * 4.2: stretched meshes; Section 5.2: a small local diffusion constant
+ * 4.3: stretched meshes; Section 5.2: a small local diffusion constant
  * degenerates the method to PCM there, conservation kept).  x_edges, y_edges,
  * z_edges: host float64 node coordinates, nx + 1, ny + 1, nz + 1 of them,
  * finite and strictly increasing; cells are numbered x fastest.
@@ -89,10 +92,13 @@ cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz,
  * volume.  The operator is the finite-volume Laplacian with flux
  * D_f A_f / d_f (e_P - e_N) through each interior face (A_f the face area,
  * d_f the distance between the two cell centres, D_f the harmonic mean of
- * the two cells' diffusivities, 0 if either is 0), stored like the tet
- * operator with six face slots per row and solved by the same
- * Jacobi-preconditioned CG (x0_mode 0).  periodic: bit a set makes axis a
- * (0 x, 1 y, 2 z) periodic (Section 3.2.2): its first and last cells share a
+ * the two cells' diffusivities, 0 if either is 0), solved by
+ * Jacobi-preconditioned CG (x0_mode 0).  When no axis is periodic and the
+ * diffusivity factors as D(i,j,k) = Dx(i) Dy(j) Dz(k) (checked to 1e-6
+ * relative at creation; NULL counts) the operator is kept as per-axis factor
+ * arrays and applied by stencil sweeps; otherwise it is stored like the tet
+ * operator with six face slots per row.  periodic: bit a set makes axis a
+ * (0 x, 1 y, 2 z) periodic (Section 3.1): its first and last cells share a
  * face at distance (h_first + h_last) / 2 instead of two walls (no effect on
  * an axis of one cell); binning is unchanged.  nx * ny * nz < 2^28, else
  * CGD_E_INVALID. */

@@ -342,7 +342,7 @@ def rect_laplacian(edges, diffusivity=None, periodic=(False, False, False)):
     D_f (A_f / d_f)(e_k - e_nb): A_f the face area, d_f the distance between
     the two cell centres, D_f = face_diffusivity of the two cells (1 when
     diffusivity is None).  Wall faces carry no flux (Section 3.2.2), except
-    on a periodic axis (Section 3.2.2: periodic conditions there), where the
+    on a periodic axis (Section 3.1: periodic conditions there), where the
     first and last cells share a face at distance (h_first + h_last) / 2
     (for two cells on that axis, a second face between the same pair)."""
     h = [np.diff(np.asarray(e, dtype=np.float64)) for e in edges]

@@ -147,7 +147,7 @@ class RectMesh(Mesh):
     """Stretched (rectilinear) hex mesh from its node coordinates per axis
     (float64, strictly increasing) and an optional cell-wise diffusivity
     (float32 [nz * ny * nx], x fastest; None: 1 everywhere).  periodic:
-    three booleans, one per axis (Section 3.2.2)."""
+    three booleans, one per axis (Section 3.1)."""
 
     def __init__(self, x_edges, y_edges, z_edges, diffusivity=None, periodic=(False, False, False)):
         import numpy as np

@@ -894,7 +894,7 @@ extern "C" cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz, int
 // between the two cell centres and D_f = 2 D_a D_b / (D_a + D_b) (0 when
 // either is 0), evaluated in float64 and rounded once; volumes
 // (hx_i hy_j) hz_k in float64.  On a periodic axis the first and last cells
-// share a face at distance (h_first + h_last) / 2 (Section 3.2.2).
+// share a face at distance (h_first + h_last) / 2 (Section 3.1).
 extern "C" cgd_status cgd_mesh_create_rect(int32_t nx, int32_t ny, int32_t nz, const double* x_edges,
                                            const double* y_edges, const double* z_edges, const float* diffusivity,
                                            int32_t periodic, cgd_mesh* out) {

@@ -631,7 +631,7 @@ def test_rect_1d_stretched_variable_diffusivity_thomas():
 
 
 def test_stretched_mesh_profile_matches_uniform_mesh():
-    """Section 4.2: on a mesh refined towards the vertical centre line with a
+    """Section 4.3: on a mesh refined towards the vertical centre line with a
     stretch ratio of 1.04 (90 x 45 cells) the coarse-grained field along the
     horizontal centre line matches the uniform 90 x 45 mesh's."""
     L, H = 1.0, 0.5
@@ -662,7 +662,7 @@ def test_stretched_mesh_profile_matches_uniform_mesh():
 
 
 def test_periodic_axis_fourier_modes_and_translation():
-    """Section 3.2.2: a periodic axis.  On a uniform periodic 1-D grid
+    """Section 3.1: a periodic axis.  On a uniform periodic 1-D grid
     K / V has the Fourier modes cos(2 pi k (i + 1/2) / n) as eigenvectors with
     eigenvalues (4 / h^2) sin^2(pi k / n); diffusing a shifted field equals
     shifting the diffused field; mass is conserved."""

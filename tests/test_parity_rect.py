@@ -182,7 +182,7 @@ def test_rect_stretched_2d_and_invalid(gpu_lib):
 
 @pytest.mark.parametrize("scheme", ["be", "cn"])
 def test_rect_periodic_matches_oracle(gpu_lib, scheme):
-    """Periodic x and z (Section 3.2.2) on a stretched grid, against the
+    """Periodic x and z (Section 3.1) on a stretched grid, against the
     oracle; mass conserved."""
     import torch
     cgd = gpu_lib
