@@ -140,6 +140,9 @@ void poly_precond_coeffs_n(double cx, double cy, double cz, int deg, double* c);
 // (those of T_{deg+1}(sig(l)) = T_{deg+1}(sig(0)) other than l = 0).
 int poly_precond_quadratics(double cx, double cy, double cz, int deg, double* s, double* q, double* g,
                             double* scale);
+// The same two for an operator whose spectrum lies in [lmin, lmax].
+void poly_precond_coeffs_iv(double lmin, double lmax, int deg, double* c);
+int poly_precond_quadratics_iv(double lmin, double lmax, int deg, double* s, double* q, double* g, double* scale);
 
 // Host: enqueues iterations through `enqueue(it)` until the device reports
 // all F fields stopped (read back one chunk late, so the device always has

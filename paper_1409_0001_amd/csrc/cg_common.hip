@@ -111,12 +111,15 @@ void poly_precond_coeffs(double cx, double cy, double cz, int deg, float* c0, fl
 }
 
 void poly_precond_coeffs_n(double cx, double cy, double cz, int deg, double* c) {
+    poly_precond_coeffs_iv(1.0, 1.0 + 4.0 * (cx + cy + cz), deg, c);
+}
+
+void poly_precond_coeffs_iv(double lmin, double lmax, int deg, double* c) {
     // p(l) = (1 - T_m(sig(l)) / T_m(sig(0))) / l with m = deg + 1 and
-    // sig(l) = (s - 2 l) / d, built from T_{n+1} = 2 sig T_n - T_{n-1} on
-    // monomial coefficient arrays in l.
+    // sig(l) = (s - 2 l) / d, s = lmax + lmin, d = lmax - lmin, built from
+    // T_{n+1} = 2 sig T_n - T_{n-1} on monomial coefficient arrays in l.
     constexpr int kMax = 8;
-    const double lmax = 1.0 + 4.0 * (cx + cy + cz);
-    const double sp = lmax + 1.0, dm = std::max(lmax - 1.0, 1e-12 * sp);
+    const double sp = lmax + lmin, dm = std::max(lmax - lmin, 1e-12 * sp);
     const int m = std::min(deg, kMax - 2) + 1;
     double t0[kMax + 1] = {1.0}, t1[kMax + 1] = {sp / dm, -2.0 / dm};
     for (int n = 1; n < m; ++n) {
@@ -137,13 +140,16 @@ void poly_precond_coeffs_n(double cx, double cy, double cz, int deg, double* c) 
 
 int poly_precond_quadratics(double cx, double cy, double cz, int deg, double* s, double* q, double* g,
                             double* scale) {
+    return poly_precond_quadratics_iv(1.0, 1.0 + 4.0 * (cx + cy + cz), deg, s, q, g, scale);
+}
+
+int poly_precond_quadratics_iv(double lmin, double lmax, int deg, double* s, double* q, double* g, double* scale) {
     // p(l) = lead prod_k (l^2 + s_k l + q_k): the roots of p are the l != 0
     // with T_n(sig(l)) = T_n(sig(0)), n = deg + 1, i.e. sig = cosh(theta + 2 pi i k / n),
     // theta = acosh(sig(0)), k = 1 .. deg, in conjugate pairs (k, n - k);
     // l = (sp - sig dm) / 2.  lead is the l^deg coefficient of
     // -(T_n(sig(l)) - T_n(sig(0))) / (T_n(sig(0)) l): -2^(n-1) (-2 / dm)^n / cosh(n theta).
-    const double lmax = 1.0 + 4.0 * (cx + cy + cz);
-    const double sp = lmax + 1.0, dm = std::max(lmax - 1.0, 1e-12 * sp);
+    const double sp = lmax + lmin, dm = std::max(lmax - lmin, 1e-12 * sp);
     const int m = deg & ~1, n = m + 1;
     const double th = std::acosh(sp / dm);
     double lead = -std::pow(2.0, n - 1) * std::pow(-2.0 / dm, n) / std::cosh(n * th);
@@ -155,9 +161,9 @@ int poly_precond_quadratics(double cx, double cy, double cz, int deg, double* s,
         const double lr = (sp - sr * dm) / 2.0, li = -si * dm / 2.0;
         s[k - 1] = -2.0 * lr;
         q[k - 1] = lr * lr + li * li;
-        // the factor is positive and convex on the spectrum [1, lmax]: its
+        // the factor is positive and convex on the spectrum [lmin, lmax]: its
         // maximum there is at an end point
-        const double f1 = 1.0 + s[k - 1] + q[k - 1], f2 = lmax * lmax + s[k - 1] * lmax + q[k - 1];
+        const double f1 = lmin * lmin + s[k - 1] * lmin + q[k - 1], f2 = lmax * lmax + s[k - 1] * lmax + q[k - 1];
         g[k - 1] = 1.0 / std::max(f1, f2);
         lead /= g[k - 1];
     }

@@ -386,15 +386,15 @@ __global__ __launch_bounds__(NW * 64) void k_dir_lds(SweepArgs a) {
 // The degree-D preconditioning sweep of preconditioned CG (precond_lds.h):
 // convergence test first (as the register sweeps' SZ prologue), then one tile
 // per block, then the block's r.z (and b.b) partials.  FORM 1, 3 and 2 are
-// the passes of the product form (two quadratic factors each): the first
-// (r -> U, coefficients pc) has the convergence test and b.b, the middle one
-// of degree 12 (U -> V, pcm) neither, the last (V -> z, pc2) the r.z
-// partials.
-template <int VEC, int D, int TY, int NW, bool FIRST, int FORM = 0>
-__global__ __launch_bounds__(NW * 64) void k_precond_lds(SweepArgs a) {
+// the passes of the product form: the first (r -> src of the next pass) has
+// the convergence test and b.b, the middle ones neither, the last (-> z) the
+// r.z partials.
+template <int VEC, int D, int TY, int NW, bool FIRST, int FORM, bool RECT>
+__device__ __forceinline__ void precond_block(const SweepArgs& a, const Geom& g, const PrecondCoef& pc,
+                                              const float* src, float* dst) {
     constexpr int NT = NW * 64;
     __shared__ double sh[NW];
-    __shared__ __align__(16) float lds[precond_lds_floats<VEC, D, TY, FORM>()];
+    __shared__ __align__(16) float lds[precond_lds_floats<VEC, D, TY, FORM, RECT>()];
 
     int b = blockIdx.x;
     if ((a.nblocks & 7) == 0) b = (b & 7) * (a.nblocks >> 3) + (b >> 3);
@@ -423,12 +423,11 @@ __global__ __launch_bounds__(NW * 64) void k_precond_lds(SweepArgs a) {
     double acc0 = 0.0, acc1 = 0.0;
     const size_t fo = (size_t)f * a.cells;
     const float* rsrc = FIRST ? a.p.B : a.p.R;  // r_k (b at a zero first guess)
-    const float* src = FORM == 2 ? a.p.V : (FORM == 3 ? a.p.U : rsrc);
-    float* dst = FORM == 1 ? a.p.U : (FORM == 3 ? a.p.V : a.p.Z);
-    constexpr int TF = FORM == 3 ? 1 : FORM;  // the middle pass is a first pass without the partials
-    precond_lds_tile<VEC, D, TY, NW, FIRST && (FORM == 0 || FORM == 1), false, TF>(
-        lds, src + fo, dst + fo, a.g, FORM == 2 ? a.pc2 : (FORM == 3 ? a.pcm : a.pc), a.ny, a.nz, yg * TY, zb,
-        min(zb + a.zc, a.nz), acc0, acc1, rsrc + fo);
+    constexpr int TF = FORM == 3 ? 1 : FORM;  // a middle pass is a first pass without the partials
+    // RECT: S on the input of the first pass and on the output of the last
+    constexpr bool SIN = RECT && (FORM == 0 || FORM == 1), SOUT = RECT && (FORM == 0 || FORM == 2);
+    precond_lds_tile<VEC, D, TY, NW, FIRST && (FORM == 0 || FORM == 1), false, TF, RECT, SIN, SOUT>(
+        lds, src + fo, dst + fo, g, pc, a.ny, a.nz, yg * TY, zb, min(zb + a.zc, a.nz), acc0, acc1, rsrc + fo);
     if constexpr (FORM == 3) return;
 
     // block reduction of the float64 partials, fixed order
@@ -453,6 +452,27 @@ __global__ __launch_bounds__(NW * 64) void k_precond_lds(SweepArgs a) {
         if (kRz) a.P3[((size_t)f * 2 + (a.k & 1)) * a.pstride + blk] = u0;
         if (kBb) a.P1[((size_t)f * 2 + 1) * a.pstride + blk] = u1;
     }
+}
+
+// Uniform grids: the Horner pass (FORM 0, coefficients pc) or the product
+// form's passes r -> U (FORM 1, pc), U -> V (FORM 3, pcm; degree 12) and
+// V -> z (FORM 2, pc2).
+template <int VEC, int D, int TY, int NW, bool FIRST, int FORM = 0>
+__global__ __launch_bounds__(NW * 64) void k_precond_lds(SweepArgs a) {
+    const float* rsrc = FIRST ? a.p.B : a.p.R;
+    const float* src = FORM == 2 ? a.p.V : (FORM == 3 ? a.p.U : rsrc);
+    float* dst = FORM == 1 ? a.p.U : (FORM == 3 ? a.p.V : a.p.Z);
+    precond_block<VEC, D, TY, NW, FIRST, FORM, false>(a, a.g, FORM == 2 ? a.pc2 : (FORM == 3 ? a.pcm : a.pc), src,
+                                                      dst);
+}
+
+// Rectilinear grids: one pass of D = 2 levels of the polynomial in S A S
+// (per-axis factors in gp) with its own coefficients and buffers (the Horner
+// pass of degree 2, or one quadratic factor of the product form).
+template <int VEC, bool FIRST, int FORM>
+__global__ __launch_bounds__(16 * 64) void k_precond_rect(SweepArgs a, Geom gp, PrecondCoef pc, const float* src,
+                                                          float* dst) {
+    precond_block<VEC, 2, 8, 16, FIRST, FORM, true>(a, gp, pc, src, dst);
 }
 
 // x0 paths: a field whose right-hand side is zero has solution zero.
@@ -626,7 +646,37 @@ void launch_sweep(int mode, const Plan& p, const SweepArgs& a, hipStream_t s) {
 constexpr int kLdsTY = 8, kLdsNW = 16;
 
 constexpr int lds_precond_bytes(int vec, int deg) {
-    return (deg == 4 ? lds_level_base<4, kLdsTY>(4) : lds_level_base<3, kLdsTY>(3)) * 64 * vec * 4;
+    return (deg == 4 ? lds_level_base<4, kLdsTY>(4)
+                     : (deg == 2 ? lds_level_base<2, kLdsTY>(2) : lds_level_base<3, kLdsTY>(3))) *
+           64 * vec * 4;
+}
+
+template <int VEC, bool FIRST>
+void launch_precond_rect_v(int form, const Plan& q, const SweepArgs& a, const Geom& gp, const PrecondCoef& pc,
+                           const float* src, float* dst, hipStream_t s) {
+    const dim3 grid(q.nblocks), block(kLdsNW * 64);
+    switch (form) {
+        case 0: hipLaunchKernelGGL((k_precond_rect<VEC, FIRST, 0>), grid, block, 0, s, a, gp, pc, src, dst); break;
+        case 1: hipLaunchKernelGGL((k_precond_rect<VEC, FIRST, 1>), grid, block, 0, s, a, gp, pc, src, dst); break;
+        case 2: hipLaunchKernelGGL((k_precond_rect<VEC, FIRST, 2>), grid, block, 0, s, a, gp, pc, src, dst); break;
+        default: hipLaunchKernelGGL((k_precond_rect<VEC, FIRST, 3>), grid, block, 0, s, a, gp, pc, src, dst); break;
+    }
+}
+
+// One pass of the rectilinear preconditioner (FORM 0: the degree-2 Horner
+// pass; 1, 3, 2: first, middle and last factor of the product form).
+void launch_precond_rect(int vec, bool first, int form, const Plan& q, const SweepArgs& a, const Geom& gp,
+                         const PrecondCoef& pc, const float* src, float* dst, hipStream_t s) {
+    if (vec == 4) {
+        if (first) launch_precond_rect_v<4, true>(form, q, a, gp, pc, src, dst, s);
+        else launch_precond_rect_v<4, false>(form, q, a, gp, pc, src, dst, s);
+    } else if (vec == 2) {
+        if (first) launch_precond_rect_v<2, true>(form, q, a, gp, pc, src, dst, s);
+        else launch_precond_rect_v<2, false>(form, q, a, gp, pc, src, dst, s);
+    } else {
+        if (first) launch_precond_rect_v<1, true>(form, q, a, gp, pc, src, dst, s);
+        else launch_precond_rect_v<1, false>(form, q, a, gp, pc, src, dst, s);
+    }
 }
 
 template <int D, int FORM>
@@ -692,6 +742,32 @@ int lds_degree(double cx, double cy, double cz, double rtol) {
     return best;
 }
 
+// Degree of the rectilinear operator's polynomial preconditioner on
+// [lmin, lmax] with the least predicted work, as lds_degree: degree m costs
+// m / 2 passes of the D = 2 tile (one for m = 2), each about 0.37 of the two
+// sweeps.  Degree 1 (Jacobi) is not a candidate: its register pass costs
+// about as much as a tile pass.
+int rect_degree(double lmin, double lmax, double rtol) {
+    const double s0 = (lmax + lmin) / std::max(lmax - lmin, 1e-12 * lmax);
+    const double th = std::acosh(std::max(s0, 1.0 + 1e-12));
+    const double want = std::log(1.0 / std::max(rtol, 1e-300));
+    int best = 2;
+    double best_cost = 1e300;
+    for (int m = 2; m <= 12; m += 2) {
+        const double e = 1.0 / std::cosh(std::min((m + 1) * th, 700.0));
+        const double K = (1.0 + e) / std::max(1.0 - e, 1e-300);
+        const double rho = (std::sqrt(K) - 1.0) / (std::sqrt(K) + 1.0);
+        const double x = rho > 0.0 ? want / std::log(1.0 / rho) : 0.0;
+        const double k = x <= 0.8 ? 1.0 : std::max(2.0, std::ceil(x));
+        const double cost = k * (1.0 + 0.37 * (m == 2 ? 1 : m / 2));
+        if (cost < best_cost * (1.0 - 1e-9)) {
+            best_cost = cost;
+            best = m;
+        }
+    }
+    return best;
+}
+
 // Tiling of the LDS preconditioning sweep: ceil(ny / TY) row groups times z
 // chunks sized to give every compute unit its share of blocks (as many as
 // its 160 KB of LDS holds).  zc_raw: the chunk depth that fills the machine,
@@ -700,7 +776,7 @@ int lds_degree(double cx, double cy, double cz, double rtol) {
 // of the degree-4 tile): at 128^3 (zc 8) degree 8 takes 1.12 ms per field,
 // degree 4 1.44 and degree 2 in registers 2.57 (before the later sweep
 // changes); at 256 x 256 x 512 (zc 64) 4.80, 5.83 and 10.31.
-Plan lds_plan(const HexGeom& g, int F, int vec, int deg, int zc_force, int* zc_raw) {
+Plan lds_plan(const HexGeom& g, int F, int vec, int deg, int zc_force, int* zc_raw, int zc_max) {
     Plan p = {};
     p.vec = vec;
     p.ty = kLdsTY;
@@ -711,7 +787,7 @@ Plan lds_plan(const HexGeom& g, int F, int vec, int deg, int zc_force, int* zc_r
     const int64_t cols = (int64_t)p.ygroups * F;
     *zc_raw = (int)std::max<int64_t>(1, ((int64_t)g.nz * cols + want_blocks - 1) / want_blocks);
     p.zc = zc_force > 0 ? zc_force : std::max(*zc_raw, 2 * deg);
-    p.zc = std::max(1, std::min(p.zc, g.nz));
+    p.zc = std::max(1, std::min({p.zc, g.nz, zc_max}));
     p.zchunks = (g.nz + p.zc - 1) / p.zc;
     p.bpf = p.ygroups * p.zchunks;
     p.wpf = p.bpf * kLdsNW;
@@ -854,18 +930,25 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, co
     a.g.cx = (float)(dtau / (g.h[0] * g.h[0]));
     a.g.cy = (float)(dtau / (g.h[1] * g.h[1]));
     a.g.cz = (float)(dtau / (g.h[2] * g.h[2]));
+    Geom gp = {};  // the rectilinear preconditioner's S A S (prepared for this dtau)
     if (ro) {
-        // the rectilinear operator (per-axis factors); its spectrum lies in
-        // [1, 1 + dtau lam] with lam the Gershgorin bound of the dtau-free
-        // part, written as equal c_a for the polynomial's interval
+        // the rectilinear operator A (per-axis factors)
         a.rect = 1;
         a.g.dt = (float)dtau;
         for (int ax = 0; ax < 3; ++ax) {
             a.g.rg[ax] = ro->g[ax];
             a.g.rs[ax] = ro->s[ax];
             a.g.rd[ax] = ro->d[ax];
+            a.g.re[ax] = ro->e[ax];
         }
-        a.g.cx = a.g.cy = a.g.cz = (float)(dtau * ro->lam / 12.0);
+        gp = a.g;
+        for (int ax = 0; ax < 3; ++ax) {
+            gp.rg[ax] = ro->pg[ax];
+            gp.rs[ax] = ro->ps[ax];
+            gp.rd[ax] = ro->pd[ax];
+            gp.re[ax] = ro->pe[ax];
+            gp.rsg[ax] = ro->psg[ax];
+        }
     }
     a.pstride = (int)max_bpf(g, F);
     a.c = ctl;
@@ -902,7 +985,7 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, co
         if (want == 3 || want == 4 || want == 8 || want == 12) {
             // degrees 8 and 12 run as two and three passes of the degree-4 tile
             const int dt = want >= 8 ? 4 : want;
-            Plan pl = lds_plan(g, F, p.vec, dt, zc_force, &zc_raw);
+            Plan pl = lds_plan(g, F, p.vec, dt, zc_force, &zc_raw, 1 << 30);
             if ((zc_force > 0 || zc_raw >= dt) && (size_t)pl.bpf <= max_bpf(g, F)) {
                 deg_lds = want;
                 pz = pl;
@@ -917,6 +1000,39 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, co
                     double c[8];
                     poly_precond_coeffs_n(a.g.cx, a.g.cy, a.g.cz, want, c);
                     precond_coef_fill(a.pc, a.g.cx, a.g.cy, a.g.cz, c, want);
+                }
+            }
+        }
+    }
+
+    // The rectilinear operator where one wave covers an x-row: S p(S A S) S
+    // with the Chebyshev polynomial p on S A S's spectrum [lmin, lmax]
+    // (RectOp), in passes of the LDS tile with D = 2 levels
+    // (k_precond_rect): degree 2 by Horner in one pass, or m / 2 passes of
+    // one quadratic factor each, by predicted cost (rect_degree); elsewhere
+    // Jacobi (the SZ modes).  CGD_HEX_PRECOND_DEG (2, 4, ..., 12; 1 for
+    // Jacobi) and CGD_HEX_LDS_ZC override.
+    int deg_rect = 0;
+    PrecondCoef rect_pc[6];
+    if (ro && row_wave) {
+        int want = rect_degree(ro->lmin, ro->lmax, da.rtol), zc_force = 0, zc_raw = 0;
+        if (const char* e = getenv("CGD_HEX_PRECOND_DEG")) want = atoi(e);
+        if (const char* e = getenv("CGD_HEX_LDS_ZC")) zc_force = atoi(e);
+        if (want >= 2 && want <= 12 && want % 2 == 0) {
+            Plan pl = lds_plan(g, F, p.vec, 2, zc_force, &zc_raw, kRectZMax - 8);  // plane table's bound
+            if ((zc_force > 0 || zc_raw >= 2) && (size_t)pl.bpf <= max_bpf(g, F)) {
+                deg_rect = want;
+                pz = pl;
+                if (want == 2) {
+                    double c[8];
+                    poly_precond_coeffs_iv(ro->lmin, ro->lmax, 2, c);
+                    precond_coef_fill(rect_pc[0], 0.f, 0.f, 0.f, c, 2);
+                } else {
+                    double qs[6], qq[6], qg[6], scale;
+                    const int nf = poly_precond_quadratics_iv(ro->lmin, ro->lmax, want, qs, qq, qg, &scale);
+                    for (int k = 0; k < nf; ++k)
+                        precond_coef_fill_quadratics(rect_pc[k], 0.f, 0.f, 0.f, qs + k, qq + k, qg + k,
+                                                     k == nf - 1 ? scale : 1.0, 2);
                 }
             }
         }
@@ -974,7 +1090,22 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, co
         const int mode = first ? mode_z_first : mode_z;
         const double cb = (double)F * cells;
         const int k0 = first ? 10 : 5;
-        if (deg_lds == 8 || deg_lds == 12) {
+        if (deg_rect) {
+            // pass k reads the previous pass's output (r or b first) and
+            // writes U, V, U, ... (z last); the middle passes share a kind
+            const Plan& q = set_plan(mode);
+            const int np = deg_rect == 2 ? 1 : deg_rect / 2;
+            const float* in = first ? a.p.B : a.p.R;
+            for (int k = 0; k < np; ++k) {
+                const int form = np == 1 ? 0 : (k == 0 ? 1 : (k == np - 1 ? 2 : 3));
+                float* out = k == np - 1 ? a.p.Z : ((k & 1) ? a.p.V : a.p.U);
+                const int t = timing_begin(&m->timing, s);
+                launch_precond_rect(p.vec, first, form, q, a, gp, rect_pc[k], in, out, s);
+                const int kind = np == 1 ? k0 : (k == 0 ? k0 : (k == np - 1 ? k0 + 2 : k0 + 1));
+                timing_end(&m->timing, t, kind, (form == 2 ? 12.0 : 8.0) * cb, s, tag);
+                in = out;
+            }
+        } else if (deg_lds == 8 || deg_lds == 12) {
             const Plan& q = set_plan(mode);
             int t = timing_begin(&m->timing, s);
             launch_precond_lds_d<4, 1>(p.vec, first, q, a, s);
@@ -1071,7 +1202,7 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, co
             // the product form's intermediate: a p buffer that holds nothing
             // live until sweep 1 writes p_new into it
             a.p.U = it == 0 ? (dir_nw ? PA : PB) : pnew;
-            a.p.V = deg_lds == 12 ? PV : a.p.U;
+            a.p.V = (deg_lds == 12 || deg_rect >= 6) ? PV : a.p.U;
             launch_precond_timed(first, tag);
             a.p.Z = Z;
             a.p.R = zb;

@@ -183,17 +183,45 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& a, char* base, con
                                hipStream_t s, const RectOp* ro = nullptr);
 
 // A rectilinear grid whose diffusivity is a product of per-axis factors
-// (D_ijk = Dx_i Dy_j Dz_k) and that has no periodic axis: the operator
-// A = I + dtau M^-1/2 K M^-1/2 in per-axis factors (device arrays; see
-// stencil::Geom) for the hex sweeps, and the square roots of the cell
-// widths for the change of variable x~ = M^1/2 x.
+// (D_ijk = Dx_i Dy_j Dz_k) and that has no periodic axis.  The solve runs on
+// A = I + dtau M^-1/2 K M^-1/2 for x~ = M^1/2 x, whose entries are products
+// of per-axis factors (stencil::Geom).  Its preconditioner is
+// S p(S A S) S with S a diagonal scaling that is itself a product of
+// per-axis factors, chosen per dtau so that S A S has a diagonal close to 1
+// (rect_op_prepare), and p the Chebyshev polynomial on S A S's spectrum.
 struct RectOp {
-    float* g[3];   // face weights [n_a + 1] (0 at walls)
-    float* s[3];   // diagonal sums [n_a]
-    float* d[3];   // diffusivity factors [n_a]
-    float* q[3];   // sqrt of the cell widths [n_a]
-    double lam;    // Gershgorin bound of M^-1/2 K M^-1/2 (times dtau: the spectrum's width)
+    // dtau-free per-axis data from the mesh: cell widths, diffusivity
+    // factors, face weights of M^-1/2 K M^-1/2 ([n + 1], 0 at walls) and its
+    // diagonal sums
+    std::vector<double> h[3], fac[3], gf[3], sd[3];
+    // device arrays of A (dtau-free): face weights g [n + 1], diagonal sums
+    // s, diffusivity factors d, identity factors e (ones), and the change of
+    // variable's factors in (sqrt h) and out (1 / sqrt h) [n each]
+    float* g[3];
+    float* s[3];
+    float* d[3];
+    float* e[3];
+    float* win[3];
+    float* wout[3];
+    // device arrays of S A S for the last prepared dtau: the same four
+    // factors with S folded in, and S's own factors sg [n each]
+    float* pg[3];
+    float* ps[3];
+    float* pd[3];
+    float* pe[3];
+    float* psg[3];
+    float* dev = nullptr;    // A's arrays
+    float* pdev = nullptr;   // S A S's arrays
+    float* host = nullptr;   // pinned staging of S A S's arrays
+    size_t pfloats = 0;
+    double dtau = -1.0;      // dtau S A S was formed for (-1: none yet)
+    double lmin = 1.0, lmax = 1.0;  // bounds of S A S's spectrum
 };
+
+// Forms S A S's device arrays and spectrum bounds for dtau (no work when
+// dtau is the one of the last call; otherwise synchronises the stream once
+// before the staging buffer is rewritten).
+cgd_status rect_op_prepare(cgd_mesh m, double dtau, hipStream_t s);
 
 // mom[c][k] /= eps[k] where eps[k] > eps_min, else 0 (cg_common.hip).
 void velocity_from_momentum(int64_t cells, int n_comp, const float* eps, float* mom, float eps_min,

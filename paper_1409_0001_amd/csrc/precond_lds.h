@@ -56,10 +56,14 @@ __device__ __forceinline__ void x_neighbours(const Vec<VEC>& c, float& lft, floa
 // above]), w = (no plane below) + 2 (no plane above), and nk = -ca c (stored
 // negated so that every term is one multiply-add with a scalar operand); a
 // missing plane also drops its nkz term.
+// The rectilinear operator (RECT tiles) has per-cell coefficients, formed
+// in the tile from the per-axis factors; a level there is u = gg (A u_prev)
+// + gs u_prev + cr (extra term), with gg and gs below.
 constexpr int kPcMaxD = 4;
 struct PrecondCoef {
     float kd[kPcMaxD][4];
     float nkx[kPcMaxD], nky[kPcMaxD], nkz[kPcMaxD], cr[kPcMaxD];
+    float gg[kPcMaxD], gs[kPcMaxD];
 };
 
 // cp: the D + 1 polynomial coefficients (float64, from poly_precond_coeffs_n).
@@ -73,6 +77,8 @@ inline void precond_coef_fill(PrecondCoef& pc, float cx, float cy, float cz, con
         pc.nky[j - 1] = -(ca * cy);
         pc.nkz[j - 1] = -(ca * cz);
         pc.cr[j - 1] = (float)cp[D - j];
+        pc.gg[j - 1] = ca;
+        pc.gs[j - 1] = 0.f;
     }
 }
 
@@ -82,15 +88,16 @@ inline void precond_coef_fill(PrecondCoef& pc, float cx, float cy, float cz, con
 // s2 u3 + q2 u2), in the coefficients above (kd folds s and the walls; cr
 // weights the level's extra term: v at level 2, u2 at level 4, none at odd
 // levels).  s, q, g: the pass's two factors (poly_precond_quadratics); last:
-// the polynomial's overall scale on the final pass, else 1.
+// the polynomial's overall scale on the final pass, else 1.  D = 2: one
+// factor per pass (levels 1 and 2).
 inline void precond_coef_fill_quadratics(PrecondCoef& pc, float cx, float cy, float cz, const double* s,
-                                         const double* q, const double* g, double last) {
+                                         const double* q, const double* g, double last, int D = 4) {
     pc = PrecondCoef{};
     const double d_in = 1.0 + 2.0 * ((double)cx + (double)cy + (double)cz);
-    for (int j = 1; j <= 4; ++j) {
+    for (int j = 1; j <= D; ++j) {
         const bool even = (j & 1) == 0;
         const int k = (j - 1) / 2;
-        const double gg = even ? g[k] * (j == 4 ? last : 1.0) : 1.0;
+        const double gg = even ? g[k] * (j == D ? last : 1.0) : 1.0;
         const double sh = even ? s[k] : 0.0;
         for (int w = 0; w < 4; ++w)
             pc.kd[j - 1][w] = (float)(gg * (d_in - ((w & 1) ? cz : 0.0) - ((w & 2) ? cz : 0.0) + sh));
@@ -98,6 +105,8 @@ inline void precond_coef_fill_quadratics(PrecondCoef& pc, float cx, float cy, fl
         pc.nky[j - 1] = (float)(-gg * cy);
         pc.nkz[j - 1] = (float)(-gg * cz);
         pc.cr[j - 1] = even ? (float)(gg * q[k]) : 0.f;
+        pc.gg[j - 1] = (float)gg;
+        pc.gs[j - 1] = (float)(gg * sh);
     }
 }
 
@@ -110,25 +119,38 @@ __host__ __device__ constexpr int lds_level_base(int j) {
     return rows;
 }
 
-// LDS floats a tile needs: levels 0..D-1 (precond_lds_tile's `lds`), and
-// for FORM 2 two planes of the output rows of r.
-template <int VEC, int D, int TY, int FORM = 0>
+// RECT tiles: the z factors of every plane a block touches (its chunk and
+// D halo planes each side) sit in an LDS table of kZtStride floats per
+// plane, so the march reads them from LDS; the host keeps chunks of such
+// tiles to at most kRectZMax - 2 D planes.
+constexpr int kRectZMax = 264, kZtStride = 8;
+
+// LDS floats a tile needs: levels 0..D-1 (precond_lds_tile's `lds`), for
+// FORM 2 two planes of the output rows of r, and RECT's plane table.
+template <int VEC, int D, int TY, int FORM = 0, bool RECT = false>
 __host__ __device__ constexpr int precond_lds_floats() {
-    return (lds_level_base<D, TY>(D) + (FORM == 2 ? 2 * TY : 0)) * 64 * VEC;
+    return (lds_level_base<D, TY>(D) + (FORM == 2 ? 2 * TY : 0)) * 64 * VEC + (RECT ? kRectZMax * kZtStride : 0);
 }
 
 // lds: precond_lds_floats<VEC, D, TY, FORM>() floats of LDS, 16-byte aligned.
 // FORM 0: z = p(A) r by Horner (src = r); acc0 = r.z (and acc1 = b.b when
-// FIRST).  FORM 1 and 2 (D = 4): one pass of the product form (src = the
-// pass's input v; dst = its output); FORM 1 adds acc1 = v.v when FIRST (v =
-// b), FORM 2 adds acc0 = r.dst with r read from side_field (the loaders feed
-// the output rows of r through LDS).
-template <int VEC, int D, int TY, int NW, bool FIRST, bool PF = false, int FORM = 0>
+// FIRST).  FORM 1 and 2 (D = 4, or D = 2 for one factor): one pass of the
+// product form (src = the pass's input v; dst = its output); FORM 1 adds
+// acc1 = v.v when FIRST (v = b), FORM 2 adds acc0 = r.dst with r read from
+// side_field (the loaders feed the output rows of r through LDS).  RECT: the
+// rectilinear operator of Geom (per-cell coefficients from per-axis
+// factors; walls have zero face weights) with the levels' gg, gs.  SIN /
+// SOUT (RECT): the input is multiplied by the scaling S (Geom::rsg) as it
+// enters LDS / the output by S before it is stored, so that the passes
+// apply S p(A) S; FIRST then takes b.b from the loaders' unscaled rows, and
+// FORM 0's r.z is (S r).p(A)(S r).
+template <int VEC, int D, int TY, int NW, bool FIRST, bool PF = false, int FORM = 0, bool RECT = false,
+          bool SIN = false, bool SOUT = false>
 __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __restrict__ src_field,
                                         float* __restrict__ dst_field, const Geom& g, const PrecondCoef& pc, int ny, int nz,
                                         int y0, int zb, int ze, double& acc0, double& acc1,
                                         const float* __restrict__ side_field = nullptr) {
-    static_assert(FORM == 0 || D == 4, "the product form runs two quadratic factors per pass");
+    static_assert(FORM == 0 || D == 4 || D == 2, "the product form runs one or two quadratic factors per pass");
     constexpr int NXR = 64 * VEC;
     constexpr int E0 = TY + 2 * D;
     constexpr int NL = NW - TY;                  // waves owning no output row: the loaders
@@ -177,6 +199,54 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     const int tl = min(nz, ze + D) - 1;  // last plane of r needed
     const int t1 = ze - 1 + D;           // last step (plane ze - 1 of z completes)
     (void)g;
+    // RECT: this lane's x factors and this wave's row factors, for every
+    // level, and the plane table (planes t0 .. tl: face weights below and
+    // above, diagonal sum, diffusivity, identity factor, S), filled here and
+    // first read after the barrier that ends the set-up below
+    RectX<VEC> X;
+    RectA Yw;
+    float sgx[VEC], sgy = 1.f;  // S of this lane's cells on x, of this wave's row on y
+    float* ztab = lds + (lds_level_base<D, TY>(D) + (FORM == 2 ? 2 * TY : 0)) * NXR;
+    if constexpr (RECT) {
+        X = rect_x<VEC>(g, x0);
+        Yw = rect_a(g, 1, yw, ny);
+        for (int i = threadIdx.x; i < (tl - t0 + 1) * kZtStride; i += NW * 64) {
+            const int q = t0 + i / kZtStride, f = i % kZtStride;
+            float v = 0.f;
+            if (f == 0) v = g.rg[2][q];
+            else if (f == 1) v = g.rg[2][q + 1];
+            else if (f == 2) v = g.rs[2][q];
+            else if (f == 3) v = g.rd[2][q];
+            else if (f == 4) v = g.re[2][q];
+            else if (f == 5) v = (SIN || SOUT) ? g.rsg[2][q] : 1.f;
+            ztab[i] = v;
+        }
+    }
+    if constexpr (SIN || SOUT) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) sgx[e] = g.rsg[0][x0 + e];
+        sgy = g.rsg[1][min(max(yw, 0), ny - 1)];
+    }
+    // SIN: S on the y axis of the loader's rows (fixed for the march)
+    float sgl[2] = {1.f, 1.f};
+    // SIN: a row of the input entering LDS at plane q (extent row e, the
+    // loader's row i): b.b over the output cells from the unscaled values,
+    // then the scaling (S on z from the table, or from memory during the
+    // set-up, before the table is complete)
+    auto scale_in = [&](Vec<VEC>& v, int e, int i, int q, bool setup) {
+        if constexpr (SIN) {
+            const int y = y0 - D + e;
+            if (FIRST && e >= D && e < D + TY && y < ny && q >= zb && q < ze) {
+#pragma unroll
+                for (int k = 0; k < VEC; ++k) acc1 = fma((double)v.f[k], (double)v.f[k], acc1);
+            }
+            const int qc = min(max(q, t0), tl);  // a plane beyond tl holds tl's values (unused)
+            const float sz = setup ? g.rsg[2][qc] : ztab[(qc - t0) * kZtStride + 5];
+            const float syz = sgl[i] * sz;
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) v.f[k] *= sgx[k] * syz;
+        }
+    };
 
     // r of this row, plane t0 + s at slot s mod RK: Horner (FORM 0) weights r
     // at every level (planes t - 1 .. t - D); the product form only at level 2
@@ -214,7 +284,10 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {
                 const int e = li + NL * i;
-                if (e < E0) stv<VEC>(row0(t + 1, e), pf[B][i]);
+                if (e < E0) {
+                    scale_in(pf[B][i], e, i, t + 1, false);
+                    stv<VEC>(row0(t + 1, e), pf[B][i]);
+                }
             }
             const int tn = min(t + 1 + P, tl);
 #pragma unroll
@@ -304,7 +377,29 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 const bool hzd = q > 0, hzu = q + 1 < nz;
                 const float cr = pc.cr[j - 1];
                 Vec<VEC> u;
-                if (hzd && hzu && pc.nkx[j - 1] == pc.nky[j - 1]) {
+                if constexpr (RECT) {
+                    // u = gg (A c) + gs c + cr ex with A's coefficients of
+                    // this row at plane q (gg folded into the row-and-plane
+                    // products); a wall's face weight is zero, so whatever
+                    // finite value stands beyond it drops out
+                    const float* zt = ztab + (q - t0) * kZtStride;
+                    const float4 z4 = *reinterpret_cast<const float4*>(zt);  // gd, gu, s, d
+                    const RectYZ yz = rect_yz(g, Yw, RectA{z4.x, z4.y, z4.z, z4.w, zt[4]});
+                    const float gg = pc.gg[j - 1], gs = pc.gs[j - 1];
+                    const float nbd = -gg * yz.bd, nbu = -gg * yz.bu, ncd = -gg * yz.cd, ncu = -gg * yz.cu;
+                    const float ge = gg * yz.e, gdyz = gg * yz.dyz, ga = gg * yz.a;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const float l = e > 0 ? c.f[e - 1] : lft;
+                        const float r = e + 1 < VEC ? c.f[e + 1] : rgt;
+                        const float xs = fmaf(X.gl[e], l, X.gr[e] * r);
+                        const float yzs = fmaf(nbd, yd.f[e], fmaf(nbu, yu.f[e], fmaf(ncd, zl.f[e], ncu * zh.f[e])));
+                        const float kdc = fmaf(X.e[e], ge, fmaf(X.s[e], gdyz, fmaf(X.d[e], ga, gs)));
+                        float v = has_ex ? fmaf(kdc, c.f[e], cr * ex.f[e]) : kdc * c.f[e];
+                        v = fmaf(-gdyz, xs, v);
+                        u.f[e] = fmaf(X.d[e], yzs, v);
+                    }
+                } else if (hzd && hzu && pc.nkx[j - 1] == pc.nky[j - 1]) {
                     const float kd = pc.kd[j - 1][0], nkx = pc.nkx[j - 1], nkz = pc.nkz[j - 1];
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
@@ -331,7 +426,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                     }
                 }
                 if (j == 1) u1 = u;
-                if (FIRST && FORM == 1 && j == 1 && owner && q >= zb && q < ze) {
+                if (FIRST && FORM == 1 && !SIN && j == 1 && owner && q >= zb && q < ze) {
                     // b.b over the output cells, from this row's b at plane q
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) acc1 = fma((double)c.f[e], (double)c.f[e], acc1);
@@ -343,16 +438,22 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 if (j >= 2 && j < D) lv[j >= 2 ? j - 2 : 0][((S - j) % 3 + 3) % 3] = u;
                 if (j == D && owner && q >= zb && q < ze) {
                     // output of plane q complete: store it and add r.z (and b.b)
-                    stv<VEC>(dst_field + x0 + (size_t)q * plane + (size_t)yw * nx, u);
+                    Vec<VEC> us = u;
+                    if constexpr (SOUT) {
+                        const float syz = sgy * ztab[(q - t0) * kZtStride + 5];
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) us.f[e] *= sgx[e] * syz;
+                    }
+                    stv<VEC>(dst_field + x0 + (size_t)q * plane + (size_t)yw * nx, us);
                     if constexpr (FORM == 2) {
                         const Vec<VEC> rr = ld(side_row(q, w - D));
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) acc0 = fma((double)rr.f[e], (double)u.f[e], acc0);
+                        for (int e = 0; e < VEC; ++e) acc0 = fma((double)rr.f[e], (double)us.f[e], acc0);
                     }
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
                         if (FORM == 0) acc0 = fma((double)rq.f[e], (double)u.f[e], acc0);
-                        if (FIRST && FORM == 0) acc1 = fma((double)rq.f[e], (double)rq.f[e], acc1);
+                        if (FIRST && FORM == 0 && !SIN) acc1 = fma((double)rq.f[e], (double)rq.f[e], acc1);
                     }
                 }
             }
@@ -381,7 +482,11 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {
                 const int e = li + NL * i;
-                if (e < E0) stv<VEC>(row0(t0, e), pf[0][i]);
+                if constexpr (SIN) sgl[i] = g.rsg[1][min(max(y0 - D + e, 0), ny - 1)];
+                if (e < E0) {
+                    scale_in(pf[0][i], e, i, t0, true);
+                    stv<VEC>(row0(t0, e), pf[0][i]);
+                }
             }
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {

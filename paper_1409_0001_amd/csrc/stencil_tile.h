@@ -57,19 +57,24 @@ struct Geom {
     // the iterate is 2 y - b when y solves the half step (0, 0: plain x)
     float xs1, xb;
     // Rectilinear grids with a separable diffusivity (RECT kernels): the
-    // operator is A = I + dt M^-1/2 K M^-1/2 (M the cell volumes, K the
-    // finite-volume Laplacian with harmonic-mean face diffusivities), whose
-    // entries are products of per-axis factors.  Per axis a with n cells:
-    // rg[a] [n + 1] face weights (0 at a wall), rs[a] [n] the cell's own
-    // diagonal sum over its two faces, rd[a] [n] the diffusivity factor.
-    // Cell (i, j, k) with D = Dx_i Dy_j Dz_k:
-    //   (A v) = (1 + dt (Dy Dz sx_i + Dx (Dz sy_j + Dy sz_k))) v
+    // operator is A = S (I + dt M^-1/2 K M^-1/2) S (M the cell volumes, K the
+    // finite-volume Laplacian with harmonic-mean face diffusivities, S a
+    // diagonal scaling that is a product of per-axis factors: the identity
+    // for the CG sweeps, a preconditioner's scaling in the polynomial
+    // passes), whose entries are products of per-axis factors.  Per axis a
+    // with n cells: rg[a] [n + 1] face weights (0 at a wall), rs[a] [n] the
+    // cell's own diagonal sum over its two faces, rd[a] [n] the diffusivity
+    // factor, re[a] [n] the identity's factor (all with S folded in), rsg[a]
+    // [n] S's own factors (polynomial passes only).  Cell (i, j, k):
+    //   (A v) = (ex ey ez + dt (Dy Dz sx_i + Dx (Dz sy_j + Dy sz_k))) v
     //           - dt Dy Dz (gx_i v_{i-1} + gx_{i+1} v_{i+1})
     //           - dt Dx Dz (gy_j v_{j-1} + gy_{j+1} v_{j+1})
     //           - dt Dx Dy (gz_k v_{k-1} + gz_{k+1} v_{k+1})
     const float* rg[3];
     const float* rs[3];
     const float* rd[3];
+    const float* re[3];
+    const float* rsg[3];
     float dt;
 };
 
@@ -77,7 +82,7 @@ struct Geom {
 // loaded once per tile; lane cells beyond the grid take the last cell's.
 template <int VEC>
 struct RectX {
-    float gl[VEC], gr[VEC], s[VEC], d[VEC];
+    float gl[VEC], gr[VEC], s[VEC], d[VEC], e[VEC];
 };
 
 template <int VEC>
@@ -90,28 +95,30 @@ __device__ __forceinline__ RectX<VEC> rect_x(const Geom& g, int x0) {
         X.gr[e] = g.dt * g.rg[0][i + 1];
         X.s[e] = g.dt * g.rs[0][i];
         X.d[e] = g.rd[0][i];
+        X.e[e] = g.re[0][i];
     }
     return X;
 }
 
 // RECT: the y and z factors of one row at one plane (wave-uniform values).
 struct RectYZ {
-    float dyz, a, bd, bu, cd, cu;
+    float e, dyz, a, bd, bu, cd, cu;
 };
 
 // The factors of one row (y) or one plane (z): lower and upper face
-// weights, diagonal sum, diffusivity factor.
+// weights, diagonal sum, diffusivity factor, identity factor.
 struct RectA {
-    float gd, gu, s, d;
+    float gd, gu, s, d, e;
 };
 
 __device__ __forceinline__ RectA rect_a(const Geom& g, int axis, int i, int n) {
     i = min(max(i, 0), n - 1);
-    return RectA{g.rg[axis][i], g.rg[axis][i + 1], g.rs[axis][i], g.rd[axis][i]};
+    return RectA{g.rg[axis][i], g.rg[axis][i + 1], g.rs[axis][i], g.rd[axis][i], g.re[axis][i]};
 }
 
 __device__ __forceinline__ RectYZ rect_yz(const Geom& g, const RectA& Y, const RectA& Z) {
     RectYZ r;
+    r.e = Y.e * Z.e;
     r.dyz = Y.d * Z.d;
     r.a = g.dt * fmaf(Z.d, Y.s, Y.d * Z.s);
     r.bd = g.dt * Z.d * Y.gd;
@@ -128,7 +135,7 @@ __device__ __forceinline__ RectYZ rect_yz(const Geom& g, int y, int z) {
 // RECT: the diagonal of A at one cell.
 template <int VEC>
 __device__ __forceinline__ float rect_diag(const RectX<VEC>& X, int e, const RectYZ& q) {
-    return fmaf(q.dyz, X.s[e], fmaf(X.d[e], q.a, 1.f));
+    return fmaf(q.dyz, X.s[e], fmaf(X.d[e], q.a, X.e[e] * q.e));
 }
 
 // RECT: (A v) at one cell (a neighbour across a wall has weight 0, so any

@@ -446,9 +446,9 @@ size_t tet_small(int F, int bpf) {
 
 void destroy_tet_data(cgd_mesh m) {
     if (RectOp* ro = m->rop) {
-        for (int a = 0; a < 3; ++a)
-            for (float* p : {ro->g[a], ro->s[a], ro->d[a], ro->q[a]})
-                if (p) (void)hipFree(p);
+        if (ro->dev) (void)hipFree(ro->dev);
+        if (ro->pdev) (void)hipFree(ro->pdev);
+        if (ro->host) (void)hipHostFree(ro->host);
         delete ro;
         m->rop = nullptr;
     }
@@ -545,37 +545,122 @@ cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
 }
 
 namespace {
-// The change of variable of the rectilinear fast path: field *= sqrt(V)
-// (dir > 0) or field /= sqrt(V), sqrt(V) = sqrt(hx_i) sqrt(hy_j) sqrt(hz_k)
-// formed the same way both times.
+// The change of variable of the rectilinear fast path: field *= fx_i fy_j fz_k
+// (sqrt of the cell widths going in, their reciprocals coming out).
 __global__ __launch_bounds__(kBlock) void k_rect_scale(float* __restrict__ field, int64_t cells, int nx, int ny,
-                                                      const float* __restrict__ qx, const float* __restrict__ qy,
-                                                      const float* __restrict__ qz, int dir) {
+                                                      const float* __restrict__ fx, const float* __restrict__ fy,
+                                                      const float* __restrict__ fz) {
     float* f = field + (size_t)blockIdx.y * cells;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(c % nx);
         const int64_t r = c / nx;
         const int j = (int)(r % ny);
         const int k = (int)(r / ny);
-        const float q = (qx[i] * qy[j]) * qz[k];
-        f[c] = dir > 0 ? f[c] * q : f[c] / q;
+        f[c] *= (fx[i] * fy[j]) * fz[k];
     }
 }
 }  // namespace
 
+// The scaling S of the rectilinear preconditioner and the bounds of S A S's
+// spectrum.  A's diagonal d_ijk = 1 + dtau (Dy Dz sx_i + Dx Dz sy_j + Dx Dy
+// sz_k) is a sum of products of per-axis factors; S^2 = mu^2 / (dx_i dy_j
+// dz_k), where dx_i is the mean of d over j and k (and so on) and mu the mean
+// of d over all cells, which is exactly 1 / d when d itself is a product of
+// per-axis factors.  Every mean is a product of per-axis means.  Since K is
+// positive semi-definite, S A S >= S^2, so lmin = min S^2 = the product of
+// the per-axis minima; lmax is the largest Gershgorin row sum of S A S, a max
+// over the cells of ex_i E_jk + hx_i P_jk + Dx_i Q_jk (nonnegative terms),
+// one pass over the cells.
+cgd_status rect_op_prepare(cgd_mesh m, double dtau, hipStream_t s) {
+    RectOp* ro = m->rop;
+    if (ro->dtau == dtau) return CGD_OK;
+    const int n[3] = {m->hex.nx, m->hex.ny, m->hex.nz};
+    auto mean = [](const std::vector<double>& v) {
+        double t = 0.0;
+        for (double x : v) t += x;
+        return t / (double)v.size();
+    };
+    double mD[3], ms[3];
+    for (int a = 0; a < 3; ++a) {
+        mD[a] = mean(ro->fac[a]);
+        ms[a] = mean(ro->sd[a]);
+    }
+    const double mu = 1.0 + dtau * (ms[0] * mD[1] * mD[2] + mD[0] * ms[1] * mD[2] + mD[0] * mD[1] * ms[2]);
+    const double mu23 = std::cbrt(mu * mu);
+    std::vector<double> sig2[3];
+    for (int a = 0; a < 3; ++a) {
+        const int b = (a + 1) % 3, c = (a + 2) % 3;
+        sig2[a].resize(n[a]);
+        for (int i = 0; i < n[a]; ++i) {
+            // mean over the other two axes of d at index i on axis a
+            const double da = 1.0 + dtau * (ro->sd[a][i] * mD[b] * mD[c] + ro->fac[a][i] * (ms[b] * mD[c] + mD[b] * ms[c]));
+            sig2[a][i] = mu23 / da;
+        }
+    }
+    // S A S's per-axis factors; h_a = s'_a + g'_a(lower) + g'_a(upper) for the Gershgorin sums
+    std::vector<double> gs[3], ss[3], ds[3], hs[3];
+    double lmin = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        const int na = n[a];
+        gs[a].assign(na + 1, 0.0);
+        ss[a].resize(na);
+        ds[a].resize(na);
+        hs[a].resize(na);
+        double mn = sig2[a][0];
+        for (int i = 0; i < na; ++i) {
+            ss[a][i] = sig2[a][i] * ro->sd[a][i];
+            ds[a][i] = sig2[a][i] * ro->fac[a][i];
+            mn = std::min(mn, sig2[a][i]);
+        }
+        for (int i = 1; i < na; ++i) gs[a][i] = std::sqrt(sig2[a][i - 1] * sig2[a][i]) * ro->gf[a][i];
+        for (int i = 0; i < na; ++i) hs[a][i] = ss[a][i] + gs[a][i] + gs[a][i + 1];
+        lmin *= mn;
+    }
+    double lmax = 0.0;
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j) {
+            const double E = sig2[1][j] * sig2[2][k];
+            const double P = dtau * ds[1][j] * ds[2][k];
+            const double Q = dtau * (ds[2][k] * hs[1][j] + ds[1][j] * hs[2][k]);
+            double rmax = 0.0;
+            for (int i = 0; i < n[0]; ++i) rmax = std::max(rmax, sig2[0][i] * E + hs[0][i] * P + ds[0][i] * Q);
+            lmax = std::max(lmax, rmax);
+        }
+    // stage and upload (the previous call's copy and kernels must be done
+    // with the staging buffer and the device arrays' old contents)
+    CGD_HIP_TRY(hipStreamSynchronize(s));
+    float* h = ro->host;
+    size_t o = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int na = n[a];
+        for (int i = 0; i <= na; ++i) h[o++] = (float)gs[a][i];
+        for (int i = 0; i < na; ++i) h[o++] = (float)ss[a][i];
+        for (int i = 0; i < na; ++i) h[o++] = (float)ds[a][i];
+        for (int i = 0; i < na; ++i) h[o++] = (float)sig2[a][i];
+        for (int i = 0; i < na; ++i) h[o++] = (float)std::sqrt(sig2[a][i]);
+    }
+    CGD_HIP_TRY(hipMemcpyAsync(ro->pdev, h, o * sizeof(float), hipMemcpyHostToDevice, s));
+    ro->dtau = dtau;
+    ro->lmin = lmin;
+    ro->lmax = std::max(lmax, lmin * (1.0 + 1e-6));
+    return CGD_OK;
+}
+
 // Rectilinear grid with a separable diffusivity: the uniform grid's sweeps
 // on A = I + dtau M^-1/2 K M^-1/2 for x~ = M^1/2 x (the same system as
-// (M + dtau K) x = M e, scaled symmetrically), with the polynomial
-// preconditioner on [1, 1 + dtau lam]; the stopping rule applies to the
-// scaled residual.
+// (M + dtau K) x = M e, scaled symmetrically), preconditioned by
+// S p(S A S) S (RectOp); the stopping rule applies to the scaled residual.
 static cgd_status diffuse_rect_fast(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s) {
     const TetData* t = m->tet;
-    const RectOp* ro = m->rop;
+    RectOp* ro = m->rop;
     const int F = da.F;
     const int n = t->n_tet;
     cgd_status rc = ensure_workspace(m, diffuse_hex_workspace(m, F));
     if (rc != CGD_OK) return rc;
     rc = ensure_pinned(m, kPinBytes);
+    if (rc != CGD_OK) return rc;
+    const double T = da.bandwidth * da.bandwidth / 4.0;
+    rc = rect_op_prepare(m, T / da.n_steps * (da.scheme == 1 ? 0.5 : 1.0), s);
     if (rc != CGD_OK) return rc;
     char* base = static_cast<char*>(m->ws.ptr);
     double* d_sums = reinterpret_cast<double*>(base + kOffSums);
@@ -587,11 +672,11 @@ static cgd_status diffuse_rect_fast(cgd_mesh m, const DiffuseArgs& da, cgd_solve
     }
     const int sblocks = std::min(4096, (n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_rect_scale, dim3(sblocks, F), dim3(kBlock), 0, s, da.field, (int64_t)n, m->hex.nx,
-                       m->hex.ny, ro->q[0], ro->q[1], ro->q[2], 1);
+                       m->hex.ny, ro->win[0], ro->win[1], ro->win[2]);
     rc = diffuse_hex_enqueue(m, da, base, nullptr, false, s, ro);
     if (rc != CGD_OK) return rc;
     hipLaunchKernelGGL(k_rect_scale, dim3(sblocks, F), dim3(kBlock), 0, s, da.field, (int64_t)n, m->hex.nx,
-                       m->hex.ny, ro->q[0], ro->q[1], ro->q[2], -1);
+                       m->hex.ny, ro->wout[0], ro->wout[1], ro->wout[2]);
     if (out) {
         hipLaunchKernelGGL(k_tet_mass, dim3(mbpf, F), dim3(kBlock), 0, s, da.field, t->vol, n, d_mpart, mbpf);
         hipLaunchKernelGGL(k_tet_sum_finish, dim3(F), dim3(kBlock), 0, s, d_mpart, mbpf, d_sums + CGD_MAX_FIELDS);
@@ -631,11 +716,19 @@ static cgd_status build_rect_op(cgd_mesh m, const int32_t dims[3], const double*
                 }
         }
     }
-    std::vector<float> g[3], sv[3], dv[3], q[3];
-    std::vector<double> rowmax[3];  // per index: diagonal sum plus both face weights (dtau-free)
+    RectOp* ro = new (std::nothrow) RectOp();
+    if (!ro) return CGD_E_NOMEM;
+    m->rop = ro;
+    size_t pfloats = 0;
+    std::vector<float> hA;  // A's arrays, in RectOp's order
     for (int a = 0; a < 3; ++a) {
         const int na = dims[a];
-        std::vector<double> h(na), gf(na + 1, 0.0), sd(na, 0.0);
+        std::vector<double>& h = ro->h[a];
+        std::vector<double>& gf = ro->gf[a];
+        std::vector<double>& sd = ro->sd[a];
+        h.resize(na);
+        gf.assign(na + 1, 0.0);
+        sd.assign(na, 0.0);
         for (int i = 0; i < na; ++i) h[i] = edges[a][i + 1] - edges[a][i];
         for (int i = 0; i + 1 < na; ++i) {
             const double da = fac[a][i], db = fac[a][i + 1];
@@ -645,31 +738,51 @@ static cgd_status build_rect_op(cgd_mesh m, const int32_t dims[3], const double*
             sd[i] += hm / (df * h[i]);
             sd[i + 1] += hm / (df * h[i + 1]);
         }
-        rowmax[a].resize(na);
-        for (int i = 0; i < na; ++i) rowmax[a][i] = sd[i] + gf[i] + gf[i + 1];
-        g[a].assign(gf.begin(), gf.end());
-        sv[a].assign(sd.begin(), sd.end());
-        dv[a].assign(fac[a].begin(), fac[a].end());
-        q[a].resize(na);
-        for (int i = 0; i < na; ++i) q[a][i] = (float)std::sqrt(h[i]);
+        ro->fac[a] = fac[a];
+        for (int i = 0; i <= na; ++i) hA.push_back((float)gf[i]);
+        for (int i = 0; i < na; ++i) hA.push_back((float)sd[i]);
+        for (int i = 0; i < na; ++i) hA.push_back((float)fac[a][i]);
+        for (int i = 0; i < na; ++i) hA.push_back(1.f);
+        for (int i = 0; i < na; ++i) hA.push_back((float)std::sqrt(h[i]));
+        for (int i = 0; i < na; ++i) hA.push_back((float)(1.0 / std::sqrt(h[i])));
+        pfloats += (size_t)na + 1 + 4 * (size_t)na;
     }
-    // Gershgorin bound of M^-1/2 K M^-1/2: the largest row of
-    // Dy Dz rx_i + Dx (Dz ry_j + Dy rz_k)
-    double lam = 0.0;
-    for (int k = 0; k < nz; ++k)
-        for (int j = 0; j < ny; ++j) {
-            const double dyz = fac[1][j] * fac[2][k];
-            const double b = fac[2][k] * rowmax[1][j] + fac[1][j] * rowmax[2][k];
-            for (int i = 0; i < nx; ++i) lam = std::max(lam, dyz * rowmax[0][i] + fac[0][i] * b);
-        }
-    RectOp* ro = new (std::nothrow) RectOp();
-    if (!ro) return CGD_E_NOMEM;
-    m->rop = ro;
-    ro->lam = lam;
+    ro->pfloats = pfloats;
+    cgd_status rc = upload(hA, &ro->dev);
+    if (rc != CGD_OK) return rc;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&ro->pdev), pfloats * sizeof(float));
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ro->host), pfloats * sizeof(float), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(std::string("cgd_mesh_create_rect: allocation failed: ") + hipGetErrorString(e));
+        return CGD_E_NOMEM;
+    }
+    float* p = ro->dev;
+    float* pp = ro->pdev;
     for (int a = 0; a < 3; ++a) {
-        for (cgd_status r : {upload(g[a], &ro->g[a]), upload(sv[a], &ro->s[a]), upload(dv[a], &ro->d[a]),
-                             upload(q[a], &ro->q[a])})
-            if (r != CGD_OK) return r;
+        const int na = dims[a];
+        ro->g[a] = p;
+        p += na + 1;
+        ro->s[a] = p;
+        p += na;
+        ro->d[a] = p;
+        p += na;
+        ro->e[a] = p;
+        p += na;
+        ro->win[a] = p;
+        p += na;
+        ro->wout[a] = p;
+        p += na;
+        ro->pg[a] = pp;
+        pp += na + 1;
+        ro->ps[a] = pp;
+        pp += na;
+        ro->pd[a] = pp;
+        pp += na;
+        ro->pe[a] = pp;
+        pp += na;
+        ro->psg[a] = pp;
+        pp += na;
     }
     HexGeom& hg = m->hex;
     hg.nx = nx;

@@ -154,6 +154,60 @@ def test_rect_separable_fast_path_matches_oracle(gpu_lib, nx, scheme, steps, mon
     assert st.status == 0
 
 
+@pytest.mark.parametrize("nx", [64, 128])
+@pytest.mark.parametrize("deg", [2, 4, 12])
+@pytest.mark.parametrize("scheme,steps", [("be", 4), ("cn", 3)])
+def test_rect_polynomial_passes_match_oracle(gpu_lib, nx, deg, scheme, steps, monkeypatch):
+    """The rectilinear operator's Chebyshev preconditioner in passes of the
+    LDS tile (degree 2 by Horner, 4 and 12 as 2 and 6 quadratic factors),
+    forced on a grid too small to pick it by itself, with z chunks of 4
+    planes (the last one ragged): against the oracle, mass conserved, the
+    band with D = 0 keeps its PCM values, fewer iterations than Jacobi."""
+    import torch
+    cgd = gpu_lib
+    rng = np.random.default_rng(77)
+    ex = _stretched(nx // 2, 1.03, -0.3, 1.1)
+    ey = np.concatenate(([0.1], 0.1 + np.cumsum(rng.random(19) + 0.3) / 20))
+    ez = np.linspace(2.0, 2.5, 14)
+    shape = (len(ex) - 1, len(ey) - 1, len(ez) - 1)
+    xc = 0.5 * (ex[1:] + ex[:-1])
+    zc = 0.5 * (ez[1:] + ez[:-1])
+    Dx = np.where(np.abs(xc - 0.25) < 0.1, 0.0, 1.0 + 0.5 * np.cos(3 * xc))
+    Dy = 0.5 + rng.random(shape[1])
+    Dz = 1.0 + 0.8 * np.sin(9 * zc) ** 2
+    D = (Dx[None, None, :] * Dy[None, :, None] * Dz[:, None, None]).astype(np.float32).ravel()
+    lo = np.array([ex[0], ey[0], ez[0]])
+    hi = np.array([ex[-1], ey[-1], ez[-1]])
+    pos = (lo + (hi - lo) * rng.random((30_000, 3))).astype(np.float32)
+    vals = np.stack([np.full(len(pos), 3.3e-8, np.float32), rng.normal(size=len(pos)).astype(np.float32)])
+    b = 0.1
+    print(f"case: rect polynomial passes nx={nx} degree {deg} {scheme} {steps} steps", flush=True)
+    mesh = cgd.RectMesh(ex, ey, ez, diffusivity=D)
+    monkeypatch.setenv("CGD_HEX_PRECOND_DEG", "1")
+    _, st_j = cgd.coarse_grain(mesh, _t(pos, torch), _t(vals, torch), b, steps, rtol=1e-7, stats=True,
+                               scheme=scheme)
+    monkeypatch.setenv("CGD_HEX_PRECOND_DEG", str(deg))
+    monkeypatch.setenv("CGD_HEX_LDS_ZC", "4")
+    out, st = cgd.coarse_grain(mesh, _t(pos, torch), _t(vals, torch), b, steps, rtol=1e-7, stats=True,
+                               scheme=scheme)
+    ref, dep = O.coarse_grain_rect(pos, vals, [ex, ey, ez], b, steps, diffusivity=D.astype(np.float64),
+                                   solver="direct", scheme=scheme)
+    o = out.cpu().numpy()
+    V = O.rect_volumes([ex, ey, ez])
+    frozen = D == 0
+    for f in range(2):
+        assert rel_l2(o[f], ref[f]) <= REL_L2, (f, rel_l2(o[f], ref[f]))
+        m0 = (dep["field64"][f] * V).sum()
+        assert abs(st.mass_after[f] - m0) <= 1e-5 * np.abs(dep["field64"][f] * V).sum()
+        pcm = dep["field64"][f][frozen]
+        assert np.abs(o[f][frozen] - pcm).max() <= 1e-5 * np.abs(dep["field64"][f]).max()
+    assert st.status == 0
+    its = sum(sum(r) for r in st.iters)
+    its_j = sum(sum(r) for r in st_j.iters)
+    print(f"iterations: degree {deg} {st.iters}, Jacobi {st_j.iters}", flush=True)
+    assert its < its_j, (its, its_j)
+
+
 def test_rect_stretched_2d_and_invalid(gpu_lib):
     """The paper's stretched mesh shape (90 x 45, ratio 1.04 towards the
     centre line) with unit diffusivity, against the oracle; invalid edges and
