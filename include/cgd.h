@@ -93,11 +93,15 @@ cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz,
  * D_f A_f / d_f (e_P - e_N) through each interior face (A_f the face area,
  * d_f the distance between the two cell centres, D_f the harmonic mean of
  * the two cells' diffusivities, 0 if either is 0), solved by
- * Jacobi-preconditioned CG (x0_mode 0).  When no axis is periodic and the
- * diffusivity factors as D(i,j,k) = Dx(i) Dy(j) Dz(k) (checked to 1e-6
- * relative at creation; NULL counts) the operator is kept as per-axis factor
- * arrays and applied by stencil sweeps; otherwise it is stored like the tet
- * operator with six face slots per row.  periodic: bit a set makes axis a
+ * preconditioned CG (x0_mode 0).  When the diffusivity factors as
+ * D(i,j,k) = Dx(i) Dy(j) Dz(k) (checked to 1e-6 relative at creation; NULL
+ * counts) the operator is kept as per-axis factor arrays and applied by
+ * stencil sweeps, with a Chebyshev polynomial preconditioner on a scaled
+ * operator where one wave covers an x-row (nx of 64, 128 or 256), Jacobi
+ * elsewhere; a periodic x axis there also needs the row in one segment of
+ * waves (nx <= 64, or 128 / 256 with 8 / 16-byte aligned fields).  Otherwise
+ * the operator is stored like the tet operator with six face slots per row
+ * and solved by Jacobi-preconditioned CG.  periodic: bit a set makes axis a
  * (0 x, 1 y, 2 z) periodic (Section 3.1): its first and last cells share a
  * face at distance (h_first + h_last) / 2 instead of two walls (no effect on
  * an axis of one cell); binning is unchanged.  nx * ny * nz < 2^28, else

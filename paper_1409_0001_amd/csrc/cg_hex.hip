@@ -852,6 +852,12 @@ static size_t max_bpf(const HexGeom& g, int F) {
     return (size_t)p.bpf;
 }
 
+bool hex_one_x_segment(const HexGeom& g, const float* field) {
+    int vec = pick_vec(g.nx);
+    if ((uintptr_t)field % (4 * vec)) vec = 1;
+    return g.nx <= 64 * vec;
+}
+
 size_t diffuse_hex_workspace(const cgd_mesh m, int32_t F) {
     return small_bytes(F, (int)max_bpf(m->hex, F)) + 6 * (size_t)F * m->cells * sizeof(float);
 }
@@ -933,8 +939,13 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, co
     Geom gp = {};  // the rectilinear preconditioner's S A S (prepared for this dtau)
     if (ro) {
         // the rectilinear operator A (per-axis factors)
+        if ((ro->per & 1) && p.xsegs != 1) {
+            set_error("cgd_diffuse: a periodic x axis needs the row in one x segment");
+            return CGD_E_UNSUPPORTED;
+        }
         a.rect = 1;
         a.g.dt = (float)dtau;
+        a.g.per = ro->per;
         for (int ax = 0; ax < 3; ++ax) {
             a.g.rg[ax] = ro->g[ax];
             a.g.rs[ax] = ro->s[ax];

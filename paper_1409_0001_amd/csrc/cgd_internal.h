@@ -183,7 +183,7 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& a, char* base, con
                                hipStream_t s, const RectOp* ro = nullptr);
 
 // A rectilinear grid whose diffusivity is a product of per-axis factors
-// (D_ijk = Dx_i Dy_j Dz_k) and that has no periodic axis.  The solve runs on
+// (D_ijk = Dx_i Dy_j Dz_k), periodic axes included.  The solve runs on
 // A = I + dtau M^-1/2 K M^-1/2 for x~ = M^1/2 x, whose entries are products
 // of per-axis factors (stencil::Geom).  Its preconditioner is
 // S p(S A S) S with S a diagonal scaling that is itself a product of
@@ -214,9 +214,14 @@ struct RectOp {
     float* pdev = nullptr;   // S A S's arrays
     float* host = nullptr;   // pinned staging of S A S's arrays
     size_t pfloats = 0;
+    int per = 0;             // bit a: axis a periodic (and of at least two cells)
     double dtau = -1.0;      // dtau S A S was formed for (-1: none yet)
     double lmin = 1.0, lmax = 1.0;  // bounds of S A S's spectrum
 };
+
+// Whether the hex sweeps on g cover an x-row with one x segment of waves
+// (the condition for a periodic x axis), for a field at `field`.
+bool hex_one_x_segment(const HexGeom& g, const float* field);
 
 // Forms S A S's device arrays and spectrum bounds for dtau (no work when
 // dtau is the one of the last call; otherwise synchronises the stream once

@@ -165,14 +165,20 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
 
     // this wave's row; it is in level j's extent (extent row w - j) iff
     // j <= w < TY + 2 D - j
+    // RECT: periodic axes (Geom::per): a row or plane beyond the grid is a
+    // real one, wrapped (the rows of a wave's extent and the planes of a
+    // chunk's halo compute like any other; only output rows are stored)
+    const int per = RECT ? g.per : 0;
     const int yw = y0 - D + w;
-    const bool in_dom = w < E0 && yw >= 0 && yw < ny;
-    const bool has_yd = yw > 0, has_yu = yw + 1 < ny;
+    const int ywr = (per & 2) ? ((yw % ny) + ny) % ny : min(max(yw, 0), ny - 1);  // the row's data
+    const bool in_dom = w < E0 && ((per & 2) || (yw >= 0 && yw < ny));
+    const bool has_yd = yw > 0 || (per & 2), has_yu = yw + 1 < ny || (per & 2);
+    auto wrapz = [&](int q) { return (per & 4) ? (q < 0 ? q + nz : (q >= nz ? q - nz : q)) : q; };
     const bool owner = w >= D && w < D + TY;  // an output row (written if yw < ny)
     const int li = w < D ? w : w - TY;        // loader index (non-owners)
 
     auto row = [&](int j, int q, int e) -> float* {  // level j, plane q, extent row e
-        const int slot = j <= 1 ? q % 3 : (q & 1);
+        const int slot = j <= 1 ? (q + 12) % 3 : (q & 1);  // q >= -D - 1
         return lds + (lds_level_base<D, TY>(j) + slot * (TY + 2 * (D - j)) + e) * NXR + x0;
     };
     auto row0 = [&](int q, int e) -> float* { return row(0, q, e); };
@@ -181,8 +187,8 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
         return ldv<VEC>(static_cast<const float*>(__builtin_assume_aligned(r, 4 * VEC)));
     };
     const float* src = src_field + x0;
-    auto ysrc = [&](int e) {  // clamped row of extent row e of level 0
-        const int y = min(max(y0 - D + e, 0), ny - 1);
+    auto ysrc = [&](int e) {  // clamped (or wrapped) row of extent row e of level 0
+        const int y = (per & 2) ? ((y0 - D + e) % ny + ny) % ny : min(max(y0 - D + e, 0), ny - 1);
         return (size_t)y * nx;
     };
 
@@ -195,8 +201,8 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     const size_t side_y = (size_t)min(y0 + (li < TY ? li : 0), ny - 1) * nx;
     auto side_load = [&](int q) { return ldv<VEC>(side + (size_t)min(max(q, 0), nz - 1) * plane + side_y); };
 
-    const int t0 = max(0, zb - D);
-    const int tl = min(nz, ze + D) - 1;  // last plane of r needed
+    const int t0 = (per & 4) ? zb - D : max(0, zb - D);
+    const int tl = (per & 4) ? ze + D - 1 : min(nz, ze + D) - 1;  // last plane of r needed
     const int t1 = ze - 1 + D;           // last step (plane ze - 1 of z completes)
     (void)g;
     // RECT: this lane's x factors and this wave's row factors, for every
@@ -209,9 +215,9 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     float* ztab = lds + (lds_level_base<D, TY>(D) + (FORM == 2 ? 2 * TY : 0)) * NXR;
     if constexpr (RECT) {
         X = rect_x<VEC>(g, x0);
-        Yw = rect_a(g, 1, yw, ny);
+        Yw = rect_a(g, 1, ywr, ny);
         for (int i = threadIdx.x; i < (tl - t0 + 1) * kZtStride; i += NW * 64) {
-            const int q = t0 + i / kZtStride, f = i % kZtStride;
+            const int q = wrapz(t0 + i / kZtStride), f = i % kZtStride;
             float v = 0.f;
             if (f == 0) v = g.rg[2][q];
             else if (f == 1) v = g.rg[2][q + 1];
@@ -225,7 +231,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     if constexpr (SIN || SOUT) {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) sgx[e] = g.rsg[0][x0 + e];
-        sgy = g.rsg[1][min(max(yw, 0), ny - 1)];
+        sgy = g.rsg[1][ywr];
     }
     // SIN: S on the y axis of the loader's rows (fixed for the march)
     float sgl[2] = {1.f, 1.f};
@@ -241,7 +247,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 for (int k = 0; k < VEC; ++k) acc1 = fma((double)v.f[k], (double)v.f[k], acc1);
             }
             const int qc = min(max(q, t0), tl);  // a plane beyond tl holds tl's values (unused)
-            const float sz = setup ? g.rsg[2][qc] : ztab[(qc - t0) * kZtStride + 5];
+            const float sz = setup ? g.rsg[2][wrapz(qc)] : ztab[(qc - t0) * kZtStride + 5];
             const float syz = sgl[i] * sz;
 #pragma unroll
             for (int k = 0; k < VEC; ++k) v.f[k] *= sgx[k] * syz;
@@ -293,7 +299,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {
                 const int e = min(li + NL * i, E0 - 1);
-                pf[B][i] = ldv<VEC>(src + (size_t)tn * plane + ysrc(e));
+                pf[B][i] = ldv<VEC>(src + (size_t)wrapz(tn) * plane + ysrc(e));
             }
         }
         if (w < E0) rk[S % RK] = ld(row0(t, w));  // own row of r at plane t (written at step t - 1)
@@ -308,6 +314,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
         // this wave (u1).
         auto go_of = [&](int j) {
             const int q = t - j;
+            if (per & 4) return in_dom && j <= w && w < E0 - j && q >= zb - (D - j) && q < ze + (D - j);
             return in_dom && j <= w && w < E0 - j && q >= max(0, zb - (D - j)) && q < min(nz, ze + (D - j));
         };
         auto ys_rows = [&](int j, Vec<VEC>& yd, Vec<VEC>& yu) {
@@ -326,7 +333,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 ys_rows(j + 1, ydn, yun);
                 if (j == 1) {
                     c2 = ld(row(1, t - 2, w - 1));
-                    zl2 = ld(row(1, t - 2 > 0 ? t - 3 : t - 2, w - 1));
+                    zl2 = ld(row(1, (t - 2 > 0 || (per & 4)) ? t - 3 : t - 2, w - 1));
                 }
             }
             if (!PF && go) {
@@ -334,7 +341,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 ys_rows(j, yd, yu);
                 if (j == 2) {
                     c2 = ld(row(1, q, w - 1));
-                    zl2 = ld(row(1, q > 0 ? q - 1 : q, w - 1));
+                    zl2 = ld(row(1, (q > 0 || (per & 4)) ? q - 1 : q, w - 1));
                 }
             }
             if (go) {
@@ -368,6 +375,13 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 for (int e = 0; e < VEC; ++e) ys.f[e] += yu.f[e];
                 float lft, rgt;
                 x_neighbours<VEC>(c, lft, rgt);
+                if (per & 1) {
+                    // periodic x: the row's end cells are neighbours
+                    const float last = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c.f[VEC - 1]), 63));
+                    const float first = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c.f[0]), 0));
+                    lft = lane == 0 ? last : lft;
+                    rgt = lane == 63 ? first : rgt;
+                }
                 // u = cp[D-j] r + ca A u_prev (ca = cp[D] at j = 1, else 1), with
                 // ca folded into the stencil's coefficients (PrecondCoef).
                 // Interior planes of a grid with h_x = h_y take the fast path:
@@ -426,7 +440,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                     }
                 }
                 if (j == 1) u1 = u;
-                if (FIRST && FORM == 1 && !SIN && j == 1 && owner && q >= zb && q < ze) {
+                if (FIRST && FORM == 1 && !SIN && j == 1 && owner && yw < ny && q >= zb && q < ze) {
                     // b.b over the output cells, from this row's b at plane q
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) acc1 = fma((double)c.f[e], (double)c.f[e], acc1);
@@ -436,7 +450,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 // not written here keeps an older, finite plane that is only
                 // ever read with a zero coefficient (beyond a wall)
                 if (j >= 2 && j < D) lv[j >= 2 ? j - 2 : 0][((S - j) % 3 + 3) % 3] = u;
-                if (j == D && owner && q >= zb && q < ze) {
+                if (j == D && owner && yw < ny && q >= zb && q < ze) {
                     // output of plane q complete: store it and add r.z (and b.b)
                     Vec<VEC> us = u;
                     if constexpr (SOUT) {
@@ -477,12 +491,12 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) {
                     const int e = min(li + NL * i, E0 - 1);
-                    pf[s][i] = ldv<VEC>(src + (size_t)min(t0 + s, tl) * plane + ysrc(e));
+                    pf[s][i] = ldv<VEC>(src + (size_t)wrapz(min(t0 + s, tl)) * plane + ysrc(e));
                 }
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {
                 const int e = li + NL * i;
-                if constexpr (SIN) sgl[i] = g.rsg[1][min(max(y0 - D + e, 0), ny - 1)];
+                if constexpr (SIN) sgl[i] = g.rsg[1][ysrc(min(e, E0 - 1)) / nx];
                 if (e < E0) {
                     scale_in(pf[0][i], e, i, t0, true);
                     stv<VEC>(row0(t0, e), pf[0][i]);
@@ -491,7 +505,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {
                 const int e = min(li + NL * i, E0 - 1);
-                pf[0][i] = ldv<VEC>(src + (size_t)min(t0 + P, tl) * plane + ysrc(e));
+                pf[0][i] = ldv<VEC>(src + (size_t)wrapz(min(t0 + P, tl)) * plane + ysrc(e));
             }
         }
         lds_barrier();

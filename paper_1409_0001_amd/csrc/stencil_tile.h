@@ -76,6 +76,10 @@ struct Geom {
     const float* re[3];
     const float* rsg[3];
     float dt;
+    // RECT: bit a set when axis a is periodic (its first and last cells are
+    // neighbours through a face of weight rg[a][0] = rg[a][n]); a periodic
+    // x axis needs the row in one x segment
+    int per;
 };
 
 // RECT: the x factors of a lane's VEC cells (dt folded into the weights),
@@ -222,9 +226,13 @@ __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t 
     int eoff = 0;
     if constexpr (EDGE) eoff = (lane == 0 && x0 > 0) ? -1 : ((lane == 63 && x0 + 1 < nx) ? 1 : 0);
 
+    // Rows and planes beyond the grid: clamped, or on a periodic axis the
+    // neighbours of the first and last (-1 -> n - 1, n -> 0; anything
+    // further is clamped: only out-of-range rows and planes use it)
+    const int per = RECT ? g.per : 0;
     auto at = [&](int z, int y) -> size_t {
-        z = z < 0 ? 0 : (z >= nz ? nz - 1 : z);
-        y = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+        z = z < 0 ? ((per & 4) && z == -1 ? nz - 1 : 0) : (z >= nz ? ((per & 4) && z == nz ? 0 : nz - 1) : z);
+        y = y < 0 ? ((per & 2) && y == -1 ? ny - 1 : 0) : (y >= ny ? ((per & 2) && y == ny ? 0 : ny - 1) : y);
         return base + (size_t)z * plane + (size_t)y * nx;
     };
 
@@ -288,19 +296,34 @@ __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t 
 #pragma unroll
             for (int j = 0; j < TY; ++j) en[j] = load_p<1, MODE>(p, at(z + 1, y0 + j) + eoff, beta).f[0];
         }
-        const bool has_zd = z > 0, has_zu = z + 1 < nz;
+        const bool has_zd = z > 0 || (per & 4), has_zu = z + 1 < nz || (per & 4);
 #pragma unroll
         for (int j = 0; j < TY; ++j) {
             const int y = y0 + j;
             const bool valid = xin && y < ny;
             const size_t i = at(z, y);
             const Vec<VEC>& c = pc[j + 1];
-            const bool has_yd = y > 0, has_yu = y + 1 < ny;
+            const bool has_yd = y > 0 || (per & 2), has_yu = y + 1 < ny || (per & 2);
             float lft = __shfl_up(c.f[VEC - 1], 1);
             float rgt = __shfl_down(c.f[0], 1);
             if constexpr (EDGE) {
                 lft = lane == 0 ? ec[j] : lft;
                 rgt = lane == 63 ? ec[j] : rgt;
+            }
+            bool wl = wall_l, wr = wall_r;
+            if constexpr (RECT) {
+                if (per & 1) {
+                    // periodic x (one segment, nx a multiple of VEC): the
+                    // row's last cell (lane (nx - 1) / VEC) is the first
+                    // cell's left neighbour, the first cell (lane 0) the last
+                    // cell's right neighbour
+                    const float last =
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c.f[VEC - 1]), (nx - 1) / VEC));
+                    const float first = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c.f[0]), 0));
+                    lft = x0 == 0 ? last : lft;
+                    rgt = x0 + VEC >= nx ? first : rgt;
+                    wl = wr = false;
+                }
             }
             Vec<VEC> ap;
             RectYZ q;
@@ -308,8 +331,8 @@ __device__ __forceinline__ void tile_sweep(const Ptrs& p, const Geom& g, size_t 
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 const float ce = c.f[e];
-                float l = e > 0 ? c.f[e - 1] : (wall_l ? ce : lft);
-                float r = e + 1 < VEC ? c.f[e + 1] : (wall_r ? ce : rgt);
+                float l = e > 0 ? c.f[e - 1] : (wl ? ce : lft);
+                float r = e + 1 < VEC ? c.f[e + 1] : (wr ? ce : rgt);
                 const float yl = has_yd ? pc[j].f[e] : ce;
                 const float yh = has_yu ? pc[j + 2].f[e] : ce;
                 const float zl = has_zd ? pm[j].f[e] : ce;

@@ -613,6 +613,7 @@ cgd_status rect_op_prepare(cgd_mesh m, double dtau, hipStream_t s) {
             mn = std::min(mn, sig2[a][i]);
         }
         for (int i = 1; i < na; ++i) gs[a][i] = std::sqrt(sig2[a][i - 1] * sig2[a][i]) * ro->gf[a][i];
+        if ((ro->per >> a) & 1) gs[a][0] = gs[a][na] = std::sqrt(sig2[a][na - 1] * sig2[a][0]) * ro->gf[a][0];
         for (int i = 0; i < na; ++i) hs[a][i] = ss[a][i] + gs[a][i] + gs[a][i + 1];
         lmin *= mn;
     }
@@ -686,9 +687,11 @@ static cgd_status diffuse_rect_fast(cgd_mesh m, const DiffuseArgs& da, cgd_solve
 
 // Per-axis factors of a rectilinear grid's operator (RectOp), when the
 // diffusivity is a product of per-axis factors (checked on every cell to a
-// relative 1e-6) and no axis is periodic; otherwise the mesh keeps the
-// face-slot rows only.
-static cgd_status build_rect_op(cgd_mesh m, const int32_t dims[3], const double* const edges[3], const float* D) {
+// relative 1e-6); otherwise the mesh keeps the face-slot rows only.  A
+// periodic axis of at least two cells gets the face between its last and
+// first cells (weights g[0] = g[n], in both cells' diagonal sums).
+static cgd_status build_rect_op(cgd_mesh m, const int32_t dims[3], const double* const edges[3], const float* D,
+                                int32_t periodic) {
     const int nx = dims[0], ny = dims[1], nz = dims[2];
     std::vector<double> fac[3];
     for (int a = 0; a < 3; ++a) fac[a].assign(dims[a], 1.0);
@@ -737,6 +740,16 @@ static cgd_status build_rect_op(cgd_mesh m, const int32_t dims[3], const double*
             gf[i + 1] = hm / (df * std::sqrt(h[i] * h[i + 1]));
             sd[i] += hm / (df * h[i]);
             sd[i + 1] += hm / (df * h[i + 1]);
+        }
+        if (((periodic >> a) & 1) && na >= 2) {
+            const int l = na - 1;
+            const double da = fac[a][l], db = fac[a][0];
+            const double hm = (da > 0.0 && db > 0.0) ? 2.0 * da * db / (da + db) : 0.0;
+            const double df = 0.5 * (h[l] + h[0]);
+            gf[0] = gf[na] = hm / (df * std::sqrt(h[l] * h[0]));
+            sd[l] += hm / (df * h[l]);
+            sd[0] += hm / (df * h[0]);
+            ro->per |= 1 << a;
         }
         ro->fac[a] = fac[a];
         for (int i = 0; i <= na; ++i) hA.push_back((float)gf[i]);
@@ -803,7 +816,11 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         set_error("cgd_diffuse: tet meshes support x0_mode 0 only");
         return CGD_E_UNSUPPORTED;
     }
-    if (m->kind == 2 && m->rop && da.precond == 0 && !getenv("CGD_RECT_SLOTS")) return diffuse_rect_fast(m, da, out, s);
+    // the per-axis factor sweeps where they apply: a periodic x axis needs
+    // the row in one x segment (otherwise the face-slot rows)
+    if (m->kind == 2 && m->rop && da.precond == 0 && !getenv("CGD_RECT_SLOTS") &&
+        (!(m->rop->per & 1) || hex_one_x_segment(m->hex, da.field)))
+        return diffuse_rect_fast(m, da, out, s);
     const TetData* t = m->tet;
     const int F = da.F;
     const int n = t->n_tet;
@@ -1137,8 +1154,8 @@ extern "C" cgd_status cgd_mesh_create_rect(int32_t nx, int32_t ny, int32_t nz, c
             return CGD_E_HIP;
         }
     }
-    if (periodic == 0) {
-        cgd_status r = build_rect_op(m, dims, edges, diffusivity);
+    {
+        cgd_status r = build_rect_op(m, dims, edges, diffusivity, periodic);
         if (r != CGD_OK) {
             cgd_mesh_destroy(m);
             return r;

@@ -235,9 +235,10 @@ def test_rect_stretched_2d_and_invalid(gpu_lib):
 
 
 @pytest.mark.parametrize("scheme", ["be", "cn"])
-def test_rect_periodic_matches_oracle(gpu_lib, scheme):
-    """Periodic x and z (Section 3.1) on a stretched grid, against the
-    oracle; mass conserved."""
+def test_rect_periodic_matches_oracle(gpu_lib, scheme, monkeypatch):
+    """Periodic x and z (Section 3.1) on a stretched grid (one x segment of
+    40 cells: the per-axis factor sweeps with the wrap), against the oracle
+    and the face-slot rows (CGD_RECT_SLOTS); mass conserved."""
     import torch
     cgd = gpu_lib
     e = _mesh_case(76, 11, 9)
@@ -253,16 +254,78 @@ def test_rect_periodic_matches_oracle(gpu_lib, scheme):
     out, st = cgd.coarse_grain(mesh, _t(pos, torch), _t(vals, torch), 0.15, 3, rtol=1e-7, stats=True,
                                scheme=scheme)
     ref, dep = O.coarse_grain_rect(pos, vals, e, 0.15, 3, solver="direct", scheme=scheme, periodic=per)
-    o = out.cpu().numpy()
+    monkeypatch.setenv("CGD_RECT_SLOTS", "1")
+    slots, _ = cgd.coarse_grain(mesh, _t(pos, torch), _t(vals, torch), 0.15, 3, rtol=1e-7, stats=True,
+                                scheme=scheme)
+    o, sl = out.cpu().numpy(), slots.cpu().numpy()
     V = O.rect_volumes(e)
     for f in range(2):
         assert rel_l2(o[f], ref[f]) <= REL_L2, (f, rel_l2(o[f], ref[f]))
+        assert rel_l2(sl[f], ref[f]) <= REL_L2, (f, rel_l2(sl[f], ref[f]))
         m0 = (dep["field64"][f] * V).sum()
         assert abs(st.mass_after[f] - m0) <= 1e-5 * np.abs(dep["field64"][f] * V).sum()
     # mass crossed the periodic x boundary: the last x cells gained from the loaded first ones
     walled, _ = O.coarse_grain_rect(pos, vals, e, 0.15, 3, solver="direct", scheme=scheme)
     last = o[0].reshape(9, 11, 40)[:, :, -1].sum()
     assert last > 1.5 * walled[0].reshape(9, 11, 40)[:, :, -1].sum()
+
+
+@pytest.mark.parametrize("nx", [64, 128])
+@pytest.mark.parametrize("per", [(True, False, False), (False, True, False), (False, False, True),
+                                 (True, True, True)])
+@pytest.mark.parametrize("grid", ["uniform", "stretched"])
+def test_rect_periodic_polynomial_passes_match_oracle(gpu_lib, nx, per, grid, monkeypatch):
+    """Periodic axes (Section 3.1) on the per-axis factor sweeps and the
+    polynomial preconditioner's LDS passes (degree 12 forced, z chunks of 4
+    planes, so chunk halos cross the periodic z boundary, and row groups of
+    8 rows over 19 rows, so the last group's halo wraps in y): a uniform grid
+    with unit diffusivity, and a stretched one with a separable diffusivity
+    and a D = 0 band, against the oracle's periodic operator; mass conserved."""
+    import torch
+    cgd = gpu_lib
+    rng = np.random.default_rng(78)
+    if grid == "uniform":
+        ex, ey, ez = np.linspace(0.0, 1.0, nx + 1), np.linspace(0.0, 0.3, 20), np.linspace(0.0, 0.2, 14)
+        D = None
+    else:
+        ex = _stretched(nx // 2, 1.03, -0.3, 1.1)
+        ey = np.concatenate(([0.1], 0.1 + np.cumsum(rng.random(19) + 0.3) / 20))
+        ez = np.linspace(2.0, 2.5, 14)
+        xc = 0.5 * (ex[1:] + ex[:-1])
+        zc = 0.5 * (ez[1:] + ez[:-1])
+        Dx = np.where(np.abs(xc - 0.25) < 0.1, 0.0, 1.0 + 0.5 * np.cos(3 * xc))
+        Dy = 0.5 + rng.random(len(ey) - 1)
+        Dz = 1.0 + 0.8 * np.sin(9 * zc) ** 2
+        D = (Dx[None, None, :] * Dy[None, :, None] * Dz[:, None, None]).astype(np.float32).ravel()
+    e = [ex, ey, ez]
+    lo = np.array([v[0] for v in e])
+    hi = np.array([v[-1] for v in e])
+    pos = (lo + (hi - lo) * rng.random((30_000, 3))).astype(np.float32)
+    pos[:6000] = (lo + (hi - lo) * 0.04 * rng.random((6000, 3))).astype(np.float32)  # load the low corner
+    vals = np.stack([np.full(len(pos), 3.3e-8, np.float32), rng.normal(size=len(pos)).astype(np.float32)])
+    b = 0.1
+    print(f"case: rect periodic {per} polynomial passes nx={nx} {grid}", flush=True)
+    mesh = cgd.RectMesh(ex, ey, ez, diffusivity=D, periodic=per)
+    monkeypatch.setenv("CGD_HEX_PRECOND_DEG", "1")
+    _, st_j = cgd.coarse_grain(mesh, _t(pos, torch), _t(vals, torch), b, 3, rtol=1e-7, stats=True)
+    monkeypatch.setenv("CGD_HEX_PRECOND_DEG", "12")
+    monkeypatch.setenv("CGD_HEX_LDS_ZC", "4")
+    out, st = cgd.coarse_grain(mesh, _t(pos, torch), _t(vals, torch), b, 3, rtol=1e-7, stats=True)
+    ref, dep = O.coarse_grain_rect(pos, vals, e, b, 3, solver="direct", periodic=per,
+                                   diffusivity=None if D is None else D.astype(np.float64))
+    o = out.cpu().numpy()
+    V = O.rect_volumes(e)
+    for f in range(2):
+        assert rel_l2(o[f], ref[f]) <= REL_L2, (f, rel_l2(o[f], ref[f]))
+        m0 = (dep["field64"][f] * V).sum()
+        assert abs(st.mass_after[f] - m0) <= 1e-5 * np.abs(dep["field64"][f] * V).sum()
+    assert st.status == 0
+    print(f"iterations {st.iters}, Jacobi {st_j.iters}", flush=True)
+    # the stretched grids' scaled spectra span a ratio of ~90 (64 cells) and
+    # ~390 (128): 7 and 14 iterations in a float64 model, Jacobi 52 and 100
+    assert sum(sum(r) for r in st.iters) < 0.5 * sum(sum(r) for r in st_j.iters)
+    if grid == "uniform":
+        assert max(max(r) for r in st.iters) <= 6
 
 
 def test_velocity_from_momentum_bit_exact_and_uniform_flow(gpu_lib):
