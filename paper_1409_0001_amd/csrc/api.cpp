@@ -126,7 +126,7 @@ struct DeviceGuard {
 // last kernel has read it, in stream order.
 static cgd_status deposit_buffers(cgd_mesh m, int64_t n, int32_t F, int64_t* user_acc, int64_t** acc,
                                   DepositInfo** info, void** temp) {
-    const size_t tiled = m->kind == 0 ? deposit_hex_temp_bytes(m, n, F) : 0;
+    const size_t tiled = m->kind != 1 ? deposit_hex_temp_bytes(m, n, F) : 0;
     size_t acc_bytes = (user_acc || tiled) ? 0 : (size_t)F * m->cells * sizeof(int64_t);
     size_t need = kSmallFixed + acc_bytes + tiled;
     size_t diff = m->kind == 0 ? diffuse_hex_workspace(m, F) : diffuse_tet_workspace(m, F);
@@ -298,7 +298,7 @@ static cgd_status do_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F,
     if (m->kind == 0)
         rc = deposit_hex(m, n, pos, F, values, field, acc_buf, info, temp, fs, &m->timing, s);
     else
-        rc = deposit_tet(m, n, pos, F, values, field, acc_buf, info, fs, s);
+        rc = deposit_tet(m, n, pos, F, values, field, acc_buf, info, temp, fs, s);
     if (rc != CGD_OK || !(st || (frac_bits && need_auto))) return rc;
     cgd_status prc = ensure_pinned(m, kPinBytes);
     if (prc != CGD_OK) return prc;

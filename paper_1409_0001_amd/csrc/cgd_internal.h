@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/cgd.h"
+#include "hex_bin.h"
 
 namespace cgd {
 
@@ -123,7 +124,13 @@ cgd_status ensure_pinned(cgd_mesh m, size_t bytes);
 cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
                        float* field, int64_t* acc, DepositInfo* info_dev, void* temp, const ScaleForce& fs,
                        Timing* timing, hipStream_t s);
+// (also the tiled path of rectilinear meshes, which tiles the same way)
 size_t deposit_hex_temp_bytes(const cgd_mesh m, int64_t n, int32_t F);
+// Edges (all three axes) of the largest rectilinear grid the tiled deposit
+// takes (it holds them in LDS); larger grids use the direct path.
+constexpr int kRectTiledEdges = 4096;
+// Clears a deposit's counters and sets its forced scales (enqueued on s).
+void deposit_info_init(DepositInfo* info, const ScaleForce& fs, hipStream_t s);
 
 // Tiled deposit of one or several snapshots on a mesh's hex grid (device
 // pointers; the counters are cleared by the caller).  The fields of snapshot
@@ -145,6 +152,9 @@ struct TiledDeposit {
     float* field;                  // [n_snap][F][cells]
     long long* acc;                // nullable: [n_snap][F][cells] int64 accumulators
     void* temp;                    // tiled_deposit_temp_bytes
+    int32_t rect = 0;              // 1: the mesh's rectilinear edges locate (rl), each cell
+    RectLoc rl = {};               //    divides by its own volume (vcell [cells])
+    const double* vcell = nullptr;
 };
 // Bytes of `temp`; 0 when the grid or the particle count rules the tiled
 // deposit out (then the direct atomic deposit is used).
@@ -276,8 +286,11 @@ cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, 
 void destroy_batched(cgd_mesh m);
 
 // tet.cpp / tet.hip
+// temp (rectilinear meshes): deposit_hex_temp_bytes(m, n, F) bytes for the
+// tiled path, as deposit_hex; nullptr on tet meshes and for the direct path.
 cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
-                       float* field, int64_t* acc, DepositInfo* info_dev, const ScaleForce& fs, hipStream_t s);
+                       float* field, int64_t* acc, DepositInfo* info_dev, void* temp, const ScaleForce& fs,
+                       hipStream_t s);
 cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hipStream_t s);
 void destroy_tet_data(cgd_mesh m);
 int64_t tet_nnz(cgd_mesh m);

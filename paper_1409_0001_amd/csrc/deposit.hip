@@ -140,6 +140,7 @@ constexpr int kTPass = kTChunk / (kTBlock * kTPer);  // register passes per chun
 constexpr int kBPer = 4;                   // particles per thread and register pass of the counting pass
 constexpr int kTileWords = 16384;          // int64 LDS accumulators of one tile workgroup (128 KB)
 constexpr int kMaxTiles = 8192;            // LDS tile counters of the bucketing passes (per snapshot)
+constexpr int kRectEdges = kRectTiledEdges;  // rectilinear grids: edges of all three axes held in LDS
 
 struct TileArgs {
     const float* pos;
@@ -170,6 +171,9 @@ struct TileArgs {
     float* field;          // [n_snap][F][cells]
     long long* acc;        // nullable, [n_snap][F][cells]
     double vol;
+    int rect;              // 1: rectilinear edges (rl) locate, vcell [cells] holds each cell's volume
+    RectLoc rl;
+    const double* vcell;
 };
 
 __device__ inline void snap_range(const TileArgs& a, int j, int64_t& s0, int64_t& s1) {
@@ -188,8 +192,14 @@ __global__ void k_tile_clear(TileArgs a) {
 // particles per tile, and the max |v| / non-finite count of every field over
 // the block's chunk of nsub_bin * kTChunk particles (the values of the direct
 // path's k_absmax, folded into this pass).
+// RECT: the host cell by the rectilinear edges (RectLoc's definition), from
+// a copy of the edges in LDS: per axis the largest i < n with e_i <= x by
+// binary lifting (steps of decreasing powers of two, the same count for
+// every lane), the kBPer particles of a thread interleaved.
+template <bool RECT>
 __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
     __shared__ uint32_t hist[kMaxTiles];
+    __shared__ double redge[RECT ? kRectEdges : 1];
     __shared__ uint32_t bmax[CGD_MAX_FIELDS];
     __shared__ unsigned long long bbad[CGD_MAX_FIELDS];
     const int j = blockIdx.y;
@@ -202,6 +212,10 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
     if (threadIdx.x < CGD_MAX_FIELDS) {
         bmax[threadIdx.x] = 0u;
         bbad[threadIdx.x] = 0ull;
+    }
+    if constexpr (RECT) {
+        const int ne = a.rl.n[0] + a.rl.n[1] + a.rl.n[2] + 3;  // <= kRectEdges (host)
+        for (int i = threadIdx.x; i < ne; i += kTBlock) redge[i] = a.rl.e[i];
     }
     __syncthreads();
     unsigned long long dropped = 0ull, nfpos = 0ull;
@@ -226,8 +240,50 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
         const int64_t p0 = cb + (int64_t)sub * (kTBlock * kBPer) + threadIdx.x;
         int32_t k[kBPer];
         bool nf[kBPer];
+        if constexpr (RECT) {
+            // a non-finite coordinate on any axis counts as non-finite; a
+            // point outside the closed box on any axis is dropped
+            double p[kBPer][3];
+            bool in[kBPer];
+            int id[kBPer];
 #pragma unroll
-        for (int i = 0; i < kBPer; ++i) k[i] = (int32_t)hex_cell(a.g, px[i], py[i], pz[i], &nf[i]);
+            for (int i = 0; i < kBPer; ++i) {
+                p[i][0] = (double)px[i];
+                p[i][1] = (double)py[i];
+                p[i][2] = (double)pz[i];
+                nf[i] = !(isfinite(p[i][0]) && isfinite(p[i][1]) && isfinite(p[i][2]));
+                in[i] = !nf[i];
+                id[i] = 0;
+            }
+            int off = 0, mul = 1;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const int na = a.rl.n[ax];
+                const double* e = redge + off;
+                int ia[kBPer];
+#pragma unroll
+                for (int i = 0; i < kBPer; ++i) {
+                    in[i] = in[i] && p[i][ax] >= e[0] && p[i][ax] <= e[na];
+                    ia[i] = 0;
+                }
+                for (int step = na > 1 ? 1 << (31 - __clz(na - 1)) : 0; step > 0; step >>= 1) {
+#pragma unroll
+                    for (int i = 0; i < kBPer; ++i) {
+                        const int c = ia[i] + step;
+                        ia[i] = (c < na && e[min(c, na - 1)] <= p[i][ax]) ? c : ia[i];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < kBPer; ++i) id[i] += mul * ia[i];
+                off += na + 1;
+                mul *= na;
+            }
+#pragma unroll
+            for (int i = 0; i < kBPer; ++i) k[i] = in[i] ? id[i] : -1;
+        } else {
+#pragma unroll
+            for (int i = 0; i < kBPer; ++i) k[i] = (int32_t)hex_cell(a.g, px[i], py[i], pz[i], &nf[i]);
+        }
         if (sub + 1 < npass) load(sub + 1);
 #pragma unroll
         for (int i = 0; i < kBPer; ++i) {
@@ -450,7 +506,7 @@ __global__ __launch_bounds__(kTBlock) void k_tile_accum(TileArgs a) {
         const size_t o = ((size_t)j * a.F + f) * a.cells + c0;
         for (int i = threadIdx.x; i < nc; i += kTBlock) {
             const long long v = (long long)lacc[f * a.cpt + i];
-            a.field[o + i] = (float)(ldexp((double)v, -S[f]) / a.vol);
+            a.field[o + i] = (float)(ldexp((double)v, -S[f]) / (a.vcell ? a.vcell[c0 + i] : a.vol));
             if (a.acc) a.acc[o + i] = v;
         }
     }
@@ -545,6 +601,10 @@ size_t tiled_deposit_temp_bytes(int64_t cells, int64_t total, int32_t n_snap, in
            al256(4 * (3 * (size_t)n_snap * nt + 1));
 }
 
+void deposit_info_init(DepositInfo* info, const ScaleForce& fs, hipStream_t s) {
+    hipLaunchKernelGGL(k_dep_init, dim3(1), dim3(64), 0, s, info, fs);
+}
+
 size_t deposit_hex_temp_bytes(const cgd_mesh m, int64_t n, int32_t F) {
     return tiled_deposit_temp_bytes(m->cells, n, 1, F);
 }
@@ -598,6 +658,9 @@ cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipS
     a.field = d.field;
     a.acc = d.acc;
     a.vol = m->hex.vol;
+    a.rect = d.rect;
+    a.rl = d.rl;
+    a.vcell = d.vcell;
     hipLaunchKernelGGL(k_tile_clear, dim3((all + 255) / 256), dim3(256), 0, s, a);
     const int64_t bchunk = (int64_t)a.nsub_bin * kTChunk, schunk = (int64_t)a.nsub * kTChunk;
     const int cblocks = (int)std::max<int64_t>(1, (d.max_n + bchunk - 1) / bchunk);
@@ -611,7 +674,8 @@ cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipS
     const double np_ = (double)d.total;
     int tm = timing ? timing_begin(timing, s) : -1;
     int t13 = timing ? timing_begin(timing, s) : -1;
-    hipLaunchKernelGGL(k_tile_bin, dim3(cblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    if (d.rect) hipLaunchKernelGGL(k_tile_bin<true>, dim3(cblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_tile_bin<false>, dim3(cblocks, d.n_snap), dim3(kTBlock), 0, s, a);
     if (timing) timing_end(timing, t13, 13, (12.0 + 4.0 * d.F + 4.0) * np_, s);
     int t14 = timing ? timing_begin(timing, s) : -1;
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kTBlock), 0, s, a);
@@ -651,7 +715,7 @@ cgd_status deposit_hex(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
         d.field = field;
         d.acc = reinterpret_cast<long long*>(acc);
         d.temp = temp;
-        hipLaunchKernelGGL(k_dep_init, dim3(1), dim3(64), 0, s, info, fs);
+        deposit_info_init(info, fs, s);
         return tiled_deposit(m, d, timing, s);
     }
     deposit_prologue(n, F, values, acc, cells, info, fs, s);

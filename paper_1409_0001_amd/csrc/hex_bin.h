@@ -1,6 +1,6 @@
-// Centroid binning on a uniform hex grid (Section 2.2: the host cell is the
-// cell that contains the particle centroid).  Shared by the single and the
-// batched deposit.  The function body is compiled without floating-point
+// Centroid binning on uniform and rectilinear hex grids (Section 2.2: the
+// host cell is the cell that contains the particle centroid).  Shared by the
+// single and the batched deposit and the point location.  The function body is compiled without floating-point
 // contraction so that the float64 expression is exactly (x - lo) * s.
 #pragma once
 
@@ -41,5 +41,30 @@ __device__ inline int64_t hex_cell(const HexBin& g, float fx, float fy, float fz
     return idx[0] + (int64_t)g.n[0] * (idx[1] + (int64_t)g.n[1] * idx[2]);
 }
 
+// Rectilinear hexes (Section 2.2 with the cell given by the edges): along
+// each axis the largest i < N with e_i <= x (the upper cell at an interior
+// face, the last cell on the upper wall); -1 outside the closed box.
+struct RectLoc {
+    const double* e;  // x edges, then y, then z
+    int n[3];
+    __device__ int operator()(const double* p) const {
+        const double* ea = e;
+        int id[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int na = n[a];
+            if (!(p[a] >= ea[0] && p[a] <= ea[na])) return -1;
+            int lo = 0, hi = na - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (ea[mid] <= p[a]) lo = mid;
+                else hi = mid - 1;
+            }
+            id[a] = lo;
+            ea += na + 1;
+        }
+        return id[0] + n[0] * (id[1] + n[1] * id[2]);
+    }
+};
 
 }  // namespace cgd

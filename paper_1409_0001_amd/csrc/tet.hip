@@ -45,6 +45,7 @@
 #include <vector>
 
 #include "cg_common.h"
+#include "hex_bin.h"
 #include "tet_data.h"
 
 namespace cgd {
@@ -161,32 +162,6 @@ __device__ inline int locate(const LocArgs& g, const double* p) {
 struct TetLoc {
     LocArgs g;
     __device__ int operator()(const double* p) const { return locate(g, p); }
-};
-
-// Rectilinear hexes (Section 2.2 with the cell given by the edges): along
-// each axis the largest i < N with e_i <= x (the upper cell at an interior
-// face, the last cell on the upper wall); -1 outside the closed box.
-struct RectLoc {
-    const double* e;  // x edges, then y, then z
-    int n[3];
-    __device__ int operator()(const double* p) const {
-        const double* ea = e;
-        int id[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int na = n[a];
-            if (!(p[a] >= ea[0] && p[a] <= ea[na])) return -1;
-            int lo = 0, hi = na - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (ea[mid] <= p[a]) lo = mid;
-                else hi = mid - 1;
-            }
-            id[a] = lo;
-            ea += na + 1;
-        }
-        return id[0] + n[0] * (id[1] + n[1] * id[2]);
-    }
 };
 
 template <class Loc>
@@ -520,10 +495,36 @@ size_t diffuse_tet_workspace(const cgd_mesh m, int32_t F) {
 }
 
 cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values, float* field,
-                       int64_t* acc, DepositInfo* info, const ScaleForce& fs, hipStream_t s) {
+                       int64_t* acc, DepositInfo* info, void* temp, const ScaleForce& fs, hipStream_t s) {
     const TetData* t = m->tet;
     const int64_t cells = t->n_tet;
     const int e_n = ceil_log2_count(n);
+    if (t->ns == 6 && temp && deposit_hex_temp_bytes(m, n, F) > 0 &&
+        (int64_t)t->rdim[0] + t->rdim[1] + t->rdim[2] + 3 <= kRectTiledEdges) {
+        // rectilinear: the hex grid's tiled deposit with the edges' binning
+        // and each cell's own volume (the same cells, sums and roundings)
+        TiledDeposit d = {};
+        d.pos = pos;
+        d.values = values;
+        d.total = n;
+        d.max_n = n;
+        d.n_snap = 1;
+        d.F = F;
+        d.maxbits = info->maxbits;
+        d.force_s = info->force_s;
+        d.nf_val = info->nonfinite_val;
+        d.nf_val_stride = 1;
+        d.dropped = &info->dropped;
+        d.nf_pos = &info->nonfinite_pos;
+        d.field = field;
+        d.acc = reinterpret_cast<long long*>(acc);
+        d.temp = temp;
+        d.rect = 1;
+        d.rl = rect_loc(t);
+        d.vcell = t->vol;
+        deposit_info_init(info, fs, s);
+        return tiled_deposit(m, d, &m->timing, s);
+    }
     deposit_prologue(n, F, values, acc, cells, info, fs, s);
     if (n > 0) {
         const int blocks = (int)std::min<int64_t>(16384, (n + kBlock - 1) / kBlock);

@@ -44,10 +44,17 @@ def _mesh_case(seed, shape_y, shape_z):
     return [ex, ey, ez]
 
 
-@pytest.mark.parametrize("seed,ny,nz", [(71, 23, 17), (72, 1, 9)])
-def test_rect_locate_and_deposit_bit_exact(gpu_lib, seed, ny, nz):
+@pytest.mark.parametrize("path", ["tiled", "direct"])
+@pytest.mark.parametrize("seed,ny,nz,F", [(71, 23, 17, 2), (72, 1, 9, 2), (73, 60, 30, 1)])
+def test_rect_locate_and_deposit_bit_exact(gpu_lib, seed, ny, nz, F, path, monkeypatch):
+    """Binning and deposit on rectilinear grids, bit for bit against the
+    oracle, through the tiled deposit (2 tiles at F = 2; 5 tiles, the last
+    ragged, at F = 1) and the direct atomic one (CGD_DEPOSIT_DIRECT), with
+    points on faces and walls, outside the box and non-finite."""
     import torch
     cgd = gpu_lib
+    if path == "direct":
+        monkeypatch.setenv("CGD_DEPOSIT_DIRECT", "1")
     e = _mesh_case(seed, ny, nz)
     rng = np.random.default_rng(seed + 100)
     lo = np.array([v[0] for v in e])
@@ -59,14 +66,14 @@ def test_rect_locate_and_deposit_bit_exact(gpu_lib, seed, ny, nz):
         if cand.size:
             pos[k:k + 100, a] = rng.choice(cand, 100)
     pos[300:303] = [[np.nan, 0.2, 2.1], [0.1, np.inf, 2.2], [0.0, 0.2, 9.0]]
-    vals = np.stack([np.full(len(pos), 3.3e-8, np.float32), rng.normal(size=len(pos)).astype(np.float32)])
-    print(f"case: rect locate/deposit seed {seed} shape {[len(v) - 1 for v in e]}", flush=True)
+    vals = np.stack([np.full(len(pos), 3.3e-8, np.float32), rng.normal(size=len(pos)).astype(np.float32)])[:F]
+    print(f"case: rect locate/deposit seed {seed} shape {[len(v) - 1 for v in e]} F={F} {path}", flush=True)
     mesh = cgd.RectMesh(*e)
     assert mesh.kind == 2 and mesh.cells == 40 * ny * nz
     cell = cgd.locate(mesh, _t(pos, torch)).cpu().numpy()
     ref_cell, ref_mask, _ = O.rect_bin(pos.astype(np.float64), e)
     assert np.array_equal(cell, np.where(ref_mask, ref_cell, -1))
-    acc = torch.empty((2, mesh.cells), dtype=torch.int64, device="cuda")
+    acc = torch.empty((F, mesh.cells), dtype=torch.int64, device="cuda")
     field, st = cgd.deposit(mesh, _t(pos, torch), _t(vals, torch), acc=acc, stats=True)
     ref = O.deposit_rect(pos, vals, e)
     assert st.n_dropped == ref["n_dropped"]
@@ -372,7 +379,8 @@ def test_rect_full_size_residual_and_conservation(gpu_lib):
     properties that hold at any size: the float64 residual of
     (M + dtau K) x = M e, with K applied here face by face (vectorised, from
     the edges and the diffusivity), is at the solver tolerance; mass is
-    conserved; cells with D = 0 keep their deposited values."""
+    conserved; cells with D = 0 keep their deposited values.  The deposit
+    itself is compared with the oracle's bit for bit."""
     import torch
     from paper_1409_0001_amd import inputs
     cgd = gpu_lib
@@ -389,6 +397,10 @@ def test_rect_full_size_residual_and_conservation(gpu_lib):
     mesh = cgd.RectMesh(ex, ey, ez, diffusivity=np.ascontiguousarray(D3))
     pos, vals = _t(w.particles.pos, torch), _t(w.particles.values, torch)
     e = cgd.deposit(mesh, pos, vals)
+    # the deposit of the benchmarked configuration (2048 tiles), bit for bit
+    ref = O.deposit_rect(w.particles.pos, w.particles.values, [ex, ey, ez])
+    assert np.array_equal(e.cpu().numpy().view(np.uint32), ref["field32"].view(np.uint32))
+    del ref
     b = 4.0 / 256.0
     x, st = cgd.coarse_grain(mesh, pos, vals, b, 1, rtol=1e-6, stats=True)
     e = e[0].cpu().numpy().astype(np.float64).reshape(512, 256, 256)
