@@ -274,13 +274,16 @@ __global__ __launch_bounds__(NW * 64) void k_dir_lds(SweepArgs a) {
     }
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    constexpr int nx = NXR;
+    // rows of nx <= NXR cells: lanes from nx / VEC on load the row's last
+    // cells, store nothing and add nothing; the last real lane has the wall
+    const int nx = a.nx;
     const int ny = a.ny, nz = a.nz;
     const int x0 = lane * VEC;
+    const bool xin = x0 < nx;
     const int yg = blk % a.ygroups, zci = blk / a.ygroups;
     const int y0 = yg * TY, zb = zci * a.zc, ze = min(zb + a.zc, nz);
     const size_t plane = (size_t)nx * ny;
-    const size_t fo = (size_t)f * a.cells + x0;
+    const size_t fo = (size_t)f * a.cells + (xin ? x0 : nx - VEC);
     const Geom& g = a.g;
 
     const int yw = y0 - 1 + w;  // this wave's row
@@ -329,13 +332,13 @@ __global__ __launch_bounds__(NW * 64) void k_dir_lds(SweepArgs a) {
             if (in_dom) {
                 stv<VEC>(row(t, w), pv);
                 // B0: p_0 = z_0, which the caller keeps in place of p
-                if (!B0 && owner && t >= zb && t < ze) stv<VEC>(pdst + (size_t)t * plane, pv);
+                if (!B0 && owner && xin && t >= zb && t < ze) stv<VEC>(pdst + (size_t)t * plane, pv);
             }
         }
         ring[S % 3] = pv;
         lds_barrier();
         const int q = t - 1;
-        if (owner && q >= zb && q < ze) {
+        if (owner && xin && q >= zb && q < ze) {
             const Vec<VEC>& c = ring[(S + 2) % 3];   // plane q
             const Vec<VEC>& zl = ring[(S + 1) % 3];  // plane q - 1
             const Vec<VEC>& zh = ring[S % 3];        // plane q + 1
@@ -347,6 +350,7 @@ __global__ __launch_bounds__(NW * 64) void k_dir_lds(SweepArgs a) {
             }
             float lft, rgt;
             x_neighbours<VEC>(c, lft, rgt);
+            if (nx != NXR) rgt = x0 + VEC >= nx ? c.f[VEC - 1] : rgt;
             const bool hzd = q > 0, hzu = q + 1 < nz;
             const float czd = hzd ? cz : 0.f, czu = hzu ? cz : 0.f;
             const float dq = d_in - (hzd ? 0.f : cz) - (hzu ? 0.f : cz);
@@ -549,11 +553,14 @@ struct Plan {
     bool edge;
 };
 
-// VEC: cells per lane.  A wave covers a whole x-row when nx = 64 * VEC for
-// VEC in {4, 2, 1}; any other nx runs with VEC = 1 and edge loads.
+// VEC: cells per lane.  A wave covers a whole x-row when nx <= 64 * VEC and
+// nx is a multiple of VEC (the lanes beyond the row idle), for VEC in {4, 2,
+// 1}; wider rows, and rows of 65..256 cells that no VEC divides, run with
+// VEC = 1 and edge loads over several x segments.
 int pick_vec(int nx) {
-    if (nx == 256) return 4;
-    if (nx == 128) return 2;
+    if (nx <= 64) return 1;
+    if (nx <= 128) return nx % 2 == 0 ? 2 : 1;
+    if (nx <= 256) return nx % 4 == 0 ? 4 : 1;
     return 1;
 }
 
@@ -565,7 +572,7 @@ bool ty_supported(int vec, int ty) {
 Plan make_plan(const HexGeom& g, int F, int vec, int ty, int zc) {
     Plan p;
     p.vec = vec;
-    p.edge = (vec == 1 && g.nx != 64);
+    p.edge = (vec == 1 && g.nx > 64);
     p.ty = ty;
     p.zc = std::max(1, std::min(zc, g.nz));
     p.xsegs = (g.nx + 64 * vec - 1) / (64 * vec);
@@ -977,7 +984,7 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, co
     // k_precond_lds with the intermediate powers in LDS.
     // CGD_HEX_PRECOND_DEG (2, 3, 4) and CGD_HEX_LDS_ZC override the choice.
     const bool pcg = da.precond == 0 || ro;  // the rectilinear operator runs preconditioned CG only
-    const bool row_wave = !p.edge && p.xsegs == 1 && g.nx == 64 * p.vec;
+    const bool row_wave = !p.edge && p.xsegs == 1;  // one wave per x-row (possibly partial)
     const int deg = (pcg && row_wave && !ro) ? 2 : 1;  // rectilinear: Jacobi (the SZ modes)
     a.pcg = pcg ? 1 : 0;
     poly_precond_coeffs(a.g.cx, a.g.cy, a.g.cz, deg, &a.g.c0, &a.g.c1, &a.g.c2);

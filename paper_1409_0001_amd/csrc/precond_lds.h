@@ -159,8 +159,14 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     static_assert(E0 <= NW, "one row per wave covers every level");
     static_assert(RPL <= 2, "loaders hold at most two rows");
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    constexpr int nx = NXR;
+    // A row of nx <= NXR cells (nx a multiple of VEC): lanes from nx / VEC
+    // on hold copies of the row's last cells, are never stored and add
+    // nothing to the sums; the last real lane takes the wall (or periodic)
+    // rule on its right
+    const int nx = g.nx;
     const int x0 = lane * VEC;
+    const bool xin = x0 < nx;
+    const int xg = xin ? x0 : nx - VEC;  // the column this lane loads
     const size_t plane = (size_t)nx * ny;
 
     // this wave's row; it is in level j's extent (extent row w - j) iff
@@ -186,7 +192,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     auto ld = [](const float* r) {  // row starts are 16-byte aligned: one LDS access per row
         return ldv<VEC>(static_cast<const float*>(__builtin_assume_aligned(r, 4 * VEC)));
     };
-    const float* src = src_field + x0;
+    const float* src = src_field + xg;
     auto ysrc = [&](int e) {  // clamped (or wrapped) row of extent row e of level 0
         const int y = (per & 2) ? ((y0 - D + e) % ny + ny) % ny : min(max(y0 - D + e, 0), ny - 1);
         return (size_t)y * nx;
@@ -197,7 +203,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     // owner of the row at step q + D
     float* side_lds = lds + lds_level_base<D, TY>(D) * NXR;
     auto side_row = [&](int q, int i) -> float* { return side_lds + ((q & 1) * TY + i) * NXR + x0; };
-    const float* side = FORM == 2 ? side_field + x0 : nullptr;
+    const float* side = FORM == 2 ? side_field + xg : nullptr;
     const size_t side_y = (size_t)min(y0 + (li < TY ? li : 0), ny - 1) * nx;
     auto side_load = [&](int q) { return ldv<VEC>(side + (size_t)min(max(q, 0), nz - 1) * plane + side_y); };
 
@@ -230,7 +236,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     }
     if constexpr (SIN || SOUT) {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) sgx[e] = g.rsg[0][x0 + e];
+        for (int e = 0; e < VEC; ++e) sgx[e] = g.rsg[0][xg + e];
         sgy = g.rsg[1][ywr];
     }
     // SIN: S on the y axis of the loader's rows (fixed for the march)
@@ -242,7 +248,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     auto scale_in = [&](Vec<VEC>& v, int e, int i, int q, bool setup) {
         if constexpr (SIN) {
             const int y = y0 - D + e;
-            if (FIRST && e >= D && e < D + TY && y < ny && q >= zb && q < ze) {
+            if (FIRST && xin && e >= D && e < D + TY && y < ny && q >= zb && q < ze) {
 #pragma unroll
                 for (int k = 0; k < VEC; ++k) acc1 = fma((double)v.f[k], (double)v.f[k], acc1);
             }
@@ -375,12 +381,14 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 for (int e = 0; e < VEC; ++e) ys.f[e] += yu.f[e];
                 float lft, rgt;
                 x_neighbours<VEC>(c, lft, rgt);
+                if (nx != NXR) rgt = x0 + VEC >= nx ? c.f[VEC - 1] : rgt;  // the row's last cell: wall
                 if (per & 1) {
                     // periodic x: the row's end cells are neighbours
-                    const float last = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c.f[VEC - 1]), 63));
+                    const float last =
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c.f[VEC - 1]), (nx - 1) / VEC));
                     const float first = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c.f[0]), 0));
                     lft = lane == 0 ? last : lft;
-                    rgt = lane == 63 ? first : rgt;
+                    rgt = x0 + VEC >= nx ? first : rgt;
                 }
                 // u = cp[D-j] r + ca A u_prev (ca = cp[D] at j = 1, else 1), with
                 // ca folded into the stencil's coefficients (PrecondCoef).
@@ -440,7 +448,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                     }
                 }
                 if (j == 1) u1 = u;
-                if (FIRST && FORM == 1 && !SIN && j == 1 && owner && yw < ny && q >= zb && q < ze) {
+                if (FIRST && FORM == 1 && !SIN && j == 1 && owner && xin && yw < ny && q >= zb && q < ze) {
                     // b.b over the output cells, from this row's b at plane q
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) acc1 = fma((double)c.f[e], (double)c.f[e], acc1);
@@ -450,7 +458,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 // not written here keeps an older, finite plane that is only
                 // ever read with a zero coefficient (beyond a wall)
                 if (j >= 2 && j < D) lv[j >= 2 ? j - 2 : 0][((S - j) % 3 + 3) % 3] = u;
-                if (j == D && owner && yw < ny && q >= zb && q < ze) {
+                if (j == D && owner && xin && yw < ny && q >= zb && q < ze) {
                     // output of plane q complete: store it and add r.z (and b.b)
                     Vec<VEC> us = u;
                     if constexpr (SOUT) {
@@ -458,7 +466,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
 #pragma unroll
                         for (int e = 0; e < VEC; ++e) us.f[e] *= sgx[e] * syz;
                     }
-                    stv<VEC>(dst_field + x0 + (size_t)q * plane + (size_t)yw * nx, us);
+                    stv<VEC>(dst_field + xg + (size_t)q * plane + (size_t)yw * nx, us);
                     if constexpr (FORM == 2) {
                         const Vec<VEC> rr = ld(side_row(q, w - D));
 #pragma unroll

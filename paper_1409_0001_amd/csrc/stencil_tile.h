@@ -502,8 +502,9 @@ __device__ __forceinline__ Vec<VEC> apply_row_lr(const Geom& g, const Vec<VEC>& 
 // halo row: when plane z+2 of r arrives, A r of plane z+1 is formed, and then
 // A (A r) of plane z.  Values at clamped rows or planes beyond a wall are
 // never used (the wall rule substitutes the cell itself).  One wave covers a
-// row (nx = 64 VEC).  FIRST: the input is b (zero initial guess) and b.b is
-// accumulated as well.
+// row (nx <= 64 VEC, a multiple of VEC; lanes beyond it load the row's last
+// cells and store and add nothing).  FIRST: the input is b (zero initial
+// guess) and b.b is accumulated as well.
 template <int VEC, int TY, bool FIRST, bool RECT = false>
 __device__ __forceinline__ void tile_precond2(const Ptrs& p, const Geom& g, size_t fo, int yg, int zb, int ze,
                                               int lane, double& acc0, double& acc1) {
@@ -511,10 +512,11 @@ __device__ __forceinline__ void tile_precond2(const Ptrs& p, const Geom& g, size
     constexpr int RA = TY + 2;  // rows of A r: y0 - 1 .. y0 + TY
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int x0 = lane * VEC;
+    const bool xin = x0 < nx;
     const bool wall_l = x0 == 0, wall_r = x0 + VEC >= nx;
     const int y0 = yg * TY;
     const size_t plane = (size_t)nx * ny;
-    const size_t base = fo + x0;
+    const size_t base = fo + (xin ? x0 : nx - VEC);
     const float* src = FIRST ? p.B : p.R;
     auto at = [&](int z, int y) -> size_t {
         z = z < 0 ? 0 : (z >= nz ? nz - 1 : z);
@@ -573,7 +575,7 @@ __device__ __forceinline__ void tile_precond2(const Ptrs& p, const Geom& g, size
 #pragma unroll
             for (int e = 0; e < VEC; ++e)
                 zv.f[e] = fmaf(g.c2, aar.f[e], fmaf(g.c1, a1[j + 1].f[e], g.c0 * rv.f[e]));
-            if (y < ny) {
+            if (xin && y < ny) {
                 stv<VEC>(p.Z + at(z, y), zv);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {

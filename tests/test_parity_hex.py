@@ -307,10 +307,13 @@ def test_dense_bed_reduced_against_dct(gpu_lib):
 
 
 @pytest.mark.parametrize("deg", [3, 4, 8, 12])
-@pytest.mark.parametrize("shape,zc", [((64, 37, 100), 16), ((128, 20, 70), 13), ((256, 13, 40), 7)])
+@pytest.mark.parametrize("shape,zc", [((64, 37, 100), 16), ((128, 20, 70), 13), ((256, 13, 40), 7),
+                                      ((40, 37, 60), 16), ((100, 21, 50), 9), ((200, 13, 40), 7)])
 def test_lds_preconditioner_matches_oracle(gpu_lib, shape, zc, deg, monkeypatch):
     """The degree-3/4 preconditioning sweep with its powers of A in LDS
-    (one wave per x-row: nx = 64, 128, 256), and degrees 8 and 12 as two and
+    (one wave per x-row: nx = 64, 128, 256, and partial rows of 40, 100 and
+    200 cells at 1, 2 and 4 cells per lane, the lanes beyond the row idle),
+    and degrees 8 and 12 as two and
     three passes of quadratic factors, forced onto small grids with ragged
     row groups (ny not a multiple of 8) and a ragged last z chunk: the result
     matches the float64 DCT solution, and the higher degree takes fewer
@@ -345,3 +348,29 @@ def test_lds_preconditioner_matches_oracle(gpu_lib, shape, zc, deg, monkeypatch)
     assert it4 < it2, (it2, it4)
     if deg >= 8:
         assert max(max(r[:2]) for r in st4.iters[:steps]) <= (3 if deg == 8 else 2), st4.iters
+
+
+@pytest.mark.parametrize("shape", [(200, 160, 256), (96, 128, 320)])
+def test_any_width_picks_lds_degree_by_default(gpu_lib, shape):
+    """Rows that are not 64, 128 or 256 cells wide (200 cells at 4 per lane,
+    96 at 2) on grids large enough to fill the machine: the default choice is
+    the LDS polynomial preconditioner (degree 12 at dtau / h^2 = 1, 2
+    iterations per step, as on the 256-wide dense bed), and the result
+    matches the float64 DCT solution."""
+    import torch
+    cgd = gpu_lib
+    nx, ny, nz = shape
+    lo, hi = (0.0, 0.0, 0.0), (nx / 256.0, ny / 256.0, nz / 256.0)
+    box = inputs.HexBox(lo, hi, shape)
+    p = inputs.uniform_bed(box, 1_000_000, 1, seed=78, diam=0.003)
+    b, steps = 4.0 / 256.0, 4  # dtau / h^2 = 1
+    print(f"case: any width default degree {shape}", flush=True)
+    mesh = cgd.HexMesh(shape, lo, hi)
+    out, st = cgd.coarse_grain(mesh, _t(p.pos, torch), _t(p.values, torch), b, steps, rtol=1e-6, stats=True)
+    dep = O.deposit_hex(p.pos, p.values, lo, hi, shape)
+    ref = O.diffuse_hex_dct(dep["field64"], lo, hi, shape, b, steps)
+    assert rel_l2(out.cpu().numpy()[0], ref[0]) <= REL_L2
+    print(f"iterations {st.iters}", flush=True)
+    assert st.status == 0
+    assert max(r[0] for r in st.iters) <= 2, st.iters
+
