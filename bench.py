@@ -569,8 +569,9 @@ def run_dense(args, w, mesh, pos, vals, scheme, steps, warmup, check=True):
 def secondary(args, w, mesh, pos, vals):
     """The other workloads, at their full sizes with few timed calls, so that
     the default run reports them too: Crank-Nicolson on the dense bed, the
-    literal 256^3 cube, the batched launch, the unstructured and stretched
-    meshes, and a reduced learned-guess sample."""
+    literal 256^3 cube, the dense bed turned to 512-cell rows, the batched
+    launch, the unstructured and stretched meshes, and a reduced
+    learned-guess sample."""
     import torch
 
     import paper_1409_0001_amd as cgd
@@ -607,6 +608,29 @@ def secondary(args, w, mesh, pos, vals):
                 "roofline_dominant": {k: r["roofline"][k] for k in ("kernel", "avg_us", "frac")},
                 "whole_solve_frac": r["roofline"]["whole_solve"]["frac"]}
 
+    def wide():
+        # the dense bed turned so that its long axis is x: 512 x 256 x 256 cells
+        # in a 2 x 1 x 1 box (h = 1/256), rows wider than one wave covers
+        import numpy as np
+        wd = inputs.dense_bed(n_particles=20_000_000, shape=(256, 256, 512))
+        ww = inputs.Workload("dense-bed-turned-512x256x256", inputs.HexBox((0.0, 0.0, 0.0), (2.0, 1.0, 1.0),
+                                                                          (512, 256, 256)),
+                             inputs.Particles(np.ascontiguousarray(wd.particles.pos[:, ::-1]), wd.particles.values),
+                             wd.bandwidth, wd.n_steps, wd.rtol)
+        del wd
+        mw = cgd.HexMesh(ww.box.shape, ww.box.lo, ww.box.hi)
+        pw = torch.from_numpy(ww.particles.pos).cuda()
+        vw = torch.from_numpy(ww.particles.values).cuda()
+        r = run_dense(args, ww, mw, pw, vw, "be", 5, 1, check=True)
+        mw.close()
+        return {"workload": "the dense bed turned so that its long axis is x: 512 x 256 x 256 hex in a 2 x 1 x 1 "
+                            "box (h = 1/256), 20M particles, 4 backward-Euler steps (rows of 512 cells: solved with "
+                            "x and y exchanged)", "unit": "fields/s", "value": round(r["value"], 2),
+                "ms_per_field": round(r["ms_per_field"], 3), "cg_iters_per_step": r["iters"],
+                "rel_l2": r["rel_l2"], "deposit_bit_exact": r["deposit_bit_exact"],
+                "roofline_dominant": {k: r["roofline"][k] for k in ("kernel", "avg_us", "frac")},
+                "whole_solve_frac": r["roofline"]["whole_solve"]["frac"]}
+
     def sub(fn, **over):
         a = argparse.Namespace(**vars(args))
         for k, v in over.items():
@@ -615,6 +639,7 @@ def secondary(args, w, mesh, pos, vals):
 
     guarded("dense_crank_nicolson", cn)
     guarded("cube_256", cube)
+    guarded("wide_512", wide)
     guarded("stretched", lambda: sub(bench_stretched, steps=2, warmup=1, no_check=False))
     guarded("unstructured", lambda: sub(bench_unstructured, steps=3, warmup=1))
     guarded("batched", lambda: sub(bench_batched, steps=2, warmup=1, snapshots=64, no_check=False))

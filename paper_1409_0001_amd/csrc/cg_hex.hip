@@ -865,8 +865,54 @@ bool hex_one_x_segment(const HexGeom& g, const float* field) {
     return g.nx <= 64 * vec;
 }
 
+// Rows wider than a wave covers (nx > 64 VEC) while the y rows fit one: the
+// uniform grid is solved with x and y exchanged, the field transposed into
+// a seventh workspace vector and back (16 bytes per cell, about 3 % of a
+// solve at 256 x 256 x 512), so that the LDS tiles apply.
+static bool fits_one_wave(int n) { return n <= 64 * pick_vec(n); }
+static bool swap_xy(const HexGeom& g) { return !fits_one_wave(g.nx) && fits_one_wave(g.ny); }
+
+static HexGeom swapped_xy(const HexGeom& g) {
+    HexGeom t = g;
+    t.nx = g.ny;
+    t.ny = g.nx;
+    std::swap(t.lo[0], t.lo[1]);
+    std::swap(t.hi[0], t.hi[1]);
+    std::swap(t.s[0], t.s[1]);
+    std::swap(t.h[0], t.h[1]);
+    return t;
+}
+
+// out[f][z][x][y] = in[f][z][y][x] for an nx-wide, ny-tall plane: 64 x 64
+// tiles through LDS (one padding column against bank conflicts), coalesced
+// on both sides.  Grid: (ceil(nx / 64), ceil(ny / 64), nz * F).
+__global__ __launch_bounds__(256) void k_transpose_xy(const float* __restrict__ in, float* __restrict__ out, int nx,
+                                                      int ny) {
+    __shared__ float t[64][65];
+    const size_t po = (size_t)blockIdx.z * nx * ny;
+    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int y = y0 + r, x = x0 + tx;
+        if (y < ny && x < nx) t[r][tx] = in[po + (size_t)y * nx + x];
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int x = x0 + r, y = y0 + tx;
+        if (x < nx && y < ny) out[po + (size_t)x * ny + y] = t[tx][r];
+    }
+}
+
+static void transpose_xy(const float* in, float* out, int nx, int ny, int64_t planes, hipStream_t s) {
+    const dim3 grid((nx + 63) / 64, (ny + 63) / 64, (unsigned)planes);
+    hipLaunchKernelGGL(k_transpose_xy, grid, dim3(256), 0, s, in, out, nx, ny);
+}
+
 size_t diffuse_hex_workspace(const cgd_mesh m, int32_t F) {
-    return small_bytes(F, (int)max_bpf(m->hex, F)) + 6 * (size_t)F * m->cells * sizeof(float);
+    const HexGeom& g = m->hex;
+    const bool sw = swap_xy(g);
+    const size_t bpf = sw ? std::max(max_bpf(g, F), max_bpf(swapped_xy(g), F)) : max_bpf(g, F);
+    return small_bytes(F, (int)bpf) + (sw ? 7 : 6) * (size_t)F * m->cells * sizeof(float);
 }
 
 cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s) {
@@ -874,14 +920,31 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     if (rc != CGD_OK) return rc;
     rc = ensure_pinned(m, kPinBytes);
     if (rc != CGD_OK) return rc;
-    rc = diffuse_hex_enqueue(m, da, static_cast<char*>(m->ws.ptr), nullptr, out != nullptr, s, nullptr);
-    if (rc != CGD_OK) return rc;
+    char* base = static_cast<char*>(m->ws.ptr);
+    const HexGeom& g = m->hex;
+    if (swap_xy(g) && (da.x0_mode == 0 || da.x0_mode == 1) && !getenv("CGD_HEX_NO_SWAP")) {
+        // the seventh vector, after the six the solve uses
+        const size_t bpf = std::max(max_bpf(g, da.F), max_bpf(swapped_xy(g), da.F));
+        float* T = reinterpret_cast<float*>(base + small_bytes(da.F, (int)bpf)) + 6 * (size_t)da.F * m->cells;
+        const HexGeom gs = swapped_xy(g);
+        const int64_t planes = (int64_t)da.F * g.nz;
+        transpose_xy(da.field, T, g.nx, g.ny, planes, s);
+        DiffuseArgs d2 = da;
+        d2.field = T;
+        rc = diffuse_hex_enqueue(m, d2, base, nullptr, out != nullptr, s, nullptr, &gs);
+        if (rc != CGD_OK) return rc;
+        transpose_xy(T, da.field, gs.nx, gs.ny, planes, s);
+        CGD_HIP_TRY(hipGetLastError());
+    } else {
+        rc = diffuse_hex_enqueue(m, da, base, nullptr, out != nullptr, s, nullptr);
+        if (rc != CGD_OK) return rc;
+    }
     return cg_finish_call(m, da.F, da.n_steps, m->hex.vol, s, out, da.x0_mode == 3);
 }
 
 cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, const int* fixed, bool sums,
-                               hipStream_t s, const RectOp* ro) {
-    const HexGeom& g = m->hex;
+                               hipStream_t s, const RectOp* ro, const HexGeom* geom) {
+    const HexGeom& g = geom ? *geom : m->hex;
     const int F = da.F;
     const int64_t cells = m->cells;
     // vector width: rows must be 16 / 8 byte aligned in every buffer touched

@@ -187,10 +187,10 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hi
 // which may be captured in a graph.  sums: the mass before and after.  The
 // statistics stay in the small region at `base`.
 // ro: nullptr for the uniform grid's operator, or a rectilinear grid's
-// (the field then holds M^1/2 e; Jacobi-preconditioned CG in the register
-// sweeps).
+// (the field then holds M^1/2 e; RectOp's preconditioner).  geom: the grid
+// to solve on in place of the mesh's (the same cells in another layout).
 cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& a, char* base, const int* fixed, bool sums,
-                               hipStream_t s, const RectOp* ro = nullptr);
+                               hipStream_t s, const RectOp* ro = nullptr, const HexGeom* geom = nullptr);
 
 // A rectilinear grid whose diffusivity is a product of per-axis factors
 // (D_ijk = Dx_i Dy_j Dz_k), periodic axes included.  The solve runs on

@@ -350,13 +350,15 @@ def test_lds_preconditioner_matches_oracle(gpu_lib, shape, zc, deg, monkeypatch)
         assert max(max(r[:2]) for r in st4.iters[:steps]) <= (3 if deg == 8 else 2), st4.iters
 
 
-@pytest.mark.parametrize("shape", [(200, 160, 256), (96, 128, 320)])
+@pytest.mark.parametrize("shape", [(200, 160, 256), (96, 128, 320), (512, 96, 128), (300, 200, 64)])
 def test_any_width_picks_lds_degree_by_default(gpu_lib, shape):
     """Rows that are not 64, 128 or 256 cells wide (200 cells at 4 per lane,
-    96 at 2) on grids large enough to fill the machine: the default choice is
-    the LDS polynomial preconditioner (degree 12 at dtau / h^2 = 1, 2
-    iterations per step, as on the 256-wide dense bed), and the result
-    matches the float64 DCT solution."""
+    96 at 2) and rows wider than a wave covers (512, 300: solved with x and y
+    exchanged, the field transposed in and out) on grids large enough to
+    fill the machine: the default choice is the LDS polynomial
+    preconditioner (degree 12 at dtau / h^2 = 1, 2 iterations per step, as
+    on the 256-wide dense bed), and the result matches the float64 DCT
+    solution."""
     import torch
     cgd = gpu_lib
     nx, ny, nz = shape
@@ -373,4 +375,38 @@ def test_any_width_picks_lds_degree_by_default(gpu_lib, shape):
     print(f"iterations {st.iters}", flush=True)
     assert st.status == 0
     assert max(r[0] for r in st.iters) <= 2, st.iters
+
+
+@pytest.mark.parametrize("deg", [2, 12])
+def test_wide_rows_exchanged_match_oracle(gpu_lib, deg, monkeypatch):
+    """Rows of 300 cells (wider than a wave covers) over 20 rows: the solve
+    runs with x and y exchanged (forced degree, z chunks of 4), two fields,
+    ragged 64 x 64 transpose tiles; against the float64 DCT solution, and
+    against the same grid solved without the exchange (edge loads, degree 1
+    sweeps) within the solver tolerance."""
+    import torch
+    cgd = gpu_lib
+    shape = (300, 20, 17)
+    lo, hi = (0.0, 0.0, 0.0), (300 / 64.0, 20 / 64.0, 17 / 64.0)
+    box = inputs.HexBox(lo, hi, shape)
+    p = inputs.uniform_bed(box, 60_000, 2, seed=79, diam=0.01)
+    b, steps = 4.0 / 64.0, 3
+    print(f"case: wide rows exchanged degree {deg}", flush=True)
+    mesh = cgd.HexMesh(shape, lo, hi)
+    pos, vals = _t(p.pos, torch), _t(p.values, torch)
+    monkeypatch.setenv("CGD_HEX_PRECOND_DEG", str(deg))
+    monkeypatch.setenv("CGD_HEX_LDS_ZC", "4")
+    out, st = cgd.coarse_grain(mesh, pos, vals, b, steps, rtol=1e-7, stats=True)
+    monkeypatch.setenv("CGD_HEX_NO_SWAP", "1")
+    out2, st2 = cgd.coarse_grain(mesh, pos, vals, b, steps, rtol=1e-7, stats=True)
+    dep = O.deposit_hex(p.pos, p.values, lo, hi, shape)
+    ref = O.diffuse_hex_dct(dep["field64"], lo, hi, shape, b, steps)
+    o, o2 = out.cpu().numpy(), out2.cpu().numpy()
+    for f in range(2):
+        assert rel_l2(o[f], ref[f]) <= REL_L2, (f, rel_l2(o[f], ref[f]))
+        assert rel_l2(o2[f], ref[f]) <= REL_L2, (f, rel_l2(o2[f], ref[f]))
+        m0 = (dep["field64"][f]).sum()
+        assert abs(o[f].astype(np.float64).sum() - m0) <= 1e-5 * np.abs(dep["field64"][f]).sum()
+    print(f"iterations: exchanged {st.iters}, not {st2.iters}", flush=True)
+    assert sum(sum(r) for r in st.iters) < sum(sum(r) for r in st2.iters)
 
