@@ -685,7 +685,8 @@ cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipS
     hipLaunchKernelGGL(k_tile_accum, dim3(all), dim3(kTBlock), 0, s, a);
     if (timing)
         timing_end(timing, t15, 15,
-                   (8.0 + 4.0 * (d.F - 1)) * np_ + 4.0 * d.F * (double)m->cells * d.n_snap, s);
+                   (8.0 + 4.0 * (d.F - 1)) * np_ + (4.0 * d.F + (d.vcell ? 8.0 : 0.0)) * (double)m->cells * d.n_snap,
+                   s);
     if (timing) timing_end(timing, tm, 2, (12.0 + 12.0 * d.F) * np_, s);
     CGD_HIP_TRY(hipGetLastError());
     return CGD_OK;
