@@ -461,13 +461,14 @@ __device__ __forceinline__ void precond_block(const SweepArgs& a, const Geom& g,
 // Uniform grids: the Horner pass (FORM 0, coefficients pc) or the product
 // form's passes r -> U (FORM 1, pc), U -> V (FORM 3, pcm; degree 12) and
 // V -> z (FORM 2, pc2).  At 2 cells per lane (LDS for two blocks per CU) the
-// middle pass and the first pass of later iterations are held to 64 VGPRs,
-// which they meet without spills, so that two blocks share a CU: the 128^3
-// batched launch went from 3,224 to 3,388 fields/s; the last pass and the
-// first iteration's first pass would spill (15 and 1 registers), and with
-// them held too it fell to 3,168.
+// middle pass, the first pass of later iterations and the last pass are
+// held to 64 VGPRs so that two blocks share a CU: the 128^3 batched launch
+// went from 3,224 to 3,388 fields/s with the first two (no spills), and to
+// 3,455 with the last pass too once its loaders keep one plane in flight
+// instead of two (5 registers spilled; with two planes it spilled 15 and
+// the launch fell to 3,168).  The first iteration's first pass would spill.
 template <int VEC, int D, int TY, int NW, bool FIRST, int FORM = 0>
-__global__ __launch_bounds__(NW * 64, (VEC <= 2 && (FORM == 3 || (FORM == 1 && !FIRST))) ? 8 : 1) void k_precond_lds(SweepArgs a) {
+__global__ __launch_bounds__(NW * 64, (VEC <= 2 && (FORM == 3 || FORM == 2 || (FORM == 1 && !FIRST))) ? 8 : 1) void k_precond_lds(SweepArgs a) {
     const float* rsrc = FIRST ? a.p.B : a.p.R;
     const float* src = FORM == 2 ? a.p.V : (FORM == 3 ? a.p.U : rsrc);
     float* dst = FORM == 1 ? a.p.U : (FORM == 3 ? a.p.V : a.p.Z);

@@ -155,7 +155,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     constexpr int E0 = TY + 2 * D;
     constexpr int NL = NW - TY;                  // waves owning no output row: the loaders
     constexpr int RPL = (E0 + NL - 1) / NL;      // rows of r per loader
-    constexpr int P = 2;                         // planes of r in flight per loader
+    constexpr int P = (VEC <= 2 && FORM == 2) ? 1 : 2;  // planes of r in flight per loader
     static_assert(E0 <= NW, "one row per wave covers every level");
     static_assert(RPL <= 2, "loaders hold at most two rows");
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
