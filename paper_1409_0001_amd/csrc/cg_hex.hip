@@ -921,7 +921,7 @@ size_t diffuse_hex_workspace(const cgd_mesh m, int32_t F) {
     return small_bytes(F, (int)bpf) + (sw ? 7 : 6) * (size_t)F * m->cells * sizeof(float);
 }
 
-cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s) {
+cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s, const int* fixed) {
     cgd_status rc = ensure_workspace(m, diffuse_hex_workspace(m, da.F));
     if (rc != CGD_OK) return rc;
     rc = ensure_pinned(m, kPinBytes);
@@ -937,12 +937,12 @@ cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         transpose_xy(da.field, T, g.nx, g.ny, planes, s);
         DiffuseArgs d2 = da;
         d2.field = T;
-        rc = diffuse_hex_enqueue(m, d2, base, nullptr, out != nullptr, s, nullptr, &gs);
+        rc = diffuse_hex_enqueue(m, d2, base, fixed, out != nullptr, s, nullptr, &gs);
         if (rc != CGD_OK) return rc;
         transpose_xy(T, da.field, gs.nx, gs.ny, planes, s);
         CGD_HIP_TRY(hipGetLastError());
     } else {
-        rc = diffuse_hex_enqueue(m, da, base, nullptr, out != nullptr, s, nullptr);
+        rc = diffuse_hex_enqueue(m, da, base, fixed, out != nullptr, s, nullptr);
         if (rc != CGD_OK) return rc;
     }
     return cg_finish_call(m, da.F, da.n_steps, m->hex.vol, s, out, da.x0_mode == 3);

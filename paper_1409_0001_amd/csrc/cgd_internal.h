@@ -60,6 +60,17 @@ struct HexGeom {
     double vol;    // (h_x h_y) h_z
 };
 
+// The CG iterations each pseudo-step of a uniform-grid coarse-graining call
+// took (largest over the fields), with the parameters that determine them;
+// a later call with the same parameters enqueues that many iterations (plus
+// one) per step without reading convergence back between steps.
+struct HexBudget {
+    bool valid = false;
+    int32_t F = 0, n_steps = 0, max_iter = 0, precond = 0, scheme = 0;
+    double bandwidth = 0.0, rtol = 0.0;
+    int32_t iters[CGD_MAX_STEPS] = {};
+};
+
 struct TetData;  // defined in tet.cpp
 struct RectOp;   // below
 
@@ -108,6 +119,7 @@ struct cgd_mesh_s {
     hipEvent_t ev[2] = {nullptr, nullptr};
     cgd::Timing timing;
     int32_t cg_hint = -1;          // iteration at which the last CG solve on this mesh stopped (-1: none yet)
+    cgd::HexBudget budget;         // iterations per step of the last uniform-grid coarse-graining call
 };
 
 namespace cgd {
@@ -176,7 +188,11 @@ struct DiffuseArgs {
     cgd_unet model;   // x0_mode 3
     int32_t scheme;   // 0 backward Euler, 1 Crank-Nicolson (half-step solve, then 2 y - e)
 };
-cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hipStream_t s);
+// fixed: nullptr, or per step the iterations to enqueue without host
+// read-backs (a step whose fields have not converged within it ends with
+// CGD_NOT_CONVERGED, as one that reaches max_iter).
+cgd_status diffuse_hex(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hipStream_t s,
+                       const int* fixed = nullptr);
 // The device work of diffuse_hex, enqueued on s with its workspace at `base`
 // (diffuse_hex_workspace(m, a.F) bytes, laid out as the mesh workspace: the
 // small region, partial sums, then the vectors).  fixed: nullptr for the

@@ -410,3 +410,46 @@ def test_wide_rows_exchanged_match_oracle(gpu_lib, deg, monkeypatch):
     print(f"iterations: exchanged {st.iters}, not {st2.iters}", flush=True)
     assert sum(sum(r) for r in st.iters) < sum(sum(r) for r in st2.iters)
 
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_repeated_calls_with_iteration_budgets(gpu_lib, precond, monkeypatch):
+    """A coarse-graining call with the parameters of the previous one on the
+    mesh enqueues the iterations that call took (plus one) per step without
+    read-backs.  Bit for bit the same fields and iteration counts as the
+    call with read-backs (CGD_HEX_NO_BUDGET), both when the budget suffices
+    (the same input again) and when it does not (a rougher input after a
+    smooth one: the call goes round again with read-backs)."""
+    import torch
+    cgd = gpu_lib
+    shape = (64, 48, 40)
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 0.75, 0.625)
+    box = inputs.HexBox(lo, hi, shape)
+    smooth = inputs.uniform_bed(box, 400_000, 2, seed=81, diam=0.01)
+    rough = inputs.uniform_bed(box, 3_000, 2, seed=82, diam=0.01)
+    b, steps = 4.0 / 64.0, 4
+    print(f"case: iteration budgets precond {precond}", flush=True)
+
+    def run(p, budget):
+        if budget:
+            monkeypatch.delenv("CGD_HEX_NO_BUDGET", raising=False)
+        else:
+            monkeypatch.setenv("CGD_HEX_NO_BUDGET", "1")
+        out, st = cgd.coarse_grain(mesh, _t(p.pos, torch), _t(p.values, torch), b, steps, rtol=1e-6, stats=True,
+                                   precond=precond)
+        return out.cpu().numpy(), [list(r) for r in st.iters], st.status
+
+    mesh = cgd.HexMesh(shape, lo, hi)
+    ref_s = run(smooth, False)
+    ref_r = run(rough, False)
+    mesh.close()
+    mesh = cgd.HexMesh(shape, lo, hi)
+    first = run(smooth, True)            # learns the budgets
+    again = run(smooth, True)            # within them
+    after = run(rough, True)             # beyond them (more iterations): the call is redone with read-backs
+    for got, ref in ((first, ref_s), (again, ref_s), (after, ref_r)):
+        assert np.array_equal(got[0].view(np.uint32), ref[0].view(np.uint32))
+        assert got[1] == ref[1] and got[2] == ref[2] == 0
+    print(f"iterations: smooth {ref_s[1]}, rough {ref_r[1]}", flush=True)
+    if precond == 1:  # plain CG: the rough input takes more iterations, so its call ran out of budget
+        assert sum(map(sum, ref_r[1])) > sum(map(sum, ref_s[1])) + steps
+
