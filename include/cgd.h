@@ -186,12 +186,14 @@ cgd_status cgd_locate(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, vo
  * sum can overflow, or with a scale S_f the caller forces, and summed in
  * int64: the sums are exact and independent of particle order (eq.
  * conserve holds exactly in the integers).  Then
- * field[f, k] = float32(acc * 2^-S_f / V_k).  On hex
- * meshes the particles are bucketed by tile of consecutive cells and each
- * tile is summed in LDS (the temporary buffers, 8 + 4 F bytes per
- * particle, come from the mesh workspace); with more than 8192 tiles or 2^32
- * particles, or CGD_DEPOSIT_DIRECT set in the environment, every particle is
- * added with a device-wide int64 atomic instead.  Both give the same bits.
+ * field[f, k] = float32(acc * 2^-S_f / V_k).  On hex meshes (and
+ * rectilinear ones of at most 4093 cells over the three axes) the particles
+ * are bucketed by tile of consecutive cells and each tile is summed in LDS
+ * (the temporary buffers, 12 bytes per particle at F = 1, 20 at F = 2 or 3
+ * and 20 + 4 (F - 3) above, come from the mesh workspace); with more than
+ * 8192 tiles or 2^32 particles, or CGD_DEPOSIT_DIRECT set in the
+ * environment, every particle is added with a device-wide int64 atomic
+ * instead.  Both give the same bits.
  *
  *  n:       number of particles (>= 0)
  *  pos:     device float32 [n, 3]
@@ -225,7 +227,8 @@ cgd_status cgd_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F,
  * other allocating routine.
  *  n, pos, F, values, field, acc, stream: as in cgd_deposit (acc nullable;
  *           no statistics, no forced scales; the call is asynchronous).
- *  Limits: the tiled deposit's scratch, (8 + 4 F) bytes per particle plus
+ *  Limits: the tiled deposit's scratch, 12 bytes per particle at F = 1
+ *           (20 at F = 2 or 3, 20 + 4 (F - 3) above) plus
  *           12 bytes per tile of 16384 / F cells, must fit 64 MiB - 4 KiB
  *           (about 5.5M particles at F = 1, 2.8M at F = 4), and the grid at
  *           most 8192 tiles; larger inputs return CGD_E_INVALID with the

@@ -158,8 +158,12 @@ struct TileArgs {
     uint32_t* counts;      // [n_snap * ntiles]: particles per tile
     uint32_t* offsets;     // [n_snap * ntiles + 1]
     uint32_t* cursor;      // [n_snap * ntiles]
-    uint2* rec;            // [total]: (cell within its tile, bits of field 0's value), tile-bucketed
-    float* rv;             // [F - 1][total]: values of fields 1.., tile-bucketed
+    // Tile-bucketed records [total]: F = 1: (cell within its tile, bits of
+    // field 0's value), 8 bytes; F >= 2: (cell, fields 0, 1, 2), 16 bytes
+    // (one scattered write per particle instead of one per field).
+    uint2* rec;
+    uint4* rec4;
+    float* rv;             // [F - 3][total]: values of fields 3.. (F >= 4), tile-bucketed
     uint32_t* maxbits;     // [n_snap][F]
     const int32_t* force_s;  // nullable: [F] scales forced by the caller
     unsigned long long* nf_val;  // snapshot j's non-finite values of field f counted at
@@ -380,7 +384,9 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scan(TileArgs a) {
 // Pass 3 (grid: blocks x snapshots): each block counts its chunk of
 // nsub * kTChunk particles per tile, reserves one range per tile, then
 // writes the particles' records there, a register pass of kTPer particles
-// per thread at a time.
+// per thread at a time (R16: 16-byte records, in two halves of the pass so
+// that the three values' registers fit).
+template <bool R16>
 __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
     __shared__ uint32_t hist[kMaxTiles];
     __shared__ uint32_t base[kMaxTiles];
@@ -416,35 +422,44 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
         hist[t] = 0u;  // reused as the in-block rank counter
     }
     __syncthreads();
-    for (int sub = 0; sub < npass; ++sub) {
-        const int64_t p0 = c0 + (int64_t)sub * (kTBlock * kTPer);
-        int32_t kk[kTPer];
-        float v0[kTPer];
+    constexpr int NP = R16 ? kTPer / 2 : kTPer;  // particles per thread in one write pass
+    for (int sub = 0; sub < npass * (kTPer / NP); ++sub) {
+        const int64_t p0 = c0 + (int64_t)sub * (kTBlock * NP);
+        int32_t kk[NP];
+        float v0[NP], v1[NP], v2[NP];
 #pragma unroll
-        for (int i = 0; i < kTPer; ++i) {
+        for (int i = 0; i < NP; ++i) {
             const int64_t p = p0 + (int64_t)i * kTBlock;
             kk[i] = p < ce ? a.cellbuf[p] : -1;
             v0[i] = p < ce ? a.values[p] : 0.f;
+            if constexpr (R16) {
+                v1[i] = p < ce ? a.values[(size_t)a.total + p] : 0.f;
+                v2[i] = (p < ce && a.F > 2) ? a.values[(size_t)2 * a.total + p] : 0.f;
+            }
         }
-        uint32_t slot[kTPer];
+        uint32_t slot[NP];
 #pragma unroll
-        for (int i = 0; i < kTPer; ++i) {
+        for (int i = 0; i < NP; ++i) {
             if (kk[i] < 0) continue;
             const int t = kk[i] >> a.cpt_log2;
             slot[i] = base[t] + atomicAdd(&hist[t], 1u);
-            a.rec[slot[i]] = make_uint2((uint32_t)(kk[i] & (a.cpt - 1)), __float_as_uint(v0[i]));
+            const uint32_t cl = (uint32_t)(kk[i] & (a.cpt - 1));
+            if constexpr (R16)
+                a.rec4[slot[i]] = make_uint4(cl, __float_as_uint(v0[i]), __float_as_uint(v1[i]), __float_as_uint(v2[i]));
+            else
+                a.rec[slot[i]] = make_uint2(cl, __float_as_uint(v0[i]));
         }
-        for (int f = 1; f < a.F; ++f) {
+        for (int f = 3; f < a.F; ++f) {
             const float* vf = a.values + (size_t)f * a.total;
-            float v[kTPer];
+            float v[NP];
 #pragma unroll
-            for (int i = 0; i < kTPer; ++i) {
+            for (int i = 0; i < NP; ++i) {
                 const int64_t p = p0 + (int64_t)i * kTBlock;
                 v[i] = p < ce ? vf[p] : 0.f;
             }
-            float* rvf = a.rv + (size_t)(f - 1) * a.total;
+            float* rvf = a.rv + (size_t)(f - 3) * a.total;
 #pragma unroll
-            for (int i = 0; i < kTPer; ++i)
+            for (int i = 0; i < NP; ++i)
                 if (kk[i] >= 0) rvf[slot[i]] = v[i];
         }
     }
@@ -457,6 +472,8 @@ __device__ inline long long quantise(float v, int S) {
 // Pass 4: one workgroup per tile (of all snapshots): exact int64 sums in LDS
 // of the quantised values rint(v 2^S_f), then the tile's
 // field = float32((acc 2^-S_f) / V) (and the accumulators when asked for).
+// R16: the records hold the cell and fields 0..2.
+template <bool R16>
 __global__ __launch_bounds__(kTBlock) void k_tile_accum(TileArgs a) {
     __shared__ unsigned long long lacc[kTileWords];
     __shared__ int S[CGD_MAX_FIELDS];
@@ -476,23 +493,36 @@ __global__ __launch_bounds__(kTBlock) void k_tile_accum(TileArgs a) {
     const int S0 = S[0];
     constexpr int U = 4;  // records per thread whose loads are in flight together
     for (uint32_t r = r0 + threadIdx.x; r < r1; r += U * kTBlock) {
-        uint2 e[U];
+        uint4 e[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t rr = r + u * kTBlock;
-            e[u] = rr < r1 ? a.rec[rr] : make_uint2(0u, 0u);
+            if constexpr (R16) {
+                e[u] = rr < r1 ? a.rec4[rr] : make_uint4(0u, 0u, 0u, 0u);
+            } else {
+                const uint2 e2 = rr < r1 ? a.rec[rr] : make_uint2(0u, 0u);
+                e[u] = make_uint4(e2.x, e2.y, 0u, 0u);
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const long long q = quantise(__uint_as_float(e[u].y), S0);
             if (q != 0) atomicAdd(&lacc[e[u].x], (unsigned long long)q);
+            if constexpr (R16) {
+                const long long q1 = quantise(__uint_as_float(e[u].z), S[1]);
+                if (q1 != 0) atomicAdd(&lacc[a.cpt + e[u].x], (unsigned long long)q1);
+                if (a.F > 2) {
+                    const long long q2 = quantise(__uint_as_float(e[u].w), S[2]);
+                    if (q2 != 0) atomicAdd(&lacc[2 * a.cpt + e[u].x], (unsigned long long)q2);
+                }
+            }
         }
-        for (int f = 1; f < a.F; ++f) {
+        for (int f = 3; f < a.F; ++f) {
             float v[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t rr = r + u * kTBlock;
-                v[u] = rr < r1 ? a.rv[(size_t)(f - 1) * a.total + rr] : 0.f;
+                v[u] = rr < r1 ? a.rv[(size_t)(f - 3) * a.total + rr] : 0.f;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -594,10 +624,15 @@ static bool tile_plan(int64_t cells, int64_t total, int32_t F, int* cpt, int* nt
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Record bytes per particle (8 at F = 1, 16 above) and the fields kept in
+// separate value arrays (3.. at F >= 4).
+static size_t rec_bytes(int F) { return F == 1 ? 8 : 16; }
+static size_t rv_fields(int F) { return F > 3 ? (size_t)(F - 3) : 0; }
+
 size_t tiled_deposit_temp_bytes(int64_t cells, int64_t total, int32_t n_snap, int32_t F) {
     int cpt, nt;
     if (!tile_plan(cells, total, F, &cpt, &nt)) return 0;
-    return al256(4 * (size_t)total) + al256(8 * (size_t)total) + al256(4 * (size_t)(F - 1) * total) +
+    return al256(4 * (size_t)total) + al256(rec_bytes(F) * total) + al256(4 * rv_fields(F) * total) +
            al256(4 * (3 * (size_t)n_snap * nt + 1));
 }
 
@@ -641,9 +676,10 @@ cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipS
     a.cellbuf = reinterpret_cast<int32_t*>(t);
     t += al256(4 * (size_t)d.total);
     a.rec = reinterpret_cast<uint2*>(t);
-    t += al256(8 * (size_t)d.total);
+    a.rec4 = reinterpret_cast<uint4*>(t);
+    t += al256(rec_bytes(d.F) * d.total);
     a.rv = reinterpret_cast<float*>(t);
-    t += al256(4 * (size_t)(d.F - 1) * d.total);
+    t += al256(4 * rv_fields(d.F) * d.total);
     const int all = d.n_snap * nt;
     a.counts = reinterpret_cast<uint32_t*>(t);
     a.offsets = a.counts + all;
@@ -668,8 +704,8 @@ cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipS
     // Timed as a whole (kind 2: 12 bytes of position and 12 per field and
     // particle, the direct path's count) and per stage (kinds 13..15, each
     // with the bytes it must move: binning reads positions and values and
-    // writes the host cell; the scatter reads cell and values and writes
-    // records of 8 + 4 (F - 1) bytes; the accumulation reads the records and
+    // writes the host cell; the scatter reads cell and values and writes the
+    // records and the values of fields 3..; the accumulation reads them and
     // writes the field, 4 bytes per cell and field).
     const double np_ = (double)d.total;
     int tm = timing ? timing_begin(timing, s) : -1;
@@ -679,13 +715,16 @@ cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipS
     if (timing) timing_end(timing, t13, 13, (12.0 + 4.0 * d.F + 4.0) * np_, s);
     int t14 = timing ? timing_begin(timing, s) : -1;
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kTBlock), 0, s, a);
-    hipLaunchKernelGGL(k_tile_scatter, dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
-    if (timing) timing_end(timing, t14, 14, (4.0 + 4.0 * d.F + 8.0 + 4.0 * (d.F - 1)) * np_, s);
+    if (d.F >= 2) hipLaunchKernelGGL(k_tile_scatter<true>, dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_tile_scatter<false>, dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    const double recb = (double)rec_bytes(d.F) + 4.0 * (double)rv_fields(d.F);  // bytes written per particle
+    if (timing) timing_end(timing, t14, 14, (4.0 + 4.0 * d.F + recb) * np_, s);
     int t15 = timing ? timing_begin(timing, s) : -1;
-    hipLaunchKernelGGL(k_tile_accum, dim3(all), dim3(kTBlock), 0, s, a);
+    if (d.F >= 2) hipLaunchKernelGGL(k_tile_accum<true>, dim3(all), dim3(kTBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_tile_accum<false>, dim3(all), dim3(kTBlock), 0, s, a);
     if (timing)
         timing_end(timing, t15, 15,
-                   (8.0 + 4.0 * (d.F - 1)) * np_ + (4.0 * d.F + (d.vcell ? 8.0 : 0.0)) * (double)m->cells * d.n_snap,
+                   recb * np_ + (4.0 * d.F + (d.vcell ? 8.0 : 0.0)) * (double)m->cells * d.n_snap,
                    s);
     if (timing) timing_end(timing, tm, 2, (12.0 + 12.0 * d.F) * np_, s);
     CGD_HIP_TRY(hipGetLastError());
