@@ -183,12 +183,6 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     const bool owner = w >= D && w < D + TY;  // an output row (written if yw < ny)
     const int li = w < D ? w : w - TY;        // loader index (non-owners)
 
-    auto row = [&](int j, int q, int e) -> float* {  // level j, plane q, extent row e
-        const int slot = j <= 1 ? (q + 12) % 3 : (q & 1);  // q >= -D - 1
-        return lds + (lds_level_base<D, TY>(j) + slot * (TY + 2 * (D - j)) + e) * NXR + x0;
-    };
-    auto row0 = [&](int q, int e) -> float* { return row(0, q, e); };
-    auto rowj = [&](int j, int q, int e) -> float* { return row(j, q, e); };
     auto ld = [](const float* r) {  // row starts are 16-byte aligned: one LDS access per row
         return ldv<VEC>(static_cast<const float*>(__builtin_assume_aligned(r, 4 * VEC)));
     };
@@ -202,7 +196,6 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     // loader i at step q + D - 1 (loaded one step earlier) and read by the
     // owner of the row at step q + D
     float* side_lds = lds + lds_level_base<D, TY>(D) * NXR;
-    auto side_row = [&](int q, int i) -> float* { return side_lds + ((q & 1) * TY + i) * NXR + x0; };
     const float* side = FORM == 2 ? side_field + xg : nullptr;
     const size_t side_y = (size_t)min(y0 + (li < TY ? li : 0), ny - 1) * nx;
     auto side_load = [&](int q) { return ldv<VEC>(side + (size_t)min(max(q, 0), nz - 1) * plane + side_y); };
@@ -210,6 +203,15 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     const int t0 = (per & 4) ? zb - D : max(0, zb - D);
     const int tl = (per & 4) ? ze + D - 1 : min(nz, ze + D) - 1;  // last plane of r needed
     const int t1 = ze - 1 + D;           // last step (plane ze - 1 of z completes)
+    // LDS slot of level j's plane q: (q - t0) mod 3 for levels 0 and 1, mod 2
+    // above.  Relative to the chunk's first plane t0, so that in the step
+    // loop (t = t0 + 6 k + S) every slot is a compile-time constant
+    // (rowk in step), with no index arithmetic per access.
+    auto row = [&](int j, int q, int e) -> float* {  // level j, plane q, extent row e
+        const int slot = j <= 1 ? (q - t0 + 12) % 3 : ((q - t0 + 12) & 1);  // q >= t0 - D - 1
+        return lds + (lds_level_base<D, TY>(j) + slot * (TY + 2 * (D - j)) + e) * NXR + x0;
+    };
+    auto row0 = [&](int q, int e) -> float* { return row(0, q, e); };
     (void)g;
     // RECT: this lane's x factors and this wave's row factors, for every
     // level, and the plane table (planes t0 .. tl: face weights below and
@@ -283,10 +285,20 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
     auto step = [&](auto S_, auto LOADER_, int t, Vec<VEC> (&pf)[P][RPL], Vec<VEC>& sr) {
         constexpr int S = decltype(S_)::value;
         constexpr bool LOADER = decltype(LOADER_)::value;
+        // level j's row e at plane t + k, and the side slot of plane t + k:
+        // t - t0 is S mod 6, so the slots fold to constants once the level
+        // loop is unrolled
+        auto rowk = [&](int j, int k, int e) -> float* {
+            const int slot = j <= 1 ? (S + k + 12) % 3 : ((S + k + 12) & 1);
+            return lds + (lds_level_base<D, TY>(j) + slot * (TY + 2 * (D - j)) + e) * NXR + x0;
+        };
+        auto side_rowk = [&](int k, int i) -> float* {
+            return side_lds + (((S + k + 12) & 1) * TY + i) * NXR + x0;
+        };
         if constexpr (LOADER && FORM == 2) {
             // side channel: output row li of r at plane t + 1 - D (in flight
             // since the previous step) into LDS, then the load of the next plane
-            if (li < TY) stv<VEC>(side_row(t + 1 - D, li), sr);
+            if (li < TY) stv<VEC>(side_rowk(1 - D, li), sr);
             sr = side_load(t + 2 - D);
         }
         if constexpr (LOADER) {
@@ -298,7 +310,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 const int e = li + NL * i;
                 if (e < E0) {
                     scale_in(pf[B][i], e, i, t + 1, false);
-                    stv<VEC>(row0(t + 1, e), pf[B][i]);
+                    stv<VEC>(rowk(0, 1, e), pf[B][i]);
                 }
             }
             const int tn = min(t + 1 + P, tl);
@@ -308,7 +320,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 pf[B][i] = ldv<VEC>(src + (size_t)wrapz(tn) * plane + ysrc(e));
             }
         }
-        if (w < E0) rk[S % RK] = ld(row0(t, w));  // own row of r at plane t (written at step t - 1)
+        if (w < E0) rk[S % RK] = ld(rowk(0, 0, w));  // own row of r at plane t (written at step t - 1)
 
         // Level j's rows y - 1 and y + 1 (level j - 1 at plane t - j, this
         // row itself at a wall) and level 2's planes q, q - 1 of level 1 were
@@ -324,9 +336,8 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
             return in_dom && j <= w && w < E0 - j && q >= max(0, zb - (D - j)) && q < min(nz, ze + (D - j));
         };
         auto ys_rows = [&](int j, Vec<VEC>& yd, Vec<VEC>& yu) {
-            const int q = t - j;
-            yd = ld(row(j - 1, q, has_yd ? w - j : w - j + 1));
-            yu = ld(row(j - 1, q, has_yu ? w - j + 2 : w - j + 1));
+            yd = ld(rowk(j - 1, -j, has_yd ? w - j : w - j + 1));
+            yu = ld(rowk(j - 1, -j, has_yu ? w - j + 2 : w - j + 1));
         };
         Vec<VEC> yd, yu, c2, zl2;
         if (PF && go_of(1)) ys_rows(1, yd, yu);
@@ -338,16 +349,16 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
             if (PF && j < D && go_of(j + 1)) {
                 ys_rows(j + 1, ydn, yun);
                 if (j == 1) {
-                    c2 = ld(row(1, t - 2, w - 1));
-                    zl2 = ld(row(1, (t - 2 > 0 || (per & 4)) ? t - 3 : t - 2, w - 1));
+                    c2 = ld(rowk(1, -2, w - 1));
+                    zl2 = ld((t - 2 > 0 || (per & 4)) ? rowk(1, -3, w - 1) : rowk(1, -2, w - 1));
                 }
             }
             if (!PF && go) {
                 // the same reads, issued just before their use
                 ys_rows(j, yd, yu);
                 if (j == 2) {
-                    c2 = ld(row(1, q, w - 1));
-                    zl2 = ld(row(1, (q > 0 || (per & 4)) ? q - 1 : q, w - 1));
+                    c2 = ld(rowk(1, -j, w - 1));
+                    zl2 = ld((q > 0 || (per & 4)) ? rowk(1, -j - 1, w - 1) : rowk(1, -j, w - 1));
                 }
             }
             if (go) {
@@ -453,7 +464,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) acc1 = fma((double)c.f[e], (double)c.f[e], acc1);
                 }
-                if (j < D) stv<VEC>(rowj(j, q, w - j), u);
+                if (j < D) stv<VEC>(rowk(j, -j, w - j), u);
                 // levels >= 2 keep their planes in a register ring; a slot
                 // not written here keeps an older, finite plane that is only
                 // ever read with a zero coefficient (beyond a wall)
@@ -468,7 +479,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                     }
                     stv<VEC>(dst_field + xg + (size_t)q * plane + (size_t)yw * nx, us);
                     if constexpr (FORM == 2) {
-                        const Vec<VEC> rr = ld(side_row(q, w - D));
+                        const Vec<VEC> rr = ld(side_rowk(-j, w - D));
 #pragma unroll
                         for (int e = 0; e < VEC; ++e) acc0 = fma((double)rr.f[e], (double)us.f[e], acc0);
                     }
