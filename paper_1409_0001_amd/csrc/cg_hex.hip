@@ -240,7 +240,7 @@ __device__ inline double block_sum_nt(const double* p, int n, double* sh) {
 // t - 1 from its own planes t - 2 .. t, the rows above and below from LDS
 // and the x-neighbours by DPP shifts.  Rows and planes beyond a wall take the
 // cell itself.
-template <int VEC, int NW, bool B0>
+template <int VEC, int NW, bool B0, bool PART = false>
 __global__ __launch_bounds__(NW * 64) void k_dir_lds(SweepArgs a) {
     constexpr int NT = NW * 64;
     constexpr int NXR = 64 * VEC;
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(NW * 64) void k_dir_lds(SweepArgs a) {
             }
             float lft, rgt;
             x_neighbours<VEC>(c, lft, rgt);
-            if (nx != NXR) rgt = x0 + VEC >= nx ? c.f[VEC - 1] : rgt;
+            if constexpr (PART) rgt = x0 + VEC >= nx ? c.f[VEC - 1] : rgt;  // a row shorter than the wave
             const bool hzd = q > 0, hzu = q + 1 < nz;
             const float czd = hzd ? cz : 0.f, czu = hzu ? cz : 0.f;
             const float dq = d_in - (hzd ? 0.f : cz) - (hzu ? 0.f : cz);
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(NW * 64) void k_dir_lds(SweepArgs a) {
 // the passes of the product form: the first (r -> src of the next pass) has
 // the convergence test and b.b, the middle ones neither, the last (-> z) the
 // r.z partials.
-template <int VEC, int D, int TY, int NW, bool FIRST, int FORM, bool RECT>
+template <int VEC, int D, int TY, int NW, bool FIRST, int FORM, bool RECT, bool PART>
 __device__ __forceinline__ void precond_block(const SweepArgs& a, const Geom& g, const PrecondCoef& pc,
                                               const float* src, float* dst) {
     constexpr int NT = NW * 64;
@@ -430,7 +430,7 @@ __device__ __forceinline__ void precond_block(const SweepArgs& a, const Geom& g,
     constexpr int TF = FORM == 3 ? 1 : FORM;  // a middle pass is a first pass without the partials
     // RECT: S on the input of the first pass and on the output of the last
     constexpr bool SIN = RECT && (FORM == 0 || FORM == 1), SOUT = RECT && (FORM == 0 || FORM == 2);
-    precond_lds_tile<VEC, D, TY, NW, FIRST && (FORM == 0 || FORM == 1), false, TF, RECT, SIN, SOUT>(
+    precond_lds_tile<VEC, D, TY, NW, FIRST && (FORM == 0 || FORM == 1), false, TF, RECT, SIN, SOUT, PART>(
         lds, src + fo, dst + fo, g, pc, a.ny, a.nz, yg * TY, zb, min(zb + a.zc, a.nz), acc0, acc1, rsrc + fo);
     if constexpr (FORM == 3) return;
 
@@ -467,22 +467,22 @@ __device__ __forceinline__ void precond_block(const SweepArgs& a, const Geom& g,
 // 3,455 with the last pass too once its loaders keep one plane in flight
 // instead of two (5 registers spilled; with two planes it spilled 15 and
 // the launch fell to 3,168).  The first iteration's first pass would spill.
-template <int VEC, int D, int TY, int NW, bool FIRST, int FORM = 0>
+template <int VEC, int D, int TY, int NW, bool FIRST, int FORM = 0, bool PART = false>
 __global__ __launch_bounds__(NW * 64, (VEC <= 2 && (FORM == 3 || FORM == 2 || (FORM == 1 && !FIRST))) ? 8 : 1) void k_precond_lds(SweepArgs a) {
     const float* rsrc = FIRST ? a.p.B : a.p.R;
     const float* src = FORM == 2 ? a.p.V : (FORM == 3 ? a.p.U : rsrc);
     float* dst = FORM == 1 ? a.p.U : (FORM == 3 ? a.p.V : a.p.Z);
-    precond_block<VEC, D, TY, NW, FIRST, FORM, false>(a, a.g, FORM == 2 ? a.pc2 : (FORM == 3 ? a.pcm : a.pc), src,
-                                                      dst);
+    precond_block<VEC, D, TY, NW, FIRST, FORM, false, PART>(a, a.g, FORM == 2 ? a.pc2 : (FORM == 3 ? a.pcm : a.pc),
+                                                            src, dst);
 }
 
 // Rectilinear grids: one pass of D = 2 levels of the polynomial in S A S
 // (per-axis factors in gp) with its own coefficients and buffers (the Horner
 // pass of degree 2, or one quadratic factor of the product form).
-template <int VEC, bool FIRST, int FORM>
+template <int VEC, bool FIRST, int FORM, bool PART>
 __global__ __launch_bounds__(16 * 64) void k_precond_rect(SweepArgs a, Geom gp, PrecondCoef pc, const float* src,
                                                           float* dst) {
-    precond_block<VEC, 2, 8, 16, FIRST, FORM, true>(a, gp, pc, src, dst);
+    precond_block<VEC, 2, 8, 16, FIRST, FORM, true, PART>(a, gp, pc, src, dst);
 }
 
 // x0 paths: a field whose right-hand side is zero has solution zero.
@@ -664,16 +664,24 @@ constexpr int lds_precond_bytes(int vec, int deg) {
            64 * vec * 4;
 }
 
-template <int VEC, bool FIRST>
-void launch_precond_rect_v(int form, const Plan& q, const SweepArgs& a, const Geom& gp, const PrecondCoef& pc,
+template <int VEC, bool FIRST, bool PART>
+void launch_precond_rect_p(int form, const Plan& q, const SweepArgs& a, const Geom& gp, const PrecondCoef& pc,
                            const float* src, float* dst, hipStream_t s) {
     const dim3 grid(q.nblocks), block(kLdsNW * 64);
     switch (form) {
-        case 0: hipLaunchKernelGGL((k_precond_rect<VEC, FIRST, 0>), grid, block, 0, s, a, gp, pc, src, dst); break;
-        case 1: hipLaunchKernelGGL((k_precond_rect<VEC, FIRST, 1>), grid, block, 0, s, a, gp, pc, src, dst); break;
-        case 2: hipLaunchKernelGGL((k_precond_rect<VEC, FIRST, 2>), grid, block, 0, s, a, gp, pc, src, dst); break;
-        default: hipLaunchKernelGGL((k_precond_rect<VEC, FIRST, 3>), grid, block, 0, s, a, gp, pc, src, dst); break;
+        case 0: hipLaunchKernelGGL((k_precond_rect<VEC, FIRST, 0, PART>), grid, block, 0, s, a, gp, pc, src, dst); break;
+        case 1: hipLaunchKernelGGL((k_precond_rect<VEC, FIRST, 1, PART>), grid, block, 0, s, a, gp, pc, src, dst); break;
+        case 2: hipLaunchKernelGGL((k_precond_rect<VEC, FIRST, 2, PART>), grid, block, 0, s, a, gp, pc, src, dst); break;
+        default: hipLaunchKernelGGL((k_precond_rect<VEC, FIRST, 3, PART>), grid, block, 0, s, a, gp, pc, src, dst); break;
     }
+}
+
+// PART: rows shorter than the wave's 64 VEC cells
+template <int VEC, bool FIRST>
+void launch_precond_rect_v(int form, const Plan& q, const SweepArgs& a, const Geom& gp, const PrecondCoef& pc,
+                           const float* src, float* dst, hipStream_t s) {
+    if (a.nx != 64 * VEC) launch_precond_rect_p<VEC, FIRST, true>(form, q, a, gp, pc, src, dst, s);
+    else launch_precond_rect_p<VEC, FIRST, false>(form, q, a, gp, pc, src, dst, s);
 }
 
 // One pass of the rectilinear preconditioner (FORM 0: the degree-2 Horner
@@ -692,19 +700,21 @@ void launch_precond_rect(int vec, bool first, int form, const Plan& q, const Swe
     }
 }
 
+template <int VEC, int D, int FORM>
+void launch_precond_lds_v(bool first, const Plan& q, const SweepArgs& a, hipStream_t s) {
+    const dim3 grid(q.nblocks), block(kLdsNW * 64);
+    const bool part = a.nx != 64 * VEC;  // rows shorter than the wave covers
+    if (first && part) hipLaunchKernelGGL((k_precond_lds<VEC, D, kLdsTY, kLdsNW, true, FORM, true>), grid, block, 0, s, a);
+    else if (first) hipLaunchKernelGGL((k_precond_lds<VEC, D, kLdsTY, kLdsNW, true, FORM, false>), grid, block, 0, s, a);
+    else if (part) hipLaunchKernelGGL((k_precond_lds<VEC, D, kLdsTY, kLdsNW, false, FORM, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_precond_lds<VEC, D, kLdsTY, kLdsNW, false, FORM, false>), grid, block, 0, s, a);
+}
+
 template <int D, int FORM>
 void launch_precond_lds_d(int vec, bool first, const Plan& q, const SweepArgs& a, hipStream_t s) {
-    const dim3 grid(q.nblocks), block(kLdsNW * 64);
-    if (vec == 4) {
-        if (first) hipLaunchKernelGGL((k_precond_lds<4, D, kLdsTY, kLdsNW, true, FORM>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_precond_lds<4, D, kLdsTY, kLdsNW, false, FORM>), grid, block, 0, s, a);
-    } else if (vec == 2) {
-        if (first) hipLaunchKernelGGL((k_precond_lds<2, D, kLdsTY, kLdsNW, true, FORM>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_precond_lds<2, D, kLdsTY, kLdsNW, false, FORM>), grid, block, 0, s, a);
-    } else {
-        if (first) hipLaunchKernelGGL((k_precond_lds<1, D, kLdsTY, kLdsNW, true, FORM>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_precond_lds<1, D, kLdsTY, kLdsNW, false, FORM>), grid, block, 0, s, a);
-    }
+    if (vec == 4) launch_precond_lds_v<4, D, FORM>(first, q, a, s);
+    else if (vec == 2) launch_precond_lds_v<2, D, FORM>(first, q, a, s);
+    else launch_precond_lds_v<1, D, FORM>(first, q, a, s);
 }
 
 // Degree 3 or 4: one Horner pass; degree 8: two product passes (r -> U,
@@ -808,19 +818,21 @@ Plan lds_plan(const HexGeom& g, int F, int vec, int deg, int zc_force, int* zc_r
     return p;
 }
 
+template <int VEC, int NW>
+void launch_dir_lds_v(bool b0, const Plan& q, const SweepArgs& a, hipStream_t s) {
+    const dim3 grid(q.nblocks), block(NW * 64);
+    const bool part = a.nx != 64 * VEC;  // rows shorter than the wave covers
+    if (b0 && part) hipLaunchKernelGGL((k_dir_lds<VEC, NW, true, true>), grid, block, 0, s, a);
+    else if (b0) hipLaunchKernelGGL((k_dir_lds<VEC, NW, true, false>), grid, block, 0, s, a);
+    else if (part) hipLaunchKernelGGL((k_dir_lds<VEC, NW, false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_dir_lds<VEC, NW, false, false>), grid, block, 0, s, a);
+}
+
 template <int NW>
 void launch_dir_lds_nw(int vec, bool b0, const Plan& q, const SweepArgs& a, hipStream_t s) {
-    const dim3 grid(q.nblocks), block(NW * 64);
-    if (vec == 4) {
-        if (b0) hipLaunchKernelGGL((k_dir_lds<4, NW, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_dir_lds<4, NW, false>), grid, block, 0, s, a);
-    } else if (vec == 2) {
-        if (b0) hipLaunchKernelGGL((k_dir_lds<2, NW, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_dir_lds<2, NW, false>), grid, block, 0, s, a);
-    } else {
-        if (b0) hipLaunchKernelGGL((k_dir_lds<1, NW, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_dir_lds<1, NW, false>), grid, block, 0, s, a);
-    }
+    if (vec == 4) launch_dir_lds_v<4, NW>(b0, q, a, s);
+    else if (vec == 2) launch_dir_lds_v<2, NW>(b0, q, a, s);
+    else launch_dir_lds_v<1, NW>(b0, q, a, s);
 }
 
 void launch_dir_lds(int nw, int vec, bool b0, const Plan& q, const SweepArgs& a, hipStream_t s) {

@@ -139,13 +139,15 @@ __host__ __device__ constexpr int precond_lds_floats() {
 // acc1 = v.v when FIRST (v = b), FORM 2 adds acc0 = r.dst with r read from
 // side_field (the loaders feed the output rows of r through LDS).  RECT: the
 // rectilinear operator of Geom (per-cell coefficients from per-axis
-// factors; walls have zero face weights) with the levels' gg, gs.  SIN /
+// factors; walls have zero face weights) with the levels' gg, gs.  PART:
+// the row is shorter than the wave's 64 VEC cells (the last real lane takes
+// the wall).  SIN /
 // SOUT (RECT): the input is multiplied by the scaling S (Geom::rsg) as it
 // enters LDS / the output by S before it is stored, so that the passes
 // apply S p(A) S; FIRST then takes b.b from the loaders' unscaled rows, and
 // FORM 0's r.z is (S r).p(A)(S r).
 template <int VEC, int D, int TY, int NW, bool FIRST, bool PF = false, int FORM = 0, bool RECT = false,
-          bool SIN = false, bool SOUT = false>
+          bool SIN = false, bool SOUT = false, bool PART = false>
 __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __restrict__ src_field,
                                         float* __restrict__ dst_field, const Geom& g, const PrecondCoef& pc, int ny, int nz,
                                         int y0, int zb, int ze, double& acc0, double& acc1,
@@ -392,7 +394,7 @@ __device__ inline void precond_lds_tile(float* __restrict__ lds, const float* __
                 for (int e = 0; e < VEC; ++e) ys.f[e] += yu.f[e];
                 float lft, rgt;
                 x_neighbours<VEC>(c, lft, rgt);
-                if (nx != NXR) rgt = x0 + VEC >= nx ? c.f[VEC - 1] : rgt;  // the row's last cell: wall
+                if constexpr (PART) rgt = x0 + VEC >= nx ? c.f[VEC - 1] : rgt;  // the row's last cell: wall
                 if (per & 1) {
                     // periodic x: the row's end cells are neighbours
                     const float last =
