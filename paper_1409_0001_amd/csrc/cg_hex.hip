@@ -1138,15 +1138,17 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, co
     }
 
     // Preconditioned CG where one wave covers an x-row: the direction sweep
-    // shares its rows through LDS (k_dir_lds, 8 waves: 6 rows per block).  On
-    // the 256 x 256 x 512 grid it takes 90 us against 98.5 for the register
-    // sweep; at 128^3 both take 11.5 us.  CGD_HEX_DIR (0: the register sweep),
-    // CGD_HEX_DIR_NW (8 or 16 waves) and CGD_HEX_DIR_ZC override.
+    // shares its rows through LDS (k_dir_lds, 16 waves: 14 rows per block, so
+    // the two halo rows cost 1/7 of a row per output row in L2 reads).  On
+    // the 256 x 256 x 512 grid it takes 82 us against 84.5 with 8 waves and
+    // 98.5 for the register sweep; at 128^3 both LDS widths are within 1 %.
+    // CGD_HEX_DIR (0: the register sweep), CGD_HEX_DIR_NW (8 or 16 waves)
+    // and CGD_HEX_DIR_ZC override.
     int dir_nw = 0;
     if (pcg && row_wave && !ro) {
-        dir_nw = 8;
+        dir_nw = 16;
         int zc_force = 0;
-        if (const char* e = getenv("CGD_HEX_DIR")) dir_nw = atoi(e) ? 8 : 0;
+        if (const char* e = getenv("CGD_HEX_DIR")) dir_nw = atoi(e) ? 16 : 0;
         if (const char* e = getenv("CGD_HEX_DIR_NW")) dir_nw = dir_nw ? (atoi(e) == 16 ? 16 : 8) : 0;
         if (const char* e = getenv("CGD_HEX_DIR_ZC")) zc_force = atoi(e);
         if (dir_nw) {
