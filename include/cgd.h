@@ -97,11 +97,11 @@ cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz,
  * D(i,j,k) = Dx(i) Dy(j) Dz(k) (checked to 1e-6 relative at creation; NULL
  * counts) the operator is kept as per-axis factor arrays and applied by
  * stencil sweeps, with a Chebyshev polynomial preconditioner on a scaled
- * operator where one wave covers an x-row (nx of 64, 128 or 256), Jacobi
- * elsewhere; a periodic x axis there also needs the row in one segment of
- * waves (nx <= 64, or 128 / 256 with 8 / 16-byte aligned fields).  Otherwise
+ * operator where one wave covers an x-row (nx <= 256), Jacobi on wider rows;
+ * a periodic x axis there also needs the row in one segment of waves
+ * (nx <= 64, or up to 128 / 256 with 8 / 16-byte aligned fields).  Otherwise
  * the operator is stored like the tet operator with six face slots per row
- * and solved by Jacobi-preconditioned CG.  periodic: bit a set makes axis a
+ * and solved by CG with the tet path's polynomial preconditioner.  periodic: bit a set makes axis a
  * (0 x, 1 y, 2 z) periodic (Section 3.1): its first and last cells share a
  * face at distance (h_first + h_last) / 2 instead of two walls (no effect on
  * an axis of one cell); binning is unchanged.  nx * ny * nz < 2^28, else
@@ -137,9 +137,14 @@ typedef struct {
                              quadratic factors each), the one with the least work predicted
                              from the Chebyshev bound on the iteration count, where one
                              wavefront covers an x-row (nx = 64, 128 or 256) and the grid
-                             fills the machine, else degree 2 or 1; 1 plain CG.  Tet and
-                             rectilinear meshes use Jacobi either way.  The stopping rule is
-                             the same for all. */
+                             fills the machine, else degree 2 or 1; 1 plain CG.  Tet meshes
+                             and the face-slot rows of rectilinear meshes: 0 CG
+                             preconditioned by the Chebyshev polynomial of even degree
+                             0..16 (0: Jacobi) of the Jacobi-scaled operator with the least
+                             predicted work, on the spectrum estimate [sum V / sum diag,
+                             1 + t / (1 + t)], t = dtau max K_ii / V_i (face coefficients
+                             rounded to float16 in the preconditioner only); 1 Jacobi.  The
+                             stopping rule is the same for all. */
     cgd_unet model;       /* x0_mode 3: a network created for this mesh's grid, else NULL */
     int32_t scheme;       /* pseudo-time integrator (Section 5.1): 0 (default) backward Euler,
                              each step solving (M + dtau K) e^{n+1} = M e^n; 1 Crank-Nicolson,
@@ -245,8 +250,8 @@ cgd_status cgd_deposit_noalloc(cgd_mesh m, int64_t n, const float* pos, int32_t 
  * T = bandwidth^2 / 4, dtau = T / n_steps; each of the n_steps backward-Euler
  * steps solves (M + dtau K) e^{n+1} = M e^n by conjugate gradients with float32
  * vectors and float64 inner products (hex: matrix-free 7-point stencil with a
- * polynomial preconditioner, see cgd_solver_opts.precond; tet: Jacobi
- * preconditioning, A p from the face slots in flux form).  Zero-flux walls: wall faces carry
+ * polynomial preconditioner, see cgd_solver_opts.precond; tet: A p from the face
+ * slots in flux form, a polynomial of the Jacobi-scaled operator as preconditioner).  Zero-flux walls: wall faces carry
  * no flux.  Fields are independent solves (Section 3.2.1: each component is
  * diffused on its own).
  *
@@ -426,8 +431,8 @@ cgd_status cgd_conv3_wgrad(int32_t nx, int32_t ny, int32_t nz, int32_t ci, int32
  *   1  CG sweep 2 (x += alpha p, r -= alpha A p, r.r), hex stencil
  *   2  whole deposit: centroid binning, bucketing and fixed-point sums
  *      (all kernels of a call; kinds 13..15 split the tiled hex path)
- *   3  matrix sweep of the Jacobi-PCG on face slots (p, A p, p.Ap)
- *   4  update sweep of the Jacobi-PCG (x, r, r.z, r.r)
+ *   3  matrix sweep of the CG on face slots (p, A p, p.Ap)
+ *   4  update sweep of the CG on face slots (x, r, z = D^-1 r or v = H r, r.r)
  *   5  hex preconditioning, degree-4 Horner pass or first product pass
  *      (r -> U), degree 1 / 2 register sweep
  *   6  hex preconditioning, middle product pass (U -> V, degree 12)
@@ -440,9 +445,12 @@ cgd_status cgd_conv3_wgrad(int32_t nx, int32_t ny, int32_t nz, int32_t ci, int32
  *  13  tiled hex deposit: binning and tile counts
  *  14  tiled hex deposit: prefix sum and scatter of records into tiles
  *  15  tiled hex deposit: fixed-point sums in LDS and the finished field
+ *  16  tet / face-slot polynomial preconditioning, pass w = B v
+ *  17  tet / face-slot polynomial preconditioning, pass v = g (B w + s w + q v)
+ *      (the last pass of each application also sums r.z)
  * bytes_per_launch is the algorithmic byte count of the last timed launch of
  * that kind (what the method must move, not what the hardware moved). */
-#define CGD_TIMING_KINDS 16
+#define CGD_TIMING_KINDS 18
 typedef struct {
     int64_t launches[CGD_TIMING_KINDS];
     double  total_ms[CGD_TIMING_KINDS];

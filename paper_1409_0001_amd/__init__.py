@@ -343,7 +343,8 @@ TIMING_KINDS = {0: "cg_sweep1", 1: "cg_sweep2", 2: "deposit", 3: "pcg_spmv_sweep
                 5: "cg_precond_pass1", 6: "cg_precond_pass_mid", 7: "cg_precond_pass_last",
                 8: "cg_first_sweep1", 9: "cg_first_sweep2", 10: "cg_first_precond_pass1",
                 11: "cg_first_precond_pass_mid", 12: "cg_first_precond_pass_last",
-                13: "deposit_bin", 14: "deposit_scatter", 15: "deposit_accum"}
+                13: "deposit_bin", 14: "deposit_scatter", 15: "deposit_accum",
+                16: "pcg_poly_pass_bv", 17: "pcg_poly_pass_factor"}
 
 
 def timing_enable(mesh: Mesh, on: bool = True):

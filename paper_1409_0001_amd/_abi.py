@@ -41,7 +41,7 @@ class SolveStats(ctypes.Structure):
                 ("status", ctypes.c_int32), ("n_fallback", ctypes.c_int32)]
 
 
-TIMING_KINDS = 16
+TIMING_KINDS = 18
 
 
 class KernelTiming(ctypes.Structure):

@@ -1,7 +1,8 @@
 // Unstructured tetrahedral meshes: centroid location + fixed-point deposit
 // (Section 2.2 on arbitrary cells) and backward-Euler diffusion with the
-// two-point-flux finite-volume Laplacian by Jacobi-preconditioned CG over a
-// sparse operator with rows padded to a tet's four face slots (Sections 2.1
+// two-point-flux finite-volume Laplacian by CG over a sparse operator with
+// rows padded to a tet's four face slots, preconditioned by a Chebyshev
+// polynomial of the Jacobi-scaled operator (or Jacobi alone) (Sections 2.1
 // item 4, 4.3, 5.1).
 //
 // Point location: a tet contains the point when, for each face, the float64
@@ -20,7 +21,9 @@
 // Crank-Nicolson (Section 5.1): the same solve with dtau / 2, then x = 2 x - e.
 //
 // Diffusion step: (M + dtau K) x = M e with M = diag(V), K the two-point-flux
-// Laplacian; Jacobi-preconditioned CG, D = diag(M + dtau K).  A p is
+// Laplacian; CG with z = D^-1 r (Jacobi, D = diag(M + dtau K)) or z = p(B) H r
+// (the polynomial preconditioner below: sweep 2 then writes v = H r to z and
+// the passes turn it into z).  A p is
 // evaluated in flux form, (A p)_i = V_i p_i + dtau sum_f a_f (p_i - p_j), from
 // the four face slots of row i (one 16-byte load of neighbour ids, one of
 // a_f): each face's flux enters its two rows with opposite signs, so A keeps
@@ -242,7 +245,9 @@ struct TetArgs {
     int k;
 };
 
-template <int MODE, int NS>
+// POLY (first iteration only): z_0 was formed by the polynomial passes, which
+// also wrote r_0 = M e, b.b and r.z; the sweep reads z_0 from Z.
+template <int MODE, int NS, bool POLY = false>
 __global__ __launch_bounds__(kBlock) void k_tet_sweep(TetArgs a) {
     int b = blockIdx.x;
     if ((a.nblocks & 7) == 0) b = (b & 7) * (a.nblocks >> 3) + (b >> 3);
@@ -290,7 +295,8 @@ __global__ __launch_bounds__(kBlock) void k_tet_sweep(TetArgs a) {
     if constexpr (MODE == T1_FIRST || MODE == T1) {
         // p at a row: z = D^-1 M e on the first iteration, else z + beta p_old
         auto pval = [&](int j) -> float {
-            if constexpr (MODE == T1_FIRST) return a.dinv[j] * (a.volf[j] * a.B[fo + j]);
+            if constexpr (MODE == T1_FIRST && POLY) return a.Z[fo + j];
+            else if constexpr (MODE == T1_FIRST) return a.dinv[j] * (a.volf[j] * a.B[fo + j]);
             else return fmaf(beta, a.Pold[fo + j], a.Z[fo + j]);
         };
         for (int chunk = blk; chunk < a.nchunks; chunk += a.bpf) {
@@ -315,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_sweep(TetArgs a) {
             a.Pnew[fo + i] = pi;
             a.Q[fo + i] = q;
             acc0 = fma((double)pi, (double)q, acc0);
-            if constexpr (MODE == T1_FIRST) {
+            if constexpr (MODE == T1_FIRST && !POLY) {
                 const float r = a.volf[i] * a.B[fo + i];
                 a.R[fo + i] = r;
                 acc1 = fma((double)r, (double)pi, acc1);  // r.z with z = p
@@ -340,12 +346,12 @@ __global__ __launch_bounds__(kBlock) void k_tet_sweep(TetArgs a) {
     }
     const double t0 = block_reduce_fixed(acc0, sh);
     const double t1 = block_reduce_fixed(acc1, sh);
-    const double t2 = (MODE == T1_FIRST) ? block_reduce_fixed(acc2, sh) : 0.0;
+    const double t2 = (MODE == T1_FIRST && !POLY) ? block_reduce_fixed(acc2, sh) : 0.0;
     if (threadIdx.x == 0) {
         if constexpr (MODE == T1_FIRST || MODE == T1) {
             double* p1 = a.P1 + (size_t)f * 3 * a.bpf;
             p1[blk] = t0;
-            if (MODE == T1_FIRST) {
+            if (MODE == T1_FIRST && !POLY) {
                 p1[a.bpf + blk] = t1;
                 p1[2 * a.bpf + blk] = t2;
             }
@@ -360,6 +366,112 @@ __global__ __launch_bounds__(kBlock) void k_tet_sweep(TetArgs a) {
 __global__ void k_tet_dinv(const float* volf, const float* kdiag, float dtau, float* dinv, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         dinv[i] = (float)(1.0 / ((double)volf[i] + (double)dtau * (double)kdiag[i]));
+}
+
+// ------------------------------------------------ polynomial preconditioner
+//
+// z = p(B) h r with B = H A~, A~ = M + dtau K~ and H = diag(A~)^-1, where K~
+// is K with its face coefficients rounded to float16 after division by their
+// maximum (symmetric: both rows of a face hold the same rounding), so that
+// p(B) H = H^1/2 p(H^1/2 A~ H^1/2) H^1/2 is symmetric.  p is the Chebyshev
+// polynomial of even degree m that makes 1 - l p(l) smallest on [lmin, lmax]
+// (the spectrum estimate of B, chosen per step), evaluated as a product of
+// m / 2 quadratic factors g_k (B^2 + s_k B + q_k), each in two passes:
+//   pass 1: w = B v                 (v gathered at the face neighbours)
+//   pass 2: v = g_k ((1 + s_k) w - h kappa sum_f a~_f w_j + q_k v)
+// with (B v)_i = v_i - h_i kappa sum_f a~_f v_j, kappa = dtau amax.  The last
+// pass 2 carries the leading coefficient and sums r.z.  For even m the
+// residual polynomial 1 - l p(l) is below 1 for every l > 0, so p > 0 on any
+// positive spectrum: a poor estimate costs iterations, never definiteness.
+
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+struct ChebArgs {
+    const int4* col;
+    const int2* col2;
+    const f16x4* kh;
+    const f16x2* kh2;
+    const float* h;       // 1 / (V + kappa sum a~)
+    const float* R;       // r (last pass: r.z)
+    const float* G;       // gathered input: v (pass 1) or w (pass 2)
+    const float* V;       // pass 2: the factor's input v (own row)
+    float* out;
+    double* part;         // last pass: r.z partial of block blk of field f at part[f * pstride + blk]
+    size_t pstride;
+    CgCtl c;
+    float kappa, c1, cq, gk;
+    int n, bpf, nblocks, nchunks;
+};
+
+template <int NS, int STAGE>  // STAGE 0: pass 1; 1: pass 2; 2: the last pass 2
+__global__ __launch_bounds__(kBlock) void k_tet_cheb(ChebArgs a) {
+    int b = blockIdx.x;
+    if ((a.nblocks & 7) == 0) b = (b & 7) * (a.nblocks >> 3) + (b >> 3);
+    const int f = b / a.bpf;
+    const int blk = b - f * a.bpf;
+    if (a.c.st[f].done) return;
+    const size_t fo = (size_t)f * a.n;
+    const float* g = a.G + fo;
+    double acc = 0.0;
+    for (int chunk = blk; chunk < a.nchunks; chunk += a.bpf) {
+        const int i = chunk * kBlock + threadIdx.x;
+        if (i >= a.n) continue;
+        const int4 c = a.col[i];
+        const f16x4 w = a.kh[i];
+        float s = (float)w.x * g[c.x];
+        s = fmaf((float)w.y, g[c.y], s);
+        s = fmaf((float)w.z, g[c.z], s);
+        s = fmaf((float)w.w, g[c.w], s);
+        if constexpr (NS == 6) {
+            const int2 c2 = a.col2[i];
+            const f16x2 w2 = a.kh2[i];
+            s = fmaf((float)w2.x, g[c2.x], s);
+            s = fmaf((float)w2.y, g[c2.y], s);
+        }
+        const float hk = a.h[i] * a.kappa;
+        float o;
+        if constexpr (STAGE == 0) {
+            o = fmaf(-hk, s, g[i]);
+        } else {
+            o = a.gk * fmaf(a.cq, a.V[fo + i], fmaf(a.c1, g[i], -hk * s));
+        }
+        a.out[fo + i] = o;
+        if constexpr (STAGE == 2) acc = fma((double)a.R[fo + i], (double)o, acc);
+    }
+    if constexpr (STAGE == 2) {
+        __shared__ double sh[kWaves];
+        const double t = block_reduce_fixed(acc, sh);
+        if (threadIdx.x == 0) a.part[(size_t)f * a.pstride + blk] = t;
+    }
+}
+
+// h = 1 / (V + kappa sum_f a~_f)
+__global__ void k_tet_hinv(const float* volf, const float* kdh, float kappa, float* h, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        h[i] = (float)(1.0 / ((double)volf[i] + (double)kappa * (double)kdh[i]));
+}
+
+// First iteration of a step: r_0 = M e, v = h r_0 (the polynomial's input),
+// b.b partials into the slot sweep 2 of the first iteration reads.
+__global__ __launch_bounds__(kBlock) void k_tet_cheb_init(TetArgs a) {
+    int b = blockIdx.x;
+    if ((a.nblocks & 7) == 0) b = (b & 7) * (a.nblocks >> 3) + (b >> 3);
+    const int f = b / a.bpf;
+    const int blk = b - f * a.bpf;
+    const size_t fo = (size_t)f * a.n;
+    double acc = 0.0;
+    for (int chunk = blk; chunk < a.nchunks; chunk += a.bpf) {
+        const int i = chunk * kBlock + threadIdx.x;
+        if (i >= a.n) continue;
+        const float r = a.volf[i] * a.B[fo + i];
+        a.R[fo + i] = r;
+        a.Z[fo + i] = a.dinv[i] * r;
+        acc = fma((double)r, (double)r, acc);
+    }
+    __shared__ double sh[kWaves];
+    const double t = block_reduce_fixed(acc, sh);
+    if (threadIdx.x == 0) a.P1[(size_t)f * 3 * a.bpf + 2 * a.bpf + blk] = t;
 }
 
 __global__ __launch_bounds__(kBlock) void k_tet_mass(const float* e, const double* vol, int n, double* part, int bpf) {
@@ -417,7 +529,75 @@ size_t tet_small(int F, int bpf) {
     return (b + 255) & ~(size_t)255;
 }
 
+// Degree of the polynomial preconditioner with the least predicted work, as
+// for the hex stencil: degree m keeps the spectrum of p(B) B in [1 - e,
+// 1 + e], e = 1 / T_{m+1}(sig(0)) on [lmin, lmax]; CG needs about
+// log(1 / rtol) / log(1 / rho) iterations, rho = (sqrt(K) - 1) / (sqrt(K) + 1),
+// K = (1 + e) / (1 - e) (K = lmax / lmin for Jacobi, m = 0).  An iteration
+// costs the two sweeps plus m passes, each pass about kPassCost of the two
+// sweeps' bytes (28 + 12 bytes per row against 52 + 32 with four slots).
+int tet_degree(double lmin, double lmax, double rtol, int ns) {
+    const double kPassCost = ns == 6 ? 44.0 / 100.0 : 40.0 / 84.0;
+    const double s0 = (lmax + lmin) / std::max(lmax - lmin, 1e-12 * lmax);
+    const double th = std::acosh(std::max(s0, 1.0 + 1e-12));
+    const double want = std::log(1.0 / std::max(rtol, 1e-300));
+    int best = 0;
+    double best_cost = 1e300;
+    for (int m = 0; m <= 16; m += 2) {
+        const double e = m == 0 ? 0.0 : 1.0 / std::cosh(std::min((m + 1) * th, 700.0));
+        const double K = m == 0 ? lmax / lmin : (1.0 + e) / std::max(1.0 - e, 1e-300);
+        const double rho = (std::sqrt(K) - 1.0) / (std::sqrt(K) + 1.0);
+        const double x = rho > 0.0 ? want / std::log(1.0 / rho) : 0.0;
+        const double k = std::max(1.0, std::ceil(x));
+        const double cost = k * (1.0 + kPassCost * m);
+        if (cost < best_cost * (1.0 - 1e-9)) {
+            best_cost = cost;
+            best = m;
+        }
+    }
+    return best;
+}
+
 }  // namespace
+
+cgd_status cheb_operator_setup(TetData* t, const std::vector<float>& kface, const std::vector<float>& kface2,
+                               const std::vector<double>& vol) {
+    const size_t n = vol.size();
+    double amax = 0.0;
+    for (float v : kface) amax = std::max(amax, (double)v);
+    for (float v : kface2) amax = std::max(amax, (double)v);
+    std::vector<_Float16> kh(kface.size()), kh2(kface2.size());
+    std::vector<float> kdh(n, 0.f);
+    const float inv = amax > 0.0 ? (float)(1.0 / amax) : 0.f;
+    for (size_t i = 0; i < n; ++i) {
+        float sum = 0.f;
+        for (int j = 0; j < 4; ++j) {
+            kh[i * 4 + j] = (_Float16)(kface[i * 4 + j] * inv);
+            sum += (float)kh[i * 4 + j];
+        }
+        if (!kface2.empty()) {
+            for (int j = 0; j < 2; ++j) {
+                kh2[i * 2 + j] = (_Float16)(kface2[i * 2 + j] * inv);
+                sum += (float)kh2[i * 2 + j];
+            }
+        }
+        kdh[i] = sum;
+    }
+    double sv = 0.0, sk = 0.0, kv = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        sv += vol[i];
+        sk += amax * (double)kdh[i];
+        kv = std::max(kv, amax * (double)kdh[i] / vol[i]);
+    }
+    t->amax = amax;
+    t->sum_v = sv;
+    t->sum_k = sk;
+    t->kv_max = kv;
+    cgd_status rc = upload(kh, &t->kh);
+    if (rc == CGD_OK) rc = upload(kh2, &t->kh2);
+    if (rc == CGD_OK) rc = upload(kdh, &t->kdh);
+    return rc;
+}
 
 void destroy_tet_data(cgd_mesh m) {
     if (RectOp* ro = m->rop) {
@@ -430,7 +610,8 @@ void destroy_tet_data(cgd_mesh m) {
     TetData* t = m->tet;
     if (!t) return;
     void* ptrs[] = {t->xyz,   t->tv,     t->vol,   t->volf,  t->bbox, t->kface, t->kdiag,
-                    t->bstart, t->blist, t->bseed, t->nbr,  t->nbr2, t->kface2, t->redges};
+                    t->bstart, t->blist, t->bseed, t->nbr,  t->nbr2, t->kface2, t->redges,
+                    t->kh,     t->kh2,   t->kdh};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete t;
@@ -490,8 +671,9 @@ cgd_status locate_tet(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hi
 
 size_t diffuse_tet_workspace(const cgd_mesh m, int32_t F) {
     const TetPlan p = tet_plan(m->tet->n_tet, F);
-    // 6 vectors per field (x, r, p twice, q, z) and D^-1
-    return tet_small(F, p.bpf) + (6 * (size_t)F + 1) * (size_t)m->tet->n_tet * sizeof(float) + 256;
+    // 7 vectors per field (x, r, p twice, q, z, the preconditioner's w) and
+    // D^-1 (or the preconditioner's h)
+    return tet_small(F, p.bpf) + (7 * (size_t)F + 1) * (size_t)m->tet->n_tet * sizeof(float) + 256;
 }
 
 cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values, float* field,
@@ -850,12 +1032,32 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     float* PB = PA + fn;
     float* Q = PB + fn;
     float* Z = Q + fn;
-    float* dinv = Z + fn;
+    float* Wv = Z + fn;
+    float* dinv = Wv + fn;
 
     // Crank-Nicolson solves with half the step, then extrapolates (below)
     const double dtau = da.bandwidth * da.bandwidth / 4.0 / da.n_steps * (da.scheme == 1 ? 0.5 : 1.0);
     const int eblocks = std::min(4096, (n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_tet_dinv, dim3(eblocks), dim3(kBlock), 0, s, t->volf, t->kdiag, (float)dtau, dinv, n);
+    // Preconditioner: the Chebyshev polynomial of B = H A~ on [lmin, lmax]
+    // with lmin the Rayleigh quotient of a constant field (sum V / sum
+    // diag A~: the slowest modes of the mass-plus-diffusion operator are the
+    // smooth ones) and lmax Gershgorin's bound 1 + t / (1 + t), t = dtau max
+    // K~_ii / V_i; Jacobi (degree 0) where the cost model prefers it or
+    // precond = 1.  CGD_TET_DEGREE forces an even degree 0..16.
+    const double kappa = dtau * t->amax;
+    const double lmin = t->sum_v / (t->sum_v + dtau * t->sum_k);
+    const double tmx = dtau * t->kv_max;
+    const double lmax = 1.0 + tmx / (1.0 + tmx);
+    int deg = da.precond == 1 || !(t->amax > 0.0) ? 0 : tet_degree(lmin, lmax, da.rtol, t->ns);
+    if (const char* e = getenv("CGD_TET_DEGREE")) deg = std::max(0, std::min(16, atoi(e))) & ~1;
+    if (!(t->amax > 0.0)) deg = 0;
+    double qs[8], qq[8], qg[8], lead = 1.0;
+    const int nq = deg > 0 ? poly_precond_quadratics_iv(lmin, lmax, deg, qs, qq, qg, &lead) : 0;
+    if (deg > 0)
+        hipLaunchKernelGGL(k_tet_hinv, dim3(eblocks), dim3(kBlock), 0, s, t->volf, t->kdh, (float)kappa, dinv, n);
+    else
+        hipLaunchKernelGGL(k_tet_dinv, dim3(eblocks), dim3(kBlock), 0, s, t->volf, t->kdiag, (float)dtau, dinv,
+                           n);
 
     TetArgs a = {};
     a.col = reinterpret_cast<const int4*>(t->nbr);
@@ -902,6 +1104,52 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             }
         }
     };
+    // z = p(B) h r from v = h r in Z (sweep 2 or the step's first kernel
+    // wrote it); the last pass sums r.z into part (field stride pstride)
+    ChebArgs ca = {};
+    ca.col = a.col;
+    ca.col2 = a.col2;
+    ca.kh = reinterpret_cast<const f16x4*>(t->kh);
+    ca.kh2 = reinterpret_cast<const f16x2*>(t->kh2);
+    ca.h = dinv;
+    ca.R = R;
+    ca.c = ctl;
+    ca.kappa = (float)kappa;
+    ca.n = n;
+    ca.bpf = p.bpf;
+    ca.nblocks = p.nblocks;
+    ca.nchunks = p.nchunks;
+    // pass 1: ids, a~, h, v; writes w.  pass 2: the same with w, plus v; writes v (+ r in the last)
+    const double slot_b = t->ns == 6 ? 36.0 : 24.0;
+    const double bp1 = (slot_b + 12.0) * n, bp2 = (slot_b + 16.0) * n;
+    auto cheb = [&](double* part, size_t pstride, int64_t tag) {
+        for (int k = 0; k < nq; ++k) {
+            const bool last = k + 1 == nq;
+            ca.G = Z;
+            ca.out = Wv;
+            int t1 = timing_begin(&m->timing, s);
+            if (t->ns == 6) hipLaunchKernelGGL((k_tet_cheb<6, 0>), grid, block, 0, s, ca);
+            else hipLaunchKernelGGL((k_tet_cheb<4, 0>), grid, block, 0, s, ca);
+            timing_end(&m->timing, t1, 16, bp1 * F, s, tag);
+            ca.G = Wv;
+            ca.V = Z;
+            ca.out = Z;
+            ca.c1 = (float)(1.0 + qs[k]);
+            ca.cq = (float)qq[k];
+            ca.gk = (float)(qg[k] * (last ? lead : 1.0));
+            ca.part = part;
+            ca.pstride = pstride;
+            int t2 = timing_begin(&m->timing, s);
+            if (t->ns == 6) {
+                if (last) hipLaunchKernelGGL((k_tet_cheb<6, 2>), grid, block, 0, s, ca);
+                else hipLaunchKernelGGL((k_tet_cheb<6, 1>), grid, block, 0, s, ca);
+            } else {
+                if (last) hipLaunchKernelGGL((k_tet_cheb<4, 2>), grid, block, 0, s, ca);
+                else hipLaunchKernelGGL((k_tet_cheb<4, 1>), grid, block, 0, s, ca);
+            }
+            timing_end(&m->timing, t2, 17, (bp2 + (last ? 4.0 * n : 0.0)) * F, s, tag);
+        }
+    };
     float* cur = da.field;
     float* nxt = W0;
     for (int step = 0; step < da.n_steps; ++step) {
@@ -913,8 +1161,18 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         a.k = 0;
         a.Pnew = PA;
         a.Pold = PB;
-        sweep(T1_FIRST);
+        if (nq > 0) {
+            // r_0 = M e, v = h r_0, b.b; z_0 and r.z from the passes; then
+            // the direction sweep with p = z_0
+            hipLaunchKernelGGL(k_tet_cheb_init, grid, block, 0, s, a);
+            cheb(d_P1 + p.bpf, (size_t)3 * p.bpf, (int64_t)step * 65536);
+            if (t->ns == 6) hipLaunchKernelGGL((k_tet_sweep<T1_FIRST, 6, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_tet_sweep<T1_FIRST, 4, true>), grid, block, 0, s, a);
+        } else {
+            sweep(T1_FIRST);
+        }
         sweep(T2_FIRST);
+        if (nq > 0) cheb(d_P2 + (size_t)2 * p.bpf, (size_t)4 * p.bpf, (int64_t)step * 65536);
         auto enqueue = [&](int it, int* host_flags) {
             a.k = it;
             a.Pold = (it & 1) ? PA : PB;
@@ -928,6 +1186,8 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             sweep(T2);
             timing_end(&m->timing, t2, 4, b2 * F, s, tag);
             a.c.host_flags = nullptr;
+            // sweep 2 of iteration it wrote v = h r and r.r for parity (it + 1) & 1
+            if (nq > 0) cheb(d_P2 + (size_t)((it + 1) & 1) * 2 * p.bpf, (size_t)4 * p.bpf, tag);
         };
         int it_end = 1;
         rc = cg_lookahead_loop(m, F, 1, da.max_iter, da.check_every, ctl.ndone, s, enqueue, &it_end);
@@ -1001,7 +1261,8 @@ extern "C" cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz, int
                                   upload(volf, &t->volf),      upload(h.bbox, &t->bbox),  upload(h.kface, &t->kface),
                                   upload(h.kdiag, &t->kdiag),
                                   upload(h.bstart, &t->bstart), upload(h.blist, &t->blist),
-                                  upload(h.bseed, &t->bseed),   upload(h.nbr, &t->nbr)};
+                                  upload(h.bseed, &t->bseed),   upload(h.nbr, &t->nbr),
+                                  cheb_operator_setup(t, h.kface, {}, h.vol)};
     for (cgd_status r : st) {
         if (r != CGD_OK) {
             cgd_mesh_destroy(m);
@@ -1141,7 +1402,8 @@ extern "C" cgd_status cgd_mesh_create_rect(int32_t nx, int32_t ny, int32_t nz, c
     for (int a = 0; a < 3; ++a) t->rdim[a] = dims[a];
     std::vector<cgd_status> st = {upload(vol, &t->vol),       upload(volf, &t->volf),   upload(kface, &t->kface),
                                   upload(kface2, &t->kface2), upload(kdiag, &t->kdiag), upload(nbr, &t->nbr),
-                                  upload(nbr2, &t->nbr2),     upload(redges, &t->redges)};
+                                  upload(nbr2, &t->nbr2),     upload(redges, &t->redges),
+                                  cheb_operator_setup(t, kface, kface2, vol)};
     for (cgd_status r : st) {
         if (r != CGD_OK) {
             cgd_mesh_destroy(m);

@@ -49,7 +49,22 @@ struct TetData {
     float* kface2 = nullptr;    // [n][2]
     int32_t rdim[3] = {0, 0, 0};
     double* redges = nullptr;   // node coordinates: x (rdim[0] + 1), then y, then z
+    // Operator of the polynomial preconditioner: face coefficients a_f / amax
+    // in float16 (one rounding per face, shared by its two rows, so the
+    // operator stays symmetric) and their float sum per row.
+    _Float16* kh = nullptr;     // [n][4]
+    _Float16* kh2 = nullptr;    // [n][2] (6 face slots)
+    float* kdh = nullptr;       // [n]
+    double amax = 0.0;          // largest a_f
+    double sum_v = 0.0;         // sum of V
+    double sum_k = 0.0;         // sum of amax * kdh
+    double kv_max = 0.0;        // max of amax * kdh / V
 };
+
+// Fills the preconditioner's operator fields of t from the float face
+// coefficients (kface2 empty for 4 slots) and the volumes, and uploads them.
+cgd_status cheb_operator_setup(TetData* t, const std::vector<float>& kface, const std::vector<float>& kface2,
+                               const std::vector<double>& vol);
 
 cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tv, TetHost* out);
 

@@ -201,7 +201,7 @@ def kuhn_tet_mesh(n: int = 100, jitter: float = 0.2, seed: int = SEED_BASE + 3,
 def unstructured(n_hex: int = 100, n_particles: int = 5_000_000, seed: int = SEED_BASE + 3):
     """Unit cube, n_hex^3 hexes x 6 jittered Kuhn tets, uniform spheres d=0.004.
 
-    Bandwidth b = 4 hex spacings, 4 pseudo-steps, Jacobi-PCG rtol 1e-6.
+    Bandwidth b = 4 hex spacings, 4 pseudo-steps, CG rtol 1e-6.
     Returns (xyz, tets, Particles, bandwidth, n_steps, rtol).
     """
     xyz, tets = kuhn_tet_mesh(n_hex, 0.2, seed)
