@@ -128,14 +128,16 @@ struct DeviceGuard {
 static cgd_status deposit_buffers(cgd_mesh m, int64_t n, int32_t F, int64_t* user_acc, int64_t** acc,
                                   DepositInfo** info, void** temp) {
     const size_t tiled = m->kind != 1 ? deposit_hex_temp_bytes(m, n, F) : 0;
-    size_t acc_bytes = (user_acc || tiled) ? 0 : (size_t)F * m->cells * sizeof(int64_t);
-    size_t need = kSmallFixed + acc_bytes + tiled;
+    size_t acc_bytes = (user_acc || tiled) ? 0 : ((size_t)F * m->cells * sizeof(int64_t) + 255) & ~(size_t)255;
+    // tet meshes: the particles' spatial ordering after the accumulators
+    const size_t order = m->kind == 1 ? deposit_tet_temp_bytes(m, n) : 0;
+    size_t need = kSmallFixed + acc_bytes + tiled + order;
     size_t diff = m->kind == 0 ? diffuse_hex_workspace(m, F) : diffuse_tet_workspace(m, F);
     cgd_status rc = ensure_workspace(m, need > diff ? need : diff);
     if (rc != CGD_OK) return rc;
     char* base = static_cast<char*>(m->ws.ptr);
     *info = reinterpret_cast<DepositInfo*>(base + kOffDeposit);
-    *temp = tiled ? base + kSmallFixed : nullptr;
+    *temp = tiled ? base + kSmallFixed : (order ? base + kSmallFixed + acc_bytes : nullptr);
     *acc = user_acc ? user_acc : (tiled ? nullptr : reinterpret_cast<int64_t*>(base + kSmallFixed));
     return CGD_OK;
 }

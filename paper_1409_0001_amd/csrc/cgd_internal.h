@@ -303,7 +303,10 @@ void destroy_batched(cgd_mesh m);
 
 // tet.cpp / tet.hip
 // temp (rectilinear meshes): deposit_hex_temp_bytes(m, n, F) bytes for the
-// tiled path, as deposit_hex; nullptr on tet meshes and for the direct path.
+// tiled path, as deposit_hex; nullptr for the direct path.  Tet meshes:
+// deposit_tet_temp_bytes(m, n) bytes for the particles' spatial ordering
+// (nullptr: located in input order).
+size_t deposit_tet_temp_bytes(const cgd_mesh m, int64_t n);
 cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
                        float* field, int64_t* acc, DepositInfo* info_dev, void* temp, const ScaleForce& fs,
                        hipStream_t s);

@@ -167,17 +167,21 @@ struct TetLoc {
     __device__ int operator()(const double* p) const { return locate(g, p); }
 };
 
+// perm (nullable): the order in which the threads take the particles (the
+// spatial ordering below), so that the threads of a wave walk nearby tets.
 template <class Loc>
 __global__ __launch_bounds__(kBlock) void k_locate_deposit_tet(const float* __restrict__ pos,
                                                                const float* __restrict__ values, int64_t n, int F,
                                                                Loc loc, int e_n, unsigned long long* __restrict__ acc,
-                                                               int64_t cells, DepositInfo* info, int32_t* cell_out) {
+                                                               int64_t cells, DepositInfo* info, int32_t* cell_out,
+                                                               const int32_t* __restrict__ perm) {
     __shared__ int S[CGD_MAX_FIELDS];
     if (threadIdx.x < F) S[threadIdx.x] = frac_bits_used(info->maxbits[threadIdx.x], info->force_s[threadIdx.x], e_n);
     __syncthreads();
     unsigned long long dropped = 0ull, nfpos = 0ull;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int64_t q = perm ? (int64_t)perm[i] : i;
         const double p[3] = {(double)pos[3 * q], (double)pos[3 * q + 1], (double)pos[3 * q + 2]};
         int t = -1;
         if (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) {
@@ -205,6 +209,109 @@ __global__ __launch_bounds__(kBlock) void k_locate_deposit_tet(const float* __re
         atomicAdd(&info->dropped, dropped);
         if (nfpos) atomicAdd(&info->nonfinite_pos, nfpos);
     }
+}
+
+// Spatial ordering of the particles for the walk: key = the walk's bucket
+// coordinates shifted right by `shift` (a block of 8^shift buckets), sorted by
+// counting with per-block histograms in LDS (no global atomics): each of
+// nblk blocks counts its contiguous run of particles into LDS and stores the
+// row hist[block][key]; the rows are scanned per key over the blocks and the
+// key totals over the keys; the scatter then ranks each block's particles
+// with LDS atomics on base[key] + hist[block][key].  The order within a key
+// is arbitrary, which the integer sums do not see.  Points outside the
+// bucket grid or non-finite take the last key.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderMaxKeys = 16383;  // LDS counters of a block: 64 KB with the last key
+
+struct OrderArgs {
+    const float* pos;
+    int64_t n;
+    int32_t* key;     // [n]
+    int32_t* hist;    // [nblk][nkey + 1]: per-block counts, then their exclusive scan over the blocks
+    int32_t* total;   // [nkey + 1]: key totals, then their exclusive scan (the keys' first slots)
+    int32_t* perm;    // [n]
+    int64_t per;      // particles per block
+    int nblk;
+    int nb[3], sb[3], shift, nkey;
+    double glo[3], ghi[3], ginv[3];
+};
+
+__device__ inline int order_key(const OrderArgs& a, const float* pq) {
+    int k = 0, mul = 1;
+    for (int d = 0; d < 3; ++d) {
+        const double p = (double)pq[d];
+        if (!(p >= a.glo[d] && p <= a.ghi[d])) return a.nkey;
+        int b = (int)floor((p - a.glo[d]) * a.ginv[d]);
+        b = b < 0 ? 0 : (b >= a.nb[d] ? a.nb[d] - 1 : b);
+        k += (b >> a.shift) * mul;
+        mul *= a.sb[d];
+    }
+    return k;
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_order_count(OrderArgs a) {
+    __shared__ int32_t h[kOrderMaxKeys + 1];
+    const int nk = a.nkey + 1;
+    for (int k = threadIdx.x; k < nk; k += kOrderThreads) h[k] = 0;
+    __syncthreads();
+    const int64_t b = (int64_t)blockIdx.x * a.per, e = min(b + a.per, a.n);
+    for (int64_t q = b + threadIdx.x; q < e; q += kOrderThreads) {
+        const int k = order_key(a, a.pos + 3 * q);
+        a.key[q] = k;
+        atomicAdd(&h[k], 1);
+    }
+    __syncthreads();
+    int32_t* row = a.hist + (size_t)blockIdx.x * nk;
+    for (int k = threadIdx.x; k < nk; k += kOrderThreads) row[k] = h[k];
+}
+
+// per key: exclusive scan of its counts over the blocks, and the total
+__global__ __launch_bounds__(kBlock) void k_order_colscan(OrderArgs a) {
+    const int nk = a.nkey + 1;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nk; k += gridDim.x * blockDim.x) {
+        int32_t run = 0;
+        for (int b = 0; b < a.nblk; ++b) {
+            int32_t* c = a.hist + (size_t)b * nk + k;
+            const int32_t v = *c;
+            *c = run;
+            run += v;
+        }
+        a.total[k] = run;
+    }
+}
+
+// Exclusive scan of count[0..m) in place, one block of 1024 threads, each
+// owning a contiguous run.
+__global__ __launch_bounds__(1024) void k_order_scan(int32_t* count, int m) {
+    __shared__ int32_t part[1024];
+    const int per = (m + 1023) / 1024;
+    const int b = threadIdx.x * per, e = min(b + per, m);
+    int32_t s = 0;
+    for (int i = b; i < e; ++i) s += count[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int32_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int32_t run = part[threadIdx.x] - s;
+    for (int i = b; i < e; ++i) {
+        const int32_t c = count[i];
+        count[i] = run;
+        run += c;
+    }
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_order_scatter(OrderArgs a) {
+    __shared__ int32_t h[kOrderMaxKeys + 1];
+    const int nk = a.nkey + 1;
+    const int32_t* row = a.hist + (size_t)blockIdx.x * nk;
+    for (int k = threadIdx.x; k < nk; k += kOrderThreads) h[k] = a.total[k] + row[k];
+    __syncthreads();
+    const int64_t b = (int64_t)blockIdx.x * a.per, e = min(b + a.per, a.n);
+    for (int64_t q = b + threadIdx.x; q < e; q += kOrderThreads) a.perm[atomicAdd(&h[a.key[q]], 1)] = (int32_t)q;
 }
 
 __global__ __launch_bounds__(kBlock) void k_finalize_vol(const long long* __restrict__ acc, float* __restrict__ field,
@@ -676,6 +783,45 @@ size_t diffuse_tet_workspace(const cgd_mesh m, int32_t F) {
     return tet_small(F, p.bpf) + (7 * (size_t)F + 1) * (size_t)m->tet->n_tet * sizeof(float) + 256;
 }
 
+namespace {
+// Key layout of the spatial ordering: the smallest shift that leaves at
+// least 256 particles per key on average and at most kOrderMaxKeys keys;
+// blocks of at least 8192 particles, at most 512 blocks.
+OrderArgs order_layout(const TetData* t, int64_t n) {
+    OrderArgs a = {};
+    a.n = n;
+    for (int sh = 0;; ++sh) {
+        int64_t k = 1;
+        for (int d = 0; d < 3; ++d) k *= ((t->nb[d] - 1) >> sh) + 1;
+        if ((k * 256 <= n && k < kOrderMaxKeys) || sh >= 10) {
+            a.shift = sh;
+            break;
+        }
+    }
+    a.nkey = 1;
+    for (int d = 0; d < 3; ++d) {
+        a.nb[d] = t->nb[d];
+        a.sb[d] = ((t->nb[d] - 1) >> a.shift) + 1;
+        a.nkey *= a.sb[d];
+        a.glo[d] = t->glo[d];
+        a.ghi[d] = t->ghi[d];
+        a.ginv[d] = t->ginv[d];
+    }
+    a.nblk = (int)std::max<int64_t>(1, std::min<int64_t>(512, n / 8192));
+    a.per = (n + a.nblk - 1) / a.nblk;
+    return a;
+}
+}  // namespace
+
+size_t deposit_tet_temp_bytes(const cgd_mesh m, int64_t n) {
+    const TetData* t = m->tet;
+    if (!t || t->ns != 4 || n < 4096 || n > INT32_MAX || getenv("CGD_TET_INPUT_ORDER")) return 0;
+    const OrderArgs a = order_layout(t, n);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t nk = (size_t)a.nkey + 1;
+    return 2 * al((size_t)n * 4) + al(nk * 4) + al((size_t)a.nblk * nk * 4);
+}
+
 cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values, float* field,
                        int64_t* acc, DepositInfo* info, void* temp, const ScaleForce& fs, hipStream_t s) {
     const TetData* t = m->tet;
@@ -711,13 +857,32 @@ cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
     if (n > 0) {
         const int blocks = (int)std::min<int64_t>(16384, (n + kBlock - 1) / kBlock);
         int tm = timing_begin(&m->timing, s);
+        int32_t* perm = nullptr;
+        if (t->ns == 4 && temp && deposit_tet_temp_bytes(m, n) > 0) {
+            // the particles in the order of a coarse bucket key
+            OrderArgs o = order_layout(t, n);
+            char* tb = static_cast<char*>(temp);
+            auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+            const size_t nb4 = al((size_t)n * 4), nk = (size_t)o.nkey + 1;
+            o.pos = pos;
+            o.key = reinterpret_cast<int32_t*>(tb);
+            o.perm = reinterpret_cast<int32_t*>(tb + nb4);
+            o.total = reinterpret_cast<int32_t*>(tb + 2 * nb4);
+            o.hist = reinterpret_cast<int32_t*>(tb + 2 * nb4 + al(nk * 4));
+            hipLaunchKernelGGL(k_order_count, dim3(o.nblk), dim3(kOrderThreads), 0, s, o);
+            hipLaunchKernelGGL(k_order_colscan, dim3((unsigned)((nk + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, o);
+            hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, s, o.total, (int)nk);
+            hipLaunchKernelGGL(k_order_scatter, dim3(o.nblk), dim3(kOrderThreads), 0, s, o);
+            perm = o.perm;
+        }
         if (t->ns == 6)
             hipLaunchKernelGGL(k_locate_deposit_tet<RectLoc>, dim3(blocks), dim3(kBlock), 0, s, pos, values, n, F,
-                               rect_loc(t), e_n, reinterpret_cast<unsigned long long*>(acc), cells, info, nullptr);
+                               rect_loc(t), e_n, reinterpret_cast<unsigned long long*>(acc), cells, info, nullptr,
+                               nullptr);
         else
             hipLaunchKernelGGL(k_locate_deposit_tet<TetLoc>, dim3(blocks), dim3(kBlock), 0, s, pos, values, n, F,
                                TetLoc{loc_args(t)}, e_n, reinterpret_cast<unsigned long long*>(acc), cells, info,
-                               nullptr);
+                               nullptr, perm);
         timing_end(&m->timing, tm, 2, (12.0 + 12.0 * F) * (double)n, s);
     }
     const int blocks = (int)std::min<int64_t>(8192, (cells + kBlock - 1) / kBlock);

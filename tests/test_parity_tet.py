@@ -28,10 +28,16 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("order", ["spatial", "input"])
 @pytest.mark.parametrize("n_hex,jitter", [(6, 0.2), (9, 0.0)])
-def test_locate_and_deposit_bit_exact(gpu_lib, n_hex, jitter):
+def test_locate_and_deposit_bit_exact(gpu_lib, n_hex, jitter, order, monkeypatch):
+    """Location and deposition bit for bit against the oracle, with the
+    particles taken in a coarse spatial order (the default from 4,096
+    particles) and in input order."""
     import torch
     cgd = gpu_lib
+    if order == "input":
+        monkeypatch.setenv("CGD_TET_INPUT_ORDER", "1")
     xyz, tets = inputs.kuhn_tet_mesh(n_hex, jitter, seed=51)
     rng = np.random.default_rng(52)
     pos = rng.random((20_000, 3)).astype(np.float32)
@@ -41,7 +47,7 @@ def test_locate_and_deposit_bit_exact(gpu_lib, n_hex, jitter):
     pos[100:150, 1] = pos[100:150, 0]
     pos[150:155] = [[1.5, 0.5, 0.5], [-0.1, 0.2, 0.3], [0.5, 0.5, 2.0], [np.nan, 0.1, 0.1], [0.2, np.inf, 0.3]]
     vals = np.stack([np.full(len(pos), 3.3e-8, np.float32), rng.normal(size=len(pos)).astype(np.float32)])
-    print(f"case: tet {n_hex}^3x6 jitter {jitter}", flush=True)
+    print(f"case: tet {n_hex}^3x6 jitter {jitter} {order} order", flush=True)
     mesh = cgd.TetMesh(xyz, tets)
     assert mesh.cells == len(tets)
     P, N, _ = O.tet_faces(tets)
