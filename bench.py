@@ -299,9 +299,10 @@ def bench_unstructured(args):
         if n:
             rl[k] = {"launches": n, "avg_us": round(ms / n * 1e3, 2), "total_ms": round(ms, 3),
                      "achieved_GBs": round(bpl / (ms / n * 1e-3) / 1e9, 1)}
-    # one application of the polynomial per iteration plus one at each step's
-    # start; each takes degree / 2 passes w = B v
-    apps = tim["pcg_update_sweep"][0] + 2 * steps
+    # one application of the polynomial per iteration that ran (timed: the
+    # update sweeps after each step's first, plus the first); each takes
+    # degree / 2 passes w = B v
+    apps = tim["pcg_update_sweep"][0] + steps
     degree = 2 * tim["pcg_poly_pass_bv"][0] // max(1, apps)
     line = {"metric": "coarse-grained fields/sec, unstructured 6M tets, 5M particles",
             "value": round(1.0 / dt, 3), "unit": "fields/s", "n_gpus": 1, "steps": args.steps,

@@ -506,6 +506,8 @@ struct ChebArgs {
     float* out;
     double* part;         // last pass: r.z partial of block blk of field f at part[f * pstride + blk]
     size_t pstride;
+    const double* rrp;    // first pass (nullable): r.r partials of sweep 2 at rrp[f * pstride + blk],
+    int kcheck;           // tested as the convergence check of iteration kcheck
     CgCtl c;
     float kappa, c1, cq, gk;
     int n, bpf, nblocks, nchunks;
@@ -517,7 +519,18 @@ __global__ __launch_bounds__(kBlock) void k_tet_cheb(ChebArgs a) {
     if ((a.nblocks & 7) == 0) b = (b & 7) * (a.nblocks >> 3) + (b >> 3);
     const int f = b / a.bpf;
     const int blk = b - f * a.bpf;
-    if (a.c.st[f].done) return;
+    CgField* stf = a.c.st + f;
+    if (stf->done) return;
+    __shared__ double sh[kWaves];
+    if constexpr (STAGE == 0) {
+        // the next iteration's convergence check, made here so that a
+        // converged field skips the polynomial as well (every block sums the
+        // partials in the same order and takes the same decision)
+        if (a.rrp) {
+            const double rr = block_sum_fixed(a.rrp + (size_t)f * a.pstride, a.bpf, sh);
+            if (check_stop(a.c, f, a.kcheck, rr, stf->bb, blk == 0 && threadIdx.x == 0)) return;
+        }
+    }
     const size_t fo = (size_t)f * a.n;
     const float* g = a.G + fo;
     double acc = 0.0;
@@ -547,7 +560,6 @@ __global__ __launch_bounds__(kBlock) void k_tet_cheb(ChebArgs a) {
         if constexpr (STAGE == 2) acc = fma((double)a.R[fo + i], (double)o, acc);
     }
     if constexpr (STAGE == 2) {
-        __shared__ double sh[kWaves];
         const double t = block_reduce_fixed(acc, sh);
         if (threadIdx.x == 0) a.part[(size_t)f * a.pstride + blk] = t;
     }
@@ -1287,9 +1299,15 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     // pass 1: ids, a~, h, v; writes w.  pass 2: the same with w, plus v; writes v (+ r in the last)
     const double slot_b = t->ns == 6 ? 36.0 : 24.0;
     const double bp1 = (slot_b + 12.0) * n, bp2 = (slot_b + 16.0) * n;
-    auto cheb = [&](double* part, size_t pstride, int64_t tag) {
+    // rrp / kcheck: sweep 2's r.r partials and the iteration they decide
+    // (the first pass makes the check, so a converged field skips the passes)
+    auto cheb = [&](double* part, size_t pstride, int64_t tag, const double* rrp, int kcheck) {
+        ca.part = part;
+        ca.pstride = pstride;
         for (int k = 0; k < nq; ++k) {
             const bool last = k + 1 == nq;
+            ca.rrp = k == 0 ? rrp : nullptr;
+            ca.kcheck = kcheck;
             ca.G = Z;
             ca.out = Wv;
             int t1 = timing_begin(&m->timing, s);
@@ -1302,8 +1320,6 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             ca.c1 = (float)(1.0 + qs[k]);
             ca.cq = (float)qq[k];
             ca.gk = (float)(qg[k] * (last ? lead : 1.0));
-            ca.part = part;
-            ca.pstride = pstride;
             int t2 = timing_begin(&m->timing, s);
             if (t->ns == 6) {
                 if (last) hipLaunchKernelGGL((k_tet_cheb<6, 2>), grid, block, 0, s, ca);
@@ -1319,6 +1335,7 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
     float* nxt = W0;
     for (int step = 0; step < da.n_steps; ++step) {
         a.c.step = step;
+        ca.c.step = step;  // the passes record a converged check in this step's row
         a.B = cur;
         a.X = nxt;
         hipLaunchKernelGGL(k_cg_step_init, dim3(1), dim3(64), 0, s, ctl.st, F, ctl.ndone,
@@ -1330,14 +1347,16 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             // r_0 = M e, v = h r_0, b.b; z_0 and r.z from the passes; then
             // the direction sweep with p = z_0
             hipLaunchKernelGGL(k_tet_cheb_init, grid, block, 0, s, a);
-            cheb(d_P1 + p.bpf, (size_t)3 * p.bpf, (int64_t)step * 65536);
+            cheb(d_P1 + p.bpf, (size_t)3 * p.bpf, (int64_t)step * 65536, nullptr, 0);
             if (t->ns == 6) hipLaunchKernelGGL((k_tet_sweep<T1_FIRST, 6, true>), grid, block, 0, s, a);
             else hipLaunchKernelGGL((k_tet_sweep<T1_FIRST, 4, true>), grid, block, 0, s, a);
         } else {
             sweep(T1_FIRST);
         }
         sweep(T2_FIRST);
-        if (nq > 0) cheb(d_P2 + (size_t)2 * p.bpf, (size_t)4 * p.bpf, (int64_t)step * 65536);
+        if (nq > 0)
+            cheb(d_P2 + (size_t)2 * p.bpf, (size_t)4 * p.bpf, (int64_t)step * 65536 + 1, d_P2 + (size_t)3 * p.bpf,
+                 1);
         auto enqueue = [&](int it, int* host_flags) {
             a.k = it;
             a.Pold = (it & 1) ? PA : PB;
@@ -1352,7 +1371,10 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
             timing_end(&m->timing, t2, 4, b2 * F, s, tag);
             a.c.host_flags = nullptr;
             // sweep 2 of iteration it wrote v = h r and r.r for parity (it + 1) & 1
-            if (nq > 0) cheb(d_P2 + (size_t)((it + 1) & 1) * 2 * p.bpf, (size_t)4 * p.bpf, tag);
+            // (tagged with the iteration it serves, so that it is timed only when that one ran)
+            if (nq > 0)
+                cheb(d_P2 + (size_t)((it + 1) & 1) * 2 * p.bpf, (size_t)4 * p.bpf, tag + 1,
+                     d_P2 + ((size_t)((it + 1) & 1) * 2 + 1) * p.bpf, it + 1);
         };
         int it_end = 1;
         rc = cg_lookahead_loop(m, F, 1, da.max_iter, da.check_every, ctl.ndone, s, enqueue, &it_end);

@@ -144,6 +144,7 @@ def test_tet_polynomial_degrees_match_oracle(gpu_lib, deg, scheme, monkeypatch):
         m0 = (dep["field64"][f] * V).sum()
         assert abs(st.mass_after[f] - m0) <= 1e-5 * np.abs(dep["field64"][f] * V).sum()
     assert st.status == 0
+    assert max(max(r) for r in st.rel_res) <= 1e-7, st.rel_res
     # more degree, fewer iterations (a float64 model of the same CG on this
     # mesh takes 71 / 26 / 9 / 5 at dtau / h^2 = 4/3, 52 / 19 / 7 / 4 at 2/3)
     its = max(max(r) for r in st.iters)
@@ -173,6 +174,13 @@ def test_tet_default_preconditioner_iterations(gpu_lib):
     print(f"iterations: polynomial {st.iters}, Jacobi {sj.iters}", flush=True)
     assert max(r[0] for r in st.iters) <= 12, st.iters
     assert min(r[0] for r in sj.iters) >= 40, sj.iters
+    # each step's statistics land in its own row: the recorded residual of
+    # every step meets rtol, and a step's count matches a one-step call
+    assert max(r[0] for r in st.rel_res) <= 1e-6 and max(r[0] for r in sj.rel_res) <= 1e-6, (st.rel_res,
+                                                                                              sj.rel_res)
+    field, _ = cgd.deposit(mesh, _t(pos, torch), _t(vals, torch), stats=True)
+    _, s1 = cgd.diffuse(mesh, field, b / np.sqrt(steps), 1, rtol=1e-6, stats=True)
+    assert s1.iters[0] == st.iters[0] and s1.rel_res[0] == st.rel_res[0], (s1, st)
     assert rel_l2(out.cpu().numpy()[0], ref[0]) <= REL_L2
     assert rel_l2(jac.cpu().numpy()[0], ref[0]) <= REL_L2
     assert st.status == 0 and sj.status == 0
