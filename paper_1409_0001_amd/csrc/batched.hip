@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kDBlock) void k_babsmax(BDep d) {
         bad += __shfl_xor(bad, o);
     }
     if ((threadIdx.x & 63) == 0) {
-        if (m) atomicMax(&d.maxbits[j * d.F + f], m);
+        if (m) atomic_max_if_larger(&d.maxbits[j * d.F + f], m);
         if (bad) atomicAdd(&d.counters[2 * j + 1], bad);
     }
 }

@@ -301,6 +301,16 @@ cgd_status coarse_grain_batched(cgd_mesh m, int32_t n_snap, const int64_t* offse
 cgd_status autotune_batched(cgd_mesh m, int n_rhs, int* chosen, double* ms_out, int* n_cand);
 void destroy_batched(cgd_mesh m);
 
+#ifdef __HIPCC__
+// atomicMax of a value that only grows, skipped when the value there is
+// already at least v (the load may be stale, never larger than the true
+// value, so a skipped update was never needed): one same-address atomic per
+// block would otherwise serialise thousands of blocks.
+__device__ inline void atomic_max_if_larger(uint32_t* p, uint32_t v) {
+    if (v > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, v);
+}
+#endif
+
 // tet.cpp / tet.hip
 // temp (rectilinear meshes): deposit_hex_temp_bytes(m, n, F) bytes for the
 // tiled path, as deposit_hex; nullptr for the direct path.  Tet meshes:

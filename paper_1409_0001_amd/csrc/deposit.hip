@@ -80,7 +80,7 @@ __global__ void k_absmax(const float* __restrict__ values, int64_t n, DepositInf
             mm = sm[i] > mm ? sm[i] : mm;
             bb += sb[i];
         }
-        if (mm) atomicMax(&info->maxbits[f], mm);
+        if (mm) atomic_max_if_larger(&info->maxbits[f], mm);
         if (bb) atomicAdd(&info->nonfinite_val[f], bb);
     }
 }
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
         if (hist[t]) atomicAdd(&counts[t], hist[t]);
     if (threadIdx.x < a.F) {
         const int f = threadIdx.x;
-        if (bmax[f]) atomicMax(&a.maxbits[j * a.F + f], bmax[f]);
+        if (bmax[f]) atomic_max_if_larger(&a.maxbits[j * a.F + f], bmax[f]);
         if (bbad[f]) atomicAdd(&a.nf_val[(size_t)j * a.cnt_jstride + f * a.nf_val_stride], bbad[f]);
     }
 }

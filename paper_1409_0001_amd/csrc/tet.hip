@@ -230,6 +230,7 @@ struct OrderArgs {
     int32_t* hist;    // [nblk][nkey + 1]: per-block counts, then their exclusive scan over the blocks
     int32_t* total;   // [nkey + 1]: key totals, then their exclusive scan (the keys' first slots)
     int32_t* perm;    // [n]
+    int32_t* seg;     // [kOrderSegs][nkey + 1]: per-segment sums of hist, then their scan
     int64_t per;      // particles per block
     int nblk;
     int nb[3], sb[3], shift, nkey;
@@ -265,18 +266,48 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_count(OrderArgs a) {
     for (int k = threadIdx.x; k < nk; k += kOrderThreads) row[k] = h[k];
 }
 
-// per key: exclusive scan of its counts over the blocks, and the total
+// per key: exclusive scan of its counts over the blocks, and the total, in
+// three coalesced passes over kOrderSegs segments of blocks (thread per key
+// and segment): segment sums; their scan per key (and the total); each
+// segment's run from its offset.
+constexpr int kOrderSegs = 16;
+
+__global__ __launch_bounds__(kBlock) void k_order_segsum(OrderArgs a) {
+    const int nk = a.nkey + 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x, sg = blockIdx.y;
+    if (k >= nk) return;
+    const int per = (a.nblk + kOrderSegs - 1) / kOrderSegs;
+    const int b0 = sg * per, b1 = min(b0 + per, a.nblk);
+    int32_t run = 0;
+    for (int b = b0; b < b1; ++b) run += a.hist[(size_t)b * nk + k];
+    a.seg[(size_t)sg * nk + k] = run;
+}
+
+__global__ __launch_bounds__(kBlock) void k_order_segscan(OrderArgs a) {
+    const int nk = a.nkey + 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nk) return;
+    int32_t run = 0;
+    for (int sg = 0; sg < kOrderSegs; ++sg) {
+        const int32_t v = a.seg[(size_t)sg * nk + k];
+        a.seg[(size_t)sg * nk + k] = run;
+        run += v;
+    }
+    a.total[k] = run;
+}
+
 __global__ __launch_bounds__(kBlock) void k_order_colscan(OrderArgs a) {
     const int nk = a.nkey + 1;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nk; k += gridDim.x * blockDim.x) {
-        int32_t run = 0;
-        for (int b = 0; b < a.nblk; ++b) {
-            int32_t* c = a.hist + (size_t)b * nk + k;
-            const int32_t v = *c;
-            *c = run;
-            run += v;
-        }
-        a.total[k] = run;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x, sg = blockIdx.y;
+    if (k >= nk) return;
+    const int per = (a.nblk + kOrderSegs - 1) / kOrderSegs;
+    const int b0 = sg * per, b1 = min(b0 + per, a.nblk);
+    int32_t run = a.seg[(size_t)sg * nk + k];
+    for (int b = b0; b < b1; ++b) {
+        int32_t* c = a.hist + (size_t)b * nk + k;
+        const int32_t v = *c;
+        *c = run;
+        run += v;
     }
 }
 
@@ -831,7 +862,7 @@ size_t deposit_tet_temp_bytes(const cgd_mesh m, int64_t n) {
     const OrderArgs a = order_layout(t, n);
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t nk = (size_t)a.nkey + 1;
-    return 2 * al((size_t)n * 4) + al(nk * 4) + al((size_t)a.nblk * nk * 4);
+    return 2 * al((size_t)n * 4) + al(nk * 4) + al((size_t)a.nblk * nk * 4) + al((size_t)kOrderSegs * nk * 4);
 }
 
 cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values, float* field,
@@ -881,8 +912,12 @@ cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const
             o.perm = reinterpret_cast<int32_t*>(tb + nb4);
             o.total = reinterpret_cast<int32_t*>(tb + 2 * nb4);
             o.hist = reinterpret_cast<int32_t*>(tb + 2 * nb4 + al(nk * 4));
+            o.seg = reinterpret_cast<int32_t*>(tb + 2 * nb4 + al(nk * 4) + al((size_t)o.nblk * nk * 4));
+            const unsigned kb = (unsigned)((nk + kBlock - 1) / kBlock);
             hipLaunchKernelGGL(k_order_count, dim3(o.nblk), dim3(kOrderThreads), 0, s, o);
-            hipLaunchKernelGGL(k_order_colscan, dim3((unsigned)((nk + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, o);
+            hipLaunchKernelGGL(k_order_segsum, dim3(kb, kOrderSegs), dim3(kBlock), 0, s, o);
+            hipLaunchKernelGGL(k_order_segscan, dim3(kb), dim3(kBlock), 0, s, o);
+            hipLaunchKernelGGL(k_order_colscan, dim3(kb, kOrderSegs), dim3(kBlock), 0, s, o);
             hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, s, o.total, (int)nk);
             hipLaunchKernelGGL(k_order_scatter, dim3(o.nblk), dim3(kOrderThreads), 0, s, o);
             perm = o.perm;
