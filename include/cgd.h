@@ -196,7 +196,8 @@ cgd_status cgd_locate(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, vo
  * are bucketed by tile of consecutive cells and each tile is summed in LDS
  * (the temporary buffers, 12 bytes per particle at F = 1, 20 at F = 2 or 3
  * and 20 + 4 (F - 3) above, come from the mesh workspace); with more than
- * 8192 tiles or 2^32 particles, or CGD_DEPOSIT_DIRECT set in the
+ * 16384 tiles (of 16384 / F cells, a power of two) or 2^32 particles, or
+ * CGD_DEPOSIT_DIRECT set in the
  * environment, every particle is added with a device-wide int64 atomic
  * instead.  Both give the same bits.
  *
@@ -236,7 +237,7 @@ cgd_status cgd_deposit(cgd_mesh m, int64_t n, const float* pos, int32_t F,
  *           (20 at F = 2 or 3, 20 + 4 (F - 3) above) plus
  *           12 bytes per tile of 16384 / F cells, must fit 64 MiB - 4 KiB
  *           (about 5.5M particles at F = 1, 2.8M at F = 4), and the grid at
- *           most 8192 tiles; larger inputs return CGD_E_INVALID with the
+ *           most 16384 tiles; larger inputs return CGD_E_INVALID with the
  *           sizes in cgd_last_error(), and other mesh kinds CGD_E_UNSUPPORTED,
  *           before anything is enqueued.
  *  Every call on a GPU uses that GPU's one array: calls that overlap on the

@@ -140,6 +140,8 @@ constexpr int kTPass = kTChunk / (kTBlock * kTPer);  // register passes per chun
 constexpr int kBPer = 4;                   // particles per thread and register pass of the counting pass
 constexpr int kTileWords = 16384;          // int64 LDS accumulators of one tile workgroup (128 KB)
 constexpr int kMaxTiles = 8192;            // LDS tile counters of the bucketing passes (per snapshot)
+constexpr int kMaxTilesPacked = 2 * kMaxTiles;  // ... as 16-bit halves of the same words (PACK)
+constexpr int kPackMaxChunks = 3;          // chunks per block with 16-bit counters (3 x 16384 < 2^16)
 constexpr int kRectEdges = kRectTiledEdges;  // rectilinear grids: edges of all three axes held in LDS
 
 struct TileArgs {
@@ -180,6 +182,27 @@ struct TileArgs {
     const double* vcell;
 };
 
+// Per-block tile counters in LDS: one 32-bit word per tile, or (PACK, for
+// up to twice the tiles in the same words) two 16-bit counters per word, tile
+// t in half t & 1 of word t >> 1; a block's chunk has fewer than 2^16
+// particles then, so no half carries into the other.
+template <bool PACK>
+__device__ inline uint32_t hist_add(uint32_t* h, int t) {  // returns the count before
+    if constexpr (PACK) {
+        const int sh = (t & 1) << 4;
+        return (atomicAdd(&h[t >> 1], 1u << sh) >> sh) & 0xFFFFu;
+    } else {
+        return atomicAdd(&h[t], 1u);
+    }
+}
+template <bool PACK>
+__device__ inline uint32_t hist_get(const uint32_t* h, int t) {
+    if constexpr (PACK) return (h[t >> 1] >> ((t & 1) << 4)) & 0xFFFFu;
+    else return h[t];
+}
+template <bool PACK>
+__device__ inline int hist_words(int ntiles) { return PACK ? (ntiles + 1) >> 1 : ntiles; }
+
 __device__ inline void snap_range(const TileArgs& a, int j, int64_t& s0, int64_t& s1) {
     s0 = a.off ? a.off[j] : 0;
     s1 = a.off ? a.off[j + 1] : a.total;
@@ -200,7 +223,7 @@ __global__ void k_tile_clear(TileArgs a) {
 // a copy of the edges in LDS: per axis the largest i < n with e_i <= x by
 // binary lifting (steps of decreasing powers of two, the same count for
 // every lane), the kBPer particles of a thread interleaved.
-template <bool RECT>
+template <bool RECT, bool PACK>
 __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
     __shared__ uint32_t hist[kMaxTiles];
     __shared__ double redge[RECT ? kRectEdges : 1];
@@ -212,7 +235,7 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
     const int64_t cb = s0 + (int64_t)blockIdx.x * a.nsub_bin * kTChunk;
     if (cb >= s1) return;  // the whole block: beyond its snapshot's particles
     const int64_t ce = min(cb + (int64_t)a.nsub_bin * kTChunk, s1);
-    for (int t = threadIdx.x; t < a.ntiles; t += kTBlock) hist[t] = 0u;
+    for (int t = threadIdx.x; t < hist_words<PACK>(a.ntiles); t += kTBlock) hist[t] = 0u;
     if (threadIdx.x < CGD_MAX_FIELDS) {
         bmax[threadIdx.x] = 0u;
         bbad[threadIdx.x] = 0ull;
@@ -298,7 +321,7 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
                 ++dropped;
                 nfpos += nf[i] ? 1ull : 0ull;
             } else {
-                atomicAdd(&hist[k[i] >> a.cpt_log2], 1u);
+                (void)hist_add<PACK>(hist, k[i] >> a.cpt_log2);
             }
         }
     }
@@ -345,7 +368,7 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
     __syncthreads();
     uint32_t* counts = a.counts + (size_t)j * a.ntiles;
     for (int t = threadIdx.x; t < a.ntiles; t += kTBlock)
-        if (hist[t]) atomicAdd(&counts[t], hist[t]);
+        if (const uint32_t c = hist_get<PACK>(hist, t)) atomicAdd(&counts[t], c);
     if (threadIdx.x < a.F) {
         const int f = threadIdx.x;
         if (bmax[f]) atomic_max_if_larger(&a.maxbits[j * a.F + f], bmax[f]);
@@ -386,10 +409,10 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scan(TileArgs a) {
 // writes the particles' records there, a register pass of kTPer particles
 // per thread at a time (R16: 16-byte records, in two halves of the pass so
 // that the three values' registers fit).
-template <bool R16>
+template <bool R16, bool PACK>
 __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
     __shared__ uint32_t hist[kMaxTiles];
-    __shared__ uint32_t base[kMaxTiles];
+    __shared__ uint32_t base[PACK ? kMaxTilesPacked : kMaxTiles];
     const int j = blockIdx.y;
     int64_t s0, s1;
     snap_range(a, j, s0, s1);
@@ -397,7 +420,8 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
     if (cb >= s1) return;  // the whole block: beyond its snapshot's particles
     const int64_t ce = min(cb + (int64_t)a.nsub * kTChunk, s1);
     const int64_t c0 = cb + threadIdx.x;
-    for (int t = threadIdx.x; t < a.ntiles; t += kTBlock) hist[t] = 0u;
+    const int nw = hist_words<PACK>(a.ntiles);
+    for (int t = threadIdx.x; t < nw; t += kTBlock) hist[t] = 0u;
     __syncthreads();
     const int npass = a.nsub * kTPass;
     for (int sub = 0; sub < npass; ++sub) {
@@ -410,16 +434,21 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
         }
 #pragma unroll
         for (int i = 0; i < kTPer; ++i)
-            if (kk[i] >= 0) atomicAdd(&hist[kk[i] >> a.cpt_log2], 1u);
+            if (kk[i] >= 0) (void)hist_add<PACK>(hist, kk[i] >> a.cpt_log2);
     }
     __syncthreads();
     // (one cursor atomic in flight per thread: issuing all of a thread's
     // together congested the tile cursors, 173 -> 224 us on the dense bed)
     uint32_t* cursor = a.cursor + (size_t)j * a.ntiles;
-    for (int t = threadIdx.x; t < a.ntiles; t += kTBlock) {
-        const uint32_t c = hist[t];
-        base[t] = c ? atomicAdd(&cursor[t], c) : 0u;
-        hist[t] = 0u;  // reused as the in-block rank counter
+    for (int w = threadIdx.x; w < nw; w += kTBlock) {
+        constexpr int TW = PACK ? 2 : 1;  // tiles per counter word
+        for (int h = 0; h < TW; ++h) {
+            const int t = w * TW + h;
+            if (t >= a.ntiles) break;
+            const uint32_t c = hist_get<PACK>(hist, t);
+            base[t] = c ? atomicAdd(&cursor[t], c) : 0u;
+        }
+        hist[w] = 0u;  // reused as the in-block rank counter
     }
     __syncthreads();
     constexpr int NP = R16 ? kTPer / 2 : kTPer;  // particles per thread in one write pass
@@ -442,7 +471,7 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
         for (int i = 0; i < NP; ++i) {
             if (kk[i] < 0) continue;
             const int t = kk[i] >> a.cpt_log2;
-            slot[i] = base[t] + atomicAdd(&hist[t], 1u);
+            slot[i] = base[t] + hist_add<PACK>(hist, t);
             const uint32_t cl = (uint32_t)(kk[i] & (a.cpt - 1));
             if constexpr (R16)
                 a.rec4[slot[i]] = make_uint4(cl, __float_as_uint(v0[i]), __float_as_uint(v1[i]), __float_as_uint(v2[i]));
@@ -611,12 +640,20 @@ cgd_status locate_hex(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, hi
 // that tile and cell-in-tile are a shift and a mask); false when the direct
 // (atomic) path is used: more tiles per grid than the bucketing passes count
 // in LDS, more particles than 32-bit offsets hold, or CGD_DEPOSIT_DIRECT set.
+// Up to kMaxTiles tiles the counters are 32-bit words, up to
+// kMaxTilesPacked 16-bit halves (the bucketing passes' PACK variant).
+// CGD_DEPOSIT_CPT forces a smaller power-of-two tile (at least 16 cells), so
+// that tests reach many tiles on small grids.
 static bool tile_plan(int64_t cells, int64_t total, int32_t F, int* cpt, int* ntiles) {
     if (getenv("CGD_DEPOSIT_DIRECT") || total <= 0 || total >= (int64_t)UINT32_MAX) return false;
     int c = kTileWords;  // the largest power of two with F * c <= kTileWords
     while (c * F > kTileWords) c >>= 1;
+    if (const char* e = getenv("CGD_DEPOSIT_CPT")) {
+        const int w = atoi(e);
+        if (w >= 16 && (w & (w - 1)) == 0 && w < c) c = w;
+    }
     const int64_t t = (cells + c - 1) / c;
-    if (t > kMaxTiles) return false;
+    if (t > kMaxTilesPacked) return false;
     *cpt = c;
     *ntiles = (int)t;
     return true;
@@ -673,6 +710,11 @@ cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipS
     a.ntiles = nt;
     a.nsub = tile_nsub("CGD_DEPOSIT_NSUB");
     a.nsub_bin = tile_nsub("CGD_DEPOSIT_BIN_NSUB");
+    const bool pack = nt > kMaxTiles;
+    if (pack) {  // 16-bit counters: fewer than 2^16 particles per block
+        a.nsub = std::min(a.nsub, kPackMaxChunks);
+        a.nsub_bin = std::min(a.nsub_bin, kPackMaxChunks);
+    }
     a.cellbuf = reinterpret_cast<int32_t*>(t);
     t += al256(4 * (size_t)d.total);
     a.rec = reinterpret_cast<uint2*>(t);
@@ -710,13 +752,23 @@ cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipS
     const double np_ = (double)d.total;
     int tm = timing ? timing_begin(timing, s) : -1;
     int t13 = timing ? timing_begin(timing, s) : -1;
-    if (d.rect) hipLaunchKernelGGL(k_tile_bin<true>, dim3(cblocks, d.n_snap), dim3(kTBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_tile_bin<false>, dim3(cblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    if (d.rect) {
+        if (pack) hipLaunchKernelGGL((k_tile_bin<true, true>), dim3(cblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_tile_bin<true, false>), dim3(cblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    } else {
+        if (pack) hipLaunchKernelGGL((k_tile_bin<false, true>), dim3(cblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_tile_bin<false, false>), dim3(cblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    }
     if (timing) timing_end(timing, t13, 13, (12.0 + 4.0 * d.F + 4.0) * np_, s);
     int t14 = timing ? timing_begin(timing, s) : -1;
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kTBlock), 0, s, a);
-    if (d.F >= 2) hipLaunchKernelGGL(k_tile_scatter<true>, dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_tile_scatter<false>, dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    if (d.F >= 2) {
+        if (pack) hipLaunchKernelGGL((k_tile_scatter<true, true>), dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_tile_scatter<true, false>), dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    } else {
+        if (pack) hipLaunchKernelGGL((k_tile_scatter<false, true>), dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_tile_scatter<false, false>), dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    }
     const double recb = (double)rec_bytes(d.F) + 4.0 * (double)rv_fields(d.F);  // bytes written per particle
     if (timing) timing_end(timing, t14, 14, (4.0 + 4.0 * d.F + recb) * np_, s);
     int t15 = timing ? timing_begin(timing, s) : -1;

@@ -86,7 +86,7 @@ extern "C" cgd_status cgd_deposit_noalloc(cgd_mesh m, int64_t n, const float* po
                   " fields need " + (temp ? std::to_string(temp) + " bytes of scratch" : std::string("the direct path")) +
                   "; the limit is " + std::to_string(kNoAllocBytes - kInfoBytes) +
                   " bytes (12 bytes per particle at F = 1, 20 at F = 2 or 3, 20 + 4 (F - 3) above) on grids of "
-                  "at most 8192 tiles");
+                  "at most 16384 tiles");
         return CGD_E_INVALID;
     }
     int prev = -1;

@@ -91,6 +91,32 @@ def test_deposit_dense_bed_single_field_many_tiles_bit_exact(gpu_lib):
     assert int(a.sum()) == int(O.quantise(w.particles.values[0], ref["S"][0]).sum())
 
 
+@pytest.mark.parametrize("shape,cpt,F", [((64, 64, 64), 32, 1), ((64, 64, 64), 16, 1), ((64, 64, 64), 16, 4),
+                                         ((60, 61, 67), 16, 2), ((64, 64, 65), 16, 1)])
+def test_deposit_tile_counts_bit_exact(gpu_lib, shape, cpt, F, monkeypatch):
+    """Tiles forced small (CGD_DEPOSIT_CPT) to reach the bucketing passes'
+    tile limits on small grids: 8,192 tiles (32-bit counters), 16,384 (two
+    16-bit counters per word), a ragged 15,327 at two fields and 16,384 at
+    four, and 16,640 (beyond both: the direct path).  Clustered particles
+    (the dense-bed recipe), so that some tiles take thousands of one block's
+    particles; accumulators and fields bit-identical to the oracle's."""
+    import torch
+    cgd = gpu_lib
+    monkeypatch.setenv("CGD_DEPOSIT_CPT", str(cpt))
+    w = inputs.dense_bed(n_particles=300_000, shape=shape, n_fields=F)
+    print(f"case: {w.name}, {cpt} cells per tile", flush=True)
+    mesh = cgd.HexMesh(w.box.shape, w.box.lo, w.box.hi)
+    acc = torch.empty((F, mesh.cells), dtype=torch.int64, device="cuda")
+    field, st = cgd.deposit(mesh, _t(w.particles.pos, torch), _t(w.particles.values, torch), acc=acc, stats=True)
+    ref = O.deposit_hex(w.particles.pos, w.particles.values, w.box.lo, w.box.hi, w.box.shape)
+    assert st.frac_bits[:F] == ref["S"]
+    assert np.array_equal(acc.cpu().numpy(), ref["acc"])
+    assert np.array_equal(field.cpu().numpy().view(np.uint32), ref["field32"].view(np.uint32))
+    a = acc.cpu().numpy()[0]
+    per_tile = np.add.reduceat((a != 0).astype(np.int64), np.arange(0, mesh.cells, cpt))
+    assert per_tile.max() == cpt and per_tile.min() == 0  # crowded and empty tiles
+
+
 @pytest.mark.parametrize("path", ["tiled", "direct"])
 def test_deposit_forced_frac_bits(gpu_lib, path, monkeypatch):
     """cgd_deposit's frac_bits: a forced scale for one field, automatic for
