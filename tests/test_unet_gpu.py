@@ -37,16 +37,20 @@ def _bf(a, torch):
 
 # ragged in every direction: two x bricks (16 + 4), y not a multiple of 4, z of 4
 GRID = (6, 7, 20)  # (nz, ny, nx)
+# and the three levels of the (24, 12, 20) network grid: every brick ragged,
+# the coarsest level one brick of 6 x 3 x 5 voxels
+GRIDS = [GRID, (20, 12, 24), (10, 6, 12), (5, 3, 6)]
 
 
+@pytest.mark.parametrize("grid", GRIDS)
 @pytest.mark.parametrize("ci,co", [(1, 16), (16, 16), (16, 32), (32, 16), (32, 32), (32, 64), (64, 32),
                                    (64, 64), (16, 64)])
-def test_conv_forward_matches_oracle(gpu_lib, ci, co):
+def test_conv_forward_matches_oracle(gpu_lib, ci, co, grid):
     import torch
     cgd = gpu_lib
     rng = np.random.default_rng(1000 + ci * 100 + co)
-    print(f"case: conv forward ci={ci} co={co} grid={GRID}", flush=True)
-    x, x64 = _bf(rng.standard_normal(GRID + (ci,)), torch)
+    print(f"case: conv forward ci={ci} co={co} grid={grid}", flush=True)
+    x, x64 = _bf(rng.standard_normal(grid + (ci,)), torch)
     w, w64 = _bf(rng.standard_normal((co, 27, ci)) / np.sqrt(27 * ci), torch)
     b = rng.standard_normal(co).astype(np.float32)
     y = cgd.conv3_forward(x, w, torch.from_numpy(b).cuda(), relu=True)
@@ -57,13 +61,14 @@ def test_conv_forward_matches_oracle(gpu_lib, ci, co):
     assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5)
 
 
+@pytest.mark.parametrize("grid", GRIDS)
 @pytest.mark.parametrize("ci,co", [(16, 16), (16, 32), (32, 16), (32, 64), (64, 32), (64, 64)])
-def test_conv_dgrad_matches_oracle(gpu_lib, ci, co):
+def test_conv_dgrad_matches_oracle(gpu_lib, ci, co, grid):
     import torch
     cgd = gpu_lib
     rng = np.random.default_rng(2000 + ci * 100 + co)
-    print(f"case: conv dgrad ci={ci} co={co} grid={GRID}", flush=True)
-    g, g64 = _bf(rng.standard_normal(GRID + (co,)), torch)
+    print(f"case: conv dgrad ci={ci} co={co} grid={grid}", flush=True)
+    g, g64 = _bf(rng.standard_normal(grid + (co,)), torch)
     w, w64 = _bf(rng.standard_normal((co, 27, ci)) / np.sqrt(27 * co), torch)
     dx = cgd.conv3_dgrad(g, w).float().cpu().numpy()
     ref = U.conv3_dgrad(g64, w64)
