@@ -199,7 +199,12 @@ cgd_status cgd_locate(cgd_mesh m, int64_t n, const float* pos, int32_t* cell, vo
  * 16384 tiles (of 16384 / F cells, a power of two) or 2^32 particles, or
  * CGD_DEPOSIT_DIRECT set in the
  * environment, every particle is added with a device-wide int64 atomic
- * instead.  Both give the same bits.
+ * instead.  Both give the same bits.  On tet meshes every particle is added
+ * with a device-wide int64 atomic after its walk to the host tet; from 4,096
+ * particles the walks are taken in a coarse spatial order (a counting sort
+ * by blocks of the point-location buckets: 8 bytes per particle plus
+ * per-block key histograms, from the mesh workspace; CGD_TET_INPUT_ORDER
+ * set: input order), which changes no bit of the result.
  *
  *  n:       number of particles (>= 0)
  *  pos:     device float32 [n, 3]
