@@ -636,12 +636,15 @@ def tet_faces(tets):
     return P, N, ts[i]
 
 
-def tet_tpfa(xyz, tets):
+def tet_tpfa(xyz, tets, diffusivity=None):
     """Two-point-flux FV Laplacian K on a tet mesh and cell volumes.
 
-    Interior face f between P and N: a_f = |A_f| / |c_N - c_P| (face area
-    over the distance between tet centroids).  Boundary faces carry no flux.
-    No non-orthogonal correction.  Returns (K csr, V [tets]).
+    Interior face f between P and N: a_f = D_f |A_f| / |c_N - c_P| (face
+    area over the distance between tet centroids, times the face
+    diffusivity D_f = face_diffusivity(D_P, D_N), the harmonic mean of the
+    two cells' diffusivities (Section 5.2's local diffusion constant); D = 1
+    when diffusivity is None).  Boundary faces carry no flux.  No
+    non-orthogonal correction.  Returns (K csr, V [tets]).
     """
     xyz = np.asarray(xyz, dtype=np.float64)
     V, _ = tet_volumes(xyz, tets)
@@ -653,6 +656,9 @@ def tet_tpfa(xyz, tets):
     area = 0.5 * np.linalg.norm(np.cross(u, w), axis=1)
     dist = np.linalg.norm(c[N] - c[P], axis=1)
     coef = area / dist
+    if diffusivity is not None:
+        D = np.asarray(diffusivity, dtype=np.float64)
+        coef = coef * face_diffusivity(D[P], D[N])
     n = len(V)
     diag = np.zeros(n)
     np.add.at(diag, P, coef)
@@ -756,8 +762,9 @@ def deposit_tet(xyz, tets, pos, values, cells=None):
                 n_dropped=int((~mask).sum()))
 
 
-def diffuse_tet(field, xyz, tets, bandwidth, n_steps, solver="cg", rtol=1e-12, scheme="be"):
+def diffuse_tet(field, xyz, tets, bandwidth, n_steps, solver="cg", rtol=1e-12, scheme="be", diffusivity=None):
     """Diffusion of tet-cell fields with the TPFA Laplacian (scheme "be":
-    backward Euler, "cn": Crank-Nicolson)."""
-    K, V = tet_tpfa(xyz, tets)
+    backward Euler, "cn": Crank-Nicolson), with a cell-wise diffusivity
+    scaling the face fluxes when given."""
+    K, V = tet_tpfa(xyz, tets, diffusivity)
     return _integrator(scheme)(V, K, field, pseudo_time(bandwidth), n_steps, solver, rtol)

@@ -363,6 +363,44 @@ def test_tpfa_properties():
     assert math.isclose(-K0[P[0], N[0]], area / np.linalg.norm(c[P[0]] - c[N[0]]))
 
 
+def test_tpfa_cellwise_diffusivity():
+    """Section 5.2's local diffusion constant on a tet mesh: face flux
+    scaled by the harmonic mean of the two cells' diffusivities.
+    - D = 1 everywhere gives the unscaled operator bit for bit, D = c
+      everywhere c K exactly (a dropped or doubled factor fails);
+    - one face by hand, D = 1 and 3 on its two tets: 1.5 a_f (the arithmetic
+      mean would give 2);
+    - cells with D = 0 exchange nothing: their rows and columns of K vanish,
+      so backward Euler keeps their values (PCM there, the use the paper
+      names), while the rest diffuses and the total is conserved."""
+    xyz, tets = inputs.kuhn_tet_mesh(4, 0.2, seed=14)
+    n = len(tets)
+    K1, V = O.tet_tpfa(xyz, tets)
+    Kone, _ = O.tet_tpfa(xyz, tets, np.ones(n))
+    assert (K1 != Kone).nnz == 0
+    K3, _ = O.tet_tpfa(xyz, tets, np.full(n, 3.0))
+    assert np.allclose(K3.toarray(), 3.0 * K1.toarray(), rtol=1e-15, atol=0)
+    P, N, tri = O.tet_faces(tets)
+    D = np.ones(n)
+    D[N[0]] = 3.0
+    KD, _ = O.tet_tpfa(xyz, tets, D)
+    assert math.isclose(KD[P[0], N[0]], 1.5 * K1[P[0], N[0]], rel_tol=1e-15)
+    # a block of frozen cells (D = 0 in the tets whose centroid has x < 0.3)
+    c = xyz[tets].mean(axis=1)
+    frozen = c[:, 0] < 0.3
+    D = np.where(frozen, 0.0, 1.0 + c[:, 1])
+    KD, V = O.tet_tpfa(xyz, tets, D)
+    Kd = KD.toarray()
+    assert np.all(Kd[frozen] == 0) and np.all(Kd[:, frozen] == 0)
+    assert np.allclose(Kd, Kd.T) and np.allclose(Kd.sum(axis=1), 0, atol=1e-14)
+    e0 = np.random.default_rng(15).random(n)
+    e = O.diffuse_tet(e0, xyz, tets, 0.5, 2, solver="direct", diffusivity=D)
+    # (to the sparse LU's rounding: the frozen rows are V_i x_i = V_i e_i)
+    assert np.allclose(e[frozen], e0[frozen], rtol=1e-13, atol=0)
+    assert not np.allclose(e[~frozen], e0[~frozen])
+    assert math.isclose((V * e).sum(), (V * e0).sum(), rel_tol=1e-12)
+
+
 def test_point_location_against_barycentric_brute_force():
     xyz, tets = inputs.kuhn_tet_mesh(4, 0.2, seed=11)
     rng = np.random.default_rng(12)
