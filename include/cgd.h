@@ -80,6 +80,18 @@ cgd_status cgd_mesh_create_hex(int32_t nx, int32_t ny, int32_t nz,
 cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz,
                                int64_t n_tet, const int32_t* tv, cgd_mesh* out);
 
+/* Tetrahedral mesh with a cell-wise diffusivity (Section 5.2: a small local
+ * diffusion constant, e.g. 0 where the cells are large, so that PCM applies
+ * there while mass stays conserved).  As cgd_mesh_create_tet, with each
+ * interior face's coefficient a_f = D_f |A_f| / |c_N - c_P|, D_f the
+ * harmonic mean 2 D_P D_N / (D_P + D_N) of the two tets' diffusivities (0
+ * when either is 0: a tet with D = 0 exchanges nothing and keeps its
+ * deposited value), in float64, rounded once.  diffusivity: host float32
+ * [n_tet], finite and >= 0 (else CGD_E_INVALID), or NULL for 1 everywhere
+ * (then the same mesh as cgd_mesh_create_tet). */
+cgd_status cgd_mesh_create_tet_d(int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tv,
+                                 const float* diffusivity, cgd_mesh* out);
+
 /* Stretched (rectilinear) hex mesh with a cell-wise diffusivity (Section
  * 4.3: stretched meshes; Section 5.2: a small local diffusion constant
  * degenerates the method to PCM there, conservation kept).  x_edges, y_edges,

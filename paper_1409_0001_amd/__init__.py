@@ -126,9 +126,11 @@ class HexMesh(Mesh):
 
 
 class TetMesh(Mesh):
-    """Tetrahedral mesh from host arrays xyz float64 [V, 3] and tets int32 [T, 4]."""
+    """Tetrahedral mesh from host arrays xyz float64 [V, 3] and tets int32
+    [T, 4], with an optional cell-wise diffusivity (float32 [T], >= 0; None:
+    1 everywhere)."""
 
-    def __init__(self, xyz, tets):
+    def __init__(self, xyz, tets, diffusivity=None):
         import numpy as np
         _torch()
         lib = _abi.load()
@@ -137,8 +139,15 @@ class TetMesh(Mesh):
         if xyz.ndim != 2 or xyz.shape[1] != 3 or tets.ndim != 2 or tets.shape[1] != 4:
             raise ValueError("xyz must be [V, 3] and tets [T, 4]")
         h = _abi.c_mesh()
-        _check(lib.cgd_mesh_create_tet(xyz.shape[0], xyz.ctypes.data, tets.shape[0], tets.ctypes.data,
-                                       ctypes.byref(h)), "cgd_mesh_create_tet", allow=(0,))
+        if diffusivity is None:
+            _check(lib.cgd_mesh_create_tet(xyz.shape[0], xyz.ctypes.data, tets.shape[0], tets.ctypes.data,
+                                           ctypes.byref(h)), "cgd_mesh_create_tet", allow=(0,))
+        else:
+            d = np.ascontiguousarray(diffusivity, dtype=np.float32).ravel()
+            if d.shape[0] != tets.shape[0]:
+                raise ValueError("diffusivity must have one value per tet")
+            _check(lib.cgd_mesh_create_tet_d(xyz.shape[0], xyz.ctypes.data, tets.shape[0], tets.ctypes.data,
+                                             d.ctypes.data, ctypes.byref(h)), "cgd_mesh_create_tet_d", allow=(0,))
         super().__init__(h)
         self.nnz = int(lib.cgd_mesh_nnz(h))
 

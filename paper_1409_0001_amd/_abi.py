@@ -58,6 +58,8 @@ SIGNATURES = {
                                              ctypes.POINTER(c_mesh)]),
     "cgd_mesh_create_tet": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                              ctypes.c_void_p, ctypes.POINTER(c_mesh)]),
+    "cgd_mesh_create_tet_d": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(c_mesh)]),
     "cgd_mesh_create_rect": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_int32, ctypes.POINTER(c_mesh)]),

@@ -1437,6 +1437,11 @@ using namespace cgd;
 
 extern "C" cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tv,
                                           cgd_mesh* out) {
+    return cgd_mesh_create_tet_d(n_vert, xyz, n_tet, tv, nullptr, out);
+}
+
+extern "C" cgd_status cgd_mesh_create_tet_d(int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tv,
+                                            const float* diffusivity, cgd_mesh* out) {
     if (!out || !xyz || !tv) {
         set_error("cgd_mesh_create_tet: null pointer");
         return CGD_E_INVALID;
@@ -1445,7 +1450,7 @@ extern "C" cgd_status cgd_mesh_create_tet(int64_t n_vert, const double* xyz, int
     TetHost h;
     cgd_status rc;
     try {
-        rc = build_tet_host(n_vert, xyz, n_tet, tv, &h);
+        rc = build_tet_host(n_vert, xyz, n_tet, tv, diffusivity, &h);
     } catch (const std::bad_alloc&) {
         set_error("cgd_mesh_create_tet: host allocation failed");
         return CGD_E_NOMEM;

@@ -66,7 +66,9 @@ struct TetData {
 cgd_status cheb_operator_setup(TetData* t, const std::vector<float>& kface, const std::vector<float>& kface2,
                                const std::vector<double>& vol);
 
-cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tv, TetHost* out);
+// D: cell-wise diffusivity [n_tet] (nullable: 1 everywhere).
+cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tv, const float* D,
+                          TetHost* out);
 
 size_t diffuse_tet_workspace(const cgd_mesh m, int32_t F);
 

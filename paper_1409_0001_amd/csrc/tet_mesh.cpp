@@ -7,9 +7,10 @@
 // table this builds:
 //   - volumes V = det[v1-v0, v2-v0, v3-v0] / 6 (positive orientation required)
 //   - interior faces by matching the sorted vertex triples of all tet faces
-//   - the two-point-flux Laplacian K: a_f = |A_f| / |c_N - c_P| between the
-//     centroids of the two tets of each interior face; boundary faces carry
-//     no flux.  K is stored as a sparse matrix with rows padded to the four
+//   - the two-point-flux Laplacian K: a_f = D_f |A_f| / |c_N - c_P| between
+//     the centroids of the two tets of each interior face (D_f the harmonic
+//     mean of the two tets' diffusivities, 1 without them); boundary faces
+//     carry no flux.  K is stored as a sparse matrix with rows padded to the four
 //     face slots a tet has: row t's off-diagonal entries are -a_f at columns
 //     nbr[t][j] (float32 values, int32 columns; a boundary slot holds the
 //     tet's own id and 0), the diagonal K_tt = sum of the tet's a_f
@@ -73,11 +74,20 @@ inline double det3(const double* a, const double* b, const double* c, const doub
 
 }  // namespace
 
-cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tv,
+cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, const int32_t* tv, const float* D,
                           TetHost* out) {
     if (n_vert < 4 || n_tet < 1 || n_tet > (int64_t)INT32_MAX / 8 || n_vert > INT32_MAX) {
         set_error("cgd_mesh_create_tet: need n_vert >= 4 and 1 <= n_tet < 2^28");
         return CGD_E_INVALID;
+    }
+    if (D) {
+        for (int64_t t = 0; t < n_tet; ++t) {
+            if (!(D[t] >= 0.f) || !isfinite(D[t])) {
+                set_error("cgd_mesh_create_tet_d: diffusivity must be finite and >= 0 (tet " + std::to_string(t) +
+                          ")");
+                return CGD_E_INVALID;
+            }
+        }
     }
     const int32_t nt = (int32_t)n_tet;
     out->n_vert = n_vert;
@@ -172,7 +182,13 @@ cgd_status build_tet_host(int64_t n_vert, const double* xyz, int64_t n_tet, cons
             const double dc[3] = {cen[(size_t)N * 3] - cen[(size_t)P * 3], cen[(size_t)N * 3 + 1] - cen[(size_t)P * 3 + 1],
                                   cen[(size_t)N * 3 + 2] - cen[(size_t)P * 3 + 2]};
             const double dist = sqrt(dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2]);
-            const double af = area / dist;
+            double af = area / dist;
+            if (D) {
+                // the face diffusivity: harmonic mean of the two cells' D,
+                // 0 when either is 0 (Section 5.2's local diffusion constant)
+                const double da = (double)D[P], db = (double)D[N];
+                af = af * ((da > 0.0 && db > 0.0) ? 2.0 * da * db / (da + db) : 0.0);
+            }
             out->nbr[(size_t)P * 4 + faces[i].j] = N;
             out->nbr[(size_t)N * 4 + faces[i + 1].j] = P;
             out->kface[(size_t)P * 4 + faces[i].j] = (float)af;
