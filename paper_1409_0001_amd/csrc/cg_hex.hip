@@ -1061,9 +1061,8 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, co
     // keeps two halo rows and planes, tile_precond2; condition number 13 ->
     // 2.1 at dtau / h^2 = 1), degree 1 otherwise (13 -> 3.8).
     // Where the grid fills the machine with z chunks of at least D planes
-    // (lds_plan), the degree rises to 4 (13 -> 1.26), applied by
-    // k_precond_lds with the intermediate powers in LDS.
-    // CGD_HEX_PRECOND_DEG (2, 3, 4) and CGD_HEX_LDS_ZC override the choice.
+    // (lds_plan), the degree rises to 4, 8 or 12, applied by k_precond_lds
+    // (below).
     const bool pcg = da.precond == 0 || ro;  // the rectilinear operator runs preconditioned CG only
     const bool row_wave = !p.edge && p.xsegs == 1;  // one wave per x-row (possibly partial)
     const int deg = (pcg && row_wave && !ro) ? 2 : 1;  // rectilinear: Jacobi (the SZ modes)
