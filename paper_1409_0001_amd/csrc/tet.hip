@@ -513,7 +513,7 @@ __global__ void k_tet_dinv(const float* volf, const float* kdiag, float dtau, fl
 // maximum (symmetric: both rows of a face hold the same rounding), so that
 // p(B) H = H^1/2 p(H^1/2 A~ H^1/2) H^1/2 is symmetric.  p is the Chebyshev
 // polynomial of even degree m that makes 1 - l p(l) smallest on [lmin, lmax]
-// (the spectrum estimate of B, chosen per step), evaluated as a product of
+// (the spectrum estimate of B, from dtau once per call), evaluated as a product of
 // m / 2 quadratic factors g_k (B^2 + s_k B + q_k), each in two passes:
 //   pass 1: w = B v                 (v gathered at the face neighbours)
 //   pass 2: v = g_k ((1 + s_k) w - h kappa sum_f a~_f w_j + q_k v)
