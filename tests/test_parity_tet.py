@@ -235,6 +235,15 @@ def test_tet_cellwise_diffusivity_matches_oracle(gpu_lib, precond, scheme):
         Db[3] = bad
         with pytest.raises(cgd.CgdError):
             cgd.TetMesh(xyz, tets, diffusivity=Db)
+    # D = 0 everywhere: no face carries flux, every tet keeps its deposited
+    # value (the degenerate operator M, solved without a polynomial)
+    if precond == 0 and scheme == "be":
+        mz = cgd.TetMesh(xyz, tets, diffusivity=np.zeros(len(tets), np.float32))
+        oz, sz = cgd.coarse_grain(mz, _t(pos, torch), _t(vals, torch), b, steps, rtol=1e-7, stats=True)
+        assert sz.status == 0
+        for f in range(2):
+            d = dep["field64"][f]
+            assert np.abs(oz.cpu().numpy()[f] - d).max() <= 1e-6 * np.abs(d).max()
 
 
 def test_tet_invalid_meshes(gpu_lib):
