@@ -494,6 +494,84 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
     }
 }
 
+// Pass 3 at F = 1 on grids of at most kStageMaxTiles tiles, staged in LDS
+// (grid: blocks x snapshots, one kTChunk chunk per block).  A block's run of
+// records in a tile is short (about 8 on the dense bed), so records written
+// straight from the particles' registers reach each cache line one at a time
+// and lines left partly written in L2 go to HBM piecewise (2.5 bytes written
+// per record byte).  Here the block ranks its particles per tile with LDS
+// atomics, prefix-sums the counts, places every record at its tile's
+// block-local position in LDS, reserves one range per tile from the cursors,
+// and then writes the staged records in order: consecutive lanes store
+// consecutive records of a run.  The cell ids and values are read once.
+constexpr int kStageMaxTiles = 2 * kTBlock;  // the prefix sum takes two tiles per thread
+static_assert(kTPer * kTBlock == kTChunk, "one register pass covers the chunk");
+__global__ __launch_bounds__(kTBlock) void k_tile_scatter_staged(TileArgs a) {
+    __shared__ uint2 stage[kTChunk];           // (cell, value bits), tile by tile
+    __shared__ uint32_t hist[kStageMaxTiles];  // the block's particles per tile
+    __shared__ uint32_t loc[kStageMaxTiles];   // block-local start of each tile's run
+    __shared__ uint32_t base[kStageMaxTiles];  // its start in the tile's global range
+    __shared__ uint32_t wsum[kTBlock / 64];
+    const int j = blockIdx.y;
+    int64_t s0, s1;
+    snap_range(a, j, s0, s1);
+    const int64_t cb = s0 + (int64_t)blockIdx.x * kTChunk;
+    if (cb >= s1) return;  // the whole block: beyond its snapshot's particles
+    const int64_t ce = min(cb + (int64_t)kTChunk, s1);
+    const int nt = a.ntiles;  // <= kStageMaxTiles (host)
+    for (int t = threadIdx.x; t < nt; t += kTBlock) hist[t] = 0u;
+    int32_t kk[kTPer];
+    uint32_t vv[kTPer];
+#pragma unroll
+    for (int i = 0; i < kTPer; ++i) {
+        const int64_t p = cb + threadIdx.x + (int64_t)i * kTBlock;
+        kk[i] = p < ce ? a.cellbuf[p] : -1;
+        vv[i] = p < ce ? __float_as_uint(a.values[p]) : 0u;
+    }
+    __syncthreads();
+    uint32_t rank[kTPer];
+#pragma unroll
+    for (int i = 0; i < kTPer; ++i) rank[i] = kk[i] >= 0 ? atomicAdd(&hist[kk[i] >> a.cpt_log2], 1u) : 0u;
+    __syncthreads();
+    // exclusive prefix sum of the counts: tiles 2 tid and 2 tid + 1 per thread,
+    // a wave scan by shuffles, then the wave totals
+    const int t0 = 2 * (int)threadIdx.x;
+    const uint32_t h0 = t0 < nt ? hist[t0] : 0u, h1 = t0 + 1 < nt ? hist[t0 + 1] : 0u;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = h0 + h1;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    uint32_t* cursor = a.cursor + (size_t)j * nt;
+    for (int t = threadIdx.x; t < nt; t += kTBlock) {
+        const uint32_t c = hist[t];
+        base[t] = c ? atomicAdd(&cursor[t], c) : 0u;
+    }
+    __syncthreads();
+    uint32_t before = 0u, total = 0u;
+    for (int w = 0; w < kTBlock / 64; ++w) {
+        const uint32_t s = wsum[w];
+        before += w < wave ? s : 0u;
+        total += s;
+    }
+    const uint32_t ex = before + incl - (h0 + h1);
+    if (t0 < nt) loc[t0] = ex;
+    if (t0 + 1 < nt) loc[t0 + 1] = ex + h0;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kTPer; ++i)
+        if (kk[i] >= 0) stage[loc[kk[i] >> a.cpt_log2] + rank[i]] = make_uint2((uint32_t)kk[i], vv[i]);
+    __syncthreads();
+    const uint32_t mask = (uint32_t)a.cpt - 1u;
+    for (uint32_t k = threadIdx.x; k < total; k += kTBlock) {
+        const uint2 e = stage[k];
+        const uint32_t t = e.x >> a.cpt_log2;
+        a.rec[base[t] + (k - loc[t])] = make_uint2(e.x & mask, e.y);
+    }
+}
+
 __device__ inline long long quantise(float v, int S) {
     return isfinite(v) ? __double2ll_rn(ldexp((double)v, S)) : 0ll;
 }
@@ -765,6 +843,8 @@ cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipS
     if (d.F >= 2) {
         if (pack) hipLaunchKernelGGL((k_tile_scatter<true, true>), dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
         else hipLaunchKernelGGL((k_tile_scatter<true, false>), dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
+    } else if (nt <= kStageMaxTiles && a.nsub == 1) {
+        hipLaunchKernelGGL(k_tile_scatter_staged, dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
     } else {
         if (pack) hipLaunchKernelGGL((k_tile_scatter<false, true>), dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
         else hipLaunchKernelGGL((k_tile_scatter<false, false>), dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
