@@ -108,17 +108,21 @@ def test_batched_conserves_each_snapshot(gpu_lib):
             assert abs(out[j, f].sum() * V - m_in) <= 1e-5 * scale
 
 
-def test_batched_tiled_and_direct_deposits_agree_bitwise(gpu_lib, monkeypatch):
+@pytest.mark.parametrize("F", [4, 1])
+def test_batched_tiled_and_direct_deposits_agree_bitwise(gpu_lib, F, monkeypatch):
     """The tiled deposit (particles bucketed by tile of every snapshot, sums
     in LDS) and the direct one (int64 atomics) are both exact, and the solve
     is deterministic, so the batched results agree bit for bit; snapshots
-    span many tiles, one is empty and one holds a single particle."""
+    span many tiles, one is empty and one holds a single particle.  F = 4:
+    96 tiles of 4096 cells per snapshot, records stored from registers; F = 1:
+    24 tiles of 16384, records ordered by tile in LDS first."""
     import torch
     cgd = gpu_lib
-    shape = (128, 64, 48)  # 96 tiles of 4096 cells per snapshot at F = 4
+    shape = (128, 64, 48)
     counts = [60_000, 0, 1, 25_000, 90_000]
     box, parts, pos, vals, off = _batch(shape, counts, seed=97)
-    print(f"case: batched tiled vs direct deposit {shape} snapshots {counts}", flush=True)
+    vals = np.ascontiguousarray(vals[:F])
+    print(f"case: batched tiled vs direct deposit {shape} F={F} snapshots {counts}", flush=True)
     mesh = cgd.HexMesh(shape, box.lo, box.hi)
     dpos, dvals = _t(pos, torch), _t(vals, torch)
     monkeypatch.delenv("CGD_DEPOSIT_DIRECT", raising=False)

@@ -148,10 +148,13 @@ def test_deposit_forced_frac_bits(gpu_lib, path, monkeypatch):
             cgd.deposit(mesh, _t(p.pos, torch), _t(p.values, torch), frac_bits=bad)
 
 
+@pytest.mark.parametrize("F", [4, 1])
 @pytest.mark.parametrize("path", ["tiled", "direct"])
-def test_deposit_signed_multifield_ragged_and_dropped(gpu_lib, path, monkeypatch):
+def test_deposit_signed_multifield_ragged_and_dropped(gpu_lib, path, F, monkeypatch):
     """Both deposit paths: tile-bucketed sums in LDS (default) and direct
-    device-wide atomics (CGD_DEPOSIT_DIRECT)."""
+    device-wide atomics (CGD_DEPOSIT_DIRECT); at one field the tiled path's
+    records are ordered by tile in LDS before they are stored, at four they
+    are stored from registers (16-byte records plus a value array)."""
     import torch
     cgd = gpu_lib
     if path == "direct":
@@ -163,15 +166,15 @@ def test_deposit_signed_multifield_ragged_and_dropped(gpu_lib, path, monkeypatch
     pos = p.pos.copy()
     pos[:50] += 0.5   # some outside the box
     pos[50, 1] = np.nan
-    vals = p.values.copy()
-    vals[2, 60] = np.inf
-    print(f"case: ragged 37x29x11, F=4, dropped/non-finite, {path} deposit", flush=True)
+    vals = p.values[:F].copy()
+    vals[min(2, F - 1), 60] = np.inf
+    print(f"case: ragged 37x29x11, F={F}, dropped/non-finite, {path} deposit", flush=True)
     mesh = cgd.HexMesh(box.shape, box.lo, box.hi)
-    acc = torch.empty((4, mesh.cells), dtype=torch.int64, device="cuda")
+    acc = torch.empty((F, mesh.cells), dtype=torch.int64, device="cuda")
     field, st = cgd.deposit(mesh, _t(pos, torch), _t(vals, torch), acc=acc, stats=True)
     ref = O.deposit_hex(pos, vals, box.lo, box.hi, box.shape)
     assert st.status == -2  # CGD_E_NONFINITE reported, field still written
-    assert st.frac_bits[:4] == ref["S"]
+    assert st.frac_bits[:F] == ref["S"]
     assert st.n_dropped == ref["n_dropped"]
     assert np.array_equal(acc.cpu().numpy(), ref["acc"])
     assert np.array_equal(field.cpu().numpy().view(np.uint32), ref["field32"].view(np.uint32))
