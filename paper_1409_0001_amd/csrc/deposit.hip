@@ -494,8 +494,8 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
     }
 }
 
-// Pass 3 at F = 1 on grids of at most kStageMaxTiles tiles, staged in LDS
-// (grid: blocks x snapshots, one kTChunk chunk per block).  A block's run of
+// Pass 3 for F <= 4 on grids of at most kStageMaxTiles tiles, staged in LDS
+// (grid: blocks x snapshots, C particles per block).  A block's run of
 // records in a tile is short (about 8 on the dense bed), so records written
 // straight from the particles' registers reach each cache line one at a time
 // and lines left partly written in L2 go to HBM piecewise (2.5 bytes written
@@ -504,34 +504,46 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scatter(TileArgs a) {
 // block-local position in LDS, reserves one range per tile from the cursors,
 // and then writes the staged records in order: consecutive lanes store
 // consecutive records of a run.  The cell ids and values are read once.
+// NV fields: the 8-byte record at NV = 1, the 16-byte record (fields 0..2)
+// above, and at NV = 4 field 3's value in its own staged array.  C is as
+// large as the LDS allows: 16384 at NV = 1, 8192 at 2 or 3, 4096 at 4.
 constexpr int kStageMaxTiles = 2 * kTBlock;  // the prefix sum takes two tiles per thread
-static_assert(kTPer * kTBlock == kTChunk, "one register pass covers the chunk");
+template <int NV>
+struct StageRec { using T = uint4; };
+template <>
+struct StageRec<1> { using T = uint2; };
+template <int C, int NV>
 __global__ __launch_bounds__(kTBlock) void k_tile_scatter_staged(TileArgs a) {
-    __shared__ uint2 stage[kTChunk];           // (cell, value bits), tile by tile
-    __shared__ uint32_t hist[kStageMaxTiles];  // the block's particles per tile
-    __shared__ uint32_t loc[kStageMaxTiles];   // block-local start of each tile's run
-    __shared__ uint32_t base[kStageMaxTiles];  // its start in the tile's global range
+    static_assert(C % kTBlock == 0 && NV >= 1 && NV <= 4, "whole passes, at most four fields");
+    constexpr int P = C / kTBlock;  // particles per thread
+    using Rec = typename StageRec<NV>::T;
+    __shared__ Rec stage[C];                        // (cell, value bits), tile by tile
+    __shared__ uint32_t stage3[NV == 4 ? C : 1];    // field 3's value bits, in the same order
+    __shared__ uint32_t hist[kStageMaxTiles];       // the block's particles per tile
+    __shared__ uint32_t loc[kStageMaxTiles];        // block-local start of each tile's run
+    __shared__ uint32_t base[kStageMaxTiles];       // its start in the tile's global range
     __shared__ uint32_t wsum[kTBlock / 64];
     const int j = blockIdx.y;
     int64_t s0, s1;
     snap_range(a, j, s0, s1);
-    const int64_t cb = s0 + (int64_t)blockIdx.x * kTChunk;
+    const int64_t cb = s0 + (int64_t)blockIdx.x * C;
     if (cb >= s1) return;  // the whole block: beyond its snapshot's particles
-    const int64_t ce = min(cb + (int64_t)kTChunk, s1);
+    const int64_t ce = min(cb + (int64_t)C, s1);
     const int nt = a.ntiles;  // <= kStageMaxTiles (host)
     for (int t = threadIdx.x; t < nt; t += kTBlock) hist[t] = 0u;
-    int32_t kk[kTPer];
-    uint32_t vv[kTPer];
+    int32_t kk[P];
+    uint32_t vv[NV][P];
 #pragma unroll
-    for (int i = 0; i < kTPer; ++i) {
+    for (int i = 0; i < P; ++i) {
         const int64_t p = cb + threadIdx.x + (int64_t)i * kTBlock;
         kk[i] = p < ce ? a.cellbuf[p] : -1;
-        vv[i] = p < ce ? __float_as_uint(a.values[p]) : 0u;
+#pragma unroll
+        for (int f = 0; f < NV; ++f) vv[f][i] = p < ce ? __float_as_uint(a.values[(size_t)f * a.total + p]) : 0u;
     }
     __syncthreads();
-    uint32_t rank[kTPer];
+    uint32_t rank[P];
 #pragma unroll
-    for (int i = 0; i < kTPer; ++i) rank[i] = kk[i] >= 0 ? atomicAdd(&hist[kk[i] >> a.cpt_log2], 1u) : 0u;
+    for (int i = 0; i < P; ++i) rank[i] = kk[i] >= 0 ? atomicAdd(&hist[kk[i] >> a.cpt_log2], 1u) : 0u;
     __syncthreads();
     // exclusive prefix sum of the counts: tiles 2 tid and 2 tid + 1 per thread,
     // a wave scan by shuffles, then the wave totals
@@ -561,14 +573,28 @@ __global__ __launch_bounds__(kTBlock) void k_tile_scatter_staged(TileArgs a) {
     if (t0 + 1 < nt) loc[t0 + 1] = ex + h0;
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kTPer; ++i)
-        if (kk[i] >= 0) stage[loc[kk[i] >> a.cpt_log2] + rank[i]] = make_uint2((uint32_t)kk[i], vv[i]);
+    for (int i = 0; i < P; ++i) {
+        if (kk[i] < 0) continue;
+        const uint32_t k = loc[kk[i] >> a.cpt_log2] + rank[i];  // < total <= C
+        if constexpr (NV == 1) {
+            stage[k] = make_uint2((uint32_t)kk[i], vv[0][i]);
+        } else {
+            stage[k] = make_uint4((uint32_t)kk[i], vv[0][i], vv[1][i], NV > 2 ? vv[NV > 2 ? 2 : 0][i] : 0u);
+            if constexpr (NV == 4) stage3[k] = vv[3][i];
+        }
+    }
     __syncthreads();
     const uint32_t mask = (uint32_t)a.cpt - 1u;
     for (uint32_t k = threadIdx.x; k < total; k += kTBlock) {
-        const uint2 e = stage[k];
+        const Rec e = stage[k];
         const uint32_t t = e.x >> a.cpt_log2;
-        a.rec[base[t] + (k - loc[t])] = make_uint2(e.x & mask, e.y);
+        const uint32_t g = base[t] + (k - loc[t]);
+        if constexpr (NV == 1) {
+            a.rec[g] = make_uint2(e.x & mask, e.y);
+        } else {
+            a.rec4[g] = make_uint4(e.x & mask, e.y, e.z, e.w);
+            if constexpr (NV == 4) a.rv[g] = __uint_as_float(stage3[k]);
+        }
     }
 }
 
@@ -840,11 +866,17 @@ cgd_status tiled_deposit(cgd_mesh m, const TiledDeposit& d, Timing* timing, hipS
     if (timing) timing_end(timing, t13, 13, (12.0 + 4.0 * d.F + 4.0) * np_, s);
     int t14 = timing ? timing_begin(timing, s) : -1;
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kTBlock), 0, s, a);
-    if (d.F >= 2) {
+    if (nt <= kStageMaxTiles && d.F <= 4 && a.nsub == 1) {
+        // staged in LDS: C = 16384 / 8192 / 4096 particles per block at F = 1 / 2..3 / 4
+        const int c = d.F == 1 ? kTChunk : (d.F <= 3 ? kTChunk / 2 : kTChunk / 4);
+        const dim3 g((unsigned)std::max<int64_t>(1, (d.max_n + c - 1) / c), d.n_snap);
+        if (d.F == 1) hipLaunchKernelGGL((k_tile_scatter_staged<kTChunk, 1>), g, dim3(kTBlock), 0, s, a);
+        else if (d.F == 2) hipLaunchKernelGGL((k_tile_scatter_staged<kTChunk / 2, 2>), g, dim3(kTBlock), 0, s, a);
+        else if (d.F == 3) hipLaunchKernelGGL((k_tile_scatter_staged<kTChunk / 2, 3>), g, dim3(kTBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_tile_scatter_staged<kTChunk / 4, 4>), g, dim3(kTBlock), 0, s, a);
+    } else if (d.F >= 2) {
         if (pack) hipLaunchKernelGGL((k_tile_scatter<true, true>), dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
         else hipLaunchKernelGGL((k_tile_scatter<true, false>), dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
-    } else if (nt <= kStageMaxTiles && a.nsub == 1) {
-        hipLaunchKernelGGL(k_tile_scatter_staged, dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
     } else {
         if (pack) hipLaunchKernelGGL((k_tile_scatter<false, true>), dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
         else hipLaunchKernelGGL((k_tile_scatter<false, false>), dim3(sblocks, d.n_snap), dim3(kTBlock), 0, s, a);
