@@ -92,12 +92,15 @@ def test_deposit_dense_bed_single_field_many_tiles_bit_exact(gpu_lib):
 
 
 @pytest.mark.parametrize("shape,cpt,F", [((64, 64, 64), 32, 1), ((64, 64, 64), 16, 1), ((64, 64, 64), 16, 4),
-                                         ((60, 61, 67), 16, 2), ((64, 64, 65), 16, 1)])
+                                         ((60, 61, 67), 16, 2), ((64, 64, 65), 16, 1),
+                                         ((64, 64, 64), 128, 1), ((64, 64, 64), 128, 4), ((64, 64, 65), 128, 3)])
 def test_deposit_tile_counts_bit_exact(gpu_lib, shape, cpt, F, monkeypatch):
     """Tiles forced small (CGD_DEPOSIT_CPT) to reach the bucketing passes'
     tile limits on small grids: 8,192 tiles (32-bit counters), 16,384 (two
     16-bit counters per word), a ragged 15,327 at two fields and 16,384 at
-    four, and 16,640 (beyond both: the direct path).  Clustered particles
+    four, and 16,640 (beyond both: the direct path); and the scatter's: 2,048
+    tiles at one and four fields (records ordered in LDS, the most tiles it
+    takes) and a ragged 2,080 at three (beyond it: stored from registers).  Clustered particles
     (the dense-bed recipe), so that some tiles take thousands of one block's
     particles; accumulators and fields bit-identical to the oracle's."""
     import torch
