@@ -477,16 +477,22 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     // Uniform grids from a zero guess: a call with the parameters of the
     // previous one on this mesh enqueues, per step, the iterations that call
-    // took plus one, with no read-back between steps (launches after a field
-    // has converged return at once, so the result is the same).  A step that
-    // runs out of its budget sends the call round again with read-backs.
+    // took plus a margin of one, with no read-back between steps (launches
+    // after a field has converged return at once, so the result is the same).
+    // Once kBudgetSteadyCalls budgeted calls in a row have taken exactly the
+    // previous counts, the margin is dropped (the spare iteration's five empty
+    // launches cost about 25 us per step).  A step that runs out of its budget
+    // (its residual checked after the last iteration) sends the call round
+    // again with read-backs, and the margin returns until the counts repeat.
     HexBudget& hb = m->budget;
     const bool budgeted = m->kind == 0 && a.x0_mode == 0 && !getenv("CGD_HEX_NO_BUDGET");
     const bool have = budgeted && hb.valid && hb.F == F && hb.n_steps == a.n_steps && hb.max_iter == a.max_iter &&
                       hb.precond == a.precond && hb.scheme == a.scheme && hb.bandwidth == a.bandwidth &&
                       hb.rtol == a.rtol;
+    constexpr int kBudgetSteadyCalls = 2;
+    const int margin = hb.repeats >= kBudgetSteadyCalls ? 0 : 1;
     int bud[CGD_MAX_STEPS];
-    for (int i = 0; i < a.n_steps; ++i) bud[i] = have ? hb.iters[i] + 1 : 0;
+    for (int i = 0; i < a.n_steps; ++i) bud[i] = have ? hb.iters[i] + margin : 0;
     for (int round = have ? 0 : 1; round < 2; ++round) {
         rc = do_deposit(m, n, pos, F, values, field, nullptr, nullptr, st, s);
         cgd_status dep_rc = rc;
@@ -506,11 +512,14 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, 
             // this call's iterations per step (cg_finish_call left them in the pinned buffer)
             hb.valid = rc == CGD_OK;
             const int32_t* it = reinterpret_cast<const int32_t*>(static_cast<char*>(m->pinned) + kPinIters);
+            bool same = round == 0 && rc == CGD_OK;  // a budgeted call that did not run out
             for (int i = 0; i < a.n_steps; ++i) {
                 int v = 0;
                 for (int f = 0; f < F; ++f) v = std::max(v, (int)it[i * CGD_MAX_FIELDS + f]);
+                same = same && v == hb.iters[i];
                 hb.iters[i] = v;
             }
+            hb.repeats = same ? hb.repeats + 1 : 0;
             hb.F = F;
             hb.n_steps = a.n_steps;
             hb.max_iter = a.max_iter;

@@ -69,6 +69,7 @@ struct HexBudget {
     int32_t F = 0, n_steps = 0, max_iter = 0, precond = 0, scheme = 0;
     double bandwidth = 0.0, rtol = 0.0;
     int32_t iters[CGD_MAX_STEPS] = {};
+    int32_t repeats = 0;  // calls in a row, each budgeted, that took exactly these iterations
 };
 
 struct TetData;  // defined in tet.cpp

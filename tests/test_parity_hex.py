@@ -446,11 +446,14 @@ def test_wide_rows_exchanged_match_oracle(gpu_lib, deg, monkeypatch):
 @pytest.mark.parametrize("precond", [0, 1])
 def test_repeated_calls_with_iteration_budgets(gpu_lib, precond, monkeypatch):
     """A coarse-graining call with the parameters of the previous one on the
-    mesh enqueues the iterations that call took (plus one) per step without
-    read-backs.  Bit for bit the same fields and iteration counts as the
-    call with read-backs (CGD_HEX_NO_BUDGET), both when the budget suffices
-    (the same input again) and when it does not (a rougher input after a
-    smooth one: the call goes round again with read-backs)."""
+    mesh enqueues the iterations that call took per step without read-backs:
+    plus one, and exactly those once two budgeted calls in a row have taken
+    them.  Bit for bit the same fields and iteration counts as the call with
+    read-backs (CGD_HEX_NO_BUDGET), both when the budget suffices (the same
+    input again, with and without the spare iteration) and when it does not
+    (a rougher input after the smooth ones, with no spare iteration left:
+    the call goes round again with read-backs, and the spare iteration
+    comes back for the calls after it)."""
     import torch
     cgd = gpu_lib
     shape = (64, 48, 40)
@@ -476,9 +479,11 @@ def test_repeated_calls_with_iteration_budgets(gpu_lib, precond, monkeypatch):
     mesh.close()
     mesh = cgd.HexMesh(shape, lo, hi)
     first = run(smooth, True)            # learns the budgets
-    again = run(smooth, True)            # within them
+    again = run(smooth, True)            # within them, one spare iteration per step
+    steady = [run(smooth, True) for _ in range(3)]  # the counts repeat: no spare iteration from the third
     after = run(rough, True)             # beyond them (more iterations): the call is redone with read-backs
-    for got, ref in ((first, ref_s), (again, ref_s), (after, ref_r)):
+    back = run(smooth, True)             # a spare iteration again
+    for got, ref in ((first, ref_s), (again, ref_s), *((x, ref_s) for x in steady), (after, ref_r), (back, ref_s)):
         assert np.array_equal(got[0].view(np.uint32), ref[0].view(np.uint32))
         assert got[1] == ref[1] and got[2] == ref[2] == 0
     print(f"iterations: smooth {ref_s[1]}, rough {ref_r[1]}", flush=True)
