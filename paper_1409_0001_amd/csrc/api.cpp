@@ -493,7 +493,7 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, 
     constexpr int kBudgetSteadyCalls = 2;
     const int margin = hb.repeats >= kBudgetSteadyCalls ? 0 : 1;
     int bud[CGD_MAX_STEPS];
-    for (int i = 0; i < a.n_steps; ++i) bud[i] = have ? hb.iters[i] + margin : 0;
+    for (int i = 0; i < a.n_steps; ++i) bud[i] = have ? std::max(1, hb.iters[i] + margin) : 0;
     for (int round = have ? 0 : 1; round < 2; ++round) {
         rc = do_deposit(m, n, pos, F, values, field, nullptr, nullptr, st, s);
         cgd_status dep_rc = rc;

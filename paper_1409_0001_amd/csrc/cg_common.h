@@ -60,20 +60,27 @@ __device__ inline void post_ndone(const CgCtl& c) {
     }
 }
 
-// Sum of n float64 values in one fixed order (thread t adds t, t+256, ...;
-// then a fixed shuffle tree and a fixed sum over the 4 waves).  Every thread
-// of the block returns the same value, bit for bit, in every block.
-__device__ inline double block_sum_fixed(const double* p, int n, double* sh) {
+// Sum of n float64 values by a block of NT threads in one fixed order
+// (thread t adds t, t + NT, ...; then a fixed shuffle tree and a fixed sum
+// over the NT / 64 waves).  Every thread of the block returns the same value,
+// bit for bit, in every block; the order depends on NT.
+template <int NT>
+__device__ inline double block_sum_nt(const double* p, int n, double* sh) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kCgBlock) s += p[i];
+    for (int i = threadIdx.x; i < n; i += NT) s += p[i];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();
     double t = 0.0;
 #pragma unroll
-    for (int i = 0; i < kCgWaves; ++i) t += sh[i];
+    for (int i = 0; i < NT / 64; ++i) t += sh[i];
     __syncthreads();
     return t;
+}
+
+// The same by a block of kCgBlock threads.
+__device__ inline double block_sum_fixed(const double* p, int n, double* sh) {
+    return block_sum_nt<kCgBlock>(p, n, sh);
 }
 
 // Block-wide float64 sum in fixed order; the result is valid in thread 0.
@@ -115,7 +122,11 @@ __device__ inline bool check_stop(const CgCtl& c, int f, int k, double rrk, doub
 
 __global__ void k_cg_step_init(CgField* st, int F, int* ndone, int32_t* status_row);
 // Settles the fields still running after k_end iterations, from the r.r
-// partial sums of the last sweep (rr_part: [F][slot stride] with stride).
+// partial sums of the last sweep (rr_part: [F][slot stride] with stride):
+// the test that iteration k_end's first kernel would have made, summed in
+// its order (NT: that kernel's block size; launch with NT threads), and
+// CGD_NOT_CONVERGED where it fails.  Instantiated for NT = 256 and 1024.
+template <int NT>
 __global__ void k_cg_step_end(CgCtl c, const double* rr_part, size_t field_stride, int bpf, int k_end);
 
 // Crank-Nicolson from its half-step solve (Section 5.1): with

@@ -20,22 +20,19 @@ __global__ void k_cg_step_init(CgField* st, int F, int* ndone, int32_t* status_r
     }
 }
 
-__global__ __launch_bounds__(kCgBlock) void k_cg_step_end(CgCtl c, const double* rr_part, size_t field_stride,
-                                                         int bpf, int k_end) {
+template <int NT>
+__global__ __launch_bounds__(NT) void k_cg_step_end(CgCtl c, const double* rr_part, size_t field_stride, int bpf,
+                                                   int k_end) {
     const int f = blockIdx.x;
     CgField* stf = c.st + f;
     if (stf->done) return;
-    __shared__ double sh[kCgWaves];
-    const double rrk = block_sum_fixed(rr_part + (size_t)f * field_stride, bpf, sh);
+    __shared__ double sh[NT / 64];
+    const double rrk = block_sum_nt<NT>(rr_part + (size_t)f * field_stride, bpf, sh);
     if (threadIdx.x != 0) return;
-    const double bb = stf->bb;
-    c.iters[c.step * CGD_MAX_FIELDS + f] = k_end;
-    c.relres[c.step * CGD_MAX_FIELDS + f] = bb > 0.0 ? sqrt(rrk / bb) : 0.0;
-    int status = CGD_OK;
-    if (!isfinite(rrk)) status = CGD_E_BREAKDOWN;
-    else if (!(rrk <= c.rtol2 * bb)) status = CGD_NOT_CONVERGED;
-    finish_field(c, f, status);
+    if (!check_stop(c, f, k_end, rrk, stf->bb, true)) finish_field(c, f, CGD_NOT_CONVERGED);
 }
+template __global__ void k_cg_step_end<kCgBlock>(CgCtl, const double*, size_t, int, int);
+template __global__ void k_cg_step_end<1024>(CgCtl, const double*, size_t, int, int);
 
 __global__ __launch_bounds__(kCgBlock) void k_cn_extrapolate(float* __restrict__ y, const float* __restrict__ e,
                                                             int64_t n) {

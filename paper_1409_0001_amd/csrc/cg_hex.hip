@@ -212,22 +212,6 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     }
 }
 
-// Fixed-order float64 sum of n partials by a block of NT threads (the same
-// value in every thread and every block of the launch).
-template <int NT>
-__device__ inline double block_sum_nt(const double* p, int n, double* sh) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += NT) s += p[i];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    double t = 0.0;
-#pragma unroll
-    for (int i = 0; i < NT / 64; ++i) t += sh[i];
-    __syncthreads();
-    return t;
-}
-
 // Direction sweep of preconditioned CG with the rows shared through LDS:
 // p = z + beta p_old, A p and p.Ap, writing p; when B0, p = z, which is not
 // written again (the caller uses z's buffer as p).  A block of NW
@@ -1358,8 +1342,16 @@ cgd_status diffuse_hex_enqueue(cgd_mesh m, const DiffuseArgs& da, char* base, co
         }
         CgCtl c2 = ctl;
         c2.step = step;
-        hipLaunchKernelGGL(k_cg_step_end, dim3(F), dim3(kBlock), 0, s, c2, d_P2 + (size_t)(it_end & 1) * a.pstride,
-                           (size_t)2 * a.pstride, p.bpf, it_end);
+        // the test of iteration it_end's first kernel, in its summation order:
+        // an LDS preconditioning pass (1024 threads) or a register sweep
+        if (pcg && (deg_lds || deg_rect)) {
+            static_assert(kLdsNW * 64 == 1024, "LDS passes sum with 1024 threads");
+            hipLaunchKernelGGL(k_cg_step_end<1024>, dim3(F), dim3(1024), 0, s, c2,
+                               d_P2 + (size_t)(it_end & 1) * a.pstride, (size_t)2 * a.pstride, p.bpf, it_end);
+        } else {
+            hipLaunchKernelGGL(k_cg_step_end<kBlock>, dim3(F), dim3(kBlock), 0, s, c2,
+                               d_P2 + (size_t)(it_end & 1) * a.pstride, (size_t)2 * a.pstride, p.bpf, it_end);
+        }
         if (use_x0) {
             int blocks = (int)std::min<int64_t>(2048, (cells + kBlock - 1) / kBlock);
             hipLaunchKernelGGL(k_zero_if_rhs_zero, dim3(blocks, F), dim3(kBlock), 0, s, nxt, cells, ctl.st);

@@ -1417,7 +1417,7 @@ cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, 
         CgCtl c2 = ctl;
         c2.step = step;
         // r.r of the last sweep 2: parity (it_end & 1), second slot
-        hipLaunchKernelGGL(k_cg_step_end, dim3(F), dim3(kBlock), 0, s, c2,
+        hipLaunchKernelGGL(k_cg_step_end<kCgBlock>, dim3(F), dim3(kCgBlock), 0, s, c2,
                            d_P2 + ((size_t)(it_end & 1) * 2 + 1) * p.bpf, (size_t)4 * p.bpf, p.bpf, it_end);
         if (da.scheme == 1) cn_extrapolate(nxt, cur, (int64_t)fn, s);
         std::swap(cur, nxt);

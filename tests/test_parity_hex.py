@@ -448,8 +448,10 @@ def test_repeated_calls_with_iteration_budgets(gpu_lib, precond, monkeypatch):
     """A coarse-graining call with the parameters of the previous one on the
     mesh enqueues the iterations that call took per step without read-backs:
     plus one, and exactly those once two budgeted calls in a row have taken
-    them.  Bit for bit the same fields and iteration counts as the call with
-    read-backs (CGD_HEX_NO_BUDGET), both when the budget suffices (the same
+    them (the step's last test then made after its last iteration, summed in
+    the order of the kernel that would have made it).  Bit for bit the same
+    fields, iteration counts and residuals as the call with read-backs
+    (CGD_HEX_NO_BUDGET), both when the budget suffices (the same
     input again, with and without the spare iteration) and when it does not
     (a rougher input after the smooth ones, with no spare iteration left:
     the call goes round again with read-backs, and the spare iteration
@@ -471,7 +473,7 @@ def test_repeated_calls_with_iteration_budgets(gpu_lib, precond, monkeypatch):
             monkeypatch.setenv("CGD_HEX_NO_BUDGET", "1")
         out, st = cgd.coarse_grain(mesh, _t(p.pos, torch), _t(p.values, torch), b, steps, rtol=1e-6, stats=True,
                                    precond=precond)
-        return out.cpu().numpy(), [list(r) for r in st.iters], st.status
+        return out.cpu().numpy(), [list(r) for r in st.iters], st.status, [list(r) for r in st.rel_res]
 
     mesh = cgd.HexMesh(shape, lo, hi)
     ref_s = run(smooth, False)
@@ -486,6 +488,7 @@ def test_repeated_calls_with_iteration_budgets(gpu_lib, precond, monkeypatch):
     for got, ref in ((first, ref_s), (again, ref_s), *((x, ref_s) for x in steady), (after, ref_r), (back, ref_s)):
         assert np.array_equal(got[0].view(np.uint32), ref[0].view(np.uint32))
         assert got[1] == ref[1] and got[2] == ref[2] == 0
+        assert got[3] == ref[3]  # float64 relative residuals, exactly
     print(f"iterations: smooth {ref_s[1]}, rough {ref_r[1]}", flush=True)
     if precond == 1:  # plain CG: the rough input takes more iterations, so its call ran out of budget
         assert sum(map(sum, ref_r[1])) > sum(map(sum, ref_s[1])) + steps
