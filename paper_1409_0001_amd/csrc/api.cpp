@@ -479,19 +479,20 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, 
     // previous one on this mesh enqueues, per step, the iterations that call
     // took plus a margin of one, with no read-back between steps (launches
     // after a field has converged return at once, so the result is the same).
-    // Once kBudgetSteadyCalls budgeted calls in a row have taken exactly the
-    // previous counts, the margin is dropped (the spare iteration's five empty
-    // launches cost about 12 us per step on a 256 x 256 x 512 grid).  A step
-    // that runs out of its budget (its residual checked after the last
+    // Once hb.steady budgeted calls in a row (2 at first) have taken exactly
+    // the previous counts, the margin is dropped (the spare iteration's five
+    // empty launches cost about 12 us per step on a 256 x 256 x 512 grid).  A
+    // step that runs out of its budget (its residual checked after the last
     // iteration) sends the call round again with read-backs, and the margin
-    // returns until the counts repeat.
+    // returns until the counts repeat; a miss without the margin doubles
+    // hb.steady (at most 64), so that inputs whose counts rise every few
+    // calls do not pay a rerun each time.
     HexBudget& hb = m->budget;
     const bool budgeted = m->kind == 0 && a.x0_mode == 0 && !getenv("CGD_HEX_NO_BUDGET");
     const bool have = budgeted && hb.valid && hb.F == F && hb.n_steps == a.n_steps && hb.max_iter == a.max_iter &&
                       hb.precond == a.precond && hb.scheme == a.scheme && hb.bandwidth == a.bandwidth &&
                       hb.rtol == a.rtol;
-    constexpr int kBudgetSteadyCalls = 2;
-    const int margin = hb.repeats >= kBudgetSteadyCalls ? 0 : 1;
+    const int margin = hb.repeats >= hb.steady ? 0 : 1;
     int bud[CGD_MAX_STEPS];
     for (int i = 0; i < a.n_steps; ++i) bud[i] = have ? std::max(1, hb.iters[i] + margin) : 0;
     for (int round = have ? 0 : 1; round < 2; ++round) {
@@ -502,6 +503,7 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, 
             rc = diffuse_hex(m, a, st, s, bud);
             if (rc == CGD_NOT_CONVERGED) {
                 hb.valid = false;
+                if (margin == 0) hb.steady = std::min(64, 2 * hb.steady);
                 if (st) memset(st, 0, sizeof(*st));
                 continue;
             }

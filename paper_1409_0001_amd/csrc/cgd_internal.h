@@ -70,6 +70,7 @@ struct HexBudget {
     double bandwidth = 0.0, rtol = 0.0;
     int32_t iters[CGD_MAX_STEPS] = {};
     int32_t repeats = 0;  // calls in a row, each budgeted, that took exactly these iterations
+    int32_t steady = 2;   // repeats after which the spare iteration is dropped (doubled by each miss without it)
 };
 
 struct TetData;  // defined in tet.cpp

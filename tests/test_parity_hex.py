@@ -455,7 +455,8 @@ def test_repeated_calls_with_iteration_budgets(gpu_lib, precond, monkeypatch):
     input again, with and without the spare iteration) and when it does not
     (a rougher input after the smooth ones, with no spare iteration left:
     the call goes round again with read-backs, and the spare iteration
-    comes back for the calls after it)."""
+    comes back for the calls after it, until twice as many calls in a row
+    have repeated the counts)."""
     import torch
     cgd = gpu_lib
     shape = (64, 48, 40)
@@ -484,8 +485,10 @@ def test_repeated_calls_with_iteration_budgets(gpu_lib, precond, monkeypatch):
     again = run(smooth, True)            # within them, one spare iteration per step
     steady = [run(smooth, True) for _ in range(3)]  # the counts repeat: no spare iteration from the third
     after = run(rough, True)             # beyond them (more iterations): the call is redone with read-backs
-    back = run(smooth, True)             # a spare iteration again
-    for got, ref in ((first, ref_s), (again, ref_s), *((x, ref_s) for x in steady), (after, ref_r), (back, ref_s)):
+    back = [run(smooth, True) for _ in range(6)]  # a spare iteration again, none from the sixth
+    after2 = run(rough, True)            # beyond them again
+    for got, ref in ((first, ref_s), (again, ref_s), *((x, ref_s) for x in steady), (after, ref_r),
+                     *((x, ref_s) for x in back), (after2, ref_r)):
         assert np.array_equal(got[0].view(np.uint32), ref[0].view(np.uint32))
         assert got[1] == ref[1] and got[2] == ref[2] == 0
         assert got[3] == ref[3]  # float64 relative residuals, exactly
