@@ -296,7 +296,8 @@ cgd_status cgd_diffuse(cgd_mesh m, int32_t F, float* field, double bandwidth,
  * On a uniform hex grid from a zero guess, a call with the arguments of the
  * previous one on the mesh (grid, F, bandwidth, n_steps, max_iter, rtol,
  * precond, scheme) enqueues each step's iterations of that call, plus one
- * until two such calls in a row have taken the same counts, with no
+ * until two such calls in a row have taken the same counts (twice as many
+ * after each call that ran out without the extra one, up to 64), with no
  * read-back between steps; if a step runs out, the call goes round again
  * with read-backs.  Fields, counts and statistics are those of the call with
  * read-backs either way (environment CGD_HEX_NO_BUDGET turns this off). */
