@@ -293,7 +293,8 @@ cgd_status cgd_diffuse(cgd_mesh m, int32_t F, float* field, double bandwidth,
 
 /* cgd_deposit followed by cgd_diffuse (Section 2.6): the whole method.
  * field: device float32 [F, cells], written.
- * On a uniform hex grid from a zero guess, a call with the arguments of the
+ * On a uniform hex grid (or a rectilinear one with a separable diffusivity
+ * and the default preconditioner) from a zero guess, a call with the arguments of the
  * previous one on the mesh (grid, F, bandwidth, n_steps, max_iter, rtol,
  * precond, scheme) enqueues each step's iterations of that call, plus one
  * until two such calls in a row have taken the same counts (twice as many

@@ -475,7 +475,8 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, 
     }
     if (st) memset(st, 0, sizeof(*st));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // Uniform grids from a zero guess: a call with the parameters of the
+    // Uniform grids (and rectilinear ones on the same sweeps, with per-axis
+    // factors) from a zero guess: a call with the parameters of the
     // previous one on this mesh enqueues, per step, the iterations that call
     // took plus a margin of one, with no read-back between steps (launches
     // after a field has converged return at once, so the result is the same).
@@ -488,7 +489,7 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, 
     // hb.steady (at most 64), so that inputs whose counts rise every few
     // calls do not pay a rerun each time.
     HexBudget& hb = m->budget;
-    const bool budgeted = m->kind == 0 && a.x0_mode == 0 && !getenv("CGD_HEX_NO_BUDGET");
+    const bool budgeted = (m->kind == 0 || rect_fast_path(m, a)) && a.x0_mode == 0 && !getenv("CGD_HEX_NO_BUDGET");
     const bool have = budgeted && hb.valid && hb.F == F && hb.n_steps == a.n_steps && hb.max_iter == a.max_iter &&
                       hb.precond == a.precond && hb.scheme == a.scheme && hb.bandwidth == a.bandwidth &&
                       hb.rtol == a.rtol;
@@ -500,7 +501,7 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, 
         cgd_status dep_rc = rc;
         if (rc < 0 && rc != CGD_E_NONFINITE) return rc;
         if (round == 0) {
-            rc = diffuse_hex(m, a, st, s, bud);
+            rc = m->kind == 0 ? diffuse_hex(m, a, st, s, bud) : diffuse_tet(m, a, st, s, bud);
             if (rc == CGD_NOT_CONVERGED) {
                 hb.valid = false;
                 if (margin == 0) hb.steady = std::min(64, 2 * hb.steady);

@@ -1046,7 +1046,8 @@ cgd_status rect_op_prepare(cgd_mesh m, double dtau, hipStream_t s) {
 // on A = I + dtau M^-1/2 K M^-1/2 for x~ = M^1/2 x (the same system as
 // (M + dtau K) x = M e, scaled symmetrically), preconditioned by
 // S p(S A S) S (RectOp); the stopping rule applies to the scaled residual.
-static cgd_status diffuse_rect_fast(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s) {
+static cgd_status diffuse_rect_fast(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s,
+                                    const int* fixed) {
     const TetData* t = m->tet;
     RectOp* ro = m->rop;
     const int F = da.F;
@@ -1069,7 +1070,7 @@ static cgd_status diffuse_rect_fast(cgd_mesh m, const DiffuseArgs& da, cgd_solve
     const int sblocks = std::min(4096, (n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_rect_scale, dim3(sblocks, F), dim3(kBlock), 0, s, da.field, (int64_t)n, m->hex.nx,
                        m->hex.ny, ro->win[0], ro->win[1], ro->win[2]);
-    rc = diffuse_hex_enqueue(m, da, base, nullptr, false, s, ro);
+    rc = diffuse_hex_enqueue(m, da, base, fixed, false, s, ro);
     if (rc != CGD_OK) return rc;
     hipLaunchKernelGGL(k_rect_scale, dim3(sblocks, F), dim3(kBlock), 0, s, da.field, (int64_t)n, m->hex.nx,
                        m->hex.ny, ro->wout[0], ro->wout[1], ro->wout[2]);
@@ -1206,16 +1207,20 @@ static cgd_status build_rect_op(cgd_mesh m, const int32_t dims[3], const double*
     return CGD_OK;
 }
 
-cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s) {
+// The per-axis factor sweeps apply: a rectilinear grid with a separable
+// diffusivity, the default preconditioner and a zero guess (a periodic x axis
+// also needs the row in one x segment; otherwise the face-slot rows).
+bool rect_fast_path(const cgd_mesh m, const DiffuseArgs& da) {
+    return m->kind == 2 && m->rop && da.precond == 0 && da.x0_mode == 0 && !getenv("CGD_RECT_SLOTS") &&
+           (!(m->rop->per & 1) || hex_one_x_segment(m->hex, da.field));
+}
+
+cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& da, cgd_solve_stats* out, hipStream_t s, const int* fixed) {
     if (da.x0_mode != 0) {
         set_error("cgd_diffuse: tet meshes support x0_mode 0 only");
         return CGD_E_UNSUPPORTED;
     }
-    // the per-axis factor sweeps where they apply: a periodic x axis needs
-    // the row in one x segment (otherwise the face-slot rows)
-    if (m->kind == 2 && m->rop && da.precond == 0 && !getenv("CGD_RECT_SLOTS") &&
-        (!(m->rop->per & 1) || hex_one_x_segment(m->hex, da.field)))
-        return diffuse_rect_fast(m, da, out, s);
+    if (rect_fast_path(m, da)) return diffuse_rect_fast(m, da, out, s, fixed);
     const TetData* t = m->tet;
     const int F = da.F;
     const int n = t->n_tet;

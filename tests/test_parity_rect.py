@@ -161,6 +161,57 @@ def test_rect_separable_fast_path_matches_oracle(gpu_lib, nx, scheme, steps, mon
     assert st.status == 0
 
 
+@pytest.mark.parametrize("scheme", ["be", "cn"])
+def test_rect_repeated_calls_with_iteration_budgets(gpu_lib, scheme, monkeypatch):
+    """Rectilinear grids on the sweeps with per-axis factors take the
+    uniform grid's iteration budgets: a repeated call enqueues the previous
+    call's iterations per step (plus one until the counts repeat) with no
+    read-backs.  Fields, iteration counts and residuals are bit for bit those
+    of the calls with read-backs (CGD_HEX_NO_BUDGET), whether the budget
+    suffices or a rougher input runs out of it and is redone."""
+    import torch
+    cgd = gpu_lib
+    rng = np.random.default_rng(91)
+    ex = _stretched(32, 1.03, -0.3, 1.1)
+    ey = np.concatenate(([0.1], 0.1 + np.cumsum(rng.random(23) + 0.3) / 20))
+    ez = np.linspace(2.0, 2.5, 18)
+    shape = (len(ex) - 1, len(ey) - 1, len(ez) - 1)
+    xc = 0.5 * (ex[1:] + ex[:-1])
+    Dx = 1.0 + 0.5 * np.cos(3 * xc)
+    D = (Dx[None, None, :] * np.ones(shape[1])[None, :, None] * np.ones(shape[2])[:, None, None]).astype(np.float32)
+    lo = np.array([ex[0], ey[0], ez[0]])
+    hi = np.array([ex[-1], ey[-1], ez[-1]])
+    smooth = (lo + (hi - lo) * rng.random((200_000, 3))).astype(np.float32)
+    rough = (lo + (hi - lo) * rng.random((500, 3))).astype(np.float32)
+    vs = np.full((1, len(smooth)), 2.0e-7, np.float32)
+    vr = rng.normal(size=(1, len(rough))).astype(np.float32)
+    b, steps = 0.12, 3
+    print(f"case: rect iteration budgets {scheme}", flush=True)
+
+    def run(mesh, p, v, budget):
+        if budget:
+            monkeypatch.delenv("CGD_HEX_NO_BUDGET", raising=False)
+        else:
+            monkeypatch.setenv("CGD_HEX_NO_BUDGET", "1")
+        out, st = cgd.coarse_grain(mesh, _t(p, torch), _t(v, torch), b, steps, rtol=1e-7, stats=True, scheme=scheme)
+        return out.cpu().numpy(), [list(r) for r in st.iters], st.status, [list(r) for r in st.rel_res]
+
+    mesh = cgd.RectMesh(ex, ey, ez, diffusivity=D.ravel())
+    ref_s = run(mesh, smooth, vs, False)
+    ref_r = run(mesh, rough, vr, False)
+    mesh.close()
+    mesh = cgd.RectMesh(ex, ey, ez, diffusivity=D.ravel())
+    calls = [(run(mesh, smooth, vs, True), ref_s) for _ in range(5)]
+    calls.append((run(mesh, rough, vr, True), ref_r))
+    calls += [(run(mesh, smooth, vs, True), ref_s) for _ in range(6)]
+    calls.append((run(mesh, rough, vr, True), ref_r))
+    for got, ref in calls:
+        assert np.array_equal(got[0].view(np.uint32), ref[0].view(np.uint32))
+        assert got[1] == ref[1] and got[2] == ref[2] == 0
+        assert got[3] == ref[3]
+    print(f"iterations: smooth {ref_s[1]}, rough {ref_r[1]}", flush=True)
+
+
 @pytest.mark.parametrize("nx", [64, 128])
 @pytest.mark.parametrize("deg", [2, 4, 12])
 @pytest.mark.parametrize("scheme,steps", [("be", 4), ("cn", 3)])
