@@ -293,15 +293,14 @@ cgd_status cgd_diffuse(cgd_mesh m, int32_t F, float* field, double bandwidth,
 
 /* cgd_deposit followed by cgd_diffuse (Section 2.6): the whole method.
  * field: device float32 [F, cells], written.
- * On a uniform hex grid (or a rectilinear one with a separable diffusivity
- * and the default preconditioner) from a zero guess, a call with the arguments of the
+ * From a zero guess (x0_mode 0), a call with the arguments of the
  * previous one on the mesh (grid, F, bandwidth, n_steps, max_iter, rtol,
  * precond, scheme) enqueues each step's iterations of that call, plus one
  * until two such calls in a row have taken the same counts (twice as many
  * after each call that ran out without the extra one, up to 64), with no
  * read-back between steps; if a step runs out, the call goes round again
  * with read-backs.  Fields, counts and statistics are those of the call with
- * read-backs either way (environment CGD_HEX_NO_BUDGET turns this off). */
+ * read-backs either way (environment CGD_NO_BUDGET turns this off). */
 cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F,
                             const float* values, double bandwidth, int32_t n_steps,
                             const cgd_solver_opts* o, float* field,

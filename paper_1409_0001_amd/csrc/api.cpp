@@ -475,8 +475,7 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, 
     }
     if (st) memset(st, 0, sizeof(*st));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // Uniform grids (and rectilinear ones on the same sweeps, with per-axis
-    // factors) from a zero guess: a call with the parameters of the
+    // Every mesh kind, from a zero guess: a call with the parameters of the
     // previous one on this mesh enqueues, per step, the iterations that call
     // took plus a margin of one, with no read-back between steps (launches
     // after a field has converged return at once, so the result is the same).
@@ -489,7 +488,7 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, 
     // hb.steady (at most 64), so that inputs whose counts rise every few
     // calls do not pay a rerun each time.
     HexBudget& hb = m->budget;
-    const bool budgeted = (m->kind == 0 || rect_fast_path(m, a)) && a.x0_mode == 0 && !getenv("CGD_HEX_NO_BUDGET");
+    const bool budgeted = a.x0_mode == 0 && !getenv("CGD_NO_BUDGET");
     const bool have = budgeted && hb.valid && hb.F == F && hb.n_steps == a.n_steps && hb.max_iter == a.max_iter &&
                       hb.precond == a.precond && hb.scheme == a.scheme && hb.bandwidth == a.bandwidth &&
                       hb.rtol == a.rtol;

@@ -322,8 +322,7 @@ size_t deposit_tet_temp_bytes(const cgd_mesh m, int64_t n);
 cgd_status deposit_tet(cgd_mesh m, int64_t n, const float* pos, int32_t F, const float* values,
                        float* field, int64_t* acc, DepositInfo* info_dev, void* temp, const ScaleForce& fs,
                        hipStream_t s);
-// fixed: iterations per step (no read-backs), used on the rectilinear fast
-// path only (rect_fast_path), nullptr elsewhere.
+// fixed: iterations per step (no read-backs) or nullptr (read-backs).
 cgd_status diffuse_tet(cgd_mesh m, const DiffuseArgs& a, cgd_solve_stats* st, hipStream_t s,
                        const int* fixed = nullptr);
 // Whether diffuse_tet takes the uniform grid's sweeps with per-axis factors.

@@ -451,7 +451,7 @@ def test_repeated_calls_with_iteration_budgets(gpu_lib, precond, monkeypatch):
     them (the step's last test then made after its last iteration, summed in
     the order of the kernel that would have made it).  Bit for bit the same
     fields, iteration counts and residuals as the call with read-backs
-    (CGD_HEX_NO_BUDGET), both when the budget suffices (the same
+    (CGD_NO_BUDGET), both when the budget suffices (the same
     input again, with and without the spare iteration) and when it does not
     (a rougher input after the smooth ones, with no spare iteration left:
     the call goes round again with read-backs, and the spare iteration
@@ -469,9 +469,9 @@ def test_repeated_calls_with_iteration_budgets(gpu_lib, precond, monkeypatch):
 
     def run(p, budget):
         if budget:
-            monkeypatch.delenv("CGD_HEX_NO_BUDGET", raising=False)
+            monkeypatch.delenv("CGD_NO_BUDGET", raising=False)
         else:
-            monkeypatch.setenv("CGD_HEX_NO_BUDGET", "1")
+            monkeypatch.setenv("CGD_NO_BUDGET", "1")
         out, st = cgd.coarse_grain(mesh, _t(p.pos, torch), _t(p.values, torch), b, steps, rtol=1e-6, stats=True,
                                    precond=precond)
         return out.cpu().numpy(), [list(r) for r in st.iters], st.status, [list(r) for r in st.rel_res]

@@ -167,7 +167,7 @@ def test_rect_repeated_calls_with_iteration_budgets(gpu_lib, scheme, monkeypatch
     uniform grid's iteration budgets: a repeated call enqueues the previous
     call's iterations per step (plus one until the counts repeat) with no
     read-backs.  Fields, iteration counts and residuals are bit for bit those
-    of the calls with read-backs (CGD_HEX_NO_BUDGET), whether the budget
+    of the calls with read-backs (CGD_NO_BUDGET), whether the budget
     suffices or a rougher input runs out of it and is redone."""
     import torch
     cgd = gpu_lib
@@ -190,9 +190,9 @@ def test_rect_repeated_calls_with_iteration_budgets(gpu_lib, scheme, monkeypatch
 
     def run(mesh, p, v, budget):
         if budget:
-            monkeypatch.delenv("CGD_HEX_NO_BUDGET", raising=False)
+            monkeypatch.delenv("CGD_NO_BUDGET", raising=False)
         else:
-            monkeypatch.setenv("CGD_HEX_NO_BUDGET", "1")
+            monkeypatch.setenv("CGD_NO_BUDGET", "1")
         out, st = cgd.coarse_grain(mesh, _t(p, torch), _t(v, torch), b, steps, rtol=1e-7, stats=True, scheme=scheme)
         return out.cpu().numpy(), [list(r) for r in st.iters], st.status, [list(r) for r in st.rel_res]
 

@@ -151,6 +151,51 @@ def test_tet_polynomial_degrees_match_oracle(gpu_lib, deg, scheme, monkeypatch):
     assert its <= {"0": 100, "2": 36, "8": 13, "16": 8}[deg], st.iters
 
 
+@pytest.mark.parametrize("precond,scheme", [(0, "be"), (1, "be"), (0, "cn")])
+def test_tet_repeated_calls_with_iteration_budgets(gpu_lib, precond, scheme, monkeypatch):
+    """A repeated coarse-graining call on a tet mesh enqueues the previous
+    call's iterations per step without read-backs (plus one until the
+    counts repeat; the last iteration leaves out the next preconditioner,
+    whose first pass would only make the step end's check).  Fields,
+    iteration counts and residuals are bit for bit those of the calls with
+    read-backs (CGD_NO_BUDGET), under the polynomial and Jacobi, whether the
+    budget suffices or a rougher input runs out of it and is redone."""
+    import torch
+    cgd = gpu_lib
+    xyz, tets = inputs.kuhn_tet_mesh(12, 0.2, seed=63)
+    rng = np.random.default_rng(64)
+    smooth = rng.random((200_000, 3)).astype(np.float32)
+    rough = rng.random((300, 3)).astype(np.float32)
+    vs = np.full((1, len(smooth)), 2.0e-7, np.float32)
+    vr = rng.normal(size=(1, len(rough))).astype(np.float32)
+    b, steps = 4.0 / 12, 3
+    print(f"case: tet iteration budgets precond={precond} {scheme}", flush=True)
+
+    def run(mesh, p, v, budget):
+        if budget:
+            monkeypatch.delenv("CGD_NO_BUDGET", raising=False)
+        else:
+            monkeypatch.setenv("CGD_NO_BUDGET", "1")
+        out, st = cgd.coarse_grain(mesh, _t(p, torch), _t(v, torch), b, steps, rtol=1e-7, stats=True,
+                                   precond=precond, scheme=scheme)
+        return out.cpu().numpy(), [list(r) for r in st.iters], st.status, [list(r) for r in st.rel_res]
+
+    mesh = cgd.TetMesh(xyz, tets)
+    ref_s = run(mesh, smooth, vs, False)
+    ref_r = run(mesh, rough, vr, False)
+    mesh.close()
+    mesh = cgd.TetMesh(xyz, tets)
+    calls = [(run(mesh, smooth, vs, True), ref_s) for _ in range(5)]
+    calls.append((run(mesh, rough, vr, True), ref_r))
+    calls += [(run(mesh, smooth, vs, True), ref_s) for _ in range(6)]
+    calls.append((run(mesh, rough, vr, True), ref_r))
+    for got, ref in calls:
+        assert np.array_equal(got[0].view(np.uint32), ref[0].view(np.uint32))
+        assert got[1] == ref[1] and got[2] == ref[2] == 0
+        assert got[3] == ref[3]
+    print(f"iterations: smooth {ref_s[1]}, rough {ref_r[1]}", flush=True)
+
+
 def test_tet_default_preconditioner_iterations(gpu_lib):
     """162,000 jittered tets at dtau / h^2 = 1 (the unstructured workload's
     ratio), rtol 1e-6: the default polynomial preconditioner takes at most 12
