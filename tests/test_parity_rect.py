@@ -161,12 +161,12 @@ def test_rect_separable_fast_path_matches_oracle(gpu_lib, nx, scheme, steps, mon
     assert st.status == 0
 
 
-@pytest.mark.parametrize("scheme", ["be", "cn"])
-def test_rect_repeated_calls_with_iteration_budgets(gpu_lib, scheme, monkeypatch):
-    """Rectilinear grids on the sweeps with per-axis factors take the
-    uniform grid's iteration budgets: a repeated call enqueues the previous
-    call's iterations per step (plus one until the counts repeat) with no
-    read-backs.  Fields, iteration counts and residuals are bit for bit those
+@pytest.mark.parametrize("scheme,path", [("be", "factors"), ("cn", "factors"), ("be", "slots")])
+def test_rect_repeated_calls_with_iteration_budgets(gpu_lib, scheme, path, monkeypatch):
+    """Rectilinear grids take iteration budgets, on the sweeps with per-axis
+    factors (as uniform grids) and on the six-slot rows (as tets): a
+    repeated call enqueues the previous call's iterations per step (plus one
+    until the counts repeat) with no read-backs.  Fields, iteration counts and residuals are bit for bit those
     of the calls with read-backs (CGD_NO_BUDGET), whether the budget
     suffices or a rougher input runs out of it and is redone."""
     import torch
@@ -186,7 +186,9 @@ def test_rect_repeated_calls_with_iteration_budgets(gpu_lib, scheme, monkeypatch
     vs = np.full((1, len(smooth)), 2.0e-7, np.float32)
     vr = rng.normal(size=(1, len(rough))).astype(np.float32)
     b, steps = 0.12, 3
-    print(f"case: rect iteration budgets {scheme}", flush=True)
+    print(f"case: rect iteration budgets {scheme} {path}", flush=True)
+    if path == "slots":
+        monkeypatch.setenv("CGD_RECT_SLOTS", "1")
 
     def run(mesh, p, v, budget):
         if budget:
