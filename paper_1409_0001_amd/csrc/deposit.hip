@@ -376,27 +376,32 @@ __global__ __launch_bounds__(kTBlock) void k_tile_bin(TileArgs a) {
     }
 }
 
-// Pass 2: offsets = exclusive prefix sum of the counts of all tiles (one block).
+// Pass 2: offsets = exclusive prefix sum of the counts of all tiles (one
+// block): each thread sums a run of consecutive tiles, a wave scan by
+// shuffles and the wave totals give each run's start.
 __global__ __launch_bounds__(kTBlock) void k_tile_scan(TileArgs a) {
-    __shared__ uint32_t part[kTBlock];
+    __shared__ uint32_t wsum[kTBlock / 64];
     const int nt = a.n_snap * a.ntiles;
     const int per = (nt + kTBlock - 1) / kTBlock;
-    const int t0 = min(threadIdx.x * per, nt), t1 = min(t0 + per, nt);
+    const int t0 = min((int)threadIdx.x * per, nt), t1 = min(t0 + per, nt);
     uint32_t s = 0u;
     for (int t = t0; t < t1; ++t) s += a.counts[t];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0u;
-        for (int i = 0; i < kTBlock; ++i) {
-            const uint32_t v = part[i];
-            part[i] = run;
-            run += v;
-        }
-        a.offsets[nt] = run;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = s;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
     }
+    if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    uint32_t run = part[threadIdx.x];
+    uint32_t before = 0u, total = 0u;
+    for (int w = 0; w < kTBlock / 64; ++w) {
+        const uint32_t v = wsum[w];
+        before += w < wave ? v : 0u;
+        total += v;
+    }
+    if (threadIdx.x == 0) a.offsets[nt] = total;
+    uint32_t run = before + incl - s;
     for (int t = t0; t < t1; ++t) {
         a.offsets[t] = run;
         a.cursor[t] = run;
