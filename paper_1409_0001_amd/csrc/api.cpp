@@ -487,7 +487,7 @@ cgd_status cgd_coarse_grain(cgd_mesh m, int64_t n, const float* pos, int32_t F, 
     // returns until the counts repeat; a miss without the margin doubles
     // hb.steady (at most 64), so that inputs whose counts rise every few
     // calls do not pay a rerun each time.
-    HexBudget& hb = m->budget;
+    IterBudget& hb = m->budget;
     const bool budgeted = a.x0_mode == 0 && !getenv("CGD_NO_BUDGET");
     const bool have = budgeted && hb.valid && hb.F == F && hb.n_steps == a.n_steps && hb.max_iter == a.max_iter &&
                       hb.precond == a.precond && hb.scheme == a.scheme && hb.bandwidth == a.bandwidth &&

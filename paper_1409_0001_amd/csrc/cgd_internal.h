@@ -60,11 +60,12 @@ struct HexGeom {
     double vol;    // (h_x h_y) h_z
 };
 
-// The CG iterations each pseudo-step of a uniform-grid coarse-graining call
-// took (largest over the fields), with the parameters that determine them;
-// a later call with the same parameters enqueues that many iterations (plus
-// one) per step without reading convergence back between steps.
-struct HexBudget {
+// The CG iterations each pseudo-step of a coarse-graining call from a zero
+// guess took (largest over the fields), with the parameters that determine
+// them; a later call with the same parameters enqueues that many iterations
+// (plus one until the counts repeat) per step without reading convergence
+// back between steps.
+struct IterBudget {
     bool valid = false;
     int32_t F = 0, n_steps = 0, max_iter = 0, precond = 0, scheme = 0;
     double bandwidth = 0.0, rtol = 0.0;
@@ -121,7 +122,7 @@ struct cgd_mesh_s {
     hipEvent_t ev[2] = {nullptr, nullptr};
     cgd::Timing timing;
     int32_t cg_hint = -1;          // iteration at which the last CG solve on this mesh stopped (-1: none yet)
-    cgd::HexBudget budget;         // iterations per step of the last uniform-grid coarse-graining call
+    cgd::IterBudget budget;        // iterations per step of the last coarse-graining call
 };
 
 namespace cgd {
